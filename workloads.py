@@ -1,0 +1,128 @@
+"""Seeded synthetic workloads shared by the CPU oracle tests, the GPU tests and the benchmark.
+
+This module holds parameter-set descriptions and seeded random draws only. It contains none of
+the method's arithmetic: no primes, no modular reduction, no encoding, no slot layout. Both the
+oracle and the GPU library receive what is drawn here and do all of the CKKS work themselves.
+
+Workloads (the paper evaluates frozen dense layers on 768-d sentence embeddings, Section 4.1;
+the embeddings and trained weights are not available, so these synthetic stand-ins keep the
+shape, dimensionality and value ranges):
+
+* ``small``  N=2^12, ciphertext primes {40,30,40} bits, scale 2^30; one 64->64 dense layer by
+  the plain diagonal method (t1 = t = 64, 63 rotations); weights and inputs U[-1,1].
+* ``mid``    N=2^13, primes {60,40,40,60}, scale 2^40; 512->128->128 with x^2 between;
+  weights N(0, 0.05^2), inputs U[-1,1].
+* ``large``  N=2^14, primes {60,40,40,40,40,60}, scale 2^40; 768->256->64 with x^2 between;
+  weights N(0, 0.05^2), inputs N(0,1) clipped to [-3,3]; batches of 64 ciphertexts.
+
+Every workload adds one 60-bit special prime for key switching and uses error sigma = 3.2.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Tuple
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Layer:
+    n_in: int
+    n_out: int
+    t1: int          # baby-step count of the BSGS split (t = t1 * t2)
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    log2n: int
+    q_bits: Tuple[int, ...]      # ciphertext primes q_0..q_L, in chain order
+    p_bits: int                  # special key-switching prime
+    log2_scale: int
+    sigma: float
+    layers: Tuple[Layer, ...]
+    weight_dist: str             # "uniform1" or "normal005"
+    input_dist: str              # "uniform1" or "clipnormal3"
+    batch: int                   # ciphertexts per launch sequence
+    seed_base: int
+
+    @property
+    def n(self) -> int:
+        return 1 << self.log2n
+
+    # seeds: base + {1 weights, 2 inputs, 3 keys, 4 encryption}
+    @property
+    def seed_weights(self) -> int:
+        return self.seed_base + 1
+
+    @property
+    def seed_inputs(self) -> int:
+        return self.seed_base + 2
+
+    @property
+    def seed_keys(self) -> int:
+        return self.seed_base + 3
+
+    @property
+    def seed_encrypt(self) -> int:
+        return self.seed_base + 4
+
+
+SMALL = Workload("small", 12, (40, 30, 40), 60, 30, 3.2,
+                 (Layer(64, 64, 64),), "uniform1", "uniform1", 1, 1000)
+MID = Workload("mid", 13, (60, 40, 40, 60), 60, 40, 3.2,
+               (Layer(512, 128, 32), Layer(128, 128, 16)), "normal005", "uniform1", 1, 2000)
+LARGE = Workload("large", 14, (60, 40, 40, 40, 40, 60), 60, 40, 3.2,
+                 (Layer(768, 256, 32), Layer(256, 64, 16)), "normal005", "clipnormal3", 64, 3000)
+
+WORKLOADS = {w.name: w for w in (SMALL, MID, LARGE)}
+
+
+def _rng(seed: int, stream: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64([seed, stream]))
+
+
+def weights(w: Workload) -> List[np.ndarray]:
+    """One float64 matrix [n_out][n_in] per layer."""
+    out = []
+    for li, layer in enumerate(w.layers):
+        g = _rng(w.seed_weights, li)
+        if w.weight_dist == "uniform1":
+            m = g.uniform(-1.0, 1.0, size=(layer.n_out, layer.n_in))
+        elif w.weight_dist == "normal005":
+            m = g.normal(0.0, 0.05, size=(layer.n_out, layer.n_in))
+        else:
+            raise ValueError(w.weight_dist)
+        out.append(np.ascontiguousarray(m, dtype=np.float64))
+    return out
+
+
+def inputs(w: Workload, n_ct: int, items: int, stream: int = 0) -> np.ndarray:
+    """float64 array [n_ct][items][n_in] of client feature vectors."""
+    g = _rng(w.seed_inputs, stream)
+    shape = (n_ct, items, w.layers[0].n_in)
+    if w.input_dist == "uniform1":
+        x = g.uniform(-1.0, 1.0, size=shape)
+    elif w.input_dist == "clipnormal3":
+        x = np.clip(g.normal(0.0, 1.0, size=shape), -3.0, 3.0)
+    else:
+        raise ValueError(w.input_dist)
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def raw_plaintexts(seed: int, count: int, n: int, bound_bits: int = 40, stream: int = 0) -> np.ndarray:
+    """int64 array [count][n] of signed plaintext coefficients, uniform in [-2^b, 2^b].
+
+    Used by the bit-exact tests: both sides take these integers as already-encoded
+    plaintexts, so the comparison covers only exact modular arithmetic.
+    """
+    g = _rng(seed, 1000 + stream)
+    lim = 1 << bound_bits
+    return np.ascontiguousarray(g.integers(-lim, lim, size=(count, n), endpoint=True, dtype=np.int64))
+
+
+def residues(seed: int, count: int, n: int, bits: int = 64, stream: int = 0) -> np.ndarray:
+    """uint64 array [count][n] of raw random words (each side reduces them mod its primes)."""
+    g = _rng(seed, 2000 + stream)
+    return np.ascontiguousarray(g.integers(0, 1 << bits, size=(count, n), dtype=np.uint64,
+                                           endpoint=False))
