@@ -1,0 +1,244 @@
+/*
+ * ctl.h — C ABI of libcryptotl: the server-side hot path of CryptoTL's encrypted frozen-layer
+ * forward pass (RNS-CKKS) on one AMD Instinct MI355X (gfx950), plus the client-side calls that
+ * feed and read it.
+ *
+ * The paper's protocol (CryptoTL, Section 3, the Train/Classify protocol figure) has the client
+ * hold a key pair and encrypt with HE.Enc_pk, the server evaluate ClassifyHE(c, M_S) on its frozen
+ * layers, and the client decrypt with HE.Dec_sk. The calls below follow that split:
+ *
+ *   client:  ctl_keygen, ctl_encode / ctl_encode_items, ctl_encrypt, ctl_decrypt, ctl_decode*
+ *   server:  ctl_model_load*, ctl_dense, ctl_square, ctl_replicate, ctl_rescale, ctl_rotate,
+ *            ctl_forward  (= ClassifyHE)
+ *
+ * Conventions
+ *   - Every call returns int: CTL_OK (0) or a negative CTL_E* code. ctl_last_error() returns a
+ *     thread-local message for the last failure. No C++ exception crosses the ABI.
+ *   - On error, outputs are left unchanged and inputs are never modified.
+ *   - Handles (ctl_ctx, ctl_sk, ctl_pk, ctl_evk, ctl_model) are owned by the library; free each
+ *     with its ctl_*_free call. Device buffers passed as uint64_t* are owned by the caller.
+ *   - Ciphertext batches are caller-owned device buffers of uint64 residues in NTT form
+ *     (bit-reversed evaluation order: slot i holds a(psi^{2 brv(i) + 1})), laid out
+ *     [n_ct][2][k][N] — ciphertext, polynomial (c0, c1), prime q_0..q_{k-1}, coefficient.
+ *     k = level + 1 is the number of live primes.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the device's default stream). Device calls
+ *     are enqueued asynchronously on it. Calls that return host data synchronize it first.
+ *   - One context may be used by one stream at a time: calls that overlap on the same context
+ *     share its workspace and race.
+ *
+ * Readings of what the paper leaves open (prime choice, NTT order, slot order, sampling, key
+ * switching variant, rounding) are listed in the design notes; the integer results of every
+ * call are defined exactly by them and are bit-reproducible across runs.
+ */
+#ifndef CTL_H
+#define CTL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ errors */
+#define CTL_OK 0
+#define CTL_EINVAL -1    /* bad argument (null pointer, size, layout) */
+#define CTL_ENOMEM -2    /* device or host allocation failed */
+#define CTL_ELEVEL -3    /* modulus chain exhausted / wrong level for this call */
+#define CTL_ESCALE -4    /* encoded value or scale out of range */
+#define CTL_EKEY -5      /* a needed Galois or relinearization key is missing */
+#define CTL_EHIP -6      /* HIP runtime error */
+#define CTL_EPARAM -7    /* no suitable prime / unsupported parameter set */
+
+#define CTL_MAX_PRIMES 8    /* ciphertext primes per chain (the special prime comes on top) */
+
+/* Thread-local text of the last error. Valid until the next failing call on this thread. */
+const char *ctl_last_error(void);
+
+/* ------------------------------------------------------------------ parameters */
+/* CKKS parameter set ("The CKKS HE scheme" and "Multiplicative Depth", Section 3.1): ring degree
+ * N = 2^log2n (supported: 12, 13, 14), ciphertext primes q_0..q_{n_q-1} of the given bit sizes
+ * (each prime = 1 mod 2N, the largest such prime below 2^bits not already taken, in listed order),
+ * one special key-switching prime P of p_bits (chosen last), default scale 2^log2_scale, and the
+ * standard deviation of the discrete Gaussian error. Bit sizes must lie in [log2n + 2, 61]. */
+typedef struct ctl_params {
+    int log2n;
+    int n_q;
+    int q_bits[CTL_MAX_PRIMES];
+    int p_bits;
+    int log2_scale;
+    double sigma;
+} ctl_params;
+
+/* Host only (no device needed): the primes q_0..q_{n_q-1}, P of a parameter set.
+ * primes_out: host array of at least n_q + 1 entries; *n_out receives n_q + 1. */
+int ctl_params_primes(const ctl_params *params, uint64_t *primes_out, int *n_out);
+
+/* Host only: the Galois element 5^(r mod N/2) mod 2N of a left rotation by r slots (SIMD
+ * Encoding, Section 3.1: rot_r rotates the slot vector r steps to the left; r < 0 rotates right). */
+int ctl_galois_elt(const ctl_params *params, int rotation, uint64_t *g_out);
+
+/* Host only: the client-side sampler, exposed so tests can check it. Draws n values from the
+ * ChaCha20 (RFC 8439) stream keyed by `seed` with nonce (tag, index): kind 0 = ternary {-1,0,1},
+ * kind 1 = discrete Gaussian (|e| <= 19), kind 2 = uniform residues mod `modulus`. out: host int64[n]. */
+int ctl_sample(const ctl_params *params, uint64_t seed, uint32_t tag, uint64_t index, int kind,
+               uint64_t modulus, int n, int64_t *out);
+
+/* ------------------------------------------------------------------ context */
+typedef struct ctl_ctx ctl_ctx;
+
+/* Create a context on HIP device `device`: derives the primes and NTT tables and uploads them. */
+int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out);
+int ctl_ctx_free(ctl_ctx *ctx);
+/* primes_out: host array of n_q + 1 entries (q_0..q_{n_q-1}, P); *n_out = n_q + 1. */
+int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
+
+/* Optional device allocator for the context's workspace and the key and model banks (for example
+ * the framework's caching allocator). alloc returns a device pointer of at least `bytes` bytes
+ * usable on `stream`, or NULL. Without a hook the library uses hipMalloc / hipFree. Install it
+ * before any allocation is made. */
+typedef void *(*ctl_alloc_fn)(uint64_t bytes, void *stream, void *user);
+typedef void (*ctl_free_fn)(void *ptr, void *stream, void *user);
+int ctl_set_allocator(ctl_ctx *ctx, ctl_alloc_fn alloc, ctl_free_fn free_fn, void *user);
+
+/* Bytes of device workspace the context currently holds (grows on demand, freed with the ctx). */
+int ctl_workspace_bytes(const ctl_ctx *ctx, uint64_t *bytes_out);
+
+/* Forward (inverse = 0) or inverse (inverse = 1) negacyclic NTT, in place, of n_res residue
+ * polynomials of N words each, stored back to back at device pointer `dev`. prime_idx: host
+ * array of n_res prime indices (0..n_q-1 for q_i, n_q for P). Values must be < their prime. */
+int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, int inverse,
+            void *stream);
+
+/* ------------------------------------------------------------------ keys (client side) */
+typedef struct ctl_sk ctl_sk;
+typedef struct ctl_pk ctl_pk;
+typedef struct ctl_evk ctl_evk;
+
+/* Key generation from a seed (the protocol's key pair (sk, pk), Section 3): ternary secret s,
+ * public key (-a s + e, a) over q_0..q_L, one Galois key per distinct rotation amount in
+ * `rotations` (host int32[n_rot]; duplicates and 0 are ignored) and, if relin != 0, a
+ * relinearization key. Keys use one digit per ciphertext prime and the special prime P.
+ * Any of sk_out / pk_out / evk_out may be NULL if not wanted. Blocks until done. */
+int ctl_keygen(ctl_ctx *ctx, uint64_t seed, const int32_t *rotations, int n_rot, int relin,
+               ctl_sk **sk_out, ctl_pk **pk_out, ctl_evk **evk_out);
+int ctl_sk_free(ctl_sk *sk);
+int ctl_pk_free(ctl_pk *pk);
+int ctl_evk_free(ctl_evk *evk);
+/* Export for checking: sk as int64[N] ternary coefficients; pk as uint64[2][n_q][N] NTT form;
+ * the key of Galois element g (g = 0 selects the relinearization key) as uint64[n_q][2][n_q+1][N]
+ * (digit, polynomial b/a, prime q_0..q_{n_q-1},P, coefficient), NTT form. Host buffers. */
+int ctl_sk_export(const ctl_sk *sk, int64_t *coeffs_out);
+int ctl_pk_export(const ctl_pk *pk, uint64_t *out);
+int ctl_evk_export(const ctl_evk *evk, uint64_t galois_elt, uint64_t *out);
+/* Number of Galois keys held and their elements (host uint64 array of at least that many). */
+int ctl_evk_galois(const ctl_evk *evk, uint64_t *elts_out, int *n_out);
+
+/* ------------------------------------------------------------------ model (server side) */
+#define CTL_ACT_NONE 0
+#define CTL_ACT_SQUARE 1
+
+/* One dense layer y = W x with W of shape [n_out][n_in], evaluated by the baby-step giant-step
+ * diagonal method (Eq. (1) of Section 3.1) with padded width t = max(n_in, n_out), t = t1 * t2
+ * (t1 must divide t). act = CTL_ACT_SQUARE applies x^2 after the layer (not allowed on the last). */
+typedef struct ctl_layer_desc {
+    int n_in;
+    int n_out;
+    int t1;
+    int act;
+} ctl_layer_desc;
+
+typedef struct ctl_model ctl_model;
+
+/* Plan summary of a loaded model. Slot layout ("Multiple Predictions", Section 3.1): each item
+ * occupies a block of `block` = 2 t_max slots; items = floor((N/2) / block) items per ciphertext.
+ * The input ciphertext must be at k_in = n_q primes with scale scale_in; the output has k_out
+ * primes and scale scale_out. */
+typedef struct ctl_model_info {
+    int n_layers;
+    int block;
+    int items;
+    int k_in;
+    int k_out;
+    int n_in;
+    int n_out;
+    int n_rotations;
+    double scale_in;
+    double scale_out;
+    int layer_k[8];      /* live primes at each layer's input */
+    int layer_t[8];      /* padded width t of each layer */
+} ctl_model_info;
+
+/* Load the frozen layers from FP64 weights: W[l] is a host row-major [n_out][n_in] matrix. The
+ * diagonal plaintexts diag'_i (Eq. (1)) are encoded at the scale of the prime each layer's rescale
+ * drops, reduced and transformed on the device, and kept resident in HBM. */
+int ctl_model_load(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers,
+                   const double *const *weights, ctl_model **model_out);
+/* Same, from already-encoded integer plaintexts: pts[l] is a host int64 [t_l][N] array of signed
+ * coefficients (|c| < 2^62) for plaintext i = 0..t_l-1 of layer l. */
+int ctl_model_load_raw(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers,
+                       const int64_t *const *pts, ctl_model **model_out);
+int ctl_model_free(ctl_model *model);
+int ctl_model_get_info(const ctl_model *model, ctl_model_info *info_out);
+/* Every left-rotation amount the model needs keys for (host int32 array of n_rotations). */
+int ctl_model_rotations(const ctl_model *model, int32_t *rots_out, int *n_out);
+
+/* ------------------------------------------------------------------ client encode / encrypt */
+/* Encode N/2 real slot values at `scale` into signed integer plaintext coefficients:
+ * m = rint(scale * tau^{-1}(z)) with slot j <-> zeta^{5^j}, zeta = exp(i pi / N). Host buffers:
+ * slots double[N/2], coeffs_out int64[N]. CTL_ESCALE if a coefficient reaches 2^62. */
+int ctl_encode(ctl_ctx *ctx, const double *slots, double scale, int64_t *coeffs_out);
+/* Place `items` feature vectors x (host double [items][n_in]) as [x | x] blocks of the model's
+ * layout and encode them at the model's input scale into coeffs_out (host int64[N]). */
+int ctl_encode_items(ctl_ctx *ctx, const ctl_model *model, const double *x, int items,
+                     int64_t *coeffs_out);
+/* Public-key encryption at the top level (HE.Enc_pk): ct = (v b + e0 + m, v a + e1) with v ternary
+ * and e0, e1 Gaussian drawn from `seed`. coeffs: host int64[N] plaintext coefficients;
+ * ct_out: device uint64[2][n_q][N]. */
+int ctl_encrypt(ctl_ctx *ctx, const ctl_pk *pk, const int64_t *coeffs, uint64_t seed,
+                uint64_t *ct_out, void *stream);
+/* Decryption (HE.Dec_sk) of one ciphertext with k live primes at device pointer ct: writes the
+ * coefficient-form residues of c0 + c1 s to host uint64[k][N]. Synchronizes the stream. */
+int ctl_decrypt(ctl_ctx *ctx, const ctl_sk *sk, const uint64_t *ct, int k, uint64_t *residues_out,
+                void *stream);
+/* Decode coefficient residues (host uint64[k][N]) at `scale` into N/2 real slots (host double). */
+int ctl_decode(ctl_ctx *ctx, const uint64_t *residues, int k, double scale, double *slots_out);
+/* Decode a model output: y_out host double [items][n_out] read from slots [b*block, b*block+n_out). */
+int ctl_decode_items(ctl_ctx *ctx, const ctl_model *model, const uint64_t *residues, double *y_out);
+
+/* ------------------------------------------------------------------ server hot path (batched) */
+/* All take n_ct ciphertexts [n_ct][2][k][N] at device pointer `in` and write [n_ct][2][k'][N] to
+ * device pointer `out` (out must not overlap in). */
+
+/* ClassifyHE (protocol figure, Section 3): every frozen layer in turn — dense, then for all but
+ * the last layer x^2 with relinearization and rescale, then replicate [y | 0] -> [y | y] for the
+ * next layer. in: k = model k_in; out: k = model k_out. */
+int ctl_forward(ctl_ctx *ctx, const ctl_model *model, const ctl_evk *evk, const uint64_t *in,
+                uint64_t *out, int n_ct, void *stream);
+
+/* One dense layer by Eq. (1): hoisted baby-step rotations rot_j, j < t1, products with the
+ * diagonal plaintexts, one key switch per giant step rot_{k t1}, one rescale at the end.
+ * in: k = the layer's input primes (ctl_model_info.layer_k); out: k - 1. */
+int ctl_dense(ctl_ctx *ctx, const ctl_model *model, int layer, const ctl_evk *evk,
+              const uint64_t *in, uint64_t *out, int n_ct, void *stream);
+
+/* x^2 activation (the polynomial activation of Section 3.1, degree 2): tensor, relinearize with
+ * the relinearization key, rescale. k -> k - 1. */
+int ctl_square(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint64_t *out,
+               int n_ct, void *stream);
+
+/* ct + rot_{-width}(ct): turns [y | 0] blocks into [y | y] for the next layer. k -> k. */
+int ctl_replicate(ctl_ctx *ctx, const ctl_evk *evk, int k, int width, const uint64_t *in,
+                  uint64_t *out, int n_ct, void *stream);
+
+/* Left rotation by `rotation` slots (needs that Galois key). k -> k. */
+int ctl_rotate(ctl_ctx *ctx, const ctl_evk *evk, int k, int rotation, const uint64_t *in,
+               uint64_t *out, int n_ct, void *stream);
+
+/* Rescale ("The CKKS HE scheme", Section 3.1): divide by q_{k-1} with rounding. k -> k - 1. */
+int ctl_rescale(ctl_ctx *ctx, int k, const uint64_t *in, uint64_t *out, int n_ct, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTL_H */

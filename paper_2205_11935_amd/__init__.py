@@ -1,0 +1,428 @@
+"""Python binding of libcryptotl (CryptoTL's encrypted frozen-layer forward pass on MI355X).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of the shared library.
+PyTorch supplies device memory (ciphertext buffers and, through the allocator hook, the library's
+workspace and banks) and streams. If the library is not built, importing the binding works but
+creating a Context raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcryptotl.so")
+
+CTL_ACT_NONE = 0
+CTL_ACT_SQUARE = 1
+MAX_PRIMES = 8
+
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ELEVEL", -4: "ESCALE", -5: "EKEY", -6: "EHIP", -7: "EPARAM"}
+
+u64p = ctypes.POINTER(ctypes.c_uint64)
+i64p = ctypes.POINTER(ctypes.c_int64)
+i32p = ctypes.POINTER(ctypes.c_int32)
+f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class CtlError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("log2n", ctypes.c_int), ("n_q", ctypes.c_int), ("q_bits", ctypes.c_int * MAX_PRIMES),
+                ("p_bits", ctypes.c_int), ("log2_scale", ctypes.c_int), ("sigma", ctypes.c_double)]
+
+
+class _LayerDesc(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int), ("n_out", ctypes.c_int), ("t1", ctypes.c_int), ("act", ctypes.c_int)]
+
+
+class _ModelInfo(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int), ("block", ctypes.c_int), ("items", ctypes.c_int),
+                ("k_in", ctypes.c_int), ("k_out", ctypes.c_int), ("n_in", ctypes.c_int), ("n_out", ctypes.c_int),
+                ("n_rotations", ctypes.c_int), ("scale_in", ctypes.c_double), ("scale_out", ctypes.c_double),
+                ("layer_k", ctypes.c_int * 8), ("layer_t", ctypes.c_int * 8)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+# every symbol the header declares, with its ctypes signature
+_SIGS = {
+    "ctl_last_error": (ctypes.c_char_p, []),
+    "ctl_params_primes": (ctypes.c_int, [ctypes.POINTER(_Params), u64p, ctypes.POINTER(ctypes.c_int)]),
+    "ctl_galois_elt": (ctypes.c_int, [ctypes.POINTER(_Params), ctypes.c_int, u64p]),
+    "ctl_sample": (ctypes.c_int, [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                  ctypes.c_int, ctypes.c_uint64, ctypes.c_int, i64p]),
+    "ctl_ctx_create": (ctypes.c_int, [ctypes.POINTER(_Params), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "ctl_ctx_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "ctl_ctx_primes": (ctypes.c_int, [ctypes.c_void_p, u64p, ctypes.POINTER(ctypes.c_int)]),
+    "ctl_set_allocator": (ctypes.c_int, [ctypes.c_void_p, _ALLOC_FN, _FREE_FN, ctypes.c_void_p]),
+    "ctl_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, u64p]),
+    "ctl_ntt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, i32p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_keygen": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, i32p, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                  ctypes.POINTER(ctypes.c_void_p)]),
+    "ctl_sk_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "ctl_pk_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "ctl_evk_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "ctl_sk_export": (ctypes.c_int, [ctypes.c_void_p, i64p]),
+    "ctl_pk_export": (ctypes.c_int, [ctypes.c_void_p, u64p]),
+    "ctl_evk_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, u64p]),
+    "ctl_evk_galois": (ctypes.c_int, [ctypes.c_void_p, u64p, ctypes.POINTER(ctypes.c_int)]),
+    "ctl_model_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_LayerDesc), ctypes.c_int,
+                                      ctypes.POINTER(f64p), ctypes.POINTER(ctypes.c_void_p)]),
+    "ctl_model_load_raw": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_LayerDesc), ctypes.c_int,
+                                          ctypes.POINTER(i64p), ctypes.POINTER(ctypes.c_void_p)]),
+    "ctl_model_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "ctl_model_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_ModelInfo)]),
+    "ctl_model_rotations": (ctypes.c_int, [ctypes.c_void_p, i32p, ctypes.POINTER(ctypes.c_int)]),
+    "ctl_encode": (ctypes.c_int, [ctypes.c_void_p, f64p, ctypes.c_double, i64p]),
+    "ctl_encode_items": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, f64p, ctypes.c_int, i64p]),
+    "ctl_encrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, i64p, ctypes.c_uint64, ctypes.c_void_p,
+                                   ctypes.c_void_p]),
+    "ctl_decrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, u64p,
+                                   ctypes.c_void_p]),
+    "ctl_decode": (ctypes.c_int, [ctypes.c_void_p, u64p, ctypes.c_int, ctypes.c_double, f64p]),
+    "ctl_decode_items": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, u64p, f64p]),
+    "ctl_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_dense": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_square": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_replicate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_rotate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_rescale": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int, ctypes.c_void_p]),
+}
+
+_LIB = None
+
+
+def lib():
+    """Load the shared library (raises if it is not built: there is no fallback path)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcryptotl.so is not built (run paper_2205_11935_amd/build.py)")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = l
+    return _LIB
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise CtlError(rc, (lib().ctl_last_error() or b"").decode())
+
+
+def _params(log2n, q_bits, p_bits, log2_scale, sigma) -> _Params:
+    if len(q_bits) > MAX_PRIMES:
+        raise ValueError("at most %d ciphertext primes" % MAX_PRIMES)
+    p = _Params()
+    p.log2n, p.n_q, p.p_bits, p.log2_scale, p.sigma = log2n, len(q_bits), p_bits, log2_scale, sigma
+    for i, b in enumerate(q_bits):
+        p.q_bits[i] = b
+    return p
+
+
+def params_primes(log2n, q_bits, p_bits, log2_scale=40, sigma=3.2) -> List[int]:
+    p = _params(log2n, q_bits, p_bits, log2_scale, sigma)
+    out = (ctypes.c_uint64 * (len(q_bits) + 1))()
+    n = ctypes.c_int()
+    _check(lib().ctl_params_primes(ctypes.byref(p), out, ctypes.byref(n)))
+    return [int(out[i]) for i in range(n.value)]
+
+
+def galois_elt(log2n: int, rotation: int) -> int:
+    p = _params(log2n, [40], 60, 40, 3.2)
+    g = ctypes.c_uint64()
+    _check(lib().ctl_galois_elt(ctypes.byref(p), rotation, ctypes.byref(g)))
+    return int(g.value)
+
+
+def sample(log2n, q_bits, p_bits, seed, tag, index, kind, modulus, n, sigma=3.2) -> np.ndarray:
+    p = _params(log2n, q_bits, p_bits, 40, sigma)
+    out = np.zeros(n, dtype=np.int64)
+    _check(lib().ctl_sample(ctypes.byref(p), seed, tag, index, kind, modulus, n, out.ctypes.data_as(i64p)))
+    return out
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class ModelInfo:
+    n_layers: int
+    block: int
+    items: int
+    k_in: int
+    k_out: int
+    n_in: int
+    n_out: int
+    scale_in: float
+    scale_out: float
+    layer_k: List[int]
+    layer_t: List[int]
+    rotations: List[int]
+
+
+class Keys:
+    def __init__(self, ctx: "Context", sk, pk, evk):
+        self.ctx, self.sk, self.pk, self.evk = ctx, sk, pk, evk
+
+    def secret(self) -> np.ndarray:
+        s = np.zeros(self.ctx.n, dtype=np.int64)
+        _check(lib().ctl_sk_export(self.sk, s.ctypes.data_as(i64p)))
+        return s
+
+    def public(self) -> np.ndarray:
+        out = np.zeros((2, self.ctx.nq, self.ctx.n), dtype=np.uint64)
+        _check(lib().ctl_pk_export(self.pk, out.ctypes.data_as(u64p)))
+        return out
+
+    def galois_key(self, g: int) -> np.ndarray:
+        out = np.zeros((self.ctx.nq, 2, self.ctx.nq + 1, self.ctx.n), dtype=np.uint64)
+        _check(lib().ctl_evk_export(self.evk, g, out.ctypes.data_as(u64p)))
+        return out
+
+    def galois_elements(self) -> List[int]:
+        n = ctypes.c_int()
+        _check(lib().ctl_evk_galois(self.evk, None, ctypes.byref(n)))
+        out = (ctypes.c_uint64 * max(n.value, 1))()
+        _check(lib().ctl_evk_galois(self.evk, out, ctypes.byref(n)))
+        return [int(out[i]) for i in range(n.value)]
+
+    def __del__(self):
+        if _LIB is not None:
+            for f, h in (("ctl_sk_free", self.sk), ("ctl_pk_free", self.pk), ("ctl_evk_free", self.evk)):
+                if h:
+                    getattr(_LIB, f)(h)
+            self.sk = self.pk = self.evk = None
+
+
+class Model:
+    def __init__(self, ctx: "Context", handle):
+        self.ctx, self.handle = ctx, handle
+        info = _ModelInfo()
+        _check(lib().ctl_model_get_info(handle, ctypes.byref(info)))
+        rots = (ctypes.c_int32 * max(info.n_rotations, 1))()
+        n = ctypes.c_int()
+        _check(lib().ctl_model_rotations(handle, rots, ctypes.byref(n)))
+        self.info = ModelInfo(info.n_layers, info.block, info.items, info.k_in, info.k_out, info.n_in,
+                              info.n_out, info.scale_in, info.scale_out, list(info.layer_k)[: info.n_layers],
+                              list(info.layer_t)[: info.n_layers], [int(rots[i]) for i in range(n.value)])
+
+    def __del__(self):
+        if _LIB is not None and self.handle:
+            _LIB.ctl_model_free(self.handle)
+            self.handle = None
+
+
+class Context:
+    """One CKKS parameter set on one GPU."""
+
+    def __init__(self, log2n: int, q_bits: Sequence[int], p_bits: int, log2_scale: int, sigma: float = 3.2,
+                 device: int = 0, torch_allocator: bool = True):
+        import torch
+        self._torch = torch
+        self.log2n, self.n, self.nq = log2n, 1 << log2n, len(q_bits)
+        self.device = device
+        self.scale = float(2.0 ** log2_scale)
+        self._params = _params(log2n, q_bits, p_bits, log2_scale, sigma)
+        h = ctypes.c_void_p()
+        torch.cuda.init()
+        _check(lib().ctl_ctx_create(ctypes.byref(self._params), device, ctypes.byref(h)))
+        self.handle = h
+        self._hooks = None
+        if torch_allocator:
+            dev = device
+
+            def _alloc(nbytes, stream, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0)
+                except Exception:       # noqa: BLE001 -- report failure to the library as NULL
+                    return None
+
+            def _free(ptr, stream, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._hooks = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+            _check(lib().ctl_set_allocator(self.handle, self._hooks[0], self._hooks[1], None))
+        pr = (ctypes.c_uint64 * (self.nq + 1))()
+        n = ctypes.c_int()
+        _check(lib().ctl_ctx_primes(self.handle, pr, ctypes.byref(n)))
+        self.primes = [int(pr[i]) for i in range(n.value)]
+
+    @classmethod
+    def for_workload(cls, w, **kw) -> "Context":
+        return cls(w.log2n, w.q_bits, w.p_bits, w.log2_scale, w.sigma, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._torch.cuda.synchronize()
+            lib().ctl_ctx_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # noqa: BLE001 -- interpreter shutdown
+            pass
+
+    # ------------------------------------------------------------ buffers
+    def empty_ct(self, n_ct: int, k: int):
+        return self._torch.empty((n_ct, 2, k, self.n), dtype=self._torch.int64, device="cuda:%d" % self.device)
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_uint64()
+        _check(lib().ctl_workspace_bytes(self.handle, ctypes.byref(b)))
+        return int(b.value)
+
+    # ------------------------------------------------------------ parity hook
+    def ntt(self, buf, prime_idx: Sequence[int], inverse: bool = False, stream=None):
+        idx = (ctypes.c_int32 * len(prime_idx))(*prime_idx)
+        _check(lib().ctl_ntt(self.handle, _ptr(buf), len(prime_idx), idx, int(inverse), _stream(stream)))
+
+    # ------------------------------------------------------------ client side
+    def keygen(self, seed: int, rotations: Sequence[int], relin: bool = True) -> Keys:
+        rots = (ctypes.c_int32 * max(len(rotations), 1))(*rotations)
+        sk, pk, evk = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().ctl_keygen(self.handle, seed, rots, len(rotations), int(relin), ctypes.byref(sk),
+                                ctypes.byref(pk), ctypes.byref(evk)))
+        return Keys(self, sk, pk, evk)
+
+    def encode(self, slots: np.ndarray, scale: float) -> np.ndarray:
+        z = np.ascontiguousarray(slots, dtype=np.float64)
+        out = np.zeros(self.n, dtype=np.int64)
+        _check(lib().ctl_encode(self.handle, z.ctypes.data_as(f64p), scale, out.ctypes.data_as(i64p)))
+        return out
+
+    def encode_items(self, model: Model, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.zeros(self.n, dtype=np.int64)
+        _check(lib().ctl_encode_items(self.handle, model.handle, x.ctypes.data_as(f64p), x.shape[0],
+                                      out.ctypes.data_as(i64p)))
+        return out
+
+    def encrypt(self, keys: Keys, coeffs: np.ndarray, seed: int, out=None, stream=None):
+        m = np.ascontiguousarray(coeffs, dtype=np.int64)
+        if out is None:
+            out = self.empty_ct(1, self.nq)[0]
+        _check(lib().ctl_encrypt(self.handle, keys.pk, m.ctypes.data_as(i64p), seed, _ptr(out), _stream(stream)))
+        return out
+
+    def decrypt(self, keys: Keys, ct, k: int, stream=None) -> np.ndarray:
+        out = np.zeros((k, self.n), dtype=np.uint64)
+        _check(lib().ctl_decrypt(self.handle, keys.sk, _ptr(ct), k, out.ctypes.data_as(u64p), _stream(stream)))
+        return out
+
+    def decode(self, residues: np.ndarray, scale: float) -> np.ndarray:
+        r = np.ascontiguousarray(residues, dtype=np.uint64)
+        out = np.zeros(self.n // 2, dtype=np.float64)
+        _check(lib().ctl_decode(self.handle, r.ctypes.data_as(u64p), r.shape[0], scale, out.ctypes.data_as(f64p)))
+        return out
+
+    def decode_items(self, model: Model, residues: np.ndarray) -> np.ndarray:
+        r = np.ascontiguousarray(residues, dtype=np.uint64)
+        out = np.zeros((model.info.items, model.info.n_out), dtype=np.float64)
+        _check(lib().ctl_decode_items(self.handle, model.handle, r.ctypes.data_as(u64p), out.ctypes.data_as(f64p)))
+        return out
+
+    # ------------------------------------------------------------ server side
+    @staticmethod
+    def _descs(layers):
+        arr = (_LayerDesc * len(layers))()
+        for i, l in enumerate(layers):
+            arr[i].n_in, arr[i].n_out, arr[i].t1 = l[0], l[1], l[2]
+            arr[i].act = l[3] if len(l) > 3 else (CTL_ACT_SQUARE if i + 1 < len(layers) else CTL_ACT_NONE)
+        return arr
+
+    def load_model(self, layers, weights: Sequence[np.ndarray]) -> Model:
+        """layers: (n_in, n_out, t1[, act]) per layer; weights: float64 [n_out][n_in] per layer."""
+        ws = [np.ascontiguousarray(w, dtype=np.float64) for w in weights]
+        ptrs = (f64p * len(ws))(*[w.ctypes.data_as(f64p) for w in ws])
+        h = ctypes.c_void_p()
+        _check(lib().ctl_model_load(self.handle, self._descs(layers), len(layers), ptrs, ctypes.byref(h)))
+        return Model(self, h)
+
+    def load_model_raw(self, layers, pts: Sequence[np.ndarray]) -> Model:
+        """pts: int64 [t][N] encoded diagonal plaintexts per layer."""
+        ps = [np.ascontiguousarray(p, dtype=np.int64) for p in pts]
+        ptrs = (i64p * len(ps))(*[p.ctypes.data_as(i64p) for p in ps])
+        h = ctypes.c_void_p()
+        _check(lib().ctl_model_load_raw(self.handle, self._descs(layers), len(layers), ptrs, ctypes.byref(h)))
+        return Model(self, h)
+
+    def forward(self, model: Model, keys: Keys, ct, out=None, stream=None):
+        n_ct = ct.shape[0]
+        if out is None:
+            out = self.empty_ct(n_ct, model.info.k_out)
+        _check(lib().ctl_forward(self.handle, model.handle, keys.evk, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        return out
+
+    def dense(self, model: Model, layer: int, keys: Keys, ct, out=None, stream=None):
+        n_ct, k = ct.shape[0], ct.shape[2]
+        if out is None:
+            out = self.empty_ct(n_ct, k - 1)
+        _check(lib().ctl_dense(self.handle, model.handle, layer, keys.evk, _ptr(ct), _ptr(out), n_ct,
+                               _stream(stream)))
+        return out
+
+    def square(self, keys: Keys, ct, out=None, stream=None):
+        n_ct, k = ct.shape[0], ct.shape[2]
+        if out is None:
+            out = self.empty_ct(n_ct, k - 1)
+        _check(lib().ctl_square(self.handle, keys.evk, k, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        return out
+
+    def replicate(self, keys: Keys, ct, width: int, out=None, stream=None):
+        n_ct, k = ct.shape[0], ct.shape[2]
+        if out is None:
+            out = self.empty_ct(n_ct, k)
+        _check(lib().ctl_replicate(self.handle, keys.evk, k, width, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        return out
+
+    def rotate(self, keys: Keys, ct, rotation: int, out=None, stream=None):
+        n_ct, k = ct.shape[0], ct.shape[2]
+        if out is None:
+            out = self.empty_ct(n_ct, k)
+        _check(lib().ctl_rotate(self.handle, keys.evk, k, rotation, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        return out
+
+    def rescale(self, ct, out=None, stream=None):
+        n_ct, k = ct.shape[0], ct.shape[2]
+        if out is None:
+            out = self.empty_ct(n_ct, k - 1)
+        _check(lib().ctl_rescale(self.handle, k, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        return out
+
+
+def to_numpy_u64(t) -> np.ndarray:
+    """Device int64 tensor of residues -> host uint64 array (bit reinterpretation)."""
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def from_numpy_u64(a: np.ndarray, device: int = 0):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to("cuda:%d" % device)

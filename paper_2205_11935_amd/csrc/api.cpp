@@ -1,0 +1,1032 @@
+// C ABI and host-side evaluator of libcryptotl: parameter tables, keys, model banks, and the
+// launch sequences of the encrypted dense layer (Eq. (1) of CryptoTL, Section 3.1), the x^2
+// activation, replicate and rescale. Every arithmetic step runs in the HIP kernels; the host only
+// samples client randomness, encodes FP64 slot vectors and orders launches on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "ctl_internal.h"
+#include "kernels.h"
+
+using namespace ctl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define CTL_HIP(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) return fail(CTL_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define CTL_TRY(expr)                  \
+    do {                               \
+        int rc_ = (expr);              \
+        if (rc_ != CTL_OK) return rc_; \
+    } while (0)
+
+// Workspace slots: each grows on demand and is reused by later calls on the same context.
+enum Slot {
+    S_COEF, S_DIG, S_U, S_PLAST, S_ROT, S_INNER, S_SUM, S_LAST, S_TENSOR, S_SQ, S_REP,
+    S_FWD_A, S_FWD_B, S_FWD_C, S_COEF2, S_ROT2, S_MISC, S_COUNT
+};
+
+}  // namespace
+
+struct ctl_ctx {
+    HostParams hp;
+    int device = 0;
+    Tables tab{};
+    void *tables_mem = nullptr;
+    ctl_alloc_fn alloc = nullptr;
+    ctl_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    void *slot_ptr[S_COUNT] = {};
+    size_t slot_bytes[S_COUNT] = {};
+    std::unique_ptr<Encoder> enc;
+    std::vector<PrimeConst> pc;
+};
+
+struct ctl_sk {
+    ctl_ctx *ctx;
+    std::vector<int64_t> s;
+    u64 *d_s = nullptr;          // [np][N] NTT form
+};
+
+struct ctl_pk {
+    ctl_ctx *ctx;
+    u64 *d_pk = nullptr;         // [2][nq][N]
+};
+
+struct ctl_evk {
+    ctl_ctx *ctx;
+    std::map<u64, u64 *> keys;   // Galois element (0 = relinearization) -> [nq][2][np][N]
+};
+
+struct LayerPlan {
+    int n_in, n_out, t, t1, t2, k, act;
+    double pt_scale;
+};
+
+struct ctl_model {
+    ctl_ctx *ctx;
+    std::vector<LayerPlan> layers;
+    std::vector<u64 *> banks;     // [t][k][N] NTT form per layer
+    std::vector<int32_t> rotations;
+    int block = 0, items = 0, k_out = 0;
+    double scale_in = 0, scale_out = 0;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- memory
+void *dev_alloc(ctl_ctx *c, size_t bytes, hipStream_t st) {
+    if (bytes == 0) bytes = 256;
+    if (c->alloc) return c->alloc(bytes, st, c->user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(ctl_ctx *c, void *p, hipStream_t st) {
+    if (!p) return;
+    if (c->free_fn) c->free_fn(p, st, c->user);
+    else (void)hipFree(p);
+}
+
+int slot(ctl_ctx *c, Slot s, size_t words, hipStream_t st, u64 **out) {
+    const size_t bytes = std::max<size_t>(words * 8, 256);
+    if (c->slot_bytes[s] < bytes) {
+        CTL_HIP(hipStreamSynchronize(st));
+        dev_free(c, c->slot_ptr[s], st);
+        c->slot_ptr[s] = nullptr;
+        c->slot_bytes[s] = 0;
+        void *p = dev_alloc(c, bytes, st);
+        if (!p) return fail(CTL_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+        c->slot_ptr[s] = p;
+        c->slot_bytes[s] = bytes;
+    }
+    *out = static_cast<u64 *>(c->slot_ptr[s]);
+    return CTL_OK;
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+int check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CTL_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return CTL_OK;
+}
+
+ResMap dense_map(int per, int prime_base = 0) {
+    ResMap m{};
+    m.per = per;
+    m.ngrp = 1;
+    m.off = 0;
+    m.gstride = per;
+    m.ostride = per;
+    for (int i = 0; i < per; ++i) m.prime[i] = prime_base + i;
+    return m;
+}
+
+const u64 *find_key(const ctl_evk *evk, u64 g) {
+    auto it = evk->keys.find(g);
+    return it == evk->keys.end() ? nullptr : it->second;
+}
+
+// ---------------------------------------------------------------- building blocks
+// Key switch G = B R polynomials d (k residues each, located by dmap over B*R*k residues, group
+// order (b, r)) with key r and automorphism gal[r]: out[b][r] = (KS0 + addend, KS1) as
+// [B][R][2][k][N]. `hoisted` = the same d for every r (dmap covers B*k residues only).
+int keyswitch_batch(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *d, const ResMap &dmap,
+                    bool hoisted, const u64 *const *keys, const u64 *gal, const DropAdd &add, u64 *out) {
+    const int logn = c->hp.logn, nq = c->hp.nq;
+    const long N = c->hp.n;
+    if (R > kMaxKeysPerLaunch) return fail(CTL_EINVAL, "too many rotations in one layer");
+    const int G = hoisted ? B : B * R;
+    u64 *coef, *dig, *U, *plast;
+    CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
+    CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
+    CTL_TRY(slot(c, S_U, (size_t)B * R * 2 * (k + 1) * N, st, &U));
+    CTL_TRY(slot(c, S_PLAST, (size_t)B * R * 2 * N, st, &plast));
+    launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st);
+    launch_modup(logn, coef, dig, G, k, nq, c->tab, st);
+    KeyList kl{};
+    for (int r = 0; r < R; ++r) {
+        kl.key[r] = keys[r];
+        kl.gal[r] = gal[r];
+    }
+    const long dsz = (long)k * (k + 1) * N;
+    launch_keyip(logn, k, dig, hoisted ? dsz : (long)R * dsz, hoisted ? 0 : dsz, kl, R, U, B, nq, c->tab, st);
+    ResMap pm{};
+    pm.per = 1;
+    pm.ngrp = 1;
+    pm.off = k;
+    pm.gstride = k + 1;
+    pm.ostride = k + 1;
+    pm.prime[0] = nq;
+    launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), B * R * 2, c->tab, st);
+    launch_drop(logn, U, plast, out, B * R * 2, k, nq, add, c->tab, st);
+    return check_launch();
+}
+
+// Rescale [B][2][k][N] -> [B][2][k-1][N].
+int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *out) {
+    const int logn = c->hp.logn;
+    const long N = c->hp.n;
+    if (k < 2) return fail(CTL_ELEVEL, "cannot rescale at one prime");
+    u64 *last;
+    CTL_TRY(slot(c, S_LAST, (size_t)B * 2 * N, st, &last));
+    ResMap m{};
+    m.per = 1;
+    m.ngrp = 1;
+    m.off = k - 1;
+    m.gstride = k;
+    m.ostride = k;
+    m.prime[0] = k - 1;
+    launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, st);
+    DropAdd add{};
+    add.R = 1;
+    add.mask = 0;
+    add.gal[0] = 1;
+    launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, st);
+    return check_launch();
+}
+
+ResMap c1_map(int k) {        // the c1 residues of a [B][2][k][N] batch
+    ResMap m{};
+    m.per = k;
+    m.ngrp = 1;
+    m.off = k;
+    m.gstride = 2 * k;
+    m.ostride = 2 * k;
+    for (int i = 0; i < k; ++i) m.prime[i] = i;
+    return m;
+}
+
+int rotate_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, long rot, const u64 *in, u64 *out) {
+    const u64 g = galois_elt(c->hp.logn, rot);
+    const long N = c->hp.n;
+    if (g == 1) {
+        CTL_HIP(hipMemcpyAsync(out, in, (size_t)B * 2 * k * N * 8, hipMemcpyDeviceToDevice, st));
+        return CTL_OK;
+    }
+    const u64 *key = find_key(evk, g);
+    if (!key) return fail(CTL_EKEY, "missing Galois key for rotation " + std::to_string(rot));
+    DropAdd add{};
+    add.base = in;
+    add.sb = 2L * k * N;
+    add.R = 1;
+    add.mask = 1;
+    add.gal[0] = g;
+    return keyswitch_batch(c, st, k, B, 1, in, c1_map(k), false, &key, &g, add, out);
+}
+
+int replicate_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, int width, const u64 *in, u64 *out) {
+    const long N = c->hp.n;
+    u64 *rot;
+    CTL_TRY(slot(c, S_REP, (size_t)B * 2 * k * N, st, &rot));
+    CTL_TRY(rotate_batch(c, st, evk, k, B, -(long)width, in, rot));
+    launch_add_terms(c->hp.logn, in, 2L * k * N, rot, 2L * k * N, 0, 1, out, B, k, c->tab, st);
+    return check_launch();
+}
+
+int square_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, const u64 *in, u64 *out) {
+    const long N = c->hp.n;
+    const u64 *rlk = find_key(evk, 0);
+    if (!rlk) return fail(CTL_EKEY, "missing relinearization key");
+    if (k < 2) return fail(CTL_ELEVEL, "x^2 needs at least two primes");
+    u64 *t3, *sq;
+    CTL_TRY(slot(c, S_TENSOR, (size_t)B * 3 * k * N, st, &t3));
+    CTL_TRY(slot(c, S_SQ, (size_t)B * 2 * k * N, st, &sq));
+    launch_tensor(c->hp.logn, in, t3, B, k, c->tab, st);
+    ResMap dm{};
+    dm.per = k;
+    dm.ngrp = 1;
+    dm.off = 2 * k;
+    dm.gstride = 3 * k;
+    dm.ostride = 3 * k;
+    for (int i = 0; i < k; ++i) dm.prime[i] = i;
+    DropAdd add{};
+    add.base = t3;
+    add.sb = 3L * k * N;
+    add.sc = (long)k * N;
+    add.R = 1;
+    add.mask = 3;
+    add.gal[0] = 1;
+    const u64 one = 1;
+    CTL_TRY(keyswitch_batch(c, st, k, B, 1, t3, dm, false, &rlk, &one, add, sq));
+    return rescale_batch(c, st, k, B, sq, out);
+}
+
+int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ctl_evk *evk, int B,
+                const u64 *in, u64 *out) {
+    const LayerPlan &L = m->layers[li];
+    const int logn = c->hp.logn, k = L.k, t1 = L.t1, t2 = L.t2;
+    const long N = c->hp.n, ctw = 2L * k * N;
+    const int R1 = t1 - 1, R2 = t2 - 1;
+    if (R1 > kMaxKeysPerLaunch || R2 > kMaxKeysPerLaunch)
+        return fail(CTL_EINVAL, "t1 and t2 must be at most 65");
+    std::vector<const u64 *> keys1(R1), keys2(R2);
+    std::vector<u64> gal1(R1), gal2(R2);
+    for (int j = 1; j < t1; ++j) {
+        gal1[j - 1] = galois_elt(logn, j);
+        keys1[j - 1] = find_key(evk, gal1[j - 1]);
+        if (!keys1[j - 1]) return fail(CTL_EKEY, "missing Galois key for rotation " + std::to_string(j));
+    }
+    for (int k2 = 1; k2 < t2; ++k2) {
+        gal2[k2 - 1] = galois_elt(logn, (long)k2 * t1);
+        keys2[k2 - 1] = find_key(evk, gal2[k2 - 1]);
+        if (!keys2[k2 - 1]) return fail(CTL_EKEY, "missing Galois key for rotation " + std::to_string(k2 * t1));
+    }
+    u64 *rot, *inner;
+    CTL_TRY(slot(c, S_ROT, (size_t)B * std::max(R1, 1) * ctw, st, &rot));
+    CTL_TRY(slot(c, S_INNER, (size_t)B * t2 * ctw, st, &inner));
+    // baby steps rot_j(ct), j = 1..t1-1, sharing one ModUp of c1
+    if (R1 > 0) {
+        DropAdd add{};
+        add.base = in;
+        add.sb = ctw;
+        add.sr = 0;
+        add.R = R1;
+        add.mask = 1;
+        for (int r = 0; r < R1; ++r) add.gal[r] = gal1[r];
+        CTL_TRY(keyswitch_batch(c, st, k, B, R1, in, c1_map(k), true, keys1.data(), gal1.data(), add, rot));
+    }
+    // inner_k2 = sum_j diag'_{k2 t1 + j} * rot_j(ct)
+    launch_mac(logn, in, rot, m->banks[li], inner, B, k, t1, t2, c->tab, st);
+    CTL_TRY(check_launch());
+    const u64 *sum = inner;
+    if (R2 > 0) {
+        // giant steps rot_{k2 t1}(inner_k2), k2 = 1..t2-1, one key switch each, then the sum
+        u64 *rot2, *acc;
+        CTL_TRY(slot(c, S_ROT2, (size_t)B * R2 * ctw, st, &rot2));
+        CTL_TRY(slot(c, S_SUM, (size_t)B * ctw, st, &acc));
+        ResMap dm{};
+        dm.per = k;
+        dm.ngrp = R2;
+        dm.off = 3L * k;                // k2 = 1, c1
+        dm.gstride = 2L * k;
+        dm.ostride = (long)t2 * 2 * k;
+        for (int i = 0; i < k; ++i) dm.prime[i] = i;
+        DropAdd add{};
+        add.base = inner + ctw;         // inner_1, c0
+        add.sb = (long)t2 * ctw;
+        add.sr = ctw;
+        add.R = R2;
+        add.mask = 1;
+        for (int r = 0; r < R2; ++r) add.gal[r] = gal2[r];
+        CTL_TRY(keyswitch_batch(c, st, k, B, R2, inner, dm, false, keys2.data(), gal2.data(), add, rot2));
+        launch_add_terms(logn, inner, (long)t2 * ctw, rot2, (long)R2 * ctw, ctw, R2, acc, B, k, c->tab, st);
+        CTL_TRY(check_launch());
+        sum = acc;
+    }
+    return rescale_batch(c, st, k, B, sum, out);
+}
+
+// ---------------------------------------------------------------- model planning
+int plan_model(const ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, ctl_model *m) {
+    if (!layers || n_layers < 1 || n_layers > 8) return fail(CTL_EINVAL, "1..8 layers supported");
+    int tmax = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        const ctl_layer_desc &d = layers[l];
+        if (d.n_in < 1 || d.n_out < 1) return fail(CTL_EINVAL, "layer widths must be positive");
+        if (l > 0 && d.n_in != layers[l - 1].n_out) return fail(CTL_EINVAL, "layer widths do not chain");
+        const int t = std::max(d.n_in, d.n_out);
+        if (d.t1 < 1 || t % d.t1) return fail(CTL_EINVAL, "t1 must divide max(n_in, n_out)");
+        if (d.act != CTL_ACT_NONE && d.act != CTL_ACT_SQUARE) return fail(CTL_EINVAL, "unknown activation");
+        if (d.act == CTL_ACT_SQUARE && l == n_layers - 1)
+            return fail(CTL_EINVAL, "the activation is applied between layers only");
+        tmax = std::max(tmax, t);
+    }
+    m->block = 2 * tmax;
+    m->items = (c->hp.n / 2) / m->block;
+    if (m->items < 1) return fail(CTL_EINVAL, "layers wider than N/4 slots");
+    int k = c->hp.nq;
+    double scale = std::ldexp(1.0, c->hp.log2_scale);
+    m->scale_in = scale;
+    std::vector<int32_t> rots;
+    for (int l = 0; l < n_layers; ++l) {
+        const ctl_layer_desc &d = layers[l];
+        LayerPlan L;
+        L.n_in = d.n_in;
+        L.n_out = d.n_out;
+        L.t = std::max(d.n_in, d.n_out);
+        L.t1 = d.t1;
+        L.t2 = L.t / d.t1;
+        L.k = k;
+        L.act = d.act;
+        if (k < 2) return fail(CTL_ELEVEL, "modulus chain exhausted at layer " + std::to_string(l));
+        L.pt_scale = (double)c->hp.mods[k - 1];
+        // the 128-bit accumulation of t1 products must not overflow
+        for (int i = 0; i < k; ++i) {
+            const u128 sq = (u128)(c->hp.mods[i] - 1) * (c->hp.mods[i] - 1);
+            if (sq > (~(u128)0) / (u128)L.t1) return fail(CTL_EPARAM, "t1 too large for the prime sizes");
+        }
+        for (int j = 1; j < L.t1; ++j) rots.push_back(j);
+        for (int k2 = 1; k2 < L.t2; ++k2) rots.push_back(k2 * L.t1);
+        m->layers.push_back(L);
+        k -= 1;                                  // dense: rescale, scale unchanged
+        if (l + 1 < n_layers) {
+            if (d.act == CTL_ACT_SQUARE) {
+                if (k < 2) return fail(CTL_ELEVEL, "modulus chain exhausted before x^2");
+                scale = scale * scale / (double)c->hp.mods[k - 1];
+                k -= 1;
+            }
+            rots.push_back(-std::max(layers[l + 1].n_in, layers[l + 1].n_out));
+        }
+    }
+    if (k < 1) return fail(CTL_ELEVEL, "modulus chain exhausted");
+    m->k_out = k;
+    m->scale_out = scale;
+    std::set<int32_t> seen;
+    for (int32_t r : rots)
+        if (seen.insert(r).second) m->rotations.push_back(r);
+    return CTL_OK;
+}
+
+// diag'_i of Eq. (1) on its support: in every item block, slot k2 t1 + s holds M[s][(s + i) mod t].
+void diag_slots(const ctl_model *m, const LayerPlan &L, const double *W, int i, int half_n, double *z) {
+    std::fill(z, z + half_n, 0.0);
+    const int k2 = i / L.t1;
+    for (int b = 0; b < m->items; ++b) {
+        double *blk = z + (long)b * m->block + (long)k2 * L.t1;
+        for (int s = 0; s < L.t; ++s) {
+            const int col = (s + i) % L.t;
+            blk[s] = (s < L.n_out && col < L.n_in) ? W[(long)s * L.n_in + col] : 0.0;
+        }
+    }
+}
+
+int encode_to_int(const ctl_ctx *c, const double *z, double scale, int64_t *out) {
+    const int n = c->hp.n;
+    std::vector<double> m(n);
+    c->enc->encode_real(z, m.data());
+    for (int i = 0; i < n; ++i) {
+        const double v = std::nearbyint(scale * m[i]);
+        if (!(std::fabs(v) < 4611686018427387904.0)) return fail(CTL_ESCALE, "encoded coefficient reaches 2^62");
+        out[i] = (int64_t)v;
+    }
+    return CTL_OK;
+}
+
+// Upload signed coefficients [G][N] and transform them to primes 0..k-1: out [G][k][N].
+int upload_ints(ctl_ctx *c, hipStream_t st, const int64_t *host, int G, int k, u64 *out) {
+    const long N = c->hp.n;
+    u64 *stage;
+    CTL_TRY(slot(c, S_MISC, (size_t)G * N, st, &stage));
+    CTL_HIP(hipMemcpyAsync(stage, host, (size_t)G * N * 8, hipMemcpyHostToDevice, st));
+    PrimeList pl{};
+    pl.n = k;
+    for (int i = 0; i < k; ++i) pl.idx[i] = i;
+    launch_int_ntt(c->hp.logn, reinterpret_cast<const int64_t *>(stage), out, G, pl, c->tab, st);
+    CTL_TRY(check_launch());
+    CTL_HIP(hipStreamSynchronize(st));
+    return CTL_OK;
+}
+
+int load_banks(ctl_ctx *c, ctl_model *m, const std::vector<std::vector<int64_t>> *ints,
+               const double *const *weights) {
+    hipStream_t st = nullptr;
+    const int n = c->hp.n;
+    for (size_t l = 0; l < m->layers.size(); ++l) {
+        const LayerPlan &L = m->layers[l];
+        u64 *bank = static_cast<u64 *>(dev_alloc(c, (size_t)L.t * L.k * n * 8, st));
+        if (!bank) return fail(CTL_ENOMEM, "plaintext bank allocation failed");
+        m->banks.push_back(bank);
+        const int chunk = 32;
+        std::vector<int64_t> buf((size_t)chunk * n);
+        std::vector<double> z(n / 2);
+        for (int i0 = 0; i0 < L.t; i0 += chunk) {
+            const int cnt = std::min(chunk, L.t - i0);
+            for (int i = 0; i < cnt; ++i) {
+                if (ints) {
+                    std::memcpy(&buf[(size_t)i * n], (*ints)[l].data() + (size_t)(i0 + i) * n, (size_t)n * 8);
+                } else {
+                    diag_slots(m, L, weights[l], i0 + i, n / 2, z.data());
+                    CTL_TRY(encode_to_int(c, z.data(), L.pt_scale, &buf[(size_t)i * n]));
+                }
+            }
+            CTL_TRY(upload_ints(c, st, buf.data(), cnt, L.k, bank + (size_t)i0 * L.k * n));
+        }
+    }
+    return CTL_OK;
+}
+
+int make_model(ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, const int64_t *const *pts,
+               const double *const *weights, ctl_model **out) {
+    if (!c || !out) return fail(CTL_EINVAL, "null argument");
+    std::unique_ptr<ctl_model> m(new (std::nothrow) ctl_model());
+    if (!m) return fail(CTL_ENOMEM, "host allocation failed");
+    m->ctx = c;
+    CTL_TRY(plan_model(c, layers, n_layers, m.get()));
+    CTL_HIP(hipSetDevice(c->device));
+    int rc;
+    if (pts) {
+        std::vector<std::vector<int64_t>> ints(n_layers);
+        for (int l = 0; l < n_layers; ++l) {
+            if (!pts[l]) return fail(CTL_EINVAL, "null plaintext array");
+            const size_t cnt = (size_t)m->layers[l].t * c->hp.n;
+            for (size_t x = 0; x < cnt; ++x)
+                if (pts[l][x] >= (int64_t)(1ull << 62) || pts[l][x] <= -(int64_t)(1ull << 62))
+                    return fail(CTL_ESCALE, "plaintext coefficient out of range");
+            ints[l].assign(pts[l], pts[l] + cnt);
+        }
+        rc = load_banks(c, m.get(), &ints, nullptr);
+    } else {
+        for (int l = 0; l < n_layers; ++l)
+            if (!weights[l]) return fail(CTL_EINVAL, "null weight matrix");
+        rc = load_banks(c, m.get(), nullptr, weights);
+    }
+    if (rc != CTL_OK) {
+        for (u64 *b : m->banks) dev_free(c, b, nullptr);
+        return rc;
+    }
+    *out = m.release();
+    return CTL_OK;
+}
+
+}  // namespace
+
+// =============================================================================== exported API
+extern "C" {
+
+const char *ctl_last_error(void) { return g_err.c_str(); }
+
+int ctl_params_primes(const ctl_params *params, uint64_t *primes_out, int *n_out) {
+    if (!params || !primes_out || !n_out) return fail(CTL_EINVAL, "null argument");
+    HostParams h;
+    CTL_TRY(derive_params(params, &h, &g_err));
+    for (int i = 0; i < h.np; ++i) primes_out[i] = h.mods[i];
+    *n_out = h.np;
+    return CTL_OK;
+}
+
+int ctl_galois_elt(const ctl_params *params, int rotation, uint64_t *g_out) {
+    if (!params || !g_out) return fail(CTL_EINVAL, "null argument");
+    if (params->log2n < 12 || params->log2n > 14) return fail(CTL_EPARAM, "log2n must be 12, 13 or 14");
+    *g_out = galois_elt(params->log2n, rotation);
+    return CTL_OK;
+}
+
+int ctl_sample(const ctl_params *params, uint64_t seed, uint32_t tag, uint64_t index, int kind,
+               uint64_t modulus, int n, int64_t *out) {
+    if (!params || !out || n < 0) return fail(CTL_EINVAL, "bad argument");
+    HostParams h;
+    CTL_TRY(derive_params(params, &h, &g_err));
+    Stream s(seed, tag, index);
+    if (kind == 0) s.ternary(n, out);
+    else if (kind == 1) s.gaussian(h.cdt, n, out);
+    else if (kind == 2) {
+        if (modulus < 2) return fail(CTL_EINVAL, "modulus must be at least 2");
+        for (int i = 0; i < n; ++i) out[i] = (int64_t)s.uniform(modulus);
+    } else return fail(CTL_EINVAL, "unknown sampler kind");
+    return CTL_OK;
+}
+
+int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
+    if (!params || !ctx_out) return fail(CTL_EINVAL, "null argument");
+    std::unique_ptr<ctl_ctx> c(new (std::nothrow) ctl_ctx());
+    if (!c) return fail(CTL_ENOMEM, "host allocation failed");
+    CTL_TRY(derive_params(params, &c->hp, &g_err));
+    c->device = device;
+    CTL_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    CTL_HIP(hipGetDeviceProperties(&prop, device));
+    const size_t lds_need = (size_t)(c->hp.n + c->hp.n / 32) * 8;
+    if (prop.sharedMemPerBlock < lds_need && prop.maxSharedMemoryPerMultiProcessor < lds_need)
+        return fail(CTL_EPARAM, "device LDS too small for N = " + std::to_string(c->hp.n));
+    const int n = c->hp.n, np = c->hp.np;
+    // tables: tw, tws, itw, itws [np][N]; PrimeConst [np]; CrossConst [kMaxMods][kMaxMods]
+    const size_t tw_words = (size_t)np * n;
+    const size_t bytes = 4 * tw_words * 8 + sizeof(PrimeConst) * kMaxMods + sizeof(CrossConst) * kMaxMods * kMaxMods;
+    std::vector<unsigned char> host(bytes, 0);
+    u64 *tw = reinterpret_cast<u64 *>(host.data());
+    u64 *tws = tw + tw_words, *itw = tws + tw_words, *itws = itw + tw_words;
+    PrimeConst *pc = reinterpret_cast<PrimeConst *>(itws + tw_words);
+    CrossConst *cross = reinterpret_cast<CrossConst *>(pc + kMaxMods);
+    std::vector<u64> pw(n), ipw(n);
+    for (int i = 0; i < np; ++i) {
+        const u64 q = c->hp.mods[i], psi = c->hp.psi[i], ipsi = h_invmod(psi, q);
+        pw[0] = ipw[0] = 1;
+        for (int e = 1; e < n; ++e) {
+            pw[e] = h_mulmod(pw[e - 1], psi, q);
+            ipw[e] = h_mulmod(ipw[e - 1], ipsi, q);
+        }
+        for (int m = 0; m < n; ++m) {
+            unsigned r = 0;
+            for (int b = 0; b < c->hp.logn; ++b) r |= ((m >> b) & 1u) << (c->hp.logn - 1 - b);
+            tw[(size_t)i * n + m] = pw[r];
+            tws[(size_t)i * n + m] = h_shoup(pw[r], q);
+            itw[(size_t)i * n + m] = ipw[r];
+            itws[(size_t)i * n + m] = h_shoup(ipw[r], q);
+        }
+        PrimeConst &p = pc[i];
+        p.q = q;
+        p.q2 = 2 * q;
+        p.r64 = (u64)(((u128)1 << 64) % q);
+        p.r64s = h_shoup(p.r64, q);
+        p.ones = (u64)(((u128)1 << 64) / q);
+        p.ninv = h_invmod((u64)n % q, q);
+        p.ninvs = h_shoup(p.ninv, q);
+        c->pc.push_back(p);
+    }
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) {
+            CrossConst &cc = cross[i * kMaxMods + j];
+            const u64 qi = c->hp.mods[i], qj = c->hp.mods[j];
+            cc.qj_mod_qi = qj % qi;
+            cc.inv = i == j ? 0 : h_invmod(qj % qi, qi);
+            cc.invs = h_shoup(cc.inv, qi);
+        }
+    void *dmem = nullptr;
+    CTL_HIP(hipMalloc(&dmem, bytes));
+    if (hipMemcpy(dmem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dmem);
+        return fail(CTL_EHIP, "table upload failed");
+    }
+    c->tables_mem = dmem;
+    u64 *d = static_cast<u64 *>(dmem);
+    c->tab.tw = d;
+    c->tab.tws = d + tw_words;
+    c->tab.itw = d + 2 * tw_words;
+    c->tab.itws = d + 3 * tw_words;
+    c->tab.pc = reinterpret_cast<const PrimeConst *>(d + 4 * tw_words);
+    c->tab.cross = reinterpret_cast<const CrossConst *>(c->tab.pc + kMaxMods);
+    if (kernels_prepare(c->hp.logn) != hipSuccess) {
+        (void)hipFree(dmem);
+        return fail(CTL_EHIP, "setting the LDS limit of the NTT kernels failed");
+    }
+    c->enc.reset(new Encoder(c->hp.logn));
+    *ctx_out = c.release();
+    return CTL_OK;
+}
+
+int ctl_ctx_free(ctl_ctx *ctx) {
+    if (!ctx) return CTL_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (int s = 0; s < S_COUNT; ++s) dev_free(ctx, ctx->slot_ptr[s], nullptr);
+    (void)hipFree(ctx->tables_mem);
+    delete ctx;
+    return CTL_OK;
+}
+
+int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out) {
+    if (!ctx || !primes_out || !n_out) return fail(CTL_EINVAL, "null argument");
+    for (int i = 0; i < ctx->hp.np; ++i) primes_out[i] = ctx->hp.mods[i];
+    *n_out = ctx->hp.np;
+    return CTL_OK;
+}
+
+int ctl_set_allocator(ctl_ctx *ctx, ctl_alloc_fn alloc, ctl_free_fn free_fn, void *user) {
+    if (!ctx) return fail(CTL_EINVAL, "null context");
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(CTL_EINVAL, "give both alloc and free");
+    for (int s = 0; s < S_COUNT; ++s)
+        if (ctx->slot_ptr[s]) return fail(CTL_EINVAL, "allocator must be set before the first allocation");
+    ctx->alloc = alloc;
+    ctx->free_fn = free_fn;
+    ctx->user = user;
+    return CTL_OK;
+}
+
+int ctl_workspace_bytes(const ctl_ctx *ctx, uint64_t *bytes_out) {
+    if (!ctx || !bytes_out) return fail(CTL_EINVAL, "null argument");
+    uint64_t t = 0;
+    for (int s = 0; s < S_COUNT; ++s) t += ctx->slot_bytes[s];
+    *bytes_out = t;
+    return CTL_OK;
+}
+
+int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, int inverse, void *stream) {
+    if (!ctx || (!dev && n_res) || (!prime_idx && n_res) || n_res < 0) return fail(CTL_EINVAL, "bad argument");
+    for (int r = 0; r < n_res; ++r)
+        if (prime_idx[r] < 0 || prime_idx[r] >= ctx->hp.np) return fail(CTL_EINVAL, "prime index out of range");
+    CTL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    const long N = ctx->hp.n;
+    for (int r0 = 0; r0 < n_res; r0 += kMaxMods) {
+        const int cnt = std::min(kMaxMods, n_res - r0);
+        ResMap m{};
+        m.per = cnt;
+        m.ngrp = 1;
+        m.off = 0;
+        m.gstride = cnt;
+        m.ostride = cnt;
+        for (int i = 0; i < cnt; ++i) m.prime[i] = prime_idx[r0 + i];
+        u64 *p = reinterpret_cast<u64 *>(dev) + (size_t)r0 * N;
+        launch_ntt(ctx->hp.logn, inverse != 0, p, m, p, m, cnt, ctx->tab, st);
+        CTL_TRY(check_launch());
+    }
+    return CTL_OK;
+}
+
+// ---------------------------------------------------------------- keys
+int ctl_keygen(ctl_ctx *ctx, uint64_t seed, const int32_t *rotations, int n_rot, int relin,
+               ctl_sk **sk_out, ctl_pk **pk_out, ctl_evk **evk_out) {
+    if (!ctx || (n_rot > 0 && !rotations) || n_rot < 0) return fail(CTL_EINVAL, "bad argument");
+    CTL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = nullptr;
+    const int n = ctx->hp.n, nq = ctx->hp.nq, np = ctx->hp.np, logn = ctx->hp.logn;
+    std::unique_ptr<ctl_sk> sk(new ctl_sk());
+    sk->ctx = ctx;
+    sk->s.resize(n);
+    Stream(seed, TAG_SK, 0).ternary(n, sk->s.data());
+    sk->d_s = static_cast<u64 *>(dev_alloc(ctx, (size_t)np * n * 8, st));
+    if (!sk->d_s) return fail(CTL_ENOMEM, "secret key allocation failed");
+    {
+        u64 *stage;
+        CTL_TRY(slot(ctx, S_MISC, (size_t)n, st, &stage));
+        CTL_HIP(hipMemcpy(stage, sk->s.data(), (size_t)n * 8, hipMemcpyHostToDevice));
+        PrimeList pl{};
+        pl.n = np;
+        for (int i = 0; i < np; ++i) pl.idx[i] = i;
+        launch_int_ntt(logn, reinterpret_cast<const int64_t *>(stage), sk->d_s, 1, pl, ctx->tab, st);
+        CTL_TRY(check_launch());
+        CTL_HIP(hipStreamSynchronize(st));
+    }
+    std::unique_ptr<ctl_pk> pk;
+    if (pk_out) {
+        pk.reset(new ctl_pk());
+        pk->ctx = ctx;
+        pk->d_pk = static_cast<u64 *>(dev_alloc(ctx, (size_t)2 * nq * n * 8, st));
+        if (!pk->d_pk) return fail(CTL_ENOMEM, "public key allocation failed");
+        std::vector<u64> a((size_t)nq * n);
+        Stream sa(seed, TAG_PK_A, 0);
+        for (int i = 0; i < nq; ++i)
+            for (int x = 0; x < n; ++x) a[(size_t)i * n + x] = sa.uniform(ctx->hp.mods[i]);
+        std::vector<int64_t> e(n);
+        Stream(seed, TAG_PK_E, 0).gaussian(ctx->hp.cdt, n, e.data());
+        CTL_HIP(hipMemcpy(pk->d_pk + (size_t)nq * n, a.data(), (size_t)nq * n * 8, hipMemcpyHostToDevice));
+        u64 *en;
+        CTL_TRY(slot(ctx, S_COEF, (size_t)nq * n, st, &en));
+        CTL_TRY(upload_ints(ctx, st, e.data(), 1, nq, en));
+        launch_pk_body(logn, pk->d_pk, en, sk->d_s, nq, ctx->tab, st);
+        CTL_TRY(check_launch());
+        CTL_HIP(hipStreamSynchronize(st));
+    }
+    std::unique_ptr<ctl_evk> evk;
+    if (evk_out) {
+        evk.reset(new ctl_evk());
+        evk->ctx = ctx;
+        std::vector<u64> gals;
+        for (int r = 0; r < n_rot; ++r) {
+            const u64 g = galois_elt(logn, rotations[r]);
+            if (g != 1 && std::find(gals.begin(), gals.end(), g) == gals.end()) gals.push_back(g);
+        }
+        if (relin) gals.push_back(0);
+        const size_t key_words = (size_t)nq * 2 * np * n;
+        std::vector<u64> hk(key_words);
+        std::vector<int64_t> e((size_t)nq * n);
+        u64 *en;
+        CTL_TRY(slot(ctx, S_DIG, (size_t)nq * np * n, st, &en));
+        PrimeList pl{};
+        pl.n = np;
+        for (int i = 0; i < np; ++i) pl.idx[i] = i;
+        for (u64 g : gals) {
+            for (int j = 0; j < nq; ++j) {
+                Stream sa(seed, TAG_KS_A, g * 64 + (u64)j);
+                for (int i = 0; i < np; ++i) {
+                    u64 *a = &hk[((size_t)(j * 2 + 1) * np + i) * n];
+                    for (int x = 0; x < n; ++x) a[x] = sa.uniform(ctx->hp.mods[i]);
+                }
+                Stream(seed, TAG_KS_E, g * 64 + (u64)j).gaussian(ctx->hp.cdt, n, &e[(size_t)j * n]);
+            }
+            u64 *key = static_cast<u64 *>(dev_alloc(ctx, key_words * 8, st));
+            if (!key) {
+                for (auto &kv : evk->keys) dev_free(ctx, kv.second, st);
+                return fail(CTL_ENOMEM, "Galois key allocation failed");
+            }
+            evk->keys[g] = key;
+            CTL_HIP(hipMemcpy(key, hk.data(), key_words * 8, hipMemcpyHostToDevice));
+            u64 *stage;
+            CTL_TRY(slot(ctx, S_MISC, (size_t)nq * n, st, &stage));
+            CTL_HIP(hipMemcpy(stage, e.data(), (size_t)nq * n * 8, hipMemcpyHostToDevice));
+            launch_int_ntt(logn, reinterpret_cast<const int64_t *>(stage), en, nq, pl, ctx->tab, st);
+            launch_ksk_body(logn, key, en, sk->d_s, g, nq, ctx->tab, st);
+            CTL_TRY(check_launch());
+            CTL_HIP(hipStreamSynchronize(st));
+        }
+    }
+    if (sk_out) *sk_out = sk.release();
+    else { dev_free(ctx, sk->d_s, st); }
+    if (pk_out) *pk_out = pk.release();
+    if (evk_out) *evk_out = evk.release();
+    return CTL_OK;
+}
+
+int ctl_sk_free(ctl_sk *sk) {
+    if (!sk) return CTL_OK;
+    dev_free(sk->ctx, sk->d_s, nullptr);
+    delete sk;
+    return CTL_OK;
+}
+
+int ctl_pk_free(ctl_pk *pk) {
+    if (!pk) return CTL_OK;
+    dev_free(pk->ctx, pk->d_pk, nullptr);
+    delete pk;
+    return CTL_OK;
+}
+
+int ctl_evk_free(ctl_evk *evk) {
+    if (!evk) return CTL_OK;
+    for (auto &kv : evk->keys) dev_free(evk->ctx, kv.second, nullptr);
+    delete evk;
+    return CTL_OK;
+}
+
+int ctl_sk_export(const ctl_sk *sk, int64_t *coeffs_out) {
+    if (!sk || !coeffs_out) return fail(CTL_EINVAL, "null argument");
+    std::memcpy(coeffs_out, sk->s.data(), sk->s.size() * 8);
+    return CTL_OK;
+}
+
+int ctl_pk_export(const ctl_pk *pk, uint64_t *out) {
+    if (!pk || !out) return fail(CTL_EINVAL, "null argument");
+    CTL_HIP(hipSetDevice(pk->ctx->device));
+    CTL_HIP(hipMemcpy(out, pk->d_pk, (size_t)2 * pk->ctx->hp.nq * pk->ctx->hp.n * 8, hipMemcpyDeviceToHost));
+    return CTL_OK;
+}
+
+int ctl_evk_export(const ctl_evk *evk, uint64_t galois_elt_, uint64_t *out) {
+    if (!evk || !out) return fail(CTL_EINVAL, "null argument");
+    const u64 *k = find_key(evk, galois_elt_);
+    if (!k) return fail(CTL_EKEY, "no key for this Galois element");
+    const HostParams &h = evk->ctx->hp;
+    CTL_HIP(hipSetDevice(evk->ctx->device));
+    CTL_HIP(hipMemcpy(out, k, (size_t)h.nq * 2 * h.np * h.n * 8, hipMemcpyDeviceToHost));
+    return CTL_OK;
+}
+
+int ctl_evk_galois(const ctl_evk *evk, uint64_t *elts_out, int *n_out) {
+    if (!evk || !n_out) return fail(CTL_EINVAL, "null argument");
+    int i = 0;
+    for (auto &kv : evk->keys) {
+        if (elts_out) elts_out[i] = kv.first;
+        ++i;
+    }
+    *n_out = i;
+    return CTL_OK;
+}
+
+// ---------------------------------------------------------------- model
+int ctl_model_load(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers, const double *const *weights,
+                   ctl_model **model_out) {
+    if (!weights) return fail(CTL_EINVAL, "null weights");
+    return make_model(ctx, layers, n_layers, nullptr, weights, model_out);
+}
+
+int ctl_model_load_raw(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers, const int64_t *const *pts,
+                       ctl_model **model_out) {
+    if (!pts) return fail(CTL_EINVAL, "null plaintexts");
+    return make_model(ctx, layers, n_layers, pts, nullptr, model_out);
+}
+
+int ctl_model_free(ctl_model *model) {
+    if (!model) return CTL_OK;
+    for (u64 *b : model->banks) dev_free(model->ctx, b, nullptr);
+    delete model;
+    return CTL_OK;
+}
+
+int ctl_model_get_info(const ctl_model *m, ctl_model_info *info) {
+    if (!m || !info) return fail(CTL_EINVAL, "null argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_layers = (int)m->layers.size();
+    info->block = m->block;
+    info->items = m->items;
+    info->k_in = m->layers[0].k;
+    info->k_out = m->k_out;
+    info->n_in = m->layers[0].n_in;
+    info->n_out = m->layers.back().n_out;
+    info->n_rotations = (int)m->rotations.size();
+    info->scale_in = m->scale_in;
+    info->scale_out = m->scale_out;
+    for (size_t l = 0; l < m->layers.size(); ++l) {
+        info->layer_k[l] = m->layers[l].k;
+        info->layer_t[l] = m->layers[l].t;
+    }
+    return CTL_OK;
+}
+
+int ctl_model_rotations(const ctl_model *m, int32_t *rots_out, int *n_out) {
+    if (!m || !n_out) return fail(CTL_EINVAL, "null argument");
+    if (rots_out) std::memcpy(rots_out, m->rotations.data(), m->rotations.size() * 4);
+    *n_out = (int)m->rotations.size();
+    return CTL_OK;
+}
+
+// ---------------------------------------------------------------- client encode / encrypt / decrypt
+int ctl_encode(ctl_ctx *ctx, const double *slots, double scale, int64_t *coeffs_out) {
+    if (!ctx || !slots || !coeffs_out) return fail(CTL_EINVAL, "null argument");
+    if (!(scale > 0) || !std::isfinite(scale)) return fail(CTL_ESCALE, "scale must be positive");
+    std::vector<int64_t> tmp(ctx->hp.n);
+    CTL_TRY(encode_to_int(ctx, slots, scale, tmp.data()));
+    std::memcpy(coeffs_out, tmp.data(), tmp.size() * 8);
+    return CTL_OK;
+}
+
+int ctl_encode_items(ctl_ctx *ctx, const ctl_model *m, const double *x, int items, int64_t *coeffs_out) {
+    if (!ctx || !m || !x || !coeffs_out) return fail(CTL_EINVAL, "null argument");
+    if (items < 1 || items > m->items) return fail(CTL_EINVAL, "items must be in 1..model items");
+    const int n_in = m->layers[0].n_in, t = m->layers[0].t;
+    std::vector<double> z(ctx->hp.n / 2, 0.0);
+    for (int b = 0; b < items; ++b)
+        for (int s = 0; s < n_in; ++s) {
+            z[(size_t)b * m->block + s] = x[(size_t)b * n_in + s];
+            z[(size_t)b * m->block + t + s] = x[(size_t)b * n_in + s];
+        }
+    return ctl_encode(ctx, z.data(), m->scale_in, coeffs_out);
+}
+
+int ctl_encrypt(ctl_ctx *ctx, const ctl_pk *pk, const int64_t *coeffs, uint64_t seed, uint64_t *ct_out, void *stream) {
+    if (!ctx || !pk || !coeffs || !ct_out) return fail(CTL_EINVAL, "null argument");
+    CTL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    const int n = ctx->hp.n, nq = ctx->hp.nq;
+    for (int i = 0; i < n; ++i)
+        if (coeffs[i] >= (int64_t)(1ull << 62) || coeffs[i] <= -(int64_t)(1ull << 62))
+            return fail(CTL_ESCALE, "plaintext coefficient out of range");
+    std::vector<int64_t> h((size_t)4 * n);
+    Stream(seed, TAG_ENC_V, 0).ternary(n, &h[0]);
+    Stream(seed, TAG_ENC_E0, 0).gaussian(ctx->hp.cdt, n, &h[(size_t)n]);
+    Stream(seed, TAG_ENC_E1, 0).gaussian(ctx->hp.cdt, n, &h[(size_t)2 * n]);
+    std::memcpy(&h[(size_t)3 * n], coeffs, (size_t)n * 8);
+    u64 *t4;
+    CTL_TRY(slot(ctx, S_COEF2, (size_t)4 * nq * n, st, &t4));
+    CTL_TRY(upload_ints(ctx, st, h.data(), 4, nq, t4));
+    launch_encrypt(ctx->hp.logn, pk->d_pk, t4, reinterpret_cast<u64 *>(ct_out), nq, ctx->tab, st);
+    return check_launch();
+}
+
+int ctl_decrypt(ctl_ctx *ctx, const ctl_sk *sk, const uint64_t *ct, int k, uint64_t *residues_out, void *stream) {
+    if (!ctx || !sk || !ct || !residues_out) return fail(CTL_EINVAL, "null argument");
+    if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    CTL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    const long n = ctx->hp.n;
+    u64 *m;
+    CTL_TRY(slot(ctx, S_COEF2, (size_t)k * n, st, &m));
+    launch_dec_mul(ctx->hp.logn, reinterpret_cast<const u64 *>(ct), sk->d_s, m, k, ctx->tab, st);
+    launch_ntt(ctx->hp.logn, true, m, dense_map(k), m, dense_map(k), k, ctx->tab, st);
+    CTL_TRY(check_launch());
+    CTL_HIP(hipMemcpyAsync(residues_out, m, (size_t)k * n * 8, hipMemcpyDeviceToHost, st));
+    CTL_HIP(hipStreamSynchronize(st));
+    return CTL_OK;
+}
+
+int ctl_decode(ctl_ctx *ctx, const uint64_t *residues, int k, double scale, double *slots_out) {
+    if (!ctx || !residues || !slots_out) return fail(CTL_EINVAL, "null argument");
+    if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    if (!(scale > 0)) return fail(CTL_ESCALE, "scale must be positive");
+    const int n = ctx->hp.n;
+    std::vector<double> m(n);
+    u64 r[kMaxMods];
+    for (int x = 0; x < n; ++x) {
+        for (int i = 0; i < k; ++i) r[i] = residues[(size_t)i * n + x];
+        m[x] = crt_centered_double(r, ctx->hp.mods.data(), k) / scale;
+    }
+    ctx->enc->decode_real(m.data(), slots_out);
+    return CTL_OK;
+}
+
+int ctl_decode_items(ctl_ctx *ctx, const ctl_model *m, const uint64_t *residues, double *y_out) {
+    if (!ctx || !m || !residues || !y_out) return fail(CTL_EINVAL, "null argument");
+    std::vector<double> z(ctx->hp.n / 2);
+    CTL_TRY(ctl_decode(ctx, residues, m->k_out, m->scale_out, z.data()));
+    const int n_out = m->layers.back().n_out;
+    for (int b = 0; b < m->items; ++b)
+        for (int s = 0; s < n_out; ++s) y_out[(size_t)b * n_out + s] = z[(size_t)b * m->block + s];
+    return CTL_OK;
+}
+
+// ---------------------------------------------------------------- server hot path
+int ctl_dense(ctl_ctx *ctx, const ctl_model *model, int layer, const ctl_evk *evk, const uint64_t *in,
+              uint64_t *out, int n_ct, void *stream) {
+    if (!ctx || !model || !evk || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
+    if (layer < 0 || layer >= (int)model->layers.size()) return fail(CTL_EINVAL, "layer out of range");
+    CTL_HIP(hipSetDevice(ctx->device));
+    return dense_batch(ctx, as_stream(stream), model, layer, evk, n_ct, reinterpret_cast<const u64 *>(in),
+                       reinterpret_cast<u64 *>(out));
+}
+
+int ctl_square(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint64_t *out, int n_ct, void *stream) {
+    if (!ctx || !evk || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
+    if (k < 2 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    CTL_HIP(hipSetDevice(ctx->device));
+    return square_batch(ctx, as_stream(stream), evk, k, n_ct, reinterpret_cast<const u64 *>(in),
+                        reinterpret_cast<u64 *>(out));
+}
+
+int ctl_replicate(ctl_ctx *ctx, const ctl_evk *evk, int k, int width, const uint64_t *in, uint64_t *out,
+                  int n_ct, void *stream) {
+    if (!ctx || !evk || !in || !out || n_ct < 1 || width < 1) return fail(CTL_EINVAL, "bad argument");
+    if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    CTL_HIP(hipSetDevice(ctx->device));
+    return replicate_batch(ctx, as_stream(stream), evk, k, n_ct, width, reinterpret_cast<const u64 *>(in),
+                           reinterpret_cast<u64 *>(out));
+}
+
+int ctl_rotate(ctl_ctx *ctx, const ctl_evk *evk, int k, int rotation, const uint64_t *in, uint64_t *out,
+               int n_ct, void *stream) {
+    if (!ctx || !evk || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
+    if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    CTL_HIP(hipSetDevice(ctx->device));
+    return rotate_batch(ctx, as_stream(stream), evk, k, n_ct, rotation, reinterpret_cast<const u64 *>(in),
+                        reinterpret_cast<u64 *>(out));
+}
+
+int ctl_rescale(ctl_ctx *ctx, int k, const uint64_t *in, uint64_t *out, int n_ct, void *stream) {
+    if (!ctx || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
+    if (k < 2 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    CTL_HIP(hipSetDevice(ctx->device));
+    return rescale_batch(ctx, as_stream(stream), k, n_ct, reinterpret_cast<const u64 *>(in),
+                         reinterpret_cast<u64 *>(out));
+}
+
+int ctl_forward(ctl_ctx *ctx, const ctl_model *m, const ctl_evk *evk, const uint64_t *in, uint64_t *out,
+                int n_ct, void *stream) {
+    if (!ctx || !m || !evk || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
+    CTL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    const long N = ctx->hp.n;
+    const u64 *cur = reinterpret_cast<const u64 *>(in);
+    const size_t words = (size_t)n_ct * 2 * ctx->hp.nq * N;
+    u64 *a, *b, *c3;
+    CTL_TRY(slot(ctx, S_FWD_A, words, st, &a));
+    CTL_TRY(slot(ctx, S_FWD_B, words, st, &b));
+    CTL_TRY(slot(ctx, S_FWD_C, words, st, &c3));
+    const int L = (int)m->layers.size();
+    for (int l = 0; l < L; ++l) {
+        const LayerPlan &P = m->layers[l];
+        const bool last = l + 1 == L;
+        u64 *dst = last ? reinterpret_cast<u64 *>(out) : a;
+        CTL_TRY(dense_batch(ctx, st, m, l, evk, n_ct, cur, dst));
+        if (last) break;
+        int k = P.k - 1;
+        const u64 *x = dst;
+        if (P.act == CTL_ACT_SQUARE) {
+            CTL_TRY(square_batch(ctx, st, evk, k, n_ct, dst, b));
+            k -= 1;
+            x = b;
+        }
+        CTL_TRY(replicate_batch(ctx, st, evk, k, n_ct, m->layers[l + 1].t, x, c3));
+        cur = c3;
+    }
+    return CTL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Launch interface of the HIP kernels (device pointers, plain structs passed by value).
+#pragma once
+
+#include "ctl_internal.h"
+
+namespace ctl {
+
+// Residue r of a launch lives at offset (in residues) off + outer * ostride + grp * gstride + e,
+// where e = r % per, grp = (r / per) % ngrp, outer = r / (per * ngrp); its prime is prime[e].
+struct ResMap {
+    int per;
+    int ngrp;
+    long off;
+    long gstride;
+    long ostride;
+    int prime[kMaxMods];
+};
+
+struct Tables {
+    const u64 *tw, *tws, *itw, *itws;   // [np][N] each
+    const PrimeConst *pc;               // [np]
+    const CrossConst *cross;            // [kMaxMods][kMaxMods], entry [i * kMaxMods + j]
+};
+
+constexpr int kMaxKeysPerLaunch = 64;
+
+struct DropAdd {
+    const u64 *base;     // addend (NTT form) or null
+    long sb, sr, sc;     // strides in words for batch index b, group r, polynomial c
+    int R;               // groups per ciphertext (<= kMaxKeysPerLaunch)
+    int mask;            // bit c set: add to polynomial c
+    u64 gal[kMaxKeysPerLaunch];   // automorphism applied to the addend of group r (1 = none)
+};
+
+struct PrimeList {
+    int n;
+    int idx[kMaxMods];
+};
+
+struct KeyList {
+    const u64 *key[kMaxKeysPerLaunch];   // [nq][2][np][N] each
+    u64 gal[kMaxKeysPerLaunch];          // Galois element applied to the digits (1 = none)
+};
+
+hipError_t kernels_prepare(int logn);
+void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
+                int count, const Tables &tab, hipStream_t st);
+void launch_modup(int logn, const u64 *coef, u64 *digits, int groups, int k, int nq, const Tables &tab,
+                  hipStream_t st);
+void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
+                 const DropAdd &add, const Tables &tab, hipStream_t st);
+void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,
+                    const Tables &tab, hipStream_t st);
+void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
+                  u64 *out, int B, int nq, const Tables &tab, hipStream_t st);
+void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *inner, int B, int k,
+                int t1, int t2, const Tables &tab, hipStream_t st);
+void launch_add_terms(int logn, const u64 *a, long a_sb, const u64 *terms, long t_sb, long t_ss, int S,
+                      u64 *out, int B, int k, const Tables &tab, hipStream_t st);
+void launch_tensor(int logn, const u64 *in, u64 *out, int B, int k, const Tables &tab, hipStream_t st);
+void launch_ksk_body(int logn, u64 *key, const u64 *e, const u64 *s, u64 g, int nq, const Tables &tab,
+                     hipStream_t st);
+void launch_pk_body(int logn, u64 *pk, const u64 *e, const u64 *s, int nq, const Tables &tab, hipStream_t st);
+void launch_encrypt(int logn, const u64 *pk, const u64 *in, u64 *ct, int nq, const Tables &tab, hipStream_t st);
+void launch_dec_mul(int logn, const u64 *ct, const u64 *s, u64 *out, int k, const Tables &tab, hipStream_t st);
+
+}  // namespace ctl

@@ -1,0 +1,665 @@
+// HIP kernels of libcryptotl for CDNA4 (gfx950, wave64).
+//
+// All arithmetic is exact modular integer arithmetic on 64-bit residues (primes < 2^61), done on
+// the integer VALU: products by fixed operands (twiddles, inverses) use Shoup's precomputed
+// quotient, products of two variables and sums of products use a 128-bit accumulator reduced
+// once (2^64 mod q and floor(2^64/q) as Shoup constants). No matrix cores: nothing here is a
+// floating-point contraction.
+//
+// NTT layout: negacyclic, bit-reversed evaluation order (slot i = a(psi^{2 brv(i)+1})), computed
+// with Cooley-Tukey butterflies forward and Gentleman-Sande inverse, twiddles psi^{brv(m)} taken
+// from per-prime tables. One workgroup transforms one residue polynomial: N/16 threads hold 16
+// values each in registers; each pass runs 4 (or 3) butterfly stages in registers and exchanges
+// through LDS between passes, so a residue makes a single HBM round trip.
+#include "ctl_internal.h"
+#include "kernels.h"
+
+namespace ctl {
+
+// ---------------------------------------------------------------- device arithmetic
+__device__ __forceinline__ u64 mulhi(u64 a, u64 b) { return __umul64hi(a, b); }
+
+// x * w mod q, result in [0, 2q), for any x < 2^64 and w < q with ws = floor(w 2^64 / q).
+__device__ __forceinline__ u64 shoup_lazy(u64 x, u64 w, u64 ws, u64 q) { return x * w - mulhi(x, ws) * q; }
+__device__ __forceinline__ u64 red2(u64 x, u64 q) { return x >= q ? x - q : x; }
+__device__ __forceinline__ u64 red4(u64 x, u64 q, u64 q2) {
+    x = x >= q2 ? x - q2 : x;
+    return x >= q ? x - q : x;
+}
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) { return red2(a + b, q); }
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+__device__ __forceinline__ u64 neg_mod(u64 a, u64 q) { return a ? q - a : 0; }
+
+struct Acc {
+    u64 lo, hi;
+};
+__device__ __forceinline__ void acc_zero(Acc &a) { a.lo = 0; a.hi = 0; }
+__device__ __forceinline__ void acc_mac(Acc &a, u64 x, u64 y) {
+    const u64 l = x * y, h = mulhi(x, y);
+    a.lo += l;
+    a.hi += h + (a.lo < l ? 1ull : 0ull);
+}
+// (hi 2^64 + lo) mod q
+__device__ __forceinline__ u64 acc_reduce(const Acc &a, const PrimeConst &p) {
+    const u64 r1 = shoup_lazy(a.hi, p.r64, p.r64s, p.q);
+    const u64 r2 = a.lo - mulhi(a.lo, p.ones) * p.q;
+    return red4(r1 + r2, p.q, p.q2);
+}
+__device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const PrimeConst &p) {
+    Acc t;
+    t.lo = a * b;
+    t.hi = mulhi(a, b);
+    return acc_reduce(t, p);
+}
+// x mod q for any x < 2^64
+__device__ __forceinline__ u64 reduce_any(u64 x, const PrimeConst &p) {
+    return red2(x - mulhi(x, p.ones) * p.q, p.q);
+}
+// centered lift of x in [0, qf) to modulus p: x > (qf-1)/2 stands for x - qf
+__device__ __forceinline__ u64 lift_centered(u64 x, u64 qf, u64 qf_mod, const PrimeConst &p) {
+    const u64 y = reduce_any(x, p);
+    return x > (qf >> 1) ? sub_mod(y, qf_mod, p.q) : y;
+}
+
+// Index gathered by the automorphism X -> X^g in bit-reversed NTT order:
+// out[i] = in[brv((g (2 brv(i) + 1) mod 2N - 1) / 2)].
+__device__ __forceinline__ int galois_src(int i, u64 g, int logn) {
+    const unsigned n = 1u << logn;
+    const unsigned e = (__brev((unsigned)i) >> (32 - logn));
+    const unsigned t = (unsigned)((g * (2ull * e + 1)) & (2ull * n - 1));
+    return (int)(__brev((t - 1) >> 1) >> (32 - logn));
+}
+
+// ---------------------------------------------------------------- NTT engine
+template <int LOGN>
+struct Geo {
+    static constexpr int N = 1 << LOGN;
+    static constexpr int T = N / 16;   // threads per residue
+};
+
+__device__ __forceinline__ int lds_idx(int j) { return j + (j >> 5); }
+
+template <int LOGN>
+constexpr int lds_words() { return (1 << LOGN) + ((1 << LOGN) >> 5); }
+
+// element index of slot (g, e) of a pass over bits [LO, LO + RB)
+template <int LOGN, int LO, int RB>
+__device__ __forceinline__ int pass_index(int g, int e, int tid) {
+    const int rest = g * Geo<LOGN>::T + tid;
+    return ((rest >> LO) << (LO + RB)) | (e << LO) | (rest & ((1 << LO) - 1));
+}
+
+template <int LOGN, int LO, int RB>
+__device__ __forceinline__ void to_lds(const u64 (&v)[16], u64 *lds, int tid) {
+    constexpr int R = 1 << RB, G = 16 / R;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int e = 0; e < R; ++e) lds[lds_idx(pass_index<LOGN, LO, RB>(g, e, tid))] = v[g * R + e];
+}
+
+template <int LOGN, int LO, int RB>
+__device__ __forceinline__ void from_lds(u64 (&v)[16], const u64 *lds, int tid) {
+    constexpr int R = 1 << RB, G = 16 / R;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int e = 0; e < R; ++e) v[g * R + e] = lds[lds_idx(pass_index<LOGN, LO, RB>(g, e, tid))];
+}
+
+// Cooley-Tukey stages over bits LO+RB-1 .. LO. Values enter and leave in [0, 4q).
+template <int LOGN, int LO, int RB>
+__device__ __forceinline__ void fwd_pass(u64 (&v)[16], int tid, const u64 *__restrict__ tw,
+                                         const u64 *__restrict__ tws, u64 q, u64 q2) {
+    constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int hi = (g * Geo<LOGN>::T + tid) >> LO;
+#pragma unroll
+        for (int sb = RB - 1; sb >= 0; --sb) {
+            const int b = LO + sb, half = 1 << sb;
+#pragma unroll
+            for (int e = 0; e < R; ++e) {
+                if (e & half) continue;
+                const int widx = (N >> (b + 1)) + ((hi << (RB - 1 - sb)) | (e >> (sb + 1)));
+                const u64 w = tw[widx], ws = tws[widx];
+                u64 x = v[g * R + e];
+                x = x >= q2 ? x - q2 : x;
+                const u64 t = shoup_lazy(v[g * R + e + half], w, ws, q);
+                v[g * R + e] = x + t;
+                v[g * R + e + half] = x - t + q2;
+            }
+        }
+    }
+}
+
+// Gentleman-Sande stages over bits LO .. LO+RB-1. Values enter and leave in [0, 2q).
+template <int LOGN, int LO, int RB>
+__device__ __forceinline__ void inv_pass(u64 (&v)[16], int tid, const u64 *__restrict__ tw,
+                                         const u64 *__restrict__ tws, u64 q, u64 q2) {
+    constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int hi = (g * Geo<LOGN>::T + tid) >> LO;
+#pragma unroll
+        for (int sb = 0; sb < RB; ++sb) {
+            const int b = LO + sb, half = 1 << sb;
+#pragma unroll
+            for (int e = 0; e < R; ++e) {
+                if (e & half) continue;
+                const int widx = (N >> (b + 1)) + ((hi << (RB - 1 - sb)) | (e >> (sb + 1)));
+                const u64 w = tw[widx], ws = tws[widx];
+                const u64 x = v[g * R + e], y = v[g * R + e + half];
+                u64 s = x + y;
+                s = s >= q2 ? s - q2 : s;
+                v[g * R + e] = s;
+                v[g * R + e + half] = shoup_lazy(x - y + q2, w, ws, q);
+            }
+        }
+    }
+}
+
+// Pass plans (bit ranges, lowest bit first for each pass):
+//   N = 2^12: [8,12) [4,8) [0,4)      N = 2^13: [9,13) [6,9) [3,6) [0,3)
+//   N = 2^14: [10,14) [6,10) [3,6) [0,3)
+// Forward: v holds elements j = tid + T e on entry; on exit the transformed residue is in LDS
+// (lds_idx(j)), values in [0, 4q), after a barrier.
+template <int LOGN>
+__device__ __forceinline__ void ntt_fwd_core(u64 (&v)[16], u64 *lds, int tid, const u64 *tw,
+                                             const u64 *tws, u64 q, u64 q2) {
+    if constexpr (LOGN == 12) {
+        fwd_pass<12, 8, 4>(v, tid, tw, tws, q, q2);
+        to_lds<12, 8, 4>(v, lds, tid); __syncthreads();
+        from_lds<12, 4, 4>(v, lds, tid); fwd_pass<12, 4, 4>(v, tid, tw, tws, q, q2);
+        to_lds<12, 4, 4>(v, lds, tid); __syncthreads();
+        from_lds<12, 0, 4>(v, lds, tid); fwd_pass<12, 0, 4>(v, tid, tw, tws, q, q2);
+        to_lds<12, 0, 4>(v, lds, tid); __syncthreads();
+    } else if constexpr (LOGN == 13) {
+        fwd_pass<13, 9, 4>(v, tid, tw, tws, q, q2);
+        to_lds<13, 9, 4>(v, lds, tid); __syncthreads();
+        from_lds<13, 6, 3>(v, lds, tid); fwd_pass<13, 6, 3>(v, tid, tw, tws, q, q2);
+        to_lds<13, 6, 3>(v, lds, tid); __syncthreads();
+        from_lds<13, 3, 3>(v, lds, tid); fwd_pass<13, 3, 3>(v, tid, tw, tws, q, q2);
+        to_lds<13, 3, 3>(v, lds, tid); __syncthreads();
+        from_lds<13, 0, 3>(v, lds, tid); fwd_pass<13, 0, 3>(v, tid, tw, tws, q, q2);
+        to_lds<13, 0, 3>(v, lds, tid); __syncthreads();
+    } else {
+        static_assert(LOGN == 14, "unsupported ring degree");
+        fwd_pass<14, 10, 4>(v, tid, tw, tws, q, q2);
+        to_lds<14, 10, 4>(v, lds, tid); __syncthreads();
+        from_lds<14, 6, 4>(v, lds, tid); fwd_pass<14, 6, 4>(v, tid, tw, tws, q, q2);
+        to_lds<14, 6, 4>(v, lds, tid); __syncthreads();
+        from_lds<14, 3, 3>(v, lds, tid); fwd_pass<14, 3, 3>(v, tid, tw, tws, q, q2);
+        to_lds<14, 3, 3>(v, lds, tid); __syncthreads();
+        from_lds<14, 0, 3>(v, lds, tid); fwd_pass<14, 0, 3>(v, tid, tw, tws, q, q2);
+        to_lds<14, 0, 3>(v, lds, tid); __syncthreads();
+    }
+}
+
+// Inverse: the residue (values in [0, 2q)) is in LDS at lds_idx(j) after a barrier on entry; on
+// exit v holds elements j = tid + T e, values in [0, 2q), not yet multiplied by N^{-1}.
+template <int LOGN>
+__device__ __forceinline__ void ntt_inv_core(u64 (&v)[16], u64 *lds, int tid, const u64 *tw,
+                                             const u64 *tws, u64 q, u64 q2) {
+    if constexpr (LOGN == 12) {
+        from_lds<12, 0, 4>(v, lds, tid); inv_pass<12, 0, 4>(v, tid, tw, tws, q, q2);
+        to_lds<12, 0, 4>(v, lds, tid); __syncthreads();
+        from_lds<12, 4, 4>(v, lds, tid); inv_pass<12, 4, 4>(v, tid, tw, tws, q, q2);
+        to_lds<12, 4, 4>(v, lds, tid); __syncthreads();
+        from_lds<12, 8, 4>(v, lds, tid); inv_pass<12, 8, 4>(v, tid, tw, tws, q, q2);
+    } else if constexpr (LOGN == 13) {
+        from_lds<13, 0, 3>(v, lds, tid); inv_pass<13, 0, 3>(v, tid, tw, tws, q, q2);
+        to_lds<13, 0, 3>(v, lds, tid); __syncthreads();
+        from_lds<13, 3, 3>(v, lds, tid); inv_pass<13, 3, 3>(v, tid, tw, tws, q, q2);
+        to_lds<13, 3, 3>(v, lds, tid); __syncthreads();
+        from_lds<13, 6, 3>(v, lds, tid); inv_pass<13, 6, 3>(v, tid, tw, tws, q, q2);
+        to_lds<13, 6, 3>(v, lds, tid); __syncthreads();
+        from_lds<13, 9, 4>(v, lds, tid); inv_pass<13, 9, 4>(v, tid, tw, tws, q, q2);
+    } else {
+        static_assert(LOGN == 14, "unsupported ring degree");
+        from_lds<14, 0, 3>(v, lds, tid); inv_pass<14, 0, 3>(v, tid, tw, tws, q, q2);
+        to_lds<14, 0, 3>(v, lds, tid); __syncthreads();
+        from_lds<14, 3, 3>(v, lds, tid); inv_pass<14, 3, 3>(v, tid, tw, tws, q, q2);
+        to_lds<14, 3, 3>(v, lds, tid); __syncthreads();
+        from_lds<14, 6, 4>(v, lds, tid); inv_pass<14, 6, 4>(v, tid, tw, tws, q, q2);
+        to_lds<14, 6, 4>(v, lds, tid); __syncthreads();
+        from_lds<14, 10, 4>(v, lds, tid); inv_pass<14, 10, 4>(v, tid, tw, tws, q, q2);
+    }
+}
+
+__device__ __forceinline__ long res_offset(const ResMap &m, int r) {
+    const int e = r % m.per, t = r / m.per;
+    return m.off + (long)(t / m.ngrp) * m.ostride + (long)(t % m.ngrp) * m.gstride + e;
+}
+
+// ---------------------------------------------------------------- NTT kernels
+template <int LOGN>
+__global__ void __launch_bounds__(Geo<LOGN>::T)
+k_ntt_fwd(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap omap, Tables tab) {
+    extern __shared__ u64 lds[];
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
+    const int tid = threadIdx.x, r = blockIdx.x;
+    const int pi = imap.prime[r % imap.per];
+    const PrimeConst p = tab.pc[pi];
+    const u64 *src = in + res_offset(imap, r) * N;
+    u64 *dst = out + res_offset(omap, r) * N;
+    u64 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = src[tid + T * e];
+    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pi * N, tab.tws + (long)pi * N, p.q, p.q2);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) dst[tid + T * e] = red4(lds[lds_idx(tid + T * e)], p.q, p.q2);
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(Geo<LOGN>::T)
+k_ntt_inv(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap omap, Tables tab) {
+    extern __shared__ u64 lds[];
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
+    const int tid = threadIdx.x, r = blockIdx.x;
+    const int pi = imap.prime[r % imap.per];
+    const PrimeConst p = tab.pc[pi];
+    const u64 *src = in + res_offset(imap, r) * N;
+    u64 *dst = out + res_offset(omap, r) * N;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) lds[lds_idx(tid + T * e)] = src[tid + T * e];
+    __syncthreads();
+    u64 v[16];
+    ntt_inv_core<LOGN>(v, lds, tid, tab.itw + (long)pi * N, tab.itws + (long)pi * N, p.q, p.q2);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) dst[tid + T * e] = red2(shoup_lazy(v[e], p.ninv, p.ninvs, p.q), p.q);
+}
+
+// ModUp: coef is dense [G][k][N] coefficient form; digit j of group g is lifted (centered) from
+// q_j to every target t in 0..k (t = k is the special prime) and transformed:
+// digits[g][j][t] (NTT form). One workgroup per (g, j, t).
+template <int LOGN>
+__global__ void __launch_bounds__(Geo<LOGN>::T)
+k_modup(const u64 *__restrict__ coef, u64 *__restrict__ digits, int k, int nq, Tables tab) {
+    extern __shared__ u64 lds[];
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
+    const int tid = threadIdx.x;
+    const int t = blockIdx.x % (k + 1);
+    const int gj = blockIdx.x / (k + 1);      // g * k + j
+    const int j = gj % k;
+    const int pt = t < k ? t : nq;
+    const PrimeConst p = tab.pc[pt];
+    const u64 qj = tab.pc[j].q;
+    const u64 qj_mod = tab.cross[pt * kMaxMods + j].qj_mod_qi;
+    const u64 *src = coef + (long)gj * N;
+    u64 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qj, qj_mod, p);
+    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pt * N, tab.tws + (long)pt * N, p.q, p.q2);
+    u64 *dst = digits + ((long)gj * (k + 1) + t) * N;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) dst[tid + T * e] = red4(lds[lds_idx(tid + T * e)], p.q, p.q2);
+}
+
+// Drop the last modulus of each group (ModDown when it is P, rescale when it is q_k):
+//   out[g][i] = (x[g][i] - NTT_i(lift(last[g]))) * m_last^{-1} mod q_i  (+ addend)
+// x: [G][k+1][N] NTT form (only i < k read); last: dense [G][N] coefficient form mod m_last;
+// out: [G][k][N]. Groups are (b, r, c) with G = B R 2; the addend for polynomial c (if bit c of
+// add_mask) is read at add + b sb + r sr + c sc + i N, gathered through sigma_{gal[r]}.
+template <int LOGN>
+__global__ void __launch_bounds__(Geo<LOGN>::T)
+k_drop(const u64 *__restrict__ x, const u64 *__restrict__ last, u64 *__restrict__ out, int k,
+       int drop, DropAdd add, Tables tab) {
+    extern __shared__ u64 lds[];
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x % k;
+    const int grp = blockIdx.x / k;
+    const PrimeConst p = tab.pc[i];
+    const u64 qd = tab.pc[drop].q;
+    const CrossConst cc = tab.cross[i * kMaxMods + drop];
+    const u64 *src = last + (long)grp * N;
+    u64 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qd, cc.qj_mod_qi, p);
+    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)i * N, tab.tws + (long)i * N, p.q, p.q2);
+    const u64 *xi = x + ((long)grp * (k + 1) + i) * N;
+    u64 *dst = out + ((long)grp * k + i) * N;
+    const int c = grp & 1, r = (grp >> 1) % add.R, b = (grp >> 1) / add.R;
+    const bool has_add = (add.mask >> c) & 1;
+    const u64 *ap = has_add ? add.base + b * add.sb + r * add.sr + c * add.sc + (long)i * N : nullptr;
+    const u64 g = add.gal[r];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int jj = tid + T * e;
+        const u64 ext = red4(lds[lds_idx(jj)], p.q, p.q2);
+        u64 val = red2(shoup_lazy(sub_mod(xi[jj], ext, p.q), cc.inv, cc.invs, p.q), p.q);
+        if (has_add) val = add_mod(val, ap[g == 1 ? jj : galois_src(jj, g, LOGN)], p.q);
+        dst[jj] = val;
+    }
+}
+
+// Signed 64-bit coefficients -> residues mod q_p -> NTT. src: dense [G][N] int64; out: [G][P][N]
+// for the P prime indices plist[0..P).
+template <int LOGN>
+__global__ void __launch_bounds__(Geo<LOGN>::T)
+k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, Tables tab) {
+    extern __shared__ u64 lds[];
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
+    const int tid = threadIdx.x;
+    const int slot = blockIdx.x % pl.n, grp = blockIdx.x / pl.n;
+    const int pi = pl.idx[slot];
+    const PrimeConst p = tab.pc[pi];
+    const int64_t *s = src + (long)grp * N;
+    u64 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int64_t a = s[tid + T * e];
+        const u64 m = reduce_any((u64)(a < 0 ? -a : a), p);
+        v[e] = a < 0 ? neg_mod(m, p.q) : m;
+    }
+    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pi * N, tab.tws + (long)pi * N, p.q, p.q2);
+    u64 *dst = out + ((long)grp * pl.n + slot) * N;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) dst[tid + T * e] = red4(lds[lds_idx(tid + T * e)], p.q, p.q2);
+}
+
+// ---------------------------------------------------------------- elementwise kernels
+// Key inner product with the automorphism fused into the digit gather:
+//   out[b][r][0][t] = sum_j D[b][r][j][t][sigma_r] * key_r[j][0][t],  out[..][1][t] likewise with
+//   key_r[j][1][t]; t = 0..k (k = the special prime). D: digits + b db + r dr + (j (k+1) + t) N.
+// grid: x = N / 256 coefficient tiles, y = t, z = r. Each thread loops over the batch so a key
+// word is read from HBM once per launch.
+template <int K>
+__global__ void __launch_bounds__(256)
+k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__restrict__ out,
+        int B, int R, int nq, int logn, const PrimeConst *__restrict__ pcs) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int t = blockIdx.y, r = blockIdx.z;
+    const int N = 1 << logn, np = nq + 1;
+    const int pt = t < K ? t : nq;
+    const PrimeConst p = pcs[pt];
+    const u64 g = keys.gal[r];
+    const u64 *key = keys.key[r];
+    const int src = g == 1 ? n : galois_src(n, g, logn);
+    u64 kb[K], ka[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        kb[j] = key[((long)(j * 2 + 0) * np + pt) * N + n];
+        ka[j] = key[((long)(j * 2 + 1) * np + pt) * N + n];
+    }
+    for (int b = 0; b < B; ++b) {
+        const u64 *d = digits + b * db + r * dr + (long)t * N + src;
+        Acc a0, a1;
+        acc_zero(a0);
+        acc_zero(a1);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const u64 x = d[(long)j * (K + 1) * N];
+            acc_mac(a0, x, kb[j]);
+            acc_mac(a1, x, ka[j]);
+        }
+        u64 *o = out + ((long)(b * R + r) * 2) * (K + 1) * N + (long)t * N + n;
+        o[0] = acc_reduce(a0, p);
+        o[(long)(K + 1) * N] = acc_reduce(a1, p);
+    }
+}
+
+// Baby-step MAC of Eq. (1): inner[b][k2][c][i] = sum_{j < t1} pt[k2 t1 + j][i] * rot_j(ct_b)[c][i]
+// with rot_0 = ct itself (ct: [B][2][K][N]) and rot_j, j >= 1, in rot: [B][t1-1][2][K][N].
+// grid: x = N / 256 tiles, y = prime i, z = batch chunks of BC ciphertexts.
+template <int BC>
+__global__ void __launch_bounds__(256)
+k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__restrict__ bank,
+      u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn, const PrimeConst *__restrict__ pcs) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.y, b0 = blockIdx.z * BC;
+    const long N = 1L << logn;
+    const long kn = (long)k * N;
+    const PrimeConst p = pcs[i];
+    for (int k2 = 0; k2 < t2; ++k2) {
+        Acc acc[BC][2];
+#pragma unroll
+        for (int bb = 0; bb < BC; ++bb) { acc_zero(acc[bb][0]); acc_zero(acc[bb][1]); }
+        for (int j = 0; j < t1; ++j) {
+            const u64 w = bank[((long)(k2 * t1 + j)) * kn + i * N + n];
+#pragma unroll
+            for (int bb = 0; bb < BC; ++bb) {
+                const int b = b0 + bb;
+                if (b >= B) break;
+                const u64 *src = j == 0 ? ct + (long)b * 2 * kn
+                                        : rot + ((long)b * (t1 - 1) + (j - 1)) * 2 * kn;
+                acc_mac(acc[bb][0], w, src[i * N + n]);
+                acc_mac(acc[bb][1], w, src[kn + i * N + n]);
+            }
+        }
+#pragma unroll
+        for (int bb = 0; bb < BC; ++bb) {
+            const int b = b0 + bb;
+            if (b >= B) break;
+            u64 *o = inner + ((long)b * t2 + k2) * 2 * kn + i * N + n;
+            o[0] = acc_reduce(acc[bb][0], p);
+            o[kn] = acc_reduce(acc[bb][1], p);
+        }
+    }
+}
+
+// out[b][c][i] = a[b][c][i] + sum_{s < S} terms[b][s][c][i]; each operand ct-shaped [2][k][N].
+__global__ void __launch_bounds__(256)
+k_add_terms(const u64 *__restrict__ a, long a_sb, const u64 *__restrict__ terms, long t_sb, long t_ss,
+            int S, u64 *__restrict__ out, int k, int logn, const PrimeConst *__restrict__ pcs) {
+    const long N = 1L << logn;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;   // over 2 k N
+    const int b = blockIdx.y;
+    const int i = (int)((idx / N) % k);
+    const u64 q = pcs[i].q;
+    u64 s = a[b * a_sb + idx];
+    for (int t = 0; t < S; ++t) s = add_mod(s, terms[b * t_sb + t * t_ss + idx], q);
+    out[(long)b * 2 * k * N + idx] = s;
+}
+
+// (c0, c1) -> (c0^2, 2 c0 c1, c1^2): in [B][2][k][N], out [B][3][k][N].
+__global__ void __launch_bounds__(256)
+k_tensor(const u64 *__restrict__ in, u64 *__restrict__ out, int k, int logn, const PrimeConst *__restrict__ pcs) {
+    const long N = 1L << logn, kn = (long)k * N;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;   // over k N
+    const int b = blockIdx.y;
+    const PrimeConst p = pcs[idx / N];
+    const u64 c0 = in[b * 2 * kn + idx], c1 = in[b * 2 * kn + kn + idx];
+    u64 *o = out + b * 3 * kn + idx;
+    o[0] = mul_mod(c0, c0, p);
+    o[kn] = mul_mod(add_mod(c0, c0, p.q), c1, p);
+    o[2 * kn] = mul_mod(c1, c1, p);
+}
+
+// Key-switching key body: key[j][0][i] = -a s + e (+ [P]_{q_i} s'_i when i == j); a already at
+// key[j][1][i]; e: [nq][np][N] NTT form; s: [np][N]; sp (s' over q_0..q_{nq-1}) either given or
+// sigma_g(s) by gather (g != 0) or s^2 (g == 0).
+__global__ void __launch_bounds__(256)
+k_ksk_body(u64 *__restrict__ key, const u64 *__restrict__ e, const u64 *__restrict__ s, u64 g,
+           int nq, int logn, const PrimeConst *__restrict__ pcs, const CrossConst *__restrict__ cross) {
+    const int N = 1 << logn, np = nq + 1;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.y, j = blockIdx.z;
+    const PrimeConst p = pcs[i];
+    const long o0 = ((long)(j * 2 + 0) * np + i) * N + n;
+    const long o1 = ((long)(j * 2 + 1) * np + i) * N + n;
+    const u64 si = s[(long)i * N + n];
+    u64 b = sub_mod(e[((long)j * np + i) * N + n], mul_mod(key[o1], si, p), p.q);
+    if (i == j) {
+        u64 sp;
+        if (g == 0) sp = mul_mod(si, si, p);
+        else sp = s[(long)i * N + galois_src(n, g, logn)];
+        const u64 pm = cross[i * kMaxMods + nq].qj_mod_qi;      // P mod q_i
+        b = add_mod(b, mul_mod(pm, sp, p), p.q);
+    }
+    key[o0] = b;
+}
+
+// Public key: pk[0][i] = -a s + e with a at pk[1][i]; e: [nq][N] NTT form.
+__global__ void __launch_bounds__(256)
+k_pk_body(u64 *__restrict__ pk, const u64 *__restrict__ e, const u64 *__restrict__ s, int nq, int logn,
+          const PrimeConst *__restrict__ pcs) {
+    const long N = 1L << logn;
+    const int n = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    const PrimeConst p = pcs[i];
+    const long o = (long)i * N + n;
+    pk[o] = sub_mod(e[o], mul_mod(pk[(long)nq * N + o], s[o], p), p.q);
+}
+
+// Encryption: in = [4][nq][N] NTT form of (v, e0, e1, m); ct = (v b + e0 + m, v a + e1).
+__global__ void __launch_bounds__(256)
+k_encrypt(const u64 *__restrict__ pk, const u64 *__restrict__ in, u64 *__restrict__ ct, int nq, int logn,
+          const PrimeConst *__restrict__ pcs) {
+    const long N = 1L << logn, qn = (long)nq * N;
+    const int n = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    const PrimeConst p = pcs[i];
+    const long o = (long)i * N + n;
+    const u64 v = in[o], e0 = in[qn + o], e1 = in[2 * qn + o], m = in[3 * qn + o];
+    ct[o] = add_mod(add_mod(mul_mod(v, pk[o], p), e0, p.q), m, p.q);
+    ct[qn + o] = add_mod(mul_mod(v, pk[qn + o], p), e1, p.q);
+}
+
+// Decryption product c0 + c1 s for k primes (NTT form): ct [2][k][N], s [np][N], out [k][N].
+__global__ void __launch_bounds__(256)
+k_dec_mul(const u64 *__restrict__ ct, const u64 *__restrict__ s, u64 *__restrict__ out, int k, int logn,
+          const PrimeConst *__restrict__ pcs) {
+    const long N = 1L << logn, kn = (long)k * N;
+    const int n = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    const PrimeConst p = pcs[i];
+    const long o = (long)i * N + n;
+    out[o] = add_mod(ct[o], mul_mod(ct[kn + o], s[o], p), p.q);
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename F>
+static hipError_t set_lds(F f, int bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(f), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <int LOGN>
+static hipError_t prepare_all() {
+    const int b = lds_words<LOGN>() * 8;
+    hipError_t e;
+    if ((e = set_lds(k_ntt_fwd<LOGN>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_ntt_inv<LOGN>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_modup<LOGN>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_drop<LOGN>, b)) != hipSuccess) return e;
+    return set_lds(k_int_ntt<LOGN>, b);
+}
+
+hipError_t kernels_prepare(int logn) {
+    switch (logn) {
+        case 12: return prepare_all<12>();
+        case 13: return prepare_all<13>();
+        case 14: return prepare_all<14>();
+        default: return hipErrorInvalidValue;
+    }
+}
+
+static dim3 ntt_block(int logn) { return dim3(1u << (logn - 4)); }
+static size_t ntt_lds(int logn) { return (size_t)((1 << logn) + ((1 << logn) >> 5)) * 8; }
+
+void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
+                int count, const Tables &tab, hipStream_t st) {
+    if (count <= 0) return;
+    const dim3 grid(count), blk = ntt_block(logn);
+    const size_t sh = ntt_lds(logn);
+    if (inverse) {
+        switch (logn) {
+            case 12: hipLaunchKernelGGL(k_ntt_inv<12>, grid, blk, sh, st, in, imap, out, omap, tab); break;
+            case 13: hipLaunchKernelGGL(k_ntt_inv<13>, grid, blk, sh, st, in, imap, out, omap, tab); break;
+            default: hipLaunchKernelGGL(k_ntt_inv<14>, grid, blk, sh, st, in, imap, out, omap, tab); break;
+        }
+    } else {
+        switch (logn) {
+            case 12: hipLaunchKernelGGL(k_ntt_fwd<12>, grid, blk, sh, st, in, imap, out, omap, tab); break;
+            case 13: hipLaunchKernelGGL(k_ntt_fwd<13>, grid, blk, sh, st, in, imap, out, omap, tab); break;
+            default: hipLaunchKernelGGL(k_ntt_fwd<14>, grid, blk, sh, st, in, imap, out, omap, tab); break;
+        }
+    }
+}
+
+void launch_modup(int logn, const u64 *coef, u64 *digits, int groups, int k, int nq, const Tables &tab,
+                  hipStream_t st) {
+    if (groups <= 0) return;
+    const dim3 grid(groups * k * (k + 1)), blk = ntt_block(logn);
+    const size_t sh = ntt_lds(logn);
+    switch (logn) {
+        case 12: hipLaunchKernelGGL(k_modup<12>, grid, blk, sh, st, coef, digits, k, nq, tab); break;
+        case 13: hipLaunchKernelGGL(k_modup<13>, grid, blk, sh, st, coef, digits, k, nq, tab); break;
+        default: hipLaunchKernelGGL(k_modup<14>, grid, blk, sh, st, coef, digits, k, nq, tab); break;
+    }
+}
+
+void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
+                 const DropAdd &add, const Tables &tab, hipStream_t st) {
+    if (groups <= 0) return;
+    const dim3 grid(groups * k), blk = ntt_block(logn);
+    const size_t sh = ntt_lds(logn);
+    switch (logn) {
+        case 12: hipLaunchKernelGGL(k_drop<12>, grid, blk, sh, st, x, last, out, k, drop, add, tab); break;
+        case 13: hipLaunchKernelGGL(k_drop<13>, grid, blk, sh, st, x, last, out, k, drop, add, tab); break;
+        default: hipLaunchKernelGGL(k_drop<14>, grid, blk, sh, st, x, last, out, k, drop, add, tab); break;
+    }
+}
+
+void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,
+                    const Tables &tab, hipStream_t st) {
+    if (groups <= 0) return;
+    const dim3 grid(groups * pl.n), blk = ntt_block(logn);
+    const size_t sh = ntt_lds(logn);
+    switch (logn) {
+        case 12: hipLaunchKernelGGL(k_int_ntt<12>, grid, blk, sh, st, src, out, pl, tab); break;
+        case 13: hipLaunchKernelGGL(k_int_ntt<13>, grid, blk, sh, st, src, out, pl, tab); break;
+        default: hipLaunchKernelGGL(k_int_ntt<14>, grid, blk, sh, st, src, out, pl, tab); break;
+    }
+}
+
+void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
+                  u64 *out, int B, int nq, const Tables &tab, hipStream_t st) {
+    if (R <= 0 || B <= 0) return;
+    const dim3 grid((1u << logn) / 256, k + 1, R), blk(256);
+    switch (k) {
+#define CTL_KIP(K) case K: hipLaunchKernelGGL(k_keyip<K>, grid, blk, 0, st, digits, db, dr, keys, out, B, R, nq, logn, tab.pc); break;
+        CTL_KIP(1) CTL_KIP(2) CTL_KIP(3) CTL_KIP(4) CTL_KIP(5) CTL_KIP(6) CTL_KIP(7) CTL_KIP(8)
+#undef CTL_KIP
+        default: break;
+    }
+}
+
+void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *inner, int B, int k,
+                int t1, int t2, const Tables &tab, hipStream_t st) {
+    constexpr int BC = 4;
+    const dim3 grid((1u << logn) / 256, k, (B + BC - 1) / BC), blk(256);
+    hipLaunchKernelGGL(k_mac<BC>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc);
+}
+
+void launch_add_terms(int logn, const u64 *a, long a_sb, const u64 *terms, long t_sb, long t_ss, int S,
+                      u64 *out, int B, int k, const Tables &tab, hipStream_t st) {
+    const dim3 grid((unsigned)((2L * k << logn) / 256), B), blk(256);
+    hipLaunchKernelGGL(k_add_terms, grid, blk, 0, st, a, a_sb, terms, t_sb, t_ss, S, out, k, logn, tab.pc);
+}
+
+void launch_tensor(int logn, const u64 *in, u64 *out, int B, int k, const Tables &tab, hipStream_t st) {
+    const dim3 grid((unsigned)(((long)k << logn) / 256), B), blk(256);
+    hipLaunchKernelGGL(k_tensor, grid, blk, 0, st, in, out, k, logn, tab.pc);
+}
+
+void launch_ksk_body(int logn, u64 *key, const u64 *e, const u64 *s, u64 g, int nq, const Tables &tab,
+                     hipStream_t st) {
+    const dim3 grid((1u << logn) / 256, nq + 1, nq), blk(256);
+    hipLaunchKernelGGL(k_ksk_body, grid, blk, 0, st, key, e, s, g, nq, logn, tab.pc, tab.cross);
+}
+
+void launch_pk_body(int logn, u64 *pk, const u64 *e, const u64 *s, int nq, const Tables &tab, hipStream_t st) {
+    const dim3 grid((1u << logn) / 256, nq), blk(256);
+    hipLaunchKernelGGL(k_pk_body, grid, blk, 0, st, pk, e, s, nq, logn, tab.pc);
+}
+
+void launch_encrypt(int logn, const u64 *pk, const u64 *in, u64 *ct, int nq, const Tables &tab, hipStream_t st) {
+    const dim3 grid((1u << logn) / 256, nq), blk(256);
+    hipLaunchKernelGGL(k_encrypt, grid, blk, 0, st, pk, in, ct, nq, logn, tab.pc);
+}
+
+void launch_dec_mul(int logn, const u64 *ct, const u64 *s, u64 *out, int k, const Tables &tab, hipStream_t st) {
+    const dim3 grid((1u << logn) / 256, k), blk(256);
+    hipLaunchKernelGGL(k_dec_mul, grid, blk, 0, st, ct, s, out, k, logn, tab.pc);
+}
+
+}  // namespace ctl

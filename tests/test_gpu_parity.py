@@ -1,0 +1,275 @@
+"""GPU parity: every HIP path result against the CPU oracle on the same seeded inputs.
+
+Integer results (NTT residues, keys, ciphertexts after every homomorphic operation) must be
+bit-exact. Decrypted outputs must match the FP64 forward pass normwise within 2^-20 (2^-12 for the
+small workload, whose 2^30 scale is noise-limited). Encoding (FP64 -> integer) must agree with the
+oracle's to within one unit per coefficient.
+"""
+import functools
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import CKKSOracle, normwise_error
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@functools.lru_cache(maxsize=None)
+def _ctx(name):
+    _need_gpu()
+    import paper_2205_11935_amd as ctl
+    return ctl.Context.for_workload(W.WORKLOADS[name])
+
+
+@functools.lru_cache(maxsize=None)
+def _orc(name):
+    return CKKSOracle.for_workload(W.WORKLOADS[name])
+
+
+def _u64(t):
+    import paper_2205_11935_amd as ctl
+    return ctl.to_numpy_u64(t)
+
+
+def _dev(a):
+    import paper_2205_11935_amd as ctl
+    return ctl.from_numpy_u64(a)
+
+
+def _plan(name):
+    w = W.WORKLOADS[name]
+    return _orc(name).plan([(l.n_in, l.n_out, l.t1) for l in w.layers])
+
+
+@functools.lru_cache(maxsize=None)
+def _keys(name):
+    """Library keys and oracle keys from the same seed (the tests below check they agree)."""
+    w = W.WORKLOADS[name]
+    o, c = _orc(name), _ctx(name)
+    plan = _plan(name)
+    rots = plan.rotations + [3, -5]
+    lk = c.keygen(w.seed_keys, rots, relin=True)
+    s = o.keygen_secret(w.seed_keys)
+    pk = o.keygen_public(w.seed_keys, s)
+    okeys = o.keygen_rotations(w.seed_keys, s, rots)
+    rlk = o.keygen_relin(w.seed_keys, s)
+    return lk, s, pk, okeys, rlk
+
+
+def _fresh_ct(name, seed, count=1):
+    """count encryptions of random integer messages, on both sides."""
+    o, c = _orc(name), _ctx(name)
+    lk, s, pk, _, _ = _keys(name)
+    msgs = W.raw_plaintexts(seed, count, o.n, bound_bits=40)
+    dev = c.empty_ct(count, o.nq)
+    ref = []
+    for i in range(count):
+        c.encrypt(lk, msgs[i], seed * 1000 + i, out=dev[i])
+        ref.append(o.encrypt(pk, msgs[i], seed * 1000 + i))
+    torch.cuda.synchronize()
+    return dev, np.stack(ref)
+
+
+# ------------------------------------------------------------------ NTT
+@pytest.mark.parametrize("name", ["small", "mid", "large"])
+def test_ntt_forward_inverse_bit_exact(name):
+    o, c = _orc(name), _ctx(name)
+    rng = np.random.default_rng(1)
+    # every prime, ragged residue counts, edge values
+    idx = [i % o.np for i in range(2 * o.np + 3)]
+    host = np.stack([rng.integers(0, o.primes[p], size=o.n, dtype=np.uint64) for p in idx])
+    host[0, :4] = [0, 1, o.primes[idx[0]] - 1, 0]
+    host[1, :] = o.primes[idx[1]] - 1
+    dev = _dev(host)
+    c.ntt(dev, idx, inverse=False)
+    got = _u64(dev)
+    want = np.stack([o.ntt(host[r], idx[r]) for r in range(len(idx))])
+    assert np.array_equal(got, want)
+    c.ntt(dev, idx, inverse=True)
+    assert np.array_equal(_u64(dev), host)
+    back = np.stack([o.ntt(host[r], idx[r], inverse=True) for r in range(len(idx))])
+    dev2 = _dev(host)
+    c.ntt(dev2, idx, inverse=True)
+    assert np.array_equal(_u64(dev2), back)
+
+
+# ------------------------------------------------------------------ keys and encryption
+@pytest.mark.parametrize("name", ["small", "mid", "large"])
+def test_keygen_bit_exact(name):
+    o = _orc(name)
+    lk, s, pk, okeys, rlk = _keys(name)
+    assert np.array_equal(lk.secret(), s)
+    assert np.array_equal(lk.public(), pk)
+    gl = sorted(lk.galois_elements())
+    assert gl == sorted(list(okeys) + [0])
+    for g in sorted(okeys)[:3] + sorted(okeys)[-2:]:
+        assert np.array_equal(lk.galois_key(g), okeys[g]), g
+    assert np.array_equal(lk.galois_key(0), rlk)
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "large"])
+def test_encrypt_decrypt_bit_exact(name):
+    o, c = _orc(name), _ctx(name)
+    lk, s, _, _, _ = _keys(name)
+    dev, ref = _fresh_ct(name, 11, count=2)
+    assert np.array_equal(_u64(dev), ref)
+    for k in (o.nq, 1):
+        got = c.decrypt(lk, dev[1, :, :k].contiguous(), k)
+        assert np.array_equal(got, o.decrypt(s, np.ascontiguousarray(ref[1][:, :k])))
+
+
+# ------------------------------------------------------------------ single operations
+@pytest.mark.parametrize("name", ["small", "mid", "large"])
+def test_rescale_bit_exact(name):
+    o, c = _orc(name), _ctx(name)
+    dev, ref = _fresh_ct(name, 12, count=3)
+    for k in (o.nq, 2):
+        got = _u64(c.rescale(dev[:, :, :k].contiguous()))
+        for b in range(3):
+            assert np.array_equal(got[b], o.rescale(np.ascontiguousarray(ref[b][:, :k])))
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "large"])
+def test_rotate_bit_exact(name):
+    o, c = _orc(name), _ctx(name)
+    lk, _, _, okeys, _ = _keys(name)
+    dev, ref = _fresh_ct(name, 13, count=2)
+    for r in (1, 3, -5):
+        g = o.galois_elt(r)
+        for k in (o.nq, 1):
+            got = _u64(c.rotate(lk, dev[:, :, :k].contiguous(), r))
+            for b in range(2):
+                assert np.array_equal(got[b], o.rotate(np.ascontiguousarray(ref[b][:, :k]), okeys[g], g)), (r, k, b)
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "large"])
+def test_square_bit_exact(name):
+    o, c = _orc(name), _ctx(name)
+    lk, _, _, _, rlk = _keys(name)
+    dev, ref = _fresh_ct(name, 14, count=2)
+    for k in (o.nq, 2):
+        got = _u64(c.square(lk, dev[:, :, :k].contiguous()))
+        for b in range(2):
+            assert np.array_equal(got[b], o.square(np.ascontiguousarray(ref[b][:, :k]), rlk)), (k, b)
+
+
+@pytest.mark.parametrize("name", ["mid", "large"])
+def test_replicate_bit_exact(name):
+    o, c = _orc(name), _ctx(name)
+    lk, _, _, okeys, _ = _keys(name)
+    plan = _plan(name)
+    w = plan.layers[0].next_t
+    dev, ref = _fresh_ct(name, 15, count=2)
+    k = o.nq - 2
+    got = _u64(c.replicate(lk, dev[:, :, :k].contiguous(), w))
+    for b in range(2):
+        assert np.array_equal(got[b], o.replicate(np.ascontiguousarray(ref[b][:, :k]), w, okeys))
+
+
+# ------------------------------------------------------------------ dense layer and forward pass
+def _raw_model(name, seed=21):
+    """The same random integer plaintext banks on both sides."""
+    o, c = _orc(name), _ctx(name)
+    w = W.WORKLOADS[name]
+    plan = _plan(name)
+    banks = [W.raw_plaintexts(seed + li, L.t, o.n, bound_bits=45, stream=li) for li, L in enumerate(plan.layers)]
+    layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
+    model = c.load_model_raw(layers, banks)
+    banks_ntt = [o.bank_ntt(banks[li], L.k) for li, L in enumerate(plan.layers)]
+    return model, banks_ntt
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "large"])
+def test_dense_bit_exact(name):
+    o, c = _orc(name), _ctx(name)
+    lk, _, _, okeys, _ = _keys(name)
+    plan = _plan(name)
+    model, banks_ntt = _raw_model(name)
+    assert model.info.items == plan.items and model.info.block == plan.block
+    assert model.info.k_out == plan.k_out
+    assert sorted(model.info.rotations) == sorted(plan.rotations)
+    dev, ref = _fresh_ct(name, 16, count=2)
+    for li, L in enumerate(plan.layers):
+        x = dev[:, :, :L.k].contiguous()
+        got = _u64(c.dense(model, li, lk, x))
+        for b in range(2):
+            want = o.dense(np.ascontiguousarray(ref[b][:, :L.k]), banks_ntt[li], L.t1, okeys)
+            assert np.array_equal(got[b], want), (li, b)
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "large"])
+def test_forward_bit_exact(name):
+    o, c = _orc(name), _ctx(name)
+    lk, _, _, okeys, rlk = _keys(name)
+    plan = _plan(name)
+    model, banks_ntt = _raw_model(name, seed=31)
+    dev, ref = _fresh_ct(name, 17, count=2)
+    got = _u64(c.forward(model, lk, dev))
+    assert got.shape == (2, 2, plan.k_out, o.n)
+    for b in range(2):
+        assert np.array_equal(got[b], o.forward(plan, ref[b], banks_ntt, okeys, rlk)), b
+
+
+def test_forward_full_batch_sampled():
+    """The large workload's batch of 64 ciphertexts in one launch sequence; ciphertexts 0 and 63
+    are recomputed by the oracle one by one."""
+    name = "large"
+    o, c = _orc(name), _ctx(name)
+    lk, _, _, okeys, rlk = _keys(name)
+    plan = _plan(name)
+    model, banks_ntt = _raw_model(name, seed=41)
+    B = W.LARGE.batch
+    dev, ref = _fresh_ct(name, 18, count=B)
+    got = _u64(c.forward(model, lk, dev))
+    for b in (0, B - 1):
+        assert np.array_equal(got[b], o.forward(plan, ref[b], banks_ntt, okeys, rlk)), b
+    # ciphertexts are independent: a lone evaluation equals its slot in the batch
+    one = _u64(c.forward(model, lk, dev[5:6].contiguous()))
+    assert np.array_equal(one[0], got[5])
+
+
+# ------------------------------------------------------------------ encoding and end-to-end tolerance
+@pytest.mark.parametrize("name", ["small", "mid", "large"])
+def test_encode_matches_oracle(name):
+    o, c = _orc(name), _ctx(name)
+    rng = np.random.default_rng(3)
+    z = rng.uniform(-1, 1, o.n // 2)
+    a, b = c.encode(z, o.scale), o.encode(z, o.scale)
+    d = np.abs(a - b)
+    assert d.max() <= 1
+    assert (d != 0).mean() < 1e-3
+    dec = c.decode(np.stack([(a % q).astype(np.uint64) for q in o.q[:1]]), o.scale)
+    assert np.max(np.abs(dec - z)) < 2.0 ** -20
+
+
+@pytest.mark.parametrize("name,tol_log2", [("small", -12), ("mid", -20), ("large", -20)])
+def test_forward_fp64_tolerance(name, tol_log2):
+    """Encode real inputs and weights with the library, run ClassifyHE on the GPU, decrypt and
+    decode: the result matches the plain FP64 forward pass normwise."""
+    w = W.WORKLOADS[name]
+    o, c = _orc(name), _ctx(name)
+    lk = _keys(name)[0]
+    ws = W.weights(w)
+    layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
+    model = c.load_model(layers, ws)
+    n_ct = 2
+    x = W.inputs(w, n_ct, model.info.items)
+    dev = c.empty_ct(n_ct, o.nq)
+    for i in range(n_ct):
+        c.encrypt(lk, c.encode_items(model, x[i]), w.seed_encrypt + i, out=dev[i])
+    out = c.forward(model, lk, dev)
+    for i in range(n_ct):
+        res = c.decrypt(lk, out[i], model.info.k_out)
+        y = c.decode_items(model, res)
+        err = normwise_error(y, o.forward_fp64(ws, x[i]))
+        assert err < 2.0 ** tol_log2, (i, err)
