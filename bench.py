@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Benchmark of the encrypted frozen-layer forward pass (CryptoTL's ClassifyHE) on one MI355X.
+
+One step = one ClassifyHE pass over a batch of ciphertexts of the large workload: N = 2^14,
+ciphertext primes {60,40,40,40,40,60} bits plus a 60-bit special prime, scale 2^40, frozen layers
+768 -> 256 -> 64 with x^2 between, weights N(0, 0.05^2), inputs N(0,1) clipped to [-3,3], 5 items
+per ciphertext, 64 ciphertexts per launch sequence. Inputs are encrypted and resident in HBM
+before the timed region starts; keys and the plaintext bank are resident too.
+
+Prints one JSON line: batched encrypted forward passes/s (value), the one-ciphertext-per-sequence
+("plain") rate, p50/p99 latencies, NTT GB/s, per-kernel times measured with HIP events on the
+launch stream, the roofline of the dominant kernel, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+# MI355X figures used for the roofline: HBM3E 8 TB/s (published). The integer work runs on the
+# vector ALU: 256 CUs at 2.4 GHz, each issuing one 64-lane VALU instruction per clock at full rate.
+HBM_PEAK_GBS = 8000.0
+CUS, CLOCK_HZ, LANES_PER_CU_CLK = 256, 2.4e9, 64
+VALU_PEAK = CUS * CLOCK_HZ * LANES_PER_CU_CLK          # 39.3e12 lane-instructions / s
+# VALU lane-instructions per unit of algorithmic work, for 64-bit residues on the 32-bit integer
+# VALU (64-bit add/sub/compare = 2 instructions):
+#   NTT butterfly (Harvey, Shoup product by the twiddle): Shoup product 16 (high half of x*w':
+#   1 mul_hi + 3 mad_u64_u32 + 1 add; low halves of x*w and h*q: 2 x (1 mad + 2 mul_lo + 1 add);
+#   final subtract 2) + lazy correction of x to [0, 2q) 5 + x + t 2 + x - t + 2q 4  = 27
+#   multiply-accumulate into a 128-bit sum: 64x64->128 product 7 (4 mad_u64_u32 + 3 carry adds)
+#   + 128-bit add 4                                                                  = 11
+SLOTS_PER_BUTTERFLY = 27
+SLOTS_PER_MAC = 11
+NTT_FAMILIES = ("k_ntt_fwd", "k_ntt_inv", "k_modup", "k_drop", "k_int_ntt")
+
+
+def _percentile(xs, p):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), p)) if xs else None
+
+
+def _src_digest():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "ctl_internal.h"):
+        with open(os.path.join(ROOT, "paper_2205_11935_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel: str, digest: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if taken on this source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != digest:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("bytes_per_launch")
+
+
+def cpu_baseline(w, n_ct: int):
+    """The CPU oracle as it stands (single thread) on n_ct ciphertexts of the same workload."""
+    from oracle import CKKSOracle
+    o = CKKSOracle.for_workload(w)
+    plan = o.plan([(l.n_in, l.n_out, l.t1) for l in w.layers])
+    s = o.keygen_secret(w.seed_keys)
+    pk = o.keygen_public(w.seed_keys, s)
+    keys = o.keygen_rotations(w.seed_keys, s, plan.rotations)
+    rlk = o.keygen_relin(w.seed_keys, s)
+    ws = W.weights(w)
+    banks = [o.bank_ntt(o.layer_bank(plan, li, ws[li]), plan.layers[li].k) for li in range(len(ws))]
+    x = W.inputs(w, n_ct, plan.items, stream=7)
+    cts = [o.encrypt(pk, o.encode(o.input_slots(plan, x[i]), o.scale), w.seed_encrypt + i) for i in range(n_ct)]
+    t0 = time.perf_counter()
+    for ct in cts:
+        o.forward(plan, ct, banks, keys, rlk)
+    dt = time.perf_counter() - t0
+    return {"value": n_ct / dt, "unit": "encrypted forward passes/s", "cores": 1, "kind": "oracle",
+            "sample": "%d ciphertexts of the large workload through the single-threaded C oracle's forward "
+                      "pass (%.1f s; key generation, bank encoding and encryption excluded)" % (n_ct, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=W.LARGE.batch)
+    ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--cpu-sample", type=int, default=3, help="ciphertexts for the CPU oracle leg (0: skip)")
+    ap.add_argument("--no-profile", action="store_true", help="do not bracket launches with events")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the encrypted forward pass shards by ciphertext with no "
+              "exchange, and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2205_11935_amd as ctl
+
+    w = W.LARGE
+    B = args.batch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    c = ctl.Context.for_workload(w)
+    layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
+    t_setup = time.perf_counter()
+    model = c.load_model(layers, W.weights(w))
+    keys = c.keygen(w.seed_keys, model.info.rotations, relin=True)
+    x = W.inputs(w, B, model.info.items)
+    ct = c.empty_ct(B, c.nq)
+    for i in range(B):
+        c.encrypt(keys, c.encode_items(model, x[i]), w.seed_encrypt + i, out=ct[i])
+    out = c.empty_ct(B, model.info.k_out)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        c.forward(model, keys, ct, out=out)
+    torch.cuda.synchronize()
+
+    # ---------------------------------------------------------------- timed region (batched)
+    if not args.no_profile:
+        c.profile_enable(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for s in range(args.steps):
+        c.forward(model, keys, ct, out=out)
+        ev[s + 1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step_ms = [ev[s].elapsed_time(ev[s + 1]) for s in range(args.steps)]
+    prof = c.profile_read() if not args.no_profile else {}
+    c.profile_enable(False)
+    value = B * args.steps / elapsed
+
+    # decrypted spot check of the last step (ciphertext 0) against the FP64 forward pass
+    res = c.decrypt(keys, out[0], model.info.k_out)
+    y = c.decode_items(model, res)
+    ref = x[0]
+    for li, wm in enumerate(W.weights(w)):
+        ref = ref @ wm.T
+        if li + 1 < len(w.layers):
+            ref = ref * ref
+    rel_err = float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+
+    # ---------------------------------------------------------------- plain: one ciphertext per sequence
+    plain = None
+    if args.plain_steps > 0:
+        one, one_out = ct[:1].contiguous(), c.empty_ct(1, model.info.k_out)
+        for _ in range(2):
+            c.forward(model, keys, one, out=one_out)
+        torch.cuda.synchronize()
+        pev = [torch.cuda.Event(enable_timing=True) for _ in range(args.plain_steps + 1)]
+        t0 = time.perf_counter()
+        pev[0].record(stream)
+        for s in range(args.plain_steps):
+            c.forward(model, keys, one, out=one_out)
+            pev[s + 1].record(stream)
+        torch.cuda.synchronize()
+        plain_elapsed = time.perf_counter() - t0
+        plain_ms = [pev[s].elapsed_time(pev[s + 1]) for s in range(args.plain_steps)]
+        plain = {"value": round(args.plain_steps / plain_elapsed, 3), "unit": "encrypted forward passes/s",
+                 "p50_ms": _percentile(plain_ms, 50), "p99_ms": _percentile(plain_ms, 99)}
+
+    # ---------------------------------------------------------------- standalone batched NTT
+    n = c.n
+    res_cnt = 64 * (c.nq + 1)
+    buf = torch.randint(0, 1 << 40, (res_cnt, n), dtype=torch.int64, device=dev)
+    pidx = [r % (c.nq + 1) for r in range(res_cnt)]
+    c.ntt(buf, pidx)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record(stream)
+    for _ in range(reps):
+        c.ntt(buf, pidx)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ntt_ms = e0.elapsed_time(e1) / reps
+    ntt_gbs = 16.0 * n * res_cnt / (ntt_ms * 1e-3) / 1e9
+
+    # ---------------------------------------------------------------- kernels and roofline
+    kernels = {}
+    total_ms = sum(v[1] for v in prof.values()) or 1.0
+    for name, (cnt, ms, work) in prof.items():
+        if cnt:
+            kernels[name] = {"launches": cnt, "ms": round(ms, 3), "share": round(ms / total_ms, 4),
+                             "avg_ms": round(ms / cnt, 4), "work": work}
+    logn = int(math.log2(n))
+    butterflies_per_ntt = (n // 2) * logn
+    ntt_res = sum(prof[f][2] for f in NTT_FAMILIES if f in prof)
+    ntt_time = sum(prof[f][1] for f in NTT_FAMILIES if f in prof)
+    ntt_gbs_fwd = 16.0 * n * ntt_res / (ntt_time * 1e-3) / 1e9 if ntt_time else None
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["ms"])
+        cnt, ms, work = prof[dom]
+        avg_s = ms / cnt * 1e-3
+        if dom in NTT_FAMILIES:
+            slots = work / cnt * butterflies_per_ntt * SLOTS_PER_BUTTERFLY
+            alg_bytes = work / cnt * 16.0 * n
+            ops = "NTT butterflies x %d VALU lane-instructions" % SLOTS_PER_BUTTERFLY
+        elif dom in ("k_mac", "k_keyip", "k_tensor"):
+            slots = work / cnt * SLOTS_PER_MAC
+            alg_bytes = None
+            ops = "64-bit modular multiply-accumulates x %d VALU lane-instructions" % SLOTS_PER_MAC
+        else:
+            slots, alg_bytes, ops = 0.0, work / cnt * 16.0, "residue words"
+        digest = _src_digest()
+        achieved = slots / avg_s / 1e12
+        peak = VALU_PEAK / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(peak, 2),
+                    "unit": "T VALU-lane-instr/s", "frac": round(achieved / peak, 4),
+                    "traffic": _traffic(dom, digest), "avg_launch_ms": round(ms / cnt, 4),
+                    "work_per_launch": work / cnt, "ops": ops, "source_digest": digest}
+        if alg_bytes:
+            roofline["hbm_gbs"] = round(alg_bytes / avg_s / 1e9, 1)
+            roofline["hbm_frac"] = round(alg_bytes / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+
+    line = {
+        "metric": "encrypted fwd passes/sec at N=2^14 (batched vs plain) + NTT GB/s; p50/p99",
+        "value": round(value, 3),
+        "unit": "encrypted forward passes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "large: N=2^14, q={60,40,40,40,40,60}+P60, scale 2^40, 768->256->64 x^2, "
+                               "%d ciphertexts per launch sequence" % B,
+                   "global_batch": B, "items_per_ct": model.info.items, "layers": "768->256->64",
+                   "parallelism": "single GPU"},
+        "items_per_s": round(value * model.info.items, 2),
+        "batched_step_ms": {"p50": _percentile(step_ms, 50), "p99": _percentile(step_ms, 99)},
+        "plain": plain,
+        "ntt_gbs": {"standalone": round(ntt_gbs, 1), "in_forward": round(ntt_gbs_fwd, 1) if ntt_gbs_fwd else None,
+                    "bytes_per_ntt": 16 * n},
+        "decrypt_check_rel_err": rel_err,
+        "kernels": kernels,
+        "roofline": roofline,
+        "setup_s": round(setup_s, 2),
+        "workspace_gib": round(c.workspace_bytes() / 2 ** 30, 2),
+    }
+    if args.cpu_sample > 0:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        line["cpu_baseline"]["cores"] = 1
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

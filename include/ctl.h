@@ -109,6 +109,20 @@ int ctl_workspace_bytes(const ctl_ctx *ctx, uint64_t *bytes_out);
 int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, int inverse,
             void *stream);
 
+/* Instrumentation for benchmarks: while enabled, every kernel launch the context makes is
+ * bracketed by a pair of HIP events recorded on the launch stream. ctl_profile_read synchronizes
+ * the recorded events and returns, for kernel family `family` (0 .. ctl_profile_families()-1),
+ * the number of launches, their summed durations in milliseconds, and the algorithmic work they
+ * processed since profiling was enabled: for the NTT-bearing kernels (k_ntt_fwd, k_ntt_inv,
+ * k_modup, k_drop, k_int_ntt) the number of length-N residue transforms; for the product kernels
+ * (k_keyip, k_mac, k_tensor) the number of 64-bit modular products; for k_add_terms the number of
+ * residue words written. Enabling clears earlier records. Adds a few microseconds per launch. */
+int ctl_profile_enable(ctl_ctx *ctx, int enable);
+int ctl_profile_families(void);
+const char *ctl_profile_family_name(int family);
+int ctl_profile_read(ctl_ctx *ctx, int family, int *launches_out, double *total_ms_out,
+                     double *work_out);
+
 /* ------------------------------------------------------------------ keys (client side) */
 typedef struct ctl_sk ctl_sk;
 typedef struct ctl_pk ctl_pk;

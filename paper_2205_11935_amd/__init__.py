@@ -67,6 +67,11 @@ _SIGS = {
     "ctl_set_allocator": (ctypes.c_int, [ctypes.c_void_p, _ALLOC_FN, _FREE_FN, ctypes.c_void_p]),
     "ctl_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, u64p]),
     "ctl_ntt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, i32p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "ctl_profile_families": (ctypes.c_int, []),
+    "ctl_profile_family_name": (ctypes.c_char_p, [ctypes.c_int]),
+    "ctl_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "ctl_keygen": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, i32p, ctypes.c_int, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_void_p)]),
@@ -298,6 +303,20 @@ class Context:
         b = ctypes.c_uint64()
         _check(lib().ctl_workspace_bytes(self.handle, ctypes.byref(b)))
         return int(b.value)
+
+    # ------------------------------------------------------------ instrumentation
+    def profile_enable(self, on: bool = True):
+        _check(lib().ctl_profile_enable(self.handle, int(on)))
+
+    def profile_read(self):
+        """{kernel family: (launches, summed milliseconds, algorithmic work)} since profiling was
+        enabled (work: residue transforms or 64-bit modular products, see ctl.h)."""
+        out = {}
+        for f in range(lib().ctl_profile_families()):
+            n, ms, wk = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+            _check(lib().ctl_profile_read(self.handle, f, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(wk)))
+            out[lib().ctl_profile_family_name(f).decode()] = (n.value, ms.value, wk.value)
+        return out
 
     # ------------------------------------------------------------ parity hook
     def ntt(self, buf, prime_idx: Sequence[int], inverse: bool = False, stream=None):

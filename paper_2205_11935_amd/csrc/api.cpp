@@ -37,6 +37,11 @@ int fail(int code, const std::string &msg) {
         if (rc_ != CTL_OK) return rc_; \
     } while (0)
 
+enum Family { F_NTT_FWD, F_NTT_INV, F_MODUP, F_KEYIP, F_DROP, F_MAC, F_ADD, F_TENSOR, F_INT_NTT, F_OTHER,
+              F_COUNT };
+const char *const kFamilyNames[F_COUNT] = {"k_ntt_fwd", "k_ntt_inv", "k_modup", "k_keyip", "k_drop",
+                                            "k_mac", "k_add_terms", "k_tensor", "k_int_ntt", "other"};
+
 // Workspace slots: each grows on demand and is reused by later calls on the same context.
 enum Slot {
     S_COEF, S_DIG, S_U, S_PLAST, S_ROT, S_INNER, S_SUM, S_LAST, S_TENSOR, S_SQ, S_REP,
@@ -57,6 +62,12 @@ struct ctl_ctx {
     size_t slot_bytes[S_COUNT] = {};
     std::unique_ptr<Encoder> enc;
     std::vector<PrimeConst> pc;
+    // launch instrumentation
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;      // pairs (start, stop)
+    std::vector<int> prof_fam;            // family of each recorded pair
+    std::vector<double> prof_work;        // algorithmic work of each recorded launch
+    size_t prof_used = 0;
 };
 
 struct ctl_sk {
@@ -124,6 +135,35 @@ int slot(ctl_ctx *c, Slot s, size_t words, hipStream_t st, u64 **out) {
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
+// Brackets one launch with events when the context's instrumentation is on.
+class Prof {
+  public:
+    Prof(ctl_ctx *c, Family f, hipStream_t st, double work) : c_(c), st_(st), idx_(SIZE_MAX) {
+        if (!c->prof_on) return;
+        if (c->prof_used * 2 + 2 > c->prof_ev.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+            c->prof_ev.push_back(a);
+            c->prof_ev.push_back(b);
+            c->prof_fam.push_back(0);
+            c->prof_work.push_back(0.0);
+        }
+        idx_ = c->prof_used++;
+        c->prof_fam[idx_] = f;
+        c->prof_work[idx_] = work;
+        (void)hipEventRecord(c->prof_ev[2 * idx_], st_);
+    }
+    ~Prof() {
+        if (idx_ != SIZE_MAX) (void)hipEventRecord(c_->prof_ev[2 * idx_ + 1], st_);
+    }
+  private:
+    ctl_ctx *c_;
+    hipStream_t st_;
+    size_t idx_;
+};
+#define CTL_PROF(fam, work) Prof prof_##__LINE__(c, fam, st, (double)(work))
+
 int check_launch() {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CTL_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -161,15 +201,15 @@ int keyswitch_batch(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
     CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
     CTL_TRY(slot(c, S_U, (size_t)B * R * 2 * (k + 1) * N, st, &U));
     CTL_TRY(slot(c, S_PLAST, (size_t)B * R * 2 * N, st, &plast));
-    launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st);
-    launch_modup(logn, coef, dig, G, k, nq, c->tab, st);
+    { CTL_PROF(F_NTT_INV, G * k); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
+    { CTL_PROF(F_MODUP, G * k * k); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, st); }
     KeyList kl{};
     for (int r = 0; r < R; ++r) {
         kl.key[r] = keys[r];
         kl.gal[r] = gal[r];
     }
     const long dsz = (long)k * (k + 1) * N;
-    launch_keyip(logn, k, dig, hoisted ? dsz : (long)R * dsz, hoisted ? 0 : dsz, kl, R, U, B, nq, c->tab, st);
+    { CTL_PROF(F_KEYIP, 2.0 * B * R * (k + 1) * k * N); launch_keyip(logn, k, dig, hoisted ? dsz : (long)R * dsz, hoisted ? 0 : dsz, kl, R, U, B, nq, c->tab, st); }
     ResMap pm{};
     pm.per = 1;
     pm.ngrp = 1;
@@ -177,8 +217,8 @@ int keyswitch_batch(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
     pm.gstride = k + 1;
     pm.ostride = k + 1;
     pm.prime[0] = nq;
-    launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), B * R * 2, c->tab, st);
-    launch_drop(logn, U, plast, out, B * R * 2, k, nq, add, c->tab, st);
+    { CTL_PROF(F_NTT_INV, B * R * 2); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), B * R * 2, c->tab, st); }
+    { CTL_PROF(F_DROP, B * R * 2 * k); launch_drop(logn, U, plast, out, B * R * 2, k, nq, add, c->tab, st); }
     return check_launch();
 }
 
@@ -196,12 +236,12 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
     m.gstride = k;
     m.ostride = k;
     m.prime[0] = k - 1;
-    launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, st);
+    { CTL_PROF(F_NTT_INV, B * 2); launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, st); }
     DropAdd add{};
     add.R = 1;
     add.mask = 0;
     add.gal[0] = 1;
-    launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, st);
+    { CTL_PROF(F_DROP, B * 2 * (k - 1)); launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, st); }
     return check_launch();
 }
 
@@ -239,7 +279,7 @@ int replicate_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B
     u64 *rot;
     CTL_TRY(slot(c, S_REP, (size_t)B * 2 * k * N, st, &rot));
     CTL_TRY(rotate_batch(c, st, evk, k, B, -(long)width, in, rot));
-    launch_add_terms(c->hp.logn, in, 2L * k * N, rot, 2L * k * N, 0, 1, out, B, k, c->tab, st);
+    { CTL_PROF(F_ADD, 2.0 * B * k * N); launch_add_terms(c->hp.logn, in, 2L * k * N, rot, 2L * k * N, 0, 1, out, B, k, c->tab, st); }
     return check_launch();
 }
 
@@ -251,7 +291,7 @@ int square_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, c
     u64 *t3, *sq;
     CTL_TRY(slot(c, S_TENSOR, (size_t)B * 3 * k * N, st, &t3));
     CTL_TRY(slot(c, S_SQ, (size_t)B * 2 * k * N, st, &sq));
-    launch_tensor(c->hp.logn, in, t3, B, k, c->tab, st);
+    { CTL_PROF(F_TENSOR, 3.0 * B * k * N); launch_tensor(c->hp.logn, in, t3, B, k, c->tab, st); }
     ResMap dm{};
     dm.per = k;
     dm.ngrp = 1;
@@ -306,7 +346,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
         CTL_TRY(keyswitch_batch(c, st, k, B, R1, in, c1_map(k), true, keys1.data(), gal1.data(), add, rot));
     }
     // inner_k2 = sum_j diag'_{k2 t1 + j} * rot_j(ct)
-    launch_mac(logn, in, rot, m->banks[li], inner, B, k, t1, t2, c->tab, st);
+    { CTL_PROF(F_MAC, 2.0 * B * k * t1 * t2 * N); launch_mac(logn, in, rot, m->banks[li], inner, B, k, t1, t2, c->tab, st); }
     CTL_TRY(check_launch());
     const u64 *sum = inner;
     if (R2 > 0) {
@@ -329,7 +369,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
         add.mask = 1;
         for (int r = 0; r < R2; ++r) add.gal[r] = gal2[r];
         CTL_TRY(keyswitch_batch(c, st, k, B, R2, inner, dm, false, keys2.data(), gal2.data(), add, rot2));
-        launch_add_terms(logn, inner, (long)t2 * ctw, rot2, (long)R2 * ctw, ctw, R2, acc, B, k, c->tab, st);
+        { CTL_PROF(F_ADD, 2.0 * B * k * N); launch_add_terms(logn, inner, (long)t2 * ctw, rot2, (long)R2 * ctw, ctw, R2, acc, B, k, c->tab, st); }
         CTL_TRY(check_launch());
         sum = acc;
     }
@@ -619,6 +659,7 @@ int ctl_ctx_free(ctl_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (int s = 0; s < S_COUNT; ++s) dev_free(ctx, ctx->slot_ptr[s], nullptr);
+    for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
     (void)hipFree(ctx->tables_mem);
     delete ctx;
     return CTL_OK;
@@ -650,6 +691,39 @@ int ctl_workspace_bytes(const ctl_ctx *ctx, uint64_t *bytes_out) {
     return CTL_OK;
 }
 
+int ctl_profile_enable(ctl_ctx *ctx, int enable) {
+    if (!ctx) return fail(CTL_EINVAL, "null context");
+    ctx->prof_on = enable != 0;
+    if (ctx->prof_on) ctx->prof_used = 0;
+    return CTL_OK;
+}
+
+int ctl_profile_families(void) { return F_COUNT; }
+
+const char *ctl_profile_family_name(int family) {
+    return family >= 0 && family < F_COUNT ? kFamilyNames[family] : "";
+}
+
+int ctl_profile_read(ctl_ctx *ctx, int family, int *launches_out, double *total_ms_out, double *work_out) {
+    if (!ctx || !launches_out || !total_ms_out || !work_out) return fail(CTL_EINVAL, "null argument");
+    if (family < 0 || family >= F_COUNT) return fail(CTL_EINVAL, "unknown kernel family");
+    int cnt = 0;
+    double tot = 0.0, work = 0.0;
+    for (size_t i = 0; i < ctx->prof_used; ++i) {
+        if (ctx->prof_fam[i] != family) continue;
+        CTL_HIP(hipEventSynchronize(ctx->prof_ev[2 * i + 1]));
+        float ms = 0.f;
+        CTL_HIP(hipEventElapsedTime(&ms, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
+        tot += ms;
+        work += ctx->prof_work[i];
+        ++cnt;
+    }
+    *launches_out = cnt;
+    *total_ms_out = tot;
+    *work_out = work;
+    return CTL_OK;
+}
+
 int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, int inverse, void *stream) {
     if (!ctx || (!dev && n_res) || (!prime_idx && n_res) || n_res < 0) return fail(CTL_EINVAL, "bad argument");
     for (int r = 0; r < n_res; ++r)
@@ -657,6 +731,21 @@ int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, in
     CTL_HIP(hipSetDevice(ctx->device));
     hipStream_t st = as_stream(stream);
     const long N = ctx->hp.n;
+    // a prime pattern that repeats with a short period runs as one launch
+    int period = 0;
+    for (int p = 1; p <= kMaxMods && p <= n_res && !period; ++p) {
+        bool ok = true;
+        for (int r = p; r < n_res && ok; ++r) ok = prime_idx[r] == prime_idx[r % p];
+        if (ok) period = p;
+    }
+    if (period) {
+        ResMap m = dense_map(period);
+        for (int i = 0; i < period; ++i) m.prime[i] = prime_idx[i];
+        u64 *p = reinterpret_cast<u64 *>(dev);
+        Prof prof(ctx, inverse ? F_NTT_INV : F_NTT_FWD, st, n_res);
+        launch_ntt(ctx->hp.logn, inverse != 0, p, m, p, m, n_res, ctx->tab, st);
+        return check_launch();
+    }
     for (int r0 = 0; r0 < n_res; r0 += kMaxMods) {
         const int cnt = std::min(kMaxMods, n_res - r0);
         ResMap m{};
@@ -667,6 +756,7 @@ int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, in
         m.ostride = cnt;
         for (int i = 0; i < cnt; ++i) m.prime[i] = prime_idx[r0 + i];
         u64 *p = reinterpret_cast<u64 *>(dev) + (size_t)r0 * N;
+        Prof prof(ctx, inverse ? F_NTT_INV : F_NTT_FWD, st, cnt);
         launch_ntt(ctx->hp.logn, inverse != 0, p, m, p, m, cnt, ctx->tab, st);
         CTL_TRY(check_launch());
     }

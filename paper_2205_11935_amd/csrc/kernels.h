@@ -45,8 +45,8 @@ struct KeyList {
 hipError_t kernels_prepare(int logn);
 void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
                 int count, const Tables &tab, hipStream_t st);
-void launch_modup(int logn, const u64 *coef, u64 *digits, int groups, int k, int nq, const Tables &tab,
-                  hipStream_t st);
+void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
+                  int nq, const Tables &tab, hipStream_t st);
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
                  const DropAdd &add, const Tables &tab, hipStream_t st);
 void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,

@@ -272,16 +272,26 @@ k_ntt_inv(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
 
 // ModUp: coef is dense [G][k][N] coefficient form; digit j of group g is lifted (centered) from
 // q_j to every target t in 0..k (t = k is the special prime) and transformed:
-// digits[g][j][t] (NTT form). One workgroup per (g, j, t).
+// digits[g][j][t] (NTT form). The diagonal t = j is the input residue itself (the lift from q_j to
+// q_j is the identity), copied from d (NTT form, residue g k + j of dmap). One workgroup per
+// (g, j, t).
 template <int LOGN>
 __global__ void __launch_bounds__(Geo<LOGN>::T)
-k_modup(const u64 *__restrict__ coef, u64 *__restrict__ digits, int k, int nq, Tables tab) {
+k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u64 *__restrict__ digits, int k,
+        int nq, Tables tab) {
     extern __shared__ u64 lds[];
     constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
     const int tid = threadIdx.x;
     const int t = blockIdx.x % (k + 1);
     const int gj = blockIdx.x / (k + 1);      // g * k + j
     const int j = gj % k;
+    u64 *dst = digits + ((long)gj * (k + 1) + t) * N;
+    if (t == j) {
+        const u64 *src = d + res_offset(dmap, gj) * N;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) dst[tid + T * e] = src[tid + T * e];
+        return;
+    }
     const int pt = t < k ? t : nq;
     const PrimeConst p = tab.pc[pt];
     const u64 qj = tab.pc[j].q;
@@ -291,7 +301,6 @@ k_modup(const u64 *__restrict__ coef, u64 *__restrict__ digits, int k, int nq, T
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qj, qj_mod, p);
     ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pt * N, tab.tws + (long)pt * N, p.q, p.q2);
-    u64 *dst = digits + ((long)gj * (k + 1) + t) * N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) dst[tid + T * e] = red4(lds[lds_idx(tid + T * e)], p.q, p.q2);
 }
@@ -402,39 +411,52 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
 
 // Baby-step MAC of Eq. (1): inner[b][k2][c][i] = sum_{j < t1} pt[k2 t1 + j][i] * rot_j(ct_b)[c][i]
 // with rot_0 = ct itself (ct: [B][2][K][N]) and rot_j, j >= 1, in rot: [B][t1-1][2][K][N].
-// grid: x = N / 256 tiles, y = prime i, z = batch chunks of BC ciphertexts.
-template <int BC>
-__global__ void __launch_bounds__(256)
+// Per coefficient this is a (t2 x t1) by (t1 x 2B) modular matrix product. A workgroup covers 64
+// consecutive coefficients of one prime for up to 8 ciphertexts (threadIdx.y); each thread keeps
+// KC giant-step accumulators (128-bit) per polynomial, so every rotated ciphertext word is read
+// once per KC-chunk, and the KC plaintext words of each baby step are staged once in LDS and
+// shared by the workgroup's ciphertexts.
+// grid: x = N / 64 tiles, y = prime i, z = ceil(B / blockDim.y).
+template <int KC>
+__global__ void __launch_bounds__(512)
 k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__restrict__ bank,
       u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn, const PrimeConst *__restrict__ pcs) {
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    const int i = blockIdx.y, b0 = blockIdx.z * BC;
-    const long N = 1L << logn;
-    const long kn = (long)k * N;
+    __shared__ u64 wt[KC * 64];
+    const int nl = threadIdx.x, bl = threadIdx.y;
+    const int tid = bl * 64 + nl, nthr = 64 * blockDim.y;
+    const int i = blockIdx.y;
+    const long N = 1L << logn, kn = (long)k * N;
+    const long n0 = (long)blockIdx.x * 64;
+    const int b = blockIdx.z * blockDim.y + bl;
+    const bool live = b < B;
     const PrimeConst p = pcs[i];
-    for (int k2 = 0; k2 < t2; ++k2) {
-        Acc acc[BC][2];
+    for (int kc0 = 0; kc0 < t2; kc0 += KC) {
+        Acc acc[KC][2];
 #pragma unroll
-        for (int bb = 0; bb < BC; ++bb) { acc_zero(acc[bb][0]); acc_zero(acc[bb][1]); }
+        for (int kk = 0; kk < KC; ++kk) { acc_zero(acc[kk][0]); acc_zero(acc[kk][1]); }
         for (int j = 0; j < t1; ++j) {
-            const u64 w = bank[((long)(k2 * t1 + j)) * kn + i * N + n];
+            __syncthreads();
+            for (int e = tid; e < KC * 64; e += nthr)
+                wt[e] = bank[((long)(kc0 + e / 64) * t1 + j) * kn + i * N + n0 + (e & 63)];
+            __syncthreads();
+            if (live) {
+                const u64 *src = j == 0 ? ct + (long)b * 2 * kn : rot + ((long)b * (t1 - 1) + (j - 1)) * 2 * kn;
+                const u64 x0 = src[i * N + n0 + nl], x1 = src[kn + i * N + n0 + nl];
 #pragma unroll
-            for (int bb = 0; bb < BC; ++bb) {
-                const int b = b0 + bb;
-                if (b >= B) break;
-                const u64 *src = j == 0 ? ct + (long)b * 2 * kn
-                                        : rot + ((long)b * (t1 - 1) + (j - 1)) * 2 * kn;
-                acc_mac(acc[bb][0], w, src[i * N + n]);
-                acc_mac(acc[bb][1], w, src[kn + i * N + n]);
+                for (int kk = 0; kk < KC; ++kk) {
+                    const u64 w = wt[kk * 64 + nl];
+                    acc_mac(acc[kk][0], w, x0);
+                    acc_mac(acc[kk][1], w, x1);
+                }
             }
         }
+        if (live) {
 #pragma unroll
-        for (int bb = 0; bb < BC; ++bb) {
-            const int b = b0 + bb;
-            if (b >= B) break;
-            u64 *o = inner + ((long)b * t2 + k2) * 2 * kn + i * N + n;
-            o[0] = acc_reduce(acc[bb][0], p);
-            o[kn] = acc_reduce(acc[bb][1], p);
+            for (int kk = 0; kk < KC; ++kk) {
+                u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
+                o[0] = acc_reduce(acc[kk][0], p);
+                o[kn] = acc_reduce(acc[kk][1], p);
+            }
         }
     }
 }
@@ -575,15 +597,15 @@ void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *
     }
 }
 
-void launch_modup(int logn, const u64 *coef, u64 *digits, int groups, int k, int nq, const Tables &tab,
-                  hipStream_t st) {
+void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
+                  int nq, const Tables &tab, hipStream_t st) {
     if (groups <= 0) return;
     const dim3 grid(groups * k * (k + 1)), blk = ntt_block(logn);
     const size_t sh = ntt_lds(logn);
     switch (logn) {
-        case 12: hipLaunchKernelGGL(k_modup<12>, grid, blk, sh, st, coef, digits, k, nq, tab); break;
-        case 13: hipLaunchKernelGGL(k_modup<13>, grid, blk, sh, st, coef, digits, k, nq, tab); break;
-        default: hipLaunchKernelGGL(k_modup<14>, grid, blk, sh, st, coef, digits, k, nq, tab); break;
+        case 12: hipLaunchKernelGGL(k_modup<12>, grid, blk, sh, st, coef, d, dmap, digits, k, nq, tab); break;
+        case 13: hipLaunchKernelGGL(k_modup<13>, grid, blk, sh, st, coef, d, dmap, digits, k, nq, tab); break;
+        default: hipLaunchKernelGGL(k_modup<14>, grid, blk, sh, st, coef, d, dmap, digits, k, nq, tab); break;
     }
 }
 
@@ -623,11 +645,24 @@ void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const Ke
     }
 }
 
+// Largest supported giant-step chunk that divides t2.
+static int mac_chunk(int t2) {
+    static const int opts[] = {16, 12, 8, 6, 4, 3, 2, 1};   // wider chunks spill registers
+    for (int c : opts)
+        if (t2 % c == 0) return c;
+    return 1;
+}
+
 void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *inner, int B, int k,
                 int t1, int t2, const Tables &tab, hipStream_t st) {
-    constexpr int BC = 4;
-    const dim3 grid((1u << logn) / 256, k, (B + BC - 1) / BC), blk(256);
-    hipLaunchKernelGGL(k_mac<BC>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc);
+    const int by = B < 8 ? B : 8;
+    const dim3 grid((1u << logn) / 64, k, (B + by - 1) / by), blk(64, by);
+    switch (mac_chunk(t2)) {
+#define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac<KC>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
+        CTL_MAC(16) CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
+        default: hipLaunchKernelGGL(k_mac<1>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
+#undef CTL_MAC
+    }
 }
 
 void launch_add_terms(int logn, const u64 *a, long a_sb, const u64 *terms, long t_sb, long t_ss, int S,
