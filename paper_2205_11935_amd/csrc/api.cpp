@@ -621,6 +621,8 @@ int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
         p.ones = (u64)(((u128)1 << 64) / q);
         p.ninv = h_invmod((u64)n % q, q);
         p.ninvs = h_shoup(p.ninv, q);
+        p.qn = 0 - q;
+        p.nq2 = 0 - 2 * q;
         c->pc.push_back(p);
     }
     for (int i = 0; i < np; ++i)

@@ -28,6 +28,8 @@ struct PrimeConst {
     u64 ones;      // floor(2^64 / q): Shoup companion of 1
     u64 ninv;      // N^{-1} mod q
     u64 ninvs;
+    u64 qn;        // 2^64 - q
+    u64 nq2;       // 2^64 - 2q
 };
 
 struct CrossConst {        // entry [i][j]: moving a value from modulus j to modulus i

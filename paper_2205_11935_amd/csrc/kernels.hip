@@ -17,10 +17,42 @@
 namespace ctl {
 
 // ---------------------------------------------------------------- device arithmetic
-__device__ __forceinline__ u64 mulhi(u64 a, u64 b) { return __umul64hi(a, b); }
+// 64-bit residues on the 32-bit integer VALU. Products are assembled from v_mad_u64_u32
+// (32 x 32 + 64 -> 64) so that carries stay inside the multiply-add instead of VCC carry chains.
+typedef unsigned int u32;
 
-// x * w mod q, result in [0, 2q), for any x < 2^64 and w < q with ws = floor(w 2^64 / q).
-__device__ __forceinline__ u64 shoup_lazy(u64 x, u64 w, u64 ws, u64 q) { return x * w - mulhi(x, ws) * q; }
+__device__ __forceinline__ u64 mad32(u32 a, u32 b, u64 c) { return (u64)a * b + c; }
+
+// high 64 bits of x * y
+__device__ __forceinline__ u64 mulhi(u64 x, u64 y) {
+    const u32 x0 = (u32)x, x1 = (u32)(x >> 32), y0 = (u32)y, y1 = (u32)(y >> 32);
+    const u64 t = mad32(x0, y1, __umulhi(x0, y0));
+    const u64 u = mad32(x1, y0, (u32)t);
+    return mad32(x1, y1, (t >> 32) + (u >> 32));
+}
+
+// x * w mod q, result in [0, 2q), for any x < 2^64 and w < q with ws = floor(w 2^64 / q):
+// r = x w - floor(x ws / 2^64) q, computed mod 2^64 as x w + h (2^64 - q) (qn = 2^64 - q).
+__device__ __forceinline__ u64 shoup_lazy(u64 x, u64 w, u64 ws, u64 q, u64 qn) {
+    const u64 h = mulhi(x, ws);
+    const u32 x0 = (u32)x, x1 = (u32)(x >> 32), w0 = (u32)w, w1 = (u32)(w >> 32);
+    const u32 h0 = (u32)h, h1 = (u32)(h >> 32), n0 = (u32)qn, n1 = (u32)(qn >> 32);
+    const u64 lo = mad32(h0, n0, (u64)x0 * w0);
+    const u32 cross = x0 * w1 + x1 * w0 + h0 * n1 + h1 * n0;
+    (void)q;
+    return lo + ((u64)cross << 32);
+}
+
+// x - m if x >= m else x, for x, m < 2^63, via the sign of x - m (no VCC mask):
+// nm = 2^64 - m.
+__device__ __forceinline__ u64 csub(u64 x, u64 nm) {
+    const u64 d = x + nm;
+    const u32 mask = (u32)((int)(u32)(d >> 32) >> 31);      // all ones when x < m
+    const u32 lo = (mask & (u32)x) | (~mask & (u32)d);
+    const u32 hi = (mask & (u32)(x >> 32)) | (~mask & (u32)(d >> 32));
+    return ((u64)hi << 32) | lo;
+}
+
 __device__ __forceinline__ u64 red2(u64 x, u64 q) { return x >= q ? x - q : x; }
 __device__ __forceinline__ u64 red4(u64 x, u64 q, u64 q2) {
     x = x >= q2 ? x - q2 : x;
@@ -41,7 +73,7 @@ __device__ __forceinline__ void acc_mac(Acc &a, u64 x, u64 y) {
 }
 // (hi 2^64 + lo) mod q
 __device__ __forceinline__ u64 acc_reduce(const Acc &a, const PrimeConst &p) {
-    const u64 r1 = shoup_lazy(a.hi, p.r64, p.r64s, p.q);
+    const u64 r1 = shoup_lazy(a.hi, p.r64, p.r64s, p.q, p.qn);
     const u64 r2 = a.lo - mulhi(a.lo, p.ones) * p.q;
     return red4(r1 + r2, p.q, p.q2);
 }
@@ -110,7 +142,7 @@ __device__ __forceinline__ void from_lds(u64 (&v)[16], const u64 *lds, int tid) 
 // Cooley-Tukey stages over bits LO+RB-1 .. LO. Values enter and leave in [0, 4q).
 template <int LOGN, int LO, int RB>
 __device__ __forceinline__ void fwd_pass(u64 (&v)[16], int tid, const u64 *__restrict__ tw,
-                                         const u64 *__restrict__ tws, u64 q, u64 q2) {
+                                         const u64 *__restrict__ tws, u64 q, u64 q2, u64 qn, u64 nq2) {
     constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -123,11 +155,10 @@ __device__ __forceinline__ void fwd_pass(u64 (&v)[16], int tid, const u64 *__res
                 if (e & half) continue;
                 const int widx = (N >> (b + 1)) + ((hi << (RB - 1 - sb)) | (e >> (sb + 1)));
                 const u64 w = tw[widx], ws = tws[widx];
-                u64 x = v[g * R + e];
-                x = x >= q2 ? x - q2 : x;
-                const u64 t = shoup_lazy(v[g * R + e + half], w, ws, q);
+                const u64 x = csub(v[g * R + e], nq2);
+                const u64 t = shoup_lazy(v[g * R + e + half], w, ws, q, qn);
                 v[g * R + e] = x + t;
-                v[g * R + e + half] = x - t + q2;
+                v[g * R + e + half] = x + q2 - t;
             }
         }
     }
@@ -136,7 +167,7 @@ __device__ __forceinline__ void fwd_pass(u64 (&v)[16], int tid, const u64 *__res
 // Gentleman-Sande stages over bits LO .. LO+RB-1. Values enter and leave in [0, 2q).
 template <int LOGN, int LO, int RB>
 __device__ __forceinline__ void inv_pass(u64 (&v)[16], int tid, const u64 *__restrict__ tw,
-                                         const u64 *__restrict__ tws, u64 q, u64 q2) {
+                                         const u64 *__restrict__ tws, u64 q, u64 q2, u64 qn, u64 nq2) {
     constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -150,10 +181,8 @@ __device__ __forceinline__ void inv_pass(u64 (&v)[16], int tid, const u64 *__res
                 const int widx = (N >> (b + 1)) + ((hi << (RB - 1 - sb)) | (e >> (sb + 1)));
                 const u64 w = tw[widx], ws = tws[widx];
                 const u64 x = v[g * R + e], y = v[g * R + e + half];
-                u64 s = x + y;
-                s = s >= q2 ? s - q2 : s;
-                v[g * R + e] = s;
-                v[g * R + e + half] = shoup_lazy(x - y + q2, w, ws, q);
+                v[g * R + e] = csub(x + y, nq2);
+                v[g * R + e + half] = shoup_lazy(x + q2 - y, w, ws, q, qn);
             }
         }
     }
@@ -166,32 +195,33 @@ __device__ __forceinline__ void inv_pass(u64 (&v)[16], int tid, const u64 *__res
 // (lds_idx(j)), values in [0, 4q), after a barrier.
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd_core(u64 (&v)[16], u64 *lds, int tid, const u64 *tw,
-                                             const u64 *tws, u64 q, u64 q2) {
+                                             const u64 *tws, const PrimeConst &pc) {
+    const u64 q = pc.q, q2 = pc.q2, qn = pc.qn, nq2 = pc.nq2;
     if constexpr (LOGN == 12) {
-        fwd_pass<12, 8, 4>(v, tid, tw, tws, q, q2);
+        fwd_pass<12, 8, 4>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<12, 8, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 4, 4>(v, lds, tid); fwd_pass<12, 4, 4>(v, tid, tw, tws, q, q2);
+        from_lds<12, 4, 4>(v, lds, tid); fwd_pass<12, 4, 4>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<12, 4, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 0, 4>(v, lds, tid); fwd_pass<12, 0, 4>(v, tid, tw, tws, q, q2);
+        from_lds<12, 0, 4>(v, lds, tid); fwd_pass<12, 0, 4>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<12, 0, 4>(v, lds, tid); __syncthreads();
     } else if constexpr (LOGN == 13) {
-        fwd_pass<13, 9, 4>(v, tid, tw, tws, q, q2);
+        fwd_pass<13, 9, 4>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<13, 9, 4>(v, lds, tid); __syncthreads();
-        from_lds<13, 6, 3>(v, lds, tid); fwd_pass<13, 6, 3>(v, tid, tw, tws, q, q2);
+        from_lds<13, 6, 3>(v, lds, tid); fwd_pass<13, 6, 3>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<13, 6, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 3, 3>(v, lds, tid); fwd_pass<13, 3, 3>(v, tid, tw, tws, q, q2);
+        from_lds<13, 3, 3>(v, lds, tid); fwd_pass<13, 3, 3>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<13, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 0, 3>(v, lds, tid); fwd_pass<13, 0, 3>(v, tid, tw, tws, q, q2);
+        from_lds<13, 0, 3>(v, lds, tid); fwd_pass<13, 0, 3>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<13, 0, 3>(v, lds, tid); __syncthreads();
     } else {
         static_assert(LOGN == 14, "unsupported ring degree");
-        fwd_pass<14, 10, 4>(v, tid, tw, tws, q, q2);
+        fwd_pass<14, 10, 4>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<14, 10, 4>(v, lds, tid); __syncthreads();
-        from_lds<14, 6, 4>(v, lds, tid); fwd_pass<14, 6, 4>(v, tid, tw, tws, q, q2);
+        from_lds<14, 6, 4>(v, lds, tid); fwd_pass<14, 6, 4>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<14, 6, 4>(v, lds, tid); __syncthreads();
-        from_lds<14, 3, 3>(v, lds, tid); fwd_pass<14, 3, 3>(v, tid, tw, tws, q, q2);
+        from_lds<14, 3, 3>(v, lds, tid); fwd_pass<14, 3, 3>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<14, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<14, 0, 3>(v, lds, tid); fwd_pass<14, 0, 3>(v, tid, tw, tws, q, q2);
+        from_lds<14, 0, 3>(v, lds, tid); fwd_pass<14, 0, 3>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<14, 0, 3>(v, lds, tid); __syncthreads();
     }
 }
@@ -200,30 +230,31 @@ __device__ __forceinline__ void ntt_fwd_core(u64 (&v)[16], u64 *lds, int tid, co
 // exit v holds elements j = tid + T e, values in [0, 2q), not yet multiplied by N^{-1}.
 template <int LOGN>
 __device__ __forceinline__ void ntt_inv_core(u64 (&v)[16], u64 *lds, int tid, const u64 *tw,
-                                             const u64 *tws, u64 q, u64 q2) {
+                                             const u64 *tws, const PrimeConst &pc) {
+    const u64 q = pc.q, q2 = pc.q2, qn = pc.qn, nq2 = pc.nq2;
     if constexpr (LOGN == 12) {
-        from_lds<12, 0, 4>(v, lds, tid); inv_pass<12, 0, 4>(v, tid, tw, tws, q, q2);
+        from_lds<12, 0, 4>(v, lds, tid); inv_pass<12, 0, 4>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<12, 0, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 4, 4>(v, lds, tid); inv_pass<12, 4, 4>(v, tid, tw, tws, q, q2);
+        from_lds<12, 4, 4>(v, lds, tid); inv_pass<12, 4, 4>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<12, 4, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 8, 4>(v, lds, tid); inv_pass<12, 8, 4>(v, tid, tw, tws, q, q2);
+        from_lds<12, 8, 4>(v, lds, tid); inv_pass<12, 8, 4>(v, tid, tw, tws, q, q2, qn, nq2);
     } else if constexpr (LOGN == 13) {
-        from_lds<13, 0, 3>(v, lds, tid); inv_pass<13, 0, 3>(v, tid, tw, tws, q, q2);
+        from_lds<13, 0, 3>(v, lds, tid); inv_pass<13, 0, 3>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<13, 0, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 3, 3>(v, lds, tid); inv_pass<13, 3, 3>(v, tid, tw, tws, q, q2);
+        from_lds<13, 3, 3>(v, lds, tid); inv_pass<13, 3, 3>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<13, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 6, 3>(v, lds, tid); inv_pass<13, 6, 3>(v, tid, tw, tws, q, q2);
+        from_lds<13, 6, 3>(v, lds, tid); inv_pass<13, 6, 3>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<13, 6, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 9, 4>(v, lds, tid); inv_pass<13, 9, 4>(v, tid, tw, tws, q, q2);
+        from_lds<13, 9, 4>(v, lds, tid); inv_pass<13, 9, 4>(v, tid, tw, tws, q, q2, qn, nq2);
     } else {
         static_assert(LOGN == 14, "unsupported ring degree");
-        from_lds<14, 0, 3>(v, lds, tid); inv_pass<14, 0, 3>(v, tid, tw, tws, q, q2);
+        from_lds<14, 0, 3>(v, lds, tid); inv_pass<14, 0, 3>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<14, 0, 3>(v, lds, tid); __syncthreads();
-        from_lds<14, 3, 3>(v, lds, tid); inv_pass<14, 3, 3>(v, tid, tw, tws, q, q2);
+        from_lds<14, 3, 3>(v, lds, tid); inv_pass<14, 3, 3>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<14, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<14, 6, 4>(v, lds, tid); inv_pass<14, 6, 4>(v, tid, tw, tws, q, q2);
+        from_lds<14, 6, 4>(v, lds, tid); inv_pass<14, 6, 4>(v, tid, tw, tws, q, q2, qn, nq2);
         to_lds<14, 6, 4>(v, lds, tid); __syncthreads();
-        from_lds<14, 10, 4>(v, lds, tid); inv_pass<14, 10, 4>(v, tid, tw, tws, q, q2);
+        from_lds<14, 10, 4>(v, lds, tid); inv_pass<14, 10, 4>(v, tid, tw, tws, q, q2, qn, nq2);
     }
 }
 
@@ -246,7 +277,7 @@ k_ntt_fwd(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
     u64 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = src[tid + T * e];
-    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pi * N, tab.tws + (long)pi * N, p.q, p.q2);
+    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pi * N, tab.tws + (long)pi * N, p);
 #pragma unroll
     for (int e = 0; e < 16; ++e) dst[tid + T * e] = red4(lds[lds_idx(tid + T * e)], p.q, p.q2);
 }
@@ -265,9 +296,9 @@ k_ntt_inv(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
     for (int e = 0; e < 16; ++e) lds[lds_idx(tid + T * e)] = src[tid + T * e];
     __syncthreads();
     u64 v[16];
-    ntt_inv_core<LOGN>(v, lds, tid, tab.itw + (long)pi * N, tab.itws + (long)pi * N, p.q, p.q2);
+    ntt_inv_core<LOGN>(v, lds, tid, tab.itw + (long)pi * N, tab.itws + (long)pi * N, p);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) dst[tid + T * e] = red2(shoup_lazy(v[e], p.ninv, p.ninvs, p.q), p.q);
+    for (int e = 0; e < 16; ++e) dst[tid + T * e] = red2(shoup_lazy(v[e], p.ninv, p.ninvs, p.q, p.qn), p.q);
 }
 
 // ModUp: coef is dense [G][k][N] coefficient form; digit j of group g is lifted (centered) from
@@ -300,7 +331,7 @@ k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u6
     u64 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qj, qj_mod, p);
-    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pt * N, tab.tws + (long)pt * N, p.q, p.q2);
+    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pt * N, tab.tws + (long)pt * N, p);
 #pragma unroll
     for (int e = 0; e < 16; ++e) dst[tid + T * e] = red4(lds[lds_idx(tid + T * e)], p.q, p.q2);
 }
@@ -326,7 +357,7 @@ k_drop(const u64 *__restrict__ x, const u64 *__restrict__ last, u64 *__restrict_
     u64 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qd, cc.qj_mod_qi, p);
-    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)i * N, tab.tws + (long)i * N, p.q, p.q2);
+    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)i * N, tab.tws + (long)i * N, p);
     const u64 *xi = x + ((long)grp * (k + 1) + i) * N;
     u64 *dst = out + ((long)grp * k + i) * N;
     const int c = grp & 1, r = (grp >> 1) % add.R, b = (grp >> 1) / add.R;
@@ -337,7 +368,7 @@ k_drop(const u64 *__restrict__ x, const u64 *__restrict__ last, u64 *__restrict_
     for (int e = 0; e < 16; ++e) {
         const int jj = tid + T * e;
         const u64 ext = red4(lds[lds_idx(jj)], p.q, p.q2);
-        u64 val = red2(shoup_lazy(sub_mod(xi[jj], ext, p.q), cc.inv, cc.invs, p.q), p.q);
+        u64 val = red2(shoup_lazy(sub_mod(xi[jj], ext, p.q), cc.inv, cc.invs, p.q, p.qn), p.q);
         if (has_add) val = add_mod(val, ap[g == 1 ? jj : galois_src(jj, g, LOGN)], p.q);
         dst[jj] = val;
     }
@@ -362,7 +393,7 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
         const u64 m = reduce_any((u64)(a < 0 ? -a : a), p);
         v[e] = a < 0 ? neg_mod(m, p.q) : m;
     }
-    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pi * N, tab.tws + (long)pi * N, p.q, p.q2);
+    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pi * N, tab.tws + (long)pi * N, p);
     u64 *dst = out + ((long)grp * pl.n + slot) * N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) dst[tid + T * e] = red4(lds[lds_idx(tid + T * e)], p.q, p.q2);
@@ -414,14 +445,16 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
 // Per coefficient this is a (t2 x t1) by (t1 x 2B) modular matrix product. A workgroup covers 64
 // consecutive coefficients of one prime for up to 8 ciphertexts (threadIdx.y); each thread keeps
 // KC giant-step accumulators (128-bit) per polynomial, so every rotated ciphertext word is read
-// once per KC-chunk, and the KC plaintext words of each baby step are staged once in LDS and
-// shared by the workgroup's ciphertexts.
+// once per KC-chunk. The plaintext words of JB baby steps are staged in LDS per barrier pair and
+// shared by the workgroup's ciphertexts; the ciphertext words of those JB steps are loaded first.
 // grid: x = N / 64 tiles, y = prime i, z = ceil(B / blockDim.y).
+constexpr int kMacJB = 4;
+
 template <int KC>
 __global__ void __launch_bounds__(512)
 k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__restrict__ bank,
       u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn, const PrimeConst *__restrict__ pcs) {
-    __shared__ u64 wt[KC * 64];
+    __shared__ u64 wt[kMacJB * KC * 64];
     const int nl = threadIdx.x, bl = threadIdx.y;
     const int tid = bl * 64 + nl, nthr = 64 * blockDim.y;
     const int i = blockIdx.y;
@@ -430,23 +463,41 @@ k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__rest
     const int b = blockIdx.z * blockDim.y + bl;
     const bool live = b < B;
     const PrimeConst p = pcs[i];
+    const u64 *ct_b = ct + (long)(live ? b : 0) * 2 * kn + i * N + n0 + nl;
+    const u64 *rot_b = rot + (long)(live ? b : 0) * (t1 - 1) * 2 * kn + i * N + n0 + nl;
     for (int kc0 = 0; kc0 < t2; kc0 += KC) {
         Acc acc[KC][2];
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) { acc_zero(acc[kk][0]); acc_zero(acc[kk][1]); }
-        for (int j = 0; j < t1; ++j) {
-            __syncthreads();
-            for (int e = tid; e < KC * 64; e += nthr)
-                wt[e] = bank[((long)(kc0 + e / 64) * t1 + j) * kn + i * N + n0 + (e & 63)];
-            __syncthreads();
-            if (live) {
-                const u64 *src = j == 0 ? ct + (long)b * 2 * kn : rot + ((long)b * (t1 - 1) + (j - 1)) * 2 * kn;
-                const u64 x0 = src[i * N + n0 + nl], x1 = src[kn + i * N + n0 + nl];
+        for (int j0 = 0; j0 < t1; j0 += kMacJB) {
+            const int jn = t1 - j0 < kMacJB ? t1 - j0 : kMacJB;
+            u64 x[kMacJB][2];
 #pragma unroll
-                for (int kk = 0; kk < KC; ++kk) {
-                    const u64 w = wt[kk * 64 + nl];
-                    acc_mac(acc[kk][0], w, x0);
-                    acc_mac(acc[kk][1], w, x1);
+            for (int jj = 0; jj < kMacJB; ++jj) {
+                const int j = j0 + jj;
+                if (live && jj < jn) {
+                    const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
+                    x[jj][0] = src[0];
+                    x[jj][1] = src[kn];
+                } else {
+                    x[jj][0] = x[jj][1] = 0;
+                }
+            }
+            __syncthreads();
+            for (int e = tid; e < jn * KC * 64; e += nthr) {
+                const int jj = e / (KC * 64), kk = (e / 64) % KC;
+                wt[e] = bank[((long)(kc0 + kk) * t1 + j0 + jj) * kn + i * N + n0 + (e & 63)];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int jj = 0; jj < kMacJB; ++jj) {
+                if (jj < jn) {
+#pragma unroll
+                    for (int kk = 0; kk < KC; ++kk) {
+                        const u64 w = wt[(jj * KC + kk) * 64 + nl];
+                        acc_mac(acc[kk][0], w, x[jj][0]);
+                        acc_mac(acc[kk][1], w, x[jj][1]);
+                    }
                 }
             }
         }
