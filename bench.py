@@ -103,6 +103,10 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=3, help="ciphertexts for the CPU oracle leg (0: skip)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket launches with events")
+    ap.add_argument("--giant", choices=("lazy", "per-step"), default="lazy",
+                    help="giant steps lowered by one ModDown of their summed key products (lazy) or one "
+                         "ModDown each (per-step); the other variant is timed too, without profiling")
+    ap.add_argument("--other-steps", type=int, default=3, help="timed steps of the other giant-step variant")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the encrypted forward pass shards by ciphertext with no "
@@ -119,7 +123,9 @@ def main():
     c = ctl.Context.for_workload(w)
     layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
     t_setup = time.perf_counter()
-    model = c.load_model(layers, W.weights(w))
+    lazy = args.giant == "lazy"
+    model = c.load_model(layers, W.weights(w), lazy=lazy)
+    other = c.load_model(layers, W.weights(w), lazy=not lazy) if args.other_steps > 0 else None
     keys = c.keygen(w.seed_keys, model.info.rotations, relin=True)
     x = W.inputs(w, B, model.info.items)
     ct = c.empty_ct(B, c.nq)
@@ -150,6 +156,21 @@ def main():
     prof = c.profile_read() if not args.no_profile else {}
     c.profile_enable(False)
     value = B * args.steps / elapsed
+
+    # ---------------------------------------------------------------- the other giant-step variant
+    other_line = None
+    if other is not None:
+        c.forward(other, keys, ct, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.other_steps):
+            c.forward(other, keys, ct, out=out)
+        torch.cuda.synchronize()
+        other_elapsed = time.perf_counter() - t0
+        other_line = {"giant": "per-step" if lazy else "lazy", "steps": args.other_steps,
+                      "value": round(B * args.other_steps / other_elapsed, 3),
+                      "ms_per_step": round(other_elapsed / args.other_steps * 1e3, 3)}
+        c.forward(model, keys, ct, out=out)     # leave the headline variant's output in `out`
 
     # decrypted spot check of the last step (ciphertext 0) against the FP64 forward pass
     res = c.decrypt(keys, out[0], model.info.k_out)
@@ -251,7 +272,8 @@ def main():
         "config": {"workload": "large: N=2^14, q={60,40,40,40,40,60}+P60, scale 2^40, 768->256->64 x^2, "
                                "%d ciphertexts per launch sequence" % B,
                    "global_batch": B, "items_per_ct": model.info.items, "layers": "768->256->64",
-                   "parallelism": "single GPU"},
+                   "giant_steps": args.giant, "parallelism": "single GPU"},
+        "other_variant": other_line,
         "items_per_s": round(value * model.info.items, 2),
         "batched_step_ms": {"p50": _percentile(step_ms, 50), "p99": _percentile(step_ms, 99)},
         "plain": plain,

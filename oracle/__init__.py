@@ -94,6 +94,7 @@ class LayerPlan:
     k: int              # live primes at the layer input
     square_after: bool
     next_t: int         # padded width of the next layer (replicate distance), 0 if last
+    lazy: bool = False  # giant steps lowered by one ModDown of their summed key products
 
 
 @dataclasses.dataclass
@@ -299,13 +300,15 @@ class CKKSOracle:
         arr = (u64p * len(gs))(*[_p(keys[int(g)]) for g in gs])
         return gs, arr
 
-    def dense(self, ct: np.ndarray, pts: np.ndarray, t1: int, keys: Dict[int, np.ndarray]) -> np.ndarray:
+    def dense(self, ct: np.ndarray, pts: np.ndarray, t1: int, keys: Dict[int, np.ndarray],
+              lazy: bool = False, rescale: bool = True) -> np.ndarray:
         k = ct.shape[1]
         t = pts.shape[0]
-        out = np.zeros((2, k - 1, self.n), dtype=np.uint64)
+        out = np.zeros((2, k - 1 if rescale else k, self.n), dtype=np.uint64)
         gs, arr = self._keyset(keys)
+        flags = (1 if lazy else 0) | (0 if rescale else 2)
         rc = self.lib.or_dense(self.c, k, _p(np.ascontiguousarray(ct)), _p(np.ascontiguousarray(pts)),
-                               t, t1, len(gs), _p(gs), arr, _p(out))
+                               t, t1, flags, len(gs), _p(gs), arr, _p(out))
         if rc:
             raise RuntimeError("or_dense failed: %d" % rc)
         return out
@@ -361,8 +364,8 @@ class CKKSOracle:
         return self.decode_coeffs(self.compose(self.decrypt(s, ct)), scale)
 
     # ------------------------------------------------------------ model plan
-    def plan(self, layers, t1s=None) -> ModelPlan:
-        """layers: sequence of (n_in, n_out, t1)."""
+    def plan(self, layers, lazy: bool = False) -> ModelPlan:
+        """layers: sequence of (n_in, n_out, t1); lazy selects the single-ModDown giant steps."""
         ts = [max(a, b) for (a, b, _) in layers]
         block = 2 * max(ts)
         items = (self.n // 2) // block
@@ -377,7 +380,7 @@ class CKKSOracle:
                 raise ValueError("t1 must divide t")
             last = li == len(layers) - 1
             nxt = 0 if last else ts[li + 1]
-            plans.append(LayerPlan(n_in, n_out, t, t1, t // t1, k, not last, nxt))
+            plans.append(LayerPlan(n_in, n_out, t, t1, t // t1, k, not last, nxt, lazy))
             scales.append(scale)
             rots += list(range(1, t1)) + [k2 * t1 for k2 in range(1, t // t1)]
             k -= 1                                    # dense rescale; scale preserved
@@ -433,7 +436,7 @@ class CKKSOracle:
     def forward(self, plan: ModelPlan, ct: np.ndarray, banks_ntt: List[np.ndarray],
                 keys: Dict[int, np.ndarray], rlk: np.ndarray) -> np.ndarray:
         for li, layer in enumerate(plan.layers):
-            ct = self.dense(ct, banks_ntt[li], layer.t1, keys)
+            ct = self.dense(ct, banks_ntt[li], layer.t1, keys, layer.lazy)
             if layer.square_after:
                 ct = self.square(ct, rlk)
                 ct = self.replicate(ct, layer.next_t, keys)

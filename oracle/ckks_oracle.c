@@ -736,10 +736,15 @@ int or_square(const or_ctx *c, int k, const u64 *ct, const u64 *rlk, u64 *out) {
 
 /* Baby-step giant-step diagonal dense layer at k live primes (Eq. (1) of the paper):
  *   out = sum_{k2 < t2} rot_{k2 t1}( sum_{j < t1} pt_{k2 t1 + j} * rot_j(ct) ),
- * baby rotations hoisted, one full key switch per giant step, one rescale at the end.
- * pts: [t][k][N] NTT form. Returns -5 if a needed rotation key is missing. */
-int or_dense(const or_ctx *c, int k, const u64 *ct, const u64 *pts, int t, int t1,
+ * baby rotations hoisted, one rescale at the end. Giant steps: with lazy == 0 each rotation is a
+ * full key switch with its own ModDown; with lazy != 0 the key inner products of all giant steps
+ * are summed over Q*P and lowered by a single ModDown (same value up to rounding: one rounding of
+ * the sum instead of one per giant step). pts: [t][k][N] NTT form. Returns -5 if a needed
+ * rotation key is missing. flags: bit 0 = lazy giant steps; bit 1 = skip the final rescale and
+ * return the [2][k][N] sum itself (used by tests to compare the two giant-step variants). */
+int or_dense(const or_ctx *c, int k, const u64 *ct, const u64 *pts, int t, int t1, int flags,
              int n_keys, const u64 *gs, const u64 *const *keys, u64 *out) {
+    const int lazy = flags & 1, no_rescale = flags & 2;
     int n = c->n, t2 = t / t1;
     size_t kn = (size_t)k * n, cts = 2 * kn;
     keyset_t ks = {n_keys, gs, keys};
@@ -748,6 +753,9 @@ int or_dense(const or_ctx *c, int k, const u64 *ct, const u64 *pts, int t, int t
     u64 *dig = (u64 *)malloc(sizeof(u64) * (size_t)k * (k + 1) * n);
     u64 *inner = (u64 *)malloc(sizeof(u64) * cts), *acc = (u64 *)calloc(cts, sizeof(u64));
     u64 *tmp = (u64 *)malloc(sizeof(u64) * cts);
+    size_t ext = 2 * (size_t)(k + 1) * n;
+    u64 *usum = (u64 *)calloc(ext, sizeof(u64)), *u = (u64 *)malloc(sizeof(u64) * ext);
+    u64 *sc1 = (u64 *)malloc(sizeof(u64) * kn);
     int rc = 0;
     memcpy(rots, ct, sizeof(u64) * cts);
     or_modup(c, k, ct + kn, dig);
@@ -772,7 +780,29 @@ int or_dense(const or_ctx *c, int k, const u64 *ct, const u64 *pts, int t, int t
                 }
         }
         const u64 *add = inner;
-        if (k2 > 0) {
+        if (k2 > 0 && lazy) {
+            /* sigma_g(c0) joins the sum directly; sigma_g(c1) is raised and multiplied by the key,
+             * and the product is accumulated over Q*P */
+            u64 g = or_galois_elt(c, (long)k2 * t1);
+            const u64 *key = find_key(&ks, g);
+            if (!key) { rc = -5; goto done; }
+            memset(tmp, 0, sizeof(u64) * cts);
+            for (int i = 0; i < k; i++) {
+                or_automorph_ntt(c, g, inner + (size_t)i * n, tmp + (size_t)i * n);
+                or_automorph_ntt(c, g, inner + kn + (size_t)i * n, sc1 + (size_t)i * n);
+            }
+            or_modup(c, k, sc1, dig);
+            key_inner(c, k, dig, key, 1, u);
+            for (int p = 0; p < 2; p++)
+                for (int i = 0; i <= k; i++) {
+                    u64 q = c->q[ext_prime(k, i, c)];
+                    for (int x = 0; x < n; x++) {
+                        size_t o = ((size_t)p * (k + 1) + i) * n + x;
+                        usum[o] = addm(usum[o], u[o], q);
+                    }
+                }
+            add = tmp;
+        } else if (k2 > 0) {
             u64 g = or_galois_elt(c, (long)k2 * t1);
             const u64 *key = find_key(&ks, g);
             if (!key) { rc = -5; goto done; }
@@ -788,9 +818,21 @@ int or_dense(const or_ctx *c, int k, const u64 *ct, const u64 *pts, int t, int t
                 }
             }
     }
-    or_rescale(c, k, acc, out);
+    if (lazy && t2 > 1) {
+        or_moddown(c, k, usum, tmp);
+        for (int p = 0; p < 2; p++)
+            for (int i = 0; i < k; i++) {
+                u64 q = c->q[i];
+                for (int x = 0; x < n; x++) {
+                    size_t o = p * kn + (size_t)i * n + x;
+                    acc[o] = addm(acc[o], tmp[o], q);
+                }
+            }
+    }
+    if (no_rescale) memcpy(out, acc, sizeof(u64) * cts);
+    else or_rescale(c, k, acc, out);
 done:
-    free(rots); free(dig); free(inner); free(acc); free(tmp);
+    free(rots); free(dig); free(inner); free(acc); free(tmp); free(usum); free(u); free(sc1);
     return rc;
 }
 

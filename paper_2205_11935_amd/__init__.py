@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libcryptotl.so")
 
 CTL_ACT_NONE = 0
 CTL_ACT_SQUARE = 1
+CTL_LAYER_LAZY_GIANT = 1
 MAX_PRIMES = 8
 
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ELEVEL", -4: "ESCALE", -5: "EKEY", -6: "EHIP", -7: "EPARAM"}
@@ -41,7 +42,8 @@ class _Params(ctypes.Structure):
 
 
 class _LayerDesc(ctypes.Structure):
-    _fields_ = [("n_in", ctypes.c_int), ("n_out", ctypes.c_int), ("t1", ctypes.c_int), ("act", ctypes.c_int)]
+    _fields_ = [("n_in", ctypes.c_int), ("n_out", ctypes.c_int), ("t1", ctypes.c_int), ("act", ctypes.c_int),
+                ("flags", ctypes.c_int)]
 
 
 class _ModelInfo(ctypes.Structure):
@@ -370,27 +372,30 @@ class Context:
 
     # ------------------------------------------------------------ server side
     @staticmethod
-    def _descs(layers):
+    def _descs(layers, lazy: bool):
         arr = (_LayerDesc * len(layers))()
         for i, l in enumerate(layers):
             arr[i].n_in, arr[i].n_out, arr[i].t1 = l[0], l[1], l[2]
             arr[i].act = l[3] if len(l) > 3 else (CTL_ACT_SQUARE if i + 1 < len(layers) else CTL_ACT_NONE)
+            arr[i].flags = CTL_LAYER_LAZY_GIANT if lazy else 0
         return arr
 
-    def load_model(self, layers, weights: Sequence[np.ndarray]) -> Model:
-        """layers: (n_in, n_out, t1[, act]) per layer; weights: float64 [n_out][n_in] per layer."""
+    def load_model(self, layers, weights: Sequence[np.ndarray], lazy: bool = False) -> Model:
+        """layers: (n_in, n_out, t1[, act]) per layer; weights: float64 [n_out][n_in] per layer;
+        lazy: single-ModDown giant steps (CTL_LAYER_LAZY_GIANT) on every layer."""
         ws = [np.ascontiguousarray(w, dtype=np.float64) for w in weights]
         ptrs = (f64p * len(ws))(*[w.ctypes.data_as(f64p) for w in ws])
         h = ctypes.c_void_p()
-        _check(lib().ctl_model_load(self.handle, self._descs(layers), len(layers), ptrs, ctypes.byref(h)))
+        _check(lib().ctl_model_load(self.handle, self._descs(layers, lazy), len(layers), ptrs, ctypes.byref(h)))
         return Model(self, h)
 
-    def load_model_raw(self, layers, pts: Sequence[np.ndarray]) -> Model:
+    def load_model_raw(self, layers, pts: Sequence[np.ndarray], lazy: bool = False) -> Model:
         """pts: int64 [t][N] encoded diagonal plaintexts per layer."""
         ps = [np.ascontiguousarray(p, dtype=np.int64) for p in pts]
         ptrs = (i64p * len(ps))(*[p.ctypes.data_as(i64p) for p in ps])
         h = ctypes.c_void_p()
-        _check(lib().ctl_model_load_raw(self.handle, self._descs(layers), len(layers), ptrs, ctypes.byref(h)))
+        _check(lib().ctl_model_load_raw(self.handle, self._descs(layers, lazy), len(layers), ptrs,
+                                        ctypes.byref(h)))
         return Model(self, h)
 
     def forward(self, model: Model, keys: Keys, ct, out=None, stream=None):

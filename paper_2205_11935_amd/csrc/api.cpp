@@ -88,6 +88,7 @@ struct ctl_evk {
 
 struct LayerPlan {
     int n_in, n_out, t, t1, t2, k, act;
+    bool lazy;
     double pt_scale;
 };
 
@@ -187,20 +188,20 @@ const u64 *find_key(const ctl_evk *evk, u64 g) {
 }
 
 // ---------------------------------------------------------------- building blocks
-// Key switch G = B R polynomials d (k residues each, located by dmap over B*R*k residues, group
-// order (b, r)) with key r and automorphism gal[r]: out[b][r] = (KS0 + addend, KS1) as
-// [B][R][2][k][N]. `hoisted` = the same d for every r (dmap covers B*k residues only).
-int keyswitch_batch(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *d, const ResMap &dmap,
-                    bool hoisted, const u64 *const *keys, const u64 *gal, const DropAdd &add, u64 *out) {
+// Raise and multiply: for G = B R polynomials d (k residues each, located by dmap over B*R*k
+// residues, group order (b, r)), U[b][r] = sum_j ModUp(d)_j * key_r[j] gathered through
+// sigma_{gal[r]}, as [B][R][2][k+1][N] over q_0..q_{k-1}, P. `hoisted` = the same d for every r
+// (dmap covers B*k residues only). Returns the U buffer (workspace slot S_U).
+int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *d, const ResMap &dmap,
+                    bool hoisted, const u64 *const *keys, const u64 *gal, u64 **U_out) {
     const int logn = c->hp.logn, nq = c->hp.nq;
     const long N = c->hp.n;
     if (R > kMaxKeysPerLaunch) return fail(CTL_EINVAL, "too many rotations in one layer");
     const int G = hoisted ? B : B * R;
-    u64 *coef, *dig, *U, *plast;
+    u64 *coef, *dig, *U;
     CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
     CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
     CTL_TRY(slot(c, S_U, (size_t)B * R * 2 * (k + 1) * N, st, &U));
-    CTL_TRY(slot(c, S_PLAST, (size_t)B * R * 2 * N, st, &plast));
     { CTL_PROF(F_NTT_INV, G * k); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
     { CTL_PROF(F_MODUP, G * k * k); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, st); }
     KeyList kl{};
@@ -210,6 +211,17 @@ int keyswitch_batch(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
     }
     const long dsz = (long)k * (k + 1) * N;
     { CTL_PROF(F_KEYIP, 2.0 * B * R * (k + 1) * k * N); launch_keyip(logn, k, dig, hoisted ? dsz : (long)R * dsz, hoisted ? 0 : dsz, kl, R, U, B, nq, c->tab, st); }
+    *U_out = U;
+    return check_launch();
+}
+
+// Lower G2 = 2 B R extended polynomials U ([G2][k+1][N]) by ModDown into out ([G2][k][N]),
+// adding `add` (see DropAdd).
+int keyswitch_lower(ctl_ctx *c, hipStream_t st, int k, int groups, const u64 *U, const DropAdd &add, u64 *out) {
+    const int logn = c->hp.logn, nq = c->hp.nq;
+    const long N = c->hp.n;
+    u64 *plast;
+    CTL_TRY(slot(c, S_PLAST, (size_t)groups * N, st, &plast));
     ResMap pm{};
     pm.per = 1;
     pm.ngrp = 1;
@@ -217,9 +229,17 @@ int keyswitch_batch(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
     pm.gstride = k + 1;
     pm.ostride = k + 1;
     pm.prime[0] = nq;
-    { CTL_PROF(F_NTT_INV, B * R * 2); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), B * R * 2, c->tab, st); }
-    { CTL_PROF(F_DROP, B * R * 2 * k); launch_drop(logn, U, plast, out, B * R * 2, k, nq, add, c->tab, st); }
+    { CTL_PROF(F_NTT_INV, groups); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), groups, c->tab, st); }
+    { CTL_PROF(F_DROP, (double)groups * k); launch_drop(logn, U, plast, out, groups, k, nq, add, c->tab, st); }
     return check_launch();
+}
+
+// Full key switch: out[b][r] = (KS0 + addend, KS1) as [B][R][2][k][N].
+int keyswitch_batch(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *d, const ResMap &dmap,
+                    bool hoisted, const u64 *const *keys, const u64 *gal, const DropAdd &add, u64 *out) {
+    u64 *U;
+    CTL_TRY(keyswitch_raise(c, st, k, B, R, d, dmap, hoisted, keys, gal, &U));
+    return keyswitch_lower(c, st, k, B * R * 2, U, add, out);
 }
 
 // Rescale [B][2][k][N] -> [B][2][k-1][N].
@@ -349,7 +369,36 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
     { CTL_PROF(F_MAC, 2.0 * B * k * t1 * t2 * N); launch_mac(logn, in, rot, m->banks[li], inner, B, k, t1, t2, c->tab, st); }
     CTL_TRY(check_launch());
     const u64 *sum = inner;
-    if (R2 > 0) {
+    if (R2 > 0 && L.lazy) {
+        // giant steps: key products of all k2 summed over Q*P, one ModDown; sigma(c0) terms summed
+        u64 *U, *usum, *s0, *acc;
+        ResMap dm{};
+        dm.per = k;
+        dm.ngrp = R2;
+        dm.off = 3L * k;                // k2 = 1, c1
+        dm.gstride = 2L * k;
+        dm.ostride = (long)t2 * 2 * k;
+        for (int i = 0; i < k; ++i) dm.prime[i] = i;
+        CTL_TRY(keyswitch_raise(c, st, k, B, R2, inner, dm, false, keys2.data(), gal2.data(), &U));
+        CTL_TRY(slot(c, S_ROT2, (size_t)B * 2 * (k + 1) * N, st, &usum));
+        CTL_TRY(slot(c, S_TENSOR, (size_t)B * ctw, st, &s0));
+        CTL_TRY(slot(c, S_SUM, (size_t)B * ctw, st, &acc));
+        GalList one{}, gl{};
+        for (int r = 0; r < kMaxKeysPerLaunch; ++r) one.g[r] = 1;
+        for (int r = 0; r < R2; ++r) gl.g[r] = gal2[r];
+        const long ext = 2L * (k + 1) * N;
+        { CTL_PROF(F_ADD, (double)B * ext); launch_sum_gather(logn, usum, ext, nullptr, 0, U, (long)R2 * ext, ext, R2, k + 1, true, 3, one, B, c->hp.nq, c->tab, st); }
+        { CTL_PROF(F_ADD, (double)B * ctw); launch_sum_gather(logn, s0, ctw, inner, (long)t2 * ctw, inner + ctw, (long)t2 * ctw, ctw, R2, k, false, 1, gl, B, c->hp.nq, c->tab, st); }
+        DropAdd add{};
+        add.base = s0;
+        add.sb = ctw;
+        add.sc = (long)k * N;
+        add.R = 1;
+        add.mask = 3;
+        add.gal[0] = 1;
+        CTL_TRY(keyswitch_lower(c, st, k, B * 2, usum, add, acc));
+        sum = acc;
+    } else if (R2 > 0) {
         // giant steps rot_{k2 t1}(inner_k2), k2 = 1..t2-1, one key switch each, then the sum
         u64 *rot2, *acc;
         CTL_TRY(slot(c, S_ROT2, (size_t)B * R2 * ctw, st, &rot2));
@@ -408,6 +457,8 @@ int plan_model(const ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, ctl
         L.t2 = L.t / d.t1;
         L.k = k;
         L.act = d.act;
+        if (d.flags & ~CTL_LAYER_LAZY_GIANT) return fail(CTL_EINVAL, "unknown layer flag");
+        L.lazy = (d.flags & CTL_LAYER_LAZY_GIANT) != 0;
         if (k < 2) return fail(CTL_ELEVEL, "modulus chain exhausted at layer " + std::to_string(l));
         L.pt_scale = (double)c->hp.mods[k - 1];
         // the 128-bit accumulation of t1 products must not overflow

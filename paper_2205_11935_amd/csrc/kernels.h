@@ -42,7 +42,14 @@ struct KeyList {
     u64 gal[kMaxKeysPerLaunch];          // Galois element applied to the digits (1 = none)
 };
 
+struct GalList {
+    u64 g[kMaxKeysPerLaunch];
+};
+
 hipError_t kernels_prepare(int logn);
+void launch_sum_gather(int logn, u64 *out, long o_sb, const u64 *base, long ba_sb, const u64 *src, long s_sb,
+                       long s_sr, int R, int kk, bool ext, int mask, const GalList &gal, int B, int nq,
+                       const Tables &tab, hipStream_t st);
 void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
                 int count, const Tables &tab, hipStream_t st);
 void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,

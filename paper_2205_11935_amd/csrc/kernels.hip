@@ -526,6 +526,29 @@ k_add_terms(const u64 *__restrict__ a, long a_sb, const u64 *__restrict__ terms,
     out[(long)b * 2 * k * N + idx] = s;
 }
 
+// out[b][c][t] = base[b][c][t] (or 0) + sum_{r < R} src[b][r][c][t] gathered through sigma_{gal[r]},
+// for the polynomials c set in mask (others copy base). kk residues per polynomial; with ext the
+// last one is mod P (prime index nq). grid: x = N / 256, y = 2 kk, z = B.
+__global__ void __launch_bounds__(256)
+k_sum_gather(u64 *__restrict__ out, long o_sb, const u64 *__restrict__ base, long ba_sb,
+             const u64 *__restrict__ src, long s_sb, long s_sr, int R, int kk, int ext, int mask, GalList gal,
+             int nq, int logn, const PrimeConst *__restrict__ pcs) {
+    const long N = 1L << logn;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y / kk, t = blockIdx.y % kk, b = blockIdx.z;
+    const int pi = (ext && t == kk - 1) ? nq : t;
+    const u64 q = pcs[pi].q;
+    const long off = ((long)c * kk + t) * N;
+    u64 s = base ? base[b * ba_sb + off + n] : 0;
+    if ((mask >> c) & 1) {
+        for (int r = 0; r < R; ++r) {
+            const u64 g = gal.g[r];
+            s = add_mod(s, src[b * s_sb + r * s_sr + off + (g == 1 ? n : galois_src(n, g, logn))], q);
+        }
+    }
+    out[b * o_sb + off + n] = s;
+}
+
 // (c0, c1) -> (c0^2, 2 c0 c1, c1^2): in [B][2][k][N], out [B][3][k][N].
 __global__ void __launch_bounds__(256)
 k_tensor(const u64 *__restrict__ in, u64 *__restrict__ out, int k, int logn, const PrimeConst *__restrict__ pcs) {
@@ -720,6 +743,14 @@ void launch_add_terms(int logn, const u64 *a, long a_sb, const u64 *terms, long 
                       u64 *out, int B, int k, const Tables &tab, hipStream_t st) {
     const dim3 grid((unsigned)((2L * k << logn) / 256), B), blk(256);
     hipLaunchKernelGGL(k_add_terms, grid, blk, 0, st, a, a_sb, terms, t_sb, t_ss, S, out, k, logn, tab.pc);
+}
+
+void launch_sum_gather(int logn, u64 *out, long o_sb, const u64 *base, long ba_sb, const u64 *src, long s_sb,
+                       long s_sr, int R, int kk, bool ext, int mask, const GalList &gal, int B, int nq,
+                       const Tables &tab, hipStream_t st) {
+    const dim3 grid((1u << logn) / 256, 2 * kk, B), blk(256);
+    hipLaunchKernelGGL(k_sum_gather, grid, blk, 0, st, out, o_sb, base, ba_sb, src, s_sb, s_sr, R, kk, (int)ext,
+                       mask, gal, nq, logn, tab.pc);
 }
 
 void launch_tensor(int logn, const u64 *in, u64 *out, int B, int k, const Tables &tab, hipStream_t st) {

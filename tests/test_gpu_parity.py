@@ -46,9 +46,9 @@ def _dev(a):
     return ctl.from_numpy_u64(a)
 
 
-def _plan(name):
+def _plan(name, lazy=False):
     w = W.WORKLOADS[name]
-    return _orc(name).plan([(l.n_in, l.n_out, l.t1) for l in w.layers])
+    return _orc(name).plan([(l.n_in, l.n_out, l.t1) for l in w.layers], lazy=lazy)
 
 
 @functools.lru_cache(maxsize=None)
@@ -177,24 +177,25 @@ def test_replicate_bit_exact(name):
 
 
 # ------------------------------------------------------------------ dense layer and forward pass
-def _raw_model(name, seed=21):
+def _raw_model(name, seed=21, lazy=False):
     """The same random integer plaintext banks on both sides."""
     o, c = _orc(name), _ctx(name)
     w = W.WORKLOADS[name]
     plan = _plan(name)
     banks = [W.raw_plaintexts(seed + li, L.t, o.n, bound_bits=45, stream=li) for li, L in enumerate(plan.layers)]
     layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
-    model = c.load_model_raw(layers, banks)
+    model = c.load_model_raw(layers, banks, lazy=lazy)
     banks_ntt = [o.bank_ntt(banks[li], L.k) for li, L in enumerate(plan.layers)]
     return model, banks_ntt
 
 
-@pytest.mark.parametrize("name", ["small", "mid", "large"])
-def test_dense_bit_exact(name):
+@pytest.mark.parametrize("name,lazy", [("small", False), ("mid", False), ("large", False),
+                                       ("mid", True), ("large", True)])
+def test_dense_bit_exact(name, lazy):
     o, c = _orc(name), _ctx(name)
     lk, _, _, okeys, _ = _keys(name)
-    plan = _plan(name)
-    model, banks_ntt = _raw_model(name)
+    plan = _plan(name, lazy)
+    model, banks_ntt = _raw_model(name, lazy=lazy)
     assert model.info.items == plan.items and model.info.block == plan.block
     assert model.info.k_out == plan.k_out
     assert sorted(model.info.rotations) == sorted(plan.rotations)
@@ -203,16 +204,16 @@ def test_dense_bit_exact(name):
         x = dev[:, :, :L.k].contiguous()
         got = _u64(c.dense(model, li, lk, x))
         for b in range(2):
-            want = o.dense(np.ascontiguousarray(ref[b][:, :L.k]), banks_ntt[li], L.t1, okeys)
+            want = o.dense(np.ascontiguousarray(ref[b][:, :L.k]), banks_ntt[li], L.t1, okeys, lazy)
             assert np.array_equal(got[b], want), (li, b)
 
 
-@pytest.mark.parametrize("name", ["small", "mid", "large"])
-def test_forward_bit_exact(name):
+@pytest.mark.parametrize("name,lazy", [("small", False), ("mid", False), ("large", False), ("large", True)])
+def test_forward_bit_exact(name, lazy):
     o, c = _orc(name), _ctx(name)
     lk, _, _, okeys, rlk = _keys(name)
-    plan = _plan(name)
-    model, banks_ntt = _raw_model(name, seed=31)
+    plan = _plan(name, lazy)
+    model, banks_ntt = _raw_model(name, seed=31, lazy=lazy)
     dev, ref = _fresh_ct(name, 17, count=2)
     got = _u64(c.forward(model, lk, dev))
     assert got.shape == (2, 2, plan.k_out, o.n)
@@ -220,14 +221,15 @@ def test_forward_bit_exact(name):
         assert np.array_equal(got[b], o.forward(plan, ref[b], banks_ntt, okeys, rlk)), b
 
 
-def test_forward_full_batch_sampled():
+@pytest.mark.parametrize("lazy", [False, True])
+def test_forward_full_batch_sampled(lazy):
     """The large workload's batch of 64 ciphertexts in one launch sequence; ciphertexts 0 and 63
     are recomputed by the oracle one by one."""
     name = "large"
     o, c = _orc(name), _ctx(name)
     lk, _, _, okeys, rlk = _keys(name)
-    plan = _plan(name)
-    model, banks_ntt = _raw_model(name, seed=41)
+    plan = _plan(name, lazy)
+    model, banks_ntt = _raw_model(name, seed=41, lazy=lazy)
     B = W.LARGE.batch
     dev, ref = _fresh_ct(name, 18, count=B)
     got = _u64(c.forward(model, lk, dev))
@@ -252,8 +254,9 @@ def test_encode_matches_oracle(name):
     assert np.max(np.abs(dec - z)) < 2.0 ** -20
 
 
-@pytest.mark.parametrize("name,tol_log2", [("small", -12), ("mid", -20), ("large", -20)])
-def test_forward_fp64_tolerance(name, tol_log2):
+@pytest.mark.parametrize("name,tol_log2,lazy", [("small", -12, False), ("mid", -20, False), ("large", -20, False),
+                                                ("mid", -20, True), ("large", -20, True)])
+def test_forward_fp64_tolerance(name, tol_log2, lazy):
     """Encode real inputs and weights with the library, run ClassifyHE on the GPU, decrypt and
     decode: the result matches the plain FP64 forward pass normwise."""
     w = W.WORKLOADS[name]
@@ -261,7 +264,7 @@ def test_forward_fp64_tolerance(name, tol_log2):
     lk = _keys(name)[0]
     ws = W.weights(w)
     layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
-    model = c.load_model(layers, ws)
+    model = c.load_model(layers, ws, lazy=lazy)
     n_ct = 2
     x = W.inputs(w, n_ct, model.info.items)
     dev = c.empty_ct(n_ct, o.nq)

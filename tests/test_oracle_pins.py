@@ -385,3 +385,57 @@ def test_forward_matches_fp64(name, tol_log2):
     y = o.output_slots(plan, o.decrypt_decode(s, out, plan.scales[-1]))
     err = normwise_error(y, o.forward_fp64(ws, x))
     assert err < 2.0 ** tol_log2
+
+
+# ------------------------------------------------------------------ single-ModDown giant steps
+@pytest.mark.parametrize("name", ["small", "mid"])
+def test_lazy_giant_steps_differ_only_by_rounding(name):
+    """One ModDown of the summed giant-step key products vs one per giant step: before the final
+    rescale each coefficient of each ciphertext polynomial differs by at most t2 - 1 (the per-step
+    roundings to nearest, at most 1/2 each, against one rounding of the sum); after the rescale the
+    decrypted coefficients differ by at most one; with t2 = 1 the variants are the same computation."""
+    w = W.WORKLOADS[name]
+    o = CKKSOracle.for_workload(w)
+    plan = o.plan([(l.n_in, l.n_out, l.t1) for l in w.layers])
+    s = o.keygen_secret(w.seed_keys)
+    pk = o.keygen_public(w.seed_keys, s)
+    keys = o.keygen_rotations(w.seed_keys, s, plan.rotations)
+    layer = plan.layers[0]
+    bank = W.raw_plaintexts(5, layer.t, o.n, bound_bits=40)
+    pts = o.bank_ntt(bank, layer.k)
+    ct = o.encrypt(pk, W.raw_plaintexts(6, 1, o.n)[0], 7)
+    a = o.dense(ct, pts, layer.t1, keys, lazy=False)
+    b = o.dense(ct, pts, layer.t1, keys, lazy=True)
+    if layer.t2 == 1:
+        assert np.array_equal(a, b)
+        return
+    da = o.compose(o.decrypt(s, a))
+    db = o.compose(o.decrypt(s, b))
+    assert max(abs(x - y) for x, y in zip(da, db)) <= 1
+    # before the rescale: the sums themselves
+    a0 = o.dense(ct, pts, layer.t1, keys, lazy=False, rescale=False)
+    b0 = o.dense(ct, pts, layer.t1, keys, lazy=True, rescale=False)
+    assert not np.array_equal(a0, b0)
+    for poly in range(2):
+        diff = np.stack([o.ntt((a0[poly, i] + (o.q[i] - b0[poly, i])) % np.uint64(o.q[i]), i, inverse=True)
+                         for i in range(layer.k)])
+        d = o.compose(diff)
+        assert max(abs(v) for v in d) <= layer.t2 - 1
+
+
+@pytest.mark.parametrize("name,tol_log2", [("mid", -20), ("large", -20)])
+def test_forward_lazy_giant_matches_fp64(name, tol_log2):
+    w = W.WORKLOADS[name]
+    o = CKKSOracle.for_workload(w)
+    plan = o.plan([(l.n_in, l.n_out, l.t1) for l in w.layers], lazy=True)
+    s = o.keygen_secret(w.seed_keys)
+    pk = o.keygen_public(w.seed_keys, s)
+    keys = o.keygen_rotations(w.seed_keys, s, plan.rotations)
+    rlk = o.keygen_relin(w.seed_keys, s)
+    ws = W.weights(w)
+    x = W.inputs(w, 1, plan.items)[0]
+    ct = o.encrypt(pk, o.encode(o.input_slots(plan, x), o.scale), w.seed_encrypt)
+    banks = [o.bank_ntt(o.layer_bank(plan, li, ws[li]), plan.layers[li].k) for li in range(len(ws))]
+    out = o.forward(plan, ct, banks, keys, rlk)
+    y = o.output_slots(plan, o.decrypt_decode(s, out, plan.scales[-1]))
+    assert normwise_error(y, o.forward_fp64(ws, x)) < 2.0 ** tol_log2
