@@ -33,15 +33,18 @@ import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 CUS, CLOCK_HZ, LANES_PER_CU_CLK = 256, 2.4e9, 64
 VALU_PEAK = CUS * CLOCK_HZ * LANES_PER_CU_CLK          # 39.3e12 lane-instructions / s
-# VALU lane-instructions per unit of algorithmic work, for 64-bit residues on the 32-bit integer
-# VALU (64-bit add/sub/compare = 2 instructions):
-#   NTT butterfly (Harvey, Shoup product by the twiddle): Shoup product 16 (high half of x*w':
-#   1 mul_hi + 3 mad_u64_u32 + 1 add; low halves of x*w and h*q: 2 x (1 mad + 2 mul_lo + 1 add);
-#   final subtract 2) + lazy correction of x to [0, 2q) 5 + x + t 2 + x - t + 2q 4  = 27
-#   multiply-accumulate into a 128-bit sum: 64x64->128 product 7 (4 mad_u64_u32 + 3 carry adds)
-#   + 128-bit add 4                                                                  = 11
-SLOTS_PER_BUTTERFLY = 27
-SLOTS_PER_MAC = 11
+# VALU lane-instructions per unit of algorithmic work. Residues modulo primes below 2^41 are
+# processed in exact FP64 arithmetic (full rate on gfx950), the others as 64-bit integers on the
+# 32-bit integer VALU (64-bit add/sub/compare = 2 instructions):
+#   NTT butterfly, FP64: product y w (mul, fma for the exact low part, mul by 1/q, rint, fma) 5
+#     + x + t + x - t 2 ... + 1 for the sum of the product's two parts                  = 8
+#   NTT butterfly, integer (Harvey, Shoup product by the twiddle): Shoup product 16 (high half
+#     of x w': 1 mul_hi + 3 mad_u64_u32 + 1 add; low halves of x w and h q: 2 x (1 mad + 2 mul_lo
+#     + 1 add); subtract 2) + lazy correction 5 + add 2 + subtract with offset 4              = 27
+#   multiply-accumulate, FP64: exact product 6 + accumulate 1                              = 7
+#   multiply-accumulate, integer, into a 128-bit sum: 64x64->128 product 7 + 128-bit add 4 = 11
+SLOTS_BFLY = {"fp": 8, "int": 27}
+SLOTS_MAC = {"fp": 7, "int": 11}
 NTT_FAMILIES = ("k_ntt_fwd", "k_ntt_inv", "k_modup", "k_drop", "k_int_ntt")
 
 
@@ -107,6 +110,9 @@ def main():
                     help="giant steps lowered by one ModDown of their summed key products (lazy) or one "
                          "ModDown each (per-step); the other variant is timed too, without profiling")
     ap.add_argument("--other-steps", type=int, default=3, help="timed steps of the other giant-step variant")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the timed region, copy a buffer of this many MiB once (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the encrypted forward pass shards by ciphertext with no "
@@ -156,6 +162,15 @@ def main():
     prof = c.profile_read() if not args.no_profile else {}
     c.profile_enable(False)
     value = B * args.steps / elapsed
+
+    if args.copy_calibration_mib > 0:
+        words = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(words, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---------------------------------------------------------------- the other giant-step variant
     other_line = None
@@ -221,10 +236,10 @@ def main():
     # ---------------------------------------------------------------- kernels and roofline
     kernels = {}
     total_ms = sum(v[1] for v in prof.values()) or 1.0
-    for name, (cnt, ms, work) in prof.items():
+    for name, (cnt, ms, work, fpw) in prof.items():
         if cnt:
             kernels[name] = {"launches": cnt, "ms": round(ms, 3), "share": round(ms / total_ms, 4),
-                             "avg_ms": round(ms / cnt, 4), "work": work}
+                             "avg_ms": round(ms / cnt, 4), "work": work, "fp64_share": round(fpw / work, 3)}
     logn = int(math.log2(n))
     butterflies_per_ntt = (n // 2) * logn
     ntt_res = sum(prof[f][2] for f in NTT_FAMILIES if f in prof)
@@ -233,16 +248,17 @@ def main():
     roofline = None
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["ms"])
-        cnt, ms, work = prof[dom]
+        cnt, ms, work, fpw = prof[dom]
         avg_s = ms / cnt * 1e-3
         if dom in NTT_FAMILIES:
-            slots = work / cnt * butterflies_per_ntt * SLOTS_PER_BUTTERFLY
+            slots = (fpw * SLOTS_BFLY["fp"] + (work - fpw) * SLOTS_BFLY["int"]) / cnt * butterflies_per_ntt
             alg_bytes = work / cnt * 16.0 * n
-            ops = "NTT butterflies x %d VALU lane-instructions" % SLOTS_PER_BUTTERFLY
+            ops = "NTT butterflies x (%d FP64 | %d integer) VALU lane-instructions" % (SLOTS_BFLY["fp"], SLOTS_BFLY["int"])
         elif dom in ("k_mac", "k_keyip", "k_tensor"):
-            slots = work / cnt * SLOTS_PER_MAC
+            slots = (fpw * SLOTS_MAC["fp"] + (work - fpw) * SLOTS_MAC["int"]) / cnt
             alg_bytes = None
-            ops = "64-bit modular multiply-accumulates x %d VALU lane-instructions" % SLOTS_PER_MAC
+            ops = "modular multiply-accumulates x (%d FP64 | %d integer) VALU lane-instructions" % (
+                SLOTS_MAC["fp"], SLOTS_MAC["int"])
         else:
             slots, alg_bytes, ops = 0.0, work / cnt * 16.0, "residue words"
         digest = _src_digest()

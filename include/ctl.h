@@ -116,12 +116,14 @@ int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, in
  * processed since profiling was enabled: for the NTT-bearing kernels (k_ntt_fwd, k_ntt_inv,
  * k_modup, k_drop, k_int_ntt) the number of length-N residue transforms; for the product kernels
  * (k_keyip, k_mac, k_tensor) the number of 64-bit modular products; for k_add_terms the number of
- * residue words written. Enabling clears earlier records. Adds a few microseconds per launch. */
+ * residue words written. fp_work_out receives the part of that work done on primes below 2^41,
+ * which run in exact FP64 arithmetic (the rest runs in 64-bit integer arithmetic). Enabling clears
+ * earlier records. Adds a few microseconds per launch. */
 int ctl_profile_enable(ctl_ctx *ctx, int enable);
 int ctl_profile_families(void);
 const char *ctl_profile_family_name(int family);
 int ctl_profile_read(ctl_ctx *ctx, int family, int *launches_out, double *total_ms_out,
-                     double *work_out);
+                     double *work_out, double *fp_work_out);
 
 /* ------------------------------------------------------------------ keys (client side) */
 typedef struct ctl_sk ctl_sk;

@@ -73,7 +73,8 @@ _SIGS = {
     "ctl_profile_families": (ctypes.c_int, []),
     "ctl_profile_family_name": (ctypes.c_char_p, [ctypes.c_int]),
     "ctl_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
-                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
     "ctl_keygen": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, i32p, ctypes.c_int, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_void_p)]),
@@ -311,13 +312,14 @@ class Context:
         _check(lib().ctl_profile_enable(self.handle, int(on)))
 
     def profile_read(self):
-        """{kernel family: (launches, summed milliseconds, algorithmic work)} since profiling was
-        enabled (work: residue transforms or 64-bit modular products, see ctl.h)."""
+        """{kernel family: (launches, summed milliseconds, algorithmic work, work on FP64 primes)}
+        since profiling was enabled (work: residue transforms or modular products, see ctl.h)."""
         out = {}
         for f in range(lib().ctl_profile_families()):
-            n, ms, wk = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
-            _check(lib().ctl_profile_read(self.handle, f, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(wk)))
-            out[lib().ctl_profile_family_name(f).decode()] = (n.value, ms.value, wk.value)
+            n, ms, wk, fw = ctypes.c_int(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            _check(lib().ctl_profile_read(self.handle, f, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(wk),
+                                          ctypes.byref(fw)))
+            out[lib().ctl_profile_family_name(f).decode()] = (n.value, ms.value, wk.value, fw.value)
         return out
 
     # ------------------------------------------------------------ parity hook

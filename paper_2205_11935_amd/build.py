@@ -16,6 +16,8 @@ ARCH = os.environ.get("CTL_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall",
+    # the exact FP64 modular products rely on separately rounded multiplies: no contraction
+    "-ffp-contract=off",
     # keep the compiler from forming packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(HERE, "..", "include"),

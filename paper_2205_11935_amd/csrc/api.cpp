@@ -67,6 +67,7 @@ struct ctl_ctx {
     std::vector<hipEvent_t> prof_ev;      // pairs (start, stop)
     std::vector<int> prof_fam;            // family of each recorded pair
     std::vector<double> prof_work;        // algorithmic work of each recorded launch
+    std::vector<double> prof_fp;          // the part of it on FP64 primes
     size_t prof_used = 0;
 };
 
@@ -139,7 +140,8 @@ hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 // Brackets one launch with events when the context's instrumentation is on.
 class Prof {
   public:
-    Prof(ctl_ctx *c, Family f, hipStream_t st, double work) : c_(c), st_(st), idx_(SIZE_MAX) {
+    Prof(ctl_ctx *c, Family f, hipStream_t st, double work, double fp_share = 0.0)
+        : c_(c), st_(st), idx_(SIZE_MAX) {
         if (!c->prof_on) return;
         if (c->prof_used * 2 + 2 > c->prof_ev.size()) {
             hipEvent_t a, b;
@@ -149,10 +151,12 @@ class Prof {
             c->prof_ev.push_back(b);
             c->prof_fam.push_back(0);
             c->prof_work.push_back(0.0);
+            c->prof_fp.push_back(0.0);
         }
         idx_ = c->prof_used++;
         c->prof_fam[idx_] = f;
         c->prof_work[idx_] = work;
+        c->prof_fp[idx_] = work * fp_share;
         (void)hipEventRecord(c->prof_ev[2 * idx_], st_);
     }
     ~Prof() {
@@ -163,7 +167,35 @@ class Prof {
     hipStream_t st_;
     size_t idx_;
 };
-#define CTL_PROF(fam, work) Prof prof_##__LINE__(c, fam, st, (double)(work))
+#define CTL_PROF(fam, work, share) Prof prof_##__LINE__(c, fam, st, (double)(work), (share))
+
+// Share of the residues of a list of prime indices that run on the FP64 path.
+double fp_share(const ctl_ctx *c, const int *primes, int n) {
+    if (n <= 0) return 0.0;
+    int f = 0;
+    for (int i = 0; i < n; ++i) f += c->pc[primes[i]].fp ? 1 : 0;
+    return (double)f / n;
+}
+
+// ModUp transforms: for each digit j the targets are the other k - 1 primes and P.
+double modup_share(const ctl_ctx *c, int k) {
+    int f = 0, n = 0;
+    for (int j = 0; j < k; ++j)
+        for (int t = 0; t <= k; ++t) {
+            if (t == j) continue;
+            f += c->pc[t < k ? t : c->hp.nq].fp ? 1 : 0;
+            ++n;
+        }
+    return n ? (double)f / n : 0.0;
+}
+
+// Share for "targets 0..k-1 plus optionally P".
+double fp_share_range(const ctl_ctx *c, int k, bool with_p) {
+    int pr[kMaxMods], n = 0;
+    for (int i = 0; i < k; ++i) pr[n++] = i;
+    if (with_p) pr[n++] = c->hp.nq;
+    return fp_share(c, pr, n);
+}
 
 int check_launch() {
     hipError_t e = hipGetLastError();
@@ -202,15 +234,15 @@ int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
     CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
     CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
     CTL_TRY(slot(c, S_U, (size_t)B * R * 2 * (k + 1) * N, st, &U));
-    { CTL_PROF(F_NTT_INV, G * k); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
-    { CTL_PROF(F_MODUP, G * k * k); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, st); }
+    { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
+    { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, st); }
     KeyList kl{};
     for (int r = 0; r < R; ++r) {
         kl.key[r] = keys[r];
         kl.gal[r] = gal[r];
     }
     const long dsz = (long)k * (k + 1) * N;
-    { CTL_PROF(F_KEYIP, 2.0 * B * R * (k + 1) * k * N); launch_keyip(logn, k, dig, hoisted ? dsz : (long)R * dsz, hoisted ? 0 : dsz, kl, R, U, B, nq, c->tab, st); }
+    { CTL_PROF(F_KEYIP, 2.0 * B * R * (k + 1) * k * N, fp_share_range(c, k, true)); launch_keyip(logn, k, dig, hoisted ? dsz : (long)R * dsz, hoisted ? 0 : dsz, kl, R, U, B, nq, c->tab, st); }
     *U_out = U;
     return check_launch();
 }
@@ -229,8 +261,8 @@ int keyswitch_lower(ctl_ctx *c, hipStream_t st, int k, int groups, const u64 *U,
     pm.gstride = k + 1;
     pm.ostride = k + 1;
     pm.prime[0] = nq;
-    { CTL_PROF(F_NTT_INV, groups); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), groups, c->tab, st); }
-    { CTL_PROF(F_DROP, (double)groups * k); launch_drop(logn, U, plast, out, groups, k, nq, add, c->tab, st); }
+    { CTL_PROF(F_NTT_INV, groups, fp_share_range(c, 0, true)); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), groups, c->tab, st); }
+    { CTL_PROF(F_DROP, (double)groups * k, fp_share_range(c, k, false)); launch_drop(logn, U, plast, out, groups, k, nq, add, c->tab, st); }
     return check_launch();
 }
 
@@ -256,12 +288,12 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
     m.gstride = k;
     m.ostride = k;
     m.prime[0] = k - 1;
-    { CTL_PROF(F_NTT_INV, B * 2); launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, st); }
+    { CTL_PROF(F_NTT_INV, B * 2, fp_share(c, &m.prime[0], 1)); launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, st); }
     DropAdd add{};
     add.R = 1;
     add.mask = 0;
     add.gal[0] = 1;
-    { CTL_PROF(F_DROP, B * 2 * (k - 1)); launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, st); }
+    { CTL_PROF(F_DROP, B * 2 * (k - 1), fp_share_range(c, k - 1, false)); launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, st); }
     return check_launch();
 }
 
@@ -299,7 +331,7 @@ int replicate_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B
     u64 *rot;
     CTL_TRY(slot(c, S_REP, (size_t)B * 2 * k * N, st, &rot));
     CTL_TRY(rotate_batch(c, st, evk, k, B, -(long)width, in, rot));
-    { CTL_PROF(F_ADD, 2.0 * B * k * N); launch_add_terms(c->hp.logn, in, 2L * k * N, rot, 2L * k * N, 0, 1, out, B, k, c->tab, st); }
+    { CTL_PROF(F_ADD, 2.0 * B * k * N, 0.0); launch_add_terms(c->hp.logn, in, 2L * k * N, rot, 2L * k * N, 0, 1, out, B, k, c->tab, st); }
     return check_launch();
 }
 
@@ -311,7 +343,7 @@ int square_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, c
     u64 *t3, *sq;
     CTL_TRY(slot(c, S_TENSOR, (size_t)B * 3 * k * N, st, &t3));
     CTL_TRY(slot(c, S_SQ, (size_t)B * 2 * k * N, st, &sq));
-    { CTL_PROF(F_TENSOR, 3.0 * B * k * N); launch_tensor(c->hp.logn, in, t3, B, k, c->tab, st); }
+    { CTL_PROF(F_TENSOR, 3.0 * B * k * N, 0.0); launch_tensor(c->hp.logn, in, t3, B, k, c->tab, st); }
     ResMap dm{};
     dm.per = k;
     dm.ngrp = 1;
@@ -366,7 +398,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
         CTL_TRY(keyswitch_batch(c, st, k, B, R1, in, c1_map(k), true, keys1.data(), gal1.data(), add, rot));
     }
     // inner_k2 = sum_j diag'_{k2 t1 + j} * rot_j(ct)
-    { CTL_PROF(F_MAC, 2.0 * B * k * t1 * t2 * N); launch_mac(logn, in, rot, m->banks[li], inner, B, k, t1, t2, c->tab, st); }
+    { CTL_PROF(F_MAC, 2.0 * B * k * t1 * t2 * N, fp_share_range(c, k, false)); launch_mac(logn, in, rot, m->banks[li], inner, B, k, t1, t2, c->tab, st); }
     CTL_TRY(check_launch());
     const u64 *sum = inner;
     if (R2 > 0 && L.lazy) {
@@ -387,8 +419,8 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
         for (int r = 0; r < kMaxKeysPerLaunch; ++r) one.g[r] = 1;
         for (int r = 0; r < R2; ++r) gl.g[r] = gal2[r];
         const long ext = 2L * (k + 1) * N;
-        { CTL_PROF(F_ADD, (double)B * ext); launch_sum_gather(logn, usum, ext, nullptr, 0, U, (long)R2 * ext, ext, R2, k + 1, true, 3, one, B, c->hp.nq, c->tab, st); }
-        { CTL_PROF(F_ADD, (double)B * ctw); launch_sum_gather(logn, s0, ctw, inner, (long)t2 * ctw, inner + ctw, (long)t2 * ctw, ctw, R2, k, false, 1, gl, B, c->hp.nq, c->tab, st); }
+        { CTL_PROF(F_ADD, (double)B * ext, 0.0); launch_sum_gather(logn, usum, ext, nullptr, 0, U, (long)R2 * ext, ext, R2, k + 1, true, 3, one, B, c->hp.nq, c->tab, st); }
+        { CTL_PROF(F_ADD, (double)B * ctw, 0.0); launch_sum_gather(logn, s0, ctw, inner, (long)t2 * ctw, inner + ctw, (long)t2 * ctw, ctw, R2, k, false, 1, gl, B, c->hp.nq, c->tab, st); }
         DropAdd add{};
         add.base = s0;
         add.sb = ctw;
@@ -418,7 +450,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
         add.mask = 1;
         for (int r = 0; r < R2; ++r) add.gal[r] = gal2[r];
         CTL_TRY(keyswitch_batch(c, st, k, B, R2, inner, dm, false, keys2.data(), gal2.data(), add, rot2));
-        { CTL_PROF(F_ADD, 2.0 * B * k * N); launch_add_terms(logn, inner, (long)t2 * ctw, rot2, (long)R2 * ctw, ctw, R2, acc, B, k, c->tab, st); }
+        { CTL_PROF(F_ADD, 2.0 * B * k * N, 0.0); launch_add_terms(logn, inner, (long)t2 * ctw, rot2, (long)R2 * ctw, ctw, R2, acc, B, k, c->tab, st); }
         CTL_TRY(check_launch());
         sum = acc;
     }
@@ -656,13 +688,21 @@ int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
             pw[e] = h_mulmod(pw[e - 1], psi, q);
             ipw[e] = h_mulmod(ipw[e - 1], ipsi, q);
         }
+        const bool fp = q < kFpPrimeLimit;
         for (int m = 0; m < n; ++m) {
             unsigned r = 0;
             for (int b = 0; b < c->hp.logn; ++b) r |= ((m >> b) & 1u) << (c->hp.logn - 1 - b);
             tw[(size_t)i * n + m] = pw[r];
-            tws[(size_t)i * n + m] = h_shoup(pw[r], q);
             itw[(size_t)i * n + m] = ipw[r];
-            itws[(size_t)i * n + m] = h_shoup(ipw[r], q);
+            if (fp) {
+                // FP64 path: the companion slots carry the twiddles as doubles (exact below 2^53)
+                const double a = (double)pw[r], b = (double)ipw[r];
+                std::memcpy(&tws[(size_t)i * n + m], &a, 8);
+                std::memcpy(&itws[(size_t)i * n + m], &b, 8);
+            } else {
+                tws[(size_t)i * n + m] = h_shoup(pw[r], q);
+                itws[(size_t)i * n + m] = h_shoup(ipw[r], q);
+            }
         }
         PrimeConst &p = pc[i];
         p.q = q;
@@ -674,6 +714,11 @@ int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
         p.ninvs = h_shoup(p.ninv, q);
         p.qn = 0 - q;
         p.nq2 = 0 - 2 * q;
+        p.fp = fp ? 1 : 0;
+        p.pad_ = 0;
+        p.qd = (double)q;
+        p.qinv = 1.0 / (double)q;
+        p.ninvd = (double)p.ninv;
         c->pc.push_back(p);
     }
     for (int i = 0; i < np; ++i)
@@ -683,6 +728,7 @@ int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
             cc.qj_mod_qi = qj % qi;
             cc.inv = i == j ? 0 : h_invmod(qj % qi, qi);
             cc.invs = h_shoup(cc.inv, qi);
+            cc.invd = (double)cc.inv;
         }
     void *dmem = nullptr;
     CTL_HIP(hipMalloc(&dmem, bytes));
@@ -757,11 +803,12 @@ const char *ctl_profile_family_name(int family) {
     return family >= 0 && family < F_COUNT ? kFamilyNames[family] : "";
 }
 
-int ctl_profile_read(ctl_ctx *ctx, int family, int *launches_out, double *total_ms_out, double *work_out) {
-    if (!ctx || !launches_out || !total_ms_out || !work_out) return fail(CTL_EINVAL, "null argument");
+int ctl_profile_read(ctl_ctx *ctx, int family, int *launches_out, double *total_ms_out, double *work_out,
+                     double *fp_work_out) {
+    if (!ctx || !launches_out || !total_ms_out || !work_out || !fp_work_out) return fail(CTL_EINVAL, "null argument");
     if (family < 0 || family >= F_COUNT) return fail(CTL_EINVAL, "unknown kernel family");
     int cnt = 0;
-    double tot = 0.0, work = 0.0;
+    double tot = 0.0, work = 0.0, fpw = 0.0;
     for (size_t i = 0; i < ctx->prof_used; ++i) {
         if (ctx->prof_fam[i] != family) continue;
         CTL_HIP(hipEventSynchronize(ctx->prof_ev[2 * i + 1]));
@@ -769,11 +816,13 @@ int ctl_profile_read(ctl_ctx *ctx, int family, int *launches_out, double *total_
         CTL_HIP(hipEventElapsedTime(&ms, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
         tot += ms;
         work += ctx->prof_work[i];
+        fpw += ctx->prof_fp[i];
         ++cnt;
     }
     *launches_out = cnt;
     *total_ms_out = tot;
     *work_out = work;
+    *fp_work_out = fpw;
     return CTL_OK;
 }
 
@@ -795,7 +844,7 @@ int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, in
         ResMap m = dense_map(period);
         for (int i = 0; i < period; ++i) m.prime[i] = prime_idx[i];
         u64 *p = reinterpret_cast<u64 *>(dev);
-        Prof prof(ctx, inverse ? F_NTT_INV : F_NTT_FWD, st, n_res);
+        Prof prof(ctx, inverse ? F_NTT_INV : F_NTT_FWD, st, n_res, fp_share(ctx, prime_idx, period));
         launch_ntt(ctx->hp.logn, inverse != 0, p, m, p, m, n_res, ctx->tab, st);
         return check_launch();
     }
@@ -809,7 +858,7 @@ int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, in
         m.ostride = cnt;
         for (int i = 0; i < cnt; ++i) m.prime[i] = prime_idx[r0 + i];
         u64 *p = reinterpret_cast<u64 *>(dev) + (size_t)r0 * N;
-        Prof prof(ctx, inverse ? F_NTT_INV : F_NTT_FWD, st, cnt);
+        Prof prof(ctx, inverse ? F_NTT_INV : F_NTT_FWD, st, cnt, fp_share(ctx, prime_idx + r0, cnt));
         launch_ntt(ctx->hp.logn, inverse != 0, p, m, p, m, cnt, ctx->tab, st);
         CTL_TRY(check_launch());
     }

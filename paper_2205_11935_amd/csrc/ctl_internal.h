@@ -30,12 +30,22 @@ struct PrimeConst {
     u64 ninvs;
     u64 qn;        // 2^64 - q
     u64 nq2;       // 2^64 - 2q
+    // FP64 arithmetic for primes below 2^41 (exact: see the kernels): fp != 0 selects it, and the
+    // Shoup-companion twiddle tables of such a prime hold the twiddles as doubles instead.
+    int fp;
+    int pad_;
+    double qd;     // q as a double
+    double qinv;   // fl(1 / q)
+    double ninvd;  // N^{-1} mod q as a double
 };
+
+constexpr u64 kFpPrimeLimit = 1ull << 41;
 
 struct CrossConst {        // entry [i][j]: moving a value from modulus j to modulus i
     u64 qj_mod_qi;
     u64 inv;               // q_j^{-1} mod q_i
     u64 invs;
+    double invd;           // inv as a double
 };
 
 // ---------------------------------------------------------------- host parameter math

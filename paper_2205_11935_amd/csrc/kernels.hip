@@ -93,6 +93,32 @@ __device__ __forceinline__ u64 lift_centered(u64 x, u64 qf, u64 qf_mod, const Pr
     return x > (qf >> 1) ? sub_mod(y, qf_mod, p.q) : y;
 }
 
+// ---------------------------------------------------------------- exact FP64 modular arithmetic
+// For a prime q < 2^41 residues are kept as integer-valued doubles. With fl(1/q) = qinv,
+//   ph = fl(y w), pl = fma(y, w, -ph) (the exact rounding error), qh = rint(ph * qinv),
+//   r = fma(-qh, q, ph) + pl
+// gives r = y w - qh q exactly, with |r| <= 0.52 q whenever |y| < 2^45 and 0 <= w < q: the
+// quotient estimate is within 0.52 of y w / q, ph - qh q = r - pl has magnitude below 2^53 and is
+// produced exactly by the fma, and the final sum of two integers below 2^53 is exact. All FP64
+// instructions issue at the full VALU rate on gfx950, so a product costs 5 instructions instead
+// of the ~16 of the 64-bit integer form.
+__device__ __forceinline__ double fp_mul(double y, double w, double q, double qinv) {
+    const double ph = y * w;
+    const double pl = __fma_rn(y, w, -ph);
+    const double qh = rint(ph * qinv);
+    return __fma_rn(-qh, q, ph) + pl;
+}
+// v - rint(v / q) q: |result| <= 0.51 q for integer-valued |v| < 2^51
+__device__ __forceinline__ double fp_center(double v, double q, double qinv) {
+    return __fma_rn(-rint(v * qinv), q, v);
+}
+__device__ __forceinline__ u64 fp_to_u64(double v, double q, double qinv) {
+    double r = fp_center(v, q, qinv);
+    r = r < 0.0 ? r + q : r;
+    return (u64)r;
+}
+__device__ __forceinline__ double u64_to_fp(u64 x) { return (double)x; }   // x < 2^53: exact
+
 // Index gathered by the automorphism X -> X^g in bit-reversed NTT order:
 // out[i] = in[brv((g (2 brv(i) + 1) mod 2N - 1) / 2)].
 __device__ __forceinline__ int galois_src(int i, u64 g, int logn) {
@@ -121,8 +147,8 @@ __device__ __forceinline__ int pass_index(int g, int e, int tid) {
     return ((rest >> LO) << (LO + RB)) | (e << LO) | (rest & ((1 << LO) - 1));
 }
 
-template <int LOGN, int LO, int RB>
-__device__ __forceinline__ void to_lds(const u64 (&v)[16], u64 *lds, int tid) {
+template <int LOGN, int LO, int RB, typename T>
+__device__ __forceinline__ void to_lds(const T (&v)[16], T *lds, int tid) {
     constexpr int R = 1 << RB, G = 16 / R;
 #pragma unroll
     for (int g = 0; g < G; ++g)
@@ -130,8 +156,8 @@ __device__ __forceinline__ void to_lds(const u64 (&v)[16], u64 *lds, int tid) {
         for (int e = 0; e < R; ++e) lds[lds_idx(pass_index<LOGN, LO, RB>(g, e, tid))] = v[g * R + e];
 }
 
-template <int LOGN, int LO, int RB>
-__device__ __forceinline__ void from_lds(u64 (&v)[16], const u64 *lds, int tid) {
+template <int LOGN, int LO, int RB, typename T>
+__device__ __forceinline__ void from_lds(T (&v)[16], const T *lds, int tid) {
     constexpr int R = 1 << RB, G = 16 / R;
 #pragma unroll
     for (int g = 0; g < G; ++g)
@@ -185,6 +211,121 @@ __device__ __forceinline__ void inv_pass(u64 (&v)[16], int tid, const u64 *__res
                 v[g * R + e + half] = shoup_lazy(x + q2 - y, w, ws, q, qn);
             }
         }
+    }
+}
+
+// FP64 Cooley-Tukey stages (prime < 2^41): t = w y with |t| <= 0.52 q, outputs x + t and x - t.
+// From canonical inputs the magnitude stays below (1 + 0.52 s) q after s stages (< 2^45 after 14),
+// so no intermediate reduction is needed.
+template <int LOGN, int LO, int RB>
+__device__ __forceinline__ void fwd_pass_fp(double (&v)[16], int tid, const double *__restrict__ tw, double q,
+                                            double qinv) {
+    constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int hi = (g * Geo<LOGN>::T + tid) >> LO;
+#pragma unroll
+        for (int sb = RB - 1; sb >= 0; --sb) {
+            const int b = LO + sb, half = 1 << sb;
+#pragma unroll
+            for (int e = 0; e < R; ++e) {
+                if (e & half) continue;
+                const int widx = (N >> (b + 1)) + ((hi << (RB - 1 - sb)) | (e >> (sb + 1)));
+                const double t = fp_mul(v[g * R + e + half], tw[widx], q, qinv);
+                const double x = v[g * R + e];
+                v[g * R + e] = x + t;
+                v[g * R + e + half] = x - t;
+            }
+        }
+    }
+}
+
+// FP64 Gentleman-Sande stages: x + y and (x - y) w. Sums double per stage, so every value is
+// centered (|v| <= 0.51 q) at the end of each pass: within a pass of at most 4 stages magnitudes
+// stay below 16 q < 2^45.
+template <int LOGN, int LO, int RB>
+__device__ __forceinline__ void inv_pass_fp(double (&v)[16], int tid, const double *__restrict__ tw, double q,
+                                            double qinv) {
+    constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int hi = (g * Geo<LOGN>::T + tid) >> LO;
+#pragma unroll
+        for (int sb = 0; sb < RB; ++sb) {
+            const int b = LO + sb, half = 1 << sb;
+#pragma unroll
+            for (int e = 0; e < R; ++e) {
+                if (e & half) continue;
+                const int widx = (N >> (b + 1)) + ((hi << (RB - 1 - sb)) | (e >> (sb + 1)));
+                const double x = v[g * R + e], y = v[g * R + e + half];
+                v[g * R + e] = x + y;
+                v[g * R + e + half] = fp_mul(x - y, tw[widx], q, qinv);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = fp_center(v[e], q, qinv);
+}
+
+// FP64 cores: same pass plans and LDS exchanges as the integer cores below, on doubles.
+template <int LOGN>
+__device__ __forceinline__ void ntt_fwd_core_fp(double (&v)[16], double *lds, int tid, const double *tw,
+                                                double q, double qinv) {
+    if constexpr (LOGN == 12) {
+        fwd_pass_fp<12, 8, 4>(v, tid, tw, q, qinv);
+        to_lds<12, 8, 4>(v, lds, tid); __syncthreads();
+        from_lds<12, 4, 4>(v, lds, tid); fwd_pass_fp<12, 4, 4>(v, tid, tw, q, qinv);
+        to_lds<12, 4, 4>(v, lds, tid); __syncthreads();
+        from_lds<12, 0, 4>(v, lds, tid); fwd_pass_fp<12, 0, 4>(v, tid, tw, q, qinv);
+        to_lds<12, 0, 4>(v, lds, tid); __syncthreads();
+    } else if constexpr (LOGN == 13) {
+        fwd_pass_fp<13, 9, 4>(v, tid, tw, q, qinv);
+        to_lds<13, 9, 4>(v, lds, tid); __syncthreads();
+        from_lds<13, 6, 3>(v, lds, tid); fwd_pass_fp<13, 6, 3>(v, tid, tw, q, qinv);
+        to_lds<13, 6, 3>(v, lds, tid); __syncthreads();
+        from_lds<13, 3, 3>(v, lds, tid); fwd_pass_fp<13, 3, 3>(v, tid, tw, q, qinv);
+        to_lds<13, 3, 3>(v, lds, tid); __syncthreads();
+        from_lds<13, 0, 3>(v, lds, tid); fwd_pass_fp<13, 0, 3>(v, tid, tw, q, qinv);
+        to_lds<13, 0, 3>(v, lds, tid); __syncthreads();
+    } else {
+        static_assert(LOGN == 14, "unsupported ring degree");
+        fwd_pass_fp<14, 10, 4>(v, tid, tw, q, qinv);
+        to_lds<14, 10, 4>(v, lds, tid); __syncthreads();
+        from_lds<14, 6, 4>(v, lds, tid); fwd_pass_fp<14, 6, 4>(v, tid, tw, q, qinv);
+        to_lds<14, 6, 4>(v, lds, tid); __syncthreads();
+        from_lds<14, 3, 3>(v, lds, tid); fwd_pass_fp<14, 3, 3>(v, tid, tw, q, qinv);
+        to_lds<14, 3, 3>(v, lds, tid); __syncthreads();
+        from_lds<14, 0, 3>(v, lds, tid); fwd_pass_fp<14, 0, 3>(v, tid, tw, q, qinv);
+        to_lds<14, 0, 3>(v, lds, tid); __syncthreads();
+    }
+}
+
+template <int LOGN>
+__device__ __forceinline__ void ntt_inv_core_fp(double (&v)[16], double *lds, int tid, const double *tw,
+                                                double q, double qinv) {
+    if constexpr (LOGN == 12) {
+        from_lds<12, 0, 4>(v, lds, tid); inv_pass_fp<12, 0, 4>(v, tid, tw, q, qinv);
+        to_lds<12, 0, 4>(v, lds, tid); __syncthreads();
+        from_lds<12, 4, 4>(v, lds, tid); inv_pass_fp<12, 4, 4>(v, tid, tw, q, qinv);
+        to_lds<12, 4, 4>(v, lds, tid); __syncthreads();
+        from_lds<12, 8, 4>(v, lds, tid); inv_pass_fp<12, 8, 4>(v, tid, tw, q, qinv);
+    } else if constexpr (LOGN == 13) {
+        from_lds<13, 0, 3>(v, lds, tid); inv_pass_fp<13, 0, 3>(v, tid, tw, q, qinv);
+        to_lds<13, 0, 3>(v, lds, tid); __syncthreads();
+        from_lds<13, 3, 3>(v, lds, tid); inv_pass_fp<13, 3, 3>(v, tid, tw, q, qinv);
+        to_lds<13, 3, 3>(v, lds, tid); __syncthreads();
+        from_lds<13, 6, 3>(v, lds, tid); inv_pass_fp<13, 6, 3>(v, tid, tw, q, qinv);
+        to_lds<13, 6, 3>(v, lds, tid); __syncthreads();
+        from_lds<13, 9, 4>(v, lds, tid); inv_pass_fp<13, 9, 4>(v, tid, tw, q, qinv);
+    } else {
+        static_assert(LOGN == 14, "unsupported ring degree");
+        from_lds<14, 0, 3>(v, lds, tid); inv_pass_fp<14, 0, 3>(v, tid, tw, q, qinv);
+        to_lds<14, 0, 3>(v, lds, tid); __syncthreads();
+        from_lds<14, 3, 3>(v, lds, tid); inv_pass_fp<14, 3, 3>(v, tid, tw, q, qinv);
+        to_lds<14, 3, 3>(v, lds, tid); __syncthreads();
+        from_lds<14, 6, 4>(v, lds, tid); inv_pass_fp<14, 6, 4>(v, tid, tw, q, qinv);
+        to_lds<14, 6, 4>(v, lds, tid); __syncthreads();
+        from_lds<14, 10, 4>(v, lds, tid); inv_pass_fp<14, 10, 4>(v, tid, tw, q, qinv);
     }
 }
 
@@ -264,6 +405,34 @@ __device__ __forceinline__ long res_offset(const ResMap &m, int r) {
 }
 
 // ---------------------------------------------------------------- NTT kernels
+// Every NTT-bearing kernel picks the arithmetic per workgroup from its prime (uniform branch):
+// FP64 for primes below 2^41, 64-bit integer otherwise. Inputs and outputs are canonical residues
+// in [0, q) either way, so the results are the same integers.
+
+// Forward transform of canonical values v[e] (element tid + T e) held in registers; the result is
+// left in LDS (as doubles for an FP64 prime, as lazy [0, 4q) integers otherwise). Returns fp.
+template <int LOGN>
+__device__ __forceinline__ bool fwd_transform(u64 (&v)[16], u64 *lds, int tid, const Tables &tab, int pi,
+                                              const PrimeConst &p) {
+    constexpr int N = Geo<LOGN>::N;
+    if (p.fp) {
+        double d[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) d[e] = u64_to_fp(v[e]);
+        ntt_fwd_core_fp<LOGN>(d, reinterpret_cast<double *>(lds), tid,
+                              reinterpret_cast<const double *>(tab.tws + (long)pi * N), p.qd, p.qinv);
+        return true;
+    }
+    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pi * N, tab.tws + (long)pi * N, p);
+    return false;
+}
+
+// Canonical value of output element j of fwd_transform.
+__device__ __forceinline__ u64 fwd_result(const u64 *lds, int j, bool fp, const PrimeConst &p) {
+    if (fp) return fp_to_u64(reinterpret_cast<const double *>(lds)[lds_idx(j)], p.qd, p.qinv);
+    return red4(lds[lds_idx(j)], p.q, p.q2);
+}
+
 template <int LOGN>
 __global__ void __launch_bounds__(Geo<LOGN>::T)
 k_ntt_fwd(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap omap, Tables tab) {
@@ -277,9 +446,9 @@ k_ntt_fwd(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
     u64 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = src[tid + T * e];
-    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pi * N, tab.tws + (long)pi * N, p);
+    const bool fp = fwd_transform<LOGN>(v, lds, tid, tab, pi, p);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) dst[tid + T * e] = red4(lds[lds_idx(tid + T * e)], p.q, p.q2);
+    for (int e = 0; e < 16; ++e) dst[tid + T * e] = fwd_result(lds, tid + T * e, fp, p);
 }
 
 template <int LOGN>
@@ -292,6 +461,17 @@ k_ntt_inv(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
     const PrimeConst p = tab.pc[pi];
     const u64 *src = in + res_offset(imap, r) * N;
     u64 *dst = out + res_offset(omap, r) * N;
+    if (p.fp) {
+        double *dl = reinterpret_cast<double *>(lds);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) dl[lds_idx(tid + T * e)] = u64_to_fp(src[tid + T * e]);
+        __syncthreads();
+        double d[16];
+        ntt_inv_core_fp<LOGN>(d, dl, tid, reinterpret_cast<const double *>(tab.itws + (long)pi * N), p.qd, p.qinv);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) dst[tid + T * e] = fp_to_u64(fp_mul(d[e], p.ninvd, p.qd, p.qinv), p.qd, p.qinv);
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < 16; ++e) lds[lds_idx(tid + T * e)] = src[tid + T * e];
     __syncthreads();
@@ -331,9 +511,9 @@ k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u6
     u64 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qj, qj_mod, p);
-    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pt * N, tab.tws + (long)pt * N, p);
+    const bool fp = fwd_transform<LOGN>(v, lds, tid, tab, pt, p);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) dst[tid + T * e] = red4(lds[lds_idx(tid + T * e)], p.q, p.q2);
+    for (int e = 0; e < 16; ++e) dst[tid + T * e] = fwd_result(lds, tid + T * e, fp, p);
 }
 
 // Drop the last modulus of each group (ModDown when it is P, rescale when it is q_k):
@@ -357,13 +537,24 @@ k_drop(const u64 *__restrict__ x, const u64 *__restrict__ last, u64 *__restrict_
     u64 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qd, cc.qj_mod_qi, p);
-    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)i * N, tab.tws + (long)i * N, p);
+    const bool fp = fwd_transform<LOGN>(v, lds, tid, tab, i, p);
     const u64 *xi = x + ((long)grp * (k + 1) + i) * N;
     u64 *dst = out + ((long)grp * k + i) * N;
     const int c = grp & 1, r = (grp >> 1) % add.R, b = (grp >> 1) / add.R;
     const bool has_add = (add.mask >> c) & 1;
     const u64 *ap = has_add ? add.base + b * add.sb + r * add.sr + c * add.sc + (long)i * N : nullptr;
     const u64 g = add.gal[r];
+    if (fp) {
+        const double *dl = reinterpret_cast<const double *>(lds);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int jj = tid + T * e;
+            double val = fp_mul(u64_to_fp(xi[jj]) - dl[lds_idx(jj)], cc.invd, p.qd, p.qinv);
+            if (has_add) val += u64_to_fp(ap[g == 1 ? jj : galois_src(jj, g, LOGN)]);
+            dst[jj] = fp_to_u64(val, p.qd, p.qinv);
+        }
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int jj = tid + T * e;
@@ -393,10 +584,10 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
         const u64 m = reduce_any((u64)(a < 0 ? -a : a), p);
         v[e] = a < 0 ? neg_mod(m, p.q) : m;
     }
-    ntt_fwd_core<LOGN>(v, lds, tid, tab.tw + (long)pi * N, tab.tws + (long)pi * N, p);
+    const bool fp = fwd_transform<LOGN>(v, lds, tid, tab, pi, p);
     u64 *dst = out + ((long)grp * pl.n + slot) * N;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) dst[tid + T * e] = red4(lds[lds_idx(tid + T * e)], p.q, p.q2);
+    for (int e = 0; e < 16; ++e) dst[tid + T * e] = fwd_result(lds, tid + T * e, fp, p);
 }
 
 // ---------------------------------------------------------------- elementwise kernels
@@ -417,6 +608,29 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
     const u64 g = keys.gal[r];
     const u64 *key = keys.key[r];
     const int src = g == 1 ? n : galois_src(n, g, logn);
+    if (p.fp) {
+        // FP64 products (prime < 2^41): each term |.| <= 0.52 q, sums stay far below 2^53
+        double kb[K], ka[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            kb[j] = u64_to_fp(key[((long)(j * 2 + 0) * np + pt) * N + n]);
+            ka[j] = u64_to_fp(key[((long)(j * 2 + 1) * np + pt) * N + n]);
+        }
+        for (int b = 0; b < B; ++b) {
+            const u64 *d = digits + b * db + r * dr + (long)t * N + src;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const double x = u64_to_fp(d[(long)j * (K + 1) * N]);
+                a0 += fp_mul(x, kb[j], p.qd, p.qinv);
+                a1 += fp_mul(x, ka[j], p.qd, p.qinv);
+            }
+            u64 *o = out + ((long)(b * R + r) * 2) * (K + 1) * N + (long)t * N + n;
+            o[0] = fp_to_u64(a0, p.qd, p.qinv);
+            o[(long)(K + 1) * N] = fp_to_u64(a1, p.qd, p.qinv);
+        }
+        return;
+    }
     u64 kb[K], ka[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -465,6 +679,56 @@ k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__rest
     const PrimeConst p = pcs[i];
     const u64 *ct_b = ct + (long)(live ? b : 0) * 2 * kn + i * N + n0 + nl;
     const u64 *rot_b = rot + (long)(live ? b : 0) * (t1 - 1) * 2 * kn + i * N + n0 + nl;
+    if (p.fp) {
+        // FP64 products (prime < 2^41); the staged plaintext words are converted once, in LDS
+        double *wd = reinterpret_cast<double *>(wt);
+        for (int kc0 = 0; kc0 < t2; kc0 += KC) {
+            double acc[KC][2];
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) acc[kk][0] = acc[kk][1] = 0.0;
+            for (int j0 = 0; j0 < t1; j0 += kMacJB) {
+                const int jn = t1 - j0 < kMacJB ? t1 - j0 : kMacJB;
+                double x[kMacJB][2];
+#pragma unroll
+                for (int jj = 0; jj < kMacJB; ++jj) {
+                    const int j = j0 + jj;
+                    if (live && jj < jn) {
+                        const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
+                        x[jj][0] = u64_to_fp(src[0]);
+                        x[jj][1] = u64_to_fp(src[kn]);
+                    } else {
+                        x[jj][0] = x[jj][1] = 0.0;
+                    }
+                }
+                __syncthreads();
+                for (int e = tid; e < jn * KC * 64; e += nthr) {
+                    const int jj = e / (KC * 64), kk = (e / 64) % KC;
+                    wd[e] = u64_to_fp(bank[((long)(kc0 + kk) * t1 + j0 + jj) * kn + i * N + n0 + (e & 63)]);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int jj = 0; jj < kMacJB; ++jj) {
+                    if (jj < jn) {
+#pragma unroll
+                        for (int kk = 0; kk < KC; ++kk) {
+                            const double w = wd[(jj * KC + kk) * 64 + nl];
+                            acc[kk][0] += fp_mul(x[jj][0], w, p.qd, p.qinv);
+                            acc[kk][1] += fp_mul(x[jj][1], w, p.qd, p.qinv);
+                        }
+                    }
+                }
+            }
+            if (live) {
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk) {
+                    u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
+                    o[0] = fp_to_u64(acc[kk][0], p.qd, p.qinv);
+                    o[kn] = fp_to_u64(acc[kk][1], p.qd, p.qinv);
+                }
+            }
+        }
+        return;
+    }
     for (int kc0 = 0; kc0 < t2; kc0 += KC) {
         Acc acc[KC][2];
 #pragma unroll
