@@ -110,6 +110,11 @@ def main():
                     help="giant steps lowered by one ModDown of their summed key products (lazy) or one "
                          "ModDown each (per-step); the other variant is timed too, without profiling")
     ap.add_argument("--other-steps", type=int, default=3, help="timed steps of the other giant-step variant")
+    ap.add_argument("--workload", choices=("large", "mix"), default="large",
+                    help="large: the 768->256->64 stack, batch 64 (the headline); mix: 512 queries of "
+                         "1-3 layers with widths from {128,256,512,768}")
+    ap.add_argument("--mix-queries", type=int, default=512)
+    ap.add_argument("--graphs", action="store_true", help="mix: replay captured HIP graphs of the dense calls")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB once (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -121,6 +126,9 @@ def main():
 
     import torch
     import paper_2205_11935_amd as ctl
+
+    if args.workload == "mix":
+        return bench_mix(args)
 
     w = W.LARGE
     B = args.batch
@@ -304,6 +312,53 @@ def main():
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
         line["cpu_baseline"]["cores"] = 1
+    print(json.dumps(line), flush=True)
+
+
+def bench_mix(args):
+    """Throughput of the batched mix: queries of 1-3 dense layers with widths drawn from
+    {128,256,512,768}, evaluated position by position with banks shared per shape."""
+    import torch
+    import paper_2205_11935_amd as ctl
+    from paper_2205_11935_amd.batch_mix import MixEngine
+    w = W.LARGE
+    c = ctl.Context.for_workload(w)
+    queries = W.mix_queries(args.mix_queries)
+    t0 = time.perf_counter()
+    keys = c.keygen(w.seed_keys, MixEngine.rotations(queries, W.MIX_T1), relin=True)
+    eng = MixEngine(c, keys, lambda p, a, b, t: W.mix_weights(p, a, b), W.MIX_T1, W.MIX_BLOCK, lazy=True,
+                    graphs=args.graphs)
+    items = (c.n // 2) // W.MIX_BLOCK
+    xs = W.mix_inputs(queries, items)
+    dev = c.empty_ct(len(queries), c.nq)
+    for i, q in enumerate(queries):
+        c.encrypt(keys, c.encode_items(eng.model(0, q.widths[0], q.widths[1]), xs[i]), 9000 + i, out=dev[i])
+    for q in queries:                       # every bank the batch touches, before timing
+        for l in range(q.depth):
+            eng.model(l, q.widths[l], q.widths[l + 1])
+    setup_s = time.perf_counter() - t0
+    eng.run(dev, queries)
+    torch.cuda.synchronize()
+    if args.graphs:
+        eng.freeze()
+        eng.run(dev, queries)               # capture
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        eng.run(dev, queries)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    depth_hist = {d: sum(1 for q in queries if q.depth == d) for d in (1, 2, 3)}
+    line = {
+        "metric": "encrypted fwd passes/sec at N=2^14, batched mix of layer widths and depths",
+        "value": round(len(queries) * args.steps / dt, 3), "unit": "encrypted forward passes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "mix: %d queries, 1-3 dense layers, widths from {128,256,512,768}, N=2^14, "
+                               "block 1536 (5 items per ciphertext)" % len(queries),
+                   "depths": depth_hist, "banks": len(eng.models), "graphs": bool(args.graphs)},
+        "setup_s": round(setup_s, 2),
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -103,6 +103,12 @@ int ctl_set_allocator(ctl_ctx *ctx, ctl_alloc_fn alloc, ctl_free_fn free_fn, voi
 /* Bytes of device workspace the context currently holds (grows on demand, freed with the ctx). */
 int ctl_workspace_bytes(const ctl_ctx *ctx, uint64_t *bytes_out);
 
+/* Freeze (frozen = 1) or unfreeze the workspace. While frozen the workspace never moves: a call that
+ * would need more of it fails with CTL_ENOMEM instead of reallocating. Freeze after a first run of
+ * the largest shapes before capturing launch sequences into a HIP graph, so that captured graphs
+ * never refer to freed workspace. */
+int ctl_workspace_freeze(ctl_ctx *ctx, int frozen);
+
 /* Forward (inverse = 0) or inverse (inverse = 1) negacyclic NTT, in place, of n_res residue
  * polynomials of N words each, stored back to back at device pointer `dev`. prime_idx: host
  * array of n_res prime indices (0..n_q-1 for q_i, n_q for P). Values must be < their prime. */
@@ -191,6 +197,23 @@ typedef struct ctl_model_info {
     int layer_k[8];      /* live primes at each layer's input */
     int layer_t[8];      /* padded width t of each layer */
 } ctl_model_info;
+
+/* Plan overrides for models that share one slot layout or start below the top level (used when
+ * several models serve one batch, e.g. layers of different widths at different depths): block =
+ * slot stride per item (0: 2 t_max of this model; else at least 2 t_max and at most N/2); k_in =
+ * live primes at the first layer's input (0: all n_q); scale_in = input scale (0: 2^log2_scale). */
+typedef struct ctl_model_opts {
+    int block;
+    int k_in;
+    double scale_in;
+} ctl_model_opts;
+
+/* Load a model from FP64 weights (weights != NULL) or from already-encoded integer plaintexts
+ * (pts != NULL; exactly one of the two), with optional plan overrides (opts may be NULL). The
+ * other two load calls are this one with opts = NULL. */
+int ctl_model_load_ex(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers,
+                      const double *const *weights, const int64_t *const *pts,
+                      const ctl_model_opts *opts, ctl_model **model_out);
 
 /* Load the frozen layers from FP64 weights: W[l] is a host row-major [n_out][n_in] matrix. The
  * diagonal plaintexts diag'_i (Eq. (1)) are encoded at the scale of the prime each layer's rescale

@@ -46,6 +46,10 @@ class _LayerDesc(ctypes.Structure):
                 ("flags", ctypes.c_int)]
 
 
+class _ModelOpts(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("k_in", ctypes.c_int), ("scale_in", ctypes.c_double)]
+
+
 class _ModelInfo(ctypes.Structure):
     _fields_ = [("n_layers", ctypes.c_int), ("block", ctypes.c_int), ("items", ctypes.c_int),
                 ("k_in", ctypes.c_int), ("k_out", ctypes.c_int), ("n_in", ctypes.c_int), ("n_out", ctypes.c_int),
@@ -89,6 +93,10 @@ _SIGS = {
                                       ctypes.POINTER(f64p), ctypes.POINTER(ctypes.c_void_p)]),
     "ctl_model_load_raw": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_LayerDesc), ctypes.c_int,
                                           ctypes.POINTER(i64p), ctypes.POINTER(ctypes.c_void_p)]),
+    "ctl_model_load_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_LayerDesc), ctypes.c_int,
+                                         ctypes.POINTER(f64p), ctypes.POINTER(i64p), ctypes.POINTER(_ModelOpts),
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "ctl_workspace_freeze": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "ctl_model_free": (ctypes.c_int, [ctypes.c_void_p]),
     "ctl_model_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_ModelInfo)]),
     "ctl_model_rotations": (ctypes.c_int, [ctypes.c_void_p, i32p, ctypes.POINTER(ctypes.c_int)]),
@@ -399,6 +407,26 @@ class Context:
         _check(lib().ctl_model_load_raw(self.handle, self._descs(layers, lazy), len(layers), ptrs,
                                         ctypes.byref(h)))
         return Model(self, h)
+
+    def load_model_ex(self, layers, weights=None, pts=None, lazy: bool = False, block: int = 0, k_in: int = 0,
+                      scale_in: float = 0.0) -> Model:
+        """One of weights (float64 [n_out][n_in] per layer) or pts (int64 [t][N] per layer), with plan
+        overrides: a shared slot stride `block`, the starting level `k_in`, the input scale."""
+        opts = _ModelOpts(block, k_in, scale_in)
+        h = ctypes.c_void_p()
+        wp = pp = None
+        if weights is not None:
+            ws = [np.ascontiguousarray(w, dtype=np.float64) for w in weights]
+            wp = (f64p * len(ws))(*[w.ctypes.data_as(f64p) for w in ws])
+        if pts is not None:
+            ps = [np.ascontiguousarray(p, dtype=np.int64) for p in pts]
+            pp = (i64p * len(ps))(*[p.ctypes.data_as(i64p) for p in ps])
+        _check(lib().ctl_model_load_ex(self.handle, self._descs(layers, lazy), len(layers), wp, pp,
+                                       ctypes.byref(opts), ctypes.byref(h)))
+        return Model(self, h)
+
+    def workspace_freeze(self, frozen: bool = True):
+        _check(lib().ctl_workspace_freeze(self.handle, int(frozen)))
 
     def forward(self, model: Model, keys: Keys, ct, out=None, stream=None):
         n_ct = ct.shape[0]

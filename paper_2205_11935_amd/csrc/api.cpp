@@ -62,6 +62,7 @@ struct ctl_ctx {
     size_t slot_bytes[S_COUNT] = {};
     std::unique_ptr<Encoder> enc;
     std::vector<PrimeConst> pc;
+    bool ws_frozen = false;
     // launch instrumentation
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;      // pairs (start, stop)
@@ -122,6 +123,9 @@ void dev_free(ctl_ctx *c, void *p, hipStream_t st) {
 int slot(ctl_ctx *c, Slot s, size_t words, hipStream_t st, u64 **out) {
     const size_t bytes = std::max<size_t>(words * 8, 256);
     if (c->slot_bytes[s] < bytes) {
+        if (c->ws_frozen)
+            return fail(CTL_ENOMEM, "workspace is frozen and this call needs " + std::to_string(bytes) +
+                                        " bytes in a slot holding " + std::to_string(c->slot_bytes[s]));
         CTL_HIP(hipStreamSynchronize(st));
         dev_free(c, c->slot_ptr[s], st);
         c->slot_ptr[s] = nullptr;
@@ -458,7 +462,8 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
 }
 
 // ---------------------------------------------------------------- model planning
-int plan_model(const ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, ctl_model *m) {
+int plan_model(const ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, const ctl_model_opts *opts,
+               ctl_model *m) {
     if (!layers || n_layers < 1 || n_layers > 8) return fail(CTL_EINVAL, "1..8 layers supported");
     int tmax = 0;
     for (int l = 0; l < n_layers; ++l) {
@@ -473,10 +478,23 @@ int plan_model(const ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, ctl
         tmax = std::max(tmax, t);
     }
     m->block = 2 * tmax;
+    if (opts && opts->block) {
+        if (opts->block < 2 * tmax || opts->block > c->hp.n / 2)
+            return fail(CTL_EINVAL, "block must lie in [2 t_max, N/2]");
+        m->block = opts->block;
+    }
     m->items = (c->hp.n / 2) / m->block;
     if (m->items < 1) return fail(CTL_EINVAL, "layers wider than N/4 slots");
     int k = c->hp.nq;
+    if (opts && opts->k_in) {
+        if (opts->k_in < 2 || opts->k_in > c->hp.nq) return fail(CTL_ELEVEL, "k_in out of range");
+        k = opts->k_in;
+    }
     double scale = std::ldexp(1.0, c->hp.log2_scale);
+    if (opts && opts->scale_in != 0.0) {
+        if (!(opts->scale_in > 0.0) || !std::isfinite(opts->scale_in)) return fail(CTL_ESCALE, "bad scale_in");
+        scale = opts->scale_in;
+    }
     m->scale_in = scale;
     std::vector<int32_t> rots;
     for (int l = 0; l < n_layers; ++l) {
@@ -589,12 +607,12 @@ int load_banks(ctl_ctx *c, ctl_model *m, const std::vector<std::vector<int64_t>>
 }
 
 int make_model(ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, const int64_t *const *pts,
-               const double *const *weights, ctl_model **out) {
+               const double *const *weights, const ctl_model_opts *opts, ctl_model **out) {
     if (!c || !out) return fail(CTL_EINVAL, "null argument");
     std::unique_ptr<ctl_model> m(new (std::nothrow) ctl_model());
     if (!m) return fail(CTL_ENOMEM, "host allocation failed");
     m->ctx = c;
-    CTL_TRY(plan_model(c, layers, n_layers, m.get()));
+    CTL_TRY(plan_model(c, layers, n_layers, opts, m.get()));
     CTL_HIP(hipSetDevice(c->device));
     int rc;
     if (pts) {
@@ -779,6 +797,12 @@ int ctl_set_allocator(ctl_ctx *ctx, ctl_alloc_fn alloc, ctl_free_fn free_fn, voi
     ctx->alloc = alloc;
     ctx->free_fn = free_fn;
     ctx->user = user;
+    return CTL_OK;
+}
+
+int ctl_workspace_freeze(ctl_ctx *ctx, int frozen) {
+    if (!ctx) return fail(CTL_EINVAL, "null context");
+    ctx->ws_frozen = frozen != 0;
     return CTL_OK;
 }
 
@@ -1015,16 +1039,22 @@ int ctl_evk_galois(const ctl_evk *evk, uint64_t *elts_out, int *n_out) {
 }
 
 // ---------------------------------------------------------------- model
+int ctl_model_load_ex(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers, const double *const *weights,
+                      const int64_t *const *pts, const ctl_model_opts *opts, ctl_model **model_out) {
+    if ((weights == nullptr) == (pts == nullptr)) return fail(CTL_EINVAL, "give exactly one of weights and pts");
+    return make_model(ctx, layers, n_layers, pts, weights, opts, model_out);
+}
+
 int ctl_model_load(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers, const double *const *weights,
                    ctl_model **model_out) {
     if (!weights) return fail(CTL_EINVAL, "null weights");
-    return make_model(ctx, layers, n_layers, nullptr, weights, model_out);
+    return make_model(ctx, layers, n_layers, nullptr, weights, nullptr, model_out);
 }
 
 int ctl_model_load_raw(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers, const int64_t *const *pts,
                        ctl_model **model_out) {
     if (!pts) return fail(CTL_EINVAL, "null plaintexts");
-    return make_model(ctx, layers, n_layers, pts, nullptr, model_out);
+    return make_model(ctx, layers, n_layers, pts, nullptr, nullptr, model_out);
 }
 
 int ctl_model_free(ctl_model *model) {

@@ -126,3 +126,43 @@ def residues(seed: int, count: int, n: int, bits: int = 64, stream: int = 0) -> 
     g = _rng(seed, 2000 + stream)
     return np.ascontiguousarray(g.integers(0, 1 << bits, size=(count, n), dtype=np.uint64,
                                            endpoint=False))
+
+
+# ---------------------------------------------------------------------------------------------
+# Batched mix of layer widths: 512 independent queries on the large workload's chain, each with
+# d ~ U{1,2,3} dense layers and widths w_0..w_d ~ U{128,256,512,768}; x^2 between layers; weights
+# drawn per (position, w_in, w_out) and shared by every query with that shape; one slot layout for
+# all queries (block stride 1536 = 2 * 768, 5 items per ciphertext).
+MIX_WIDTHS = (128, 256, 512, 768)
+MIX_T1 = {128: 16, 256: 16, 512: 32, 768: 32}      # BSGS split of each padded width
+MIX_BLOCK = 1536
+MIX_SEED = 4000
+
+
+@dataclasses.dataclass(frozen=True)
+class Query:
+    widths: Tuple[int, ...]          # w_0 .. w_d
+
+    @property
+    def depth(self) -> int:
+        return len(self.widths) - 1
+
+
+def mix_queries(n: int = 512, seed: int = MIX_SEED, widths=MIX_WIDTHS, max_depth: int = 3) -> List[Query]:
+    g = _rng(seed, 5)
+    out = []
+    for _ in range(n):
+        d = int(g.integers(1, max_depth + 1))
+        out.append(Query(tuple(int(widths[i]) for i in g.integers(0, len(widths), size=d + 1))))
+    return out
+
+
+def mix_weights(pos: int, w_in: int, w_out: int, seed: int = MIX_SEED) -> np.ndarray:
+    g = _rng(seed + 1, pos * 1_000_000 + w_in * 1000 + w_out)
+    return np.ascontiguousarray(g.normal(0.0, 0.05, size=(w_out, w_in)), dtype=np.float64)
+
+
+def mix_inputs(queries: List[Query], items: int, seed: int = MIX_SEED) -> List[np.ndarray]:
+    g = _rng(seed + 2, 0)
+    return [np.ascontiguousarray(np.clip(g.normal(0.0, 1.0, size=(items, q.widths[0])), -3.0, 3.0))
+            for q in queries]
