@@ -110,9 +110,12 @@ def main():
                     help="giant steps lowered by one ModDown of their summed key products (lazy) or one "
                          "ModDown each (per-step); the other variant is timed too, without profiling")
     ap.add_argument("--other-steps", type=int, default=3, help="timed steps of the other giant-step variant")
-    ap.add_argument("--workload", choices=("large", "mix"), default="large",
+    ap.add_argument("--workload", choices=("large", "mix", "serve"), default="large",
                     help="large: the 768->256->64 stack, batch 64 (the headline); mix: 512 queries of "
-                         "1-3 layers with widths from {128,256,512,768}")
+                         "1-3 layers with widths from {128,256,512,768}; serve: the serving loop alone")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="serving sweep: seconds of Poisson arrivals per rate (0: skip the sweep)")
+    ap.add_argument("--serve-rates", default="10,100,500,1000,2000", help="serving sweep: arrival rates, q/s")
     ap.add_argument("--mix-queries", type=int, default=512)
     ap.add_argument("--graphs", action="store_true", help="mix: replay captured HIP graphs of the dense calls")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -129,6 +132,8 @@ def main():
 
     if args.workload == "mix":
         return bench_mix(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     w = W.LARGE
     B = args.batch
@@ -207,6 +212,7 @@ def main():
 
     # ---------------------------------------------------------------- plain: one ciphertext per sequence
     plain = None
+    one = one_out = None
     if args.plain_steps > 0:
         one, one_out = ct[:1].contiguous(), c.empty_ct(1, model.info.k_out)
         for _ in range(2):
@@ -309,9 +315,90 @@ def main():
         "setup_s": round(setup_s, 2),
         "workspace_gib": round(c.workspace_bytes() / 2 ** 30, 2),
     }
+    if args.serve_seconds > 0:
+        del c, model, other, keys, ct, out, one, one_out, buf
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        line["serving"] = serving_sweep(args)
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
         line["cpu_baseline"]["cores"] = 1
+    print(json.dumps(line), flush=True)
+
+
+def serving_sweep(args):
+    """The serving loop under Poisson load: 80% of queries on the mid parameter set (N=2^13,
+    512->128->128) and 20% on the large one (N=2^14, 768->256->64), four clients per set with
+    their evaluation keys resident in HBM, continuous batching on two lanes per set."""
+    import torch
+    import paper_2205_11935_amd as ctl
+    from paper_2205_11935_amd.serving import GpuServer, PsetSpec, Request, latency_stats, poisson_arrivals
+    t0 = time.perf_counter()
+    wl = {"mid": W.MID, "large": W.LARGE}
+    specs = [PsetSpec("mid", W.MID, W.weights(W.MID), slot_bytes_budget=1 << 30, max_batch=64, lanes=2),
+             PsetSpec("large", W.LARGE, W.weights(W.LARGE), slot_bytes_budget=2 << 30, max_batch=64, lanes=2)]
+    clients = {c: ("mid" if c < 4 else "large") for c in range(8)}
+    cctx = {p: ctl.Context.for_workload(wl[p]) for p in wl}
+    cmodel = {p: cctx[p].load_model([(l.n_in, l.n_out, l.t1) for l in wl[p].layers], W.weights(wl[p]), lazy=True)
+              for p in wl}
+    uploads, cts = {}, {}
+    g = np.random.Generator(np.random.PCG64(W.MIX_SEED + 9))
+    for c, p in clients.items():
+        k = cctx[p].keygen(wl[p].seed_keys + 100 * c, cmodel[p].info.rotations, relin=True)
+        uploads[c] = k.evaluation_keys()
+        m = cmodel[p]
+        cts[c] = []
+        for j in range(4):
+            x = g.uniform(-1.0, 1.0, size=(m.info.items, m.info.n_in))
+            cts[c].append(cctx[p].encrypt(k, cctx[p].encode_items(m, x), seed=7000 + 10 * c + j))
+        del k
+    key_budget = sum(sum(a.nbytes for a in u.values()) for u in uploads.values()) + (64 << 20)
+    srv = GpuServer(specs, key_budget=key_budget)
+    for c, p in clients.items():
+        srv.register_client(c, p, uploads[c])
+    srv.warmup()
+    for c in clients:                               # every client's keys resident before the load
+        assert srv.keys.acquire(c)
+        srv.keys.release(c)
+    # one untimed pass of the loop itself (first calls of the gather/scatter paths on every lane)
+    warm = [Request(-1 - i, c, p, ct=cts[c][0]) for i, (c, p) in enumerate(list(clients.items()) * 2)]
+    srv.run_trace(warm, [0.0] * len(warm), timeout=120)
+    setup_s = time.perf_counter() - t0
+    sweep = []
+    rid = 0
+    for rate in [float(r) for r in args.serve_rates.split(",")]:
+        n = int(min(max(rate * args.serve_seconds, 50), 4 * rate * args.serve_seconds))
+        offs = poisson_arrivals(rate, n, seed=int(rate))
+        reqs = []
+        for i in range(n):
+            p = "mid" if g.random() < 0.8 else "large"
+            c = int(g.integers(0, 4)) + (0 if p == "mid" else 4)
+            reqs.append(Request(rid, c, p, ct=cts[c][i % 4]))
+            rid += 1
+        wall = srv.run_trace(reqs, offs, timeout=300)
+        st = latency_stats(reqs)
+        per = {p: latency_stats([r for r in reqs if r.pset == p]) for p in wl}
+        sweep.append({"rate_qps": rate, "queries": n, "wall_s": round(wall, 3),
+                      "throughput_qps": round(st["throughput_qps"], 1),
+                      "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                      "mean_batch": round(st["mean_batch"], 2), "rejected": st["rejected"],
+                      "p99_ms_by_set": {p: round(per[p]["p99_ms"], 3) for p in per if per[p]["completed"]}})
+        print("serving rate %.0f q/s: %s" % (rate, json.dumps(sweep[-1])), file=sys.stderr, flush=True)
+    srv.close()
+    return {"workload": "Poisson arrivals, 80% mid (N=2^13, 512->128->128) / 20% large (N=2^14, "
+                        "768->256->64), 4 clients per set, keys resident, 2 lanes per set, batches up to 64",
+            "sweep": sweep, "key_bytes": key_budget, "setup_s": round(setup_s, 2)}
+
+
+def bench_serve(args):
+    sv = serving_sweep(args)
+    top = sv["sweep"][-1]
+    line = {"metric": "p50/p99 latency and throughput of the serving loop under Poisson load",
+            "value": top["throughput_qps"], "unit": "queries/s", "n_gpus": 1, "steps": len(sv["sweep"]),
+            "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u64", "data": "synthetic", "config": {"workload": sv["workload"]},
+            "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "serving": sv}
     print(json.dumps(line), flush=True)
 
 

@@ -25,6 +25,10 @@
  *     are enqueued asynchronously on it. Calls that return host data synchronize it first.
  *   - One context may be used by one stream at a time: calls that overlap on the same context
  *     share its workspace and race.
+ *   - Key and model handles may be used with any context of identical parameters on the same
+ *     device (several contexts, one per stream, can serve one parameter set with shared keys and
+ *     banks); a handle from a context of other parameters is rejected with CTL_EINVAL. The
+ *     context a handle was made on must outlive it.
  *
  * Readings of what the paper leaves open (prime choice, NTT order, slot order, sampling, key
  * switching variant, rounding) are listed in the design notes; the integer results of every
@@ -154,6 +158,16 @@ int ctl_pk_export(const ctl_pk *pk, uint64_t *out);
 int ctl_evk_export(const ctl_evk *evk, uint64_t galois_elt, uint64_t *out);
 /* Number of Galois keys held and their elements (host uint64 array of at least that many). */
 int ctl_evk_galois(const ctl_evk *evk, uint64_t *elts_out, int *n_out);
+/* Evaluation keys as a server receives them from a client (the protocol of Section 3 has the
+ * client hold the key pair; the server needs only these public keys to evaluate): n_keys keys,
+ * key i for Galois element galois_elts[i] (0 = relinearization key) in host array keys[i] with the
+ * export layout above. Every element must be 0 or an odd rotation element below 2N, with no
+ * duplicates, and every word must be reduced modulo the prime of its row; otherwise CTL_EINVAL
+ * and nothing is allocated. Copies the keys to device memory and blocks until done. */
+int ctl_evk_import(ctl_ctx *ctx, const uint64_t *galois_elts, int n_keys, const uint64_t *const *keys,
+                   ctl_evk **evk_out);
+/* Device bytes held by a key set / by a model's plaintext banks. */
+int ctl_evk_bytes(const ctl_evk *evk, uint64_t *bytes_out);
 
 /* ------------------------------------------------------------------ model (server side) */
 #define CTL_ACT_NONE 0
@@ -228,6 +242,7 @@ int ctl_model_free(ctl_model *model);
 int ctl_model_get_info(const ctl_model *model, ctl_model_info *info_out);
 /* Every left-rotation amount the model needs keys for (host int32 array of n_rotations). */
 int ctl_model_rotations(const ctl_model *model, int32_t *rots_out, int *n_out);
+int ctl_model_bytes(const ctl_model *model, uint64_t *bytes_out);
 
 /* ------------------------------------------------------------------ client encode / encrypt */
 /* Encode N/2 real slot values at `scale` into signed integer plaintext coefficients:

@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import os
-from typing import List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
@@ -89,6 +89,10 @@ _SIGS = {
     "ctl_pk_export": (ctypes.c_int, [ctypes.c_void_p, u64p]),
     "ctl_evk_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, u64p]),
     "ctl_evk_galois": (ctypes.c_int, [ctypes.c_void_p, u64p, ctypes.POINTER(ctypes.c_int)]),
+    "ctl_evk_import": (ctypes.c_int, [ctypes.c_void_p, u64p, ctypes.c_int, ctypes.POINTER(u64p),
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "ctl_evk_bytes": (ctypes.c_int, [ctypes.c_void_p, u64p]),
+    "ctl_model_bytes": (ctypes.c_int, [ctypes.c_void_p, u64p]),
     "ctl_model_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_LayerDesc), ctypes.c_int,
                                       ctypes.POINTER(f64p), ctypes.POINTER(ctypes.c_void_p)]),
     "ctl_model_load_raw": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_LayerDesc), ctypes.c_int,
@@ -229,6 +233,15 @@ class Keys:
         _check(lib().ctl_evk_galois(self.evk, out, ctypes.byref(n)))
         return [int(out[i]) for i in range(n.value)]
 
+    def evaluation_keys(self) -> Dict[int, np.ndarray]:
+        """Every evaluation key (Galois element -> [n_q][2][n_q+1][N]), as a client would send them."""
+        return {g: self.galois_key(g) for g in self.galois_elements()}
+
+    def nbytes(self) -> int:
+        b = ctypes.c_uint64()
+        _check(lib().ctl_evk_bytes(self.evk, ctypes.byref(b)))
+        return int(b.value)
+
     def __del__(self):
         if _LIB is not None:
             for f, h in (("ctl_sk_free", self.sk), ("ctl_pk_free", self.pk), ("ctl_evk_free", self.evk)):
@@ -248,6 +261,11 @@ class Model:
         self.info = ModelInfo(info.n_layers, info.block, info.items, info.k_in, info.k_out, info.n_in,
                               info.n_out, info.scale_in, info.scale_out, list(info.layer_k)[: info.n_layers],
                               list(info.layer_t)[: info.n_layers], [int(rots[i]) for i in range(n.value)])
+
+    def nbytes(self) -> int:
+        b = ctypes.c_uint64()
+        _check(lib().ctl_model_bytes(self.handle, ctypes.byref(b)))
+        return int(b.value)
 
     def __del__(self):
         if _LIB is not None and self.handle:
@@ -342,6 +360,19 @@ class Context:
         _check(lib().ctl_keygen(self.handle, seed, rots, len(rotations), int(relin), ctypes.byref(sk),
                                 ctypes.byref(pk), ctypes.byref(evk)))
         return Keys(self, sk, pk, evk)
+
+    def import_keys(self, keys: Dict[int, np.ndarray]) -> Keys:
+        """Evaluation keys received from a client (Galois element -> [n_q][2][n_q+1][N] uint64)."""
+        gs = sorted(keys)
+        arrs = [np.ascontiguousarray(keys[g], dtype=np.uint64) for g in gs]
+        for a in arrs:
+            if a.shape != (self.nq, 2, self.nq + 1, self.n):
+                raise ValueError("key shape %s, expected %s" % (a.shape, (self.nq, 2, self.nq + 1, self.n)))
+        elts = (ctypes.c_uint64 * max(len(gs), 1))(*gs)
+        ptrs = (u64p * max(len(arrs), 1))(*[a.ctypes.data_as(u64p) for a in arrs])
+        h = ctypes.c_void_p()
+        _check(lib().ctl_evk_import(self.handle, elts, len(gs), ptrs, ctypes.byref(h)))
+        return Keys(self, None, None, h)
 
     def encode(self, slots: np.ndarray, scale: float) -> np.ndarray:
         z = np.ascontiguousarray(slots, dtype=np.float64)

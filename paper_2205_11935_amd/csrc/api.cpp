@@ -218,6 +218,23 @@ ResMap dense_map(int per, int prime_base = 0) {
     return m;
 }
 
+// Handles made on one context may be used with any context of identical parameters on the same
+// device (for example several contexts serving one parameter set on different streams).
+bool same_params(const ctl_ctx *a, const ctl_ctx *b) {
+    if (a == b) return true;
+    if (a->device != b->device || a->hp.logn != b->hp.logn || a->hp.nq != b->hp.nq || a->hp.np != b->hp.np)
+        return false;
+    for (int i = 0; i < a->hp.np; ++i)
+        if (a->hp.mods[i] != b->hp.mods[i]) return false;
+    return true;
+}
+
+#define CTL_SAME(ctx, h, what)                                                                          \
+    do {                                                                                                \
+        if (!same_params((ctx), (h)->ctx))                                                              \
+            return fail(CTL_EINVAL, what " was made for a context with other parameters or device");     \
+    } while (0)
+
 const u64 *find_key(const ctl_evk *evk, u64 g) {
     auto it = evk->keys.find(g);
     return it == evk->keys.end() ? nullptr : it->second;
@@ -1038,6 +1055,58 @@ int ctl_evk_galois(const ctl_evk *evk, uint64_t *elts_out, int *n_out) {
     return CTL_OK;
 }
 
+int ctl_evk_import(ctl_ctx *ctx, const uint64_t *galois_elts, int n_keys, const uint64_t *const *keys,
+                   ctl_evk **evk_out) {
+    if (!ctx || !evk_out || n_keys < 0 || (n_keys > 0 && (!galois_elts || !keys)))
+        return fail(CTL_EINVAL, "bad argument");
+    const HostParams &h = ctx->hp;
+    const size_t per_prime = (size_t)h.n, key_words = (size_t)h.nq * 2 * h.np * h.n;
+    for (int i = 0; i < n_keys; ++i) {
+        const u64 g = galois_elts[i];
+        if (g != 0 && (g % 2 == 0 || g >= 2 * (u64)h.n || g == 1))
+            return fail(CTL_EINVAL, "Galois element " + std::to_string(g) + " is not a rotation of this ring");
+        for (int j = 0; j < i; ++j)
+            if (galois_elts[j] == g) return fail(CTL_EINVAL, "duplicate Galois element");
+        if (!keys[i]) return fail(CTL_EINVAL, "null key array");
+        // every word must be a canonical residue of the prime of its row
+        for (size_t row = 0; row < (size_t)h.nq * 2 * h.np; ++row) {
+            const u64 q = h.mods[row % h.np];
+            const uint64_t *w = keys[i] + row * per_prime;
+            for (size_t x = 0; x < per_prime; ++x)
+                if (w[x] >= q) return fail(CTL_EINVAL, "key word is not reduced modulo its prime");
+        }
+    }
+    CTL_HIP(hipSetDevice(ctx->device));
+    std::unique_ptr<ctl_evk> evk(new ctl_evk());
+    evk->ctx = ctx;
+    for (int i = 0; i < n_keys; ++i) {
+        u64 *key = static_cast<u64 *>(dev_alloc(ctx, key_words * 8, nullptr));
+        if (!key || hipMemcpy(key, keys[i], key_words * 8, hipMemcpyHostToDevice) != hipSuccess) {
+            if (key) dev_free(ctx, key, nullptr);
+            for (auto &kv : evk->keys) dev_free(ctx, kv.second, nullptr);
+            return fail(key ? CTL_EHIP : CTL_ENOMEM, "Galois key upload failed");
+        }
+        evk->keys[galois_elts[i]] = key;
+    }
+    *evk_out = evk.release();
+    return CTL_OK;
+}
+
+int ctl_evk_bytes(const ctl_evk *evk, uint64_t *bytes_out) {
+    if (!evk || !bytes_out) return fail(CTL_EINVAL, "null argument");
+    const HostParams &h = evk->ctx->hp;
+    *bytes_out = (uint64_t)evk->keys.size() * h.nq * 2 * h.np * h.n * 8;
+    return CTL_OK;
+}
+
+int ctl_model_bytes(const ctl_model *m, uint64_t *bytes_out) {
+    if (!m || !bytes_out) return fail(CTL_EINVAL, "null argument");
+    uint64_t b = 0;
+    for (const LayerPlan &L : m->layers) b += (uint64_t)L.t * L.k * m->ctx->hp.n * 8;
+    *bytes_out = b;
+    return CTL_OK;
+}
+
 // ---------------------------------------------------------------- model
 int ctl_model_load_ex(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers, const double *const *weights,
                       const int64_t *const *pts, const ctl_model_opts *opts, ctl_model **model_out) {
@@ -1103,6 +1172,7 @@ int ctl_encode(ctl_ctx *ctx, const double *slots, double scale, int64_t *coeffs_
 
 int ctl_encode_items(ctl_ctx *ctx, const ctl_model *m, const double *x, int items, int64_t *coeffs_out) {
     if (!ctx || !m || !x || !coeffs_out) return fail(CTL_EINVAL, "null argument");
+    CTL_SAME(ctx, m, "the model");
     if (items < 1 || items > m->items) return fail(CTL_EINVAL, "items must be in 1..model items");
     const int n_in = m->layers[0].n_in, t = m->layers[0].t;
     std::vector<double> z(ctx->hp.n / 2, 0.0);
@@ -1116,6 +1186,7 @@ int ctl_encode_items(ctl_ctx *ctx, const ctl_model *m, const double *x, int item
 
 int ctl_encrypt(ctl_ctx *ctx, const ctl_pk *pk, const int64_t *coeffs, uint64_t seed, uint64_t *ct_out, void *stream) {
     if (!ctx || !pk || !coeffs || !ct_out) return fail(CTL_EINVAL, "null argument");
+    CTL_SAME(ctx, pk, "the public key");
     CTL_HIP(hipSetDevice(ctx->device));
     hipStream_t st = as_stream(stream);
     const int n = ctx->hp.n, nq = ctx->hp.nq;
@@ -1136,6 +1207,7 @@ int ctl_encrypt(ctl_ctx *ctx, const ctl_pk *pk, const int64_t *coeffs, uint64_t 
 
 int ctl_decrypt(ctl_ctx *ctx, const ctl_sk *sk, const uint64_t *ct, int k, uint64_t *residues_out, void *stream) {
     if (!ctx || !sk || !ct || !residues_out) return fail(CTL_EINVAL, "null argument");
+    CTL_SAME(ctx, sk, "the secret key");
     if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
     CTL_HIP(hipSetDevice(ctx->device));
     hipStream_t st = as_stream(stream);
@@ -1167,6 +1239,7 @@ int ctl_decode(ctl_ctx *ctx, const uint64_t *residues, int k, double scale, doub
 
 int ctl_decode_items(ctl_ctx *ctx, const ctl_model *m, const uint64_t *residues, double *y_out) {
     if (!ctx || !m || !residues || !y_out) return fail(CTL_EINVAL, "null argument");
+    CTL_SAME(ctx, m, "the model");
     std::vector<double> z(ctx->hp.n / 2);
     CTL_TRY(ctl_decode(ctx, residues, m->k_out, m->scale_out, z.data()));
     const int n_out = m->layers.back().n_out;
@@ -1180,6 +1253,8 @@ int ctl_dense(ctl_ctx *ctx, const ctl_model *model, int layer, const ctl_evk *ev
               uint64_t *out, int n_ct, void *stream) {
     if (!ctx || !model || !evk || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
     if (layer < 0 || layer >= (int)model->layers.size()) return fail(CTL_EINVAL, "layer out of range");
+    CTL_SAME(ctx, model, "the model");
+    CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
     return dense_batch(ctx, as_stream(stream), model, layer, evk, n_ct, reinterpret_cast<const u64 *>(in),
                        reinterpret_cast<u64 *>(out));
@@ -1188,6 +1263,7 @@ int ctl_dense(ctl_ctx *ctx, const ctl_model *model, int layer, const ctl_evk *ev
 int ctl_square(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint64_t *out, int n_ct, void *stream) {
     if (!ctx || !evk || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
     if (k < 2 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
     return square_batch(ctx, as_stream(stream), evk, k, n_ct, reinterpret_cast<const u64 *>(in),
                         reinterpret_cast<u64 *>(out));
@@ -1197,6 +1273,7 @@ int ctl_replicate(ctl_ctx *ctx, const ctl_evk *evk, int k, int width, const uint
                   int n_ct, void *stream) {
     if (!ctx || !evk || !in || !out || n_ct < 1 || width < 1) return fail(CTL_EINVAL, "bad argument");
     if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
     return replicate_batch(ctx, as_stream(stream), evk, k, n_ct, width, reinterpret_cast<const u64 *>(in),
                            reinterpret_cast<u64 *>(out));
@@ -1206,6 +1283,7 @@ int ctl_rotate(ctl_ctx *ctx, const ctl_evk *evk, int k, int rotation, const uint
                int n_ct, void *stream) {
     if (!ctx || !evk || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
     if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
     return rotate_batch(ctx, as_stream(stream), evk, k, n_ct, rotation, reinterpret_cast<const u64 *>(in),
                         reinterpret_cast<u64 *>(out));
@@ -1222,6 +1300,8 @@ int ctl_rescale(ctl_ctx *ctx, int k, const uint64_t *in, uint64_t *out, int n_ct
 int ctl_forward(ctl_ctx *ctx, const ctl_model *m, const ctl_evk *evk, const uint64_t *in, uint64_t *out,
                 int n_ct, void *stream) {
     if (!ctx || !m || !evk || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
+    CTL_SAME(ctx, m, "the model");
+    CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
     hipStream_t st = as_stream(stream);
     const long N = ctx->hp.n;
