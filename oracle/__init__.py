@@ -47,6 +47,15 @@ def _lib():
         lib.or_min_psi.restype = ctypes.c_uint64
         lib.or_min_psi.argtypes = [ctypes.c_uint64, ctypes.c_int]
         lib.or_find_primes.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, u64p]
+        lib.or_affine.restype = None
+        lib.or_affine.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, u64p, ctypes.c_int64,
+                                  ctypes.c_int64, u64p]
+        lib.or_poly3_consts.restype = ctypes.c_double
+        lib.or_poly3_consts.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_double), i64p]
+        lib.or_poly3.restype = ctypes.c_double
+        lib.or_poly3.argtypes = [ctypes.c_void_p, ctypes.c_int, u64p, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_double), u64p, u64p]
         _LIB = lib
     return _LIB
 
@@ -321,6 +330,61 @@ class CKKSOracle:
         if rc:
             raise RuntimeError("or_replicate failed: %d" % rc)
         return out
+
+    # ------------------------------------------------------------ layers of the paper's CNN
+    def mul(self, a: np.ndarray, b: np.ndarray, rlk: np.ndarray) -> np.ndarray:
+        """Ciphertext product with relinearization and rescale: [2][k][N] -> [2][k-1][N]."""
+        k = a.shape[1]
+        out = np.zeros((2, k - 1, self.n), dtype=np.uint64)
+        self.lib.or_mul(self.c, k, _p(np.ascontiguousarray(a)), _p(np.ascontiguousarray(b)),
+                        _p(np.ascontiguousarray(rlk)), _p(out))
+        return out
+
+    def affine(self, ct: np.ndarray, mul: int, add: int, k_out: int = 0) -> np.ndarray:
+        """ct * mul + add (signed integer constants; add goes to c0), keeping the first k_out primes."""
+        k = ct.shape[1]
+        k_out = k_out or k
+        out = np.zeros((2, k_out, self.n), dtype=np.uint64)
+        self.lib.or_affine(self.c, k, k_out, _p(np.ascontiguousarray(ct)), mul, add, _p(out))
+        return out
+
+    def conv1d(self, ct: np.ndarray, pts: np.ndarray, keys: Dict[int, np.ndarray]) -> np.ndarray:
+        """sum_i pts_i * rot_{i - (f-1)/2}(ct), rescaled. pts: [f][k][N] NTT form."""
+        k = ct.shape[1]
+        out = np.zeros((2, k - 1, self.n), dtype=np.uint64)
+        gs, arr = self._keyset(keys)
+        rc = self.lib.or_conv1d(self.c, k, _p(np.ascontiguousarray(ct)), _p(np.ascontiguousarray(pts)),
+                                pts.shape[0], len(gs), _p(gs), arr, _p(out))
+        if rc:
+            raise RuntimeError("or_conv1d failed: %d" % rc)
+        return out
+
+    def avgpool(self, ct: np.ndarray, pt: np.ndarray, f: int, keys: Dict[int, np.ndarray]) -> np.ndarray:
+        """pt * sum_{i < f} rot_{-i}(ct), rescaled. pt: [k][N] NTT form."""
+        k = ct.shape[1]
+        out = np.zeros((2, k - 1, self.n), dtype=np.uint64)
+        gs, arr = self._keyset(keys)
+        rc = self.lib.or_avgpool(self.c, k, _p(np.ascontiguousarray(ct)), _p(np.ascontiguousarray(pt)), f,
+                                 len(gs), _p(gs), arr, _p(out))
+        if rc:
+            raise RuntimeError("or_avgpool failed: %d" % rc)
+        return out
+
+    def poly3_consts(self, k: int, scale: float, coef: Sequence[float]):
+        """Integer constants (C0..C3) and output scale of the degree-3 activation at k primes."""
+        cf = (ctypes.c_double * 4)(*coef)
+        C = np.zeros(4, dtype=np.int64)
+        s3 = self.lib.or_poly3_consts(self.c, k, scale, cf, _p(C))
+        return [int(x) for x in C], float(s3)
+
+    def poly3(self, ct: np.ndarray, scale: float, coef: Sequence[float], rlk: np.ndarray):
+        """c0 + c1 z + c2 z^2 + c3 z^3 with depth 2: returns ([2][k-2][N], output scale)."""
+        k = ct.shape[1]
+        out = np.zeros((2, k - 2, self.n), dtype=np.uint64)
+        cf = (ctypes.c_double * 4)(*coef)
+        s3 = self.lib.or_poly3(self.c, k, _p(np.ascontiguousarray(ct)), scale, cf,
+                               _p(np.ascontiguousarray(rlk)), _p(out))
+        return out, float(s3)
 
     # ------------------------------------------------------------ encoding (canonical embedding)
     def slot_exponents(self) -> np.ndarray:

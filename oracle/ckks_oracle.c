@@ -865,3 +865,182 @@ void or_mul_ntt(const or_ctx *c, int pi, const u64 *a, const u64 *b, u64 *out) {
 void or_lift(const or_ctx *c, int from, int to, const u64 *in, u64 *out) {
     for (int x = 0; x < c->n; x++) out[x] = lift_centered(in[x], c->q[from], c->q[to]);
 }
+
+/* ---------------------------------------------------------------- layers of the paper's CNN */
+
+/* Product of two ciphertexts at k primes (tensor, relinearization of the s^2 part, rescale):
+ * [2][k][N] x [2][k][N] -> [2][k-1][N]. */
+int or_mul(const or_ctx *c, int k, const u64 *a, const u64 *b, const u64 *rlk, u64 *out) {
+    int n = c->n;
+    size_t kn = (size_t)k * n;
+    u64 *d = (u64 *)calloc(3 * kn, sizeof(u64)), *ks = (u64 *)calloc(2 * kn, sizeof(u64));
+    for (int i = 0; i < k; i++) {
+        u64 q = c->q[i];
+        for (int x = 0; x < n; x++) {
+            size_t o = (size_t)i * n + x;
+            d[o] = mulm(a[o], b[o], q);
+            d[kn + o] = addm(mulm(a[o], b[kn + o], q), mulm(a[kn + o], b[o], q), q);
+            d[2 * kn + o] = mulm(a[kn + o], b[kn + o], q);
+        }
+    }
+    or_keyswitch(c, k, d + 2 * kn, rlk, ks);
+    for (int i = 0; i < k; i++) {
+        u64 q = c->q[i];
+        for (int x = 0; x < n; x++) {
+            size_t o = (size_t)i * n + x;
+            d[o] = addm(d[o], ks[o], q);
+            d[kn + o] = addm(d[kn + o], ks[kn + o], q);
+        }
+    }
+    or_rescale(c, k, d, out);
+    free(d); free(ks);
+    return 0;
+}
+
+/* A signed integer as a residue mod q. */
+static u64 signed_mod(int64_t v, u64 q) {
+    u64 m = (u64)(v < 0 ? -(v + 1) : v) % q;     /* |v| - 1 for negatives avoids INT64_MIN overflow */
+    if (v < 0) m = negm(addm(m, 1 % q, q), q);
+    return m;
+}
+
+/* ct * mul + add, where mul and add are signed integer constants: every residue is multiplied by
+ * mul, and add (the constant polynomial, whose NTT form is add in every slot) is added to c0.
+ * in: [2][k_in][N]; out: [2][k_out][N] with k_out <= k_in (the residues of primes >= k_out are
+ * discarded, which keeps the value and lowers the level). */
+void or_affine(const or_ctx *c, int k_in, int k_out, const u64 *in, int64_t mul, int64_t add, u64 *out) {
+    int n = c->n;
+    for (int p = 0; p < 2; p++)
+        for (int i = 0; i < k_out; i++) {
+            u64 q = c->q[i], m = signed_mod(mul, q), a = p == 0 ? signed_mod(add, q) : 0;
+            const u64 *src = in + ((size_t)p * k_in + i) * n;
+            u64 *dst = out + ((size_t)p * k_out + i) * n;
+            for (int x = 0; x < n; x++) dst[x] = addm(mulm(src[x], m, q), a, q);
+        }
+}
+
+/* 1D convolution, packed single-channel (Section 3.1, "1D Convolutions"): with f taps and centre
+ * h = (f - 1) / 2, out = rescale(sum_{i < f} pts_i * rot_{i - h}(ct)). One plaintext product per
+ * tap and one rotation per tap but the centre one; the zero padding is carried by the plaintexts.
+ * pts: [f][k][N] NTT form. */
+int or_conv1d(const or_ctx *c, int k, const u64 *ct, const u64 *pts, int f, int n_keys, const u64 *gs,
+              const u64 *const *keys, u64 *out) {
+    keyset_t ks = {n_keys, gs, keys};
+    int n = c->n, h = (f - 1) / 2;
+    size_t kn = (size_t)k * n, cts = 2 * kn;
+    u64 *acc = (u64 *)calloc(cts, sizeof(u64)), *r = (u64 *)malloc(sizeof(u64) * cts);
+    int rc = 0;
+    for (int i = 0; i < f; i++) {
+        if (i == h) {
+            memcpy(r, ct, sizeof(u64) * cts);
+        } else {
+            u64 g = or_galois_elt(c, (long)i - h);
+            const u64 *key = find_key(&ks, g);
+            if (!key) { rc = -5; goto done; }
+            or_rotate(c, k, ct, key, g, r);
+        }
+        const u64 *pt = pts + (size_t)i * kn;
+        for (int p = 0; p < 2; p++)
+            for (int j = 0; j < k; j++) {
+                u64 q = c->q[j];
+                for (int x = 0; x < n; x++) {
+                    size_t o = (size_t)j * n + x;
+                    acc[p * kn + o] = addm(acc[p * kn + o], mulm(pt[o], r[p * kn + o], q), q);
+                }
+            }
+    }
+    or_rescale(c, k, acc, out);
+done:
+    free(acc); free(r);
+    return rc;
+}
+
+/* Average pool, stride 1, size f (Section 3.1, "Average Pool"): s = sum_{i < f} rot_{-i}(ct)
+ * (f - 1 rotations), then one plaintext product with pt (1/f on the valid outputs, 0 elsewhere)
+ * and a rescale. pt: [k][N] NTT form. */
+int or_avgpool(const or_ctx *c, int k, const u64 *ct, const u64 *pt, int f, int n_keys, const u64 *gs,
+               const u64 *const *keys, u64 *out) {
+    keyset_t ks = {n_keys, gs, keys};
+    int n = c->n;
+    size_t kn = (size_t)k * n, cts = 2 * kn;
+    u64 *s = (u64 *)malloc(sizeof(u64) * cts), *r = (u64 *)malloc(sizeof(u64) * cts);
+    int rc = 0;
+    memcpy(s, ct, sizeof(u64) * cts);
+    for (int i = 1; i < f; i++) {
+        u64 g = or_galois_elt(c, -(long)i);
+        const u64 *key = find_key(&ks, g);
+        if (!key) { rc = -5; goto done; }
+        or_rotate(c, k, ct, key, g, r);
+        for (int p = 0; p < 2; p++)
+            for (int j = 0; j < k; j++) {
+                u64 q = c->q[j];
+                for (int x = 0; x < n; x++) {
+                    size_t o = p * kn + (size_t)j * n + x;
+                    s[o] = addm(s[o], r[o], q);
+                }
+            }
+    }
+    for (int p = 0; p < 2; p++)
+        for (int j = 0; j < k; j++) {
+            u64 q = c->q[j];
+            for (int x = 0; x < n; x++) {
+                size_t o = (size_t)j * n + x;
+                s[p * kn + o] = mulm(s[p * kn + o], pt[o], q);
+            }
+        }
+    or_rescale(c, k, s, out);
+done:
+    free(s); free(r);
+    return rc;
+}
+
+/* Integer constants of the degree-3 activation c0 + c1 z + c2 z^2 + c3 z^3 on z at k primes and
+ * scale S (q_a = q_{k-1}, q_b = q_{k-2} are the primes its two rescales drop):
+ *   S2 = S S / q_a                      scale of z^2 and of (c3 z + c2)
+ *   S3 = S2 S2 / q_b                    output scale
+ *   C3 = llround(c3 S), C2 = llround(c2 S2), C1 = llround(c1 (S3 q_a / S)), C0 = llround(c0 S3).
+ * Returns S3. */
+double or_poly3_consts(const or_ctx *c, int k, double S, const double *coef, int64_t *C) {
+    double qa = (double)c->q[k - 1], qb = (double)c->q[k - 2];
+    double S2 = (S * S) / qa;
+    double S3 = (S2 * S2) / qb;
+    C[3] = llround(coef[3] * S);
+    C[2] = llround(coef[2] * S2);
+    C[1] = llround(coef[1] * ((S3 * qa) / S));
+    C[0] = llround(coef[0] * S3);
+    return S3;
+}
+
+/* Degree-3 polynomial activation with depth 2 (the ReLU approximation of Section 3.1):
+ *   z2 = rescale(relin(z z))                        k-1 primes, scale S2
+ *   u  = rescale(z C3) + C2                         k-1 primes, scale S2  (c3 z + c2)
+ *   w  = rescale(relin(z2 u))                       k-2 primes, scale S3  (c3 z^3 + c2 z^2)
+ *   v  = drop(rescale(z C1)) + C0                   k-2 primes, scale S3  (c1 z + c0)
+ *   out = w + v.
+ * ct: [2][k][N] (k >= 3); out: [2][k-2][N]. Returns the output scale. */
+double or_poly3(const or_ctx *c, int k, const u64 *ct, double S, const double *coef, const u64 *rlk, u64 *out) {
+    int n = c->n;
+    size_t kn = (size_t)k * n, k1 = (size_t)(k - 1) * n, k2 = (size_t)(k - 2) * n;
+    int64_t C[4];
+    double S3 = or_poly3_consts(c, k, S, coef, C);
+    u64 *z2 = (u64 *)malloc(sizeof(u64) * 2 * k1), *t = (u64 *)malloc(sizeof(u64) * 2 * kn);
+    u64 *u = (u64 *)malloc(sizeof(u64) * 2 * k1), *w = (u64 *)malloc(sizeof(u64) * 2 * k2);
+    or_square(c, k, ct, rlk, z2);
+    or_affine(c, k, k, ct, C[3], 0, t);
+    or_rescale(c, k, t, u);
+    or_affine(c, k - 1, k - 1, u, 1, C[2], u);
+    or_mul(c, k - 1, z2, u, rlk, w);
+    or_affine(c, k, k, ct, C[1], 0, t);
+    or_rescale(c, k, t, u);
+    or_affine(c, k - 1, k - 2, u, 1, C[0], out);
+    for (int p = 0; p < 2; p++)
+        for (int i = 0; i < k - 2; i++) {
+            u64 q = c->q[i];
+            for (int x = 0; x < n; x++) {
+                size_t o = p * k2 + (size_t)i * n + x;
+                out[o] = addm(out[o], w[o], q);
+            }
+        }
+    free(z2); free(t); free(u); free(w);
+    return S3;
+}

@@ -166,3 +166,61 @@ def mix_inputs(queries: List[Query], items: int, seed: int = MIX_SEED) -> List[n
     g = _rng(seed + 2, 0)
     return [np.ascontiguousarray(np.clip(g.normal(0.0, 1.0, size=(items, q.widths[0])), -3.0, 3.0))
             for q in queries]
+
+
+# ---------------------------------------------------------------------------------------------
+# The paper's frozen server layers (Section 4.1 server CNN; its first four layers are frozen):
+# Conv1D (f = 9, 'same' padding, one channel, 768 -> 768), Dense 768 with the degree-3 ReLU
+# approximation, AveragePooling (size 3, stride 1, 768 -> 766), Dense 766. Parameter sets of
+# Table 2 with q_0 and P of log2(Delta) + 9 or + 10 bits: CryptoTL_p1 (N = 2^13, log2 q = 218,
+# Delta = 2^25, p = 2 items) and CryptoTL_p2 (N = 2^14, log2 q = 420, Delta = 2^50, p = 5).
+# Trained weights are not available: taps N(0, 1/9), dense weights N(0, 0.03^2) and N(0, 0.05^2),
+# inputs N(0,1) clipped to [-3, 3] (the encoder features' stand-in).
+@dataclasses.dataclass(frozen=True)
+class CnnWorkload:
+    name: str
+    log2n: int
+    q_bits: Tuple[int, ...]
+    p_bits: int
+    log2_scale: int
+    seed_base: int
+    batch: int
+    sigma: float = 3.2
+    width: int = 768
+    f_conv: int = 9
+    f_pool: int = 3
+    t1: int = 32                     # BSGS split of both dense layers (t = 768 = 32 x 24)
+
+    @property
+    def n(self) -> int:
+        return 1 << self.log2n
+
+    @property
+    def pooled(self) -> int:
+        return self.width - self.f_pool + 1
+
+    @property
+    def seed_keys(self) -> int:
+        return self.seed_base + 3
+
+
+CNN_P1 = CnnWorkload("cnn_p1", 13, (34,) + (25,) * 6, 34, 25, 5000, 64)
+CNN_P2 = CnnWorkload("cnn_p2", 14, (60,) + (50,) * 6, 60, 50, 6000, 64)
+CNN_WORKLOADS = {w.name: w for w in (CNN_P1, CNN_P2)}
+
+# The degree-3 ReLU approximation as printed in Section 3.1, coefficients of z^0 .. z^3.
+RELU3_COEF = (0.49383, 0.59259, 0.092593, -0.0061728)
+
+
+def cnn_weights(w: CnnWorkload):
+    """(taps [f_conv], W1 [width][width], W2 [pooled][pooled]) as float64."""
+    g = _rng(w.seed_base + 1, 0)
+    taps = g.normal(0.0, 1.0 / 3.0, size=w.f_conv)
+    w1 = g.normal(0.0, 0.03, size=(w.width, w.width))
+    w2 = g.normal(0.0, 0.05, size=(w.pooled, w.pooled))
+    return (np.ascontiguousarray(taps), np.ascontiguousarray(w1), np.ascontiguousarray(w2))
+
+
+def cnn_inputs(w: CnnWorkload, n_ct: int, items: int, stream: int = 0) -> np.ndarray:
+    g = _rng(w.seed_base + 2, stream)
+    return np.ascontiguousarray(np.clip(g.normal(0.0, 1.0, size=(n_ct, items, w.width)), -3.0, 3.0))
