@@ -173,22 +173,43 @@ int ctl_evk_bytes(const ctl_evk *evk, uint64_t *bytes_out);
 #define CTL_ACT_NONE 0
 #define CTL_ACT_SQUARE 1
 
+/* Degree-3 polynomial activation c0 + c1 z + c2 z^2 + c3 z^3 (coef of the layer descriptor), the
+ * form of the paper's ReLU approximation (Section 3.1, "ReLU"); depth 2. */
+#define CTL_ACT_POLY3 2
+
+/* Layer kinds (Section 3.1):
+ *   CTL_LAYER_DENSE    y = W x by Eq. (1); weights [n_out][n_in]; t1 = BSGS baby steps.
+ *   CTL_LAYER_CONV1D   packed single-channel 1D convolution ("1D Convolutions"), filter size f
+ *                      (odd), 'same' zero padding, n_out = n_in; y[s] = sum_i w_i x[s + i - (f-1)/2];
+ *                      weights [f]; f plaintext products, f - 1 rotations.
+ *   CTL_LAYER_AVGPOOL  average pooling, stride 1, size f ("Average Pool"), n_out = n_in - f + 1;
+ *                      sum_{i < f} rot_{-i}(x) times a plaintext holding 1/f on the valid
+ *                      outputs; no weights. Its outputs sit at slots f-1 .. n_in-1 of each block,
+ *                      and the layer that follows (which must be dense) reads them there. */
+#define CTL_LAYER_DENSE 0
+#define CTL_LAYER_CONV1D 1
+#define CTL_LAYER_AVGPOOL 2
+
 /* Giant-step variant of a dense layer: by default every giant-step rotation is a full key switch
  * with its own ModDown; with CTL_LAYER_LAZY_GIANT the key products of all giant steps are summed
  * over Q*P and lowered by a single ModDown (same value up to rounding, one rounding instead of
  * t2 - 1, about 40% fewer residue transforms in the ModDown kernels). */
 #define CTL_LAYER_LAZY_GIANT 1
 
-/* One dense layer y = W x with W of shape [n_out][n_in], evaluated by the baby-step giant-step
- * diagonal method (Eq. (1) of Section 3.1) with padded width t = max(n_in, n_out), t = t1 * t2
- * (t1 must divide t). act = CTL_ACT_SQUARE applies x^2 after the layer (not allowed on the last).
- * flags: 0 or CTL_LAYER_LAZY_GIANT. */
+/* One layer. A dense layer y = W x with W of shape [n_out][n_in] is evaluated by the baby-step
+ * giant-step diagonal method (Eq. (1) of Section 3.1) with padded width t = max(off + n_in, n_out),
+ * t = t1 * t2 (t1 must divide t; off = f - 1 after an average pool, else 0). act applies x^2
+ * (CTL_ACT_SQUARE) or the cubic in coef (CTL_ACT_POLY3) after the layer, never after the last.
+ * flags: 0 or CTL_LAYER_LAZY_GIANT (dense only). Zero-filled fields select a dense layer. */
 typedef struct ctl_layer_desc {
     int n_in;
     int n_out;
-    int t1;
-    int act;
-    int flags;
+    int t1;          /* dense: baby steps (divides the padded width) */
+    int act;         /* CTL_ACT_* applied after the layer (not after the last) */
+    int flags;       /* CTL_LAYER_LAZY_GIANT */
+    int kind;        /* CTL_LAYER_* */
+    int f;           /* conv / pool size */
+    double coef[4];  /* CTL_ACT_POLY3: c0..c3 */
 } ctl_layer_desc;
 
 typedef struct ctl_model ctl_model;
@@ -229,13 +250,17 @@ int ctl_model_load_ex(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers,
                       const double *const *weights, const int64_t *const *pts,
                       const ctl_model_opts *opts, ctl_model **model_out);
 
-/* Load the frozen layers from FP64 weights: W[l] is a host row-major [n_out][n_in] matrix. The
- * diagonal plaintexts diag'_i (Eq. (1)) are encoded at the scale of the prime each layer's rescale
- * drops, reduced and transformed on the device, and kept resident in HBM. */
+/* Load the frozen layers from FP64 weights: for a dense layer W[l] is a host row-major
+ * [n_out][n_in] matrix, for a convolution the f taps, for an average pool it is ignored (may be
+ * NULL). The plaintexts (diag'_i of Eq. (1), the masked taps, the pooling mask) are encoded at the
+ * scale of the prime each layer's rescale drops, reduced and transformed on the device, and kept
+ * resident in HBM. Before a dense layer or a convolution whose input is not already [x | x] the
+ * forward pass replicates it (ct + rot_{-t}(ct)). */
 int ctl_model_load(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers,
                    const double *const *weights, ctl_model **model_out);
-/* Same, from already-encoded integer plaintexts: pts[l] is a host int64 [t_l][N] array of signed
- * coefficients (|c| < 2^62) for plaintext i = 0..t_l-1 of layer l. */
+/* Same, from already-encoded integer plaintexts: pts[l] is a host int64 array of signed
+ * coefficients (|c| < 2^62) — dense: [t][N], plaintext i = diag'_i; convolution: [f][N], plaintext
+ * i multiplies rot_{i-(f-1)/2}; average pool: [1][N], the pooling plaintext. */
 int ctl_model_load_raw(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers,
                        const int64_t *const *pts, ctl_model **model_out);
 int ctl_model_free(ctl_model *model);
@@ -277,11 +302,27 @@ int ctl_decode_items(ctl_ctx *ctx, const ctl_model *model, const uint64_t *resid
 int ctl_forward(ctl_ctx *ctx, const ctl_model *model, const ctl_evk *evk, const uint64_t *in,
                 uint64_t *out, int n_ct, void *stream);
 
-/* One dense layer by Eq. (1): hoisted baby-step rotations rot_j, j < t1, products with the
- * diagonal plaintexts, one key switch per giant step rot_{k t1}, one rescale at the end.
- * in: k = the layer's input primes (ctl_model_info.layer_k); out: k - 1. */
+/* One layer of the model. Dense, by Eq. (1): hoisted baby-step rotations rot_j, j < t1, products
+ * with the diagonal plaintexts, one key switch per giant step rot_{k t1}, one rescale at the end.
+ * Convolution and average pool: their rotations hoisted the same way, the plaintext products
+ * summed, one rescale. The input must already be in the layer's layout (the replicate that
+ * ctl_forward inserts is not part of this call). in: k = ctl_model_info.layer_k; out: k - 1. */
 int ctl_dense(ctl_ctx *ctx, const ctl_model *model, int layer, const ctl_evk *evk,
               const uint64_t *in, uint64_t *out, int n_ct, void *stream);
+
+/* Product of two ciphertexts at k primes: tensor, relinearization, rescale. k -> k - 1. */
+int ctl_mul(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *a, const uint64_t *b, uint64_t *out,
+            int n_ct, void *stream);
+
+/* Degree-3 activation c0 + c1 z + c2 z^2 + c3 z^3 (coef[0..3]; the paper's ReLU approximation of
+ * Section 3.1 has this form) on ciphertexts at k >= 3 primes and scale `scale`, depth 2, k -> k - 2:
+ *   z2 = rescale(relin(z z));  u = rescale(z C3) + C2;  w = rescale(relin(z2 u));
+ *   v = (rescale(z C1) without its last prime) + C0;   out = w + v,
+ * with integer constants rounded (llround) at the scales the terms carry, q_a = q_{k-1},
+ * q_b = q_{k-2}: S2 = S S / q_a, S3 = S2 S2 / q_b, C3 = c3 S, C2 = c2 S2, C1 = c1 (S3 q_a / S),
+ * C0 = c0 S3 (each product evaluated in this order in FP64). *scale_out receives S3. */
+int ctl_poly3(ctl_ctx *ctx, const ctl_evk *evk, int k, double scale, const double *coef, const uint64_t *in,
+              uint64_t *out, int n_ct, void *stream, double *scale_out);
 
 /* x^2 activation (the polynomial activation of Section 3.1, degree 2): tensor, relinearize with
  * the relinearization key, rescale. k -> k - 1. */

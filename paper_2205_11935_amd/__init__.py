@@ -19,7 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libcryptotl.so")
 
 CTL_ACT_NONE = 0
 CTL_ACT_SQUARE = 1
+CTL_ACT_POLY3 = 2
 CTL_LAYER_LAZY_GIANT = 1
+CTL_LAYER_DENSE = 0
+CTL_LAYER_CONV1D = 1
+CTL_LAYER_AVGPOOL = 2
 MAX_PRIMES = 8
 
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ELEVEL", -4: "ESCALE", -5: "EKEY", -6: "EHIP", -7: "EPARAM"}
@@ -43,7 +47,33 @@ class _Params(ctypes.Structure):
 
 class _LayerDesc(ctypes.Structure):
     _fields_ = [("n_in", ctypes.c_int), ("n_out", ctypes.c_int), ("t1", ctypes.c_int), ("act", ctypes.c_int),
-                ("flags", ctypes.c_int)]
+                ("flags", ctypes.c_int), ("kind", ctypes.c_int), ("f", ctypes.c_int),
+                ("coef", ctypes.c_double * 4)]
+
+
+@dataclasses.dataclass
+class Layer:
+    """One layer descriptor (ctl_layer_desc). Plain (n_in, n_out, t1[, act]) tuples stand for dense
+    layers with x^2 between them."""
+    kind: int
+    n_in: int
+    n_out: int
+    t1: int = 0
+    f: int = 0
+    act: int = CTL_ACT_NONE
+    coef: Sequence[float] = (0.0, 0.0, 0.0, 0.0)
+
+    @staticmethod
+    def dense(n_in, n_out, t1, act=CTL_ACT_NONE, coef=(0.0, 0.0, 0.0, 0.0)):
+        return Layer(CTL_LAYER_DENSE, n_in, n_out, t1=t1, act=act, coef=coef)
+
+    @staticmethod
+    def conv1d(width, f, act=CTL_ACT_NONE, coef=(0.0, 0.0, 0.0, 0.0)):
+        return Layer(CTL_LAYER_CONV1D, width, width, f=f, act=act, coef=coef)
+
+    @staticmethod
+    def avgpool(width, f, act=CTL_ACT_NONE, coef=(0.0, 0.0, 0.0, 0.0)):
+        return Layer(CTL_LAYER_AVGPOOL, width, width - f + 1, f=f, act=act, coef=coef)
 
 
 class _ModelOpts(ctypes.Structure):
@@ -118,6 +148,11 @@ _SIGS = {
                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "ctl_square": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_mul": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_poly3": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double, f64p,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_double)]),
     "ctl_replicate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "ctl_rotate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
@@ -416,16 +451,30 @@ class Context:
     def _descs(layers, lazy: bool):
         arr = (_LayerDesc * len(layers))()
         for i, l in enumerate(layers):
-            arr[i].n_in, arr[i].n_out, arr[i].t1 = l[0], l[1], l[2]
-            arr[i].act = l[3] if len(l) > 3 else (CTL_ACT_SQUARE if i + 1 < len(layers) else CTL_ACT_NONE)
-            arr[i].flags = CTL_LAYER_LAZY_GIANT if lazy else 0
+            if isinstance(l, Layer):
+                arr[i].kind, arr[i].n_in, arr[i].n_out, arr[i].t1, arr[i].f = l.kind, l.n_in, l.n_out, l.t1, l.f
+                arr[i].act = l.act
+                for j in range(4):
+                    arr[i].coef[j] = float(l.coef[j])
+                lazy_ok = l.kind == CTL_LAYER_DENSE
+            else:
+                arr[i].n_in, arr[i].n_out, arr[i].t1 = l[0], l[1], l[2]
+                arr[i].act = l[3] if len(l) > 3 else (CTL_ACT_SQUARE if i + 1 < len(layers) else CTL_ACT_NONE)
+                lazy_ok = True
+            arr[i].flags = CTL_LAYER_LAZY_GIANT if (lazy and lazy_ok) else 0
         return arr
 
+    @staticmethod
+    def _f64_ptrs(weights):
+        """(arrays kept alive, double* array); None entries (average pools) become NULL."""
+        ws = [None if w is None else np.ascontiguousarray(w, dtype=np.float64) for w in weights]
+        return ws, (f64p * len(ws))(*[None if w is None else w.ctypes.data_as(f64p) for w in ws])
+
     def load_model(self, layers, weights: Sequence[np.ndarray], lazy: bool = False) -> Model:
-        """layers: (n_in, n_out, t1[, act]) per layer; weights: float64 [n_out][n_in] per layer;
-        lazy: single-ModDown giant steps (CTL_LAYER_LAZY_GIANT) on every layer."""
-        ws = [np.ascontiguousarray(w, dtype=np.float64) for w in weights]
-        ptrs = (f64p * len(ws))(*[w.ctypes.data_as(f64p) for w in ws])
+        """layers: Layer descriptors or (n_in, n_out, t1[, act]) dense tuples; weights per layer:
+        float64 [n_out][n_in] (dense), [f] taps (convolution), None (average pool);
+        lazy: single-ModDown giant steps (CTL_LAYER_LAZY_GIANT) on every dense layer."""
+        ws, ptrs = self._f64_ptrs(weights)
         h = ctypes.c_void_p()
         _check(lib().ctl_model_load(self.handle, self._descs(layers, lazy), len(layers), ptrs, ctypes.byref(h)))
         return Model(self, h)
@@ -447,8 +496,7 @@ class Context:
         h = ctypes.c_void_p()
         wp = pp = None
         if weights is not None:
-            ws = [np.ascontiguousarray(w, dtype=np.float64) for w in weights]
-            wp = (f64p * len(ws))(*[w.ctypes.data_as(f64p) for w in ws])
+            ws, wp = self._f64_ptrs(weights)
         if pts is not None:
             ps = [np.ascontiguousarray(p, dtype=np.int64) for p in pts]
             pp = (i64p * len(ps))(*[p.ctypes.data_as(i64p) for p in ps])
@@ -473,6 +521,24 @@ class Context:
         _check(lib().ctl_dense(self.handle, model.handle, layer, keys.evk, _ptr(ct), _ptr(out), n_ct,
                                _stream(stream)))
         return out
+
+    def mul(self, keys: Keys, a, b, out=None, stream=None):
+        n_ct, k = a.shape[0], a.shape[2]
+        if out is None:
+            out = self.empty_ct(n_ct, k - 1)
+        _check(lib().ctl_mul(self.handle, keys.evk, k, _ptr(a), _ptr(b), _ptr(out), n_ct, _stream(stream)))
+        return out
+
+    def poly3(self, keys: Keys, ct, scale: float, coef: Sequence[float], out=None, stream=None):
+        """Degree-3 activation; returns (output [n][2][k-2][N], output scale)."""
+        n_ct, k = ct.shape[0], ct.shape[2]
+        if out is None:
+            out = self.empty_ct(n_ct, k - 2)
+        cf = (ctypes.c_double * 4)(*[float(c) for c in coef])
+        so = ctypes.c_double()
+        _check(lib().ctl_poly3(self.handle, keys.evk, k, scale, cf, _ptr(ct), _ptr(out), n_ct, _stream(stream),
+                               ctypes.byref(so)))
+        return out, so.value
 
     def square(self, keys: Keys, ct, out=None, stream=None):
         n_ct, k = ct.shape[0], ct.shape[2]

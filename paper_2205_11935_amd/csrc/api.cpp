@@ -45,7 +45,7 @@ const char *const kFamilyNames[F_COUNT] = {"k_ntt_fwd", "k_ntt_inv", "k_modup", 
 // Workspace slots: each grows on demand and is reused by later calls on the same context.
 enum Slot {
     S_COEF, S_DIG, S_U, S_PLAST, S_ROT, S_INNER, S_SUM, S_LAST, S_TENSOR, S_SQ, S_REP,
-    S_FWD_A, S_FWD_B, S_FWD_C, S_COEF2, S_ROT2, S_MISC, S_COUNT
+    S_FWD_A, S_FWD_B, S_FWD_C, S_COEF2, S_ROT2, S_MISC, S_P_Z2, S_P_T, S_P_U, S_P_W, S_P_V, S_COUNT
 };
 
 }  // namespace
@@ -92,6 +92,14 @@ struct LayerPlan {
     int n_in, n_out, t, t1, t2, k, act;
     bool lazy;
     double pt_scale;
+    int kind = CTL_LAYER_DENSE;
+    int f = 0;                    // convolution / pooling size
+    int in_off = 0;               // slot offset of a dense layer's input (f - 1 after a pool)
+    int rep_before = 0;           // replicate with this width before the layer (0: none)
+    int nb = 0;                   // plaintexts in the bank (t1 * t2)
+    std::vector<long> rots1;      // baby rotations; bank entry j >= 1 multiplies rot_{rots1[j-1]}
+    double act_scale_in = 0;      // scale at the activation's input
+    double act_coef[4] = {0, 0, 0, 0};
 };
 
 struct ctl_model {
@@ -356,15 +364,16 @@ int replicate_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B
     return check_launch();
 }
 
-int square_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, const u64 *in, u64 *out) {
+// a x b: tensor, relinearization, rescale ([B][2][k][N] each -> [B][2][k-1][N]); a == b squares.
+int mul_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, const u64 *a, const u64 *b, u64 *out) {
     const long N = c->hp.n;
     const u64 *rlk = find_key(evk, 0);
     if (!rlk) return fail(CTL_EKEY, "missing relinearization key");
-    if (k < 2) return fail(CTL_ELEVEL, "x^2 needs at least two primes");
+    if (k < 2) return fail(CTL_ELEVEL, "a ciphertext product needs at least two primes");
     u64 *t3, *sq;
     CTL_TRY(slot(c, S_TENSOR, (size_t)B * 3 * k * N, st, &t3));
     CTL_TRY(slot(c, S_SQ, (size_t)B * 2 * k * N, st, &sq));
-    { CTL_PROF(F_TENSOR, 3.0 * B * k * N, 0.0); launch_tensor(c->hp.logn, in, t3, B, k, c->tab, st); }
+    { CTL_PROF(F_TENSOR, 4.0 * B * k * N, 0.0); launch_tensor(c->hp.logn, a, b, t3, B, k, c->tab, st); }
     ResMap dm{};
     dm.per = k;
     dm.ngrp = 1;
@@ -384,6 +393,78 @@ int square_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, c
     return rescale_batch(c, st, k, B, sq, out);
 }
 
+int square_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, const u64 *in, u64 *out) {
+    return mul_batch(c, st, evk, k, B, in, in, out);
+}
+
+u64 signed_mod(int64_t v, u64 q) {
+    const u64 m = (u64)(v < 0 ? -(v + 1) : v) % q;      // |v| - 1 for negatives (no overflow at INT64_MIN)
+    if (v >= 0) return m;
+    const u64 a = (m + 1) % q;
+    return a ? q - a : 0;
+}
+
+// out = in * mul + add (add to c0), keeping the first k_out of k_in residues per polynomial.
+int affine_batch(ctl_ctx *c, hipStream_t st, int B, int k_in, int k_out, const u64 *in, int64_t mul, int64_t add,
+                 u64 *out) {
+    AffineConst ac{};
+    for (int i = 0; i < k_out; ++i) {
+        const u64 q = c->hp.mods[i];
+        ac.mul[i] = signed_mod(mul, q);
+        ac.muls[i] = (u64)(((u128)ac.mul[i] << 64) / q);
+        ac.add[i] = signed_mod(add, q);
+    }
+    { CTL_PROF(F_ADD, 2.0 * B * k_out * c->hp.n, 0.0); launch_affine(c->hp.logn, in, out, B, k_in, k_out, ac, c->tab, st); }
+    return check_launch();
+}
+
+// Integer constants of the degree-3 activation at k primes and input scale S (see ctl_poly3).
+double poly3_consts(const ctl_ctx *c, int k, double S, const double *coef, int64_t *C) {
+    const double qa = (double)c->hp.mods[k - 1], qb = (double)c->hp.mods[k - 2];
+    const double S2 = (S * S) / qa;
+    const double S3 = (S2 * S2) / qb;
+    C[3] = std::llround(coef[3] * S);
+    C[2] = std::llround(coef[2] * S2);
+    C[1] = std::llround(coef[1] * ((S3 * qa) / S));
+    C[0] = std::llround(coef[0] * S3);
+    return S3;
+}
+
+bool poly3_consts_ok(const ctl_ctx *c, int k, double S, const double *coef) {
+    const double qa = (double)c->hp.mods[k - 1], qb = (double)c->hp.mods[k - 2];
+    const double S2 = (S * S) / qa, S3 = (S2 * S2) / qb;
+    const double v[4] = {coef[0] * S3, coef[1] * ((S3 * qa) / S), coef[2] * S2, coef[3] * S};
+    for (double x : v)
+        if (!std::isfinite(x) || std::fabs(x) >= 4611686018427387904.0) return false;
+    return true;
+}
+
+// c0 + c1 z + c2 z^2 + c3 z^3 on [B][2][k][N] -> [B][2][k-2][N] (schedule in ctl.h).
+int poly3_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, double S, const double *coef,
+                const u64 *in, u64 *out) {
+    if (k < 3) return fail(CTL_ELEVEL, "the cubic activation needs at least three primes");
+    if (!poly3_consts_ok(c, k, S, coef)) return fail(CTL_ESCALE, "activation constant out of range");
+    const long N = c->hp.n;
+    int64_t C[4];
+    poly3_consts(c, k, S, coef, C);
+    u64 *z2, *t, *u, *w, *v;
+    CTL_TRY(slot(c, S_P_Z2, (size_t)B * 2 * (k - 1) * N, st, &z2));
+    CTL_TRY(slot(c, S_P_T, (size_t)B * 2 * k * N, st, &t));
+    CTL_TRY(slot(c, S_P_U, (size_t)B * 2 * (k - 1) * N, st, &u));
+    CTL_TRY(slot(c, S_P_W, (size_t)B * 2 * (k - 2) * N, st, &w));
+    CTL_TRY(slot(c, S_P_V, (size_t)B * 2 * (k - 2) * N, st, &v));
+    CTL_TRY(square_batch(c, st, evk, k, B, in, z2));
+    CTL_TRY(affine_batch(c, st, B, k, k, in, C[3], 0, t));
+    CTL_TRY(rescale_batch(c, st, k, B, t, u));
+    CTL_TRY(affine_batch(c, st, B, k - 1, k - 1, u, 1, C[2], u));
+    CTL_TRY(mul_batch(c, st, evk, k - 1, B, z2, u, w));
+    CTL_TRY(affine_batch(c, st, B, k, k, in, C[1], 0, t));
+    CTL_TRY(rescale_batch(c, st, k, B, t, u));
+    CTL_TRY(affine_batch(c, st, B, k - 1, k - 2, u, 1, C[0], v));
+    { CTL_PROF(F_ADD, 2.0 * B * (k - 2) * N, 0.0); launch_add_terms(c->hp.logn, w, 2L * (k - 2) * N, v, 2L * (k - 2) * N, 0, 1, out, B, k - 2, c->tab, st); }
+    return check_launch();
+}
+
 int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ctl_evk *evk, int B,
                 const u64 *in, u64 *out) {
     const LayerPlan &L = m->layers[li];
@@ -395,9 +476,10 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
     std::vector<const u64 *> keys1(R1), keys2(R2);
     std::vector<u64> gal1(R1), gal2(R2);
     for (int j = 1; j < t1; ++j) {
-        gal1[j - 1] = galois_elt(logn, j);
+        gal1[j - 1] = galois_elt(logn, L.rots1[j - 1]);
         keys1[j - 1] = find_key(evk, gal1[j - 1]);
-        if (!keys1[j - 1]) return fail(CTL_EKEY, "missing Galois key for rotation " + std::to_string(j));
+        if (!keys1[j - 1])
+            return fail(CTL_EKEY, "missing Galois key for rotation " + std::to_string(L.rots1[j - 1]));
     }
     for (int k2 = 1; k2 < t2; ++k2) {
         gal2[k2 - 1] = galois_elt(logn, (long)k2 * t1);
@@ -485,14 +567,53 @@ int plan_model(const ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, con
     int tmax = 0;
     for (int l = 0; l < n_layers; ++l) {
         const ctl_layer_desc &d = layers[l];
+        LayerPlan L;
+        L.kind = d.kind;
+        L.n_in = d.n_in;
+        L.n_out = d.n_out;
+        L.act = d.act;
+        L.f = d.f;
         if (d.n_in < 1 || d.n_out < 1) return fail(CTL_EINVAL, "layer widths must be positive");
         if (l > 0 && d.n_in != layers[l - 1].n_out) return fail(CTL_EINVAL, "layer widths do not chain");
-        const int t = std::max(d.n_in, d.n_out);
-        if (d.t1 < 1 || t % d.t1) return fail(CTL_EINVAL, "t1 must divide max(n_in, n_out)");
-        if (d.act != CTL_ACT_NONE && d.act != CTL_ACT_SQUARE) return fail(CTL_EINVAL, "unknown activation");
-        if (d.act == CTL_ACT_SQUARE && l == n_layers - 1)
+        if (l > 0 && layers[l - 1].kind == CTL_LAYER_AVGPOOL && d.kind != CTL_LAYER_DENSE)
+            return fail(CTL_EINVAL, "an average pool must be followed by a dense layer");
+        if (d.flags & ~CTL_LAYER_LAZY_GIANT) return fail(CTL_EINVAL, "unknown layer flag");
+        if (d.kind == CTL_LAYER_DENSE) {
+            L.in_off = (l > 0 && layers[l - 1].kind == CTL_LAYER_AVGPOOL) ? layers[l - 1].f - 1 : 0;
+            L.t = std::max(L.in_off + d.n_in, d.n_out);
+            if (d.t1 < 1 || L.t % d.t1) return fail(CTL_EINVAL, "t1 must divide the padded width");
+            L.t1 = d.t1;
+            L.t2 = L.t / d.t1;
+            L.lazy = (d.flags & CTL_LAYER_LAZY_GIANT) != 0;
+            for (int j = 1; j < L.t1; ++j) L.rots1.push_back(j);
+        } else if (d.kind == CTL_LAYER_CONV1D) {
+            if (d.f < 1 || d.f % 2 == 0 || d.f > 2 * d.n_in - 1)
+                return fail(CTL_EINVAL, "convolution size must be odd and below twice the width");
+            if (d.n_out != d.n_in) return fail(CTL_EINVAL, "a 'same' convolution keeps the width");
+            L.t = d.n_in;
+            L.t1 = d.f;
+            L.t2 = 1;
+            const int h = (d.f - 1) / 2;
+            for (int r = -h; r <= h; ++r)
+                if (r) L.rots1.push_back(r);
+        } else if (d.kind == CTL_LAYER_AVGPOOL) {
+            if (d.f < 1 || d.f > d.n_in) return fail(CTL_EINVAL, "pool size must lie in 1..n_in");
+            if (d.n_out != d.n_in - d.f + 1) return fail(CTL_EINVAL, "a stride-1 pool gives n_in - f + 1 outputs");
+            L.t = d.n_in;
+            L.t1 = d.f;
+            L.t2 = 1;
+            for (int i = 1; i < d.f; ++i) L.rots1.push_back(-i);
+        } else {
+            return fail(CTL_EINVAL, "unknown layer kind");
+        }
+        L.nb = L.t1 * L.t2;
+        if (d.act != CTL_ACT_NONE && d.act != CTL_ACT_SQUARE && d.act != CTL_ACT_POLY3)
+            return fail(CTL_EINVAL, "unknown activation");
+        if (d.act != CTL_ACT_NONE && l == n_layers - 1)
             return fail(CTL_EINVAL, "the activation is applied between layers only");
-        tmax = std::max(tmax, t);
+        for (int i = 0; i < 4; ++i) L.act_coef[i] = d.coef[i];
+        tmax = std::max(tmax, L.t);
+        m->layers.push_back(L);
     }
     m->block = 2 * tmax;
     if (opts && opts->block) {
@@ -514,36 +635,37 @@ int plan_model(const ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, con
     }
     m->scale_in = scale;
     std::vector<int32_t> rots;
+    int doubled = m->layers[0].t;            // the client encodes [x | x] with the first layer's width
     for (int l = 0; l < n_layers; ++l) {
-        const ctl_layer_desc &d = layers[l];
-        LayerPlan L;
-        L.n_in = d.n_in;
-        L.n_out = d.n_out;
-        L.t = std::max(d.n_in, d.n_out);
-        L.t1 = d.t1;
-        L.t2 = L.t / d.t1;
-        L.k = k;
-        L.act = d.act;
-        if (d.flags & ~CTL_LAYER_LAZY_GIANT) return fail(CTL_EINVAL, "unknown layer flag");
-        L.lazy = (d.flags & CTL_LAYER_LAZY_GIANT) != 0;
+        LayerPlan &L = m->layers[l];
+        if (L.kind != CTL_LAYER_AVGPOOL && doubled != L.t) {
+            L.rep_before = L.t;
+            rots.push_back(-L.t);
+            doubled = L.t;
+        }
         if (k < 2) return fail(CTL_ELEVEL, "modulus chain exhausted at layer " + std::to_string(l));
+        L.k = k;
         L.pt_scale = (double)c->hp.mods[k - 1];
         // the 128-bit accumulation of t1 products must not overflow
         for (int i = 0; i < k; ++i) {
             const u128 sq = (u128)(c->hp.mods[i] - 1) * (c->hp.mods[i] - 1);
             if (sq > (~(u128)0) / (u128)L.t1) return fail(CTL_EPARAM, "t1 too large for the prime sizes");
         }
-        for (int j = 1; j < L.t1; ++j) rots.push_back(j);
+        for (long r : L.rots1) rots.push_back((int32_t)r);
         for (int k2 = 1; k2 < L.t2; ++k2) rots.push_back(k2 * L.t1);
-        m->layers.push_back(L);
-        k -= 1;                                  // dense: rescale, scale unchanged
-        if (l + 1 < n_layers) {
-            if (d.act == CTL_ACT_SQUARE) {
-                if (k < 2) return fail(CTL_ELEVEL, "modulus chain exhausted before x^2");
-                scale = scale * scale / (double)c->hp.mods[k - 1];
-                k -= 1;
-            }
-            rots.push_back(-std::max(layers[l + 1].n_in, layers[l + 1].n_out));
+        k -= 1;                                  // one rescale, scale unchanged
+        doubled = L.kind == CTL_LAYER_CONV1D ? L.t : 0;
+        L.act_scale_in = scale;
+        if (L.act == CTL_ACT_SQUARE) {
+            if (k < 2) return fail(CTL_ELEVEL, "modulus chain exhausted before x^2");
+            scale = scale * scale / (double)c->hp.mods[k - 1];
+            k -= 1;
+        } else if (L.act == CTL_ACT_POLY3) {
+            if (k < 3) return fail(CTL_ELEVEL, "modulus chain exhausted before the cubic activation");
+            if (!poly3_consts_ok(c, k, scale, L.act_coef)) return fail(CTL_ESCALE, "activation constant out of range");
+            int64_t C[4];
+            scale = poly3_consts(c, k, scale, L.act_coef, C);
+            k -= 2;
         }
     }
     if (k < 1) return fail(CTL_ELEVEL, "modulus chain exhausted");
@@ -555,17 +677,44 @@ int plan_model(const ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, con
     return CTL_OK;
 }
 
-// diag'_i of Eq. (1) on its support: in every item block, slot k2 t1 + s holds M[s][(s + i) mod t].
+// diag'_i of Eq. (1) on its support: in every item block, slot k2 t1 + s holds M[s][(s + i) mod t],
+// M the t x t matrix with W in rows 0..n_out-1 and columns in_off..in_off+n_in-1.
 void diag_slots(const ctl_model *m, const LayerPlan &L, const double *W, int i, int half_n, double *z) {
     std::fill(z, z + half_n, 0.0);
     const int k2 = i / L.t1;
     for (int b = 0; b < m->items; ++b) {
         double *blk = z + (long)b * m->block + (long)k2 * L.t1;
         for (int s = 0; s < L.t; ++s) {
-            const int col = (s + i) % L.t;
-            blk[s] = (s < L.n_out && col < L.n_in) ? W[(long)s * L.n_in + col] : 0.0;
+            const int col = (s + i) % L.t - L.in_off;
+            blk[s] = (s < L.n_out && col >= 0 && col < L.n_in) ? W[(long)s * L.n_in + col] : 0.0;
         }
     }
+}
+
+// Bank entry j of a convolution multiplies rot_r(x), r = 0 for j = 0 and rots1[j-1] otherwise; it
+// carries tap r + (f-1)/2 on both halves of every block, where x[s + r] lies inside the width.
+int conv_tap(const LayerPlan &L, int j) { return (j == 0 ? 0 : (int)L.rots1[j - 1]) + (L.f - 1) / 2; }
+
+void conv_slots(const ctl_model *m, const LayerPlan &L, const double *taps, int j, int half_n, double *z) {
+    std::fill(z, z + half_n, 0.0);
+    const int i = conv_tap(L, j), r = i - (L.f - 1) / 2, w = L.n_in;
+    for (int b = 0; b < m->items; ++b)
+        for (int h = 0; h < 2; ++h) {
+            double *blk = z + (long)b * m->block + (long)h * w;
+            for (int s = 0; s < w; ++s) blk[s] = (s + r >= 0 && s + r < w) ? taps[i] : 0.0;
+        }
+}
+
+// The pooling plaintext: 1/f on the valid outputs (slots f-1 .. n_in-1 of each block), 0 elsewhere.
+void pool_slots(const ctl_model *m, const LayerPlan &L, int half_n, double *z) {
+    std::fill(z, z + half_n, 0.0);
+    for (int b = 0; b < m->items; ++b)
+        for (int s = L.f - 1; s < L.n_in; ++s) z[(long)b * m->block + s] = 1.0 / L.f;
+}
+
+// Plaintexts a caller of the raw loader passes for a layer: dense t, convolution f, pool 1.
+int raw_count(const LayerPlan &L) {
+    return L.kind == CTL_LAYER_DENSE ? L.t : L.kind == CTL_LAYER_CONV1D ? L.f : 1;
 }
 
 int encode_to_int(const ctl_ctx *c, const double *z, double scale, int64_t *out) {
@@ -601,19 +750,24 @@ int load_banks(ctl_ctx *c, ctl_model *m, const std::vector<std::vector<int64_t>>
     const int n = c->hp.n;
     for (size_t l = 0; l < m->layers.size(); ++l) {
         const LayerPlan &L = m->layers[l];
-        u64 *bank = static_cast<u64 *>(dev_alloc(c, (size_t)L.t * L.k * n * 8, st));
+        u64 *bank = static_cast<u64 *>(dev_alloc(c, (size_t)L.nb * L.k * n * 8, st));
         if (!bank) return fail(CTL_ENOMEM, "plaintext bank allocation failed");
         m->banks.push_back(bank);
         const int chunk = 32;
         std::vector<int64_t> buf((size_t)chunk * n);
         std::vector<double> z(n / 2);
-        for (int i0 = 0; i0 < L.t; i0 += chunk) {
-            const int cnt = std::min(chunk, L.t - i0);
+        for (int i0 = 0; i0 < L.nb; i0 += chunk) {
+            const int cnt = std::min(chunk, L.nb - i0);
             for (int i = 0; i < cnt; ++i) {
+                const int j = i0 + i;
+                // the caller's plaintext for bank entry j (dense: j; convolution: its tap; pool: the one)
+                const int src = L.kind == CTL_LAYER_DENSE ? j : L.kind == CTL_LAYER_CONV1D ? conv_tap(L, j) : 0;
                 if (ints) {
-                    std::memcpy(&buf[(size_t)i * n], (*ints)[l].data() + (size_t)(i0 + i) * n, (size_t)n * 8);
+                    std::memcpy(&buf[(size_t)i * n], (*ints)[l].data() + (size_t)src * n, (size_t)n * 8);
                 } else {
-                    diag_slots(m, L, weights[l], i0 + i, n / 2, z.data());
+                    if (L.kind == CTL_LAYER_DENSE) diag_slots(m, L, weights[l], j, n / 2, z.data());
+                    else if (L.kind == CTL_LAYER_CONV1D) conv_slots(m, L, weights[l], j, n / 2, z.data());
+                    else pool_slots(m, L, n / 2, z.data());
                     CTL_TRY(encode_to_int(c, z.data(), L.pt_scale, &buf[(size_t)i * n]));
                 }
             }
@@ -636,7 +790,7 @@ int make_model(ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, const int
         std::vector<std::vector<int64_t>> ints(n_layers);
         for (int l = 0; l < n_layers; ++l) {
             if (!pts[l]) return fail(CTL_EINVAL, "null plaintext array");
-            const size_t cnt = (size_t)m->layers[l].t * c->hp.n;
+            const size_t cnt = (size_t)raw_count(m->layers[l]) * c->hp.n;
             for (size_t x = 0; x < cnt; ++x)
                 if (pts[l][x] >= (int64_t)(1ull << 62) || pts[l][x] <= -(int64_t)(1ull << 62))
                     return fail(CTL_ESCALE, "plaintext coefficient out of range");
@@ -645,7 +799,7 @@ int make_model(ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, const int
         rc = load_banks(c, m.get(), &ints, nullptr);
     } else {
         for (int l = 0; l < n_layers; ++l)
-            if (!weights[l]) return fail(CTL_EINVAL, "null weight matrix");
+            if (!weights[l] && m->layers[l].kind != CTL_LAYER_AVGPOOL) return fail(CTL_EINVAL, "null weights");
         rc = load_banks(c, m.get(), nullptr, weights);
     }
     if (rc != CTL_OK) {
@@ -1102,7 +1256,7 @@ int ctl_evk_bytes(const ctl_evk *evk, uint64_t *bytes_out) {
 int ctl_model_bytes(const ctl_model *m, uint64_t *bytes_out) {
     if (!m || !bytes_out) return fail(CTL_EINVAL, "null argument");
     uint64_t b = 0;
-    for (const LayerPlan &L : m->layers) b += (uint64_t)L.t * L.k * m->ctx->hp.n * 8;
+    for (const LayerPlan &L : m->layers) b += (uint64_t)L.nb * L.k * m->ctx->hp.n * 8;
     *bytes_out = b;
     return CTL_OK;
 }
@@ -1242,9 +1396,10 @@ int ctl_decode_items(ctl_ctx *ctx, const ctl_model *m, const uint64_t *residues,
     CTL_SAME(ctx, m, "the model");
     std::vector<double> z(ctx->hp.n / 2);
     CTL_TRY(ctl_decode(ctx, residues, m->k_out, m->scale_out, z.data()));
-    const int n_out = m->layers.back().n_out;
+    const LayerPlan &last = m->layers.back();
+    const int n_out = last.n_out, off = last.kind == CTL_LAYER_AVGPOOL ? last.f - 1 : 0;
     for (int b = 0; b < m->items; ++b)
-        for (int s = 0; s < n_out; ++s) y_out[(size_t)b * n_out + s] = z[(size_t)b * m->block + s];
+        for (int s = 0; s < n_out; ++s) y_out[(size_t)b * n_out + s] = z[(size_t)b * m->block + off + s];
     return CTL_OK;
 }
 
@@ -1305,28 +1460,62 @@ int ctl_forward(ctl_ctx *ctx, const ctl_model *m, const ctl_evk *evk, const uint
     CTL_HIP(hipSetDevice(ctx->device));
     hipStream_t st = as_stream(stream);
     const long N = ctx->hp.n;
-    const u64 *cur = reinterpret_cast<const u64 *>(in);
     const size_t words = (size_t)n_ct * 2 * ctx->hp.nq * N;
-    u64 *a, *b, *c3;
-    CTL_TRY(slot(ctx, S_FWD_A, words, st, &a));
-    CTL_TRY(slot(ctx, S_FWD_B, words, st, &b));
-    CTL_TRY(slot(ctx, S_FWD_C, words, st, &c3));
+    u64 *bufs[3];
+    CTL_TRY(slot(ctx, S_FWD_A, words, st, &bufs[0]));
+    CTL_TRY(slot(ctx, S_FWD_B, words, st, &bufs[1]));
+    CTL_TRY(slot(ctx, S_FWD_C, words, st, &bufs[2]));
+    const u64 *cur = reinterpret_cast<const u64 *>(in);
+    int ci = 2;                                   // the next result goes to bufs[(ci + 1) % 3]
+    auto next = [&]() { ci = (ci + 1) % 3; return bufs[ci]; };
     const int L = (int)m->layers.size();
     for (int l = 0; l < L; ++l) {
         const LayerPlan &P = m->layers[l];
-        const bool last = l + 1 == L;
-        u64 *dst = last ? reinterpret_cast<u64 *>(out) : a;
-        CTL_TRY(dense_batch(ctx, st, m, l, evk, n_ct, cur, dst));
-        if (last) break;
-        int k = P.k - 1;
-        const u64 *x = dst;
-        if (P.act == CTL_ACT_SQUARE) {
-            CTL_TRY(square_batch(ctx, st, evk, k, n_ct, dst, b));
-            k -= 1;
-            x = b;
+        if (P.rep_before) {
+            u64 *dst = next();
+            CTL_TRY(replicate_batch(ctx, st, evk, P.k, n_ct, P.rep_before, cur, dst));
+            cur = dst;
         }
-        CTL_TRY(replicate_batch(ctx, st, evk, k, n_ct, m->layers[l + 1].t, x, c3));
-        cur = c3;
+        const bool last = l + 1 == L;
+        u64 *dst = last ? reinterpret_cast<u64 *>(out) : next();
+        CTL_TRY(dense_batch(ctx, st, m, l, evk, n_ct, cur, dst));
+        cur = dst;
+        if (last) break;
+        if (P.act == CTL_ACT_SQUARE) {
+            u64 *d2 = next();
+            CTL_TRY(square_batch(ctx, st, evk, P.k - 1, n_ct, cur, d2));
+            cur = d2;
+        } else if (P.act == CTL_ACT_POLY3) {
+            u64 *d2 = next();
+            CTL_TRY(poly3_batch(ctx, st, evk, P.k - 1, n_ct, P.act_scale_in, P.act_coef, cur, d2));
+            cur = d2;
+        }
+    }
+    return CTL_OK;
+}
+
+int ctl_mul(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *a, const uint64_t *b, uint64_t *out,
+            int n_ct, void *stream) {
+    if (!ctx || !evk || !a || !b || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
+    if (k < 2 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    CTL_SAME(ctx, evk, "the evaluation key set");
+    CTL_HIP(hipSetDevice(ctx->device));
+    return mul_batch(ctx, as_stream(stream), evk, k, n_ct, reinterpret_cast<const u64 *>(a),
+                     reinterpret_cast<const u64 *>(b), reinterpret_cast<u64 *>(out));
+}
+
+int ctl_poly3(ctl_ctx *ctx, const ctl_evk *evk, int k, double scale, const double *coef, const uint64_t *in,
+              uint64_t *out, int n_ct, void *stream, double *scale_out) {
+    if (!ctx || !evk || !coef || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
+    if (k < 3 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    if (!(scale > 0) || !std::isfinite(scale)) return fail(CTL_ESCALE, "scale must be positive");
+    CTL_SAME(ctx, evk, "the evaluation key set");
+    CTL_HIP(hipSetDevice(ctx->device));
+    CTL_TRY(poly3_batch(ctx, as_stream(stream), evk, k, n_ct, scale, coef, reinterpret_cast<const u64 *>(in),
+                        reinterpret_cast<u64 *>(out)));
+    if (scale_out) {
+        int64_t C[4];
+        *scale_out = poly3_consts(ctx, k, scale, coef, C);
     }
     return CTL_OK;
 }

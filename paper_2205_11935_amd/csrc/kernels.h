@@ -64,7 +64,14 @@ void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *i
                 int t1, int t2, const Tables &tab, hipStream_t st);
 void launch_add_terms(int logn, const u64 *a, long a_sb, const u64 *terms, long t_sb, long t_ss, int S,
                       u64 *out, int B, int k, const Tables &tab, hipStream_t st);
-void launch_tensor(int logn, const u64 *in, u64 *out, int B, int k, const Tables &tab, hipStream_t st);
+void launch_tensor(int logn, const u64 *a, const u64 *b, u64 *out, int B, int k, const Tables &tab, hipStream_t st);
+// Per-prime constants of k_affine: multiplier (with its Shoup companion floor(mul 2^64 / q)) and
+// addend of c0, each reduced mod q_i.
+struct AffineConst {
+    u64 mul[kMaxMods], muls[kMaxMods], add[kMaxMods];
+};
+void launch_affine(int logn, const u64 *in, u64 *out, int B, int k_in, int k_out, const AffineConst &ac,
+                   const Tables &tab, hipStream_t st);
 void launch_ksk_body(int logn, u64 *key, const u64 *e, const u64 *s, u64 g, int nq, const Tables &tab,
                      hipStream_t st);
 void launch_pk_body(int logn, u64 *pk, const u64 *e, const u64 *s, int nq, const Tables &tab, hipStream_t st);

@@ -813,18 +813,37 @@ k_sum_gather(u64 *__restrict__ out, long o_sb, const u64 *__restrict__ base, lon
     out[b * o_sb + off + n] = s;
 }
 
-// (c0, c1) -> (c0^2, 2 c0 c1, c1^2): in [B][2][k][N], out [B][3][k][N].
+// (a0, a1) x (b0, b1) -> (a0 b0, a0 b1 + a1 b0, a1 b1): a, b [B][2][k][N], out [B][3][k][N].
 __global__ void __launch_bounds__(256)
-k_tensor(const u64 *__restrict__ in, u64 *__restrict__ out, int k, int logn, const PrimeConst *__restrict__ pcs) {
+k_tensor(const u64 *__restrict__ a, const u64 *__restrict__ bb, u64 *__restrict__ out, int k, int logn,
+         const PrimeConst *__restrict__ pcs) {
     const long N = 1L << logn, kn = (long)k * N;
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;   // over k N
     const int b = blockIdx.y;
     const PrimeConst p = pcs[idx / N];
-    const u64 c0 = in[b * 2 * kn + idx], c1 = in[b * 2 * kn + kn + idx];
+    const u64 a0 = a[b * 2 * kn + idx], a1 = a[b * 2 * kn + kn + idx];
+    const u64 b0 = bb[b * 2 * kn + idx], b1 = bb[b * 2 * kn + kn + idx];
     u64 *o = out + b * 3 * kn + idx;
-    o[0] = mul_mod(c0, c0, p);
-    o[kn] = mul_mod(add_mod(c0, c0, p.q), c1, p);
-    o[2 * kn] = mul_mod(c1, c1, p);
+    o[0] = mul_mod(a0, b0, p);
+    o[kn] = add_mod(mul_mod(a0, b1, p), mul_mod(a1, b0, p), p.q);
+    o[2 * kn] = mul_mod(a1, b1, p);
+}
+
+// out[b][c][i] = in[b][c][i] * mul_i + (c == 0 ? add_i : 0) mod q_i for the first k_out of the
+// k_in residues of each polynomial (dropping the others lowers the level, keeping the value).
+__global__ void __launch_bounds__(256)
+k_affine(const u64 *in, u64 *out, int k_in, int k_out, AffineConst ac, int logn,
+         const PrimeConst *__restrict__ pcs) {
+    const long N = 1L << logn;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;   // over 2 k_out N
+    const int b = blockIdx.y;
+    const int c = (int)(idx / ((long)k_out * N)), i = (int)((idx / N) % k_out);
+    const long x = idx % N;
+    const PrimeConst p = pcs[i];
+    const u64 v = in[((long)b * 2 * k_in + (long)c * k_in + i) * N + x];
+    u64 r = red2(shoup_lazy(v, ac.mul[i], ac.muls[i], p.q, p.qn), p.q);
+    if (c == 0) r = add_mod(r, ac.add[i], p.q);
+    out[((long)b * 2 * k_out + (long)c * k_out + i) * N + x] = r;
 }
 
 // Key-switching key body: key[j][0][i] = -a s + e (+ [P]_{q_i} s'_i when i == j); a already at
@@ -1017,9 +1036,15 @@ void launch_sum_gather(int logn, u64 *out, long o_sb, const u64 *base, long ba_s
                        mask, gal, nq, logn, tab.pc);
 }
 
-void launch_tensor(int logn, const u64 *in, u64 *out, int B, int k, const Tables &tab, hipStream_t st) {
+void launch_tensor(int logn, const u64 *a, const u64 *b, u64 *out, int B, int k, const Tables &tab, hipStream_t st) {
     const dim3 grid((unsigned)(((long)k << logn) / 256), B), blk(256);
-    hipLaunchKernelGGL(k_tensor, grid, blk, 0, st, in, out, k, logn, tab.pc);
+    hipLaunchKernelGGL(k_tensor, grid, blk, 0, st, a, b, out, k, logn, tab.pc);
+}
+
+void launch_affine(int logn, const u64 *in, u64 *out, int B, int k_in, int k_out, const AffineConst &ac,
+                   const Tables &tab, hipStream_t st) {
+    const dim3 grid((unsigned)((2L * k_out << logn) / 256), B), blk(256);
+    hipLaunchKernelGGL(k_affine, grid, blk, 0, st, in, out, k_in, k_out, ac, logn, tab.pc);
 }
 
 void launch_ksk_body(int logn, u64 *key, const u64 *e, const u64 *s, u64 g, int nq, const Tables &tab,
