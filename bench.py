@@ -110,9 +110,13 @@ def main():
                     help="giant steps lowered by one ModDown of their summed key products (lazy) or one "
                          "ModDown each (per-step); the other variant is timed too, without profiling")
     ap.add_argument("--other-steps", type=int, default=3, help="timed steps of the other giant-step variant")
-    ap.add_argument("--workload", choices=("large", "mix", "serve"), default="large",
+    ap.add_argument("--workload", choices=("large", "mix", "serve", "cnn"), default="large",
                     help="large: the 768->256->64 stack, batch 64 (the headline); mix: 512 queries of "
-                         "1-3 layers with widths from {128,256,512,768}; serve: the serving loop alone")
+                         "1-3 layers with widths from {128,256,512,768}; serve: the serving loop alone; "
+                         "cnn: the paper's frozen CNN stack at its two parameter sets")
+    ap.add_argument("--paper-stack", type=int, default=1,
+                    help="also time the paper's frozen CNN stack (Conv1D, Dense+ReLU approx., AvgPool, "
+                         "Dense) at CryptoTL_p1 and _p2 and report it beside the headline (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="serving sweep: seconds of Poisson arrivals per rate (0: skip the sweep)")
     ap.add_argument("--serve-rates", default="10,100,500,1000,2000", help="serving sweep: arrival rates, q/s")
@@ -134,6 +138,8 @@ def main():
         return bench_mix(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "cnn":
+        return bench_cnn(args)
 
     w = W.LARGE
     B = args.batch
@@ -315,12 +321,16 @@ def main():
         "setup_s": round(setup_s, 2),
         "workspace_gib": round(c.workspace_bytes() / 2 ** 30, 2),
     }
-    if args.serve_seconds > 0:
+    if args.serve_seconds > 0 or args.paper_stack:
         del c, model, other, keys, ct, out, one, one_out, buf
         import gc
         gc.collect()
         torch.cuda.empty_cache()
+    if args.serve_seconds > 0:
         line["serving"] = serving_sweep(args)
+    if args.paper_stack:
+        line["paper_stack"] = {name: cnn_measure(name, args.batch, max(2, args.steps // 2), plain_steps=5)
+                               for name in ("cnn_p1", "cnn_p2")}
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
         line["cpu_baseline"]["cores"] = 1
@@ -389,6 +399,81 @@ def serving_sweep(args):
     return {"workload": "Poisson arrivals, 80% mid (N=2^13, 512->128->128) / 20% large (N=2^14, "
                         "768->256->64), 4 clients per set, keys resident, 2 lanes per set, batches up to 64",
             "sweep": sweep, "key_bytes": key_budget, "setup_s": round(setup_s, 2)}
+
+
+PAPER_T_S = {"cnn_p1": {"avx512_s": 1.08, "portable_s": 2.72}, "cnn_p2": {"avx512_s": 2.56, "portable_s": 5.93}}
+
+
+def cnn_measure(name: str, batch: int, steps: int, plain_steps: int = 5):
+    """The paper's frozen layers (Conv1D f=9, Dense 768 + cubic ReLU approximation, AvgPool 3,
+    Dense 766) at one of Table 2's parameter sets: batched throughput, one-ciphertext latency (the
+    paper's t_S, single-threaded CPU there) and a decrypted check against FP64."""
+    import torch
+    import paper_2205_11935_amd as ctl
+    w = W.CNN_WORKLOADS[name]
+    t0 = time.perf_counter()
+    c = ctl.Context(w.log2n, w.q_bits, w.p_bits, w.log2_scale, w.sigma)
+    layers = [ctl.Layer.conv1d(w.width, w.f_conv),
+              ctl.Layer.dense(w.width, w.width, w.t1, act=ctl.CTL_ACT_POLY3, coef=W.RELU3_COEF),
+              ctl.Layer.avgpool(w.width, w.f_pool),
+              ctl.Layer.dense(w.pooled, w.pooled, w.t1)]
+    taps, w1, w2 = W.cnn_weights(w)
+    m = c.load_model(layers, [taps, w1, None, w2], lazy=True)
+    keys = c.keygen(w.seed_keys, m.info.rotations, relin=True)
+    x = W.cnn_inputs(w, batch, m.info.items)
+    ct = c.empty_ct(batch, c.nq)
+    for i in range(batch):
+        c.encrypt(keys, c.encode_items(m, x[i]), 800 + i, out=ct[i])
+    out = c.empty_ct(batch, m.info.k_out)
+    setup_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    c.forward(m, keys, ct, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.forward(m, keys, ct, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    one, one_out = ct[:1].contiguous(), c.empty_ct(1, m.info.k_out)
+    c.forward(m, keys, one, out=one_out)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(plain_steps + 1)]
+    ev[0].record(stream)
+    for i in range(plain_steps):
+        c.forward(m, keys, one, out=one_out)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(plain_steps)]
+    y = c.decode_items(m, c.decrypt(keys, out[0], m.info.k_out))
+    ref = []
+    for b in range(m.info.items):                     # FP64 forward pass of the same layers
+        z = w1 @ np.convolve(x[0][b], taps[::-1], mode="same")
+        a = np.polyval(np.array(W.RELU3_COEF)[::-1], z)
+        ref.append(w2 @ np.convolve(a, np.ones(w.f_pool) / w.f_pool, mode="valid"))
+    ref = np.stack(ref)
+    err = float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+    value = batch * steps / el
+    t_s = _percentile(lat, 50) / 1e3
+    return {"params": "N=2^%d, log2 q=%d, Delta=2^%d, p=%d" % (w.log2n, sum(x.bit_length() for x in c.primes),
+                                                                 w.log2_scale, m.info.items),
+            "batch": batch, "fwd_per_s": round(value, 2), "items_per_s": round(value * m.info.items, 1),
+            "ms_per_batch": round(el / steps * 1e3, 2), "t_s_one_ct_ms": {"p50": _percentile(lat, 50),
+                                                                           "p99": _percentile(lat, 99)},
+            "paper_t_s": PAPER_T_S[name], "speedup_vs_paper_avx512_t_s": round(PAPER_T_S[name]["avx512_s"] / t_s, 1),
+            "decrypt_check_rel_err": err, "setup_s": round(setup_s, 2)}
+
+
+def bench_cnn(args):
+    res = {name: cnn_measure(name, args.batch, args.steps, plain_steps=10) for name in ("cnn_p1", "cnn_p2")}
+    p2 = res["cnn_p2"]
+    line = {"metric": "encrypted fwd passes/sec of the paper's frozen CNN layers (CryptoTL_p2, N=2^14)",
+            "value": p2["fwd_per_s"], "unit": "encrypted forward passes/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": p2["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "Conv1D f=9 -> Dense 768 + ReLU approx. (degree 3) -> AvgPool 3 -> Dense 766, "
+                                   "batch %d" % args.batch},
+            "paper_stack": res}
+    print(json.dumps(line), flush=True)
 
 
 def bench_serve(args):
