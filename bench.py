@@ -401,6 +401,7 @@ def serving_sweep(args):
             "sweep": sweep, "key_bytes": key_budget, "setup_s": round(setup_s, 2)}
 
 
+PAPER_KB = {"cnn_p1": [235.3, 82.4], "cnn_p2": [838.1, 262.3]}
 PAPER_T_S = {"cnn_p1": {"avx512_s": 1.08, "portable_s": 2.72}, "cnn_p2": {"avx512_s": 2.56, "portable_s": 5.93}}
 
 
@@ -454,12 +455,16 @@ def cnn_measure(name: str, batch: int, steps: int, plain_steps: int = 5):
     err = float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
     value = batch * steps / el
     t_s = _percentile(lat, 50) / 1e3
+    up = ctl.ct_packed_bytes(w.log2n, w.q_bits, w.p_bits, len(w.q_bits), 1)      # seeded c0 + seed
+    down = ctl.ct_packed_bytes(w.log2n, w.q_bits, w.p_bits, m.info.k_out, 2)
     return {"params": "N=2^%d, log2 q=%d, Delta=2^%d, p=%d" % (w.log2n, sum(x.bit_length() for x in c.primes),
                                                                  w.log2_scale, m.info.items),
             "batch": batch, "fwd_per_s": round(value, 2), "items_per_s": round(value * m.info.items, 1),
             "ms_per_batch": round(el / steps * 1e3, 2), "t_s_one_ct_ms": {"p50": _percentile(lat, 50),
                                                                            "p99": _percentile(lat, 99)},
             "paper_t_s": PAPER_T_S[name], "speedup_vs_paper_avx512_t_s": round(PAPER_T_S[name]["avx512_s"] / t_s, 1),
+            "message_kB": {"client_to_server": round(up / 1000, 1), "server_to_client": round(down / 1000, 1),
+                           "paper": PAPER_KB[name]},
             "decrypt_check_rel_err": err, "setup_s": round(setup_s, 2)}
 
 

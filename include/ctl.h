@@ -7,7 +7,8 @@
  * hold a key pair and encrypt with HE.Enc_pk, the server evaluate ClassifyHE(c, M_S) on its frozen
  * layers, and the client decrypt with HE.Dec_sk. The calls below follow that split:
  *
- *   client:  ctl_keygen, ctl_encode / ctl_encode_items, ctl_encrypt, ctl_decrypt, ctl_decode*
+ *   client:  ctl_keygen, ctl_encode / ctl_encode_items, ctl_encrypt / ctl_encrypt_sym,
+ *            ctl_decrypt, ctl_decode*, ctl_ct_pack / ctl_ct_unpack (wire format)
  *   server:  ctl_model_load*, ctl_dense, ctl_square, ctl_replicate, ctl_rescale, ctl_rotate,
  *            ctl_forward  (= ClassifyHE)
  *
@@ -283,6 +284,15 @@ int ctl_encode_items(ctl_ctx *ctx, const ctl_model *model, const double *x, int 
  * ct_out: device uint64[2][n_q][N]. */
 int ctl_encrypt(ctl_ctx *ctx, const ctl_pk *pk, const int64_t *coeffs, uint64_t seed,
                 uint64_t *ct_out, void *stream);
+/* Seeded secret-key encryption at the top level: ct = (-a s + e + m, a) with a uniform (drawn as
+ * NTT values, prime by prime, from the stream (seed, 11, 0)) and e Gaussian (stream (seed, 12, 0)).
+ * c1 = a depends on the seed alone, so a client can send c0 and the seed: half the upload, the
+ * size Table 2's client-to-server column implies. ct_out: device uint64[2][n_q][N]; blocks. */
+int ctl_encrypt_sym(ctl_ctx *ctx, const ctl_sk *sk, const int64_t *coeffs, uint64_t seed,
+                    uint64_t *ct_out, void *stream);
+/* Server side of a seeded upload: c0 (host uint64[n_q][N], every word reduced, else CTL_EINVAL)
+ * and the seed become the full ciphertext at device pointer ct_out ([2][n_q][N]); blocks. */
+int ctl_expand_seeded(ctl_ctx *ctx, const uint64_t *c0, uint64_t seed, uint64_t *ct_out, void *stream);
 /* Decryption (HE.Dec_sk) of one ciphertext with k live primes at device pointer ct: writes the
  * coefficient-form residues of c0 + c1 s to host uint64[k][N]. Synchronizes the stream. */
 int ctl_decrypt(ctl_ctx *ctx, const ctl_sk *sk, const uint64_t *ct, int k, uint64_t *residues_out,
@@ -291,6 +301,24 @@ int ctl_decrypt(ctl_ctx *ctx, const ctl_sk *sk, const uint64_t *ct, int k, uint6
 int ctl_decode(ctl_ctx *ctx, const uint64_t *residues, int k, double scale, double *slots_out);
 /* Decode a model output: y_out host double [items][n_out] read from slots [b*block, b*block+n_out). */
 int ctl_decode_items(ctl_ctx *ctx, const ctl_model *model, const uint64_t *residues, double *y_out);
+
+/* ------------------------------------------------------------------ wire format (host only) */
+/* Serialized ciphertexts for the client-server messages ("Communication" paragraph of Section 4.2:
+ * the client sends a ciphertext at the top level, the server returns one at q_0). Little-endian:
+ *   bytes 0-3 "CTL1", 4 version (1), 5 log2 N, 6 k, 7 n_poly (2: (c0, c1); 1: c0 of a seeded
+ *   symmetric ciphertext), 8-15 FNV-1a-64 digest of the primes q_0..q_{n_q-1}, P as little-endian
+ *   words, 16-23 the seed (n_poly = 1) or 0; then for each polynomial and each prime q_i
+ *   (i < k) the N residues, each in bits(q_i) bits, least significant bit first, packed
+ *   back to back (every row is a whole number of bytes because N is a multiple of 8).
+ * Size: 24 + n_poly * N * sum_{i<k} bits(q_i) / 8 bytes. ct: host uint64[n_poly][k][N].
+ * Pack fails with CTL_EINVAL on an unreduced word or a short buffer; unpack rejects a wrong magic,
+ * version or length (CTL_EINVAL), another parameter set (CTL_EPARAM) or an unreduced word, and
+ * then writes nothing. ct_out must hold n_poly * k * N words (at most 2 * n_q * N). */
+int ctl_ct_packed_bytes(const ctl_params *params, int k, int n_poly, uint64_t *bytes_out);
+int ctl_ct_pack(const ctl_params *params, const uint64_t *ct, int k, int n_poly, uint64_t seed, uint8_t *out,
+                uint64_t cap, uint64_t *len_out);
+int ctl_ct_unpack(const ctl_params *params, const uint8_t *in, uint64_t len, uint64_t *ct_out, int *k_out,
+                  int *n_poly_out, uint64_t *seed_out);
 
 /* ------------------------------------------------------------------ server hot path (batched) */
 /* All take n_ct ciphertexts [n_ct][2][k][N] at device pointer `in` and write [n_ct][2][k'][N] to

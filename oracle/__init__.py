@@ -229,6 +229,14 @@ class CKKSOracle:
         self.lib.or_encrypt(self.c, _p(pk), _p(m), ctypes.c_uint64(seed), _p(ct))
         return ct
 
+    def encrypt_sym(self, s: np.ndarray, m: np.ndarray, seed: int) -> np.ndarray:
+        """Seeded secret-key encryption (-a s + e + m, a); a depends on the seed only."""
+        m = np.ascontiguousarray(m, dtype=np.int64)
+        ct = np.zeros((2, self.nq, self.n), dtype=np.uint64)
+        self.lib.or_encrypt_sym(self.c, _p(np.ascontiguousarray(s, dtype=np.int64)), _p(m),
+                                ctypes.c_uint64(seed), _p(ct))
+        return ct
+
     def decrypt(self, s: np.ndarray, ct: np.ndarray) -> np.ndarray:
         """Coefficient-form residues of c0 + c1 s, [k][N]."""
         ct = np.ascontiguousarray(ct, dtype=np.uint64)

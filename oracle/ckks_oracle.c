@@ -352,7 +352,7 @@ static u64 stream_u64(stream_t *st) {
 }
 
 enum { TAG_SK = 1, TAG_PK_A = 2, TAG_PK_E = 3, TAG_KS_A = 4, TAG_KS_E = 5,
-       TAG_ENC_V = 8, TAG_ENC_E0 = 9, TAG_ENC_E1 = 10 };
+       TAG_ENC_V = 8, TAG_ENC_E0 = 9, TAG_ENC_E1 = 10, TAG_SYM_A = 11, TAG_SYM_E = 12 };
 
 static void sample_ternary(stream_t *st, int n, int64_t *out) {
     for (int k = 0; k < n; k++) {
@@ -1043,4 +1043,30 @@ double or_poly3(const or_ctx *c, int k, const u64 *ct, double S, const double *c
         }
     free(z2); free(t); free(u); free(w);
     return S3;
+}
+
+/* ---------------------------------------------------------------- seeded symmetric encryption */
+
+/* Secret-key encryption at the top level: ct = (-a s + e + m, a), [2][nq][N] NTT form, with a
+ * uniform drawn directly as NTT values prime by prime from the stream (seed, TAG_SYM_A, 0) and e
+ * Gaussian from (seed, TAG_SYM_E, 0). c1 = a is a function of the seed alone, so the client can
+ * send c0 and the seed (half the bytes) and the server regenerates c1. */
+void or_encrypt_sym(const or_ctx *c, const int64_t *s, const int64_t *m, u64 seed, u64 *ct) {
+    int n = c->n, nq = c->nq;
+    int64_t *e = (int64_t *)malloc(sizeof(int64_t) * n);
+    u64 *sn = (u64 *)malloc(sizeof(u64) * n), *tn = (u64 *)malloc(sizeof(u64) * n);
+    stream_t sa, se;
+    stream_init(&sa, seed, TAG_SYM_A, 0);
+    stream_init(&se, seed, TAG_SYM_E, 0);
+    sample_gauss(c, &se, n, e);
+    for (int i = 0; i < nq; i++) {
+        u64 q = c->q[i];
+        u64 *c0 = ct + (size_t)i * n, *a = ct + (size_t)(nq + i) * n;
+        for (int k = 0; k < n; k++) a[k] = sample_uniform1(&sa, q);
+        small_to_ntt(c, i, s, sn);
+        small_to_ntt(c, i, e, c0);
+        small_to_ntt(c, i, m, tn);
+        for (int k = 0; k < n; k++) c0[k] = addm(subm(c0[k], mulm(a[k], sn[k], q), q), tn[k], q);
+    }
+    free(e); free(sn); free(tn);
 }

@@ -138,6 +138,14 @@ _SIGS = {
     "ctl_encode_items": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, f64p, ctypes.c_int, i64p]),
     "ctl_encrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, i64p, ctypes.c_uint64, ctypes.c_void_p,
                                    ctypes.c_void_p]),
+    "ctl_encrypt_sym": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, i64p, ctypes.c_uint64, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "ctl_expand_seeded": (ctypes.c_int, [ctypes.c_void_p, u64p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "ctl_ct_packed_bytes": (ctypes.c_int, [ctypes.POINTER(_Params), ctypes.c_int, ctypes.c_int, u64p]),
+    "ctl_ct_pack": (ctypes.c_int, [ctypes.POINTER(_Params), u64p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                   ctypes.POINTER(ctypes.c_uint8), ctypes.c_uint64, u64p]),
+    "ctl_ct_unpack": (ctypes.c_int, [ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_uint8), ctypes.c_uint64, u64p,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), u64p]),
     "ctl_decrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, u64p,
                                    ctypes.c_void_p]),
     "ctl_decode": (ctypes.c_int, [ctypes.c_void_p, u64p, ctypes.c_int, ctypes.c_double, f64p]),
@@ -429,6 +437,20 @@ class Context:
         _check(lib().ctl_encrypt(self.handle, keys.pk, m.ctypes.data_as(i64p), seed, _ptr(out), _stream(stream)))
         return out
 
+    def encrypt_sym(self, keys: Keys, coeffs: np.ndarray, seed: int, out=None, stream=None):
+        m = np.ascontiguousarray(coeffs, dtype=np.int64)
+        if out is None:
+            out = self.empty_ct(1, self.nq)[0]
+        _check(lib().ctl_encrypt_sym(self.handle, keys.sk, m.ctypes.data_as(i64p), seed, _ptr(out), _stream(stream)))
+        return out
+
+    def expand_seeded(self, c0: np.ndarray, seed: int, out=None, stream=None):
+        c0 = np.ascontiguousarray(c0, dtype=np.uint64)
+        if out is None:
+            out = self.empty_ct(1, self.nq)[0]
+        _check(lib().ctl_expand_seeded(self.handle, c0.ctypes.data_as(u64p), seed, _ptr(out), _stream(stream)))
+        return out
+
     def decrypt(self, keys: Keys, ct, k: int, stream=None) -> np.ndarray:
         out = np.zeros((k, self.n), dtype=np.uint64)
         _check(lib().ctl_decrypt(self.handle, keys.sk, _ptr(ct), k, out.ctypes.data_as(u64p), _stream(stream)))
@@ -567,6 +589,37 @@ class Context:
             out = self.empty_ct(n_ct, k - 1)
         _check(lib().ctl_rescale(self.handle, k, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
         return out
+
+
+def ct_packed_bytes(log2n, q_bits, p_bits, k: int, n_poly: int) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().ctl_ct_packed_bytes(ctypes.byref(_params(log2n, q_bits, p_bits, 40, 3.2)), k, n_poly, ctypes.byref(b)))
+    return int(b.value)
+
+
+def ct_pack(log2n, q_bits, p_bits, ct: np.ndarray, seed: int = 0) -> bytes:
+    """Serialize host residues [n_poly][k][N] (n_poly = 1: c0 of a seeded upload, with its seed)."""
+    ct = np.ascontiguousarray(ct, dtype=np.uint64)
+    n_poly, k = ct.shape[0], ct.shape[1]
+    prm = _params(log2n, q_bits, p_bits, 40, 3.2)
+    size = ct_packed_bytes(log2n, q_bits, p_bits, k, n_poly)
+    out = np.zeros(size, dtype=np.uint8)
+    ln = ctypes.c_uint64()
+    _check(lib().ctl_ct_pack(ctypes.byref(prm), ct.ctypes.data_as(u64p), k, n_poly, seed,
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), size, ctypes.byref(ln)))
+    return out[: ln.value].tobytes()
+
+
+def ct_unpack(log2n, q_bits, p_bits, data: bytes):
+    """-> (residues [n_poly][k][N] uint64, seed)."""
+    buf = np.frombuffer(data, dtype=np.uint8).copy()
+    out = np.zeros(2 * len(q_bits) << log2n, dtype=np.uint64)
+    k, npl, seed = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint64()
+    _check(lib().ctl_ct_unpack(ctypes.byref(_params(log2n, q_bits, p_bits, 40, 3.2)),
+                               buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), len(data),
+                               out.ctypes.data_as(u64p), ctypes.byref(k), ctypes.byref(npl), ctypes.byref(seed)))
+    n = 1 << log2n
+    return out[: npl.value * k.value * n].reshape(npl.value, k.value, n), int(seed.value)
 
 
 def to_numpy_u64(t) -> np.ndarray:

@@ -810,6 +810,40 @@ int make_model(ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, const int
     return CTL_OK;
 }
 
+// c1 = a of a seeded symmetric ciphertext: uniform NTT values over q_0..q_{nq-1}, prime by prime.
+void seeded_a(const ctl_ctx *ctx, uint64_t seed, std::vector<u64> &a) {
+    const int n = ctx->hp.n, nq = ctx->hp.nq;
+    a.resize((size_t)nq * n);
+    Stream sa(seed, TAG_SYM_A, 0);
+    for (int i = 0; i < nq; ++i)
+        for (int x = 0; x < n; ++x) a[(size_t)i * n + x] = sa.uniform(ctx->hp.mods[i]);
+}
+
+// ---------------------------------------------------------------- wire format
+constexpr uint8_t kMagic[4] = {'C', 'T', 'L', '1'};
+constexpr int kHeader = 24;
+
+u64 params_digest(const HostParams &h) {             // FNV-1a over the primes, little-endian words
+    u64 d = 1469598103934665603ull;
+    for (int i = 0; i < h.np; ++i)
+        for (int b = 0; b < 8; ++b) {
+            d ^= (h.mods[i] >> (8 * b)) & 0xff;
+            d *= 1099511628211ull;
+        }
+    return d;
+}
+
+int bits_of(u64 q) { int b = 0; while (b < 64 && (q >> b)) ++b; return b; }
+
+u64 packed_bytes(const HostParams &h, int k, int n_poly) {
+    u64 bits = 0;
+    for (int i = 0; i < k; ++i) bits += (u64)bits_of(h.mods[i]) * h.n;
+    return kHeader + (u64)n_poly * bits / 8;
+}
+
+void put_u64(uint8_t *p, u64 v) { for (int b = 0; b < 8; ++b) p[b] = (uint8_t)(v >> (8 * b)); }
+u64 get_u64(const uint8_t *p) { u64 v = 0; for (int b = 0; b < 8; ++b) v |= (u64)p[b] << (8 * b); return v; }
+
 }  // namespace
 
 // =============================================================================== exported API
@@ -1209,6 +1243,85 @@ int ctl_evk_galois(const ctl_evk *evk, uint64_t *elts_out, int *n_out) {
     return CTL_OK;
 }
 
+
+int ctl_ct_packed_bytes(const ctl_params *params, int k, int n_poly, uint64_t *bytes_out) {
+    if (!params || !bytes_out || (n_poly != 1 && n_poly != 2)) return fail(CTL_EINVAL, "bad argument");
+    HostParams h;
+    CTL_TRY(derive_params(params, &h, &g_err));
+    if (k < 1 || k > h.nq) return fail(CTL_ELEVEL, "k out of range");
+    *bytes_out = packed_bytes(h, k, n_poly);
+    return CTL_OK;
+}
+
+int ctl_ct_pack(const ctl_params *params, const uint64_t *ct, int k, int n_poly, uint64_t seed, uint8_t *out,
+                uint64_t cap, uint64_t *len_out) {
+    if (!params || !ct || !out || !len_out || (n_poly != 1 && n_poly != 2)) return fail(CTL_EINVAL, "bad argument");
+    HostParams h;
+    CTL_TRY(derive_params(params, &h, &g_err));
+    if (k < 1 || k > h.nq) return fail(CTL_ELEVEL, "k out of range");
+    const u64 len = packed_bytes(h, k, n_poly);
+    if (cap < len) return fail(CTL_EINVAL, "output buffer too small");
+    const size_t n = h.n;
+    for (int p = 0; p < n_poly; ++p)
+        for (int i = 0; i < k; ++i)
+            for (size_t x = 0; x < n; ++x)
+                if (ct[((size_t)p * k + i) * n + x] >= h.mods[i]) return fail(CTL_EINVAL, "word not reduced");
+    std::memcpy(out, kMagic, 4);
+    out[4] = 1;
+    out[5] = (uint8_t)h.logn;
+    out[6] = (uint8_t)k;
+    out[7] = (uint8_t)n_poly;
+    put_u64(out + 8, params_digest(h));
+    put_u64(out + 16, n_poly == 1 ? seed : 0);
+    uint8_t *w = out + kHeader;
+    std::memset(w, 0, len - kHeader);
+    u64 bit = 0;
+    for (int p = 0; p < n_poly; ++p)
+        for (int i = 0; i < k; ++i) {
+            const int b = bits_of(h.mods[i]);
+            for (size_t x = 0; x < n; ++x, bit += b) {
+                const u64 v = ct[((size_t)p * k + i) * n + x];
+                for (int j = 0; j < b; ++j)
+                    if ((v >> j) & 1) w[(bit + j) >> 3] |= (uint8_t)(1u << ((bit + j) & 7));
+            }
+        }
+    *len_out = len;
+    return CTL_OK;
+}
+
+int ctl_ct_unpack(const ctl_params *params, const uint8_t *in, uint64_t len, uint64_t *ct_out, int *k_out,
+                  int *n_poly_out, uint64_t *seed_out) {
+    if (!params || !in || !ct_out || !k_out || !n_poly_out || !seed_out) return fail(CTL_EINVAL, "null argument");
+    HostParams h;
+    CTL_TRY(derive_params(params, &h, &g_err));
+    if (len < (u64)kHeader || std::memcmp(in, kMagic, 4) != 0 || in[4] != 1)
+        return fail(CTL_EINVAL, "not a serialized ciphertext of this format");
+    const int logn = in[5], k = in[6], n_poly = in[7];
+    if (logn != h.logn || get_u64(in + 8) != params_digest(h))
+        return fail(CTL_EPARAM, "serialized for another parameter set");
+    if (k < 1 || k > h.nq || (n_poly != 1 && n_poly != 2)) return fail(CTL_EINVAL, "bad level or polynomial count");
+    if (len != packed_bytes(h, k, n_poly)) return fail(CTL_EINVAL, "length does not match the header");
+    const size_t n = h.n;
+    std::vector<u64> tmp((size_t)n_poly * k * n);
+    const uint8_t *r = in + kHeader;
+    u64 bit = 0;
+    for (int p = 0; p < n_poly; ++p)
+        for (int i = 0; i < k; ++i) {
+            const int b = bits_of(h.mods[i]);
+            for (size_t x = 0; x < n; ++x, bit += b) {
+                u64 v = 0;
+                for (int j = 0; j < b; ++j) v |= (u64)((r[(bit + j) >> 3] >> ((bit + j) & 7)) & 1) << j;
+                if (v >= h.mods[i]) return fail(CTL_EINVAL, "serialized word not reduced");
+                tmp[((size_t)p * k + i) * n + x] = v;
+            }
+        }
+    std::memcpy(ct_out, tmp.data(), tmp.size() * 8);
+    *k_out = k;
+    *n_poly_out = n_poly;
+    *seed_out = get_u64(in + 16);
+    return CTL_OK;
+}
+
 int ctl_evk_import(ctl_ctx *ctx, const uint64_t *galois_elts, int n_keys, const uint64_t *const *keys,
                    ctl_evk **evk_out) {
     if (!ctx || !evk_out || n_keys < 0 || (n_keys > 0 && (!galois_elts || !keys)))
@@ -1357,6 +1470,50 @@ int ctl_encrypt(ctl_ctx *ctx, const ctl_pk *pk, const int64_t *coeffs, uint64_t 
     CTL_TRY(upload_ints(ctx, st, h.data(), 4, nq, t4));
     launch_encrypt(ctx->hp.logn, pk->d_pk, t4, reinterpret_cast<u64 *>(ct_out), nq, ctx->tab, st);
     return check_launch();
+}
+
+int ctl_encrypt_sym(ctl_ctx *ctx, const ctl_sk *sk, const int64_t *coeffs, uint64_t seed, uint64_t *ct_out,
+                    void *stream) {
+    if (!ctx || !sk || !coeffs || !ct_out) return fail(CTL_EINVAL, "null argument");
+    CTL_SAME(ctx, sk, "the secret key");
+    CTL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    const int n = ctx->hp.n, nq = ctx->hp.nq;
+    std::vector<int64_t> em(n);
+    Stream(seed, TAG_SYM_E, 0).gaussian(ctx->hp.cdt, n, em.data());
+    for (int i = 0; i < n; ++i) {
+        if (coeffs[i] >= (int64_t)(1ull << 62) || coeffs[i] <= -(int64_t)(1ull << 62))
+            return fail(CTL_ESCALE, "plaintext coefficient out of range");
+        em[i] += coeffs[i];
+    }
+    std::vector<u64> a;
+    seeded_a(ctx, seed, a);
+    u64 *emn;
+    CTL_TRY(slot(ctx, S_COEF2, (size_t)nq * n, st, &emn));
+    CTL_TRY(upload_ints(ctx, st, em.data(), 1, nq, emn));
+    u64 *ct = reinterpret_cast<u64 *>(ct_out);
+    CTL_HIP(hipMemcpyAsync(ct + (size_t)nq * n, a.data(), (size_t)nq * n * 8, hipMemcpyHostToDevice, st));
+    launch_pk_body(ctx->hp.logn, ct, emn, sk->d_s, nq, ctx->tab, st);     // c0 = (e + m) - a s
+    CTL_TRY(check_launch());
+    CTL_HIP(hipStreamSynchronize(st));
+    return CTL_OK;
+}
+
+int ctl_expand_seeded(ctl_ctx *ctx, const uint64_t *c0, uint64_t seed, uint64_t *ct_out, void *stream) {
+    if (!ctx || !c0 || !ct_out) return fail(CTL_EINVAL, "null argument");
+    const int n = ctx->hp.n, nq = ctx->hp.nq;
+    for (int i = 0; i < nq; ++i)
+        for (int x = 0; x < n; ++x)
+            if (c0[(size_t)i * n + x] >= ctx->hp.mods[i]) return fail(CTL_EINVAL, "c0 word not reduced");
+    CTL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    std::vector<u64> a;
+    seeded_a(ctx, seed, a);
+    u64 *ct = reinterpret_cast<u64 *>(ct_out);
+    CTL_HIP(hipMemcpyAsync(ct, c0, (size_t)nq * n * 8, hipMemcpyHostToDevice, st));
+    CTL_HIP(hipMemcpyAsync(ct + (size_t)nq * n, a.data(), (size_t)nq * n * 8, hipMemcpyHostToDevice, st));
+    CTL_HIP(hipStreamSynchronize(st));
+    return CTL_OK;
 }
 
 int ctl_decrypt(ctl_ctx *ctx, const ctl_sk *sk, const uint64_t *ct, int k, uint64_t *residues_out, void *stream) {

@@ -67,7 +67,7 @@ u64 galois_elt(int logn, long r);
 
 // ChaCha20 stream (RFC 8439 block function) with the sampler conventions.
 enum : uint32_t { TAG_SK = 1, TAG_PK_A = 2, TAG_PK_E = 3, TAG_KS_A = 4, TAG_KS_E = 5,
-                  TAG_ENC_V = 8, TAG_ENC_E0 = 9, TAG_ENC_E1 = 10 };
+                  TAG_ENC_V = 8, TAG_ENC_E0 = 9, TAG_ENC_E1 = 10, TAG_SYM_A = 11, TAG_SYM_E = 12 };
 
 class Stream {
   public:

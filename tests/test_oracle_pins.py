@@ -439,3 +439,17 @@ def test_forward_lazy_giant_matches_fp64(name, tol_log2):
     out = o.forward(plan, ct, banks, keys, rlk)
     y = o.output_slots(plan, o.decrypt_decode(s, out, plan.scales[-1]))
     assert normwise_error(y, o.forward_fp64(ws, x)) < 2.0 ** tol_log2
+
+
+def test_seeded_symmetric_encryption():
+    """(-a s + e + m, a): decryption returns m + e exactly with |e| within the Gaussian's tail cut,
+    and c1 is the uniform stream of the seed (its first prime's row equals the sampler's output)."""
+    o = CKKSOracle(12, (40, 30, 30), 40, 30)
+    s = o.keygen_secret(5)
+    m = np.random.default_rng(1).integers(-2 ** 35, 2 ** 35, o.n)
+    ct = o.encrypt_sym(s, m, 99)
+    e = np.array([int(c) - int(x) for c, x in zip(o.compose(o.decrypt(s, ct)), m)])
+    assert np.max(np.abs(e)) <= 19 and 2.5 < e.std() < 4.0
+    assert np.array_equal(np.asarray(o.sample(99, 11, 0, 2, o.q[0], o.n), dtype=np.uint64), ct[1, 0])
+    assert np.array_equal(o.encrypt_sym(s, m, 99)[1], ct[1])          # c1 depends on the seed only
+    assert not np.array_equal(o.encrypt_sym(s, m, 100)[1], ct[1])
