@@ -912,6 +912,7 @@ int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
             ipw[e] = h_mulmod(ipw[e - 1], ipsi, q);
         }
         const bool fp = q < kFpPrimeLimit;
+        c->tab.host_fp[i] = fp ? 1 : 0;
         for (int m = 0; m < n; ++m) {
             unsigned r = 0;
             for (int b = 0; b < c->hp.logn; ++b) r |= ((m >> b) & 1u) << (c->hp.logn - 1 - b);

@@ -20,6 +20,7 @@ struct Tables {
     const u64 *tw, *tws, *itw, *itws;   // [np][N] each
     const PrimeConst *pc;               // [np]
     const CrossConst *cross;            // [kMaxMods][kMaxMods], entry [i * kMaxMods + j]
+    unsigned char host_fp[kMaxMods];    // host copy of pc[i].fp, for launch decisions
 };
 
 constexpr int kMaxKeysPerLaunch = 64;

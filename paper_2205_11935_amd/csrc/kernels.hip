@@ -112,12 +112,16 @@ __device__ __forceinline__ double fp_mul(double y, double w, double q, double qi
 __device__ __forceinline__ double fp_center(double v, double q, double qinv) {
     return __fma_rn(-rint(v * qinv), q, v);
 }
+// Integer-valued doubles in [0, 2^52) and u64 words below 2^52 convert through the bit pattern of
+// 2^52 + x, whose exponent is fixed: two instructions each way instead of a library conversion.
 __device__ __forceinline__ u64 fp_to_u64(double v, double q, double qinv) {
     double r = fp_center(v, q, qinv);
     r = r < 0.0 ? r + q : r;
-    return (u64)r;
+    return (u64)__double_as_longlong(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
 }
-__device__ __forceinline__ double u64_to_fp(u64 x) { return (double)x; }   // x < 2^53: exact
+__device__ __forceinline__ double u64_to_fp(u64 x) {      // x < 2^52
+    return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 4503599627370496.0;
+}
 
 // Index gathered by the automorphism X -> X^g in bit-reversed NTT order:
 // out[i] = in[brv((g (2 brv(i) + 1) mod 2N - 1) / 2)].
@@ -172,7 +176,9 @@ __device__ __forceinline__ void fwd_pass(u64 (&v)[16], int tid, const u64 *__res
     constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int hi = (g * Geo<LOGN>::T + tid) >> LO;
+        // for LO >= 6 the 64 lanes of a wave share hi: make that visible so twiddles use scalar loads
+        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane((g * Geo<LOGN>::T + tid) >> LO)
+                               : (g * Geo<LOGN>::T + tid) >> LO;
 #pragma unroll
         for (int sb = RB - 1; sb >= 0; --sb) {
             const int b = LO + sb, half = 1 << sb;
@@ -197,7 +203,9 @@ __device__ __forceinline__ void inv_pass(u64 (&v)[16], int tid, const u64 *__res
     constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int hi = (g * Geo<LOGN>::T + tid) >> LO;
+        // for LO >= 6 the 64 lanes of a wave share hi: make that visible so twiddles use scalar loads
+        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane((g * Geo<LOGN>::T + tid) >> LO)
+                               : (g * Geo<LOGN>::T + tid) >> LO;
 #pragma unroll
         for (int sb = 0; sb < RB; ++sb) {
             const int b = LO + sb, half = 1 << sb;
@@ -223,7 +231,9 @@ __device__ __forceinline__ void fwd_pass_fp(double (&v)[16], int tid, const doub
     constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int hi = (g * Geo<LOGN>::T + tid) >> LO;
+        // for LO >= 6 the 64 lanes of a wave share hi: make that visible so twiddles use scalar loads
+        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane((g * Geo<LOGN>::T + tid) >> LO)
+                               : (g * Geo<LOGN>::T + tid) >> LO;
 #pragma unroll
         for (int sb = RB - 1; sb >= 0; --sb) {
             const int b = LO + sb, half = 1 << sb;
@@ -249,7 +259,9 @@ __device__ __forceinline__ void inv_pass_fp(double (&v)[16], int tid, const doub
     constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int hi = (g * Geo<LOGN>::T + tid) >> LO;
+        // for LO >= 6 the 64 lanes of a wave share hi: make that visible so twiddles use scalar loads
+        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane((g * Geo<LOGN>::T + tid) >> LO)
+                               : (g * Geo<LOGN>::T + tid) >> LO;
 #pragma unroll
         for (int sb = 0; sb < RB; ++sb) {
             const int b = LO + sb, half = 1 << sb;
@@ -594,14 +606,19 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
 // Key inner product with the automorphism fused into the digit gather:
 //   out[b][r][0][t] = sum_j D[b][r][j][t][sigma_r] * key_r[j][0][t],  out[..][1][t] likewise with
 //   key_r[j][1][t]; t = 0..k (k = the special prime). D: digits + b db + r dr + (j (k+1) + t) N.
-// grid: x = N / 256 coefficient tiles, y = t, z = r. Each thread loops over the batch so a key
-// word is read from HBM once per launch.
+// One workgroup per (coefficient tile of 256, t, r); each thread loops over the batch so a key
+// word is read from HBM once per launch. Workgroups are dealt to the 8 XCDs in turn (id mod 8), so
+// the 1D grid is numbered such that all R rotations of one (tile, t) run back to back on the same
+// XCD: with hoisted digits (dr = 0) they read the same digit words, which its L2 then serves.
 template <int K>
 __global__ void __launch_bounds__(256)
 k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__restrict__ out,
         int B, int R, int nq, int logn, const PrimeConst *__restrict__ pcs) {
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    const int t = blockIdx.y, r = blockIdx.z;
+    const int id = blockIdx.x, xcd = id & 7, j = id >> 3;
+    const int r = j % R, pair = (j / R) * 8 + xcd;          // pair = tile * (K + 1) + t
+    if (pair >= (K + 1) << (logn - 8)) return;
+    const int n = (pair / (K + 1)) * 256 + threadIdx.x;
+    const int t = pair % (K + 1);
     const int N = 1 << logn, np = nq + 1;
     const int pt = t < K ? t : nq;
     const PrimeConst p = pcs[pt];
@@ -664,14 +681,17 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
 // grid: x = N / 64 tiles, y = prime i, z = ceil(B / blockDim.y).
 constexpr int kMacJB = 4;
 
+// The FP64 and integer forms are separate kernels launched over their own primes (PrimeList,
+// grid y), so that the FP64 one is not held to the register budget of 128-bit accumulators.
 template <int KC>
 __global__ void __launch_bounds__(512)
-k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__restrict__ bank,
-      u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn, const PrimeConst *__restrict__ pcs) {
-    __shared__ u64 wt[kMacJB * KC * 64];
+k_mac_fp(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__restrict__ bank,
+         u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn, PrimeList pl,
+         const PrimeConst *__restrict__ pcs) {
+    __shared__ double wd[kMacJB * KC * 64];
     const int nl = threadIdx.x, bl = threadIdx.y;
     const int tid = bl * 64 + nl, nthr = 64 * blockDim.y;
-    const int i = blockIdx.y;
+    const int i = pl.idx[blockIdx.y];
     const long N = 1L << logn, kn = (long)k * N;
     const long n0 = (long)blockIdx.x * 64;
     const int b = blockIdx.z * blockDim.y + bl;
@@ -679,56 +699,69 @@ k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__rest
     const PrimeConst p = pcs[i];
     const u64 *ct_b = ct + (long)(live ? b : 0) * 2 * kn + i * N + n0 + nl;
     const u64 *rot_b = rot + (long)(live ? b : 0) * (t1 - 1) * 2 * kn + i * N + n0 + nl;
-    if (p.fp) {
-        // FP64 products (prime < 2^41); the staged plaintext words are converted once, in LDS
-        double *wd = reinterpret_cast<double *>(wt);
-        for (int kc0 = 0; kc0 < t2; kc0 += KC) {
-            double acc[KC][2];
+    for (int kc0 = 0; kc0 < t2; kc0 += KC) {
+        double acc[KC][2];
 #pragma unroll
-            for (int kk = 0; kk < KC; ++kk) acc[kk][0] = acc[kk][1] = 0.0;
-            for (int j0 = 0; j0 < t1; j0 += kMacJB) {
-                const int jn = t1 - j0 < kMacJB ? t1 - j0 : kMacJB;
-                double x[kMacJB][2];
+        for (int kk = 0; kk < KC; ++kk) acc[kk][0] = acc[kk][1] = 0.0;
+        for (int j0 = 0; j0 < t1; j0 += kMacJB) {
+            const int jn = t1 - j0 < kMacJB ? t1 - j0 : kMacJB;
+            double x[kMacJB][2];
 #pragma unroll
-                for (int jj = 0; jj < kMacJB; ++jj) {
-                    const int j = j0 + jj;
-                    if (live && jj < jn) {
-                        const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
-                        x[jj][0] = u64_to_fp(src[0]);
-                        x[jj][1] = u64_to_fp(src[kn]);
-                    } else {
-                        x[jj][0] = x[jj][1] = 0.0;
-                    }
-                }
-                __syncthreads();
-                for (int e = tid; e < jn * KC * 64; e += nthr) {
-                    const int jj = e / (KC * 64), kk = (e / 64) % KC;
-                    wd[e] = u64_to_fp(bank[((long)(kc0 + kk) * t1 + j0 + jj) * kn + i * N + n0 + (e & 63)]);
-                }
-                __syncthreads();
-#pragma unroll
-                for (int jj = 0; jj < kMacJB; ++jj) {
-                    if (jj < jn) {
-#pragma unroll
-                        for (int kk = 0; kk < KC; ++kk) {
-                            const double w = wd[(jj * KC + kk) * 64 + nl];
-                            acc[kk][0] += fp_mul(x[jj][0], w, p.qd, p.qinv);
-                            acc[kk][1] += fp_mul(x[jj][1], w, p.qd, p.qinv);
-                        }
-                    }
+            for (int jj = 0; jj < kMacJB; ++jj) {
+                const int j = j0 + jj;
+                if (live && jj < jn) {
+                    const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
+                    x[jj][0] = u64_to_fp(src[0]);
+                    x[jj][1] = u64_to_fp(src[kn]);
+                } else {
+                    x[jj][0] = x[jj][1] = 0.0;
                 }
             }
-            if (live) {
+            __syncthreads();
+            for (int e = tid; e < jn * KC * 64; e += nthr) {
+                const int jj = e / (KC * 64), kk = (e / 64) % KC;
+                wd[e] = u64_to_fp(bank[((long)(kc0 + kk) * t1 + j0 + jj) * kn + i * N + n0 + (e & 63)]);
+            }
+            __syncthreads();
 #pragma unroll
-                for (int kk = 0; kk < KC; ++kk) {
-                    u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
-                    o[0] = fp_to_u64(acc[kk][0], p.qd, p.qinv);
-                    o[kn] = fp_to_u64(acc[kk][1], p.qd, p.qinv);
+            for (int jj = 0; jj < kMacJB; ++jj) {
+                if (jj < jn) {
+#pragma unroll
+                    for (int kk = 0; kk < KC; ++kk) {
+                        const double w = wd[(jj * KC + kk) * 64 + nl];
+                        acc[kk][0] += fp_mul(x[jj][0], w, p.qd, p.qinv);
+                        acc[kk][1] += fp_mul(x[jj][1], w, p.qd, p.qinv);
+                    }
                 }
             }
         }
-        return;
+        if (live) {
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
+                o[0] = fp_to_u64(acc[kk][0], p.qd, p.qinv);
+                o[kn] = fp_to_u64(acc[kk][1], p.qd, p.qinv);
+            }
+        }
     }
+}
+
+template <int KC>
+__global__ void __launch_bounds__(512)
+k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__restrict__ bank,
+      u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn, PrimeList pl,
+      const PrimeConst *__restrict__ pcs) {
+    __shared__ u64 wt[kMacJB * KC * 64];
+    const int nl = threadIdx.x, bl = threadIdx.y;
+    const int tid = bl * 64 + nl, nthr = 64 * blockDim.y;
+    const int i = pl.idx[blockIdx.y];
+    const long N = 1L << logn, kn = (long)k * N;
+    const long n0 = (long)blockIdx.x * 64;
+    const int b = blockIdx.z * blockDim.y + bl;
+    const bool live = b < B;
+    const PrimeConst p = pcs[i];
+    const u64 *ct_b = ct + (long)(live ? b : 0) * 2 * kn + i * N + n0 + nl;
+    const u64 *rot_b = rot + (long)(live ? b : 0) * (t1 - 1) * 2 * kn + i * N + n0 + nl;
     for (int kc0 = 0; kc0 < t2; kc0 += KC) {
         Acc acc[KC][2];
 #pragma unroll
@@ -993,7 +1026,8 @@ void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const Pr
 void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
                   u64 *out, int B, int nq, const Tables &tab, hipStream_t st) {
     if (R <= 0 || B <= 0) return;
-    const dim3 grid((1u << logn) / 256, k + 1, R), blk(256);
+    const int pairs = (k + 1) << (logn - 8);
+    const dim3 grid((unsigned)(((pairs + 7) / 8) * 8 * R)), blk(256);
     switch (k) {
 #define CTL_KIP(K) case K: hipLaunchKernelGGL(k_keyip<K>, grid, blk, 0, st, digits, db, dr, keys, out, B, R, nq, logn, tab.pc); break;
         CTL_KIP(1) CTL_KIP(2) CTL_KIP(3) CTL_KIP(4) CTL_KIP(5) CTL_KIP(6) CTL_KIP(7) CTL_KIP(8)
@@ -1013,12 +1047,29 @@ static int mac_chunk(int t2) {
 void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *inner, int B, int k,
                 int t1, int t2, const Tables &tab, hipStream_t st) {
     const int by = B < 8 ? B : 8;
-    const dim3 grid((1u << logn) / 64, k, (B + by - 1) / by), blk(64, by);
-    switch (mac_chunk(t2)) {
-#define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac<KC>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
-        CTL_MAC(16) CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
-        default: hipLaunchKernelGGL(k_mac<1>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
+    PrimeList fp{}, in{};
+    for (int i = 0; i < k; ++i) {
+        if (tab.host_fp[i]) fp.idx[fp.n++] = i;
+        else in.idx[in.n++] = i;
+    }
+    const int kc = mac_chunk(t2);
+    if (fp.n) {
+        const dim3 grid((1u << logn) / 64, fp.n, (B + by - 1) / by), blk(64, by);
+        switch (kc) {
+#define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac_fp<KC>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, fp, tab.pc); break;
+            CTL_MAC(16) CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
+            default: hipLaunchKernelGGL(k_mac_fp<1>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, fp, tab.pc); break;
 #undef CTL_MAC
+        }
+    }
+    if (in.n) {
+        const dim3 grid((1u << logn) / 64, in.n, (B + by - 1) / by), blk(64, by);
+        switch (kc) {
+#define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac<KC>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, in, tab.pc); break;
+            CTL_MAC(16) CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
+            default: hipLaunchKernelGGL(k_mac<1>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, in, tab.pc); break;
+#undef CTL_MAC
+        }
     }
 }
 
