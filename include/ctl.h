@@ -97,6 +97,22 @@ int ctl_ctx_free(ctl_ctx *ctx);
 /* primes_out: host array of n_q + 1 entries (q_0..q_{n_q-1}, P); *n_out = n_q + 1. */
 int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
 
+/* Launch knobs an autotuner may set per context. They change which kernels run and how their
+ * work is divided, never the results (every choice computes the same residues):
+ *   CTL_KNOB_MAC_CHUNK   largest number of giant-step accumulators a MAC thread keeps (1..16,
+ *                        default 16; the chunk used is the largest of 16, 12, 8, 6, 4, 3, 2, 1
+ *                        that divides t2 and does not exceed this cap);
+ *   CTL_KNOB_MAC_CTS     ciphertexts per MAC workgroup, sharing its staged plaintexts (1..8,
+ *                        default 8);
+ *   CTL_KNOB_KEYIP_XCD   1 (default): key-product workgroups numbered so that all rotations of a
+ *                        digit tile run on one XCD; 0: tiles first.
+ * Out-of-range values give CTL_EINVAL and leave the knob unchanged. */
+#define CTL_KNOB_MAC_CHUNK 0
+#define CTL_KNOB_MAC_CTS 1
+#define CTL_KNOB_KEYIP_XCD 2
+int ctl_knob_set(ctl_ctx *ctx, int knob, int value);
+int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value);
+
 /* Optional device allocator for the context's workspace and the key and model banks (for example
  * the framework's caching allocator). alloc returns a device pointer of at least `bytes` bytes
  * usable on `stream`, or NULL. Without a hook the library uses hipMalloc / hipFree. Install it

@@ -21,6 +21,10 @@ CTL_ACT_NONE = 0
 CTL_ACT_SQUARE = 1
 CTL_ACT_POLY3 = 2
 CTL_LAYER_LAZY_GIANT = 1
+CTL_KNOB_MAC_CHUNK = 0
+CTL_KNOB_MAC_CTS = 1
+CTL_KNOB_KEYIP_XCD = 2
+KNOBS = {"mac_chunk": CTL_KNOB_MAC_CHUNK, "mac_cts": CTL_KNOB_MAC_CTS, "keyip_xcd": CTL_KNOB_KEYIP_XCD}
 CTL_LAYER_DENSE = 0
 CTL_LAYER_CONV1D = 1
 CTL_LAYER_AVGPOOL = 2
@@ -131,6 +135,8 @@ _SIGS = {
                                          ctypes.POINTER(f64p), ctypes.POINTER(i64p), ctypes.POINTER(_ModelOpts),
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "ctl_workspace_freeze": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "ctl_knob_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "ctl_knob_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "ctl_model_free": (ctypes.c_int, [ctypes.c_void_p]),
     "ctl_model_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_ModelInfo)]),
     "ctl_model_rotations": (ctypes.c_int, [ctypes.c_void_p, i32p, ctypes.POINTER(ctypes.c_int)]),
@@ -525,6 +531,14 @@ class Context:
         _check(lib().ctl_model_load_ex(self.handle, self._descs(layers, lazy), len(layers), wp, pp,
                                        ctypes.byref(opts), ctypes.byref(h)))
         return Model(self, h)
+
+    def knob(self, name: str, value: Optional[int] = None) -> int:
+        """Read (value None) or set a launch knob ("mac_chunk", "mac_cts", "keyip_xcd")."""
+        if value is not None:
+            _check(lib().ctl_knob_set(self.handle, KNOBS[name], int(value)))
+        v = ctypes.c_int()
+        _check(lib().ctl_knob_get(self.handle, KNOBS[name], ctypes.byref(v)))
+        return v.value
 
     def workspace_freeze(self, frozen: bool = True):
         _check(lib().ctl_workspace_freeze(self.handle, int(frozen)))

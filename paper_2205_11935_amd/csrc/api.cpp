@@ -63,6 +63,7 @@ struct ctl_ctx {
     std::unique_ptr<Encoder> enc;
     std::vector<PrimeConst> pc;
     bool ws_frozen = false;
+    Knobs knobs;
     // launch instrumentation
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;      // pairs (start, stop)
@@ -271,7 +272,7 @@ int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
         kl.gal[r] = gal[r];
     }
     const long dsz = (long)k * (k + 1) * N;
-    { CTL_PROF(F_KEYIP, 2.0 * B * R * (k + 1) * k * N, fp_share_range(c, k, true)); launch_keyip(logn, k, dig, hoisted ? dsz : (long)R * dsz, hoisted ? 0 : dsz, kl, R, U, B, nq, c->tab, st); }
+    { CTL_PROF(F_KEYIP, 2.0 * B * R * (k + 1) * k * N, fp_share_range(c, k, true)); launch_keyip(logn, k, dig, hoisted ? dsz : (long)R * dsz, hoisted ? 0 : dsz, kl, R, U, B, nq, c->tab, c->knobs, st); }
     *U_out = U;
     return check_launch();
 }
@@ -501,7 +502,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
         CTL_TRY(keyswitch_batch(c, st, k, B, R1, in, c1_map(k), true, keys1.data(), gal1.data(), add, rot));
     }
     // inner_k2 = sum_j diag'_{k2 t1 + j} * rot_j(ct)
-    { CTL_PROF(F_MAC, 2.0 * B * k * t1 * t2 * N, fp_share_range(c, k, false)); launch_mac(logn, in, rot, m->banks[li], inner, B, k, t1, t2, c->tab, st); }
+    { CTL_PROF(F_MAC, 2.0 * B * k * t1 * t2 * N, fp_share_range(c, k, false)); launch_mac(logn, in, rot, m->banks[li], inner, B, k, t1, t2, c->tab, c->knobs, st); }
     CTL_TRY(check_launch());
     const u64 *sum = inner;
     if (R2 > 0 && L.lazy) {
@@ -1010,6 +1011,36 @@ int ctl_workspace_freeze(ctl_ctx *ctx, int frozen) {
     if (!ctx) return fail(CTL_EINVAL, "null context");
     ctx->ws_frozen = frozen != 0;
     return CTL_OK;
+}
+
+int ctl_knob_set(ctl_ctx *ctx, int knob, int value) {
+    if (!ctx) return fail(CTL_EINVAL, "null context");
+    switch (knob) {
+        case CTL_KNOB_MAC_CHUNK:
+            if (value < 1 || value > 16) return fail(CTL_EINVAL, "MAC chunk cap must lie in 1..16");
+            ctx->knobs.mac_chunk_cap = value;
+            return CTL_OK;
+        case CTL_KNOB_MAC_CTS:
+            if (value < 1 || value > 8) return fail(CTL_EINVAL, "ciphertexts per MAC workgroup must lie in 1..8");
+            ctx->knobs.mac_cts = value;
+            return CTL_OK;
+        case CTL_KNOB_KEYIP_XCD:
+            if (value != 0 && value != 1) return fail(CTL_EINVAL, "key-product numbering is 0 or 1");
+            ctx->knobs.keyip_xcd = value;
+            return CTL_OK;
+        default:
+            return fail(CTL_EINVAL, "unknown knob");
+    }
+}
+
+int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value) {
+    if (!ctx || !value) return fail(CTL_EINVAL, "null argument");
+    switch (knob) {
+        case CTL_KNOB_MAC_CHUNK: *value = ctx->knobs.mac_chunk_cap; return CTL_OK;
+        case CTL_KNOB_MAC_CTS: *value = ctx->knobs.mac_cts; return CTL_OK;
+        case CTL_KNOB_KEYIP_XCD: *value = ctx->knobs.keyip_xcd; return CTL_OK;
+        default: return fail(CTL_EINVAL, "unknown knob");
+    }
 }
 
 int ctl_workspace_bytes(const ctl_ctx *ctx, uint64_t *bytes_out) {

@@ -59,10 +59,17 @@ void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, 
                  const DropAdd &add, const Tables &tab, hipStream_t st);
 void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,
                     const Tables &tab, hipStream_t st);
+// Launch choices an autotuner may set (defaults in brackets): the largest giant-step chunk of the
+// MAC [16], ciphertexts per MAC workgroup [8], XCD-grouped key-product numbering [1].
+struct Knobs {
+    int mac_chunk_cap = 16;
+    int mac_cts = 8;
+    int keyip_xcd = 1;
+};
 void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
-                  u64 *out, int B, int nq, const Tables &tab, hipStream_t st);
+                  u64 *out, int B, int nq, const Tables &tab, const Knobs &kn, hipStream_t st);
 void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *inner, int B, int k,
-                int t1, int t2, const Tables &tab, hipStream_t st);
+                int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st);
 void launch_add_terms(int logn, const u64 *a, long a_sb, const u64 *terms, long t_sb, long t_ss, int S,
                       u64 *out, int B, int k, const Tables &tab, hipStream_t st);
 void launch_tensor(int logn, const u64 *a, const u64 *b, u64 *out, int B, int k, const Tables &tab, hipStream_t st);

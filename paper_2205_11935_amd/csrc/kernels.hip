@@ -607,16 +607,26 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
 //   out[b][r][0][t] = sum_j D[b][r][j][t][sigma_r] * key_r[j][0][t],  out[..][1][t] likewise with
 //   key_r[j][1][t]; t = 0..k (k = the special prime). D: digits + b db + r dr + (j (k+1) + t) N.
 // One workgroup per (coefficient tile of 256, t, r); each thread loops over the batch so a key
-// word is read from HBM once per launch. Workgroups are dealt to the 8 XCDs in turn (id mod 8), so
-// the 1D grid is numbered such that all R rotations of one (tile, t) run back to back on the same
-// XCD: with hoisted digits (dr = 0) they read the same digit words, which its L2 then serves.
+// word is read from HBM once per launch. Workgroups are dealt to the 8 XCDs in turn (id mod 8); with
+// xcd set the 1D grid is numbered such that all R rotations of one (tile, t) run back to back on
+// the same XCD (with hoisted digits, dr = 0, they read the same digit words, which its L2 serves);
+// otherwise tiles vary fastest, then t, then r.
 template <int K>
 __global__ void __launch_bounds__(256)
 k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__restrict__ out,
-        int B, int R, int nq, int logn, const PrimeConst *__restrict__ pcs) {
-    const int id = blockIdx.x, xcd = id & 7, j = id >> 3;
-    const int r = j % R, pair = (j / R) * 8 + xcd;          // pair = tile * (K + 1) + t
-    if (pair >= (K + 1) << (logn - 8)) return;
+        int B, int R, int nq, int logn, int xcd_order, const PrimeConst *__restrict__ pcs) {
+    const int pairs = (K + 1) << (logn - 8);
+    int r, pair;
+    if (xcd_order) {
+        const int id = blockIdx.x, xcd = id & 7, j = id >> 3;
+        r = j % R;
+        pair = (j / R) * 8 + xcd;                            // pair = tile * (K + 1) + t
+    } else {
+        const int tiles = 1 << (logn - 8), id = blockIdx.x;
+        r = id / pairs;
+        pair = (id % tiles) * (K + 1) + (id / tiles) % (K + 1);
+    }
+    if (pair >= pairs || r >= R) return;
     const int n = (pair / (K + 1)) * 256 + threadIdx.x;
     const int t = pair % (K + 1);
     const int N = 1 << logn, np = nq + 1;
@@ -1024,35 +1034,37 @@ void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const Pr
 }
 
 void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
-                  u64 *out, int B, int nq, const Tables &tab, hipStream_t st) {
+                  u64 *out, int B, int nq, const Tables &tab, const Knobs &kn, hipStream_t st) {
     if (R <= 0 || B <= 0) return;
     const int pairs = (k + 1) << (logn - 8);
-    const dim3 grid((unsigned)(((pairs + 7) / 8) * 8 * R)), blk(256);
+    const int xo = kn.keyip_xcd ? 1 : 0;
+    const dim3 grid((unsigned)(xo ? ((pairs + 7) / 8) * 8 * R : pairs * R)), blk(256);
     switch (k) {
-#define CTL_KIP(K) case K: hipLaunchKernelGGL(k_keyip<K>, grid, blk, 0, st, digits, db, dr, keys, out, B, R, nq, logn, tab.pc); break;
+#define CTL_KIP(K) case K: hipLaunchKernelGGL(k_keyip<K>, grid, blk, 0, st, digits, db, dr, keys, out, B, R, nq, logn, xo, tab.pc); break;
         CTL_KIP(1) CTL_KIP(2) CTL_KIP(3) CTL_KIP(4) CTL_KIP(5) CTL_KIP(6) CTL_KIP(7) CTL_KIP(8)
 #undef CTL_KIP
         default: break;
     }
 }
 
-// Largest supported giant-step chunk that divides t2.
-static int mac_chunk(int t2) {
+// Largest supported giant-step chunk that divides t2 and does not exceed cap.
+static int mac_chunk(int t2, int cap) {
     static const int opts[] = {16, 12, 8, 6, 4, 3, 2, 1};   // wider chunks spill registers
     for (int c : opts)
-        if (t2 % c == 0) return c;
+        if (c <= cap && t2 % c == 0) return c;
     return 1;
 }
 
 void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *inner, int B, int k,
-                int t1, int t2, const Tables &tab, hipStream_t st) {
-    const int by = B < 8 ? B : 8;
+                int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st) {
+    const int cts = kn.mac_cts < 1 ? 1 : kn.mac_cts > 8 ? 8 : kn.mac_cts;
+    const int by = B < cts ? B : cts;
     PrimeList fp{}, in{};
     for (int i = 0; i < k; ++i) {
         if (tab.host_fp[i]) fp.idx[fp.n++] = i;
         else in.idx[in.n++] = i;
     }
-    const int kc = mac_chunk(t2);
+    const int kc = mac_chunk(t2, kn.mac_chunk_cap);
     if (fp.n) {
         const dim3 grid((1u << logn) / 64, fp.n, (B + by - 1) / by), blk(64, by);
         switch (kc) {
