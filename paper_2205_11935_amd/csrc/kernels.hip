@@ -643,6 +643,8 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
             kb[j] = u64_to_fp(key[((long)(j * 2 + 0) * np + pt) * N + n]);
             ka[j] = u64_to_fp(key[((long)(j * 2 + 1) * np + pt) * N + n]);
         }
+        // four ciphertexts per unrolled step keep their digit loads in flight together
+#pragma unroll 4
         for (int b = 0; b < B; ++b) {
             const u64 *d = digits + b * db + r * dr + (long)t * N + src;
             double a0 = 0.0, a1 = 0.0;
@@ -664,6 +666,7 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
         kb[j] = key[((long)(j * 2 + 0) * np + pt) * N + n];
         ka[j] = key[((long)(j * 2 + 1) * np + pt) * N + n];
     }
+#pragma unroll 4
     for (int b = 0; b < B; ++b) {
         const u64 *d = digits + b * db + r * dr + (long)t * N + src;
         Acc a0, a1;
