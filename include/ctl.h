@@ -105,11 +105,15 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
  *   CTL_KNOB_MAC_CTS     ciphertexts per MAC workgroup, sharing its staged plaintexts (1..8,
  *                        default 8);
  *   CTL_KNOB_KEYIP_XCD   1 (default): key-product workgroups numbered so that all rotations of a
- *                        digit tile run on one XCD; 0: tiles first.
+ *                        digit tile run on one XCD; 0: tiles first;
+ *   CTL_KNOB_MAC_DIRECT  largest batch whose MAC reads plaintext words directly instead of staging
+ *                        them in LDS for the workgroup's ciphertexts (0..64, default 3: at N = 2^14
+ *                        the direct form is faster up to 3 ciphertexts, the staged one from 4).
  * Out-of-range values give CTL_EINVAL and leave the knob unchanged. */
 #define CTL_KNOB_MAC_CHUNK 0
 #define CTL_KNOB_MAC_CTS 1
 #define CTL_KNOB_KEYIP_XCD 2
+#define CTL_KNOB_MAC_DIRECT 3
 int ctl_knob_set(ctl_ctx *ctx, int knob, int value);
 int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value);
 

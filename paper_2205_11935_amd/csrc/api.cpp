@@ -1028,6 +1028,10 @@ int ctl_knob_set(ctl_ctx *ctx, int knob, int value) {
             if (value != 0 && value != 1) return fail(CTL_EINVAL, "key-product numbering is 0 or 1");
             ctx->knobs.keyip_xcd = value;
             return CTL_OK;
+        case CTL_KNOB_MAC_DIRECT:
+            if (value < 0 || value > 64) return fail(CTL_EINVAL, "direct-MAC batch limit must lie in 0..64");
+            ctx->knobs.mac_direct_max = value;
+            return CTL_OK;
         default:
             return fail(CTL_EINVAL, "unknown knob");
     }
@@ -1039,6 +1043,7 @@ int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value) {
         case CTL_KNOB_MAC_CHUNK: *value = ctx->knobs.mac_chunk_cap; return CTL_OK;
         case CTL_KNOB_MAC_CTS: *value = ctx->knobs.mac_cts; return CTL_OK;
         case CTL_KNOB_KEYIP_XCD: *value = ctx->knobs.keyip_xcd; return CTL_OK;
+        case CTL_KNOB_MAC_DIRECT: *value = ctx->knobs.mac_direct_max; return CTL_OK;
         default: return fail(CTL_EINVAL, "unknown knob");
     }
 }

@@ -60,11 +60,13 @@ void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, 
 void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,
                     const Tables &tab, hipStream_t st);
 // Launch choices an autotuner may set (defaults in brackets): the largest giant-step chunk of the
-// MAC [16], ciphertexts per MAC workgroup [8], XCD-grouped key-product numbering [1].
+// MAC [16], ciphertexts per MAC workgroup [8], XCD-grouped key-product numbering [1], largest
+// batch that uses the unstaged MAC [3].
 struct Knobs {
     int mac_chunk_cap = 16;
     int mac_cts = 8;
     int keyip_xcd = 1;
+    int mac_direct_max = 3;      // batches up to this size use the unstaged MAC
 };
 void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
                   u64 *out, int B, int nq, const Tables &tab, const Knobs &kn, hipStream_t st);

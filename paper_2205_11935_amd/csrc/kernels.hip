@@ -688,10 +688,11 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
 // with rot_0 = ct itself (ct: [B][2][K][N]) and rot_j, j >= 1, in rot: [B][t1-1][2][K][N].
 // Per coefficient this is a (t2 x t1) by (t1 x 2B) modular matrix product. A workgroup covers 64
 // consecutive coefficients of one prime for up to 8 ciphertexts (threadIdx.y); each thread keeps
-// KC giant-step accumulators (128-bit) per polynomial, so every rotated ciphertext word is read
-// once per KC-chunk. The plaintext words of JB baby steps are staged in LDS per barrier pair and
-// shared by the workgroup's ciphertexts; the ciphertext words of those JB steps are loaded first.
-// grid: x = N / 64 tiles, y = prime i, z = ceil(B / blockDim.y).
+// KC giant-step accumulators per polynomial, so every rotated ciphertext word is read once per
+// KC-chunk. The plaintext words of JB baby steps are staged in LDS per barrier pair and shared by
+// the workgroup's ciphertexts; the ciphertext words of those JB steps are loaded first.
+// grid: x = N / 64 tiles, y = prime (from a PrimeList), z = ceil(B / blockDim.y) ciphertext
+// groups times t2 / KC chunks (a grid dimension, so that small batches still fill the GPU).
 constexpr int kMacJB = 4;
 
 // The FP64 and integer forms are separate kernels launched over their own primes (PrimeList,
@@ -707,12 +708,14 @@ k_mac_fp(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__r
     const int i = pl.idx[blockIdx.y];
     const long N = 1L << logn, kn = (long)k * N;
     const long n0 = (long)blockIdx.x * 64;
-    const int b = blockIdx.z * blockDim.y + bl;
+    const int nbz = (B + blockDim.y - 1) / blockDim.y;   // grid z = ciphertext groups x KC-chunks
+    const int b = (blockIdx.z % nbz) * blockDim.y + bl;
+    const int kc0 = (blockIdx.z / nbz) * KC;
     const bool live = b < B;
     const PrimeConst p = pcs[i];
     const u64 *ct_b = ct + (long)(live ? b : 0) * 2 * kn + i * N + n0 + nl;
     const u64 *rot_b = rot + (long)(live ? b : 0) * (t1 - 1) * 2 * kn + i * N + n0 + nl;
-    for (int kc0 = 0; kc0 < t2; kc0 += KC) {
+    {
         double acc[KC][2];
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) acc[kk][0] = acc[kk][1] = 0.0;
@@ -770,12 +773,14 @@ k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__rest
     const int i = pl.idx[blockIdx.y];
     const long N = 1L << logn, kn = (long)k * N;
     const long n0 = (long)blockIdx.x * 64;
-    const int b = blockIdx.z * blockDim.y + bl;
+    const int nbz = (B + blockDim.y - 1) / blockDim.y;   // grid z = ciphertext groups x KC-chunks
+    const int b = (blockIdx.z % nbz) * blockDim.y + bl;
+    const int kc0 = (blockIdx.z / nbz) * KC;
     const bool live = b < B;
     const PrimeConst p = pcs[i];
     const u64 *ct_b = ct + (long)(live ? b : 0) * 2 * kn + i * N + n0 + nl;
     const u64 *rot_b = rot + (long)(live ? b : 0) * (t1 - 1) * 2 * kn + i * N + n0 + nl;
-    for (int kc0 = 0; kc0 < t2; kc0 += KC) {
+    {
         Acc acc[KC][2];
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) { acc_zero(acc[kk][0]); acc_zero(acc[kk][1]); }
@@ -819,6 +824,65 @@ k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__rest
                 o[kn] = acc_reduce(acc[kk][1], p);
             }
         }
+    }
+}
+
+// The same MAC for batches of one or two ciphertexts: there is nothing to share a staged plaintext
+// word with, so each thread reads its plaintext words straight from memory (coalesced across the
+// coefficients of a wave), with no LDS and no barriers, and FP64 and integer primes go in one
+// launch (the branch is uniform per workgroup). grid: x = N / 64 tiles, y = prime, z = B t2 / KC.
+template <int KC>
+__global__ void __launch_bounds__(64)
+k_mac_direct(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__restrict__ bank,
+             u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn, const PrimeConst *__restrict__ pcs) {
+    const int nl = threadIdx.x, i = blockIdx.y;
+    const long N = 1L << logn, kn = (long)k * N;
+    const long n0 = (long)blockIdx.x * 64;
+    const int b = blockIdx.z % B, kc0 = (blockIdx.z / B) * KC;
+    const PrimeConst p = pcs[i];
+    const u64 *ct_b = ct + (long)b * 2 * kn + i * N + n0 + nl;
+    const u64 *rot_b = rot + (long)b * (t1 - 1) * 2 * kn + i * N + n0 + nl;
+    const u64 *bk = bank + i * N + n0 + nl;
+    if (p.fp) {
+        double acc[KC][2];
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) acc[kk][0] = acc[kk][1] = 0.0;
+        for (int j = 0; j < t1; ++j) {
+            const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
+            const double x0 = u64_to_fp(src[0]), x1 = u64_to_fp(src[kn]);
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const double w = u64_to_fp(bk[((long)(kc0 + kk) * t1 + j) * kn]);
+                acc[kk][0] += fp_mul(x0, w, p.qd, p.qinv);
+                acc[kk][1] += fp_mul(x1, w, p.qd, p.qinv);
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
+            o[0] = fp_to_u64(acc[kk][0], p.qd, p.qinv);
+            o[kn] = fp_to_u64(acc[kk][1], p.qd, p.qinv);
+        }
+        return;
+    }
+    Acc acc[KC][2];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) { acc_zero(acc[kk][0]); acc_zero(acc[kk][1]); }
+    for (int j = 0; j < t1; ++j) {
+        const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
+        const u64 x0 = src[0], x1 = src[kn];
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const u64 w = bk[((long)(kc0 + kk) * t1 + j) * kn];
+            acc_mac(acc[kk][0], w, x0);
+            acc_mac(acc[kk][1], w, x1);
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
+        o[0] = acc_reduce(acc[kk][0], p);
+        o[kn] = acc_reduce(acc[kk][1], p);
     }
 }
 
@@ -1068,8 +1132,19 @@ void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *i
         else in.idx[in.n++] = i;
     }
     const int kc = mac_chunk(t2, kn.mac_chunk_cap);
+    if (B <= kn.mac_direct_max) {
+        const int kd = mac_chunk(t2, 4);        // few accumulators: more workgroups for one ciphertext
+        const dim3 grid((1u << logn) / 64, k, B * (t2 / kd)), blk(64);
+        switch (kd) {
+            case 4: hipLaunchKernelGGL(k_mac_direct<4>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
+            case 3: hipLaunchKernelGGL(k_mac_direct<3>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
+            case 2: hipLaunchKernelGGL(k_mac_direct<2>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
+            default: hipLaunchKernelGGL(k_mac_direct<1>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
+        }
+        return;
+    }
     if (fp.n) {
-        const dim3 grid((1u << logn) / 64, fp.n, (B + by - 1) / by), blk(64, by);
+        const dim3 grid((1u << logn) / 64, fp.n, ((B + by - 1) / by) * (t2 / kc)), blk(64, by);
         switch (kc) {
 #define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac_fp<KC>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, fp, tab.pc); break;
             CTL_MAC(16) CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
@@ -1078,7 +1153,7 @@ void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *i
         }
     }
     if (in.n) {
-        const dim3 grid((1u << logn) / 64, in.n, (B + by - 1) / by), blk(64, by);
+        const dim3 grid((1u << logn) / 64, in.n, ((B + by - 1) / by) * (t2 / kc)), blk(64, by);
         switch (kc) {
 #define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac<KC>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, in, tab.pc); break;
             CTL_MAC(16) CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
