@@ -108,12 +108,16 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
  *                        digit tile run on one XCD; 0: tiles first;
  *   CTL_KNOB_MAC_DIRECT  largest batch whose MAC reads plaintext words directly instead of staging
  *                        them in LDS for the workgroup's ciphertexts (0..64, default 3: at N = 2^14
- *                        the direct form is faster up to 3 ciphertexts, the staged one from 4).
+ *                        the direct form is faster up to 3 ciphertexts, the staged one from 4);
+ *   CTL_KNOB_NTT_XCD     1: ModUp workgroups numbered so that the targets of one digit, and ModDown
+ *                        workgroups so that the primes of one group, run on one XCD and share its
+ *                        L2; 0 (default): plain order (measured slightly faster at N = 2^14).
  * Out-of-range values give CTL_EINVAL and leave the knob unchanged. */
 #define CTL_KNOB_MAC_CHUNK 0
 #define CTL_KNOB_MAC_CTS 1
 #define CTL_KNOB_KEYIP_XCD 2
 #define CTL_KNOB_MAC_DIRECT 3
+#define CTL_KNOB_NTT_XCD 4
 int ctl_knob_set(ctl_ctx *ctx, int knob, int value);
 int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value);
 

@@ -25,8 +25,9 @@ CTL_KNOB_MAC_CHUNK = 0
 CTL_KNOB_MAC_CTS = 1
 CTL_KNOB_KEYIP_XCD = 2
 CTL_KNOB_MAC_DIRECT = 3
+CTL_KNOB_NTT_XCD = 4
 KNOBS = {"mac_chunk": CTL_KNOB_MAC_CHUNK, "mac_cts": CTL_KNOB_MAC_CTS, "keyip_xcd": CTL_KNOB_KEYIP_XCD,
-         "mac_direct": CTL_KNOB_MAC_DIRECT}
+         "mac_direct": CTL_KNOB_MAC_DIRECT, "ntt_xcd": CTL_KNOB_NTT_XCD}
 CTL_LAYER_DENSE = 0
 CTL_LAYER_CONV1D = 1
 CTL_LAYER_AVGPOOL = 2
@@ -535,7 +536,7 @@ class Context:
         return Model(self, h)
 
     def knob(self, name: str, value: Optional[int] = None) -> int:
-        """Read (value None) or set a launch knob ("mac_chunk", "mac_cts", "keyip_xcd", "mac_direct")."""
+        """Read (value None) or set a launch knob ("mac_chunk", "mac_cts", "keyip_xcd", "mac_direct", "ntt_xcd")."""
         if value is not None:
             _check(lib().ctl_knob_set(self.handle, KNOBS[name], int(value)))
         v = ctypes.c_int()

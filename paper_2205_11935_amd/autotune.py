@@ -21,6 +21,7 @@ CANDIDATES: Dict[str, List[int]] = {
     "mac_chunk": [16, 12, 8, 6, 4],
     "mac_cts": [8, 4, 2],
     "keyip_xcd": [1, 0],
+    "ntt_xcd": [1, 0],
 }
 
 

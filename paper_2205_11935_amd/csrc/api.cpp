@@ -265,7 +265,7 @@ int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
     CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
     CTL_TRY(slot(c, S_U, (size_t)B * R * 2 * (k + 1) * N, st, &U));
     { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
-    { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, st); }
+    { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st); }
     KeyList kl{};
     for (int r = 0; r < R; ++r) {
         kl.key[r] = keys[r];
@@ -292,7 +292,7 @@ int keyswitch_lower(ctl_ctx *c, hipStream_t st, int k, int groups, const u64 *U,
     pm.ostride = k + 1;
     pm.prime[0] = nq;
     { CTL_PROF(F_NTT_INV, groups, fp_share_range(c, 0, true)); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), groups, c->tab, st); }
-    { CTL_PROF(F_DROP, (double)groups * k, fp_share_range(c, k, false)); launch_drop(logn, U, plast, out, groups, k, nq, add, c->tab, st); }
+    { CTL_PROF(F_DROP, (double)groups * k, fp_share_range(c, k, false)); launch_drop(logn, U, plast, out, groups, k, nq, add, c->tab, c->knobs, st); }
     return check_launch();
 }
 
@@ -323,7 +323,7 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
     add.R = 1;
     add.mask = 0;
     add.gal[0] = 1;
-    { CTL_PROF(F_DROP, B * 2 * (k - 1), fp_share_range(c, k - 1, false)); launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, st); }
+    { CTL_PROF(F_DROP, B * 2 * (k - 1), fp_share_range(c, k - 1, false)); launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, c->knobs, st); }
     return check_launch();
 }
 
@@ -1032,6 +1032,10 @@ int ctl_knob_set(ctl_ctx *ctx, int knob, int value) {
             if (value < 0 || value > 64) return fail(CTL_EINVAL, "direct-MAC batch limit must lie in 0..64");
             ctx->knobs.mac_direct_max = value;
             return CTL_OK;
+        case CTL_KNOB_NTT_XCD:
+            if (value != 0 && value != 1) return fail(CTL_EINVAL, "ModUp/ModDown numbering is 0 or 1");
+            ctx->knobs.ntt_xcd = value;
+            return CTL_OK;
         default:
             return fail(CTL_EINVAL, "unknown knob");
     }
@@ -1044,6 +1048,7 @@ int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value) {
         case CTL_KNOB_MAC_CTS: *value = ctx->knobs.mac_cts; return CTL_OK;
         case CTL_KNOB_KEYIP_XCD: *value = ctx->knobs.keyip_xcd; return CTL_OK;
         case CTL_KNOB_MAC_DIRECT: *value = ctx->knobs.mac_direct_max; return CTL_OK;
+        case CTL_KNOB_NTT_XCD: *value = ctx->knobs.ntt_xcd; return CTL_OK;
         default: return fail(CTL_EINVAL, "unknown knob");
     }
 }

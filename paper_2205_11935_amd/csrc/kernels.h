@@ -51,23 +51,25 @@ hipError_t kernels_prepare(int logn);
 void launch_sum_gather(int logn, u64 *out, long o_sb, const u64 *base, long ba_sb, const u64 *src, long s_sb,
                        long s_sr, int R, int kk, bool ext, int mask, const GalList &gal, int B, int nq,
                        const Tables &tab, hipStream_t st);
-void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
-                int count, const Tables &tab, hipStream_t st);
-void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
-                  int nq, const Tables &tab, hipStream_t st);
-void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
-                 const DropAdd &add, const Tables &tab, hipStream_t st);
-void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,
-                    const Tables &tab, hipStream_t st);
 // Launch choices an autotuner may set (defaults in brackets): the largest giant-step chunk of the
 // MAC [16], ciphertexts per MAC workgroup [8], XCD-grouped key-product numbering [1], largest
-// batch that uses the unstaged MAC [3].
+// batch that uses the unstaged MAC [3], XCD-grouped ModUp / ModDown numbering [0].
 struct Knobs {
     int mac_chunk_cap = 16;
     int mac_cts = 8;
     int keyip_xcd = 1;
     int mac_direct_max = 3;      // batches up to this size use the unstaged MAC
+    int ntt_xcd = 0;             // XCD-grouped numbering of ModUp and ModDown workgroups
 };
+
+void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
+                int count, const Tables &tab, hipStream_t st);
+void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
+                  int nq, const Tables &tab, const Knobs &kn, hipStream_t st);
+void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
+                 const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st);
+void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,
+                    const Tables &tab, hipStream_t st);
 void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
                   u64 *out, int B, int nq, const Tables &tab, const Knobs &kn, hipStream_t st);
 void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *inner, int B, int k,

@@ -501,12 +501,22 @@ k_ntt_inv(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
 template <int LOGN>
 __global__ void __launch_bounds__(Geo<LOGN>::T)
 k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u64 *__restrict__ digits, int k,
-        int nq, Tables tab) {
+        int nq, int units, int xcd_order, Tables tab) {
     extern __shared__ u64 lds[];
     constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
     const int tid = threadIdx.x;
-    const int t = blockIdx.x % (k + 1);
-    const int gj = blockIdx.x / (k + 1);      // g * k + j
+    int t, gj;                                // gj = g * k + j, the digit; t, its target
+    if (xcd_order) {
+        // the k + 1 targets of a digit run back to back on one XCD (workgroups are dealt to the 8
+        // XCDs in turn), so its L2 serves the k re-reads of the digit
+        const int loc = blockIdx.x >> 3;
+        t = loc % (k + 1);
+        gj = (loc / (k + 1)) * 8 + (blockIdx.x & 7);
+        if (gj >= units) return;
+    } else {
+        t = blockIdx.x % (k + 1);
+        gj = blockIdx.x / (k + 1);
+    }
     const int j = gj % k;
     u64 *dst = digits + ((long)gj * (k + 1) + t) * N;
     if (t == j) {
@@ -536,12 +546,21 @@ k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u6
 template <int LOGN>
 __global__ void __launch_bounds__(Geo<LOGN>::T)
 k_drop(const u64 *__restrict__ x, const u64 *__restrict__ last, u64 *__restrict__ out, int k,
-       int drop, DropAdd add, Tables tab) {
+       int drop, int groups, int xcd_order, DropAdd add, Tables tab) {
     extern __shared__ u64 lds[];
     constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
     const int tid = threadIdx.x;
-    const int i = blockIdx.x % k;
-    const int grp = blockIdx.x / k;
+    int i, grp;
+    if (xcd_order) {
+        // the k primes of a group run back to back on one XCD, which then reads `last` once
+        const int loc = blockIdx.x >> 3;
+        i = loc % k;
+        grp = (loc / k) * 8 + (blockIdx.x & 7);
+        if (grp >= groups) return;
+    } else {
+        i = blockIdx.x % k;
+        grp = blockIdx.x / k;
+    }
     const PrimeConst p = tab.pc[i];
     const u64 qd = tab.pc[drop].q;
     const CrossConst cc = tab.cross[i * kMaxMods + drop];
@@ -1065,26 +1084,28 @@ void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *
 }
 
 void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
-                  int nq, const Tables &tab, hipStream_t st) {
+                  int nq, const Tables &tab, const Knobs &kn, hipStream_t st) {
     if (groups <= 0) return;
-    const dim3 grid(groups * k * (k + 1)), blk = ntt_block(logn);
+    const int units = groups * k, xo = kn.ntt_xcd ? 1 : 0;
+    const dim3 grid(xo ? ((units + 7) / 8) * 8 * (k + 1) : units * (k + 1)), blk = ntt_block(logn);
     const size_t sh = ntt_lds(logn);
     switch (logn) {
-        case 12: hipLaunchKernelGGL(k_modup<12>, grid, blk, sh, st, coef, d, dmap, digits, k, nq, tab); break;
-        case 13: hipLaunchKernelGGL(k_modup<13>, grid, blk, sh, st, coef, d, dmap, digits, k, nq, tab); break;
-        default: hipLaunchKernelGGL(k_modup<14>, grid, blk, sh, st, coef, d, dmap, digits, k, nq, tab); break;
+        case 12: hipLaunchKernelGGL(k_modup<12>, grid, blk, sh, st, coef, d, dmap, digits, k, nq, units, xo, tab); break;
+        case 13: hipLaunchKernelGGL(k_modup<13>, grid, blk, sh, st, coef, d, dmap, digits, k, nq, units, xo, tab); break;
+        default: hipLaunchKernelGGL(k_modup<14>, grid, blk, sh, st, coef, d, dmap, digits, k, nq, units, xo, tab); break;
     }
 }
 
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
-                 const DropAdd &add, const Tables &tab, hipStream_t st) {
+                 const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st) {
     if (groups <= 0) return;
-    const dim3 grid(groups * k), blk = ntt_block(logn);
+    const int xo = kn.ntt_xcd ? 1 : 0;
+    const dim3 grid(xo ? ((groups + 7) / 8) * 8 * k : groups * k), blk = ntt_block(logn);
     const size_t sh = ntt_lds(logn);
     switch (logn) {
-        case 12: hipLaunchKernelGGL(k_drop<12>, grid, blk, sh, st, x, last, out, k, drop, add, tab); break;
-        case 13: hipLaunchKernelGGL(k_drop<13>, grid, blk, sh, st, x, last, out, k, drop, add, tab); break;
-        default: hipLaunchKernelGGL(k_drop<14>, grid, blk, sh, st, x, last, out, k, drop, add, tab); break;
+        case 12: hipLaunchKernelGGL(k_drop<12>, grid, blk, sh, st, x, last, out, k, drop, groups, xo, add, tab); break;
+        case 13: hipLaunchKernelGGL(k_drop<13>, grid, blk, sh, st, x, last, out, k, drop, groups, xo, add, tab); break;
+        default: hipLaunchKernelGGL(k_drop<14>, grid, blk, sh, st, x, last, out, k, drop, groups, xo, add, tab); break;
     }
 }
 
