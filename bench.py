@@ -449,7 +449,8 @@ def serving_sweep(args):
         print("serving rate %.0f q/s: %s" % (rate, json.dumps(sweep[-1])), file=sys.stderr, flush=True)
     srv.close()
     return {"workload": "Poisson arrivals, 80% mid (N=2^13, 512->128->128) / 20% large (N=2^14, "
-                        "768->256->64), 4 clients per set, keys resident, 2 lanes per set, batches up to 64",
+                        "768->256->64), 4 clients per set, keys resident, 2 lanes per set, batches of up to 64 "
+                        "of the oldest queries across clients",
             "sweep": sweep, "key_bytes": key_budget, "setup_s": round(setup_s, 2)}
 
 

@@ -354,6 +354,16 @@ int ctl_ct_unpack(const ctl_params *params, const uint8_t *in, uint64_t len, uin
 int ctl_forward(ctl_ctx *ctx, const ctl_model *model, const ctl_evk *evk, const uint64_t *in,
                 uint64_t *out, int n_ct, void *stream);
 
+/* ctl_forward on a batch that mixes clients (Algorithm 2, ClassifyHE, for several key owners at
+ * once): ciphertext b is evaluated with evks[b], an array of n_ct handles (host memory, read during
+ * the call only). Consecutive equal handles form a run; the key products of Section 3.1's
+ * rotations and relinearizations run once per run, every other kernel (NTTs, ModUp, ModDown,
+ * plaintext products, rescales) once over the whole batch. Output b equals ctl_forward of
+ * ciphertext b alone with evks[b], bit for bit. Errors: a NULL handle or one of other parameters
+ * gives CTL_EINVAL; a handle without a key the model needs gives CTL_EKEY. */
+int ctl_forward_multi(ctl_ctx *ctx, const ctl_model *model, const ctl_evk *const *evks,
+                      const uint64_t *in, uint64_t *out, int n_ct, void *stream);
+
 /* One layer of the model. Dense, by Eq. (1): hoisted baby-step rotations rot_j, j < t1, products
  * with the diagonal plaintexts, one key switch per giant step rot_{k t1}, one rescale at the end.
  * Convolution and average pool: their rotations hoisted the same way, the plaintext products

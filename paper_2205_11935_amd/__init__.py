@@ -161,6 +161,8 @@ _SIGS = {
     "ctl_decode_items": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, u64p, f64p]),
     "ctl_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_forward_multi": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "ctl_dense": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "ctl_square": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -551,6 +553,19 @@ class Context:
         if out is None:
             out = self.empty_ct(n_ct, model.info.k_out)
         _check(lib().ctl_forward(self.handle, model.handle, keys.evk, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        return out
+
+    def forward_multi(self, model: Model, keys: Sequence[Keys], ct, out=None, stream=None):
+        """forward on a batch mixing clients: ciphertext b is evaluated with keys[b]. Key products
+        run once per run of consecutive ciphertexts with the same Keys object."""
+        n_ct = ct.shape[0]
+        if len(keys) != n_ct:
+            raise ValueError("one Keys per ciphertext")
+        if out is None:
+            out = self.empty_ct(n_ct, model.info.k_out)
+        arr = (ctypes.c_void_p * n_ct)(*[kk.evk for kk in keys])
+        _check(lib().ctl_forward_multi(self.handle, model.handle, arr, _ptr(ct), _ptr(out), n_ct,
+                                       _stream(stream)))
         return out
 
     def dense(self, model: Model, layer: int, keys: Keys, ct, out=None, stream=None):

@@ -249,13 +249,36 @@ const u64 *find_key(const ctl_evk *evk, u64 g) {
     return it == evk->keys.end() ? nullptr : it->second;
 }
 
+// The evaluation keys of a batch: runs of consecutive ciphertexts that share one key set (one
+// client). Key products run per run; every other kernel covers the whole batch.
+struct KeySet {
+    struct Run {
+        const ctl_evk *evk;
+        int b0, nb;
+    };
+    std::vector<Run> runs;
+};
+
+KeySet one_key_set(const ctl_evk *evk, int B) {
+    KeySet ks;
+    ks.runs.push_back({evk, 0, B});
+    return ks;
+}
+
+// Every run holds key `id` (a Galois element, or 0 for the relinearization key); `what` names it.
+int need_key(const KeySet &ks, u64 id, const std::string &what) {
+    for (const KeySet::Run &r : ks.runs)
+        if (!find_key(r.evk, id)) return fail(CTL_EKEY, "missing " + what);
+    return CTL_OK;
+}
+
 // ---------------------------------------------------------------- building blocks
 // Raise and multiply: for G = B R polynomials d (k residues each, located by dmap over B*R*k
 // residues, group order (b, r)), U[b][r] = sum_j ModUp(d)_j * key_r[j] gathered through
 // sigma_{gal[r]}, as [B][R][2][k+1][N] over q_0..q_{k-1}, P. `hoisted` = the same d for every r
 // (dmap covers B*k residues only). Returns the U buffer (workspace slot S_U).
 int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *d, const ResMap &dmap,
-                    bool hoisted, const u64 *const *keys, const u64 *gal, u64 **U_out) {
+                    bool hoisted, const KeySet &ks, const u64 *key_ids, const u64 *gal, u64 **U_out) {
     const int logn = c->hp.logn, nq = c->hp.nq;
     const long N = c->hp.n;
     if (R > kMaxKeysPerLaunch) return fail(CTL_EINVAL, "too many rotations in one layer");
@@ -266,13 +289,18 @@ int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
     CTL_TRY(slot(c, S_U, (size_t)B * R * 2 * (k + 1) * N, st, &U));
     { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
     { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st); }
-    KeyList kl{};
-    for (int r = 0; r < R; ++r) {
-        kl.key[r] = keys[r];
-        kl.gal[r] = gal[r];
+    const long dsz = (long)k * (k + 1) * N, db = hoisted ? dsz : (long)R * dsz;
+    CTL_PROF(F_KEYIP, 2.0 * B * R * (k + 1) * k * N, fp_share_range(c, k, true));
+    for (const KeySet::Run &run : ks.runs) {       // one launch per key set
+        KeyList kl{};
+        for (int r = 0; r < R; ++r) {
+            kl.key[r] = find_key(run.evk, key_ids[r]);
+            if (!kl.key[r]) return fail(CTL_EKEY, "missing evaluation key");
+            kl.gal[r] = gal[r];
+        }
+        launch_keyip(logn, k, dig + run.b0 * db, db, hoisted ? 0 : dsz, kl, R,
+                     U + (long)run.b0 * R * 2 * (k + 1) * N, run.nb, nq, c->tab, c->knobs, st);
     }
-    const long dsz = (long)k * (k + 1) * N;
-    { CTL_PROF(F_KEYIP, 2.0 * B * R * (k + 1) * k * N, fp_share_range(c, k, true)); launch_keyip(logn, k, dig, hoisted ? dsz : (long)R * dsz, hoisted ? 0 : dsz, kl, R, U, B, nq, c->tab, c->knobs, st); }
     *U_out = U;
     return check_launch();
 }
@@ -298,9 +326,10 @@ int keyswitch_lower(ctl_ctx *c, hipStream_t st, int k, int groups, const u64 *U,
 
 // Full key switch: out[b][r] = (KS0 + addend, KS1) as [B][R][2][k][N].
 int keyswitch_batch(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *d, const ResMap &dmap,
-                    bool hoisted, const u64 *const *keys, const u64 *gal, const DropAdd &add, u64 *out) {
+                    bool hoisted, const KeySet &ks, const u64 *key_ids, const u64 *gal, const DropAdd &add,
+                    u64 *out) {
     u64 *U;
-    CTL_TRY(keyswitch_raise(c, st, k, B, R, d, dmap, hoisted, keys, gal, &U));
+    CTL_TRY(keyswitch_raise(c, st, k, B, R, d, dmap, hoisted, ks, key_ids, gal, &U));
     return keyswitch_lower(c, st, k, B * R * 2, U, add, out);
 }
 
@@ -338,38 +367,36 @@ ResMap c1_map(int k) {        // the c1 residues of a [B][2][k][N] batch
     return m;
 }
 
-int rotate_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, long rot, const u64 *in, u64 *out) {
+int rotate_batch(ctl_ctx *c, hipStream_t st, const KeySet &ks, int k, int B, long rot, const u64 *in, u64 *out) {
     const u64 g = galois_elt(c->hp.logn, rot);
     const long N = c->hp.n;
     if (g == 1) {
         CTL_HIP(hipMemcpyAsync(out, in, (size_t)B * 2 * k * N * 8, hipMemcpyDeviceToDevice, st));
         return CTL_OK;
     }
-    const u64 *key = find_key(evk, g);
-    if (!key) return fail(CTL_EKEY, "missing Galois key for rotation " + std::to_string(rot));
+    CTL_TRY(need_key(ks, g, "Galois key for rotation " + std::to_string(rot)));
     DropAdd add{};
     add.base = in;
     add.sb = 2L * k * N;
     add.R = 1;
     add.mask = 1;
     add.gal[0] = g;
-    return keyswitch_batch(c, st, k, B, 1, in, c1_map(k), false, &key, &g, add, out);
+    return keyswitch_batch(c, st, k, B, 1, in, c1_map(k), false, ks, &g, &g, add, out);
 }
 
-int replicate_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, int width, const u64 *in, u64 *out) {
+int replicate_batch(ctl_ctx *c, hipStream_t st, const KeySet &ks, int k, int B, int width, const u64 *in, u64 *out) {
     const long N = c->hp.n;
     u64 *rot;
     CTL_TRY(slot(c, S_REP, (size_t)B * 2 * k * N, st, &rot));
-    CTL_TRY(rotate_batch(c, st, evk, k, B, -(long)width, in, rot));
+    CTL_TRY(rotate_batch(c, st, ks, k, B, -(long)width, in, rot));
     { CTL_PROF(F_ADD, 2.0 * B * k * N, 0.0); launch_add_terms(c->hp.logn, in, 2L * k * N, rot, 2L * k * N, 0, 1, out, B, k, c->tab, st); }
     return check_launch();
 }
 
 // a x b: tensor, relinearization, rescale ([B][2][k][N] each -> [B][2][k-1][N]); a == b squares.
-int mul_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, const u64 *a, const u64 *b, u64 *out) {
+int mul_batch(ctl_ctx *c, hipStream_t st, const KeySet &ks, int k, int B, const u64 *a, const u64 *b, u64 *out) {
     const long N = c->hp.n;
-    const u64 *rlk = find_key(evk, 0);
-    if (!rlk) return fail(CTL_EKEY, "missing relinearization key");
+    CTL_TRY(need_key(ks, 0, "relinearization key"));
     if (k < 2) return fail(CTL_ELEVEL, "a ciphertext product needs at least two primes");
     u64 *t3, *sq;
     CTL_TRY(slot(c, S_TENSOR, (size_t)B * 3 * k * N, st, &t3));
@@ -389,13 +416,13 @@ int mul_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, cons
     add.R = 1;
     add.mask = 3;
     add.gal[0] = 1;
-    const u64 one = 1;
-    CTL_TRY(keyswitch_batch(c, st, k, B, 1, t3, dm, false, &rlk, &one, add, sq));
+    const u64 rlk_id = 0, one = 1;
+    CTL_TRY(keyswitch_batch(c, st, k, B, 1, t3, dm, false, ks, &rlk_id, &one, add, sq));
     return rescale_batch(c, st, k, B, sq, out);
 }
 
-int square_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, const u64 *in, u64 *out) {
-    return mul_batch(c, st, evk, k, B, in, in, out);
+int square_batch(ctl_ctx *c, hipStream_t st, const KeySet &ks, int k, int B, const u64 *in, u64 *out) {
+    return mul_batch(c, st, ks, k, B, in, in, out);
 }
 
 u64 signed_mod(int64_t v, u64 q) {
@@ -441,7 +468,7 @@ bool poly3_consts_ok(const ctl_ctx *c, int k, double S, const double *coef) {
 }
 
 // c0 + c1 z + c2 z^2 + c3 z^3 on [B][2][k][N] -> [B][2][k-2][N] (schedule in ctl.h).
-int poly3_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, double S, const double *coef,
+int poly3_batch(ctl_ctx *c, hipStream_t st, const KeySet &ks, int k, int B, double S, const double *coef,
                 const u64 *in, u64 *out) {
     if (k < 3) return fail(CTL_ELEVEL, "the cubic activation needs at least three primes");
     if (!poly3_consts_ok(c, k, S, coef)) return fail(CTL_ESCALE, "activation constant out of range");
@@ -454,11 +481,11 @@ int poly3_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, do
     CTL_TRY(slot(c, S_P_U, (size_t)B * 2 * (k - 1) * N, st, &u));
     CTL_TRY(slot(c, S_P_W, (size_t)B * 2 * (k - 2) * N, st, &w));
     CTL_TRY(slot(c, S_P_V, (size_t)B * 2 * (k - 2) * N, st, &v));
-    CTL_TRY(square_batch(c, st, evk, k, B, in, z2));
+    CTL_TRY(square_batch(c, st, ks, k, B, in, z2));
     CTL_TRY(affine_batch(c, st, B, k, k, in, C[3], 0, t));
     CTL_TRY(rescale_batch(c, st, k, B, t, u));
     CTL_TRY(affine_batch(c, st, B, k - 1, k - 1, u, 1, C[2], u));
-    CTL_TRY(mul_batch(c, st, evk, k - 1, B, z2, u, w));
+    CTL_TRY(mul_batch(c, st, ks, k - 1, B, z2, u, w));
     CTL_TRY(affine_batch(c, st, B, k, k, in, C[1], 0, t));
     CTL_TRY(rescale_batch(c, st, k, B, t, u));
     CTL_TRY(affine_batch(c, st, B, k - 1, k - 2, u, 1, C[0], v));
@@ -466,7 +493,7 @@ int poly3_batch(ctl_ctx *c, hipStream_t st, const ctl_evk *evk, int k, int B, do
     return check_launch();
 }
 
-int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ctl_evk *evk, int B,
+int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const KeySet &ks, int B,
                 const u64 *in, u64 *out) {
     const LayerPlan &L = m->layers[li];
     const int logn = c->hp.logn, k = L.k, t1 = L.t1, t2 = L.t2;
@@ -474,18 +501,14 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
     const int R1 = t1 - 1, R2 = t2 - 1;
     if (R1 > kMaxKeysPerLaunch || R2 > kMaxKeysPerLaunch)
         return fail(CTL_EINVAL, "t1 and t2 must be at most 65");
-    std::vector<const u64 *> keys1(R1), keys2(R2);
     std::vector<u64> gal1(R1), gal2(R2);
     for (int j = 1; j < t1; ++j) {
         gal1[j - 1] = galois_elt(logn, L.rots1[j - 1]);
-        keys1[j - 1] = find_key(evk, gal1[j - 1]);
-        if (!keys1[j - 1])
-            return fail(CTL_EKEY, "missing Galois key for rotation " + std::to_string(L.rots1[j - 1]));
+        CTL_TRY(need_key(ks, gal1[j - 1], "Galois key for rotation " + std::to_string(L.rots1[j - 1])));
     }
     for (int k2 = 1; k2 < t2; ++k2) {
         gal2[k2 - 1] = galois_elt(logn, (long)k2 * t1);
-        keys2[k2 - 1] = find_key(evk, gal2[k2 - 1]);
-        if (!keys2[k2 - 1]) return fail(CTL_EKEY, "missing Galois key for rotation " + std::to_string(k2 * t1));
+        CTL_TRY(need_key(ks, gal2[k2 - 1], "Galois key for rotation " + std::to_string(k2 * t1)));
     }
     u64 *rot, *inner;
     CTL_TRY(slot(c, S_ROT, (size_t)B * std::max(R1, 1) * ctw, st, &rot));
@@ -499,7 +522,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
         add.R = R1;
         add.mask = 1;
         for (int r = 0; r < R1; ++r) add.gal[r] = gal1[r];
-        CTL_TRY(keyswitch_batch(c, st, k, B, R1, in, c1_map(k), true, keys1.data(), gal1.data(), add, rot));
+        CTL_TRY(keyswitch_batch(c, st, k, B, R1, in, c1_map(k), true, ks, gal1.data(), gal1.data(), add, rot));
     }
     // inner_k2 = sum_j diag'_{k2 t1 + j} * rot_j(ct)
     { CTL_PROF(F_MAC, 2.0 * B * k * t1 * t2 * N, fp_share_range(c, k, false)); launch_mac(logn, in, rot, m->banks[li], inner, B, k, t1, t2, c->tab, c->knobs, st); }
@@ -515,7 +538,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
         dm.gstride = 2L * k;
         dm.ostride = (long)t2 * 2 * k;
         for (int i = 0; i < k; ++i) dm.prime[i] = i;
-        CTL_TRY(keyswitch_raise(c, st, k, B, R2, inner, dm, false, keys2.data(), gal2.data(), &U));
+        CTL_TRY(keyswitch_raise(c, st, k, B, R2, inner, dm, false, ks, gal2.data(), gal2.data(), &U));
         CTL_TRY(slot(c, S_ROT2, (size_t)B * 2 * (k + 1) * N, st, &usum));
         CTL_TRY(slot(c, S_TENSOR, (size_t)B * ctw, st, &s0));
         CTL_TRY(slot(c, S_SUM, (size_t)B * ctw, st, &acc));
@@ -553,12 +576,51 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const ct
         add.R = R2;
         add.mask = 1;
         for (int r = 0; r < R2; ++r) add.gal[r] = gal2[r];
-        CTL_TRY(keyswitch_batch(c, st, k, B, R2, inner, dm, false, keys2.data(), gal2.data(), add, rot2));
+        CTL_TRY(keyswitch_batch(c, st, k, B, R2, inner, dm, false, ks, gal2.data(), gal2.data(), add, rot2));
         { CTL_PROF(F_ADD, 2.0 * B * k * N, 0.0); launch_add_terms(logn, inner, (long)t2 * ctw, rot2, (long)R2 * ctw, ctw, R2, acc, B, k, c->tab, st); }
         CTL_TRY(check_launch());
         sum = acc;
     }
     return rescale_batch(c, st, k, B, sum, out);
+}
+
+// The model's layers in order on [B][2][n_q][N] -> [B][2][k_out][N], through three rotating
+// context buffers (a layer's input may be the caller's `in`, its output never aliases it).
+int forward_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, const KeySet &ks, int B, const u64 *in,
+                  u64 *out) {
+    const long N = c->hp.n;
+    const size_t words = (size_t)B * 2 * c->hp.nq * N;
+    u64 *bufs[3];
+    CTL_TRY(slot(c, S_FWD_A, words, st, &bufs[0]));
+    CTL_TRY(slot(c, S_FWD_B, words, st, &bufs[1]));
+    CTL_TRY(slot(c, S_FWD_C, words, st, &bufs[2]));
+    const u64 *cur = in;
+    int ci = 2;                                   // the next result goes to bufs[(ci + 1) % 3]
+    auto next = [&]() { ci = (ci + 1) % 3; return bufs[ci]; };
+    const int L = (int)m->layers.size();
+    for (int l = 0; l < L; ++l) {
+        const LayerPlan &P = m->layers[l];
+        if (P.rep_before) {
+            u64 *dst = next();
+            CTL_TRY(replicate_batch(c, st, ks, P.k, B, P.rep_before, cur, dst));
+            cur = dst;
+        }
+        const bool last = l + 1 == L;
+        u64 *dst = last ? out : next();
+        CTL_TRY(dense_batch(c, st, m, l, ks, B, cur, dst));
+        cur = dst;
+        if (last) break;
+        if (P.act == CTL_ACT_SQUARE) {
+            u64 *d2 = next();
+            CTL_TRY(square_batch(c, st, ks, P.k - 1, B, cur, d2));
+            cur = d2;
+        } else if (P.act == CTL_ACT_POLY3) {
+            u64 *d2 = next();
+            CTL_TRY(poly3_batch(c, st, ks, P.k - 1, B, P.act_scale_in, P.act_coef, cur, d2));
+            cur = d2;
+        }
+    }
+    return CTL_OK;
 }
 
 // ---------------------------------------------------------------- model planning
@@ -1610,7 +1672,7 @@ int ctl_dense(ctl_ctx *ctx, const ctl_model *model, int layer, const ctl_evk *ev
     CTL_SAME(ctx, model, "the model");
     CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
-    return dense_batch(ctx, as_stream(stream), model, layer, evk, n_ct, reinterpret_cast<const u64 *>(in),
+    return dense_batch(ctx, as_stream(stream), model, layer, one_key_set(evk, n_ct), n_ct, reinterpret_cast<const u64 *>(in),
                        reinterpret_cast<u64 *>(out));
 }
 
@@ -1619,7 +1681,7 @@ int ctl_square(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint
     if (k < 2 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
     CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
-    return square_batch(ctx, as_stream(stream), evk, k, n_ct, reinterpret_cast<const u64 *>(in),
+    return square_batch(ctx, as_stream(stream), one_key_set(evk, n_ct), k, n_ct, reinterpret_cast<const u64 *>(in),
                         reinterpret_cast<u64 *>(out));
 }
 
@@ -1629,7 +1691,7 @@ int ctl_replicate(ctl_ctx *ctx, const ctl_evk *evk, int k, int width, const uint
     if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
     CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
-    return replicate_batch(ctx, as_stream(stream), evk, k, n_ct, width, reinterpret_cast<const u64 *>(in),
+    return replicate_batch(ctx, as_stream(stream), one_key_set(evk, n_ct), k, n_ct, width, reinterpret_cast<const u64 *>(in),
                            reinterpret_cast<u64 *>(out));
 }
 
@@ -1639,7 +1701,7 @@ int ctl_rotate(ctl_ctx *ctx, const ctl_evk *evk, int k, int rotation, const uint
     if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
     CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
-    return rotate_batch(ctx, as_stream(stream), evk, k, n_ct, rotation, reinterpret_cast<const u64 *>(in),
+    return rotate_batch(ctx, as_stream(stream), one_key_set(evk, n_ct), k, n_ct, rotation, reinterpret_cast<const u64 *>(in),
                         reinterpret_cast<u64 *>(out));
 }
 
@@ -1657,40 +1719,26 @@ int ctl_forward(ctl_ctx *ctx, const ctl_model *m, const ctl_evk *evk, const uint
     CTL_SAME(ctx, m, "the model");
     CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
-    hipStream_t st = as_stream(stream);
-    const long N = ctx->hp.n;
-    const size_t words = (size_t)n_ct * 2 * ctx->hp.nq * N;
-    u64 *bufs[3];
-    CTL_TRY(slot(ctx, S_FWD_A, words, st, &bufs[0]));
-    CTL_TRY(slot(ctx, S_FWD_B, words, st, &bufs[1]));
-    CTL_TRY(slot(ctx, S_FWD_C, words, st, &bufs[2]));
-    const u64 *cur = reinterpret_cast<const u64 *>(in);
-    int ci = 2;                                   // the next result goes to bufs[(ci + 1) % 3]
-    auto next = [&]() { ci = (ci + 1) % 3; return bufs[ci]; };
-    const int L = (int)m->layers.size();
-    for (int l = 0; l < L; ++l) {
-        const LayerPlan &P = m->layers[l];
-        if (P.rep_before) {
-            u64 *dst = next();
-            CTL_TRY(replicate_batch(ctx, st, evk, P.k, n_ct, P.rep_before, cur, dst));
-            cur = dst;
-        }
-        const bool last = l + 1 == L;
-        u64 *dst = last ? reinterpret_cast<u64 *>(out) : next();
-        CTL_TRY(dense_batch(ctx, st, m, l, evk, n_ct, cur, dst));
-        cur = dst;
-        if (last) break;
-        if (P.act == CTL_ACT_SQUARE) {
-            u64 *d2 = next();
-            CTL_TRY(square_batch(ctx, st, evk, P.k - 1, n_ct, cur, d2));
-            cur = d2;
-        } else if (P.act == CTL_ACT_POLY3) {
-            u64 *d2 = next();
-            CTL_TRY(poly3_batch(ctx, st, evk, P.k - 1, n_ct, P.act_scale_in, P.act_coef, cur, d2));
-            cur = d2;
-        }
+    return forward_batch(ctx, as_stream(stream), m, one_key_set(evk, n_ct), n_ct, reinterpret_cast<const u64 *>(in),
+                         reinterpret_cast<u64 *>(out));
+}
+
+int ctl_forward_multi(ctl_ctx *ctx, const ctl_model *m, const ctl_evk *const *evks, const uint64_t *in,
+                      uint64_t *out, int n_ct, void *stream) {
+    if (!ctx || !m || !evks || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
+    CTL_SAME(ctx, m, "the model");
+    KeySet ks;
+    for (int b = 0; b < n_ct; ++b) {
+        if (!evks[b]) return fail(CTL_EINVAL, "null evaluation key set");
+        CTL_SAME(ctx, evks[b], "every evaluation key set");
+        if (!ks.runs.empty() && ks.runs.back().evk == evks[b])
+            ++ks.runs.back().nb;
+        else
+            ks.runs.push_back({evks[b], b, 1});
     }
-    return CTL_OK;
+    CTL_HIP(hipSetDevice(ctx->device));
+    return forward_batch(ctx, as_stream(stream), m, ks, n_ct, reinterpret_cast<const u64 *>(in),
+                         reinterpret_cast<u64 *>(out));
 }
 
 int ctl_mul(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *a, const uint64_t *b, uint64_t *out,
@@ -1699,7 +1747,7 @@ int ctl_mul(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *a, const ui
     if (k < 2 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
     CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
-    return mul_batch(ctx, as_stream(stream), evk, k, n_ct, reinterpret_cast<const u64 *>(a),
+    return mul_batch(ctx, as_stream(stream), one_key_set(evk, n_ct), k, n_ct, reinterpret_cast<const u64 *>(a),
                      reinterpret_cast<const u64 *>(b), reinterpret_cast<u64 *>(out));
 }
 
@@ -1710,7 +1758,7 @@ int ctl_poly3(ctl_ctx *ctx, const ctl_evk *evk, int k, double scale, const doubl
     if (!(scale > 0) || !std::isfinite(scale)) return fail(CTL_ESCALE, "scale must be positive");
     CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
-    CTL_TRY(poly3_batch(ctx, as_stream(stream), evk, k, n_ct, scale, coef, reinterpret_cast<const u64 *>(in),
+    CTL_TRY(poly3_batch(ctx, as_stream(stream), one_key_set(evk, n_ct), k, n_ct, scale, coef, reinterpret_cast<const u64 *>(in),
                         reinterpret_cast<u64 *>(out)));
     if (scale_out) {
         int64_t C[4];

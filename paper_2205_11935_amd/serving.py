@@ -12,10 +12,13 @@ results. Each client's evaluation keys and every admitted ciphertext stay reside
   rejected.
 * Continuous batching. A parameter set has one or more lanes, each a library context with its own
   stream and workspace (keys and plaintext banks are shared between the lanes). Whenever a lane
-  is idle it takes the client with the oldest admitted query and launches one batched forward pass
-  over that client's admitted queries (up to `max_batch`). Queries that arrive while other
-  batches run are admitted into free slots at once and join the next batch; the lanes of both
-  parameter sets run concurrently on their own streams, so their work overlaps on the device.
+  is idle it takes the oldest admitted queries of its parameter set (up to `max_batch`), whatever
+  their clients, groups them by client and launches one batched forward pass
+  (ctl_forward_multi: key products per client run, everything else over the whole batch). With
+  `mix_clients=False` a batch holds one client's queries only (the client whose oldest admitted
+  query arrived first). Queries that arrive while other batches run are admitted into free slots
+  at once and join the next batch; the lanes of both parameter sets run concurrently on their own
+  streams, so their work overlaps on the device.
 * Every arithmetic step runs in the library; this module only schedules, copies ciphertexts
   between slots and batch buffers, and records times.
 
@@ -26,6 +29,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import heapq
 import math
 import time
 from typing import Callable, Deque, Dict, Iterable, List, Optional, Sequence, Tuple
@@ -129,10 +133,12 @@ class PsetConfig:
 class Scheduler:
     """Admission, batch formation and completion bookkeeping (no device work)."""
 
-    def __init__(self, configs: Sequence[PsetConfig], keys: KeyCache, max_pending: int = 1 << 20):
+    def __init__(self, configs: Sequence[PsetConfig], keys: KeyCache, max_pending: int = 1 << 20,
+                 mix_clients: bool = True):
         self.cfg = {c.name: c for c in configs}
         self.keys = keys
         self.max_pending = max_pending
+        self.mix_clients = mix_clients
         self.pending: Dict[str, Deque[Request]] = {c.name: collections.deque() for c in configs}
         self.admitted: Dict[str, "collections.OrderedDict[int, Deque[Request]]"] = {
             c.name: collections.OrderedDict() for c in configs}
@@ -174,16 +180,35 @@ class Scheduler:
         return out
 
     def next_batch(self, pset: str, now: float) -> List[Request]:
-        """The admitted queries of the client whose oldest admitted query arrived first (at most
-        max_batch, in arrival order)."""
+        """mix_clients: the oldest admitted queries (at most max_batch), grouped by client in order
+        of each client's oldest one, arrival order within a client. Otherwise the admitted queries
+        of the client whose oldest admitted query arrived first (at most max_batch)."""
         adm = self.admitted[pset]
         if not adm:
             return []
-        client = min(adm, key=lambda c: adm[c][0].t_arrive)
-        q = adm[client]
-        batch = [q.popleft() for _ in range(min(len(q), self.cfg[pset].max_batch))]
-        if not q:
-            del adm[client]
+        cap = self.cfg[pset].max_batch
+        if self.mix_clients:
+            heap = [(q[0].t_arrive, i, c) for i, (c, q) in enumerate(adm.items())]
+            heapq.heapify(heap)
+            runs: Dict[int, List[Request]] = {}          # insertion order = order of first pick
+            n = 0
+            while heap and n < cap:
+                _, i, c = heapq.heappop(heap)
+                q = adm[c]
+                runs.setdefault(c, []).append(q.popleft())
+                n += 1
+                if q:
+                    heapq.heappush(heap, (q[0].t_arrive, i, c))
+            for c in runs:
+                if not adm[c]:
+                    del adm[c]
+            batch = [r for rs in runs.values() for r in rs]
+        else:
+            client = min(adm, key=lambda c: adm[c][0].t_arrive)
+            q = adm[client]
+            batch = [q.popleft() for _ in range(min(len(q), cap))]
+            if not q:
+                del adm[client]
         self._batch_id += 1
         for r in batch:
             r.status, r.t_launch, r.batch = "running", now, self._batch_id
@@ -247,7 +272,7 @@ class GpuServer:
     server holds them on the host and loads them into HBM on demand (KeyCache)."""
 
     def __init__(self, specs: Sequence[PsetSpec], key_budget: int, max_pending: int = 1 << 20,
-                 keep_outputs: bool = False, device: int = 0):
+                 keep_outputs: bool = False, device: int = 0, mix_clients: bool = True):
         import torch
         from . import Context
         self.torch = torch
@@ -274,7 +299,7 @@ class GpuServer:
                                   for c in ctxs]
             cfgs.append(PsetConfig(s.name, slots, s.max_batch, s.lanes))
         self.keys = KeyCache(key_budget, self._key_size, self._load_keys, self._unload_keys)
-        self.sched = Scheduler(cfgs, self.keys, max_pending)
+        self.sched = Scheduler(cfgs, self.keys, max_pending, mix_clients)
 
     # ------------------------------------------------------------------ clients and keys
     def register_client(self, client: int, pset: str, evaluation_keys: Dict[int, np.ndarray]):
@@ -333,12 +358,12 @@ class GpuServer:
                     break
                 n = len(batch)
                 ln.idx_host.numpy()[:n] = [r.slot for r in batch]
-                keys = self.keys.handle(batch[0].client)
+                keys = [self.keys.handle(r.client) for r in batch]
                 with torch.cuda.stream(ln.stream):
                     ln.stream.wait_stream(cur)       # the slot copies above
                     ln.idx[:n].copy_(ln.idx_host[:n], non_blocking=True)
                     torch.index_select(self.pool_in[name], 0, ln.idx[:n], out=ln.inp[:n])
-                    ln.ctx.forward(self.models[name], keys, ln.inp[:n], out=ln.out[:n], stream=ln.stream)
+                    ln.ctx.forward_multi(self.models[name], keys, ln.inp[:n], out=ln.out[:n], stream=ln.stream)
                     self.pool_out[name].index_copy_(0, ln.idx[:n], ln.out[:n])
                     ln.event = torch.cuda.Event()
                     ln.event.record(ln.stream)

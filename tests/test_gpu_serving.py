@@ -1,5 +1,6 @@
 """GPU test of the serving loop: queries of two parameter sets (N=2^13 and N=2^14) from four
-clients arrive as a Poisson stream and are served with continuous batching, with a key budget
+clients arrive as a Poisson stream and are served with continuous batching (batches mix clients,
+each evaluated with its own keys), with a key budget
 that holds only one N=2^14 client's keys at a time (so keys are evicted and uploaded again). Every
 result must equal, bit for bit, the same query evaluated alone with the client's own keys, and the
 decrypted results must match the FP64 forward pass."""
@@ -62,6 +63,10 @@ def test_serving_results_equal_alone_and_in_the_mix():
     assert st["completed"] == n_req, st
     assert srv.keys.evictions >= 1 and srv.keys.loads >= 3
     assert st["mean_batch"] > 1.0, st
+    by_batch = {}
+    for r in reqs:
+        by_batch.setdefault(r.batch, set()).add(r.client)
+    assert any(len(cs) > 1 for cs in by_batch.values())      # batches mixing clients ran
 
     for r, x, ct in zip(reqs, xs, inputs):
         m = cmodel[r.pset]

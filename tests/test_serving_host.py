@@ -56,7 +56,7 @@ def test_keycache_lru_and_pins():
 def test_scheduler_admission_batches_and_rejection():
     fk = FakeKeys({0: 1, 1: 1, 2: 1})
     kc = KeyCache(100, fk.size_of, fk.load, fk.unload)
-    s = Scheduler([PsetConfig("a", slots=3, max_batch=2, lanes=1)], kc, max_pending=5)
+    s = Scheduler([PsetConfig("a", slots=3, max_batch=2, lanes=1)], kc, max_pending=5, mix_clients=False)
     reqs = [Request(i, client=[0, 1, 0, 0, 2, 1][i], pset="a") for i in range(6)]
     for i, r in enumerate(reqs[:5]):
         assert s.arrive(r, float(i))
@@ -83,6 +83,26 @@ def test_scheduler_admission_batches_and_rejection():
     assert st["completed"] == 5 and st["rejected"] == 1
 
 
+def test_scheduler_mixed_batches_take_the_oldest_queries_grouped_by_client():
+    fk = FakeKeys({0: 1, 1: 1, 2: 1})
+    kc = KeyCache(100, fk.size_of, fk.load, fk.unload)
+    s = Scheduler([PsetConfig("a", slots=8, max_batch=5, lanes=1)], kc)
+    owners = [1, 0, 1, 2, 0, 0, 1]
+    reqs = [Request(i, client=c, pset="a") for i, c in enumerate(owners)]
+    for i, r in enumerate(reqs):
+        s.arrive(r, float(i))
+    assert len(s.admit(7.0)) == 7
+    b1 = s.next_batch("a", 8.0)
+    # the five oldest (0..4), client 1's run first (its oldest query is 0), then 0's, then 2's
+    assert [r.rid for r in b1] == [0, 2, 1, 4, 3]
+    assert [r.client for r in b1] == [1, 1, 0, 0, 2]
+    b2 = s.next_batch("a", 8.0)
+    assert [r.rid for r in b2] == [5, 6]
+    assert s.next_batch("a", 8.0) == []
+    s.finish(b1 + b2, 9.0)
+    assert s.idle() and kc.used == 3 and all(kc._pins.get(c, 0) == 0 for c in range(3))
+
+
 def test_scheduler_waits_for_keys_and_lets_others_pass():
     fk = FakeKeys({0: 6, 1: 6, 2: 2})
     kc = KeyCache(10, fk.size_of, fk.load, fk.unload)
@@ -99,15 +119,17 @@ def test_scheduler_waits_for_keys_and_lets_others_pass():
     assert [r.rid for r in got] == [1] and kc.evictions == 1
 
 
-def test_simulated_trace_invariants():
+@pytest.mark.parametrize("mix", [False, True])
+def test_simulated_trace_invariants(mix):
     """Discrete-event run: two parameter sets, eight clients, Poisson arrivals, batch time affine in
-    the batch size; checks slots, key residency, batch purity and that every query finishes once."""
+    the batch size; checks slots, key residency, batch composition (one client, or contiguous runs
+    of the oldest queries) and that every query finishes once."""
     rnd = random.Random(5)
     sizes = {c: (3 if c < 4 else 7) for c in range(8)}
     fk = FakeKeys(sizes)
     kc = KeyCache(20, fk.size_of, fk.load, fk.unload)
     cfgs = [PsetConfig("mid", slots=16, max_batch=8, lanes=2), PsetConfig("large", slots=6, max_batch=4, lanes=2)]
-    s = Scheduler(cfgs, kc)
+    s = Scheduler(cfgs, kc, mix_clients=mix)
     arr = poisson_arrivals(400.0, 600, seed=3)
     reqs = []
     for i, t in enumerate(arr):
@@ -141,10 +163,18 @@ def test_simulated_trace_invariants():
         for name, lns in lanes.items():
             for i, ln in enumerate(lns):
                 if ln is None:
+                    waiting = sorted((r.t_arrive, r.rid) for q in s.admitted[name].values() for r in q)
                     b = s.next_batch(name, now)
                     if b:
-                        assert len({r.client for r in b}) == 1 and {r.pset for r in b} == {name}
-                        assert b[0].client in kc.resident()
+                        assert {r.pset for r in b} == {name}
+                        clients = [r.client for r in b]
+                        if mix:
+                            assert sorted((r.t_arrive, r.rid) for r in b) == waiting[:len(b)]
+                            runs = [c for i, c in enumerate(clients) if i == 0 or clients[i - 1] != c]
+                            assert len(runs) == len(set(runs))          # each client one run
+                        else:
+                            assert len(set(clients)) == 1
+                        assert set(clients) <= set(kc.resident())
                         a, per = cost[name]
                         lns[i] = (now + a + per * len(b), b)
     assert all(r.status == "done" for r in reqs)
