@@ -104,6 +104,7 @@ class LayerPlan:
     square_after: bool
     next_t: int         # padded width of the next layer (replicate distance), 0 if last
     lazy: bool = False  # giant steps lowered by one ModDown of their summed key products
+    qp: bool = False    # baby steps kept over Q*P (implies one final ModDown of the giant steps)
 
 
 @dataclasses.dataclass
@@ -217,10 +218,11 @@ class CKKSOracle:
         return keys
 
     # ------------------------------------------------------------ encrypt / decrypt
-    def plaintext(self, m: np.ndarray, k: int) -> np.ndarray:
+    def plaintext(self, m: np.ndarray, k: int, ext: bool = False) -> np.ndarray:
+        """[k][N] NTT form over q_0..q_{k-1}; with ext a last row mod P ([k+1][N])."""
         m = np.ascontiguousarray(m, dtype=np.int64)
-        pt = np.zeros((k, self.n), dtype=np.uint64)
-        self.lib.or_plaintext(self.c, _p(m), k, _p(pt))
+        pt = np.zeros((k + (1 if ext else 0), self.n), dtype=np.uint64)
+        (self.lib.or_plaintext_ext if ext else self.lib.or_plaintext)(self.c, _p(m), k, _p(pt))
         return pt
 
     def encrypt(self, pk: np.ndarray, m: np.ndarray, seed: int) -> np.ndarray:
@@ -318,12 +320,15 @@ class CKKSOracle:
         return gs, arr
 
     def dense(self, ct: np.ndarray, pts: np.ndarray, t1: int, keys: Dict[int, np.ndarray],
-              lazy: bool = False, rescale: bool = True) -> np.ndarray:
+              lazy: bool = False, rescale: bool = True, qp: bool = False) -> np.ndarray:
+        """qp: baby steps over Q*P (pts then [t][k+1][N], see bank_ntt(ext=True))."""
         k = ct.shape[1]
         t = pts.shape[0]
+        if pts.shape[1] != k + (1 if qp else 0):
+            raise ValueError("plaintext rows do not match the variant")
         out = np.zeros((2, k - 1 if rescale else k, self.n), dtype=np.uint64)
         gs, arr = self._keyset(keys)
-        flags = (1 if lazy else 0) | (0 if rescale else 2)
+        flags = (1 if lazy else 0) | (0 if rescale else 2) | (4 if qp else 0)
         rc = self.lib.or_dense(self.c, k, _p(np.ascontiguousarray(ct)), _p(np.ascontiguousarray(pts)),
                                t, t1, flags, len(gs), _p(gs), arr, _p(out))
         if rc:
@@ -436,8 +441,9 @@ class CKKSOracle:
         return self.decode_coeffs(self.compose(self.decrypt(s, ct)), scale)
 
     # ------------------------------------------------------------ model plan
-    def plan(self, layers, lazy: bool = False) -> ModelPlan:
-        """layers: sequence of (n_in, n_out, t1); lazy selects the single-ModDown giant steps."""
+    def plan(self, layers, lazy: bool = False, qp: bool = False) -> ModelPlan:
+        """layers: sequence of (n_in, n_out, t1); lazy selects the single-ModDown giant steps, qp
+        the baby steps over Q*P."""
         ts = [max(a, b) for (a, b, _) in layers]
         block = 2 * max(ts)
         items = (self.n // 2) // block
@@ -452,7 +458,7 @@ class CKKSOracle:
                 raise ValueError("t1 must divide t")
             last = li == len(layers) - 1
             nxt = 0 if last else ts[li + 1]
-            plans.append(LayerPlan(n_in, n_out, t, t1, t // t1, k, not last, nxt, lazy))
+            plans.append(LayerPlan(n_in, n_out, t, t1, t // t1, k, not last, nxt, lazy, qp))
             scales.append(scale)
             rots += list(range(1, t1)) + [k2 * t1 for k2 in range(1, t // t1)]
             k -= 1                                    # dense rescale; scale preserved
@@ -502,13 +508,13 @@ class CKKSOracle:
         sc = float(self.q[layer.k - 1])
         return np.stack([self.encode(self.diag_slots(plan, layer, w, i), sc) for i in range(layer.t)])
 
-    def bank_ntt(self, bank: np.ndarray, k: int) -> np.ndarray:
-        return np.stack([self.plaintext(bank[i], k) for i in range(bank.shape[0])])
+    def bank_ntt(self, bank: np.ndarray, k: int, ext: bool = False) -> np.ndarray:
+        return np.stack([self.plaintext(bank[i], k, ext) for i in range(bank.shape[0])])
 
     def forward(self, plan: ModelPlan, ct: np.ndarray, banks_ntt: List[np.ndarray],
                 keys: Dict[int, np.ndarray], rlk: np.ndarray) -> np.ndarray:
         for li, layer in enumerate(plan.layers):
-            ct = self.dense(ct, banks_ntt[li], layer.t1, keys, layer.lazy)
+            ct = self.dense(ct, banks_ntt[li], layer.t1, keys, layer.lazy, qp=layer.qp)
             if layer.square_after:
                 ct = self.square(ct, rlk)
                 ct = self.replicate(ct, layer.next_t, keys)

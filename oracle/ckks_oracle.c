@@ -27,7 +27,9 @@
  * properties, NTT against the O(N^2) definition and negacyclic schoolbook products, automorphism
  * composition laws, ModDown/rescale against big-integer round(x/P), ChaCha20 against the RFC 8439
  * block test vector, decrypt(encrypt(m)) against m within the noise bound, hoisted rotations
- * against unhoisted ones, the BSGS dense layer against an FP64 matrix product.
+ * against unhoisted ones, the BSGS dense layer against an FP64 matrix product, its Q*P baby-step
+ * variant against the single-ModDown one where they coincide (t1 = 1) and against plain
+ * rotations when a unit plaintext selects one baby step.
  */
 #include <math.h>
 #include <stdint.h>
@@ -510,6 +512,12 @@ void or_plaintext(const or_ctx *c, const int64_t *m, int k, u64 *pt) {
     for (int i = 0; i < k; i++) small_to_ntt(c, i, m, pt + (size_t)i * c->n);
 }
 
+/* The same plaintext over q_0..q_{k-1}, P: [k+1][N], row k under the special prime. */
+void or_plaintext_ext(const or_ctx *c, const int64_t *m, int k, u64 *pt) {
+    or_plaintext(c, m, k, pt);
+    small_to_ntt(c, c->nq, m, pt + (size_t)k * c->n);
+}
+
 /* Public-key encryption at the top level: ct = (v b + e0 + m, v a + e1), [2][nq][N]. */
 void or_encrypt(const or_ctx *c, const u64 *pk, const int64_t *m, u64 seed, u64 *ct) {
     int n = c->n, nq = c->nq;
@@ -734,6 +742,93 @@ int or_square(const or_ctx *c, int k, const u64 *ct, const u64 *rlk, u64 *out) {
     return 0;
 }
 
+/* The dense layer with its baby steps kept over Q*P ("double hoisting": Bossuat, Mouchet,
+ * Troncoso-Pastoriza, Hubaux, Eurocrypt 2021). Every baby rotation stays in the extended basis,
+ *   ct~_j = (key product of sigma_j(c1)) + (P sigma_j(c0), 0),   ct~_0 = P ct,
+ * so that ModDown(ct~_j) = rot_j(ct) up to rounding; the plaintext products of Eq. (1) are taken
+ * over Q*P with plaintexts that carry a residue mod P as well, and only then lowered:
+ *   inner~_k2 = sum_j pt_{k2 t1 + j} ct~_j            (over Q*P)
+ *   giant step k2 >= 1: its c1 is lowered (ModDown), rotated by sigma = 5^{k2 t1} and key
+ *   switched; the key product plus sigma(c0 of inner~_k2) joins the extended sum,
+ *   out = ModDown(inner~_0 + sum_{k2 >= 1} (KS_k2 + (sigma(c0~_k2), 0))), then the rescale.
+ * The value is that of the other variants up to rounding (one ModDown per giant step plus one
+ * at the end, instead of one per baby rotation). pts: [t][k+1][N] (row k mod P). */
+static int dense_qp(const or_ctx *c, int k, const u64 *ct, const u64 *pts, int t1, int t2, int no_rescale,
+                    const keyset_t *ks, u64 *out) {
+    int n = c->n, nq = c->nq;
+    size_t kn = (size_t)k * n, en = (size_t)(k + 1) * n, ecs = 2 * en;
+    u64 *rots = (u64 *)calloc(ecs * t1, sizeof(u64));
+    u64 *dig = (u64 *)malloc(sizeof(u64) * (size_t)k * (k + 1) * n);
+    u64 *u = (u64 *)malloc(sizeof(u64) * ecs), *inner = (u64 *)malloc(sizeof(u64) * ecs);
+    u64 *acc = (u64 *)calloc(ecs, sizeof(u64)), *low = (u64 *)malloc(sizeof(u64) * 2 * kn);
+    u64 *i1 = (u64 *)malloc(sizeof(u64) * kn), *sc1 = (u64 *)malloc(sizeof(u64) * kn);
+    u64 *tmp = (u64 *)malloc(sizeof(u64) * n);
+    int primes[OR_MAXP], rc = 0;
+    for (int i = 0; i < k; i++) primes[i] = i;
+    primes[k] = nq;
+    /* j = 0: P ct (zero mod P) */
+    for (int p = 0; p < 2; p++)
+        for (int i = 0; i < k; i++) {
+            u64 q = c->q[i], pm = c->q[nq] % q;
+            for (int x = 0; x < n; x++) rots[p * en + (size_t)i * n + x] = mulm(pm, ct[p * kn + (size_t)i * n + x], q);
+        }
+    or_modup(c, k, ct + kn, dig);
+    for (int j = 1; j < t1; j++) {
+        u64 g = or_galois_elt(c, j);
+        const u64 *key = find_key(ks, g);
+        if (!key) { rc = -5; goto done; }
+        key_inner(c, k, dig, key, g, u);
+        u64 *r = rots + ecs * j;
+        memcpy(r, u, sizeof(u64) * ecs);
+        for (int i = 0; i < k; i++) {
+            u64 q = c->q[i], pm = c->q[nq] % q;
+            or_automorph_ntt(c, g, ct + (size_t)i * n, tmp);
+            for (int x = 0; x < n; x++) r[(size_t)i * n + x] = addm(r[(size_t)i * n + x], mulm(pm, tmp[x], q), q);
+        }
+    }
+    for (int k2 = 0; k2 < t2; k2++) {
+        memset(inner, 0, sizeof(u64) * ecs);
+        for (int j = 0; j < t1; j++) {
+            const u64 *pt = pts + (size_t)(k2 * t1 + j) * en;
+            const u64 *r = rots + ecs * j;
+            for (int p = 0; p < 2; p++)
+                for (int i = 0; i <= k; i++) {
+                    u64 q = c->q[primes[i]];
+                    for (int x = 0; x < n; x++) {
+                        size_t o = (size_t)i * n + x;
+                        inner[p * en + o] = addm(inner[p * en + o], mulm(pt[o], r[p * en + o], q), q);
+                    }
+                }
+        }
+        if (k2 == 0) {
+            memcpy(acc, inner, sizeof(u64) * ecs);
+            continue;
+        }
+        u64 g = or_galois_elt(c, (long)k2 * t1);
+        const u64 *key = find_key(ks, g);
+        if (!key) { rc = -5; goto done; }
+        drop_last(c, k, primes, inner + en, i1);            /* c1 of the giant step, over Q */
+        for (int i = 0; i < k; i++) or_automorph_ntt(c, g, i1 + (size_t)i * n, sc1 + (size_t)i * n);
+        or_modup(c, k, sc1, dig);
+        key_inner(c, k, dig, key, 1, u);
+        for (int i = 0; i <= k; i++) {
+            u64 q = c->q[primes[i]];
+            or_automorph_ntt(c, g, inner + (size_t)i * n, tmp);
+            for (int x = 0; x < n; x++) {
+                size_t o = (size_t)i * n + x;
+                acc[o] = addm(acc[o], addm(u[o], tmp[x], q), q);
+                acc[en + o] = addm(acc[en + o], u[en + o], q);
+            }
+        }
+    }
+    or_moddown(c, k, acc, low);
+    if (no_rescale) memcpy(out, low, sizeof(u64) * 2 * kn);
+    else or_rescale(c, k, low, out);
+done:
+    free(rots); free(dig); free(u); free(inner); free(acc); free(low); free(i1); free(sc1); free(tmp);
+    return rc;
+}
+
 /* Baby-step giant-step diagonal dense layer at k live primes (Eq. (1) of the paper):
  *   out = sum_{k2 < t2} rot_{k2 t1}( sum_{j < t1} pt_{k2 t1 + j} * rot_j(ct) ),
  * baby rotations hoisted, one rescale at the end. Giant steps: with lazy == 0 each rotation is a
@@ -741,7 +836,8 @@ int or_square(const or_ctx *c, int k, const u64 *ct, const u64 *rlk, u64 *out) {
  * are summed over Q*P and lowered by a single ModDown (same value up to rounding: one rounding of
  * the sum instead of one per giant step). pts: [t][k][N] NTT form. Returns -5 if a needed
  * rotation key is missing. flags: bit 0 = lazy giant steps; bit 1 = skip the final rescale and
- * return the [2][k][N] sum itself (used by tests to compare the two giant-step variants). */
+ * return the [2][k][N] sum itself (used by tests to compare the variants); bit 2 = baby steps over
+ * Q*P (dense_qp above; its giant steps are lowered by one final ModDown, and pts is [t][k+1][N]). */
 int or_dense(const or_ctx *c, int k, const u64 *ct, const u64 *pts, int t, int t1, int flags,
              int n_keys, const u64 *gs, const u64 *const *keys, u64 *out) {
     const int lazy = flags & 1, no_rescale = flags & 2;
@@ -749,6 +845,7 @@ int or_dense(const or_ctx *c, int k, const u64 *ct, const u64 *pts, int t, int t
     size_t kn = (size_t)k * n, cts = 2 * kn;
     keyset_t ks = {n_keys, gs, keys};
     if (t1 * t2 != t) return -1;
+    if (flags & 4) return dense_qp(c, k, ct, pts, t1, t2, no_rescale, &ks, out);
     u64 *rots = (u64 *)malloc(sizeof(u64) * cts * t1);
     u64 *dig = (u64 *)malloc(sizeof(u64) * (size_t)k * (k + 1) * n);
     u64 *inner = (u64 *)malloc(sizeof(u64) * cts), *acc = (u64 *)calloc(cts, sizeof(u64));

@@ -441,6 +441,66 @@ def test_forward_lazy_giant_matches_fp64(name, tol_log2):
     assert normwise_error(y, o.forward_fp64(ws, x)) < 2.0 ** tol_log2
 
 
+# ------------------------------------------------------------------ baby steps over Q*P
+def _qp_setup(rots):
+    o = CKKSOracle.for_workload(W.SMALL)
+    s = o.keygen_secret(41)
+    pk = o.keygen_public(41, s)
+    keys = o.keygen_rotations(41, s, rots)
+    ct = o.encrypt(pk, W.raw_plaintexts(42, 1, o.n)[0], 43)
+    return o, s, keys, ct
+
+
+def test_qp_baby_steps_without_baby_rotations_equal_lazy():
+    """t1 = 1: the only baby term is P ct, whose ModDown is ct exactly, so every giant step sees
+    the same c1 and the final ModDown absorbs the P multiples exactly: the Q*P variant must equal
+    the single-ModDown variant bit for bit (a check of its giant steps and final sum)."""
+    t = 8
+    o, s, keys, ct = _qp_setup(list(range(1, t)))
+    bank = W.raw_plaintexts(44, t, o.n, bound_bits=40)
+    k = o.nq
+    for rescale in (False, True):
+        a = o.dense(ct, o.bank_ntt(bank, k), 1, keys, lazy=True, rescale=rescale)
+        b = o.dense(ct, o.bank_ntt(bank, k, ext=True), 1, keys, rescale=rescale, qp=True)
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("j", [0, 1, 5, 7])
+def test_qp_unit_diagonal_selects_one_rotation(j):
+    """t2 = 1 and every plaintext zero except pt_j = 1: the output before the rescale is
+    ModDown(ct~_j), which must be the rotation rot_j(ct) computed by the plain (unhoisted) key
+    switch, bit for bit (ModDown of P sigma(c0) is sigma(c0) exactly); j = 0 gives ct itself."""
+    t1 = 8
+    o, s, keys, ct = _qp_setup(list(range(1, t1)))
+    k = o.nq
+    raw = np.zeros((t1, o.n), dtype=np.int64)
+    raw[j, 0] = 1
+    out = o.dense(ct, o.bank_ntt(raw, k, ext=True), t1, keys, rescale=False, qp=True)
+    if j == 0:
+        assert np.array_equal(out, ct)
+    else:
+        g = o.galois_elt(j)
+        assert np.array_equal(out, o.rotate(ct, keys[g], g))
+
+
+@pytest.mark.parametrize("name,tol_log2", [("mid", -20), ("large", -20)])
+def test_forward_qp_baby_steps_matches_fp64(name, tol_log2):
+    w = W.WORKLOADS[name]
+    o = CKKSOracle.for_workload(w)
+    plan = o.plan([(l.n_in, l.n_out, l.t1) for l in w.layers], lazy=True, qp=True)
+    s = o.keygen_secret(w.seed_keys)
+    pk = o.keygen_public(w.seed_keys, s)
+    keys = o.keygen_rotations(w.seed_keys, s, plan.rotations)
+    rlk = o.keygen_relin(w.seed_keys, s)
+    ws = W.weights(w)
+    x = W.inputs(w, 1, plan.items)[0]
+    ct = o.encrypt(pk, o.encode(o.input_slots(plan, x), o.scale), w.seed_encrypt)
+    banks = [o.bank_ntt(o.layer_bank(plan, li, ws[li]), plan.layers[li].k, ext=True) for li in range(len(ws))]
+    out = o.forward(plan, ct, banks, keys, rlk)
+    y = o.output_slots(plan, o.decrypt_decode(s, out, plan.scales[-1]))
+    assert normwise_error(y, o.forward_fp64(ws, x)) < 2.0 ** tol_log2
+
+
 def test_seeded_symmetric_encryption():
     """(-a s + e + m, a): decryption returns m + e exactly with |e| within the Gaussian's tail cut,
     and c1 is the uniform stream of the seed (its first prime's row equals the sampler's output)."""
