@@ -76,6 +76,7 @@ def _traffic(kernel: str, digest: str):
 
 
 _ORACLE_WORKLOAD = None
+_ORACLE_VARIANT = "qp"
 
 
 def _oracle_job(i: int):
@@ -84,13 +85,14 @@ def _oracle_job(i: int):
     from oracle import CKKSOracle
     w = _ORACLE_WORKLOAD
     o = CKKSOracle.for_workload(w)
-    plan = o.plan([(l.n_in, l.n_out, l.t1) for l in w.layers], lazy=True)
+    v = _variant_flags(_ORACLE_VARIANT)
+    plan = o.plan([(l.n_in, l.n_out, l.t1) for l in w.layers], **v)
     s = o.keygen_secret(w.seed_keys)
     pk = o.keygen_public(w.seed_keys, s)
     keys = o.keygen_rotations(w.seed_keys, s, plan.rotations)
     rlk = o.keygen_relin(w.seed_keys, s)
     ws = W.weights(w)
-    banks = [o.bank_ntt(o.layer_bank(plan, li, ws[li]), plan.layers[li].k) for li in range(len(ws))]
+    banks = [o.bank_ntt(o.layer_bank(plan, li, ws[li]), plan.layers[li].k, ext=v["qp"]) for li in range(len(ws))]
     x = W.inputs(w, i + 1, plan.items, stream=7)[i]
     ct = o.encrypt(pk, o.encode(o.input_slots(plan, x), o.scale), w.seed_encrypt + i)
     t0 = time.time()
@@ -98,18 +100,19 @@ def _oracle_job(i: int):
     return t0, time.time()
 
 
-def cpu_pool(workers: int):
+def cpu_pool(workers: int, variant: str):
     """Fork the oracle workers now, before this process touches the GPU; they stay idle until
     cpu_baseline hands them work."""
     import multiprocessing as mp
-    global _ORACLE_WORKLOAD
+    global _ORACLE_WORKLOAD, _ORACLE_VARIANT
     _ORACLE_WORKLOAD = W.LARGE
+    _ORACLE_VARIANT = variant
     return mp.get_context("fork").Pool(workers)
 
 
 def cpu_baseline(pool, workers: int):
     """The CPU oracle as it stands: one ciphertext of the large workload per worker process, all
-    at once, single-ModDown giant steps as in the GPU headline. Throughput = ciphertexts / (last
+    at once, the same dense-layer variant as the GPU headline. Throughput = ciphertexts / (last
     end - first start) of the forward passes; set-up is excluded."""
     spans = pool.map(_oracle_job, range(workers), chunksize=1)
     pool.close()
@@ -128,8 +131,15 @@ def cpu_baseline(pool, workers: int):
             "kind": "oracle", "single_ct_s": round(sorted(per)[len(per) // 2], 3),
             "host": {"cpu": cpu, "nproc": os.cpu_count()},
             "sample": "%d ciphertexts of the large workload, one per worker process, through the C "
-                      "oracle's forward pass (single-ModDown giant steps) run together (%.1f s wall; "
-                      "key generation, bank encoding and encryption excluded)" % (workers, t1 - t0)}
+                      "oracle's forward pass (%s variant) run together (%.1f s wall; key generation, "
+                      "bank encoding and encryption excluded)" % (workers, _ORACLE_VARIANT, t1 - t0)}
+
+
+VARIANTS = ("qp", "lazy", "per-step")
+
+
+def _variant_flags(v: str):
+    return {"lazy": v != "per-step", "qp": v == "qp"}
 
 
 def main():
@@ -143,10 +153,11 @@ def main():
                     help="oracle worker processes for the CPU leg, one ciphertext each, capped at the host's "
                          "cores (0: skip)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket launches with events")
-    ap.add_argument("--giant", choices=("lazy", "per-step"), default="lazy",
-                    help="giant steps lowered by one ModDown of their summed key products (lazy) or one "
-                         "ModDown each (per-step); the other variant is timed too, without profiling")
-    ap.add_argument("--other-steps", type=int, default=3, help="timed steps of the other giant-step variant")
+    ap.add_argument("--variant", choices=VARIANTS, default="qp",
+                    help="dense-layer variant: baby steps kept over Q*P with one ModDown per giant step "
+                         "(qp), single-ModDown giant steps (lazy) or one ModDown per rotation (per-step); "
+                         "the other two are timed too, without profiling")
+    ap.add_argument("--other-steps", type=int, default=3, help="timed steps of each other variant")
     ap.add_argument("--workload", choices=("large", "mix", "serve", "cnn"), default="large",
                     help="large: the 768->256->64 stack, batch 64 (the headline); mix: 512 queries of "
                          "1-3 layers with widths from {128,256,512,768}; serve: the serving loop alone; "
@@ -172,7 +183,7 @@ def main():
     pool, workers = None, 0
     if args.cpu_sample > 0 and args.workload == "large":
         workers = max(1, min(args.cpu_sample, os.cpu_count() or 1, 16))
-        pool = cpu_pool(workers)
+        pool = cpu_pool(workers, args.variant)
 
     import torch
     import paper_2205_11935_amd as ctl
@@ -191,9 +202,9 @@ def main():
     c = ctl.Context.for_workload(w)
     layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
     t_setup = time.perf_counter()
-    lazy = args.giant == "lazy"
-    model = c.load_model(layers, W.weights(w), lazy=lazy)
-    other = c.load_model(layers, W.weights(w), lazy=not lazy) if args.other_steps > 0 else None
+    model = c.load_model(layers, W.weights(w), **_variant_flags(args.variant))
+    others = {v: c.load_model(layers, W.weights(w), **_variant_flags(v))
+              for v in VARIANTS if v != args.variant} if args.other_steps > 0 else {}
     keys = c.keygen(w.seed_keys, model.info.rotations, relin=True)
     x = W.inputs(w, B, model.info.items)
     ct = c.empty_ct(B, c.nq)
@@ -240,9 +251,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # ---------------------------------------------------------------- the other giant-step variant
-    other_line = None
-    if other is not None:
+    # ---------------------------------------------------------------- the other dense-layer variants
+    other_lines = []
+    for v, other in others.items():
         c.forward(other, keys, ct, out=out)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -250,9 +261,10 @@ def main():
             c.forward(other, keys, ct, out=out)
         torch.cuda.synchronize()
         other_elapsed = time.perf_counter() - t0
-        other_line = {"giant": "per-step" if lazy else "lazy", "steps": args.other_steps,
-                      "value": round(B * args.other_steps / other_elapsed, 3),
-                      "ms_per_step": round(other_elapsed / args.other_steps * 1e3, 3)}
+        other_lines.append({"variant": v, "steps": args.other_steps,
+                            "value": round(B * args.other_steps / other_elapsed, 3),
+                            "ms_per_step": round(other_elapsed / args.other_steps * 1e3, 3)})
+    if others:
         c.forward(model, keys, ct, out=out)     # leave the headline variant's output in `out`
 
     # decrypted spot check of the last step (ciphertext 0) against the FP64 forward pass
@@ -357,8 +369,8 @@ def main():
         "config": {"workload": "large: N=2^14, q={60,40,40,40,40,60}+P60, scale 2^40, 768->256->64 x^2, "
                                "%d ciphertexts per launch sequence" % B,
                    "global_batch": B, "items_per_ct": model.info.items, "layers": "768->256->64",
-                   "giant_steps": args.giant, "parallelism": "single GPU"},
-        "other_variant": other_line,
+                   "variant": args.variant, "t1": [l.t1 for l in w.layers], "parallelism": "single GPU"},
+        "other_variants": other_lines,
         "autotune": tuning,
         "items_per_s": round(value * model.info.items, 2),
         "batched_step_ms": {"p50": _percentile(step_ms, 50), "p99": _percentile(step_ms, 99)},
@@ -372,7 +384,7 @@ def main():
         "workspace_gib": round(c.workspace_bytes() / 2 ** 30, 2),
     }
     if args.serve_seconds > 0 or args.paper_stack:
-        del c, model, other, keys, ct, out, one, one_out, buf
+        del c, model, others, keys, ct, out, one, one_out, buf
         import gc
         gc.collect()
         torch.cuda.empty_cache()
@@ -402,7 +414,7 @@ def serving_sweep(args):
              PsetSpec("large", W.LARGE, W.weights(W.LARGE), slot_bytes_budget=2 << 30, max_batch=64, lanes=2)]
     clients = {c: ("mid" if c < 4 else "large") for c in range(8)}
     cctx = {p: ctl.Context.for_workload(wl[p]) for p in wl}
-    cmodel = {p: cctx[p].load_model([(l.n_in, l.n_out, l.t1) for l in wl[p].layers], W.weights(wl[p]), lazy=True)
+    cmodel = {p: cctx[p].load_model([(l.n_in, l.n_out, l.t1) for l in wl[p].layers], W.weights(wl[p]), lazy=True, qp=True)
               for p in wl}
     uploads, cts = {}, {}
     g = np.random.Generator(np.random.PCG64(W.MIX_SEED + 9))
@@ -472,7 +484,7 @@ def cnn_measure(name: str, batch: int, steps: int, plain_steps: int = 5):
               ctl.Layer.avgpool(w.width, w.f_pool),
               ctl.Layer.dense(w.pooled, w.pooled, w.t1)]
     taps, w1, w2 = W.cnn_weights(w)
-    m = c.load_model(layers, [taps, w1, None, w2], lazy=True)
+    m = c.load_model(layers, [taps, w1, None, w2], lazy=True, qp=True)
     keys = c.keygen(w.seed_keys, m.info.rotations, relin=True)
     x = W.cnn_inputs(w, batch, m.info.items)
     ct = c.empty_ct(batch, c.nq)

@@ -220,18 +220,27 @@ int ctl_evk_bytes(const ctl_evk *evk, uint64_t *bytes_out);
  * over Q*P and lowered by a single ModDown (same value up to rounding, one rounding instead of
  * t2 - 1, about 40% fewer residue transforms in the ModDown kernels). */
 #define CTL_LAYER_LAZY_GIANT 1
+/* Baby steps kept over Q*P ("double hoisting", Bossuat et al., Eurocrypt 2021): each baby-step
+ * rotation of a dense layer stays in the extended basis (its key product plus P sigma_j(c0), no
+ * ModDown), the diagonal plaintexts are stored with a residue mod P as well, the products of
+ * Eq. (1) are summed over Q*P, and only the c1 of each giant step and the final sum are lowered:
+ * t2 + 1 polynomials per ciphertext go through ModDown instead of 2 t1. Implies
+ * CTL_LAYER_LAZY_GIANT. Same value up to rounding; the bank takes (k+1)/k of the memory. Dense
+ * layers only. */
+#define CTL_LAYER_BABY_QP 2
 
 /* One layer. A dense layer y = W x with W of shape [n_out][n_in] is evaluated by the baby-step
  * giant-step diagonal method (Eq. (1) of Section 3.1) with padded width t = max(off + n_in, n_out),
  * t = t1 * t2 (t1 must divide t; off = f - 1 after an average pool, else 0). act applies x^2
  * (CTL_ACT_SQUARE) or the cubic in coef (CTL_ACT_POLY3) after the layer, never after the last.
- * flags: 0 or CTL_LAYER_LAZY_GIANT (dense only). Zero-filled fields select a dense layer. */
+ * flags: 0, CTL_LAYER_LAZY_GIANT or CTL_LAYER_BABY_QP (dense only). Zero-filled fields select a
+ * dense layer. */
 typedef struct ctl_layer_desc {
     int n_in;
     int n_out;
     int t1;          /* dense: baby steps (divides the padded width) */
     int act;         /* CTL_ACT_* applied after the layer (not after the last) */
-    int flags;       /* CTL_LAYER_LAZY_GIANT */
+    int flags;       /* CTL_LAYER_LAZY_GIANT, CTL_LAYER_BABY_QP */
     int kind;        /* CTL_LAYER_* */
     int f;           /* conv / pool size */
     double coef[4];  /* CTL_ACT_POLY3: c0..c3 */

@@ -125,15 +125,16 @@ def banks(p: CnnPlan, o: CKKSOracle, taps, w1, w2) -> Dict[str, np.ndarray]:
 
 
 def forward(p: CnnPlan, o: CKKSOracle, ct: np.ndarray, raw: Dict[str, np.ndarray], keys, rlk,
-            coef: Sequence[float]) -> np.ndarray:
-    """The encrypted frozen stack on one top-level ciphertext; raw: int64 plaintexts (see banks)."""
+            coef: Sequence[float], qp: bool = False) -> np.ndarray:
+    """The encrypted frozen stack on one top-level ciphertext; raw: int64 plaintexts (see banks).
+    Dense layers with single-ModDown giant steps; qp: their baby steps over Q*P as well."""
     conv = np.stack([o.plaintext(m, p.k_conv) for m in raw["conv"]])
     ct = o.conv1d(ct, conv, keys)
-    ct = o.dense(ct, o.bank_ntt(raw["dense1"], p.k_dense1), p.t1, keys, lazy=True)
+    ct = o.dense(ct, o.bank_ntt(raw["dense1"], p.k_dense1, ext=qp), p.t1, keys, lazy=True, qp=qp)
     ct, _ = o.poly3(ct, p.scale_in, coef, rlk)
     ct = o.avgpool(ct, o.plaintext(raw["pool"], p.k_pool), p.f_pool, keys)
     ct = o.replicate(ct, p.width, keys)
-    return o.dense(ct, o.bank_ntt(raw["dense2"], p.k_dense2), p.t1, keys, lazy=True)
+    return o.dense(ct, o.bank_ntt(raw["dense2"], p.k_dense2, ext=qp), p.t1, keys, lazy=True, qp=qp)
 
 
 def forward_fp64(x: np.ndarray, taps, w1, w2, coef: Sequence[float], f_pool: int) -> np.ndarray:

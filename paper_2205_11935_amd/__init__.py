@@ -21,6 +21,7 @@ CTL_ACT_NONE = 0
 CTL_ACT_SQUARE = 1
 CTL_ACT_POLY3 = 2
 CTL_LAYER_LAZY_GIANT = 1
+CTL_LAYER_BABY_QP = 2
 CTL_KNOB_MAC_CHUNK = 0
 CTL_KNOB_MAC_CTS = 1
 CTL_KNOB_KEYIP_XCD = 2
@@ -481,7 +482,7 @@ class Context:
 
     # ------------------------------------------------------------ server side
     @staticmethod
-    def _descs(layers, lazy: bool):
+    def _descs(layers, lazy: bool, qp: bool = False):
         arr = (_LayerDesc * len(layers))()
         for i, l in enumerate(layers):
             if isinstance(l, Layer):
@@ -494,7 +495,8 @@ class Context:
                 arr[i].n_in, arr[i].n_out, arr[i].t1 = l[0], l[1], l[2]
                 arr[i].act = l[3] if len(l) > 3 else (CTL_ACT_SQUARE if i + 1 < len(layers) else CTL_ACT_NONE)
                 lazy_ok = True
-            arr[i].flags = CTL_LAYER_LAZY_GIANT if (lazy and lazy_ok) else 0
+            arr[i].flags = (CTL_LAYER_BABY_QP if (qp and lazy_ok) else
+                            CTL_LAYER_LAZY_GIANT if (lazy and lazy_ok) else 0)
         return arr
 
     @staticmethod
@@ -503,26 +505,27 @@ class Context:
         ws = [None if w is None else np.ascontiguousarray(w, dtype=np.float64) for w in weights]
         return ws, (f64p * len(ws))(*[None if w is None else w.ctypes.data_as(f64p) for w in ws])
 
-    def load_model(self, layers, weights: Sequence[np.ndarray], lazy: bool = False) -> Model:
+    def load_model(self, layers, weights: Sequence[np.ndarray], lazy: bool = False, qp: bool = False) -> Model:
         """layers: Layer descriptors or (n_in, n_out, t1[, act]) dense tuples; weights per layer:
         float64 [n_out][n_in] (dense), [f] taps (convolution), None (average pool);
-        lazy: single-ModDown giant steps (CTL_LAYER_LAZY_GIANT) on every dense layer."""
+        lazy: single-ModDown giant steps (CTL_LAYER_LAZY_GIANT) on every dense layer; qp: baby
+        steps over Q*P as well (CTL_LAYER_BABY_QP)."""
         ws, ptrs = self._f64_ptrs(weights)
         h = ctypes.c_void_p()
-        _check(lib().ctl_model_load(self.handle, self._descs(layers, lazy), len(layers), ptrs, ctypes.byref(h)))
+        _check(lib().ctl_model_load(self.handle, self._descs(layers, lazy, qp), len(layers), ptrs, ctypes.byref(h)))
         return Model(self, h)
 
-    def load_model_raw(self, layers, pts: Sequence[np.ndarray], lazy: bool = False) -> Model:
+    def load_model_raw(self, layers, pts: Sequence[np.ndarray], lazy: bool = False, qp: bool = False) -> Model:
         """pts: int64 [t][N] encoded diagonal plaintexts per layer."""
         ps = [np.ascontiguousarray(p, dtype=np.int64) for p in pts]
         ptrs = (i64p * len(ps))(*[p.ctypes.data_as(i64p) for p in ps])
         h = ctypes.c_void_p()
-        _check(lib().ctl_model_load_raw(self.handle, self._descs(layers, lazy), len(layers), ptrs,
+        _check(lib().ctl_model_load_raw(self.handle, self._descs(layers, lazy, qp), len(layers), ptrs,
                                         ctypes.byref(h)))
         return Model(self, h)
 
     def load_model_ex(self, layers, weights=None, pts=None, lazy: bool = False, block: int = 0, k_in: int = 0,
-                      scale_in: float = 0.0) -> Model:
+                      scale_in: float = 0.0, qp: bool = False) -> Model:
         """One of weights (float64 [n_out][n_in] per layer) or pts (int64 [t][N] per layer), with plan
         overrides: a shared slot stride `block`, the starting level `k_in`, the input scale."""
         opts = _ModelOpts(block, k_in, scale_in)
@@ -533,7 +536,7 @@ class Context:
         if pts is not None:
             ps = [np.ascontiguousarray(p, dtype=np.int64) for p in pts]
             pp = (i64p * len(ps))(*[p.ctypes.data_as(i64p) for p in ps])
-        _check(lib().ctl_model_load_ex(self.handle, self._descs(layers, lazy), len(layers), wp, pp,
+        _check(lib().ctl_model_load_ex(self.handle, self._descs(layers, lazy, qp), len(layers), wp, pp,
                                        ctypes.byref(opts), ctypes.byref(h)))
         return Model(self, h)
 

@@ -25,11 +25,12 @@ from . import CTL_ACT_NONE, Context, Keys, Model
 class MixEngine:
     def __init__(self, ctx: Context, keys: Keys, bank: Callable[[int, int, int, int], np.ndarray],
                  t1_of: Dict[int, int], block: int, raw: bool = False, lazy: bool = True,
-                 graphs: bool = False):
+                 graphs: bool = False, qp: bool = True):
         """bank(pos, w_in, w_out, t) gives the layer's float64 weights [w_out][w_in] (raw=False) or
-        its int64 [t][N] encoded diagonal plaintexts (raw=True)."""
+        its int64 [t][N] encoded diagonal plaintexts (raw=True). lazy / qp: the dense-layer variant
+        (single-ModDown giant steps; baby steps over Q*P as well)."""
         self.c, self.keys, self.bank, self.t1_of = ctx, keys, bank, t1_of
-        self.block, self.raw, self.lazy, self.graphs = block, raw, lazy, graphs
+        self.block, self.raw, self.lazy, self.graphs, self.qp = block, raw, lazy, graphs, qp
         self.models: Dict[Tuple[int, int, int], Model] = {}
         self._graphs: Dict[Tuple, Tuple] = {}
         self._frozen = False
@@ -45,7 +46,7 @@ class MixEngine:
             t = max(w_in, w_out)
             layer = [(w_in, w_out, self.t1_of[t], CTL_ACT_NONE)]
             src = self.bank(pos, w_in, w_out, t)
-            kw = dict(lazy=self.lazy, block=self.block, k_in=self.level(pos))
+            kw = dict(lazy=self.lazy, qp=self.qp, block=self.block, k_in=self.level(pos))
             self.models[key] = (self.c.load_model_ex(layer, pts=[src], **kw) if self.raw
                                 else self.c.load_model_ex(layer, weights=[src], **kw))
         return self.models[key]

@@ -92,6 +92,7 @@ struct ctl_evk {
 struct LayerPlan {
     int n_in, n_out, t, t1, t2, k, act;
     bool lazy;
+    bool qp = false;              // baby steps over Q*P: the bank carries a row mod P
     double pt_scale;
     int kind = CTL_LAYER_DENSE;
     int f = 0;                    // convolution / pooling size
@@ -275,10 +276,13 @@ int need_key(const KeySet &ks, u64 id, const std::string &what) {
 // ---------------------------------------------------------------- building blocks
 // Raise and multiply: for G = B R polynomials d (k residues each, located by dmap over B*R*k
 // residues, group order (b, r)), U[b][r] = sum_j ModUp(d)_j * key_r[j] gathered through
-// sigma_{gal[r]}, as [B][R][2][k+1][N] over q_0..q_{k-1}, P. `hoisted` = the same d for every r
-// (dmap covers B*k residues only). Returns the U buffer (workspace slot S_U).
+// sigma_{gal[r]} (plus the fold term, see KeyFold), as [2][k+1][N] over q_0..q_{k-1}, P.
+// `hoisted` = the same d for every r (dmap covers B*k residues only). U goes to U_dst with batch
+// stride U_sb and [R][2][k+1][N] per ciphertext, or, with U_dst null, to workspace slot S_U as
+// [B][R][2][k+1][N]; *U_out receives its address.
 int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *d, const ResMap &dmap,
-                    bool hoisted, const KeySet &ks, const u64 *key_ids, const u64 *gal, u64 **U_out) {
+                    bool hoisted, const KeySet &ks, const u64 *key_ids, const u64 *gal, u64 **U_out,
+                    const KeyFold *fold = nullptr, u64 *U_dst = nullptr, long U_sb = 0) {
     const int logn = c->hp.logn, nq = c->hp.nq;
     const long N = c->hp.n;
     if (R > kMaxKeysPerLaunch) return fail(CTL_EINVAL, "too many rotations in one layer");
@@ -286,7 +290,14 @@ int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
     u64 *coef, *dig, *U;
     CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
     CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
-    CTL_TRY(slot(c, S_U, (size_t)B * R * 2 * (k + 1) * N, st, &U));
+    if (U_dst) {
+        U = U_dst;
+    } else {
+        CTL_TRY(slot(c, S_U, (size_t)B * R * 2 * (k + 1) * N, st, &U));
+        U_sb = (long)R * 2 * (k + 1) * N;
+    }
+    KeyFold fd{};
+    if (fold) fd = *fold;
     { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
     { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st); }
     const long dsz = (long)k * (k + 1) * N, db = hoisted ? dsz : (long)R * dsz;
@@ -298,8 +309,10 @@ int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
             if (!kl.key[r]) return fail(CTL_EKEY, "missing evaluation key");
             kl.gal[r] = gal[r];
         }
-        launch_keyip(logn, k, dig + run.b0 * db, db, hoisted ? 0 : dsz, kl, R,
-                     U + (long)run.b0 * R * 2 * (k + 1) * N, run.nb, nq, c->tab, c->knobs, st);
+        KeyFold fr = fd;
+        if (fr.src) fr.src += run.b0 * fr.sb;
+        launch_keyip(logn, k, dig + run.b0 * db, db, hoisted ? 0 : dsz, kl, R, U + run.b0 * U_sb, U_sb, fr,
+                     run.nb, nq, c->tab, c->knobs, st);
     }
     *U_out = U;
     return check_launch();
@@ -493,6 +506,73 @@ int poly3_batch(ctl_ctx *c, hipStream_t st, const KeySet &ks, int k, int B, doub
     return check_launch();
 }
 
+// Dense layer with the baby steps kept over Q*P (double hoisting, see CTL_LAYER_BABY_QP):
+//   rot~[b][0] = P ct,  rot~[b][j] = U_j + (P sigma_j(c0), 0)        [B][t1][2][k+1][N]
+//   inner~[b][k2] = sum_j pt~_{k2 t1 + j} rot~[b][j]                   [B][t2][2][k+1][N]
+//   I1[b][k2-1] = ModDown(c1 of inner~[b][k2]), k2 >= 1                [B][t2-1][k][N]
+//   usum[b] = inner~[b][0] + sum_{k2 >= 1} (KS_k2(sigma I1) + (sigma(c0 of inner~[b][k2]), 0))
+//   out = rescale(ModDown(usum)).
+// The bank of such a layer carries a last row mod P ([t][k+1][N]).
+int dense_qp_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const KeySet &ks, int B,
+                   const u64 *in, u64 *out, const std::vector<u64> &gal1, const std::vector<u64> &gal2) {
+    const LayerPlan &L = m->layers[li];
+    const int logn = c->hp.logn, nq = c->hp.nq, k = L.k, t1 = L.t1, t2 = L.t2;
+    const int R1 = t1 - 1, R2 = t2 - 1;
+    const long N = c->hp.n, ctw = 2L * k * N, ext = 2L * (k + 1) * N;
+    u64 *rot, *inner, *acc;
+    CTL_TRY(slot(c, S_ROT, (size_t)B * t1 * ext, st, &rot));
+    CTL_TRY(slot(c, S_INNER, (size_t)B * t2 * ext, st, &inner));
+    CTL_TRY(slot(c, S_SUM, (size_t)B * ctw, st, &acc));
+    { CTL_PROF(F_ADD, (double)B * ext, 0.0); launch_times_p(logn, in, rot, (long)t1 * ext, B, k, nq, c->tab, st); }
+    if (R1 > 0) {
+        KeyFold fd{};
+        fd.src = in;                        // c0, gathered through sigma_j and scaled by P
+        fd.sb = ctw;
+        fd.sr = 0;
+        fd.rows = k;
+        for (int t = 0; t < k; ++t) fd.mul[t] = c->hp.mods[nq] % c->hp.mods[t];
+        u64 *U;
+        CTL_TRY(keyswitch_raise(c, st, k, B, R1, in, c1_map(k), true, ks, gal1.data(), gal1.data(), &U, &fd,
+                                rot + ext, (long)t1 * ext));
+    }
+    { CTL_PROF(F_MAC, 2.0 * B * (k + 1) * t1 * t2 * N, fp_share_range(c, k, false)); launch_mac(logn, rot, (long)t1 * ext, rot + ext, (long)t1 * ext, m->banks[li], inner, B, k + 1, nq, t1, t2, c->tab, c->knobs, st); }
+    CTL_TRY(check_launch());
+    DropAdd none{};
+    none.R = 1;
+    none.mask = 0;
+    none.gal[0] = 1;
+    const u64 *usum = inner;                // t2 = 1: inner~[b][0] is the whole sum
+    if (R2 > 0) {
+        u64 *i1, *plast, *U, *sum;
+        CTL_TRY(slot(c, S_COEF2, (size_t)B * R2 * k * N, st, &i1));
+        CTL_TRY(slot(c, S_PLAST, (size_t)B * R2 * N, st, &plast));
+        ResMap pm{};                        // the P rows of the c1 of inner~[b][k2], k2 >= 1
+        pm.per = 1;
+        pm.ngrp = R2;
+        pm.off = 3L * (k + 1) + k;
+        pm.gstride = 2L * (k + 1);
+        pm.ostride = (long)t2 * 2 * (k + 1);
+        pm.prime[0] = nq;
+        { CTL_PROF(F_NTT_INV, B * R2, fp_share_range(c, 0, true)); launch_ntt(logn, true, inner, pm, plast, dense_map(1, nq), B * R2, c->tab, st); }
+        GrpMap xm{3L * (k + 1) * N, (long)t2 * ext, ext, R2};
+        { CTL_PROF(F_DROP, (double)B * R2 * k, fp_share_range(c, k, false)); launch_drop(logn, inner, plast, i1, B * R2, k, nq, none, c->tab, c->knobs, st, &xm); }
+        KeyFold fg{};
+        fg.src = inner + ext;               // c0 of inner~[b][1], all k + 1 rows
+        fg.sb = (long)t2 * ext;
+        fg.sr = ext;
+        fg.rows = k + 1;
+        for (int t = 0; t <= k; ++t) fg.mul[t] = 1;
+        CTL_TRY(keyswitch_raise(c, st, k, B, R2, i1, dense_map(k), false, ks, gal2.data(), gal2.data(), &U, &fg));
+        CTL_TRY(slot(c, S_ROT2, (size_t)B * ext, st, &sum));
+        GalList one{};
+        for (int r = 0; r < kMaxKeysPerLaunch; ++r) one.g[r] = 1;
+        { CTL_PROF(F_ADD, (double)B * ext, 0.0); launch_sum_gather(logn, sum, ext, inner, (long)t2 * ext, U, (long)R2 * ext, ext, R2, k + 1, true, 3, one, B, nq, c->tab, st); }
+        usum = sum;
+    }
+    CTL_TRY(keyswitch_lower(c, st, k, B * 2, usum, none, acc));
+    return rescale_batch(c, st, k, B, acc, out);
+}
+
 int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const KeySet &ks, int B,
                 const u64 *in, u64 *out) {
     const LayerPlan &L = m->layers[li];
@@ -510,6 +590,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const Ke
         gal2[k2 - 1] = galois_elt(logn, (long)k2 * t1);
         CTL_TRY(need_key(ks, gal2[k2 - 1], "Galois key for rotation " + std::to_string(k2 * t1)));
     }
+    if (L.qp) return dense_qp_batch(c, st, m, li, ks, B, in, out, gal1, gal2);
     u64 *rot, *inner;
     CTL_TRY(slot(c, S_ROT, (size_t)B * std::max(R1, 1) * ctw, st, &rot));
     CTL_TRY(slot(c, S_INNER, (size_t)B * t2 * ctw, st, &inner));
@@ -525,7 +606,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const Ke
         CTL_TRY(keyswitch_batch(c, st, k, B, R1, in, c1_map(k), true, ks, gal1.data(), gal1.data(), add, rot));
     }
     // inner_k2 = sum_j diag'_{k2 t1 + j} * rot_j(ct)
-    { CTL_PROF(F_MAC, 2.0 * B * k * t1 * t2 * N, fp_share_range(c, k, false)); launch_mac(logn, in, rot, m->banks[li], inner, B, k, t1, t2, c->tab, c->knobs, st); }
+    { CTL_PROF(F_MAC, 2.0 * B * k * t1 * t2 * N, fp_share_range(c, k, false)); launch_mac(logn, in, ctw, rot, (long)R1 * ctw, m->banks[li], inner, B, k, -1, t1, t2, c->tab, c->knobs, st); }
     CTL_TRY(check_launch());
     const u64 *sum = inner;
     if (R2 > 0 && L.lazy) {
@@ -640,14 +721,17 @@ int plan_model(const ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, con
         if (l > 0 && d.n_in != layers[l - 1].n_out) return fail(CTL_EINVAL, "layer widths do not chain");
         if (l > 0 && layers[l - 1].kind == CTL_LAYER_AVGPOOL && d.kind != CTL_LAYER_DENSE)
             return fail(CTL_EINVAL, "an average pool must be followed by a dense layer");
-        if (d.flags & ~CTL_LAYER_LAZY_GIANT) return fail(CTL_EINVAL, "unknown layer flag");
+        if (d.flags & ~(CTL_LAYER_LAZY_GIANT | CTL_LAYER_BABY_QP)) return fail(CTL_EINVAL, "unknown layer flag");
+        if ((d.flags & CTL_LAYER_BABY_QP) && d.kind != CTL_LAYER_DENSE)
+            return fail(CTL_EINVAL, "CTL_LAYER_BABY_QP applies to dense layers");
         if (d.kind == CTL_LAYER_DENSE) {
             L.in_off = (l > 0 && layers[l - 1].kind == CTL_LAYER_AVGPOOL) ? layers[l - 1].f - 1 : 0;
             L.t = std::max(L.in_off + d.n_in, d.n_out);
             if (d.t1 < 1 || L.t % d.t1) return fail(CTL_EINVAL, "t1 must divide the padded width");
             L.t1 = d.t1;
             L.t2 = L.t / d.t1;
-            L.lazy = (d.flags & CTL_LAYER_LAZY_GIANT) != 0;
+            L.qp = (d.flags & CTL_LAYER_BABY_QP) != 0;
+            L.lazy = L.qp || (d.flags & CTL_LAYER_LAZY_GIANT) != 0;
             for (int j = 1; j < L.t1; ++j) L.rots1.push_back(j);
         } else if (d.kind == CTL_LAYER_CONV1D) {
             if (d.f < 1 || d.f % 2 == 0 || d.f > 2 * d.n_in - 1)
@@ -793,7 +877,8 @@ int encode_to_int(const ctl_ctx *c, const double *z, double scale, int64_t *out)
 }
 
 // Upload signed coefficients [G][N] and transform them to primes 0..k-1: out [G][k][N].
-int upload_ints(ctl_ctx *c, hipStream_t st, const int64_t *host, int G, int k, u64 *out) {
+// G signed polynomials -> [G][k][N] NTT form over q_0..q_{k-1} (ext: [G][k+1][N], last row mod P).
+int upload_ints(ctl_ctx *c, hipStream_t st, const int64_t *host, int G, int k, u64 *out, bool ext = false) {
     const long N = c->hp.n;
     u64 *stage;
     CTL_TRY(slot(c, S_MISC, (size_t)G * N, st, &stage));
@@ -801,11 +886,14 @@ int upload_ints(ctl_ctx *c, hipStream_t st, const int64_t *host, int G, int k, u
     PrimeList pl{};
     pl.n = k;
     for (int i = 0; i < k; ++i) pl.idx[i] = i;
+    if (ext) pl.idx[pl.n++] = c->hp.nq;
     launch_int_ntt(c->hp.logn, reinterpret_cast<const int64_t *>(stage), out, G, pl, c->tab, st);
     CTL_TRY(check_launch());
     CTL_HIP(hipStreamSynchronize(st));
     return CTL_OK;
 }
+
+int bank_rows(const LayerPlan &L) { return L.k + (L.qp ? 1 : 0); }
 
 int load_banks(ctl_ctx *c, ctl_model *m, const std::vector<std::vector<int64_t>> *ints,
                const double *const *weights) {
@@ -813,7 +901,8 @@ int load_banks(ctl_ctx *c, ctl_model *m, const std::vector<std::vector<int64_t>>
     const int n = c->hp.n;
     for (size_t l = 0; l < m->layers.size(); ++l) {
         const LayerPlan &L = m->layers[l];
-        u64 *bank = static_cast<u64 *>(dev_alloc(c, (size_t)L.nb * L.k * n * 8, st));
+        const int rows = bank_rows(L);
+        u64 *bank = static_cast<u64 *>(dev_alloc(c, (size_t)L.nb * rows * n * 8, st));
         if (!bank) return fail(CTL_ENOMEM, "plaintext bank allocation failed");
         m->banks.push_back(bank);
         const int chunk = 32;
@@ -834,7 +923,7 @@ int load_banks(ctl_ctx *c, ctl_model *m, const std::vector<std::vector<int64_t>>
                     CTL_TRY(encode_to_int(c, z.data(), L.pt_scale, &buf[(size_t)i * n]));
                 }
             }
-            CTL_TRY(upload_ints(c, st, buf.data(), cnt, L.k, bank + (size_t)i0 * L.k * n));
+            CTL_TRY(upload_ints(c, st, buf.data(), cnt, L.k, bank + (size_t)i0 * rows * n, L.qp));
         }
     }
     return CTL_OK;
@@ -1473,7 +1562,7 @@ int ctl_evk_bytes(const ctl_evk *evk, uint64_t *bytes_out) {
 int ctl_model_bytes(const ctl_model *m, uint64_t *bytes_out) {
     if (!m || !bytes_out) return fail(CTL_EINVAL, "null argument");
     uint64_t b = 0;
-    for (const LayerPlan &L : m->layers) b += (uint64_t)L.nb * L.k * m->ctx->hp.n * 8;
+    for (const LayerPlan &L : m->layers) b += (uint64_t)L.nb * bank_rows(L) * m->ctx->hp.n * 8;
     *bytes_out = b;
     return CTL_OK;
 }

@@ -33,9 +33,27 @@ struct DropAdd {
     u64 gal[kMaxKeysPerLaunch];   // automorphism applied to the addend of group r (1 = none)
 };
 
+// Entry y of a launch over residues: idx[y] is the residue row (or, for k_int_ntt, the prime
+// index); prime[y] is the prime-table index of that row where a kernel needs both.
 struct PrimeList {
     int n;
     int idx[kMaxMods];
+    int prime[kMaxMods];
+};
+
+// Term folded into the key product of polynomial 0 (see k_keyip): rows t < rows add
+// mul[t] * src[b sb + r sr + t N + sigma_r(n)].
+struct KeyFold {
+    const u64 *src;      // null: no fold
+    long sb, sr;
+    int rows;
+    u64 mul[kMaxMods];
+};
+
+// Location of group g of a ModDown input: off + (g / R) sb + (g % R) sr (words).
+struct GrpMap {
+    long off, sb, sr;
+    int R;
 };
 
 struct KeyList {
@@ -67,13 +85,21 @@ void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *
 void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
                   int nq, const Tables &tab, const Knobs &kn, hipStream_t st);
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
-                 const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st);
+                 const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st,
+                 const GrpMap *xmap = nullptr);
 void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,
                     const Tables &tab, hipStream_t st);
 void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
-                  u64 *out, int B, int nq, const Tables &tab, const Knobs &kn, hipStream_t st);
-void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *inner, int B, int k,
-                int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st);
+                  u64 *out, long ob, const KeyFold &fold, int B, int nq, const Tables &tab, const Knobs &kn,
+                  hipStream_t st);
+// rows = k residues per polynomial, or k + 1 with the last one mod P (ext_nq = its prime index;
+// -1 without). ct / rot: j = 0 / j >= 1 operands with batch strides ct_sb / rot_sb.
+void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb, const u64 *bank, u64 *inner,
+                int B, int rows, int ext_nq, int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st);
+// out[b][c][t] = P x in[b][c][t] mod q_t for t < k, 0 for t = k (the row mod P): in [B][2][k][N],
+// out with batch stride o_sb and [2][k+1][N] per ciphertext.
+void launch_times_p(int logn, const u64 *in, u64 *out, long o_sb, int B, int k, int nq, const Tables &tab,
+                    hipStream_t st);
 void launch_add_terms(int logn, const u64 *a, long a_sb, const u64 *terms, long t_sb, long t_ss, int S,
                       u64 *out, int B, int k, const Tables &tab, hipStream_t st);
 void launch_tensor(int logn, const u64 *a, const u64 *b, u64 *out, int B, int k, const Tables &tab, hipStream_t st);

@@ -540,12 +540,12 @@ k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u6
 
 // Drop the last modulus of each group (ModDown when it is P, rescale when it is q_k):
 //   out[g][i] = (x[g][i] - NTT_i(lift(last[g]))) * m_last^{-1} mod q_i  (+ addend)
-// x: [G][k+1][N] NTT form (only i < k read); last: dense [G][N] coefficient form mod m_last;
-// out: [G][k][N]. Groups are (b, r, c) with G = B R 2; the addend for polynomial c (if bit c of
+// x: [G][k+1][N] NTT form (only i < k read), group g at xm.off + (g / xm.R) xm.sb + (g % xm.R) xm.sr;
+// last: dense [G][N] coefficient form mod m_last; out: [G][k][N]. Groups are (b, r, c) with G = B R 2; the addend for polynomial c (if bit c of
 // add_mask) is read at add + b sb + r sr + c sc + i N, gathered through sigma_{gal[r]}.
 template <int LOGN>
 __global__ void __launch_bounds__(Geo<LOGN>::T)
-k_drop(const u64 *__restrict__ x, const u64 *__restrict__ last, u64 *__restrict__ out, int k,
+k_drop(const u64 *__restrict__ x, GrpMap xm, const u64 *__restrict__ last, u64 *__restrict__ out, int k,
        int drop, int groups, int xcd_order, DropAdd add, Tables tab) {
     extern __shared__ u64 lds[];
     constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
@@ -569,7 +569,7 @@ k_drop(const u64 *__restrict__ x, const u64 *__restrict__ last, u64 *__restrict_
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qd, cc.qj_mod_qi, p);
     const bool fp = fwd_transform<LOGN>(v, lds, tid, tab, i, p);
-    const u64 *xi = x + ((long)grp * (k + 1) + i) * N;
+    const u64 *xi = x + xm.off + (long)(grp / xm.R) * xm.sb + (long)(grp % xm.R) * xm.sr + (long)i * N;
     u64 *dst = out + ((long)grp * k + i) * N;
     const int c = grp & 1, r = (grp >> 1) % add.R, b = (grp >> 1) / add.R;
     const bool has_add = (add.mask >> c) & 1;
@@ -623,8 +623,11 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
 
 // ---------------------------------------------------------------- elementwise kernels
 // Key inner product with the automorphism fused into the digit gather:
-//   out[b][r][0][t] = sum_j D[b][r][j][t][sigma_r] * key_r[j][0][t],  out[..][1][t] likewise with
-//   key_r[j][1][t]; t = 0..k (k = the special prime). D: digits + b db + r dr + (j (k+1) + t) N.
+//   out[b][r][0][t] = sum_j D[b][r][j][t][sigma_r] * key_r[j][0][t] (+ fold),  out[..][1][t]
+//   likewise with key_r[j][1][t]; t = 0..k (k = the special prime). D: digits + b db + r dr +
+//   (j (k+1) + t) N; out[b][r] at out + b ob + r 2 (k+1) N. For rows t < fold.rows, polynomial 0
+//   also gets fold.mul[t] * fold.src[b sb + r sr + t N] gathered through sigma_r (the P sigma(c0)
+//   term of a baby step kept over Q*P, or the sigma(c0) of a giant step's extended operand).
 // One workgroup per (coefficient tile of 256, t, r); each thread loops over the batch so a key
 // word is read from HBM once per launch. Workgroups are dealt to the 8 XCDs in turn (id mod 8); with
 // xcd set the 1D grid is numbered such that all R rotations of one (tile, t) run back to back on
@@ -632,8 +635,8 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
 // otherwise tiles vary fastest, then t, then r.
 template <int K>
 __global__ void __launch_bounds__(256)
-k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__restrict__ out,
-        int B, int R, int nq, int logn, int xcd_order, const PrimeConst *__restrict__ pcs) {
+k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__restrict__ out, long ob,
+        KeyFold fold, int B, int R, int nq, int logn, int xcd_order, const PrimeConst *__restrict__ pcs) {
     const int pairs = (K + 1) << (logn - 8);
     int r, pair;
     if (xcd_order) {
@@ -654,6 +657,9 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
     const u64 g = keys.gal[r];
     const u64 *key = keys.key[r];
     const int src = g == 1 ? n : galois_src(n, g, logn);
+    const bool fd = fold.src != nullptr && t < fold.rows;            // uniform per workgroup
+    const u64 fm = fd ? fold.mul[t] : 0;
+    const u64 *fsrc = fd ? fold.src + r * fold.sr + (long)t * N + src : nullptr;
     if (p.fp) {
         // FP64 products (prime < 2^41): each term |.| <= 0.52 q, sums stay far below 2^53
         double kb[K], ka[K];
@@ -673,7 +679,8 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
                 a0 += fp_mul(x, kb[j], p.qd, p.qinv);
                 a1 += fp_mul(x, ka[j], p.qd, p.qinv);
             }
-            u64 *o = out + ((long)(b * R + r) * 2) * (K + 1) * N + (long)t * N + n;
+            if (fd) a0 += fp_mul(u64_to_fp(fsrc[b * fold.sb]), u64_to_fp(fm), p.qd, p.qinv);
+            u64 *o = out + b * ob + (long)r * 2 * (K + 1) * N + (long)t * N + n;
             o[0] = fp_to_u64(a0, p.qd, p.qinv);
             o[(long)(K + 1) * N] = fp_to_u64(a1, p.qd, p.qinv);
         }
@@ -697,14 +704,17 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
             acc_mac(a0, x, kb[j]);
             acc_mac(a1, x, ka[j]);
         }
-        u64 *o = out + ((long)(b * R + r) * 2) * (K + 1) * N + (long)t * N + n;
+        if (fd) acc_mac(a0, fsrc[b * fold.sb], fm);
+        u64 *o = out + b * ob + (long)r * 2 * (K + 1) * N + (long)t * N + n;
         o[0] = acc_reduce(a0, p);
         o[(long)(K + 1) * N] = acc_reduce(a1, p);
     }
 }
 
 // Baby-step MAC of Eq. (1): inner[b][k2][c][i] = sum_{j < t1} pt[k2 t1 + j][i] * rot_j(ct_b)[c][i]
-// with rot_0 = ct itself (ct: [B][2][K][N]) and rot_j, j >= 1, in rot: [B][t1-1][2][K][N].
+// with rot_0 = ct itself (ct_b at ct + b ct_sb, [2][K][N]) and rot_j, j >= 1, at rot + b rot_sb +
+// (j - 1) 2 K N. K = `k` residue rows per polynomial (with the baby steps kept over Q*P the last
+// row is mod P); row i = pl.idx[y] has prime pl.prime[y].
 // Per coefficient this is a (t2 x t1) by (t1 x 2B) modular matrix product. A workgroup covers 64
 // consecutive coefficients of one prime for up to 8 ciphertexts (threadIdx.y); each thread keeps
 // KC giant-step accumulators per polynomial, so every rotated ciphertext word is read once per
@@ -718,9 +728,9 @@ constexpr int kMacJB = 4;
 // grid y), so that the FP64 one is not held to the register budget of 128-bit accumulators.
 template <int KC>
 __global__ void __launch_bounds__(512)
-k_mac_fp(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__restrict__ bank,
-         u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn, PrimeList pl,
-         const PrimeConst *__restrict__ pcs) {
+k_mac_fp(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long rot_sb,
+         const u64 *__restrict__ bank, u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn,
+         PrimeList pl, const PrimeConst *__restrict__ pcs) {
     __shared__ double wd[kMacJB * KC * 64];
     const int nl = threadIdx.x, bl = threadIdx.y;
     const int tid = bl * 64 + nl, nthr = 64 * blockDim.y;
@@ -731,9 +741,9 @@ k_mac_fp(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__r
     const int b = (blockIdx.z % nbz) * blockDim.y + bl;
     const int kc0 = (blockIdx.z / nbz) * KC;
     const bool live = b < B;
-    const PrimeConst p = pcs[i];
-    const u64 *ct_b = ct + (long)(live ? b : 0) * 2 * kn + i * N + n0 + nl;
-    const u64 *rot_b = rot + (long)(live ? b : 0) * (t1 - 1) * 2 * kn + i * N + n0 + nl;
+    const PrimeConst p = pcs[pl.prime[blockIdx.y]];
+    const u64 *ct_b = ct + (long)(live ? b : 0) * ct_sb + i * N + n0 + nl;
+    const u64 *rot_b = rot + (long)(live ? b : 0) * rot_sb + i * N + n0 + nl;
     {
         double acc[KC][2];
 #pragma unroll
@@ -783,9 +793,9 @@ k_mac_fp(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__r
 
 template <int KC>
 __global__ void __launch_bounds__(512)
-k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__restrict__ bank,
-      u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn, PrimeList pl,
-      const PrimeConst *__restrict__ pcs) {
+k_mac(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long rot_sb,
+      const u64 *__restrict__ bank, u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn,
+      PrimeList pl, const PrimeConst *__restrict__ pcs) {
     __shared__ u64 wt[kMacJB * KC * 64];
     const int nl = threadIdx.x, bl = threadIdx.y;
     const int tid = bl * 64 + nl, nthr = 64 * blockDim.y;
@@ -796,9 +806,9 @@ k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__rest
     const int b = (blockIdx.z % nbz) * blockDim.y + bl;
     const int kc0 = (blockIdx.z / nbz) * KC;
     const bool live = b < B;
-    const PrimeConst p = pcs[i];
-    const u64 *ct_b = ct + (long)(live ? b : 0) * 2 * kn + i * N + n0 + nl;
-    const u64 *rot_b = rot + (long)(live ? b : 0) * (t1 - 1) * 2 * kn + i * N + n0 + nl;
+    const PrimeConst p = pcs[pl.prime[blockIdx.y]];
+    const u64 *ct_b = ct + (long)(live ? b : 0) * ct_sb + i * N + n0 + nl;
+    const u64 *rot_b = rot + (long)(live ? b : 0) * rot_sb + i * N + n0 + nl;
     {
         Acc acc[KC][2];
 #pragma unroll
@@ -849,18 +859,20 @@ k_mac(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__rest
 // The same MAC for batches of one or two ciphertexts: there is nothing to share a staged plaintext
 // word with, so each thread reads its plaintext words straight from memory (coalesced across the
 // coefficients of a wave), with no LDS and no barriers, and FP64 and integer primes go in one
-// launch (the branch is uniform per workgroup). grid: x = N / 64 tiles, y = prime, z = B t2 / KC.
+// launch (the branch is uniform per workgroup). grid: x = N / 64 tiles, y = residue row
+// (PrimeList), z = B t2 / KC.
 template <int KC>
 __global__ void __launch_bounds__(64)
-k_mac_direct(const u64 *__restrict__ ct, const u64 *__restrict__ rot, const u64 *__restrict__ bank,
-             u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn, const PrimeConst *__restrict__ pcs) {
-    const int nl = threadIdx.x, i = blockIdx.y;
+k_mac_direct(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long rot_sb,
+             const u64 *__restrict__ bank, u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn,
+             PrimeList pl, const PrimeConst *__restrict__ pcs) {
+    const int nl = threadIdx.x, i = pl.idx[blockIdx.y];
     const long N = 1L << logn, kn = (long)k * N;
     const long n0 = (long)blockIdx.x * 64;
     const int b = blockIdx.z % B, kc0 = (blockIdx.z / B) * KC;
-    const PrimeConst p = pcs[i];
-    const u64 *ct_b = ct + (long)b * 2 * kn + i * N + n0 + nl;
-    const u64 *rot_b = rot + (long)b * (t1 - 1) * 2 * kn + i * N + n0 + nl;
+    const PrimeConst p = pcs[pl.prime[blockIdx.y]];
+    const u64 *ct_b = ct + (long)b * ct_sb + i * N + n0 + nl;
+    const u64 *rot_b = rot + (long)b * rot_sb + i * N + n0 + nl;
     const u64 *bk = bank + i * N + n0 + nl;
     if (p.fp) {
         double acc[KC][2];
@@ -917,6 +929,22 @@ k_add_terms(const u64 *__restrict__ a, long a_sb, const u64 *__restrict__ terms,
     u64 s = a[b * a_sb + idx];
     for (int t = 0; t < S; ++t) s = add_mod(s, terms[b * t_sb + t * t_ss + idx], q);
     out[(long)b * 2 * k * N + idx] = s;
+}
+
+// out[b][c][t] = P in[b][c][t] mod q_t (t < k) and 0 for the row mod P (t = k).
+// grid: x = N / 256, y = 2 (k + 1), z = B.
+__global__ void __launch_bounds__(256)
+k_times_p(const u64 *__restrict__ in, u64 *__restrict__ out, long o_sb, int k, int nq, int logn,
+          const PrimeConst *__restrict__ pcs, const CrossConst *__restrict__ cross) {
+    const long N = 1L << logn;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y / (k + 1), t = blockIdx.y % (k + 1), b = blockIdx.z;
+    u64 v = 0;
+    if (t < k) {
+        const PrimeConst p = pcs[t];
+        v = mul_mod(in[((long)b * 2 * k + (long)c * k + t) * N + n], cross[t * kMaxMods + nq].qj_mod_qi, p);
+    }
+    out[b * o_sb + ((long)c * (k + 1) + t) * N + n] = v;
 }
 
 // out[b][c][t] = base[b][c][t] (or 0) + sum_{r < R} src[b][r][c][t] gathered through sigma_{gal[r]},
@@ -1097,15 +1125,17 @@ void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u
 }
 
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
-                 const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st) {
+                 const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st, const GrpMap *xmap) {
     if (groups <= 0) return;
+    const long N = 1L << logn;
+    const GrpMap xm = xmap ? *xmap : GrpMap{0, (k + 1) * N, 0, 1};
     const int xo = kn.ntt_xcd ? 1 : 0;
     const dim3 grid(xo ? ((groups + 7) / 8) * 8 * k : groups * k), blk = ntt_block(logn);
     const size_t sh = ntt_lds(logn);
     switch (logn) {
-        case 12: hipLaunchKernelGGL(k_drop<12>, grid, blk, sh, st, x, last, out, k, drop, groups, xo, add, tab); break;
-        case 13: hipLaunchKernelGGL(k_drop<13>, grid, blk, sh, st, x, last, out, k, drop, groups, xo, add, tab); break;
-        default: hipLaunchKernelGGL(k_drop<14>, grid, blk, sh, st, x, last, out, k, drop, groups, xo, add, tab); break;
+        case 12: hipLaunchKernelGGL(k_drop<12>, grid, blk, sh, st, x, xm, last, out, k, drop, groups, xo, add, tab); break;
+        case 13: hipLaunchKernelGGL(k_drop<13>, grid, blk, sh, st, x, xm, last, out, k, drop, groups, xo, add, tab); break;
+        default: hipLaunchKernelGGL(k_drop<14>, grid, blk, sh, st, x, xm, last, out, k, drop, groups, xo, add, tab); break;
     }
 }
 
@@ -1122,13 +1152,14 @@ void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const Pr
 }
 
 void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
-                  u64 *out, int B, int nq, const Tables &tab, const Knobs &kn, hipStream_t st) {
+                  u64 *out, long ob, const KeyFold &fold, int B, int nq, const Tables &tab, const Knobs &kn,
+                  hipStream_t st) {
     if (R <= 0 || B <= 0) return;
     const int pairs = (k + 1) << (logn - 8);
     const int xo = kn.keyip_xcd ? 1 : 0;
     const dim3 grid((unsigned)(xo ? ((pairs + 7) / 8) * 8 * R : pairs * R)), blk(256);
     switch (k) {
-#define CTL_KIP(K) case K: hipLaunchKernelGGL(k_keyip<K>, grid, blk, 0, st, digits, db, dr, keys, out, B, R, nq, logn, xo, tab.pc); break;
+#define CTL_KIP(K) case K: hipLaunchKernelGGL(k_keyip<K>, grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, tab.pc); break;
         CTL_KIP(1) CTL_KIP(2) CTL_KIP(3) CTL_KIP(4) CTL_KIP(5) CTL_KIP(6) CTL_KIP(7) CTL_KIP(8)
 #undef CTL_KIP
         default: break;
@@ -1143,45 +1174,53 @@ static int mac_chunk(int t2, int cap) {
     return 1;
 }
 
-void launch_mac(int logn, const u64 *ct, const u64 *rot, const u64 *bank, u64 *inner, int B, int k,
-                int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st) {
+void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb, const u64 *bank, u64 *inner,
+                int B, int rows, int ext_nq, int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st) {
     const int cts = kn.mac_cts < 1 ? 1 : kn.mac_cts > 8 ? 8 : kn.mac_cts;
     const int by = B < cts ? B : cts;
-    PrimeList fp{}, in{};
-    for (int i = 0; i < k; ++i) {
-        if (tab.host_fp[i]) fp.idx[fp.n++] = i;
-        else in.idx[in.n++] = i;
+    PrimeList all{}, fp{}, in{};
+    for (int i = 0; i < rows; ++i) {
+        const int pi = (ext_nq >= 0 && i == rows - 1) ? ext_nq : i;
+        PrimeList &l = tab.host_fp[pi] ? fp : in;
+        l.idx[l.n] = all.idx[all.n] = i;
+        l.prime[l.n++] = all.prime[all.n++] = pi;
     }
     const int kc = mac_chunk(t2, kn.mac_chunk_cap);
     if (B <= kn.mac_direct_max) {
         const int kd = mac_chunk(t2, 4);        // few accumulators: more workgroups for one ciphertext
-        const dim3 grid((1u << logn) / 64, k, B * (t2 / kd)), blk(64);
+        const dim3 grid((1u << logn) / 64, rows, B * (t2 / kd)), blk(64);
         switch (kd) {
-            case 4: hipLaunchKernelGGL(k_mac_direct<4>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
-            case 3: hipLaunchKernelGGL(k_mac_direct<3>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
-            case 2: hipLaunchKernelGGL(k_mac_direct<2>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
-            default: hipLaunchKernelGGL(k_mac_direct<1>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, tab.pc); break;
+#define CTL_MACD(KD) case KD: hipLaunchKernelGGL(k_mac_direct<KD>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, all, tab.pc); break;
+            CTL_MACD(4) CTL_MACD(3) CTL_MACD(2)
+            default: hipLaunchKernelGGL(k_mac_direct<1>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, all, tab.pc); break;
+#undef CTL_MACD
         }
         return;
     }
     if (fp.n) {
         const dim3 grid((1u << logn) / 64, fp.n, ((B + by - 1) / by) * (t2 / kc)), blk(64, by);
         switch (kc) {
-#define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac_fp<KC>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, fp, tab.pc); break;
+#define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac_fp<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, fp, tab.pc); break;
             CTL_MAC(16) CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
-            default: hipLaunchKernelGGL(k_mac_fp<1>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, fp, tab.pc); break;
+            default: hipLaunchKernelGGL(k_mac_fp<1>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, fp, tab.pc); break;
 #undef CTL_MAC
         }
     }
     if (in.n) {
         const dim3 grid((1u << logn) / 64, in.n, ((B + by - 1) / by) * (t2 / kc)), blk(64, by);
         switch (kc) {
-#define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac<KC>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, in, tab.pc); break;
+#define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, in, tab.pc); break;
             CTL_MAC(16) CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
-            default: hipLaunchKernelGGL(k_mac<1>, grid, blk, 0, st, ct, rot, bank, inner, B, k, t1, t2, logn, in, tab.pc); break;
+            default: hipLaunchKernelGGL(k_mac<1>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, in, tab.pc); break;
 #undef CTL_MAC
         }
     }
+}
+
+void launch_times_p(int logn, const u64 *in, u64 *out, long o_sb, int B, int k, int nq, const Tables &tab,
+                    hipStream_t st) {
+    const dim3 grid((1u << logn) / 256, 2 * (k + 1), B), blk(256);
+    hipLaunchKernelGGL(k_times_p, grid, blk, 0, st, in, out, o_sb, k, nq, logn, tab.pc, tab.cross);
 }
 
 void launch_add_terms(int logn, const u64 *a, long a_sb, const u64 *terms, long t_sb, long t_ss, int S,

@@ -254,6 +254,7 @@ class PsetSpec:
     max_batch: int = 64
     lanes: int = 2
     lazy: bool = True
+    qp: bool = True              # baby steps over Q*P (dense-layer variant)
 
 
 class _Lane:
@@ -288,7 +289,7 @@ class GpuServer:
             w = s.workload
             ctxs = [Context.for_workload(w, device=device) for _ in range(s.lanes)]
             layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
-            m = ctxs[0].load_model(layers, s.weights, lazy=s.lazy)
+            m = ctxs[0].load_model(layers, s.weights, lazy=s.lazy, qp=s.qp)
             self.models[s.name] = m
             k_in, k_out = m.info.k_in, m.info.k_out
             per_slot = 2 * (k_in + k_out) * ctxs[0].n * 8

@@ -42,7 +42,7 @@ def test_tune_forward_pass_bit_identical():
     import workloads as W
     w = W.MID
     c = ctl.Context.for_workload(w)
-    m = c.load_model([(l.n_in, l.n_out, l.t1) for l in w.layers], W.weights(w), lazy=True)
+    m = c.load_model([(l.n_in, l.n_out, l.t1) for l in w.layers], W.weights(w), lazy=True, qp=True)
     keys = c.keygen(w.seed_keys, m.info.rotations, relin=True)
     ct = c.empty_ct(6, c.nq)
     for i in range(6):

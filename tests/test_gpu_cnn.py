@@ -40,7 +40,8 @@ def _setup(name):
            "dense1": W.raw_plaintexts(w.seed_base + 12, w.width, o.n, 40),
            "pool": W.raw_plaintexts(w.seed_base + 13, 1, o.n, 40)[0],
            "dense2": W.raw_plaintexts(w.seed_base + 14, w.width, o.n, 40)}
-    m = c.load_model_raw(_layers(ctl, w), [raw["conv"], raw["dense1"], raw["pool"][None], raw["dense2"]], lazy=True)
+    m = c.load_model_raw(_layers(ctl, w), [raw["conv"], raw["dense1"], raw["pool"][None], raw["dense2"]], lazy=True,
+                         qp=True)
     keys = c.keygen(w.seed_keys, m.info.rotations, relin=True)
     s = o.keygen_secret(w.seed_keys)
     pk = o.keygen_public(w.seed_keys, s)
@@ -103,7 +104,7 @@ def test_stack_bit_exact(name):
     got = ctl.to_numpy_u64(c.forward(m, keys, dev))
     assert got.shape == (3, 2, 1, o.n)
     for i in (0, 2):                                   # the oracle takes seconds per ciphertext
-        want = cnn.forward(p, o, o.encrypt(pk, msgs[i], 500 + i), raw, okeys, rlk, W.RELU3_COEF)
+        want = cnn.forward(p, o, o.encrypt(pk, msgs[i], 500 + i), raw, okeys, rlk, W.RELU3_COEF, qp=True)
         assert np.array_equal(got[i], want), i
 
 
@@ -116,7 +117,7 @@ def test_stack_fp64_tolerance(name, tol):
     w = W.CNN_WORKLOADS[name]
     c = ctl.Context(w.log2n, w.q_bits, w.p_bits, w.log2_scale, w.sigma)
     taps, w1, w2 = W.cnn_weights(w)
-    m = c.load_model(_layers(ctl, w), [taps, w1, None, w2], lazy=True)
+    m = c.load_model(_layers(ctl, w), [taps, w1, None, w2], lazy=True, qp=True)
     keys = c.keygen(w.seed_keys, m.info.rotations, relin=True)
     n_ct = 4
     x = W.cnn_inputs(w, n_ct, m.info.items)

@@ -49,8 +49,8 @@ def _oracle_query(o, q, ct, bank, okeys, rlk):
         w_in, w_out = q.widths[l], q.widths[l + 1]
         t = max(w_in, w_out)
         k = o.nq - 2 * l
-        pts = o.bank_ntt(bank(l, w_in, w_out, t), k)
-        ct = o.dense(ct, pts, W.MIX_T1[t], okeys, lazy=True)
+        pts = o.bank_ntt(bank(l, w_in, w_out, t), k, ext=True)
+        ct = o.dense(ct, pts, W.MIX_T1[t], okeys, lazy=True, qp=True)
         if l + 1 < q.depth:
             ct = o.square(ct, rlk)
             ct = o.replicate(ct, max(q.widths[l + 1], q.widths[l + 2]), okeys)

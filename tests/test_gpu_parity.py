@@ -47,8 +47,10 @@ def _dev(a):
 
 
 def _plan(name, lazy=False):
+    """lazy: False (one ModDown per giant step), True (single-ModDown giant steps) or "qp" (baby
+    steps over Q*P as well)."""
     w = W.WORKLOADS[name]
-    return _orc(name).plan([(l.n_in, l.n_out, l.t1) for l in w.layers], lazy=lazy)
+    return _orc(name).plan([(l.n_in, l.n_out, l.t1) for l in w.layers], lazy=bool(lazy), qp=lazy == "qp")
 
 
 @functools.lru_cache(maxsize=None)
@@ -184,13 +186,14 @@ def _raw_model(name, seed=21, lazy=False):
     plan = _plan(name)
     banks = [W.raw_plaintexts(seed + li, L.t, o.n, bound_bits=45, stream=li) for li, L in enumerate(plan.layers)]
     layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
-    model = c.load_model_raw(layers, banks, lazy=lazy)
-    banks_ntt = [o.bank_ntt(banks[li], L.k) for li, L in enumerate(plan.layers)]
+    model = c.load_model_raw(layers, banks, lazy=bool(lazy), qp=lazy == "qp")
+    banks_ntt = [o.bank_ntt(banks[li], L.k, ext=lazy == "qp") for li, L in enumerate(plan.layers)]
     return model, banks_ntt
 
 
 @pytest.mark.parametrize("name,lazy", [("small", False), ("mid", False), ("large", False),
-                                       ("mid", True), ("large", True)])
+                                       ("mid", True), ("large", True),
+                                       ("small", "qp"), ("mid", "qp"), ("large", "qp")])
 def test_dense_bit_exact(name, lazy):
     o, c = _orc(name), _ctx(name)
     lk, _, _, okeys, _ = _keys(name)
@@ -204,11 +207,13 @@ def test_dense_bit_exact(name, lazy):
         x = dev[:, :, :L.k].contiguous()
         got = _u64(c.dense(model, li, lk, x))
         for b in range(2):
-            want = o.dense(np.ascontiguousarray(ref[b][:, :L.k]), banks_ntt[li], L.t1, okeys, lazy)
+            want = o.dense(np.ascontiguousarray(ref[b][:, :L.k]), banks_ntt[li], L.t1, okeys, bool(lazy),
+                           qp=lazy == "qp")
             assert np.array_equal(got[b], want), (li, b)
 
 
-@pytest.mark.parametrize("name,lazy", [("small", False), ("mid", False), ("large", False), ("large", True)])
+@pytest.mark.parametrize("name,lazy", [("small", False), ("mid", False), ("large", False), ("large", True),
+                                       ("mid", "qp"), ("large", "qp")])
 def test_forward_bit_exact(name, lazy):
     o, c = _orc(name), _ctx(name)
     lk, _, _, okeys, rlk = _keys(name)
@@ -221,7 +226,7 @@ def test_forward_bit_exact(name, lazy):
         assert np.array_equal(got[b], o.forward(plan, ref[b], banks_ntt, okeys, rlk)), b
 
 
-@pytest.mark.parametrize("lazy", [False, True])
+@pytest.mark.parametrize("lazy", [False, True, "qp"])
 def test_forward_full_batch_sampled(lazy):
     """The large workload's batch of 64 ciphertexts in one launch sequence; ciphertexts 0 and 63
     are recomputed by the oracle one by one."""
@@ -255,7 +260,8 @@ def test_encode_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name,tol_log2,lazy", [("small", -12, False), ("mid", -20, False), ("large", -20, False),
-                                                ("mid", -20, True), ("large", -20, True)])
+                                                ("mid", -20, True), ("large", -20, True),
+                                                ("mid", -20, "qp"), ("large", -20, "qp")])
 def test_forward_fp64_tolerance(name, tol_log2, lazy):
     """Encode real inputs and weights with the library, run ClassifyHE on the GPU, decrypt and
     decode: the result matches the plain FP64 forward pass normwise."""
@@ -264,7 +270,7 @@ def test_forward_fp64_tolerance(name, tol_log2, lazy):
     lk = _keys(name)[0]
     ws = W.weights(w)
     layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
-    model = c.load_model(layers, ws, lazy=lazy)
+    model = c.load_model(layers, ws, lazy=bool(lazy), qp=lazy == "qp")
     n_ct = 2
     x = W.inputs(w, n_ct, model.info.items)
     dev = c.empty_ct(n_ct, o.nq)

@@ -27,7 +27,7 @@ def test_serving_results_equal_alone_and_in_the_mix():
     # client side: own context, keys, encrypted inputs
     cctx = {"mid": ctl.Context.for_workload(W.MID), "large": ctl.Context.for_workload(W.LARGE)}
     wl = {"mid": W.MID, "large": W.LARGE}
-    cmodel = {p: cctx[p].load_model([(l.n_in, l.n_out, l.t1) for l in wl[p].layers], W.weights(wl[p]), lazy=True)
+    cmodel = {p: cctx[p].load_model([(l.n_in, l.n_out, l.t1) for l in wl[p].layers], W.weights(wl[p]), lazy=True, qp=True)
               for p in cctx}
     ckeys, uploads = {}, {}
     for c, p in clients.items():

@@ -44,8 +44,8 @@ def test_protocol_through_the_wire_format_p1():
     # keys, uploaded once per session)
     client = ctl.Context(w.log2n, w.q_bits, w.p_bits, w.log2_scale, w.sigma)
     server = ctl.Context(w.log2n, w.q_bits, w.p_bits, w.log2_scale, w.sigma)
-    cm = client.load_model(layers, [taps, w1, None, w2], lazy=True)
-    sm = server.load_model(layers, [taps, w1, None, w2], lazy=True)
+    cm = client.load_model(layers, [taps, w1, None, w2], lazy=True, qp=True)
+    sm = server.load_model(layers, [taps, w1, None, w2], lazy=True, qp=True)
     ck = client.keygen(w.seed_keys, cm.info.rotations, relin=True)
     sk = server.import_keys(ck.evaluation_keys())
     x = W.cnn_inputs(w, 1, cm.info.items)[0]

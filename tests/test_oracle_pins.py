@@ -358,7 +358,7 @@ def test_rotation_counts_and_layout():
     for layer in plan.layers:
         rots = list(range(1, layer.t1)) + [k2 * layer.t1 for k2 in range(1, layer.t2)]
         assert len(rots) == layer.t1 + layer.t2 - 2
-    assert plan.layers[0].t1 + plan.layers[0].t2 - 2 == 54
+    assert plan.layers[0].t1 + plan.layers[0].t2 - 2 == 74          # 768 = 64 x 12 (the split's reading)
     spec = json.load(open(os.path.join(GOLDEN, "table2_layout.json")))
     for case in spec["cases"]:
         o2 = CKKSOracle(int(math.log2(case["n"])), (40, 40), 60, 30)

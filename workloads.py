@@ -16,6 +16,12 @@ shape, dimensionality and value ranges):
   weights N(0, 0.05^2), inputs N(0,1) clipped to [-3,3]; batches of 64 ciphertexts.
 
 Every workload adds one 60-bit special prime for key switching and uses error sigma = 3.2.
+
+The BSGS split t = t1 * t2 of a dense layer is not fixed by the paper (Eq. (1) gives t only). With
+the baby steps hoisted and kept over Q*P a baby rotation costs one key product, a giant rotation a
+full key switch (ModDown, ModUp, key product), measured about 5x more at N = 2^14; t1 near
+sqrt(5 t) balances them: 768 = 64 x 12, 512 = 64 x 8, 256 = 32 x 8, 128 = 32 x 4 (t1 <= 64, the
+largest rotation count one key-product launch takes). The small workload keeps t1 = t = 64.
 """
 from __future__ import annotations
 
@@ -71,9 +77,9 @@ class Workload:
 SMALL = Workload("small", 12, (40, 30, 40), 60, 30, 3.2,
                  (Layer(64, 64, 64),), "uniform1", "uniform1", 1, 1000)
 MID = Workload("mid", 13, (60, 40, 40, 60), 60, 40, 3.2,
-               (Layer(512, 128, 32), Layer(128, 128, 16)), "normal005", "uniform1", 1, 2000)
+               (Layer(512, 128, 64), Layer(128, 128, 32)), "normal005", "uniform1", 1, 2000)
 LARGE = Workload("large", 14, (60, 40, 40, 40, 40, 60), 60, 40, 3.2,
-                 (Layer(768, 256, 32), Layer(256, 64, 16)), "normal005", "clipnormal3", 64, 3000)
+                 (Layer(768, 256, 64), Layer(256, 64, 32)), "normal005", "clipnormal3", 64, 3000)
 
 WORKLOADS = {w.name: w for w in (SMALL, MID, LARGE)}
 
@@ -134,7 +140,7 @@ def residues(seed: int, count: int, n: int, bits: int = 64, stream: int = 0) -> 
 # drawn per (position, w_in, w_out) and shared by every query with that shape; one slot layout for
 # all queries (block stride 1536 = 2 * 768, 5 items per ciphertext).
 MIX_WIDTHS = (128, 256, 512, 768)
-MIX_T1 = {128: 16, 256: 16, 512: 32, 768: 32}      # BSGS split of each padded width
+MIX_T1 = {128: 32, 256: 32, 512: 64, 768: 64}      # BSGS split of each padded width
 MIX_BLOCK = 1536
 MIX_SEED = 4000
 
@@ -189,7 +195,7 @@ class CnnWorkload:
     width: int = 768
     f_conv: int = 9
     f_pool: int = 3
-    t1: int = 32                     # BSGS split of both dense layers (t = 768 = 32 x 24)
+    t1: int = 64                     # BSGS split of both dense layers (t = 768 = 64 x 12)
 
     @property
     def n(self) -> int:
