@@ -335,7 +335,7 @@ def main():
             slots = (fpw * SLOTS_BFLY["fp"] + (work - fpw) * SLOTS_BFLY["int"]) / cnt * butterflies_per_ntt
             alg_bytes = work / cnt * 16.0 * n
             ops = "NTT butterflies x (%d FP64 | %d integer) VALU lane-instructions" % (SLOTS_BFLY["fp"], SLOTS_BFLY["int"])
-        elif dom in ("k_mac", "k_keyip", "k_tensor"):
+        elif dom in ("k_mac", "k_mac_fp", "k_mac_direct", "k_keyip", "k_tensor"):
             slots = (fpw * SLOTS_MAC["fp"] + (work - fpw) * SLOTS_MAC["int"]) / cnt
             alg_bytes = None
             ops = "modular multiply-accumulates x (%d FP64 | %d integer) VALU lane-instructions" % (

@@ -38,9 +38,12 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 enum Family { F_NTT_FWD, F_NTT_INV, F_MODUP, F_KEYIP, F_DROP, F_MAC, F_ADD, F_TENSOR, F_INT_NTT, F_OTHER,
-              F_COUNT };
+              F_MAC_FP, F_MAC_DIRECT, F_COUNT };
+// Names of the kernels each family brackets (k_mac: the MAC over integer primes; k_mac_fp: over
+// FP64 primes; k_mac_direct: the unstaged MAC of small batches, all primes in one launch).
 const char *const kFamilyNames[F_COUNT] = {"k_ntt_fwd", "k_ntt_inv", "k_modup", "k_keyip", "k_drop",
-                                            "k_mac", "k_add_terms", "k_tensor", "k_int_ntt", "other"};
+                                            "k_mac", "k_add_terms", "k_tensor", "k_int_ntt", "other",
+                                            "k_mac_fp", "k_mac_direct"};
 
 // Workspace slots: each grows on demand and is reused by later calls on the same context.
 enum Slot {
@@ -211,6 +214,30 @@ double fp_share_range(const ctl_ctx *c, int k, bool with_p) {
     return fp_share(c, pr, n);
 }
 
+// The plaintext-product MAC over `rows` residue rows (the last one mod P when ext), bracketed per
+// kernel: the FP64-prime and integer-prime launches, or the one unstaged launch of a small batch.
+void run_mac(ctl_ctx *c, hipStream_t st, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb, const u64 *bank,
+             u64 *inner, int B, int rows, bool ext, int t1, int t2) {
+    const int logn = c->hp.logn, nq = c->hp.nq;
+    const double per_row = 2.0 * B * t1 * t2 * c->hp.n;
+    int fp_rows = 0;
+    for (int r = 0; r < rows; ++r) fp_rows += c->tab.host_fp[(ext && r == rows - 1) ? nq : r] ? 1 : 0;
+    const int ext_nq = ext ? nq : -1;
+    if (B <= c->knobs.mac_direct_max) {
+        CTL_PROF(F_MAC_DIRECT, per_row * rows, (double)fp_rows / rows);
+        launch_mac(logn, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, ext_nq, t1, t2, c->tab, c->knobs, st, 0);
+        return;
+    }
+    if (fp_rows) {
+        CTL_PROF(F_MAC_FP, per_row * fp_rows, 1.0);
+        launch_mac(logn, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, ext_nq, t1, t2, c->tab, c->knobs, st, 1);
+    }
+    if (fp_rows < rows) {
+        CTL_PROF(F_MAC, per_row * (rows - fp_rows), 0.0);
+        launch_mac(logn, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, ext_nq, t1, t2, c->tab, c->knobs, st, 2);
+    }
+}
+
 int check_launch() {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CTL_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -308,6 +335,7 @@ int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
             kl.key[r] = find_key(run.evk, key_ids[r]);
             if (!kl.key[r]) return fail(CTL_EKEY, "missing evaluation key");
             kl.gal[r] = gal[r];
+            kl.ginv[r] = galois_inv(logn, gal[r]);
         }
         KeyFold fr = fd;
         if (fr.src) fr.src += run.b0 * fr.sb;
@@ -535,7 +563,7 @@ int dense_qp_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const
         CTL_TRY(keyswitch_raise(c, st, k, B, R1, in, c1_map(k), true, ks, gal1.data(), gal1.data(), &U, &fd,
                                 rot + ext, (long)t1 * ext));
     }
-    { CTL_PROF(F_MAC, 2.0 * B * (k + 1) * t1 * t2 * N, fp_share_range(c, k, false)); launch_mac(logn, rot, (long)t1 * ext, rot + ext, (long)t1 * ext, m->banks[li], inner, B, k + 1, nq, t1, t2, c->tab, c->knobs, st); }
+    run_mac(c, st, rot, (long)t1 * ext, rot + ext, (long)t1 * ext, m->banks[li], inner, B, k + 1, true, t1, t2);
     CTL_TRY(check_launch());
     DropAdd none{};
     none.R = 1;
@@ -606,7 +634,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const Ke
         CTL_TRY(keyswitch_batch(c, st, k, B, R1, in, c1_map(k), true, ks, gal1.data(), gal1.data(), add, rot));
     }
     // inner_k2 = sum_j diag'_{k2 t1 + j} * rot_j(ct)
-    { CTL_PROF(F_MAC, 2.0 * B * k * t1 * t2 * N, fp_share_range(c, k, false)); launch_mac(logn, in, ctw, rot, (long)R1 * ctw, m->banks[li], inner, B, k, -1, t1, t2, c->tab, c->knobs, st); }
+    run_mac(c, st, in, ctw, rot, (long)R1 * ctw, m->banks[li], inner, B, k, false, t1, t2);
     CTL_TRY(check_launch());
     const u64 *sum = inner;
     if (R2 > 0 && L.lazy) {

@@ -64,6 +64,7 @@ u64 h_powmod(u64 a, u64 e, u64 q);
 u64 h_invmod(u64 a, u64 q);
 u64 h_shoup(u64 w, u64 q);
 u64 galois_elt(int logn, long r);
+u64 galois_inv(int logn, u64 g);    // g^{-1} mod 2N
 
 // ChaCha20 stream (RFC 8439 block function) with the sampler conventions.
 enum : uint32_t { TAG_SK = 1, TAG_PK_A = 2, TAG_PK_E = 3, TAG_KS_A = 4, TAG_KS_E = 5,

@@ -130,6 +130,16 @@ u64 galois_elt(int logn, long r) {
     return g;
 }
 
+u64 galois_inv(int logn, u64 g) {
+    const u64 m = 2ull << logn;       // the odd residues mod 2N form a group of order N
+    u64 r = 1, base = g % m;
+    for (u64 e = (1ull << logn) - 1; e; e >>= 1) {
+        if (e & 1) r = r * base % m;
+        base = base * base % m;
+    }
+    return r;
+}
+
 // ---------------------------------------------------------------- ChaCha20
 static inline uint32_t rotl(uint32_t v, int s) { return (v << s) | (v >> (32 - s)); }
 

@@ -59,6 +59,7 @@ struct GrpMap {
 struct KeyList {
     const u64 *key[kMaxKeysPerLaunch];   // [nq][2][np][N] each
     u64 gal[kMaxKeysPerLaunch];          // Galois element applied to the digits (1 = none)
+    u64 ginv[kMaxKeysPerLaunch];         // its inverse mod 2N
 };
 
 struct GalList {
@@ -93,9 +94,12 @@ void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const Ke
                   u64 *out, long ob, const KeyFold &fold, int B, int nq, const Tables &tab, const Knobs &kn,
                   hipStream_t st);
 // rows = k residues per polynomial, or k + 1 with the last one mod P (ext_nq = its prime index;
-// -1 without). ct / rot: j = 0 / j >= 1 operands with batch strides ct_sb / rot_sb.
+// -1 without). ct / rot: j = 0 / j >= 1 operands with batch strides ct_sb / rot_sb. part: 0 =
+// every row, 1 = the FP64-prime rows only, 2 = the integer-prime rows only (batches above
+// kn.mac_direct_max; smaller ones take one unstaged launch over every row whatever part says).
 void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb, const u64 *bank, u64 *inner,
-                int B, int rows, int ext_nq, int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st);
+                int B, int rows, int ext_nq, int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st,
+                int part);
 // out[b][c][t] = P x in[b][c][t] mod q_t for t < k, 0 for t = k (the row mod P): in [B][2][k][N],
 // out with batch stride o_sb and [2][k+1][N] per ciphertext.
 void launch_times_p(int logn, const u64 *in, u64 *out, long o_sb, int B, int k, int nq, const Tables &tab,

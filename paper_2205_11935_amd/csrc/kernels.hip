@@ -11,6 +11,8 @@
 // from per-prime tables. One workgroup transforms one residue polynomial: N/16 threads hold 16
 // values each in registers; each pass runs 4 (or 3) butterfly stages in registers and exchanges
 // through LDS between passes, so a residue makes a single HBM round trip.
+#include <type_traits>
+
 #include "ctl_internal.h"
 #include "kernels.h"
 
@@ -628,11 +630,15 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
 //   (j (k+1) + t) N; out[b][r] at out + b ob + r 2 (k+1) N. For rows t < fold.rows, polynomial 0
 //   also gets fold.mul[t] * fold.src[b sb + r sr + t N] gathered through sigma_r (the P sigma(c0)
 //   term of a baby step kept over Q*P, or the sigma(c0) of a giant step's extended operand).
-// One workgroup per (coefficient tile of 256, t, r); each thread loops over the batch so a key
-// word is read from HBM once per launch. Workgroups are dealt to the 8 XCDs in turn (id mod 8); with
-// xcd set the 1D grid is numbered such that all R rotations of one (tile, t) run back to back on
-// the same XCD (with hoisted digits, dr = 0, they read the same digit words, which its L2 serves);
-// otherwise tiles vary fastest, then t, then r.
+// One workgroup per (source tile of 256 coefficients, t, r); each thread loops over the batch so a
+// key word is read from HBM once per launch. A thread reads the digits (and the fold term) at its
+// source coefficient m and writes output coefficient n = sigma_r^{-1}(m), so that the digit loads
+// are contiguous; in bit-reversed evaluation order the automorphism permutes aligned blocks of
+// 2^j coefficients among themselves, so n stays inside one aligned 256-block and the key loads and
+// output stores of a wave stay within 512 bytes. Workgroups are dealt to the 8 XCDs in turn (id
+// mod 8); with xcd set the 1D grid is numbered such that all R rotations of one (source tile, t)
+// run back to back on the same XCD (with hoisted digits, dr = 0, they read the same digit words,
+// which its L2 serves); otherwise tiles vary fastest, then t, then r.
 template <int K>
 __global__ void __launch_bounds__(256)
 k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__restrict__ out, long ob,
@@ -649,17 +655,20 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
         pair = (id % tiles) * (K + 1) + (id / tiles) % (K + 1);
     }
     if (pair >= pairs || r >= R) return;
-    const int n = (pair / (K + 1)) * 256 + threadIdx.x;
+    const int m = (pair / (K + 1)) * 256 + threadIdx.x;     // source coefficient
     const int t = pair % (K + 1);
     const int N = 1 << logn, np = nq + 1;
     const int pt = t < K ? t : nq;
     const PrimeConst p = pcs[pt];
     const u64 g = keys.gal[r];
     const u64 *key = keys.key[r];
-    const int src = g == 1 ? n : galois_src(n, g, logn);
+    const int src = m;
+    const int n = g == 1 ? m : galois_src(m, keys.ginv[r], logn);   // the output that gathers from m
     const bool fd = fold.src != nullptr && t < fold.rows;            // uniform per workgroup
     const u64 fm = fd ? fold.mul[t] : 0;
     const u64 *fsrc = fd ? fold.src + r * fold.sr + (long)t * N + src : nullptr;
+    const u64 *dig0 = digits + r * dr + (long)t * N + src;           // ciphertext b at + b db
+    u64 *out0 = out + (long)r * 2 * (K + 1) * N + (long)t * N + n;   // ciphertext b at + b ob
     if (p.fp) {
         // FP64 products (prime < 2^41): each term |.| <= 0.52 q, sums stay far below 2^53
         double kb[K], ka[K];
@@ -668,22 +677,40 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
             kb[j] = u64_to_fp(key[((long)(j * 2 + 0) * np + pt) * N + n]);
             ka[j] = u64_to_fp(key[((long)(j * 2 + 1) * np + pt) * N + n]);
         }
-        // four ciphertexts per unrolled step keep their digit loads in flight together
-#pragma unroll 4
-        for (int b = 0; b < B; ++b) {
-            const u64 *d = digits + b * db + r * dr + (long)t * N + src;
-            double a0 = 0.0, a1 = 0.0;
+        const double fmd = u64_to_fp(fm);
+        auto run = [&](auto fold_tag) {
+            constexpr bool FOLD = decltype(fold_tag)::value;
+            // the words of ciphertext b + 1 are loaded while b is multiplied
+            u64 xn[K], fn = 0;
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const double x = u64_to_fp(d[(long)j * (K + 1) * N]);
-                a0 += fp_mul(x, kb[j], p.qd, p.qinv);
-                a1 += fp_mul(x, ka[j], p.qd, p.qinv);
+            for (int j = 0; j < K; ++j) xn[j] = dig0[(long)j * (K + 1) * N];
+            if constexpr (FOLD) fn = fsrc[0];
+            for (int b = 0; b < B; ++b) {
+                u64 x[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) x[j] = xn[j];
+                const u64 fx = fn;
+                if (b + 1 < B) {
+                    const u64 *d = dig0 + (b + 1) * db;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) xn[j] = d[(long)j * (K + 1) * N];
+                    if constexpr (FOLD) fn = fsrc[(b + 1) * fold.sb];
+                }
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const double xd = u64_to_fp(x[j]);
+                    a0 += fp_mul(xd, kb[j], p.qd, p.qinv);
+                    a1 += fp_mul(xd, ka[j], p.qd, p.qinv);
+                }
+                if constexpr (FOLD) a0 += fp_mul(u64_to_fp(fx), fmd, p.qd, p.qinv);
+                u64 *o = out0 + b * ob;
+                o[0] = fp_to_u64(a0, p.qd, p.qinv);
+                o[(long)(K + 1) * N] = fp_to_u64(a1, p.qd, p.qinv);
             }
-            if (fd) a0 += fp_mul(u64_to_fp(fsrc[b * fold.sb]), u64_to_fp(fm), p.qd, p.qinv);
-            u64 *o = out + b * ob + (long)r * 2 * (K + 1) * N + (long)t * N + n;
-            o[0] = fp_to_u64(a0, p.qd, p.qinv);
-            o[(long)(K + 1) * N] = fp_to_u64(a1, p.qd, p.qinv);
-        }
+        };
+        if (fd) run(std::true_type{});
+        else run(std::false_type{});
         return;
     }
     u64 kb[K], ka[K];
@@ -692,23 +719,39 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
         kb[j] = key[((long)(j * 2 + 0) * np + pt) * N + n];
         ka[j] = key[((long)(j * 2 + 1) * np + pt) * N + n];
     }
-#pragma unroll 4
-    for (int b = 0; b < B; ++b) {
-        const u64 *d = digits + b * db + r * dr + (long)t * N + src;
-        Acc a0, a1;
-        acc_zero(a0);
-        acc_zero(a1);
+    auto run = [&](auto fold_tag) {
+        constexpr bool FOLD = decltype(fold_tag)::value;
+        u64 xn[K], fn = 0;
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const u64 x = d[(long)j * (K + 1) * N];
-            acc_mac(a0, x, kb[j]);
-            acc_mac(a1, x, ka[j]);
+        for (int j = 0; j < K; ++j) xn[j] = dig0[(long)j * (K + 1) * N];
+        if constexpr (FOLD) fn = fsrc[0];
+        for (int b = 0; b < B; ++b) {
+            u64 x[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) x[j] = xn[j];
+            const u64 fx = fn;
+            if (b + 1 < B) {
+                const u64 *d = dig0 + (b + 1) * db;
+#pragma unroll
+                for (int j = 0; j < K; ++j) xn[j] = d[(long)j * (K + 1) * N];
+                if constexpr (FOLD) fn = fsrc[(b + 1) * fold.sb];
+            }
+            Acc a0, a1;
+            acc_zero(a0);
+            acc_zero(a1);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                acc_mac(a0, x[j], kb[j]);
+                acc_mac(a1, x[j], ka[j]);
+            }
+            if constexpr (FOLD) acc_mac(a0, fx, fm);
+            u64 *o = out0 + b * ob;
+            o[0] = acc_reduce(a0, p);
+            o[(long)(K + 1) * N] = acc_reduce(a1, p);
         }
-        if (fd) acc_mac(a0, fsrc[b * fold.sb], fm);
-        u64 *o = out + b * ob + (long)r * 2 * (K + 1) * N + (long)t * N + n;
-        o[0] = acc_reduce(a0, p);
-        o[(long)(K + 1) * N] = acc_reduce(a1, p);
-    }
+    };
+    if (fd) run(std::true_type{});
+    else run(std::false_type{});
 }
 
 // Baby-step MAC of Eq. (1): inner[b][k2][c][i] = sum_{j < t1} pt[k2 t1 + j][i] * rot_j(ct_b)[c][i]
@@ -1175,7 +1218,8 @@ static int mac_chunk(int t2, int cap) {
 }
 
 void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb, const u64 *bank, u64 *inner,
-                int B, int rows, int ext_nq, int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st) {
+                int B, int rows, int ext_nq, int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st,
+                int part) {
     const int cts = kn.mac_cts < 1 ? 1 : kn.mac_cts > 8 ? 8 : kn.mac_cts;
     const int by = B < cts ? B : cts;
     PrimeList all{}, fp{}, in{};
@@ -1197,7 +1241,7 @@ void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb
         }
         return;
     }
-    if (fp.n) {
+    if (fp.n && part != 2) {
         const dim3 grid((1u << logn) / 64, fp.n, ((B + by - 1) / by) * (t2 / kc)), blk(64, by);
         switch (kc) {
 #define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac_fp<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, fp, tab.pc); break;
@@ -1206,7 +1250,7 @@ void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb
 #undef CTL_MAC
         }
     }
-    if (in.n) {
+    if (in.n && part != 1) {
         const dim3 grid((1u << logn) / 64, in.n, ((B + by - 1) / by) * (t2 / kc)), blk(64, by);
         switch (kc) {
 #define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, in, tab.pc); break;
