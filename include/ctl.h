@@ -111,13 +111,18 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
  *                        the direct form is faster up to 3 ciphertexts, the staged one from 4);
  *   CTL_KNOB_NTT_XCD     1: ModUp workgroups numbered so that the targets of one digit, and ModDown
  *                        workgroups so that the primes of one group, run on one XCD and share its
- *                        L2; 0 (default): plain order (measured slightly faster at N = 2^14).
+ *                        L2; 0 (default): plain order (measured slightly faster at N = 2^14);
+ *   CTL_KNOB_MAC_LIMB    1 (default): the plaintext MAC and the key product over primes of 41..60
+ *                        bits multiply 30-bit limbs into carry-free column sums (the MAC then
+ *                        keeps at most 8 giant-step accumulators per thread); 0: 128-bit
+ *                        accumulation. Primes of 61 bits always take the latter.
  * Out-of-range values give CTL_EINVAL and leave the knob unchanged. */
 #define CTL_KNOB_MAC_CHUNK 0
 #define CTL_KNOB_MAC_CTS 1
 #define CTL_KNOB_KEYIP_XCD 2
 #define CTL_KNOB_MAC_DIRECT 3
 #define CTL_KNOB_NTT_XCD 4
+#define CTL_KNOB_MAC_LIMB 5
 int ctl_knob_set(ctl_ctx *ctx, int knob, int value);
 int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value);
 

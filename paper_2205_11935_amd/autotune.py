@@ -22,6 +22,7 @@ CANDIDATES: Dict[str, List[int]] = {
     "mac_cts": [8, 4, 2],
     "keyip_xcd": [1, 0],
     "ntt_xcd": [1, 0],
+    "mac_limb": [1, 0],
 }
 
 

@@ -1093,6 +1093,7 @@ int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
         }
         const bool fp = q < kFpPrimeLimit;
         c->tab.host_fp[i] = fp ? 1 : 0;
+        c->tab.host_lt60[i] = c->hp.mods[i] < (1ull << 60) ? 1 : 0;
         for (int m = 0; m < n; ++m) {
             unsigned r = 0;
             for (int b = 0; b < c->hp.logn; ++b) r |= ((m >> b) & 1u) << (c->hp.logn - 1 - b);
@@ -1215,6 +1216,10 @@ int ctl_knob_set(ctl_ctx *ctx, int knob, int value) {
             if (value != 0 && value != 1) return fail(CTL_EINVAL, "ModUp/ModDown numbering is 0 or 1");
             ctx->knobs.ntt_xcd = value;
             return CTL_OK;
+        case CTL_KNOB_MAC_LIMB:
+            if (value != 0 && value != 1) return fail(CTL_EINVAL, "the limb MAC switch is 0 or 1");
+            ctx->knobs.mac_limb = value;
+            return CTL_OK;
         default:
             return fail(CTL_EINVAL, "unknown knob");
     }
@@ -1228,6 +1233,7 @@ int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value) {
         case CTL_KNOB_KEYIP_XCD: *value = ctx->knobs.keyip_xcd; return CTL_OK;
         case CTL_KNOB_MAC_DIRECT: *value = ctx->knobs.mac_direct_max; return CTL_OK;
         case CTL_KNOB_NTT_XCD: *value = ctx->knobs.ntt_xcd; return CTL_OK;
+        case CTL_KNOB_MAC_LIMB: *value = ctx->knobs.mac_limb; return CTL_OK;
         default: return fail(CTL_EINVAL, "unknown knob");
     }
 }

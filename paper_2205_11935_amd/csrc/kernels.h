@@ -21,6 +21,7 @@ struct Tables {
     const PrimeConst *pc;               // [np]
     const CrossConst *cross;            // [kMaxMods][kMaxMods], entry [i * kMaxMods + j]
     unsigned char host_fp[kMaxMods];    // host copy of pc[i].fp, for launch decisions
+    unsigned char host_lt60[kMaxMods];  // prime i below 2^60 (30-bit limb products apply)
 };
 
 constexpr int kMaxKeysPerLaunch = 64;
@@ -72,13 +73,15 @@ void launch_sum_gather(int logn, u64 *out, long o_sb, const u64 *base, long ba_s
                        const Tables &tab, hipStream_t st);
 // Launch choices an autotuner may set (defaults in brackets): the largest giant-step chunk of the
 // MAC [16], ciphertexts per MAC workgroup [8], XCD-grouped key-product numbering [1], largest
-// batch that uses the unstaged MAC [3], XCD-grouped ModUp / ModDown numbering [0].
+// batch that uses the unstaged MAC [3], XCD-grouped ModUp / ModDown numbering [0], 30-bit limb
+// products in the integer-prime MAC [1].
 struct Knobs {
     int mac_chunk_cap = 16;
     int mac_cts = 8;
     int keyip_xcd = 1;
     int mac_direct_max = 3;      // batches up to this size use the unstaged MAC
     int ntt_xcd = 0;             // XCD-grouped numbering of ModUp and ModDown workgroups
+    int mac_limb = 1;            // integer-prime MAC by 30-bit limbs where every prime is below 2^60
 };
 
 void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,

@@ -623,6 +623,45 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
     for (int e = 0; e < 16; ++e) dst[tid + T * e] = fwd_result(lds, tid + T * e, fp, p);
 }
 
+// ---------------------------------------------------------------- 30-bit limb products
+// For a prime below 2^60 every residue splits as x = xh 2^30 + xl with xh, xl < 2^30, and a
+// product x w is four 30 x 30-bit products (each below 2^60) that v_mad_u64_u32 adds into 64-bit
+// column sums of weights 1, 2^30 and 2^60 without carries; a column takes 16 such products
+// before it could reach 2^64. The value is reduced mod q once, from its 128-bit form.
+constexpr u64 kM30 = (1ull << 30) - 1;
+
+__device__ __forceinline__ void limb_normalize(u64 (&c)[3], const PrimeConst &p) {
+    c[1] += c[0] >> 30;
+    c[0] &= kM30;
+    c[2] += c[1] >> 30;
+    c[1] &= kM30;
+    c[2] = reduce_any(c[2], p);
+}
+
+__device__ __forceinline__ u64 limb_reduce(u64 (&c)[3], const PrimeConst &p) {
+    limb_normalize(c, p);
+    Acc a;                                   // (c1 2^30 + c0) + c2 2^60 as a 128-bit value
+    const u64 lo = c[0] | (c[1] << 30), add = c[2] << 60;
+    a.lo = lo + add;
+    a.hi = (c[2] >> 4) + (a.lo < add ? 1ull : 0ull);
+    return acc_reduce(a, p);
+}
+
+// c[0] + (c[1] + c[2]) 2^30 + c[3] 2^60 mod q for column sums below 2^64 each.
+__device__ __forceinline__ u64 limb_reduce4(const u64 (&c)[4], const PrimeConst &p) {
+    Acc a;
+    a.lo = c[0];
+    a.hi = 0;
+    const u64 t1 = c[1] << 30, t2 = c[2] << 30, t3 = c[3] << 60;
+    a.lo += t1;
+    a.hi += (c[1] >> 34) + (a.lo < t1 ? 1ull : 0ull);
+    a.lo += t2;
+    a.hi += (c[2] >> 34) + (a.lo < t2 ? 1ull : 0ull);
+    a.lo += t3;
+    a.hi += (c[3] >> 4) + (a.lo < t3 ? 1ull : 0ull);
+    return acc_reduce(a, p);
+}
+
 // ---------------------------------------------------------------- elementwise kernels
 // Key inner product with the automorphism fused into the digit gather:
 //   out[b][r][0][t] = sum_j D[b][r][j][t][sigma_r] * key_r[j][0][t] (+ fold),  out[..][1][t]
@@ -642,7 +681,7 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
 template <int K>
 __global__ void __launch_bounds__(256)
 k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__restrict__ out, long ob,
-        KeyFold fold, int B, int R, int nq, int logn, int xcd_order, const PrimeConst *__restrict__ pcs) {
+        KeyFold fold, int B, int R, int nq, int logn, int xcd_order, unsigned lt60, const PrimeConst *__restrict__ pcs) {
     const int pairs = (K + 1) << (logn - 8);
     int r, pair;
     if (xcd_order) {
@@ -707,6 +746,67 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
                 u64 *o = out0 + b * ob;
                 o[0] = fp_to_u64(a0, p.qd, p.qinv);
                 o[(long)(K + 1) * N] = fp_to_u64(a1, p.qd, p.qinv);
+            }
+        };
+        if (fd) run(std::true_type{});
+        else run(std::false_type{});
+        return;
+    }
+    if ((lt60 >> pt) & 1) {
+        // prime below 2^60: 30-bit limb products into carry-free column sums (see k_mac_limb);
+        // with the two cross products in separate columns every column takes 16 terms, and a
+        // sum has at most K + 1 <= 9
+        u32 bl[K], bh[K], al[K], ah[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const u64 b0 = key[((long)(j * 2 + 0) * np + pt) * N + n];
+            const u64 a0 = key[((long)(j * 2 + 1) * np + pt) * N + n];
+            bl[j] = (u32)b0 & (u32)kM30;
+            bh[j] = (u32)(b0 >> 30);
+            al[j] = (u32)a0 & (u32)kM30;
+            ah[j] = (u32)(a0 >> 30);
+        }
+        const u32 fml = (u32)fm & (u32)kM30, fmh = (u32)(fm >> 30);
+        auto run = [&](auto fold_tag) {
+            constexpr bool FOLD = decltype(fold_tag)::value;
+            u64 xn[K], fn = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) xn[j] = dig0[(long)j * (K + 1) * N];
+            if constexpr (FOLD) fn = fsrc[0];
+            for (int b = 0; b < B; ++b) {
+                u64 x[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) x[j] = xn[j];
+                const u64 fx = fn;
+                if (b + 1 < B) {
+                    const u64 *d = dig0 + (b + 1) * db;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) xn[j] = d[(long)j * (K + 1) * N];
+                    if constexpr (FOLD) fn = fsrc[(b + 1) * fold.sb];
+                }
+                u64 c0[4] = {0, 0, 0, 0}, c1[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const u32 xl = (u32)x[j] & (u32)kM30, xh = (u32)(x[j] >> 30);
+                    c0[0] += (u64)xl * bl[j];
+                    c0[1] += (u64)xl * bh[j];
+                    c0[2] += (u64)xh * bl[j];
+                    c0[3] += (u64)xh * bh[j];
+                    c1[0] += (u64)xl * al[j];
+                    c1[1] += (u64)xl * ah[j];
+                    c1[2] += (u64)xh * al[j];
+                    c1[3] += (u64)xh * ah[j];
+                }
+                if constexpr (FOLD) {
+                    const u32 xl = (u32)fx & (u32)kM30, xh = (u32)(fx >> 30);
+                    c0[0] += (u64)xl * fml;
+                    c0[1] += (u64)xl * fmh;
+                    c0[2] += (u64)xh * fml;
+                    c0[3] += (u64)xh * fmh;
+                }
+                u64 *o = out0 + b * ob;
+                o[0] = limb_reduce4(c0, p);
+                o[(long)(K + 1) * N] = limb_reduce4(c1, p);
             }
         };
         if (fd) run(std::true_type{});
@@ -895,6 +995,97 @@ k_mac(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long 
                 o[0] = acc_reduce(acc[kk][0], p);
                 o[kn] = acc_reduce(acc[kk][1], p);
             }
+        }
+    }
+}
+
+// The integer-prime MAC with 30-bit limbs, for rows whose prime is below 2^60 (every residue
+// then splits as x = xh 2^30 + xl with xh, xl < 2^30). A product x w is four 30 x 30-bit products
+// accumulated by v_mad_u64_u32 without carries into three 64-bit column sums of weights 1, 2^30
+// and 2^60 (c[1] takes both cross products). Every 8 terms the columns are normalized (c0, c1 <
+// 2^30, c2 reduced mod q), which keeps each below 2^64 for the next 8: c0 < 2^30 + 8 2^60,
+// c1 < 2^30 + 16 (2^30 - 1)^2, c2 < q + 8 2^60 + 2^34. Once per output the 128-bit value
+// c0 + c1 2^30 + c2 2^60 is reduced mod q. Same staging, grid and outputs as k_mac.
+template <int KC>
+__global__ void __launch_bounds__(512)
+k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long rot_sb,
+           const u64 *__restrict__ bank, u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn,
+           PrimeList pl, const PrimeConst *__restrict__ pcs) {
+    __shared__ u64 wt[kMacJB * KC * 64];
+    const int nl = threadIdx.x, bl = threadIdx.y;
+    const int tid = bl * 64 + nl, nthr = 64 * blockDim.y;
+    const int i = pl.idx[blockIdx.y];
+    const long N = 1L << logn, kn = (long)k * N;
+    const long n0 = (long)blockIdx.x * 64;
+    const int nbz = (B + blockDim.y - 1) / blockDim.y;   // grid z = ciphertext groups x KC-chunks
+    const int b = (blockIdx.z % nbz) * blockDim.y + bl;
+    const int kc0 = (blockIdx.z / nbz) * KC;
+    const bool live = b < B;
+    const PrimeConst p = pcs[pl.prime[blockIdx.y]];
+    const u64 *ct_b = ct + (long)(live ? b : 0) * ct_sb + i * N + n0 + nl;
+    const u64 *rot_b = rot + (long)(live ? b : 0) * rot_sb + i * N + n0 + nl;
+    u64 c[KC][2][3];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) c[kk][q][0] = c[kk][q][1] = c[kk][q][2] = 0;
+    int since = 0;                               // terms added since the last normalization
+    for (int j0 = 0; j0 < t1; j0 += kMacJB) {
+        const int jn = t1 - j0 < kMacJB ? t1 - j0 : kMacJB;
+        u32 xl[kMacJB][2], xh[kMacJB][2];
+#pragma unroll
+        for (int jj = 0; jj < kMacJB; ++jj) {
+            const int j = j0 + jj;
+            u64 x0 = 0, x1 = 0;
+            if (live && jj < jn) {
+                const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
+                x0 = src[0];
+                x1 = src[kn];
+            }
+            xl[jj][0] = (u32)x0 & (u32)kM30;
+            xh[jj][0] = (u32)(x0 >> 30);
+            xl[jj][1] = (u32)x1 & (u32)kM30;
+            xh[jj][1] = (u32)(x1 >> 30);
+        }
+        __syncthreads();
+        for (int e = tid; e < jn * KC * 64; e += nthr) {
+            const int jj = e / (KC * 64), kk = (e / 64) % KC;
+            wt[e] = bank[((long)(kc0 + kk) * t1 + j0 + jj) * kn + i * N + n0 + (e & 63)];
+        }
+        __syncthreads();
+        if (since + jn > 8) {                    // uniform: keep every column below 2^64
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                limb_normalize(c[kk][0], p);
+                limb_normalize(c[kk][1], p);
+            }
+            since = 0;
+        }
+#pragma unroll
+        for (int jj = 0; jj < kMacJB; ++jj) {
+            if (jj < jn) {
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk) {
+                    const u64 w = wt[(jj * KC + kk) * 64 + nl];
+                    const u32 wl = (u32)w & (u32)kM30, wh = (u32)(w >> 30);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        c[kk][q][0] += (u64)xl[jj][q] * wl;
+                        c[kk][q][1] += (u64)xl[jj][q] * wh;
+                        c[kk][q][1] += (u64)xh[jj][q] * wl;
+                        c[kk][q][2] += (u64)xh[jj][q] * wh;
+                    }
+                }
+            }
+        }
+        since += jn;
+    }
+    if (live) {
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
+            o[0] = limb_reduce(c[kk][0], p);
+            o[kn] = limb_reduce(c[kk][1], p);
         }
     }
 }
@@ -1200,9 +1391,11 @@ void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const Ke
     if (R <= 0 || B <= 0) return;
     const int pairs = (k + 1) << (logn - 8);
     const int xo = kn.keyip_xcd ? 1 : 0;
+    unsigned lt60 = 0;
+    for (int i = 0; i <= nq && kn.mac_limb; ++i) lt60 |= (tab.host_lt60[i] ? 1u : 0u) << i;
     const dim3 grid((unsigned)(xo ? ((pairs + 7) / 8) * 8 * R : pairs * R)), blk(256);
     switch (k) {
-#define CTL_KIP(K) case K: hipLaunchKernelGGL(k_keyip<K>, grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, tab.pc); break;
+#define CTL_KIP(K) case K: hipLaunchKernelGGL(k_keyip<K>, grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, lt60, tab.pc); break;
         CTL_KIP(1) CTL_KIP(2) CTL_KIP(3) CTL_KIP(4) CTL_KIP(5) CTL_KIP(6) CTL_KIP(7) CTL_KIP(8)
 #undef CTL_KIP
         default: break;
@@ -1251,6 +1444,19 @@ void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb
         }
     }
     if (in.n && part != 1) {
+        bool limb = kn.mac_limb != 0;
+        for (int y = 0; y < in.n; ++y) limb = limb && tab.host_lt60[in.prime[y]];
+        if (limb) {
+            const int kl = mac_chunk(t2, kn.mac_chunk_cap < 8 ? kn.mac_chunk_cap : 8);   // 12 VGPRs per chunk entry
+            const dim3 grid((1u << logn) / 64, in.n, ((B + by - 1) / by) * (t2 / kl)), blk(64, by);
+            switch (kl) {
+#define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac_limb<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, in, tab.pc); break;
+                CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
+                default: hipLaunchKernelGGL(k_mac_limb<1>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, in, tab.pc); break;
+#undef CTL_MAC
+            }
+            return;
+        }
         const dim3 grid((1u << logn) / 64, in.n, ((B + by - 1) / by) * (t2 / kc)), blk(64, by);
         switch (kc) {
 #define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, in, tab.pc); break;
