@@ -1201,7 +1201,7 @@ int ctl_knob_set(ctl_ctx *ctx, int knob, int value) {
             ctx->knobs.mac_chunk_cap = value;
             return CTL_OK;
         case CTL_KNOB_MAC_CTS:
-            if (value < 1 || value > 8) return fail(CTL_EINVAL, "ciphertexts per MAC workgroup must lie in 1..8");
+            if (value < 1 || value > 16) return fail(CTL_EINVAL, "ciphertexts per MAC workgroup must lie in 1..16");
             ctx->knobs.mac_cts = value;
             return CTL_OK;
         case CTL_KNOB_KEYIP_XCD:

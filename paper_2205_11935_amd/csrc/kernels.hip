@@ -134,6 +134,28 @@ __device__ __forceinline__ int galois_src(int i, u64 g, int logn) {
     return (int)(__brev((t - 1) >> 1) >> (32 - logn));
 }
 
+// ---------------------------------------------------------------- buffer loads and stores
+// A raw buffer resource over `bytes` bytes from `base` (scalar registers when base is uniform):
+// a load or store then addresses base + voffset (a per-lane 32-bit byte offset) + soffset (a
+// uniform one) with no address arithmetic on the vector ALU. Accesses at or past `bytes` read 0
+// and write nothing. Third descriptor word 0x00020000: raw 32-bit data, as for every gfx9 part.
+typedef __amdgpu_buffer_rsrc_t BufRsrc;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ BufRsrc buf_rsrc(const void *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ u64 buf_load(BufRsrc r, int voffset, int soffset) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voffset, soffset, 0);
+    return ((u64)v.y << 32) | v.x;
+}
+__device__ __forceinline__ void buf_store(u64 x, BufRsrc r, int voffset, int soffset) {
+    u32x2 v;
+    v.x = (unsigned)x;
+    v.y = (unsigned)(x >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voffset, soffset, 0);
+}
+
 // ---------------------------------------------------------------- NTT engine
 template <int LOGN>
 struct Geo {
@@ -705,9 +727,42 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
     const int n = g == 1 ? m : galois_src(m, keys.ginv[r], logn);   // the output that gathers from m
     const bool fd = fold.src != nullptr && t < fold.rows;            // uniform per workgroup
     const u64 fm = fd ? fold.mul[t] : 0;
-    const u64 *fsrc = fd ? fold.src + r * fold.sr + (long)t * N + src : nullptr;
-    const u64 *dig0 = digits + r * dr + (long)t * N + src;           // ciphertext b at + b db
-    u64 *out0 = out + (long)r * 2 * (K + 1) * N + (long)t * N + n;   // ciphertext b at + b ob
+    // Batch loop. Ciphertext b's K digit words (and its fold word) come from buffer loads whose
+    // address is a per-lane offset plus scalar parts (no per-load address arithmetic on the
+    // VALU), one ciphertext ahead of the products; ciphertexts go in pairs so that the prefetched
+    // words need no copies.
+    const int voff_d = (int)(((long)t * N + src) * 8);
+    const int voff_o = (int)(((long)r * 2 * (K + 1) * N + (long)t * N + n) * 8);
+    const int voff_f = fd ? (int)(((long)r * fold.sr + (long)t * N + src) * 8) : 0;
+    const int rec_d = K * (K + 1) * N * 8, rec_o = (int)(ob * 8), rec_f = fd ? (int)(fold.sb * 8) : 0;
+    const int sd = (K + 1) * N * 8;                                    // digit j at + j sd bytes
+    const u64 *dbase = digits + r * dr;
+    auto load = [&](int b, u64 (&x)[K], u64 &f, bool fold_on) {
+        const BufRsrc rd = buf_rsrc(dbase + b * db, rec_d);
+#pragma unroll
+        for (int j = 0; j < K; ++j) x[j] = buf_load(rd, voff_d, j * sd);
+        if (fold_on) f = buf_load(buf_rsrc(fold.src + b * fold.sb, rec_f), voff_f, 0);
+    };
+    auto store = [&](int b, u64 v0, u64 v1) {
+        const BufRsrc ro = buf_rsrc(out + b * ob, rec_o);
+        buf_store(v0, ro, voff_o, 0);
+        buf_store(v1, ro, voff_o, sd);
+    };
+    // pairs (b, b + 1): xa holds b, xb is filled with b + 1 while b is multiplied, then xa with b + 2
+    auto batch = [&](auto fold_tag, auto &&product) {
+        constexpr bool FOLD = decltype(fold_tag)::value;
+        u64 xa[K], xb[K], fa = 0, fb = 0;
+        load(0, xa, fa, FOLD);
+        for (int b = 0; b < B; b += 2) {
+            const bool two = b + 1 < B;
+            if (two) load(b + 1, xb, fb, FOLD);
+            product(b, xa, fa);
+            if (two) {
+                if (b + 2 < B) load(b + 2, xa, fa, FOLD);
+                product(b + 1, xb, fb);
+            }
+        }
+    };
     if (p.fp) {
         // FP64 products (prime < 2^41): each term |.| <= 0.52 q, sums stay far below 2^53
         double kb[K], ka[K];
@@ -719,22 +774,7 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
         const double fmd = u64_to_fp(fm);
         auto run = [&](auto fold_tag) {
             constexpr bool FOLD = decltype(fold_tag)::value;
-            // the words of ciphertext b + 1 are loaded while b is multiplied
-            u64 xn[K], fn = 0;
-#pragma unroll
-            for (int j = 0; j < K; ++j) xn[j] = dig0[(long)j * (K + 1) * N];
-            if constexpr (FOLD) fn = fsrc[0];
-            for (int b = 0; b < B; ++b) {
-                u64 x[K];
-#pragma unroll
-                for (int j = 0; j < K; ++j) x[j] = xn[j];
-                const u64 fx = fn;
-                if (b + 1 < B) {
-                    const u64 *d = dig0 + (b + 1) * db;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) xn[j] = d[(long)j * (K + 1) * N];
-                    if constexpr (FOLD) fn = fsrc[(b + 1) * fold.sb];
-                }
+            batch(fold_tag, [&](int b, const u64 (&x)[K], u64 fx) {
                 double a0 = 0.0, a1 = 0.0;
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
@@ -743,10 +783,8 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
                     a1 += fp_mul(xd, ka[j], p.qd, p.qinv);
                 }
                 if constexpr (FOLD) a0 += fp_mul(u64_to_fp(fx), fmd, p.qd, p.qinv);
-                u64 *o = out0 + b * ob;
-                o[0] = fp_to_u64(a0, p.qd, p.qinv);
-                o[(long)(K + 1) * N] = fp_to_u64(a1, p.qd, p.qinv);
-            }
+                store(b, fp_to_u64(a0, p.qd, p.qinv), fp_to_u64(a1, p.qd, p.qinv));
+            });
         };
         if (fd) run(std::true_type{});
         else run(std::false_type{});
@@ -769,21 +807,7 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
         const u32 fml = (u32)fm & (u32)kM30, fmh = (u32)(fm >> 30);
         auto run = [&](auto fold_tag) {
             constexpr bool FOLD = decltype(fold_tag)::value;
-            u64 xn[K], fn = 0;
-#pragma unroll
-            for (int j = 0; j < K; ++j) xn[j] = dig0[(long)j * (K + 1) * N];
-            if constexpr (FOLD) fn = fsrc[0];
-            for (int b = 0; b < B; ++b) {
-                u64 x[K];
-#pragma unroll
-                for (int j = 0; j < K; ++j) x[j] = xn[j];
-                const u64 fx = fn;
-                if (b + 1 < B) {
-                    const u64 *d = dig0 + (b + 1) * db;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) xn[j] = d[(long)j * (K + 1) * N];
-                    if constexpr (FOLD) fn = fsrc[(b + 1) * fold.sb];
-                }
+            batch(fold_tag, [&](int b, const u64 (&x)[K], u64 fx) {
                 u64 c0[4] = {0, 0, 0, 0}, c1[4] = {0, 0, 0, 0};
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
@@ -804,10 +828,8 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
                     c0[2] += (u64)xh * fml;
                     c0[3] += (u64)xh * fmh;
                 }
-                u64 *o = out0 + b * ob;
-                o[0] = limb_reduce4(c0, p);
-                o[(long)(K + 1) * N] = limb_reduce4(c1, p);
-            }
+                store(b, limb_reduce4(c0, p), limb_reduce4(c1, p));
+            });
         };
         if (fd) run(std::true_type{});
         else run(std::false_type{});
@@ -821,21 +843,7 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
     }
     auto run = [&](auto fold_tag) {
         constexpr bool FOLD = decltype(fold_tag)::value;
-        u64 xn[K], fn = 0;
-#pragma unroll
-        for (int j = 0; j < K; ++j) xn[j] = dig0[(long)j * (K + 1) * N];
-        if constexpr (FOLD) fn = fsrc[0];
-        for (int b = 0; b < B; ++b) {
-            u64 x[K];
-#pragma unroll
-            for (int j = 0; j < K; ++j) x[j] = xn[j];
-            const u64 fx = fn;
-            if (b + 1 < B) {
-                const u64 *d = dig0 + (b + 1) * db;
-#pragma unroll
-                for (int j = 0; j < K; ++j) xn[j] = d[(long)j * (K + 1) * N];
-                if constexpr (FOLD) fn = fsrc[(b + 1) * fold.sb];
-            }
+        batch(fold_tag, [&](int b, const u64 (&x)[K], u64 fx) {
             Acc a0, a1;
             acc_zero(a0);
             acc_zero(a1);
@@ -845,10 +853,8 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
                 acc_mac(a1, x[j], ka[j]);
             }
             if constexpr (FOLD) acc_mac(a0, fx, fm);
-            u64 *o = out0 + b * ob;
-            o[0] = acc_reduce(a0, p);
-            o[(long)(K + 1) * N] = acc_reduce(a1, p);
-        }
+            store(b, acc_reduce(a0, p), acc_reduce(a1, p));
+        });
     };
     if (fd) run(std::true_type{});
     else run(std::false_type{});
@@ -859,7 +865,8 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
 // (j - 1) 2 K N. K = `k` residue rows per polynomial (with the baby steps kept over Q*P the last
 // row is mod P); row i = pl.idx[y] has prime pl.prime[y].
 // Per coefficient this is a (t2 x t1) by (t1 x 2B) modular matrix product. A workgroup covers 64
-// consecutive coefficients of one prime for up to 8 ciphertexts (threadIdx.y); each thread keeps
+// consecutive coefficients of one prime for up to 16 (FP64) or 8 (integer) ciphertexts
+// (threadIdx.y); each thread keeps
 // KC giant-step accumulators per polynomial, so every rotated ciphertext word is read once per
 // KC-chunk. The plaintext words of JB baby steps are staged in LDS per barrier pair and shared by
 // the workgroup's ciphertexts; the ciphertext words of those JB steps are loaded first.
@@ -870,7 +877,7 @@ constexpr int kMacJB = 4;
 // The FP64 and integer forms are separate kernels launched over their own primes (PrimeList,
 // grid y), so that the FP64 one is not held to the register budget of 128-bit accumulators.
 template <int KC>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_mac_fp(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long rot_sb,
          const u64 *__restrict__ bank, u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn,
          PrimeList pl, const PrimeConst *__restrict__ pcs) {
@@ -1413,8 +1420,9 @@ static int mac_chunk(int t2, int cap) {
 void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb, const u64 *bank, u64 *inner,
                 int B, int rows, int ext_nq, int t1, int t2, const Tables &tab, const Knobs &kn, hipStream_t st,
                 int part) {
-    const int cts = kn.mac_cts < 1 ? 1 : kn.mac_cts > 8 ? 8 : kn.mac_cts;
-    const int by = B < cts ? B : cts;
+    // ciphertexts per workgroup: up to 16 for the FP64 kernel (1024 threads), 8 for the integer ones
+    const int cts = kn.mac_cts < 1 ? 1 : kn.mac_cts > 16 ? 16 : kn.mac_cts;
+    const int by = B < cts ? B : cts, by_int = by < 8 ? by : 8;
     PrimeList all{}, fp{}, in{};
     for (int i = 0; i < rows; ++i) {
         const int pi = (ext_nq >= 0 && i == rows - 1) ? ext_nq : i;
@@ -1448,7 +1456,7 @@ void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb
         for (int y = 0; y < in.n; ++y) limb = limb && tab.host_lt60[in.prime[y]];
         if (limb) {
             const int kl = mac_chunk(t2, kn.mac_chunk_cap < 8 ? kn.mac_chunk_cap : 8);   // 12 VGPRs per chunk entry
-            const dim3 grid((1u << logn) / 64, in.n, ((B + by - 1) / by) * (t2 / kl)), blk(64, by);
+            const dim3 grid((1u << logn) / 64, in.n, ((B + by_int - 1) / by_int) * (t2 / kl)), blk(64, by_int);
             switch (kl) {
 #define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac_limb<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, in, tab.pc); break;
                 CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
@@ -1457,7 +1465,7 @@ void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb
             }
             return;
         }
-        const dim3 grid((1u << logn) / 64, in.n, ((B + by - 1) / by) * (t2 / kc)), blk(64, by);
+        const dim3 grid((1u << logn) / 64, in.n, ((B + by_int - 1) / by_int) * (t2 / kc)), blk(64, by_int);
         switch (kc) {
 #define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, in, tab.pc); break;
             CTL_MAC(16) CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
