@@ -245,6 +245,25 @@ def test_forward_full_batch_sampled(lazy):
     assert np.array_equal(one[0], got[5])
 
 
+@pytest.mark.parametrize("lazy", [True, "qp"])
+def test_forward_ragged_batch(lazy):
+    """13 ciphertexts of the mid workload: not a multiple of the MAC's ciphertexts per workgroup
+    (8) and odd for the key product's pairs; ciphertexts 0, 7 and 12 against the oracle, every one
+    against its own evaluation alone."""
+    name = "mid"
+    o, c = _orc(name), _ctx(name)
+    lk, _, _, okeys, rlk = _keys(name)
+    plan = _plan(name, lazy)
+    model, banks_ntt = _raw_model(name, seed=51, lazy=lazy)
+    B = 13
+    dev, ref = _fresh_ct(name, 19, count=B)
+    got = _u64(c.forward(model, lk, dev))
+    for b in (0, 7, 12):
+        assert np.array_equal(got[b], o.forward(plan, ref[b], banks_ntt, okeys, rlk)), b
+    for b in range(B):
+        assert np.array_equal(_u64(c.forward(model, lk, dev[b:b + 1].contiguous()))[0], got[b]), b
+
+
 # ------------------------------------------------------------------ encoding and end-to-end tolerance
 @pytest.mark.parametrize("name", ["small", "mid", "large"])
 def test_encode_matches_oracle(name):
