@@ -29,9 +29,9 @@ def _setup(name, lazy):
     w = W.WORKLOADS[name]
     c = ctl.Context.for_workload(w)
     o = CKKSOracle.for_workload(w)
-    plan = o.plan([(l.n_in, l.n_out, l.t1) for l in w.layers], lazy=lazy)
+    plan = o.plan([(l.n_in, l.n_out, l.t1) for l in w.layers], lazy=bool(lazy), qp=lazy == "qp")
     banks = [W.raw_plaintexts(61 + li, L.t, o.n, bound_bits=45, stream=li) for li, L in enumerate(plan.layers)]
-    model = c.load_model_raw([(l.n_in, l.n_out, l.t1) for l in w.layers], banks, lazy=lazy)
+    model = c.load_model_raw([(l.n_in, l.n_out, l.t1) for l in w.layers], banks, lazy=bool(lazy), qp=lazy == "qp")
     keys = [c.keygen(s, model.info.rotations, relin=True) for s in CLIENT_SEEDS]
     return ctl, w, c, o, plan, banks, model, keys
 
@@ -44,7 +44,7 @@ def _batch(c, o, keys, owners, seed):
     return dev, msgs
 
 
-@pytest.mark.parametrize("name,lazy", [("mid", False), ("large", True)])
+@pytest.mark.parametrize("name,lazy", [("mid", False), ("mid", "qp"), ("large", "qp")])
 def test_mixed_clients_equal_each_alone(name, lazy):
     ctl, w, c, o, plan, banks, model, keys = _setup(name, lazy)
     owners = [0, 0, 1, 2, 0, 1, 1, 2]              # runs of 2, 1, 1, 1, 2, 1
@@ -59,10 +59,11 @@ def test_mixed_clients_equal_each_alone(name, lazy):
     assert np.array_equal(same, ctl.to_numpy_u64(c.forward(model, keys[0], dev)))
 
 
-def test_mixed_clients_against_oracle():
+@pytest.mark.parametrize("lazy", [False, "qp"])
+def test_mixed_clients_against_oracle(lazy):
     """Client 1's ciphertexts, batched between client 0's and 2's, against the oracle run with
     client 1's key seed."""
-    ctl, w, c, o, plan, banks, model, keys = _setup("mid", False)
+    ctl, w, c, o, plan, banks, model, keys = _setup("mid", lazy)
     owners = [0, 1, 2, 1]
     dev, msgs = _batch(c, o, keys, owners, 72)
     got = ctl.to_numpy_u64(c.forward_multi(model, [keys[i] for i in owners], dev))
@@ -71,7 +72,7 @@ def test_mixed_clients_against_oracle():
     pk = o.keygen_public(seed, s)
     okeys = o.keygen_rotations(seed, s, plan.rotations)
     rlk = o.keygen_relin(seed, s)
-    banks_ntt = [o.bank_ntt(banks[li], L.k) for li, L in enumerate(plan.layers)]
+    banks_ntt = [o.bank_ntt(banks[li], L.k, ext=lazy == "qp") for li, L in enumerate(plan.layers)]
     for b in (1, 3):
         ct = o.encrypt(pk, msgs[b], 72 * 1000 + b)
         assert np.array_equal(got[b], o.forward(plan, ct, banks_ntt, okeys, rlk)), b
