@@ -361,24 +361,33 @@ class CKKSOracle:
         self.lib.or_affine(self.c, k, k_out, _p(np.ascontiguousarray(ct)), mul, add, _p(out))
         return out
 
-    def conv1d(self, ct: np.ndarray, pts: np.ndarray, keys: Dict[int, np.ndarray]) -> np.ndarray:
-        """sum_i pts_i * rot_{i - (f-1)/2}(ct), rescaled. pts: [f][k][N] NTT form."""
+    def conv1d(self, ct: np.ndarray, pts: np.ndarray, keys: Dict[int, np.ndarray], qp: bool = False) -> np.ndarray:
+        """sum_i pts_i * rot_{i - (f-1)/2}(ct), rescaled. pts: [f][k][N] NTT form; qp: the rotations
+        kept over Q*P with one ModDown of the sum (pts then [f][k+1][N])."""
         k = ct.shape[1]
+        if pts.shape[1] != k + (1 if qp else 0):
+            raise ValueError("plaintext rows do not match the variant")
         out = np.zeros((2, k - 1, self.n), dtype=np.uint64)
         gs, arr = self._keyset(keys)
-        rc = self.lib.or_conv1d(self.c, k, _p(np.ascontiguousarray(ct)), _p(np.ascontiguousarray(pts)),
-                                pts.shape[0], len(gs), _p(gs), arr, _p(out))
+        fn = self.lib.or_conv1d_qp if qp else self.lib.or_conv1d
+        rc = fn(self.c, k, _p(np.ascontiguousarray(ct)), _p(np.ascontiguousarray(pts)),
+                pts.shape[0], len(gs), _p(gs), arr, _p(out))
         if rc:
             raise RuntimeError("or_conv1d failed: %d" % rc)
         return out
 
-    def avgpool(self, ct: np.ndarray, pt: np.ndarray, f: int, keys: Dict[int, np.ndarray]) -> np.ndarray:
-        """pt * sum_{i < f} rot_{-i}(ct), rescaled. pt: [k][N] NTT form."""
+    def avgpool(self, ct: np.ndarray, pt: np.ndarray, f: int, keys: Dict[int, np.ndarray],
+                qp: bool = False) -> np.ndarray:
+        """pt * sum_{i < f} rot_{-i}(ct), rescaled. pt: [k][N] NTT form; qp: the rotations kept over
+        Q*P with one ModDown of the sum (pt then [k+1][N])."""
         k = ct.shape[1]
+        if pt.shape[0] != k + (1 if qp else 0):
+            raise ValueError("plaintext rows do not match the variant")
         out = np.zeros((2, k - 1, self.n), dtype=np.uint64)
         gs, arr = self._keyset(keys)
-        rc = self.lib.or_avgpool(self.c, k, _p(np.ascontiguousarray(ct)), _p(np.ascontiguousarray(pt)), f,
-                                 len(gs), _p(gs), arr, _p(out))
+        fn = self.lib.or_avgpool_qp if qp else self.lib.or_avgpool
+        rc = fn(self.c, k, _p(np.ascontiguousarray(ct)), _p(np.ascontiguousarray(pt)), f,
+                len(gs), _p(gs), arr, _p(out))
         if rc:
             raise RuntimeError("or_avgpool failed: %d" % rc)
         return out

@@ -1055,6 +1055,94 @@ done:
 /* Average pool, stride 1, size f (Section 3.1, "Average Pool"): s = sum_{i < f} rot_{-i}(ct)
  * (f - 1 rotations), then one plaintext product with pt (1/f on the valid outputs, 0 elsewhere)
  * and a rescale. pt: [k][N] NTT form. */
+/* sum_j pts_j * ct~_{rots_j} over Q*P ([2][k+1][N] into acc): ct~_0 = P ct for rotation 0, else the
+ * hoisted key product of sigma(c1) plus (P sigma(c0), 0) (the baby steps of dense_qp).
+ * pts: [n][k+1][N] (row k mod P), or a single plaintext for every term when pt_stride is 0. */
+static int qp_rotation_sum(const or_ctx *c, int k, const u64 *ct, const long *rots, int n_rot, const u64 *pts,
+                           size_t pt_stride, const keyset_t *ks, u64 *acc) {
+    int n = c->n, nq = c->nq;
+    size_t kn = (size_t)k * n, en = (size_t)(k + 1) * n, ecs = 2 * en;
+    u64 *dig = (u64 *)malloc(sizeof(u64) * (size_t)k * (k + 1) * n);
+    u64 *r = (u64 *)malloc(sizeof(u64) * ecs), *tmp = (u64 *)malloc(sizeof(u64) * n);
+    int primes[OR_MAXP], rc = 0;
+    for (int i = 0; i < k; i++) primes[i] = i;
+    primes[k] = nq;
+    memset(acc, 0, sizeof(u64) * ecs);
+    or_modup(c, k, ct + kn, dig);
+    for (int j = 0; j < n_rot; j++) {
+        if (rots[j] == 0) {
+            memset(r, 0, sizeof(u64) * ecs);
+            for (int p = 0; p < 2; p++)
+                for (int i = 0; i < k; i++) {
+                    u64 q = c->q[i], pm = c->q[nq] % q;
+                    for (int x = 0; x < n; x++) r[p * en + (size_t)i * n + x] = mulm(pm, ct[p * kn + (size_t)i * n + x], q);
+                }
+        } else {
+            u64 g = or_galois_elt(c, rots[j]);
+            const u64 *key = find_key(ks, g);
+            if (!key) { rc = -5; goto done; }
+            key_inner(c, k, dig, key, g, r);
+            for (int i = 0; i < k; i++) {
+                u64 q = c->q[i], pm = c->q[nq] % q;
+                or_automorph_ntt(c, g, ct + (size_t)i * n, tmp);
+                for (int x = 0; x < n; x++) r[(size_t)i * n + x] = addm(r[(size_t)i * n + x], mulm(pm, tmp[x], q), q);
+            }
+        }
+        const u64 *pt = pts + pt_stride * j;
+        for (int p = 0; p < 2; p++)
+            for (int i = 0; i <= k; i++) {
+                u64 q = c->q[primes[i]];
+                for (int x = 0; x < n; x++) {
+                    size_t o = (size_t)i * n + x;
+                    acc[p * en + o] = addm(acc[p * en + o], mulm(pt[o], r[p * en + o], q), q);
+                }
+            }
+    }
+done:
+    free(dig); free(r); free(tmp);
+    return rc;
+}
+
+/* Convolution with its rotations kept over Q*P (the baby steps of dense_qp, one ModDown of the
+ * sum): ModDown(sum_i pts_i * ct~_{i-(f-1)/2}), then the rescale. pts: [f][k+1][N]. */
+int or_conv1d_qp(const or_ctx *c, int k, const u64 *ct, const u64 *pts, int f, int n_keys, const u64 *gs,
+                 const u64 *const *keys, u64 *out) {
+    keyset_t ks = {n_keys, gs, keys};
+    int n = c->n, h = (f - 1) / 2;
+    size_t en = (size_t)(k + 1) * n;
+    long rots[64];
+    if (f > 64) return -1;
+    for (int i = 0; i < f; i++) rots[i] = (long)i - h;
+    u64 *acc = (u64 *)malloc(sizeof(u64) * 2 * en), *low = (u64 *)malloc(sizeof(u64) * 2 * (size_t)k * n);
+    int rc = qp_rotation_sum(c, k, ct, rots, f, pts, en, &ks, acc);
+    if (!rc) {
+        or_moddown(c, k, acc, low);
+        or_rescale(c, k, low, out);
+    }
+    free(acc); free(low);
+    return rc;
+}
+
+/* Average pool with its rotations kept over Q*P: ModDown(pt * sum_{i<f} ct~_{-i}) (the products
+ * summed term by term, the same residues by distributivity), then the rescale. pt: [k+1][N]. */
+int or_avgpool_qp(const or_ctx *c, int k, const u64 *ct, const u64 *pt, int f, int n_keys, const u64 *gs,
+                  const u64 *const *keys, u64 *out) {
+    keyset_t ks = {n_keys, gs, keys};
+    int n = c->n;
+    size_t en = (size_t)(k + 1) * n;
+    long rots[64];
+    if (f > 64) return -1;
+    for (int i = 0; i < f; i++) rots[i] = -(long)i;
+    u64 *acc = (u64 *)malloc(sizeof(u64) * 2 * en), *low = (u64 *)malloc(sizeof(u64) * 2 * (size_t)k * n);
+    int rc = qp_rotation_sum(c, k, ct, rots, f, pt, 0, &ks, acc);
+    if (!rc) {
+        or_moddown(c, k, acc, low);
+        or_rescale(c, k, low, out);
+    }
+    free(acc); free(low);
+    return rc;
+}
+
 int or_avgpool(const or_ctx *c, int k, const u64 *ct, const u64 *pt, int f, int n_keys, const u64 *gs,
                const u64 *const *keys, u64 *out) {
     keyset_t ks = {n_keys, gs, keys};

@@ -127,12 +127,13 @@ def banks(p: CnnPlan, o: CKKSOracle, taps, w1, w2) -> Dict[str, np.ndarray]:
 def forward(p: CnnPlan, o: CKKSOracle, ct: np.ndarray, raw: Dict[str, np.ndarray], keys, rlk,
             coef: Sequence[float], qp: bool = False) -> np.ndarray:
     """The encrypted frozen stack on one top-level ciphertext; raw: int64 plaintexts (see banks).
-    Dense layers with single-ModDown giant steps; qp: their baby steps over Q*P as well."""
-    conv = np.stack([o.plaintext(m, p.k_conv) for m in raw["conv"]])
-    ct = o.conv1d(ct, conv, keys)
+    Dense layers with single-ModDown giant steps; qp: every hoisted rotation (dense baby steps,
+    convolution, pool) kept over Q*P with one ModDown per sum."""
+    conv = np.stack([o.plaintext(m, p.k_conv, ext=qp) for m in raw["conv"]])
+    ct = o.conv1d(ct, conv, keys, qp=qp)
     ct = o.dense(ct, o.bank_ntt(raw["dense1"], p.k_dense1, ext=qp), p.t1, keys, lazy=True, qp=qp)
     ct, _ = o.poly3(ct, p.scale_in, coef, rlk)
-    ct = o.avgpool(ct, o.plaintext(raw["pool"], p.k_pool), p.f_pool, keys)
+    ct = o.avgpool(ct, o.plaintext(raw["pool"], p.k_pool, ext=qp), p.f_pool, keys, qp=qp)
     ct = o.replicate(ct, p.width, keys)
     return o.dense(ct, o.bank_ntt(raw["dense2"], p.k_dense2, ext=qp), p.t1, keys, lazy=True, qp=qp)
 

@@ -121,6 +121,60 @@ def test_avgpool_matches_numpy_valid_mean():
         assert np.max(np.abs(z[base + p.width: base + p.block])) < 2.0 ** -12
 
 
+# ------------------------------------------------------------------ rotations kept over Q*P
+def _unit_pts(o, k, f, i, ext):
+    raw = np.zeros((f, o.n), dtype=np.int64)
+    raw[i, 0] = 1
+    return np.stack([o.plaintext(m, k, ext) for m in raw])
+
+
+@pytest.mark.parametrize("i", [0, 3, 4, 8])
+def test_conv1d_qp_with_a_unit_tap_equals_plain_rotation(i):
+    """One tap equal to 1, the others 0: the Q*P sum is ct~_{i-4}, whose ModDown is exactly
+    rot_{i-4}(ct), so both variants give the same bits."""
+    o, s, pk, keys, rlk = _small()
+    g = np.random.Generator(np.random.PCG64(31))
+    ct = _enc(o, pk, g.uniform(-1, 1, o.n // 2), 32)
+    k = o.nq
+    a = o.conv1d(ct, _unit_pts(o, k, 9, i, False), keys)
+    b = o.conv1d(ct, _unit_pts(o, k, 9, i, True), keys, qp=True)
+    assert np.array_equal(a, b)
+
+
+def test_conv1d_and_pool_qp_single_term_equal_plain():
+    """f = 1: the only term is P ct, which ModDown returns exactly, for any plaintext."""
+    o, s, pk, keys, rlk = _small()
+    g = np.random.Generator(np.random.PCG64(33))
+    ct = _enc(o, pk, g.uniform(-1, 1, o.n // 2), 34)
+    k = o.nq
+    m = o.encode(g.uniform(-1, 1, o.n // 2), float(o.q[k - 1]))
+    assert np.array_equal(o.conv1d(ct, o.plaintext(m, k)[None], keys),
+                          o.conv1d(ct, o.plaintext(m, k, True)[None], keys, qp=True))
+    assert np.array_equal(o.avgpool(ct, o.plaintext(m, k), 1, keys),
+                          o.avgpool(ct, o.plaintext(m, k, True), 1, keys, qp=True))
+
+
+def test_conv1d_and_pool_qp_match_numpy():
+    o, s, pk, keys, rlk = _small()
+    p = _cnn_small_plan()
+    g = np.random.Generator(np.random.PCG64(35))
+    x = g.uniform(-1, 1, (p.items, p.width))
+    taps = g.normal(0, 0.3, p.f_conv)
+    ct = _enc(o, pk, cnn.input_slots(p, o, x), 36)
+    k = o.nq
+    pts = np.stack([o.plaintext(o.encode(cnn.conv_tap_slots(p, o, taps, i), float(o.q[k - 1])), k, True)
+                    for i in range(p.f_conv)])
+    z = _dec(o, s, o.conv1d(ct, pts, keys, qp=True), o.scale)
+    ptp = o.plaintext(o.encode(cnn.pool_slots(p, o), float(o.q[k - 1])), k, True)
+    zp = _dec(o, s, o.avgpool(ct, ptp, p.f_pool, keys, qp=True), o.scale)
+    for b in range(p.items):
+        base = b * p.block
+        ref = np.convolve(x[b], taps[::-1], mode="same")
+        assert np.max(np.abs(z[base: base + p.width] - ref)) < 2.0 ** -12
+        refp = np.convolve(x[b], np.ones(p.f_pool) / p.f_pool, mode="valid")
+        assert np.max(np.abs(zp[base + p.f_pool - 1: base + p.width] - refp)) < 2.0 ** -12
+
+
 @pytest.mark.parametrize("coef", [(0.75, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1), W.RELU3_COEF,
                                   (-0.3, 0.2, -0.05, 0.01)])
 def test_poly3_evaluates_the_polynomial(coef):
@@ -160,9 +214,11 @@ def test_fp64_stack_matches_numpy_routines():
     assert np.max(np.abs(got - ref)) < 1e-9 * np.max(np.abs(ref))
 
 
-def test_frozen_stack_p1_end_to_end():
-    """The whole frozen stack at CryptoTL_p1 (N = 2^13, Delta = 2^25, 2 items) against FP64.
-    Fresh encryption noise alone is about 2^-10.6 of a unit slot at this scale; measured 2^-11."""
+@pytest.mark.parametrize("qp", [False, True])
+def test_frozen_stack_p1_end_to_end(qp):
+    """The whole frozen stack at CryptoTL_p1 (N = 2^13, Delta = 2^25, 2 items) against FP64, with
+    every hoisted rotation lowered per rotation or kept over Q*P. Fresh encryption noise alone is
+    about 2^-10.6 of a unit slot at this scale; measured 2^-11."""
     w = W.CNN_P1
     o = CKKSOracle(w.log2n, w.q_bits, w.p_bits, w.log2_scale, w.sigma)
     assert sum(x.bit_length() for x in o.primes) == 218            # Table 2's log2 q
@@ -176,7 +232,7 @@ def test_frozen_stack_p1_end_to_end():
     rlk = o.keygen_relin(w.seed_keys, s)
     x = W.cnn_inputs(w, 1, p.items)[0]
     ct = o.encrypt(pk, o.encode(cnn.input_slots(p, o, x), o.scale), 11)
-    out = cnn.forward(p, o, ct, raw, keys, rlk, W.RELU3_COEF)
+    out = cnn.forward(p, o, ct, raw, keys, rlk, W.RELU3_COEF, qp=qp)
     assert out.shape == (2, 1, o.n)
     y = cnn.output_values(p, o.decrypt_decode(s, out, p.scale_act_out), w.pooled)
     ref = np.stack([cnn.forward_fp64(x[b], taps, w1, w2, W.RELU3_COEF, w.f_pool) for b in range(p.items)])
