@@ -230,15 +230,15 @@ int ctl_evk_bytes(const ctl_evk *evk, uint64_t *bytes_out);
  * ModDown), the diagonal plaintexts are stored with a residue mod P as well, the products of
  * Eq. (1) are summed over Q*P, and only the c1 of each giant step and the final sum are lowered:
  * t2 + 1 polynomials per ciphertext go through ModDown instead of 2 t1. Implies
- * CTL_LAYER_LAZY_GIANT. Same value up to rounding; the bank takes (k+1)/k of the memory. Dense
- * layers only. */
+ * CTL_LAYER_LAZY_GIANT. Same value up to rounding; the bank takes (k+1)/k of the memory. Also
+ * for convolutions and average pools: their rotations over Q*P, one ModDown of the sum. */
 #define CTL_LAYER_BABY_QP 2
 
 /* One layer. A dense layer y = W x with W of shape [n_out][n_in] is evaluated by the baby-step
  * giant-step diagonal method (Eq. (1) of Section 3.1) with padded width t = max(off + n_in, n_out),
  * t = t1 * t2 (t1 must divide t; off = f - 1 after an average pool, else 0). act applies x^2
  * (CTL_ACT_SQUARE) or the cubic in coef (CTL_ACT_POLY3) after the layer, never after the last.
- * flags: 0, CTL_LAYER_LAZY_GIANT or CTL_LAYER_BABY_QP (dense only). Zero-filled fields select a
+ * flags: 0, CTL_LAYER_LAZY_GIANT (dense only) or CTL_LAYER_BABY_QP. Zero-filled fields select a
  * dense layer. */
 typedef struct ctl_layer_desc {
     int n_in;

@@ -492,11 +492,12 @@ class Context:
                 for j in range(4):
                     arr[i].coef[j] = float(l.coef[j])
                 lazy_ok = l.kind == CTL_LAYER_DENSE
+                qp_ok = True                       # every kind has hoisted rotations
             else:
                 arr[i].n_in, arr[i].n_out, arr[i].t1 = l[0], l[1], l[2]
                 arr[i].act = l[3] if len(l) > 3 else (CTL_ACT_SQUARE if i + 1 < len(layers) else CTL_ACT_NONE)
-                lazy_ok = True
-            arr[i].flags = (CTL_LAYER_BABY_QP if (qp and lazy_ok) else
+                lazy_ok = qp_ok = True
+            arr[i].flags = (CTL_LAYER_BABY_QP if (qp and qp_ok) else
                             CTL_LAYER_LAZY_GIANT if (lazy and lazy_ok) else 0)
         return arr
 

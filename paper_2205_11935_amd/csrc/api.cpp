@@ -94,7 +94,7 @@ struct ctl_evk {
 
 struct LayerPlan {
     int n_in, n_out, t, t1, t2, k, act;
-    bool lazy;
+    bool lazy = false;
     bool qp = false;              // baby steps over Q*P: the bank carries a row mod P
     double pt_scale;
     int kind = CTL_LAYER_DENSE;
@@ -750,15 +750,15 @@ int plan_model(const ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, con
         if (l > 0 && layers[l - 1].kind == CTL_LAYER_AVGPOOL && d.kind != CTL_LAYER_DENSE)
             return fail(CTL_EINVAL, "an average pool must be followed by a dense layer");
         if (d.flags & ~(CTL_LAYER_LAZY_GIANT | CTL_LAYER_BABY_QP)) return fail(CTL_EINVAL, "unknown layer flag");
-        if ((d.flags & CTL_LAYER_BABY_QP) && d.kind != CTL_LAYER_DENSE)
-            return fail(CTL_EINVAL, "CTL_LAYER_BABY_QP applies to dense layers");
+        if ((d.flags & CTL_LAYER_LAZY_GIANT) && d.kind != CTL_LAYER_DENSE)
+            return fail(CTL_EINVAL, "CTL_LAYER_LAZY_GIANT applies to dense layers");
+        L.qp = (d.flags & CTL_LAYER_BABY_QP) != 0;
         if (d.kind == CTL_LAYER_DENSE) {
             L.in_off = (l > 0 && layers[l - 1].kind == CTL_LAYER_AVGPOOL) ? layers[l - 1].f - 1 : 0;
             L.t = std::max(L.in_off + d.n_in, d.n_out);
             if (d.t1 < 1 || L.t % d.t1) return fail(CTL_EINVAL, "t1 must divide the padded width");
             L.t1 = d.t1;
             L.t2 = L.t / d.t1;
-            L.qp = (d.flags & CTL_LAYER_BABY_QP) != 0;
             L.lazy = L.qp || (d.flags & CTL_LAYER_LAZY_GIANT) != 0;
             for (int j = 1; j < L.t1; ++j) L.rots1.push_back(j);
         } else if (d.kind == CTL_LAYER_CONV1D) {

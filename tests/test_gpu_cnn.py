@@ -81,16 +81,18 @@ def test_mul_and_poly3_bit_exact(name):
 
 @pytest.mark.parametrize("name", ["cnn_p1", "cnn_p2"])
 def test_each_layer_bit_exact(name):
-    """Convolution and average pool alone (ctl_dense on their layer index) against the oracle."""
+    """Convolution and average pool alone (ctl_dense on their layer index, rotations over Q*P)
+    against the oracle."""
     ctl, w, c, o, p, raw, m, keys, (s, pk, okeys, rlk) = _setup(name)
     g = np.random.Generator(np.random.PCG64(22))
     ct = o.encrypt(pk, g.integers(-2 ** 40, 2 ** 40, o.n), 400)
     got = ctl.to_numpy_u64(c.dense(m, 0, keys, ctl.from_numpy_u64(ct[None])))[0]
-    conv = np.stack([o.plaintext(x, p.k_conv) for x in raw["conv"]])
-    assert np.array_equal(got, o.conv1d(ct, conv, okeys))
+    conv = np.stack([o.plaintext(x, p.k_conv, ext=True) for x in raw["conv"]])
+    assert np.array_equal(got, o.conv1d(ct, conv, okeys, qp=True))
     ct3 = ct[:, : p.k_pool].copy()
     got = ctl.to_numpy_u64(c.dense(m, 2, keys, ctl.from_numpy_u64(ct3[None])))[0]
-    assert np.array_equal(got, o.avgpool(ct3, o.plaintext(raw["pool"], p.k_pool), p.f_pool, okeys))
+    assert np.array_equal(got, o.avgpool(ct3, o.plaintext(raw["pool"], p.k_pool, ext=True), p.f_pool, okeys,
+                                         qp=True))
 
 
 @pytest.mark.parametrize("name", ["cnn_p1", "cnn_p2"])
