@@ -139,6 +139,8 @@ __device__ __forceinline__ int galois_src(int i, u64 g, int logn) {
 // a load or store then addresses base + voffset (a per-lane 32-bit byte offset) + soffset (a
 // uniform one) with no address arithmetic on the vector ALU. Accesses at or past `bytes` read 0
 // and write nothing. Third descriptor word 0x00020000: raw 32-bit data, as for every gfx9 part.
+// Stores are non-temporal: their data (rotated ciphertexts, read back by a later kernel) would
+// otherwise displace the digit words that the key product's workgroups share through L2.
 typedef __amdgpu_buffer_rsrc_t BufRsrc;
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -153,7 +155,7 @@ __device__ __forceinline__ void buf_store(u64 x, BufRsrc r, int voffset, int sof
     u32x2 v;
     v.x = (unsigned)x;
     v.y = (unsigned)(x >> 32);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, voffset, soffset, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voffset, soffset, 2);    // nt: streamed, not kept in L2
 }
 
 // ---------------------------------------------------------------- NTT engine
