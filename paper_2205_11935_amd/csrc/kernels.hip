@@ -523,7 +523,9 @@ k_ntt_inv(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
 // q_j to every target t in 0..k (t = k is the special prime) and transformed:
 // digits[g][j][t] (NTT form). The diagonal t = j is the input residue itself (the lift from q_j to
 // q_j is the identity), copied from d (NTT form, residue g k + j of dmap). One workgroup per
-// (g, j, t).
+// (g, j, t). The digits are stored non-temporally: the key product reads them after every
+// workgroup here has finished, so keeping them in L2 only displaces the coefficients this kernel
+// re-reads (the MAC's outputs are stored the same way for the same reason).
 template <int LOGN>
 __global__ void __launch_bounds__(Geo<LOGN>::T)
 k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u64 *__restrict__ digits, int k,
@@ -561,7 +563,7 @@ k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u6
     for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qj, qj_mod, p);
     const bool fp = fwd_transform<LOGN>(v, lds, tid, tab, pt, p);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) dst[tid + T * e] = fwd_result(lds, tid + T * e, fp, p);
+    for (int e = 0; e < 16; ++e) __builtin_nontemporal_store(fwd_result(lds, tid + T * e, fp, p), &dst[tid + T * e]);
 }
 
 // Drop the last modulus of each group (ModDown when it is P, rescale when it is q_k):
@@ -936,8 +938,8 @@ k_mac_fp(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, lo
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
                 u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
-                o[0] = fp_to_u64(acc[kk][0], p.qd, p.qinv);
-                o[kn] = fp_to_u64(acc[kk][1], p.qd, p.qinv);
+                __builtin_nontemporal_store(fp_to_u64(acc[kk][0], p.qd, p.qinv), &o[0]);
+                __builtin_nontemporal_store(fp_to_u64(acc[kk][1], p.qd, p.qinv), &o[kn]);
             }
         }
     }
@@ -1093,8 +1095,8 @@ k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, 
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
             u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
-            o[0] = limb_reduce(c[kk][0], p);
-            o[kn] = limb_reduce(c[kk][1], p);
+            __builtin_nontemporal_store(limb_reduce(c[kk][0], p), &o[0]);
+            __builtin_nontemporal_store(limb_reduce(c[kk][1], p), &o[kn]);
         }
     }
 }
