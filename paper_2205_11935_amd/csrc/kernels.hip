@@ -910,8 +910,8 @@ k_mac_fp(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, lo
                 const int j = j0 + jj;
                 if (live && jj < jn) {
                     const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
-                    x[jj][0] = u64_to_fp(src[0]);
-                    x[jj][1] = u64_to_fp(src[kn]);
+                    x[jj][0] = u64_to_fp(__builtin_nontemporal_load(&src[0]));
+                    x[jj][1] = u64_to_fp(__builtin_nontemporal_load(&src[kn]));
                 } else {
                     x[jj][0] = x[jj][1] = 0.0;
                 }
@@ -1050,8 +1050,8 @@ k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, 
             u64 x0 = 0, x1 = 0;
             if (live && jj < jn) {
                 const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
-                x0 = src[0];
-                x1 = src[kn];
+                x0 = __builtin_nontemporal_load(&src[0]);
+                x1 = __builtin_nontemporal_load(&src[kn]);
             }
             xl[jj][0] = (u32)x0 & (u32)kM30;
             xh[jj][0] = (u32)(x0 >> 30);
