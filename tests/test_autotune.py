@@ -54,5 +54,5 @@ def test_tune_forward_pass_bit_identical():
         assert v in autotune.CANDIDATES[name] and c.knob(name) == v
     assert res["best_ms"] > 0
     with pytest.raises(ctl.CtlError):
-        c.knob("mac_cts", 9)
+        c.knob("mac_cts", 17)
     assert c.knob("mac_cts") == res["knobs"]["mac_cts"]
