@@ -1119,6 +1119,7 @@ int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
         p.ninvs = h_shoup(p.ninv, q);
         p.qn = 0 - q;
         p.nq2 = 0 - 2 * q;
+        p.r60 = q < (1ull << 60) ? (1ull << 60) % q : 1ull << 60;
         p.fp = fp ? 1 : 0;
         p.pad_ = 0;
         p.qd = (double)q;

@@ -656,12 +656,16 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
 // before it could reach 2^64. The value is reduced mod q once, from its 128-bit form.
 constexpr u64 kM30 = (1ull << 30) - 1;
 
+// c2 only has to come back below 2^63 here (8 more terms then add < 2^63 + 2^34). When 2^60 mod q
+// is below 2^58 (primes near 2^60), c2 = t 2^60 + u with t < 16 is replaced by the congruent
+// t (2^60 mod q) + u < 2^60 + 15 2^58 < 2^62; for other primes it is reduced mod q.
 __device__ __forceinline__ void limb_normalize(u64 (&c)[3], const PrimeConst &p) {
     c[1] += c[0] >> 30;
     c[0] &= kM30;
     c[2] += c[1] >> 30;
     c[1] &= kM30;
-    c[2] = reduce_any(c[2], p);
+    if (p.r60 < (1ull << 58)) c[2] = (c[2] & ((1ull << 60) - 1)) + (u64)(u32)(c[2] >> 60) * p.r60;
+    else c[2] = reduce_any(c[2], p);
 }
 
 __device__ __forceinline__ u64 limb_reduce(u64 (&c)[3], const PrimeConst &p) {
@@ -880,67 +884,101 @@ constexpr int kMacJB = 4;
 
 // The FP64 and integer forms are separate kernels launched over their own primes (PrimeList,
 // grid y), so that the FP64 one is not held to the register budget of 128-bit accumulators.
+//
+// k_mac_fp and k_mac_limb are software-pipelined over JB-chunks of baby steps. Before a chunk is
+// multiplied, this wave's rows of the next chunk's plaintext words are loaded into registers; they
+// go to the other of two LDS buffers afterwards, so each chunk costs one barrier. Each rotated
+// ciphertext word, once consumed, has its register refilled with the word at the same position
+// of the next chunk. Staging row r of a chunk (r = jj KC + kk, 64 words) belongs to the wave of
+// threadIdx.y = r mod blockDim.y; with 8 or more ciphertexts per workgroup that is at most
+// kMacStage(KC) rows per wave, and smaller workgroups stage their remaining rows after the
+// multiplications.
+template <int KC>
+constexpr int kMacStage = (kMacJB * KC + 7) / 8;
+
 template <int KC>
 __global__ void __launch_bounds__(1024)
 k_mac_fp(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long rot_sb,
          const u64 *__restrict__ bank, u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn,
          PrimeList pl, const PrimeConst *__restrict__ pcs) {
-    __shared__ double wd[kMacJB * KC * 64];
-    const int nl = threadIdx.x, bl = threadIdx.y;
-    const int tid = bl * 64 + nl, nthr = 64 * blockDim.y;
+    constexpr int kSt = kMacStage<KC>;
+    __shared__ double wd[2][kMacJB * KC * 64];
+    const int nl = threadIdx.x, bl = __builtin_amdgcn_readfirstlane(threadIdx.y), by = blockDim.y;
     const int i = pl.idx[blockIdx.y];
     const long N = 1L << logn, kn = (long)k * N;
     const long n0 = (long)blockIdx.x * 64;
-    const int nbz = (B + blockDim.y - 1) / blockDim.y;   // grid z = ciphertext groups x KC-chunks
-    const int b = (blockIdx.z % nbz) * blockDim.y + bl;
+    const int nbz = (B + by - 1) / by;              // grid z = ciphertext groups x KC-chunks
+    const int b = (blockIdx.z % nbz) * by + bl;
     const int kc0 = (blockIdx.z / nbz) * KC;
     const bool live = b < B;
     const PrimeConst p = pcs[pl.prime[blockIdx.y]];
     const u64 *ct_b = ct + (long)(live ? b : 0) * ct_sb + i * N + n0 + nl;
     const u64 *rot_b = rot + (long)(live ? b : 0) * rot_sb + i * N + n0 + nl;
+    const u64 *bk = bank + (long)kc0 * t1 * kn + i * N + n0 + nl;
+    // plaintext word of staging row r (wave-uniform) of the chunk starting at baby step j0
+    auto bank_row = [&](int j0, int r) -> u64 { return bk[((long)(r % KC) * t1 + j0 + r / KC) * kn]; };
+    double acc[KC][2];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) acc[kk][0] = acc[kk][1] = 0.0;
+    u64 xr[kMacJB][2];
     {
-        double acc[KC][2];
+        const int jn = t1 < kMacJB ? t1 : kMacJB;
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) acc[kk][0] = acc[kk][1] = 0.0;
-        for (int j0 = 0; j0 < t1; j0 += kMacJB) {
-            const int jn = t1 - j0 < kMacJB ? t1 - j0 : kMacJB;
-            double x[kMacJB][2];
+        for (int jj = 0; jj < kMacJB; ++jj) {
+            if (jj < jn) {
+                const u64 *src = jj == 0 ? ct_b : rot_b + (long)(jj - 1) * 2 * kn;
+                xr[jj][0] = __builtin_nontemporal_load(&src[0]);
+                xr[jj][1] = __builtin_nontemporal_load(&src[kn]);
+            }
+        }
+        for (int r = bl; r < jn * KC; r += by) wd[0][r * 64 + nl] = u64_to_fp(bank_row(0, r));
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int j0 = 0; j0 < t1; j0 += kMacJB, buf ^= 1) {
+        const int jn = t1 - j0 < kMacJB ? t1 - j0 : kMacJB;
+        const int j1 = j0 + kMacJB;
+        const int jn1 = j1 >= t1 ? 0 : (t1 - j1 < kMacJB ? t1 - j1 : kMacJB);
+        const int rows1 = jn1 * KC;
+        u64 bs[kSt];
 #pragma unroll
-            for (int jj = 0; jj < kMacJB; ++jj) {
-                const int j = j0 + jj;
-                if (live && jj < jn) {
-                    const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
-                    x[jj][0] = u64_to_fp(__builtin_nontemporal_load(&src[0]));
-                    x[jj][1] = u64_to_fp(__builtin_nontemporal_load(&src[kn]));
-                } else {
-                    x[jj][0] = x[jj][1] = 0.0;
+        for (int s = 0; s < kSt; ++s) {
+            const int r = bl + s * by;
+            bs[s] = bank_row(j1 < t1 ? j1 : j0, r < rows1 ? r : 0);   // unconditional: no early wait
+        }
+        const double *w_l = wd[buf];
+#pragma unroll
+        for (int jj = 0; jj < kMacJB; ++jj) {
+            if (jj < jn) {
+                const double x0 = u64_to_fp(live ? xr[jj][0] : 0), x1 = u64_to_fp(live ? xr[jj][1] : 0);
+                if (jj < jn1) {                  // uniform; rot_b of a spare thread is a valid row
+                    const u64 *src = rot_b + (long)(j1 + jj - 1) * 2 * kn;
+                    xr[jj][0] = __builtin_nontemporal_load(&src[0]);
+                    xr[jj][1] = __builtin_nontemporal_load(&src[kn]);
                 }
-            }
-            __syncthreads();
-            for (int e = tid; e < jn * KC * 64; e += nthr) {
-                const int jj = e / (KC * 64), kk = (e / 64) % KC;
-                wd[e] = u64_to_fp(bank[((long)(kc0 + kk) * t1 + j0 + jj) * kn + i * N + n0 + (e & 63)]);
-            }
-            __syncthreads();
 #pragma unroll
-            for (int jj = 0; jj < kMacJB; ++jj) {
-                if (jj < jn) {
-#pragma unroll
-                    for (int kk = 0; kk < KC; ++kk) {
-                        const double w = wd[(jj * KC + kk) * 64 + nl];
-                        acc[kk][0] += fp_mul(x[jj][0], w, p.qd, p.qinv);
-                        acc[kk][1] += fp_mul(x[jj][1], w, p.qd, p.qinv);
-                    }
+                for (int kk = 0; kk < KC; ++kk) {
+                    const double w = w_l[(jj * KC + kk) * 64 + nl];
+                    acc[kk][0] += fp_mul(x0, w, p.qd, p.qinv);
+                    acc[kk][1] += fp_mul(x1, w, p.qd, p.qinv);
                 }
             }
         }
-        if (live) {
+        double *w_n = wd[buf ^ 1];
 #pragma unroll
-            for (int kk = 0; kk < KC; ++kk) {
-                u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
-                __builtin_nontemporal_store(fp_to_u64(acc[kk][0], p.qd, p.qinv), &o[0]);
-                __builtin_nontemporal_store(fp_to_u64(acc[kk][1], p.qd, p.qinv), &o[kn]);
-            }
+        for (int s = 0; s < kSt; ++s) {
+            const int r = bl + s * by;
+            if (r < rows1) w_n[r * 64 + nl] = u64_to_fp(bs[s]);
+        }
+        for (int r = bl + kSt * by; r < rows1; r += by) w_n[r * 64 + nl] = u64_to_fp(bank_row(j1, r));
+        __syncthreads();
+    }
+    if (live) {
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            u64 *o = inner + ((long)b * t2 + kc0 + kk) * 2 * kn + i * N + n0 + nl;
+            __builtin_nontemporal_store(fp_to_u64(acc[kk][0], p.qd, p.qinv), &o[0]);
+            __builtin_nontemporal_store(fp_to_u64(acc[kk][1], p.qd, p.qinv), &o[kn]);
         }
     }
 }
@@ -1014,56 +1052,61 @@ k_mac(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long 
 // then splits as x = xh 2^30 + xl with xh, xl < 2^30). A product x w is four 30 x 30-bit products
 // accumulated by v_mad_u64_u32 without carries into three 64-bit column sums of weights 1, 2^30
 // and 2^60 (c[1] takes both cross products). Every 8 terms the columns are normalized (c0, c1 <
-// 2^30, c2 reduced mod q), which keeps each below 2^64 for the next 8: c0 < 2^30 + 8 2^60,
-// c1 < 2^30 + 16 (2^30 - 1)^2, c2 < q + 8 2^60 + 2^34. Once per output the 128-bit value
+// 2^30, c2 < 2^62), which keeps each below 2^64 for the next 8: c0 < 2^30 + 8 2^60,
+// c1 < 2^30 + 16 (2^30 - 1)^2, c2 < 2^62 + 8 2^60 + 2^34. Once per output the 128-bit value
 // c0 + c1 2^30 + c2 2^60 is reduced mod q. Same staging, grid and outputs as k_mac.
 template <int KC>
 __global__ void __launch_bounds__(512)
 k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long rot_sb,
            const u64 *__restrict__ bank, u64 *__restrict__ inner, int B, int k, int t1, int t2, int logn,
            PrimeList pl, const PrimeConst *__restrict__ pcs) {
-    __shared__ u64 wt[kMacJB * KC * 64];
-    const int nl = threadIdx.x, bl = threadIdx.y;
-    const int tid = bl * 64 + nl, nthr = 64 * blockDim.y;
+    constexpr int kSt = kMacStage<KC>;
+    __shared__ u64 wt[2][kMacJB * KC * 64];
+    const int nl = threadIdx.x, bl = __builtin_amdgcn_readfirstlane(threadIdx.y), by = blockDim.y;
     const int i = pl.idx[blockIdx.y];
     const long N = 1L << logn, kn = (long)k * N;
     const long n0 = (long)blockIdx.x * 64;
-    const int nbz = (B + blockDim.y - 1) / blockDim.y;   // grid z = ciphertext groups x KC-chunks
-    const int b = (blockIdx.z % nbz) * blockDim.y + bl;
+    const int nbz = (B + by - 1) / by;              // grid z = ciphertext groups x KC-chunks
+    const int b = (blockIdx.z % nbz) * by + bl;
     const int kc0 = (blockIdx.z / nbz) * KC;
     const bool live = b < B;
     const PrimeConst p = pcs[pl.prime[blockIdx.y]];
     const u64 *ct_b = ct + (long)(live ? b : 0) * ct_sb + i * N + n0 + nl;
     const u64 *rot_b = rot + (long)(live ? b : 0) * rot_sb + i * N + n0 + nl;
+    const u64 *bk = bank + (long)kc0 * t1 * kn + i * N + n0 + nl;
+    auto bank_row = [&](int j0, int r) -> u64 { return bk[((long)(r % KC) * t1 + j0 + r / KC) * kn]; };
     u64 c[KC][2][3];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
 #pragma unroll
         for (int q = 0; q < 2; ++q) c[kk][q][0] = c[kk][q][1] = c[kk][q][2] = 0;
-    int since = 0;                               // terms added since the last normalization
-    for (int j0 = 0; j0 < t1; j0 += kMacJB) {
-        const int jn = t1 - j0 < kMacJB ? t1 - j0 : kMacJB;
-        u32 xl[kMacJB][2], xh[kMacJB][2];
+    u64 xr[kMacJB][2];
+    {
+        const int jn = t1 < kMacJB ? t1 : kMacJB;
 #pragma unroll
         for (int jj = 0; jj < kMacJB; ++jj) {
-            const int j = j0 + jj;
-            u64 x0 = 0, x1 = 0;
             if (live && jj < jn) {
-                const u64 *src = j == 0 ? ct_b : rot_b + (long)(j - 1) * 2 * kn;
-                x0 = __builtin_nontemporal_load(&src[0]);
-                x1 = __builtin_nontemporal_load(&src[kn]);
+                const u64 *src = jj == 0 ? ct_b : rot_b + (long)(jj - 1) * 2 * kn;
+                xr[jj][0] = __builtin_nontemporal_load(&src[0]);
+                xr[jj][1] = __builtin_nontemporal_load(&src[kn]);
             }
-            xl[jj][0] = (u32)x0 & (u32)kM30;
-            xh[jj][0] = (u32)(x0 >> 30);
-            xl[jj][1] = (u32)x1 & (u32)kM30;
-            xh[jj][1] = (u32)(x1 >> 30);
         }
-        __syncthreads();
-        for (int e = tid; e < jn * KC * 64; e += nthr) {
-            const int jj = e / (KC * 64), kk = (e / 64) % KC;
-            wt[e] = bank[((long)(kc0 + kk) * t1 + j0 + jj) * kn + i * N + n0 + (e & 63)];
+        for (int r = bl; r < jn * KC; r += by) wt[0][r * 64 + nl] = bank_row(0, r);
+    }
+    __syncthreads();
+    int since = 0;                               // terms added since the last normalization
+    int buf = 0;
+    for (int j0 = 0; j0 < t1; j0 += kMacJB, buf ^= 1) {
+        const int jn = t1 - j0 < kMacJB ? t1 - j0 : kMacJB;
+        const int j1 = j0 + kMacJB;
+        const int jn1 = j1 >= t1 ? 0 : (t1 - j1 < kMacJB ? t1 - j1 : kMacJB);
+        const int rows1 = jn1 * KC;
+        u64 bs[kSt];
+#pragma unroll
+        for (int s = 0; s < kSt; ++s) {
+            const int r = bl + s * by;
+            bs[s] = bank_row(j1 < t1 ? j1 : j0, r < rows1 ? r : 0);   // unconditional: no early wait
         }
-        __syncthreads();
         if (since + jn > 8) {                    // uniform: keep every column below 2^64
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
@@ -1072,24 +1115,41 @@ k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, 
             }
             since = 0;
         }
+        const u64 *w_l = wt[buf];
 #pragma unroll
         for (int jj = 0; jj < kMacJB; ++jj) {
             if (jj < jn) {
+                const u64 x0 = live ? xr[jj][0] : 0, x1 = live ? xr[jj][1] : 0;
+                const u32 xl[2] = {(u32)x0 & (u32)kM30, (u32)x1 & (u32)kM30};
+                const u32 xh[2] = {(u32)(x0 >> 30), (u32)(x1 >> 30)};
+                if (jj < jn1) {                  // uniform; rot_b of a spare thread is a valid row
+                    const u64 *src = rot_b + (long)(j1 + jj - 1) * 2 * kn;
+                    xr[jj][0] = __builtin_nontemporal_load(&src[0]);
+                    xr[jj][1] = __builtin_nontemporal_load(&src[kn]);
+                }
 #pragma unroll
                 for (int kk = 0; kk < KC; ++kk) {
-                    const u64 w = wt[(jj * KC + kk) * 64 + nl];
+                    const u64 w = w_l[(jj * KC + kk) * 64 + nl];
                     const u32 wl = (u32)w & (u32)kM30, wh = (u32)(w >> 30);
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
-                        c[kk][q][0] += (u64)xl[jj][q] * wl;
-                        c[kk][q][1] += (u64)xl[jj][q] * wh;
-                        c[kk][q][1] += (u64)xh[jj][q] * wl;
-                        c[kk][q][2] += (u64)xh[jj][q] * wh;
+                        c[kk][q][0] += (u64)xl[q] * wl;
+                        c[kk][q][1] += (u64)xl[q] * wh;
+                        c[kk][q][1] += (u64)xh[q] * wl;
+                        c[kk][q][2] += (u64)xh[q] * wh;
                     }
                 }
             }
         }
         since += jn;
+        u64 *w_n = wt[buf ^ 1];
+#pragma unroll
+        for (int s = 0; s < kSt; ++s) {
+            const int r = bl + s * by;
+            if (r < rows1) w_n[r * 64 + nl] = bs[s];
+        }
+        for (int r = bl + kSt * by; r < rows1; r += by) w_n[r * 64 + nl] = bank_row(j1, r);
+        __syncthreads();
     }
     if (live) {
 #pragma unroll
@@ -1447,10 +1507,11 @@ void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb
         return;
     }
     if (fp.n && part != 2) {
-        const dim3 grid((1u << logn) / 64, fp.n, ((B + by - 1) / by) * (t2 / kc)), blk(64, by);
-        switch (kc) {
+        const int kf = mac_chunk(t2, kn.mac_chunk_cap < 12 ? kn.mac_chunk_cap : 12);   // 16 would spill
+        const dim3 grid((1u << logn) / 64, fp.n, ((B + by - 1) / by) * (t2 / kf)), blk(64, by);
+        switch (kf) {
 #define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac_fp<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, fp, tab.pc); break;
-            CTL_MAC(16) CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
+            CTL_MAC(12) CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
             default: hipLaunchKernelGGL(k_mac_fp<1>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, fp, tab.pc); break;
 #undef CTL_MAC
         }
