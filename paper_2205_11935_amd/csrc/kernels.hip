@@ -45,14 +45,11 @@ __device__ __forceinline__ u64 shoup_lazy(u64 x, u64 w, u64 ws, u64 q, u64 qn) {
     return lo + ((u64)cross << 32);
 }
 
-// x - m if x >= m else x, for x, m < 2^63, via the sign of x - m (no VCC mask):
-// nm = 2^64 - m.
+// x - m if x >= m else x, for x, m < 2^63, from the sign of x - m (nm = 2^64 - m): one 64-bit
+// add, one compare of the high word and two selects.
 __device__ __forceinline__ u64 csub(u64 x, u64 nm) {
     const u64 d = x + nm;
-    const u32 mask = (u32)((int)(u32)(d >> 32) >> 31);      // all ones when x < m
-    const u32 lo = (mask & (u32)x) | (~mask & (u32)d);
-    const u32 hi = (mask & (u32)(x >> 32)) | (~mask & (u32)(d >> 32));
-    return ((u64)hi << 32) | lo;
+    return (int)(u32)(d >> 32) < 0 ? x : d;
 }
 
 __device__ __forceinline__ u64 red2(u64 x, u64 q) { return x >= q ? x - q : x; }
