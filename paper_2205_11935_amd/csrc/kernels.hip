@@ -523,6 +523,9 @@ k_ntt_inv(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
 // (g, j, t). The digits are stored non-temporally: the key product reads them after every
 // workgroup here has finished, so keeping them in L2 only displaces the coefficients this kernel
 // re-reads (the MAC's outputs are stored the same way for the same reason).
+// Targets with an FP64 prime hold the bit patterns of FP64 values congruent to the digit, of
+// magnitude below 2^45 (the forward transform's output as it stands, or the copied residue): the
+// key product, their only reader, multiplies them as they are.
 template <int LOGN>
 __global__ void __launch_bounds__(Geo<LOGN>::T)
 k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u64 *__restrict__ digits, int k,
@@ -546,8 +549,14 @@ k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u6
     u64 *dst = digits + ((long)gj * (k + 1) + t) * N;
     if (t == j) {
         const u64 *src = d + res_offset(dmap, gj) * N;
+        if (tab.pc[t].fp) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) dst[tid + T * e] = src[tid + T * e];
+            for (int e = 0; e < 16; ++e)
+                dst[tid + T * e] = (u64)__double_as_longlong(u64_to_fp(src[tid + T * e]));
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) dst[tid + T * e] = src[tid + T * e];
+        }
         return;
     }
     const int pt = t < k ? t : nq;
@@ -558,9 +567,13 @@ k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u6
     u64 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qj, qj_mod, p);
-    const bool fp = fwd_transform<LOGN>(v, lds, tid, tab, pt, p);
+    if (fwd_transform<LOGN>(v, lds, tid, tab, pt, p)) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) __builtin_nontemporal_store(fwd_result(lds, tid + T * e, fp, p), &dst[tid + T * e]);
+        for (int e = 0; e < 16; ++e) __builtin_nontemporal_store(lds[lds_idx(tid + T * e)], &dst[tid + T * e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) __builtin_nontemporal_store(fwd_result(lds, tid + T * e, false, p), &dst[tid + T * e]);
+    }
 }
 
 // Drop the last modulus of each group (ModDown when it is P, rescale when it is q_k):
@@ -693,7 +706,8 @@ __device__ __forceinline__ u64 limb_reduce4(const u64 (&c)[4], const PrimeConst 
 // Key inner product with the automorphism fused into the digit gather:
 //   out[b][r][0][t] = sum_j D[b][r][j][t][sigma_r] * key_r[j][0][t] (+ fold),  out[..][1][t]
 //   likewise with key_r[j][1][t]; t = 0..k (k = the special prime). D: digits + b db + r dr +
-//   (j (k+1) + t) N; out[b][r] at out + b ob + r 2 (k+1) N. For rows t < fold.rows, polynomial 0
+//   (j (k+1) + t) N, as k_modup stores them (FP64 bit patterns for FP64 primes);
+//   out[b][r] at out + b ob + r 2 (k+1) N. For rows t < fold.rows, polynomial 0
 //   also gets fold.mul[t] * fold.src[b sb + r sr + t N] gathered through sigma_r (the P sigma(c0)
 //   term of a baby step kept over Q*P, or the sigma(c0) of a giant step's extended operand).
 // One workgroup per (source tile of 256 coefficients, t, r); each thread loops over the batch so a
@@ -783,7 +797,7 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
                 double a0 = 0.0, a1 = 0.0;
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
-                    const double xd = u64_to_fp(x[j]);
+                    const double xd = __longlong_as_double((long long)x[j]);   // FP64 digit (ModUp)
                     a0 += fp_mul(xd, kb[j], p.qd, p.qinv);
                     a1 += fp_mul(xd, ka[j], p.qd, p.qinv);
                 }
