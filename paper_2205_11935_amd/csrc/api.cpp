@@ -1120,6 +1120,7 @@ int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
         p.qn = 0 - q;
         p.nq2 = 0 - 2 * q;
         p.r60 = q < (1ull << 60) ? (1ull << 60) % q : 1ull << 60;
+        p.r60s = q < (1ull << 60) ? h_shoup(p.r60, q) : 0;
         p.fp = fp ? 1 : 0;
         p.pad_ = 0;
         p.qd = (double)q;

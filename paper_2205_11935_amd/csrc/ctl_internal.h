@@ -31,6 +31,7 @@ struct PrimeConst {
     u64 qn;        // 2^64 - q
     u64 nq2;       // 2^64 - 2q
     u64 r60;       // 2^60 mod q for q below 2^60 (2^60 otherwise)
+    u64 r60s;      // Shoup companion of r60 (q below 2^60)
     // FP64 arithmetic for primes below 2^41 (exact: see the kernels): fp != 0 selects it, and the
     // Shoup-companion twiddle tables of such a prime hold the twiddles as doubles instead.
     int fp;

@@ -678,28 +678,27 @@ __device__ __forceinline__ void limb_normalize(u64 (&c)[3], const PrimeConst &p)
     else c[2] = reduce_any(c[2], p);
 }
 
+// L + h 2^60 mod q for L < 2^60, any h < 2^64 and q < 2^60: h 2^60 is congruent to h (2^60 mod q),
+// a Shoup product in [0, 2q); the sum is below 4q when q >= 2^59 (two conditional subtracts) and
+// below 2^62 otherwise (one general reduction).
+__device__ __forceinline__ u64 limb_fold60(u64 l, u64 h, const PrimeConst &p) {
+    const u64 s = l + shoup_lazy(h, p.r60, p.r60s, p.q, p.qn);
+    return (p.q >> 59) ? red4(s, p.q, p.q2) : reduce_any(s, p);
+}
+// c0 + c1 2^30 + c2 2^60 = L + c2 2^60 with L < 2^60 once normalized.
 __device__ __forceinline__ u64 limb_reduce(u64 (&c)[3], const PrimeConst &p) {
     limb_normalize(c, p);
-    Acc a;                                   // (c1 2^30 + c0) + c2 2^60 as a 128-bit value
-    const u64 lo = c[0] | (c[1] << 30), add = c[2] << 60;
-    a.lo = lo + add;
-    a.hi = (c[2] >> 4) + (a.lo < add ? 1ull : 0ull);
-    return acc_reduce(a, p);
+    return limb_fold60(c[0] | (c[1] << 30), c[2], p);
 }
 
-// c[0] + (c[1] + c[2]) 2^30 + c[3] 2^60 mod q for column sums below 2^64 each.
+// (c0 + (c1 + c2) 2^30 + c3 2^60) mod q for q below 2^60, each column below 2^64 - 2^61: the
+// weight-2^30 columns are carried so that the value is L + h 2^60 with L < 2^60 and
+// h < c3 + 2^35.
 __device__ __forceinline__ u64 limb_reduce4(const u64 (&c)[4], const PrimeConst &p) {
-    Acc a;
-    a.lo = c[0];
-    a.hi = 0;
-    const u64 t1 = c[1] << 30, t2 = c[2] << 30, t3 = c[3] << 60;
-    a.lo += t1;
-    a.hi += (c[1] >> 34) + (a.lo < t1 ? 1ull : 0ull);
-    a.lo += t2;
-    a.hi += (c[2] >> 34) + (a.lo < t2 ? 1ull : 0ull);
-    a.lo += t3;
-    a.hi += (c[3] >> 4) + (a.lo < t3 ? 1ull : 0ull);
-    return acc_reduce(a, p);
+    const u64 u = (c[0] >> 30) + (c[1] & kM30) + (c[2] & kM30);     // below 2^35
+    const u64 l = (c[0] & kM30) | ((u & kM30) << 30);
+    const u64 h = c[3] + (c[1] >> 30) + (c[2] >> 30) + (u >> 30);
+    return limb_fold60(l, h, p);
 }
 
 // ---------------------------------------------------------------- elementwise kernels
