@@ -164,6 +164,12 @@ int ctl_profile_families(void);
 const char *ctl_profile_family_name(int family);
 int ctl_profile_read(ctl_ctx *ctx, int family, int *launches_out, double *total_ms_out,
                      double *work_out, double *fp_work_out);
+/* Algorithmic HBM bytes of the launches of family `family` recorded since profiling was enabled,
+ * for the families that model them (k_keyip: digit words once per ciphertext when the rotations
+ * are hoisted, else once per rotation, each key set's key words once, output words, fold words;
+ * the MAC families: ciphertext and rotated-ciphertext words once, plaintext-bank words once,
+ * output words); 0 for the others. No synchronization. */
+int ctl_profile_read_bytes(ctl_ctx *ctx, int family, double *bytes_out);
 
 /* ------------------------------------------------------------------ keys (client side) */
 typedef struct ctl_sk ctl_sk;

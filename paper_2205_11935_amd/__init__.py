@@ -118,6 +118,7 @@ _SIGS = {
     "ctl_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
+    "ctl_profile_read_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "ctl_keygen": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, i32p, ctypes.c_int, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_void_p)]),
@@ -402,6 +403,15 @@ class Context:
             _check(lib().ctl_profile_read(self.handle, f, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(wk),
                                           ctypes.byref(fw)))
             out[lib().ctl_profile_family_name(f).decode()] = (n.value, ms.value, wk.value, fw.value)
+        return out
+
+    def profile_bytes(self):
+        """{kernel family: algorithmic HBM bytes of its recorded launches} (0 where not modelled)."""
+        out = {}
+        for f in range(lib().ctl_profile_families()):
+            b = ctypes.c_double()
+            _check(lib().ctl_profile_read_bytes(self.handle, f, ctypes.byref(b)))
+            out[lib().ctl_profile_family_name(f).decode()] = b.value
         return out
 
     # ------------------------------------------------------------ parity hook

@@ -73,6 +73,7 @@ struct ctl_ctx {
     std::vector<int> prof_fam;            // family of each recorded pair
     std::vector<double> prof_work;        // algorithmic work of each recorded launch
     std::vector<double> prof_fp;          // the part of it on FP64 primes
+    std::vector<double> prof_bytes;       // algorithmic HBM bytes of each recorded launch (0: not modelled)
     size_t prof_used = 0;
 };
 
@@ -157,7 +158,7 @@ hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 // Brackets one launch with events when the context's instrumentation is on.
 class Prof {
   public:
-    Prof(ctl_ctx *c, Family f, hipStream_t st, double work, double fp_share = 0.0)
+    Prof(ctl_ctx *c, Family f, hipStream_t st, double work, double fp_share = 0.0, double bytes = 0.0)
         : c_(c), st_(st), idx_(SIZE_MAX) {
         if (!c->prof_on) return;
         if (c->prof_used * 2 + 2 > c->prof_ev.size()) {
@@ -169,11 +170,13 @@ class Prof {
             c->prof_fam.push_back(0);
             c->prof_work.push_back(0.0);
             c->prof_fp.push_back(0.0);
+            c->prof_bytes.push_back(0.0);
         }
         idx_ = c->prof_used++;
         c->prof_fam[idx_] = f;
         c->prof_work[idx_] = work;
         c->prof_fp[idx_] = work * fp_share;
+        c->prof_bytes[idx_] = bytes;
         (void)hipEventRecord(c->prof_ev[2 * idx_], st_);
     }
     ~Prof() {
@@ -185,6 +188,7 @@ class Prof {
     size_t idx_;
 };
 #define CTL_PROF(fam, work, share) Prof prof_##__LINE__(c, fam, st, (double)(work), (share))
+#define CTL_PROFB(fam, work, share, bytes) Prof prof_##__LINE__(c, fam, st, (double)(work), (share), (double)(bytes))
 
 // Share of the residues of a list of prime indices that run on the FP64 path.
 double fp_share(const ctl_ctx *c, const int *primes, int n) {
@@ -220,20 +224,22 @@ void run_mac(ctl_ctx *c, hipStream_t st, const u64 *ct, long ct_sb, const u64 *r
              u64 *inner, int B, int rows, bool ext, int t1, int t2) {
     const int logn = c->hp.logn, nq = c->hp.nq;
     const double per_row = 2.0 * B * t1 * t2 * c->hp.n;
+    // per residue row: the ciphertext and its rotations read once, the bank once, the sums written
+    const double row_bytes = 8.0 * c->hp.n * (2.0 * B * t1 + (double)t1 * t2 + 2.0 * B * t2);
     int fp_rows = 0;
     for (int r = 0; r < rows; ++r) fp_rows += c->tab.host_fp[(ext && r == rows - 1) ? nq : r] ? 1 : 0;
     const int ext_nq = ext ? nq : -1;
     if (B <= c->knobs.mac_direct_max) {
-        CTL_PROF(F_MAC_DIRECT, per_row * rows, (double)fp_rows / rows);
+        CTL_PROFB(F_MAC_DIRECT, per_row * rows, (double)fp_rows / rows, row_bytes * rows);
         launch_mac(logn, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, ext_nq, t1, t2, c->tab, c->knobs, st, 0);
         return;
     }
     if (fp_rows) {
-        CTL_PROF(F_MAC_FP, per_row * fp_rows, 1.0);
+        CTL_PROFB(F_MAC_FP, per_row * fp_rows, 1.0, row_bytes * fp_rows);
         launch_mac(logn, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, ext_nq, t1, t2, c->tab, c->knobs, st, 1);
     }
     if (fp_rows < rows) {
-        CTL_PROF(F_MAC, per_row * (rows - fp_rows), 0.0);
+        CTL_PROFB(F_MAC, per_row * (rows - fp_rows), 0.0, row_bytes * (rows - fp_rows));
         launch_mac(logn, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, ext_nq, t1, t2, c->tab, c->knobs, st, 2);
     }
 }
@@ -328,7 +334,12 @@ int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
     { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
     { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st); }
     const long dsz = (long)k * (k + 1) * N, db = hoisted ? dsz : (long)R * dsz;
-    CTL_PROF(F_KEYIP, 2.0 * B * R * (k + 1) * k * N, fp_share_range(c, k, true));
+    // algorithmic bytes: digits (once per ciphertext when hoisted), each key set's keys, the
+    // outputs, and the fold term's words
+    const double kip_bytes = 8.0 * N * ((double)B * (hoisted ? 1 : R) * k * (k + 1) +
+                                        (double)ks.runs.size() * R * 2 * k * (k + 1) + (double)B * R * 2 * (k + 1) +
+                                        (fold && fold->src ? (double)B * (fold->sr ? R : 1) * fold->rows : 0.0));
+    CTL_PROFB(F_KEYIP, 2.0 * B * R * (k + 1) * k * N, fp_share_range(c, k, true), kip_bytes);
     for (const KeySet::Run &run : ks.runs) {       // one launch per key set
         KeyList kl{};
         for (int r = 0; r < R; ++r) {
@@ -1281,6 +1292,16 @@ int ctl_profile_read(ctl_ctx *ctx, int family, int *launches_out, double *total_
     *total_ms_out = tot;
     *work_out = work;
     *fp_work_out = fpw;
+    return CTL_OK;
+}
+
+int ctl_profile_read_bytes(ctl_ctx *ctx, int family, double *bytes_out) {
+    if (!ctx || !bytes_out) return fail(CTL_EINVAL, "null argument");
+    if (family < 0 || family >= F_COUNT) return fail(CTL_EINVAL, "unknown kernel family");
+    double b = 0.0;
+    for (size_t i = 0; i < ctx->prof_used; ++i)
+        if (ctx->prof_fam[i] == family) b += ctx->prof_bytes[i];
+    *bytes_out = b;
     return CTL_OK;
 }
 
