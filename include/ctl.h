@@ -115,7 +115,11 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
  *   CTL_KNOB_MAC_LIMB    1 (default): the plaintext MAC and the key product over primes of 41..60
  *                        bits multiply 30-bit limbs into carry-free column sums (the MAC then
  *                        keeps at most 8 giant-step accumulators per thread); 0: 128-bit
- *                        accumulation. Primes of 61 bits always take the latter.
+ *                        accumulation. Primes of 61 bits always take the latter;
+ *   CTL_KNOB_KEYIP_RR    hoisted rotations per key-product workgroup, which read each digit word
+ *                        once for all of them (1..4, default 4; at most 3 with 7 or more primes,
+ *                        for the register budget; launches whose rotations have their own digits
+ *                        use 1).
  * Out-of-range values give CTL_EINVAL and leave the knob unchanged. */
 #define CTL_KNOB_MAC_CHUNK 0
 #define CTL_KNOB_MAC_CTS 1
@@ -123,6 +127,7 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
 #define CTL_KNOB_MAC_DIRECT 3
 #define CTL_KNOB_NTT_XCD 4
 #define CTL_KNOB_MAC_LIMB 5
+#define CTL_KNOB_KEYIP_RR 6
 int ctl_knob_set(ctl_ctx *ctx, int knob, int value);
 int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value);
 

@@ -28,8 +28,10 @@ CTL_KNOB_KEYIP_XCD = 2
 CTL_KNOB_MAC_DIRECT = 3
 CTL_KNOB_NTT_XCD = 4
 CTL_KNOB_MAC_LIMB = 5
+CTL_KNOB_KEYIP_RR = 6
 KNOBS = {"mac_chunk": CTL_KNOB_MAC_CHUNK, "mac_cts": CTL_KNOB_MAC_CTS, "keyip_xcd": CTL_KNOB_KEYIP_XCD,
-         "mac_direct": CTL_KNOB_MAC_DIRECT, "ntt_xcd": CTL_KNOB_NTT_XCD, "mac_limb": CTL_KNOB_MAC_LIMB}
+         "mac_direct": CTL_KNOB_MAC_DIRECT, "ntt_xcd": CTL_KNOB_NTT_XCD, "mac_limb": CTL_KNOB_MAC_LIMB,
+         "keyip_rr": CTL_KNOB_KEYIP_RR}
 CTL_LAYER_DENSE = 0
 CTL_LAYER_CONV1D = 1
 CTL_LAYER_AVGPOOL = 2
@@ -554,7 +556,7 @@ class Context:
 
     def knob(self, name: str, value: Optional[int] = None) -> int:
         """Read (value None) or set a launch knob ("mac_chunk", "mac_cts", "keyip_xcd", "mac_direct", "ntt_xcd",
-        "mac_limb")."""
+        "mac_limb", "keyip_rr")."""
         if value is not None:
             _check(lib().ctl_knob_set(self.handle, KNOBS[name], int(value)))
         v = ctypes.c_int()

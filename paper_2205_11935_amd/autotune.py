@@ -23,6 +23,7 @@ CANDIDATES: Dict[str, List[int]] = {
     "keyip_xcd": [1, 0],
     "ntt_xcd": [1, 0],
     "mac_limb": [1, 0],
+    "keyip_rr": [4, 3, 2, 1],
 }
 
 

@@ -1233,6 +1233,10 @@ int ctl_knob_set(ctl_ctx *ctx, int knob, int value) {
             if (value != 0 && value != 1) return fail(CTL_EINVAL, "the limb MAC switch is 0 or 1");
             ctx->knobs.mac_limb = value;
             return CTL_OK;
+        case CTL_KNOB_KEYIP_RR:
+            if (value < 1 || value > 4) return fail(CTL_EINVAL, "rotations per key-product workgroup must lie in 1..4");
+            ctx->knobs.keyip_rr = value;
+            return CTL_OK;
         default:
             return fail(CTL_EINVAL, "unknown knob");
     }
@@ -1247,6 +1251,7 @@ int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value) {
         case CTL_KNOB_MAC_DIRECT: *value = ctx->knobs.mac_direct_max; return CTL_OK;
         case CTL_KNOB_NTT_XCD: *value = ctx->knobs.ntt_xcd; return CTL_OK;
         case CTL_KNOB_MAC_LIMB: *value = ctx->knobs.mac_limb; return CTL_OK;
+        case CTL_KNOB_KEYIP_RR: *value = ctx->knobs.keyip_rr; return CTL_OK;
         default: return fail(CTL_EINVAL, "unknown knob");
     }
 }

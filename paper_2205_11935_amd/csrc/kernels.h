@@ -74,7 +74,7 @@ void launch_sum_gather(int logn, u64 *out, long o_sb, const u64 *base, long ba_s
 // Launch choices an autotuner may set (defaults in brackets): the largest giant-step chunk of the
 // MAC [16], ciphertexts per MAC workgroup [8], XCD-grouped key-product numbering [1], largest
 // batch that uses the unstaged MAC [3], XCD-grouped ModUp / ModDown numbering [0], 30-bit limb
-// products in the integer-prime MAC [1].
+// products in the integer-prime MAC [1], hoisted rotations per key-product workgroup [4].
 struct Knobs {
     int mac_chunk_cap = 16;
     int mac_cts = 8;
@@ -82,6 +82,7 @@ struct Knobs {
     int mac_direct_max = 3;      // batches up to this size use the unstaged MAC
     int ntt_xcd = 0;             // XCD-grouped numbering of ModUp and ModDown workgroups
     int mac_limb = 1;            // integer-prime MAC by 30-bit limbs where every prime is below 2^60
+    int keyip_rr = 4;            // key product: hoisted rotations per workgroup sharing digit words (1..4)
 };
 
 void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,

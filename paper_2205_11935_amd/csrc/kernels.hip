@@ -709,62 +709,77 @@ __device__ __forceinline__ u64 limb_reduce4(const u64 (&c)[4], const PrimeConst 
 //   out[b][r] at out + b ob + r 2 (k+1) N. For rows t < fold.rows, polynomial 0
 //   also gets fold.mul[t] * fold.src[b sb + r sr + t N] gathered through sigma_r (the P sigma(c0)
 //   term of a baby step kept over Q*P, or the sigma(c0) of a giant step's extended operand).
-// One workgroup per (source tile of 256 coefficients, t, r); each thread loops over the batch so a
-// key word is read from HBM once per launch. A thread reads the digits (and the fold term) at its
-// source coefficient m and writes output coefficient n = sigma_r^{-1}(m), so that the digit loads
-// are contiguous; in bit-reversed evaluation order the automorphism permutes aligned blocks of
-// 2^j coefficients among themselves, so n stays inside one aligned 256-block and the key loads and
-// output stores of a wave stay within 512 bytes. Workgroups are dealt to the 8 XCDs in turn (id
-// mod 8); with xcd set the 1D grid is numbered such that all R rotations of one (source tile, t)
-// run back to back on the same XCD (with hoisted digits, dr = 0, they read the same digit words,
-// which its L2 serves); otherwise tiles vary fastest, then t, then r.
-template <int K>
-__global__ void __launch_bounds__(256)
+// One workgroup per (source tile of 256 coefficients, t, group of RR rotations); each thread
+// loops over the batch so a key word is read from HBM once per launch. A thread reads the digits
+// (and the fold term) at its source coefficient m once and, for each rotation r of its group,
+// writes output coefficient n = sigma_r^{-1}(m), so that the digit loads are contiguous; in
+// bit-reversed evaluation order the automorphism permutes aligned blocks of 2^j coefficients
+// among themselves, so n stays inside one aligned 256-block and the key loads and output stores
+// of a wave stay within 512 bytes. Hoisted rotations all read the same digit words: RR of them per
+// workgroup divide the digit reads (served by L2, and the key product's limit at RR = 1) by RR.
+// Workgroups are dealt to the 8 XCDs in turn (id mod 8); with xcd set the 1D grid is numbered
+// such that all rotation groups of one (source tile, t) run back to back on the same XCD (with
+// hoisted digits, dr = 0, they read the same digit words, which its L2 serves); otherwise tiles
+// vary fastest, then t, then the rotation group.
+template <int K, int RR>
+__global__ void __launch_bounds__(256, RR == 2 ? 3 : RR > 2 ? 2 : 1)
 k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__restrict__ out, long ob,
         KeyFold fold, int B, int R, int nq, int logn, int xcd_order, unsigned lt60, const PrimeConst *__restrict__ pcs) {
     const int pairs = (K + 1) << (logn - 8);
-    int r, pair;
+    const int RG = (R + RR - 1) / RR;                       // groups of RR rotations
+    int rg, pair;
     if (xcd_order) {
         const int id = blockIdx.x, xcd = id & 7, j = id >> 3;
-        r = j % R;
-        pair = (j / R) * 8 + xcd;                            // pair = tile * (K + 1) + t
+        rg = j % RG;
+        pair = (j / RG) * 8 + xcd;                           // pair = tile * (K + 1) + t
     } else {
         const int tiles = 1 << (logn - 8), id = blockIdx.x;
-        r = id / pairs;
+        rg = id / pairs;
         pair = (id % tiles) * (K + 1) + (id / tiles) % (K + 1);
     }
-    if (pair >= pairs || r >= R) return;
+    if (pair >= pairs || rg >= RG) return;
     const int m = (pair / (K + 1)) * 256 + threadIdx.x;     // source coefficient
     const int t = pair % (K + 1);
     const int N = 1 << logn, np = nq + 1;
     const int pt = t < K ? t : nq;
     const PrimeConst p = pcs[pt];
-    const u64 g = keys.gal[r];
-    const u64 *key = keys.key[r];
+    const int r0 = rg * RR, nr = R - r0 < RR ? R - r0 : RR;  // rotations r0 .. r0 + nr - 1
     const int src = m;
-    const int n = g == 1 ? m : galois_src(m, keys.ginv[r], logn);   // the output that gathers from m
     const bool fd = fold.src != nullptr && t < fold.rows;            // uniform per workgroup
     const u64 fm = fd ? fold.mul[t] : 0;
+    // Rotation rr of the group: its key, the output that gathers from m, its output offset. A
+    // group short of RR rotations repeats its last one and drops that one's stores.
+    const u64 *key[RR];
+    int voff_o[RR];
+    bool live[RR];
+#pragma unroll
+    for (int rr = 0; rr < RR; ++rr) {
+        const int r = r0 + (rr < nr ? rr : nr - 1);
+        live[rr] = rr < nr;
+        key[rr] = keys.key[r];
+        const int n = keys.gal[r] == 1 ? m : galois_src(m, keys.ginv[r], logn);
+        voff_o[rr] = (int)(((long)r * 2 * (K + 1) * N + (long)t * N + n) * 8);
+    }
     // Batch loop. Ciphertext b's K digit words (and its fold word) come from buffer loads whose
     // address is a per-lane offset plus scalar parts (no per-load address arithmetic on the
     // VALU), one ciphertext ahead of the products; ciphertexts go in pairs so that the prefetched
-    // words need no copies.
+    // words need no copies. With RR > 1 the rotations of the group share the digit words (the
+    // launcher uses it only for hoisted digits, dr = 0, and a fold shared by the rotations).
     const int voff_d = (int)(((long)t * N + src) * 8);
-    const int voff_o = (int)(((long)r * 2 * (K + 1) * N + (long)t * N + n) * 8);
-    const int voff_f = fd ? (int)(((long)r * fold.sr + (long)t * N + src) * 8) : 0;
+    const int voff_f = fd ? (int)(((long)r0 * fold.sr + (long)t * N + src) * 8) : 0;
     const int rec_d = K * (K + 1) * N * 8, rec_o = (int)(ob * 8), rec_f = fd ? (int)(fold.sb * 8) : 0;
     const int sd = (K + 1) * N * 8;                                    // digit j at + j sd bytes
-    const u64 *dbase = digits + r * dr;
+    const u64 *dbase = digits + r0 * dr;
     auto load = [&](int b, u64 (&x)[K], u64 &f, bool fold_on) {
         const BufRsrc rd = buf_rsrc(dbase + b * db, rec_d);
 #pragma unroll
         for (int j = 0; j < K; ++j) x[j] = buf_load(rd, voff_d, j * sd);
         if (fold_on) f = buf_load(buf_rsrc(fold.src + b * fold.sb, rec_f), voff_f, 0);
     };
-    auto store = [&](int b, u64 v0, u64 v1) {
-        const BufRsrc ro = buf_rsrc(out + b * ob, rec_o);
-        buf_store(v0, ro, voff_o, 0);
-        buf_store(v1, ro, voff_o, sd);
+    auto store = [&](int b, int rr, u64 v0, u64 v1) {
+        const BufRsrc ro = buf_rsrc(out + b * ob, live[rr] ? rec_o : 0);   // 0 bytes: stores dropped
+        buf_store(v0, ro, voff_o[rr], 0);
+        buf_store(v1, ro, voff_o[rr], sd);
     };
     // pairs (b, b + 1): xa holds b, xb is filled with b + 1 while b is multiplied, then xa with b + 2
     auto batch = [&](auto fold_tag, auto &&product) {
@@ -783,25 +798,33 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
     };
     if (p.fp) {
         // FP64 products (prime < 2^41): each term |.| <= 0.52 q, sums stay far below 2^53
-        double kb[K], ka[K];
+        double kb[RR][K], ka[RR][K];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            kb[j] = u64_to_fp(key[((long)(j * 2 + 0) * np + pt) * N + n]);
-            ka[j] = u64_to_fp(key[((long)(j * 2 + 1) * np + pt) * N + n]);
-        }
+        for (int rr = 0; rr < RR; ++rr)
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int n = (voff_o[rr] >> 3) % N;
+                kb[rr][j] = u64_to_fp(key[rr][((long)(j * 2 + 0) * np + pt) * N + n]);
+                ka[rr][j] = u64_to_fp(key[rr][((long)(j * 2 + 1) * np + pt) * N + n]);
+            }
         const double fmd = u64_to_fp(fm);
         auto run = [&](auto fold_tag) {
             constexpr bool FOLD = decltype(fold_tag)::value;
             batch(fold_tag, [&](int b, const u64 (&x)[K], u64 fx) {
-                double a0 = 0.0, a1 = 0.0;
+                double xd[K];
 #pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const double xd = __longlong_as_double((long long)x[j]);   // FP64 digit (ModUp)
-                    a0 += fp_mul(xd, kb[j], p.qd, p.qinv);
-                    a1 += fp_mul(xd, ka[j], p.qd, p.qinv);
+                for (int j = 0; j < K; ++j) xd[j] = __longlong_as_double((long long)x[j]);   // FP64 digit (ModUp)
+                const double f = FOLD ? fp_mul(u64_to_fp(fx), fmd, p.qd, p.qinv) : 0.0;
+#pragma unroll
+                for (int rr = 0; rr < RR; ++rr) {
+                    double a0 = f, a1 = 0.0;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        a0 += fp_mul(xd[j], kb[rr][j], p.qd, p.qinv);
+                        a1 += fp_mul(xd[j], ka[rr][j], p.qd, p.qinv);
+                    }
+                    store(b, rr, fp_to_u64(a0, p.qd, p.qinv), fp_to_u64(a1, p.qd, p.qinv));
                 }
-                if constexpr (FOLD) a0 += fp_mul(u64_to_fp(fx), fmd, p.qd, p.qinv);
-                store(b, fp_to_u64(a0, p.qd, p.qinv), fp_to_u64(a1, p.qd, p.qinv));
             });
         };
         if (fd) run(std::true_type{});
@@ -812,66 +835,83 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
         // prime below 2^60: 30-bit limb products into carry-free column sums (see k_mac_limb);
         // with the two cross products in separate columns every column takes 16 terms, and a
         // sum has at most K + 1 <= 9
-        u32 bl[K], bh[K], al[K], ah[K];
+        u32 bl[RR][K], bh[RR][K], al[RR][K], ah[RR][K];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const u64 b0 = key[((long)(j * 2 + 0) * np + pt) * N + n];
-            const u64 a0 = key[((long)(j * 2 + 1) * np + pt) * N + n];
-            bl[j] = (u32)b0 & (u32)kM30;
-            bh[j] = (u32)(b0 >> 30);
-            al[j] = (u32)a0 & (u32)kM30;
-            ah[j] = (u32)(a0 >> 30);
-        }
+        for (int rr = 0; rr < RR; ++rr)
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int n = (voff_o[rr] >> 3) % N;
+                const u64 b0 = key[rr][((long)(j * 2 + 0) * np + pt) * N + n];
+                const u64 a0 = key[rr][((long)(j * 2 + 1) * np + pt) * N + n];
+                bl[rr][j] = (u32)b0 & (u32)kM30;
+                bh[rr][j] = (u32)(b0 >> 30);
+                al[rr][j] = (u32)a0 & (u32)kM30;
+                ah[rr][j] = (u32)(a0 >> 30);
+            }
         const u32 fml = (u32)fm & (u32)kM30, fmh = (u32)(fm >> 30);
         auto run = [&](auto fold_tag) {
             constexpr bool FOLD = decltype(fold_tag)::value;
             batch(fold_tag, [&](int b, const u64 (&x)[K], u64 fx) {
-                u64 c0[4] = {0, 0, 0, 0}, c1[4] = {0, 0, 0, 0};
+                u32 xl[K], xh[K];
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
-                    const u32 xl = (u32)x[j] & (u32)kM30, xh = (u32)(x[j] >> 30);
-                    c0[0] += (u64)xl * bl[j];
-                    c0[1] += (u64)xl * bh[j];
-                    c0[2] += (u64)xh * bl[j];
-                    c0[3] += (u64)xh * bh[j];
-                    c1[0] += (u64)xl * al[j];
-                    c1[1] += (u64)xl * ah[j];
-                    c1[2] += (u64)xh * al[j];
-                    c1[3] += (u64)xh * ah[j];
+                    xl[j] = (u32)x[j] & (u32)kM30;
+                    xh[j] = (u32)(x[j] >> 30);
                 }
-                if constexpr (FOLD) {
-                    const u32 xl = (u32)fx & (u32)kM30, xh = (u32)(fx >> 30);
-                    c0[0] += (u64)xl * fml;
-                    c0[1] += (u64)xl * fmh;
-                    c0[2] += (u64)xh * fml;
-                    c0[3] += (u64)xh * fmh;
+#pragma unroll
+                for (int rr = 0; rr < RR; ++rr) {
+                    u64 c0[4] = {0, 0, 0, 0}, c1[4] = {0, 0, 0, 0};
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        c0[0] += (u64)xl[j] * bl[rr][j];
+                        c0[1] += (u64)xl[j] * bh[rr][j];
+                        c0[2] += (u64)xh[j] * bl[rr][j];
+                        c0[3] += (u64)xh[j] * bh[rr][j];
+                        c1[0] += (u64)xl[j] * al[rr][j];
+                        c1[1] += (u64)xl[j] * ah[rr][j];
+                        c1[2] += (u64)xh[j] * al[rr][j];
+                        c1[3] += (u64)xh[j] * ah[rr][j];
+                    }
+                    if constexpr (FOLD) {
+                        const u32 fl = (u32)fx & (u32)kM30, fh = (u32)(fx >> 30);
+                        c0[0] += (u64)fl * fml;
+                        c0[1] += (u64)fl * fmh;
+                        c0[2] += (u64)fh * fml;
+                        c0[3] += (u64)fh * fmh;
+                    }
+                    store(b, rr, limb_reduce4(c0, p), limb_reduce4(c1, p));
                 }
-                store(b, limb_reduce4(c0, p), limb_reduce4(c1, p));
             });
         };
         if (fd) run(std::true_type{});
         else run(std::false_type{});
         return;
     }
-    u64 kb[K], ka[K];
+    u64 kb[RR][K], ka[RR][K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        kb[j] = key[((long)(j * 2 + 0) * np + pt) * N + n];
-        ka[j] = key[((long)(j * 2 + 1) * np + pt) * N + n];
-    }
+    for (int rr = 0; rr < RR; ++rr)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int n = (voff_o[rr] >> 3) % N;
+            kb[rr][j] = key[rr][((long)(j * 2 + 0) * np + pt) * N + n];
+            ka[rr][j] = key[rr][((long)(j * 2 + 1) * np + pt) * N + n];
+        }
     auto run = [&](auto fold_tag) {
         constexpr bool FOLD = decltype(fold_tag)::value;
         batch(fold_tag, [&](int b, const u64 (&x)[K], u64 fx) {
-            Acc a0, a1;
-            acc_zero(a0);
-            acc_zero(a1);
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                acc_mac(a0, x[j], kb[j]);
-                acc_mac(a1, x[j], ka[j]);
+            for (int rr = 0; rr < RR; ++rr) {
+                Acc a0, a1;
+                acc_zero(a0);
+                acc_zero(a1);
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    acc_mac(a0, x[j], kb[rr][j]);
+                    acc_mac(a1, x[j], ka[rr][j]);
+                }
+                if constexpr (FOLD) acc_mac(a0, fx, fm);
+                store(b, rr, acc_reduce(a0, p), acc_reduce(a1, p));
             }
-            if constexpr (FOLD) acc_mac(a0, fx, fm);
-            store(b, acc_reduce(a0, p), acc_reduce(a1, p));
         });
     };
     if (fd) run(std::true_type{});
@@ -1474,9 +1514,19 @@ void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const Ke
     const int xo = kn.keyip_xcd ? 1 : 0;
     unsigned lt60 = 0;
     for (int i = 0; i <= nq && kn.mac_limb; ++i) lt60 |= (tab.host_lt60[i] ? 1u : 0u) << i;
-    const dim3 grid((unsigned)(xo ? ((pairs + 7) / 8) * 8 * R : pairs * R)), blk(256);
-    switch (k) {
-#define CTL_KIP(K) case K: hipLaunchKernelGGL(k_keyip<K>, grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, lt60, tab.pc); break;
+    // kn.keyip_rr rotations per workgroup share each digit word when the digits are hoisted
+    // (dr = 0) and the fold term, if any, is the same for every rotation (sr = 0)
+    int rr = kn.keyip_rr < 1 ? 1 : kn.keyip_rr > 4 ? 4 : kn.keyip_rr;
+    if (k >= 7 && rr > 3) rr = 3;                 // register budget: 4 would spill heavily
+    if (dr != 0 || (fold.src && fold.sr != 0)) rr = 1;
+    if (rr > R) rr = R;
+    const int RG = (R + rr - 1) / rr;
+    const dim3 grid((unsigned)(xo ? ((pairs + 7) / 8) * 8 * RG : pairs * RG)), blk(256);
+    switch (k * 4 + rr - 1) {
+#define CTL_KIP(K) case 4 * K: hipLaunchKernelGGL((k_keyip<K, 1>), grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, lt60, tab.pc); break; \
+                   case 4 * K + 1: hipLaunchKernelGGL((k_keyip<K, 2>), grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, lt60, tab.pc); break; \
+                   case 4 * K + 2: hipLaunchKernelGGL((k_keyip<K, 3>), grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, lt60, tab.pc); break; \
+                   case 4 * K + 3: hipLaunchKernelGGL((k_keyip<K, 4>), grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, lt60, tab.pc); break;
         CTL_KIP(1) CTL_KIP(2) CTL_KIP(3) CTL_KIP(4) CTL_KIP(5) CTL_KIP(6) CTL_KIP(7) CTL_KIP(8)
 #undef CTL_KIP
         default: break;
