@@ -264,6 +264,31 @@ def test_forward_ragged_batch(lazy):
         assert np.array_equal(_u64(c.forward(model, lk, dev[b:b + 1].contiguous()))[0], got[b]), b
 
 
+def test_forward_key_product_rotation_groups():
+    """Hoisted rotations per key-product workgroup (the keyip_rr knob, 1..4): every setting gives
+    the same residues, the oracle's, on the large workload with a batch of 5 (odd for the key
+    product's ciphertext pairs); 63 and 31 baby rotations leave a short last group for 2, 3 and 4
+    (groups of 2 and 4 at layer 1, of 2, 3 and 4 at layer 2)."""
+    name, lazy = "large", "qp"
+    o, c = _orc(name), _ctx(name)
+    lk, _, _, okeys, rlk = _keys(name)
+    plan = _plan(name, lazy)
+    model, banks_ntt = _raw_model(name, seed=61, lazy=lazy)
+    dev, ref = _fresh_ct(name, 20, count=5)
+    before = c.knob("keyip_rr")
+    try:
+        outs = {}
+        for rr in (1, 2, 3, 4):
+            c.knob("keyip_rr", rr)
+            outs[rr] = _u64(c.forward(model, lk, dev))
+    finally:
+        c.knob("keyip_rr", before)
+    for rr in (1, 2, 3):
+        assert np.array_equal(outs[rr], outs[4]), rr
+    for b in (0, 4):
+        assert np.array_equal(outs[4][b], o.forward(plan, ref[b], banks_ntt, okeys, rlk)), b
+
+
 # ------------------------------------------------------------------ encoding and end-to-end tolerance
 @pytest.mark.parametrize("name", ["small", "mid", "large"])
 def test_encode_matches_oracle(name):
