@@ -297,6 +297,33 @@ def main():
         plain_ms = [pev[s].elapsed_time(pev[s + 1]) for s in range(args.plain_steps)]
         plain = {"value": round(args.plain_steps / plain_elapsed, 3), "unit": "encrypted forward passes/s",
                  "p50_ms": _percentile(plain_ms, 50), "p99_ms": _percentile(plain_ms, 99)}
+        # the same single-ciphertext pass replayed from a captured graph (the library's launch
+        # sequence with the host's per-launch work removed); the workspace is frozen meanwhile so
+        # that nothing is allocated under capture, and every replay must equal the eager result
+        want = one_out.clone()
+        c.workspace_freeze(True)
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                c.forward(model, keys, one, out=one_out)
+            gev = [torch.cuda.Event(enable_timing=True) for _ in range(args.plain_steps + 1)]
+            same = True
+            for s in range(args.plain_steps):
+                one_out.zero_()
+                gev[s].record(stream)
+                g.replay()
+                gev[s + 1].record(stream)
+                torch.cuda.synchronize()
+                same = same and bool(torch.equal(one_out, want))
+            gms = [gev[s].elapsed_time(gev[s + 1]) for s in range(args.plain_steps)]
+            plain["graph"] = {"p50_ms": _percentile(gms, 50), "p99_ms": _percentile(gms, 99),
+                              "replays_equal_eager": same}
+            del g
+        except RuntimeError as e:          # capture refused: report it, keep the eager figures
+            plain["graph"] = {"error": str(e)[:200]}
+        finally:
+            c.workspace_freeze(False)
+        torch.cuda.synchronize()
 
     # ---------------------------------------------------------------- standalone batched NTT
     n = c.n

@@ -30,7 +30,7 @@ __device__ __forceinline__ u64 mulhi(u64 x, u64 y) {
     const u32 x0 = (u32)x, x1 = (u32)(x >> 32), y0 = (u32)y, y1 = (u32)(y >> 32);
     const u64 t = mad32(x0, y1, __umulhi(x0, y0));
     const u64 u = mad32(x1, y0, (u32)t);
-    return mad32(x1, y1, (t >> 32) + (u >> 32));
+    return mad32(x1, y1, t >> 32) + (u >> 32);
 }
 
 // x * w mod q, result in [0, 2q), for any x < 2^64 and w < q with ws = floor(w 2^64 / q):
