@@ -926,8 +926,9 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
 // consecutive coefficients of one prime for up to 16 (FP64) or 8 (integer) ciphertexts
 // (threadIdx.y); each thread keeps
 // KC giant-step accumulators per polynomial, so every rotated ciphertext word is read once per
-// KC-chunk. The plaintext words of JB baby steps are staged in LDS per barrier pair and shared by
-// the workgroup's ciphertexts; the ciphertext words of those JB steps are loaded first.
+// KC-chunk. The plaintext words of JB baby steps are staged in LDS and shared by the workgroup's
+// ciphertexts (k_mac: per barrier pair, the ciphertext words of those JB steps loaded first;
+// k_mac_fp and k_mac_limb: pipelined, see below).
 // grid: x = N / 64 tiles, y = prime (from a PrimeList), z = ceil(B / blockDim.y) ciphertext
 // groups times t2 / KC chunks (a grid dimension, so that small batches still fill the GPU).
 constexpr int kMacJB = 4;
