@@ -103,7 +103,7 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
  *                        default 16; the chunk used is the largest of 16, 12, 8, 6, 4, 3, 2, 1
  *                        that divides t2 and does not exceed this cap);
  *   CTL_KNOB_MAC_CTS     ciphertexts per MAC workgroup, sharing its staged plaintexts (1..16,
- *                        default 8);
+ *                        default 16; the integer-prime MAC takes at most 8);
  *   CTL_KNOB_KEYIP_XCD   1 (default): key-product workgroups numbered so that all rotations of a
  *                        digit tile run on one XCD; 0: tiles first;
  *   CTL_KNOB_MAC_DIRECT  largest batch whose MAC reads plaintext words directly instead of staging
