@@ -264,6 +264,28 @@ def test_forward_ragged_batch(lazy):
         assert np.array_equal(_u64(c.forward(model, lk, dev[b:b + 1].contiguous()))[0], got[b]), b
 
 
+def test_profile_bytes_model():
+    """The algorithmic bytes the library records for a key product: one rotation of 3 ciphertexts
+    reads 3 k(k+1) digit rows and one key set's 2 k(k+1) key rows and writes 3 2(k+1) rows, N
+    words each; families that do not model bytes report 0."""
+    name = "mid"
+    c = _ctx(name)
+    lk = _keys(name)[0]
+    dev, _ = _fresh_ct(name, 23, count=3)
+    k, n = dev.shape[2], c.n
+    c.profile_enable(True)
+    try:
+        c.rotate(lk, dev, 3)
+        torch.cuda.synchronize()
+        launches = c.profile_read()
+        pb = c.profile_bytes()
+    finally:
+        c.profile_enable(False)
+    assert launches["k_keyip"][0] == 1 and launches["k_ntt_inv"][0] >= 1
+    assert pb["k_keyip"] == 8.0 * n * (3 * k * (k + 1) + 2 * k * (k + 1) + 3 * 2 * (k + 1))
+    assert pb["k_ntt_inv"] == 0.0
+
+
 def test_forward_key_product_rotation_groups():
     """Hoisted rotations per key-product workgroup (the keyip_rr knob, 1..4): every setting gives
     the same residues, the oracle's, on the large workload with a batch of 5 (odd for the key
