@@ -177,8 +177,8 @@ def main():
                          "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the encrypted forward pass shards by ciphertext with no "
-              "exchange, and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU (the encrypted forward pass would shard by ciphertext with "
+              "no exchange between GPUs, and no multi-GPU run is made); run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     pool, workers = None, 0
     if args.cpu_sample > 0 and args.workload == "large":
