@@ -109,9 +109,9 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
  *   CTL_KNOB_MAC_DIRECT  largest batch whose MAC reads plaintext words directly instead of staging
  *                        them in LDS for the workgroup's ciphertexts (0..64, default 3: at N = 2^14
  *                        the direct form is faster up to 3 ciphertexts, the staged one from 4);
- *   CTL_KNOB_NTT_XCD     1: ModUp workgroups numbered so that the targets of one digit, and ModDown
- *                        workgroups so that the primes of one group, run on one XCD and share its
- *                        L2; 0 (default): plain order (measured slightly faster at N = 2^14);
+ *   CTL_KNOB_NTT_XCD     1 (default): ModUp workgroups numbered so that the targets of one digit,
+ *                        and ModDown workgroups so that the primes of one group, run on one XCD
+ *                        and share its L2; 0: plain order;
  *   CTL_KNOB_MAC_LIMB    1 (default): the plaintext MAC and the key product over primes of 41..60
  *                        bits multiply 30-bit limbs into carry-free column sums (the MAC then
  *                        keeps at most 8 giant-step accumulators per thread); 0: 128-bit

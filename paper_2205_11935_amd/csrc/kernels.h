@@ -73,14 +73,14 @@ void launch_sum_gather(int logn, u64 *out, long o_sb, const u64 *base, long ba_s
                        const Tables &tab, hipStream_t st);
 // Launch choices an autotuner may set (defaults in brackets): the largest giant-step chunk of the
 // MAC [16], ciphertexts per MAC workgroup [16], XCD-grouped key-product numbering [1], largest
-// batch that uses the unstaged MAC [3], XCD-grouped ModUp / ModDown numbering [0], 30-bit limb
+// batch that uses the unstaged MAC [3], XCD-grouped ModUp / ModDown numbering [1], 30-bit limb
 // products in the integer-prime MAC [1], hoisted rotations per key-product workgroup [4].
 struct Knobs {
     int mac_chunk_cap = 16;
     int mac_cts = 16;
     int keyip_xcd = 1;
     int mac_direct_max = 3;      // batches up to this size use the unstaged MAC
-    int ntt_xcd = 0;             // XCD-grouped numbering of ModUp and ModDown workgroups
+    int ntt_xcd = 1;             // XCD-grouped numbering of ModUp and ModDown workgroups
     int mac_limb = 1;            // integer-prime MAC by 30-bit limbs where every prime is below 2^60
     int keyip_rr = 4;            // key product: hoisted rotations per workgroup sharing digit words (1..4)
 };
