@@ -154,6 +154,27 @@ int ctl_workspace_freeze(ctl_ctx *ctx, int frozen);
 int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, int inverse,
             void *stream);
 
+/* Parity hooks (the bit-exact tests feed both the library and an independent implementation the
+ * same integers, since FP64 encoding is not bit-reproducible across implementations).
+ * Residue polynomials [n_poly][k][N] over q_0..q_{k-1} (a ciphertext has n_poly = 2), in NTT form
+ * (CTL_FORM_NTT, the library's form at rest) or coefficient form (CTL_FORM_COEFF).
+ * ctl_ct_export copies device `ct` (NTT form) to host `host_out`, transformed to the requested
+ * form on the device first; synchronizes the stream. ctl_ct_import copies host residues in the given
+ * form to device `ct_out` in NTT form; every word must be reduced modulo its row's prime, else
+ * CTL_EINVAL and nothing is written; synchronizes. ctl_pt_import uploads n_pt signed integer
+ * plaintexts (host int64 [n_pt][N] coefficients, |c| < 2^62, else CTL_ESCALE) to device `pt_out` as
+ * [n_pt][k][N] NTT form over q_0..q_{k-1}, or [n_pt][k+1][N] with a last row mod P when ext != 0
+ * (the layout of a plaintext-bank row of a layer with baby steps over Q*P); synchronizes. k outside
+ * 1..n_q gives CTL_ELEVEL. */
+#define CTL_FORM_NTT 0
+#define CTL_FORM_COEFF 1
+int ctl_ct_export(ctl_ctx *ctx, const uint64_t *ct, int k, int n_poly, int form, uint64_t *host_out,
+                  void *stream);
+int ctl_ct_import(ctl_ctx *ctx, const uint64_t *host, int k, int n_poly, int form, uint64_t *ct_out,
+                  void *stream);
+int ctl_pt_import(ctl_ctx *ctx, const int64_t *coeffs, int n_pt, int k, int ext, uint64_t *pt_out,
+                  void *stream);
+
 /* Instrumentation for benchmarks: while enabled, every kernel launch the context makes is
  * bracketed by a pair of HIP events recorded on the launch stream. ctl_profile_read synchronizes
  * the recorded events and returns, for kernel family `family` (0 .. ctl_profile_families()-1),
@@ -352,7 +373,7 @@ int ctl_decode(ctl_ctx *ctx, const uint64_t *residues, int k, double scale, doub
 int ctl_decode_items(ctl_ctx *ctx, const ctl_model *model, const uint64_t *residues, double *y_out);
 
 /* ------------------------------------------------------------------ wire format (host only) */
-/* Serialized ciphertexts for the client-server messages ("Communication" paragraph of Section 4.2:
+/* Serialized ciphertexts for the client-server messages (Section 5.1, "Runtime and Data Communication", Table 2:
  * the client sends a ciphertext at the top level, the server returns one at q_0). Little-endian:
  *   bytes 0-3 "CTL1", 4 version (1), 5 log2 N, 6 k, 7 n_poly (2: (c0, c1); 1: c0 of a seeded
  *   symmetric ciphertext), 8-15 FNV-1a-64 digest of the primes q_0..q_{n_q-1}, P as little-endian
@@ -379,8 +400,8 @@ int ctl_ct_unpack(const ctl_params *params, const uint8_t *in, uint64_t len, uin
 int ctl_forward(ctl_ctx *ctx, const ctl_model *model, const ctl_evk *evk, const uint64_t *in,
                 uint64_t *out, int n_ct, void *stream);
 
-/* ctl_forward on a batch that mixes clients (Algorithm 2, ClassifyHE, for several key owners at
- * once): ciphertext b is evaluated with evks[b], an array of n_ct handles (host memory, read during
+/* ctl_forward on a batch that mixes clients (ClassifyHE of the protocol figure of Section 3, for
+ * several key owners at once): ciphertext b is evaluated with evks[b], an array of n_ct handles (host memory, read during
  * the call only). Consecutive equal handles form a run; the key products of Section 3.1's
  * rotations and relinearizations run once per run, every other kernel (NTTs, ModUp, ModDown,
  * plaintext products, rescales) once over the whole batch. Output b equals ctl_forward of

@@ -36,7 +36,8 @@ i64p = ctypes.POINTER(ctypes.c_int64)
 def _lib():
     global _LIB
     if _LIB is None:
-        path = _build.build(force=False)
+        # CTL_ORACLE_LIB: another build of the same source (the sanitizer run of the tests)
+        path = os.environ.get("CTL_ORACLE_LIB") or _build.build(force=False)
         lib = ctypes.CDLL(path)
         lib.or_ctx_new.restype = ctypes.c_void_p
         lib.or_ctx_new.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),

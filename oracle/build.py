@@ -18,5 +18,17 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+def build_sanitized(out_dir: str) -> str:
+    """The oracle under AddressSanitizer and UndefinedBehaviorSanitizer, built with the ROCm clang
+    so that it shares the library's sanitizer runtime (preload that runtime to load it)."""
+    os.makedirs(out_dir, exist_ok=True)
+    lib = os.path.join(out_dir, "liboracle.so")
+    cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-fno-omit-frame-pointer", "-std=c11", "-Wall", "-fPIC",
+           "-shared", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-o", lib, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return lib
+
+
 if __name__ == "__main__":
     print(build(force="--lazy" not in sys.argv))

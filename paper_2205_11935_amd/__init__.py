@@ -15,7 +15,8 @@ from typing import Dict, List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcryptotl.so")
+# CTL_LIB_PATH: another build of the same sources (the sanitizer run of the host tests)
+LIB_PATH = os.environ.get("CTL_LIB_PATH") or os.path.join(_HERE, "libcryptotl.so")
 
 CTL_ACT_NONE = 0
 CTL_ACT_SQUARE = 1
@@ -32,6 +33,8 @@ CTL_KNOB_KEYIP_RR = 6
 KNOBS = {"mac_chunk": CTL_KNOB_MAC_CHUNK, "mac_cts": CTL_KNOB_MAC_CTS, "keyip_xcd": CTL_KNOB_KEYIP_XCD,
          "mac_direct": CTL_KNOB_MAC_DIRECT, "ntt_xcd": CTL_KNOB_NTT_XCD, "mac_limb": CTL_KNOB_MAC_LIMB,
          "keyip_rr": CTL_KNOB_KEYIP_RR}
+CTL_FORM_NTT = 0
+CTL_FORM_COEFF = 1
 CTL_LAYER_DENSE = 0
 CTL_LAYER_CONV1D = 1
 CTL_LAYER_AVGPOOL = 2
@@ -114,6 +117,12 @@ _SIGS = {
     "ctl_set_allocator": (ctypes.c_int, [ctypes.c_void_p, _ALLOC_FN, _FREE_FN, ctypes.c_void_p]),
     "ctl_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, u64p]),
     "ctl_ntt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, i32p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_ct_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     u64p, ctypes.c_void_p]),
+    "ctl_ct_import": (ctypes.c_int, [ctypes.c_void_p, u64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "ctl_pt_import": (ctypes.c_int, [ctypes.c_void_p, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
     "ctl_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "ctl_profile_families": (ctypes.c_int, []),
     "ctl_profile_family_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -248,6 +257,40 @@ def _stream(stream) -> ctypes.c_void_p:
 
 def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
+
+
+def check_tensor(t, shape, device: int, what: str):
+    """Check a device buffer before its address crosses the C ABI, which takes only sizes and a
+    pointer: the tensor must be a contiguous torch.int64 tensor of exactly `shape` on cuda:`device`.
+    Raises TypeError / ValueError naming `what` otherwise. Returns the pointer."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s: expected a torch.Tensor, got %s" % (what, type(t).__name__))
+    if t.dtype != torch.int64:
+        raise ValueError("%s: dtype %s, expected torch.int64 (uint64 residues)" % (what, t.dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s: shape %s, expected %s" % (what, tuple(t.shape), tuple(shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s: tensor is not contiguous" % what)
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError("%s: tensor on %s, expected cuda:%d" % (what, t.device, device))
+    return _ptr(t)
+
+
+def check_disjoint(a, b, what: str):
+    """The library's outputs must not overlap its inputs."""
+    a0, b0 = a.data_ptr(), b.data_ptr()
+    a1, b1 = a0 + a.numel() * a.element_size(), b0 + b.numel() * b.element_size()
+    if a0 < b1 and b0 < a1:
+        raise ValueError("%s: output overlaps the input" % what)
+
+
+def _batch_dims(t, what: str):
+    """(n_ct, k) of a ciphertext batch [n_ct][2][k][N]."""
+    if getattr(t, "dim", None) is None or t.dim() != 4 or t.shape[1] != 2:
+        raise ValueError("%s: expected a ciphertext batch [n_ct][2][k][N], got shape %s"
+                         % (what, tuple(getattr(t, "shape", ()))))
+    return int(t.shape[0]), int(t.shape[2])
 
 
 @dataclasses.dataclass
@@ -387,6 +430,20 @@ class Context:
     def empty_ct(self, n_ct: int, k: int):
         return self._torch.empty((n_ct, 2, k, self.n), dtype=self._torch.int64, device="cuda:%d" % self.device)
 
+    def _dev(self, t, shape, what: str) -> ctypes.c_void_p:
+        return check_tensor(t, shape, self.device, what)
+
+    def _level(self, t, k_min: int, what: str):
+        """(n_ct, k) of a ciphertext batch whose level this context holds, k >= k_min."""
+        n_ct, k = _batch_dims(t, what)
+        if not k_min <= k <= self.nq:
+            raise ValueError("%s: %d primes, this call takes %d..%d" % (what, k, k_min, self.nq))
+        return n_ct, k
+
+    def _coeffs(self, m: np.ndarray, what: str):
+        if m.shape != (self.n,):
+            raise ValueError("%s: shape %s, expected (%d,)" % (what, m.shape, self.n))
+
     def workspace_bytes(self) -> int:
         b = ctypes.c_uint64()
         _check(lib().ctl_workspace_bytes(self.handle, ctypes.byref(b)))
@@ -419,7 +476,49 @@ class Context:
     # ------------------------------------------------------------ parity hook
     def ntt(self, buf, prime_idx: Sequence[int], inverse: bool = False, stream=None):
         idx = (ctypes.c_int32 * len(prime_idx))(*prime_idx)
-        _check(lib().ctl_ntt(self.handle, _ptr(buf), len(prime_idx), idx, int(inverse), _stream(stream)))
+        if buf.numel() != len(prime_idx) * self.n:
+            raise ValueError("ntt: %d residues of %d words need %d elements, the buffer has %d"
+                             % (len(prime_idx), self.n, len(prime_idx) * self.n, buf.numel()))
+        p = self._dev(buf, tuple(buf.shape), "ntt buffer")
+        _check(lib().ctl_ntt(self.handle, p, len(prime_idx), idx, int(inverse), _stream(stream)))
+
+    def ct_export(self, ct, coeff: bool = False, stream=None) -> np.ndarray:
+        """Device residues [..][k][N] in NTT form -> host uint64 array of the same shape, in NTT or
+        coefficient form (ctl_ct_export)."""
+        if ct.dim() < 2 or ct.shape[-1] != self.n:
+            raise ValueError("ct_export: expected [..][k][N], got %s" % (tuple(ct.shape),))
+        k = int(ct.shape[-2])
+        n_poly = ct.numel() // (k * self.n)
+        p = self._dev(ct, tuple(ct.shape), "ct_export input")
+        out = np.zeros(tuple(ct.shape), dtype=np.uint64)
+        _check(lib().ctl_ct_export(self.handle, p, k, n_poly, CTL_FORM_COEFF if coeff else CTL_FORM_NTT,
+                                   out.ctypes.data_as(u64p), _stream(stream)))
+        return out
+
+    def ct_import(self, host: np.ndarray, coeff: bool = False, out=None, stream=None):
+        """Host residues [..][k][N] (NTT or coefficient form) -> device tensor in NTT form (ctl_ct_import)."""
+        h = np.ascontiguousarray(host, dtype=np.uint64)
+        if h.ndim < 2 or h.shape[-1] != self.n:
+            raise ValueError("ct_import: expected [..][k][N], got %s" % (h.shape,))
+        k = int(h.shape[-2])
+        if out is None:
+            out = self._torch.empty(h.shape, dtype=self._torch.int64, device="cuda:%d" % self.device)
+        p = self._dev(out, h.shape, "ct_import output")
+        _check(lib().ctl_ct_import(self.handle, h.ctypes.data_as(u64p), k, h.size // (k * self.n),
+                                   CTL_FORM_COEFF if coeff else CTL_FORM_NTT, p, _stream(stream)))
+        return out
+
+    def pt_import(self, coeffs: np.ndarray, k: int, ext: bool = False, out=None, stream=None):
+        """Signed integer plaintexts [n_pt][N] -> device [n_pt][k (+1 with ext)][N] NTT form (ctl_pt_import)."""
+        m = np.ascontiguousarray(coeffs, dtype=np.int64)
+        if m.ndim != 2 or m.shape[1] != self.n:
+            raise ValueError("pt_import: expected [n_pt][N], got %s" % (m.shape,))
+        shape = (m.shape[0], k + (1 if ext else 0), self.n)
+        if out is None:
+            out = self._torch.empty(shape, dtype=self._torch.int64, device="cuda:%d" % self.device)
+        p = self._dev(out, shape, "pt_import output")
+        _check(lib().ctl_pt_import(self.handle, m.ctypes.data_as(i64p), m.shape[0], k, int(ext), p, _stream(stream)))
+        return out
 
     # ------------------------------------------------------------ client side
     def keygen(self, seed: int, rotations: Sequence[int], relin: bool = True) -> Keys:
@@ -457,38 +556,50 @@ class Context:
 
     def encrypt(self, keys: Keys, coeffs: np.ndarray, seed: int, out=None, stream=None):
         m = np.ascontiguousarray(coeffs, dtype=np.int64)
+        self._coeffs(m, "plaintext")
         if out is None:
             out = self.empty_ct(1, self.nq)[0]
-        _check(lib().ctl_encrypt(self.handle, keys.pk, m.ctypes.data_as(i64p), seed, _ptr(out), _stream(stream)))
+        p = self._dev(out, (2, self.nq, self.n), "encrypt output")
+        _check(lib().ctl_encrypt(self.handle, keys.pk, m.ctypes.data_as(i64p), seed, p, _stream(stream)))
         return out
 
     def encrypt_sym(self, keys: Keys, coeffs: np.ndarray, seed: int, out=None, stream=None):
         m = np.ascontiguousarray(coeffs, dtype=np.int64)
+        self._coeffs(m, "plaintext")
         if out is None:
             out = self.empty_ct(1, self.nq)[0]
-        _check(lib().ctl_encrypt_sym(self.handle, keys.sk, m.ctypes.data_as(i64p), seed, _ptr(out), _stream(stream)))
+        p = self._dev(out, (2, self.nq, self.n), "encrypt output")
+        _check(lib().ctl_encrypt_sym(self.handle, keys.sk, m.ctypes.data_as(i64p), seed, p, _stream(stream)))
         return out
 
     def expand_seeded(self, c0: np.ndarray, seed: int, out=None, stream=None):
         c0 = np.ascontiguousarray(c0, dtype=np.uint64)
+        if c0.size != self.nq * self.n:
+            raise ValueError("c0: %d words, expected %d" % (c0.size, self.nq * self.n))
         if out is None:
             out = self.empty_ct(1, self.nq)[0]
-        _check(lib().ctl_expand_seeded(self.handle, c0.ctypes.data_as(u64p), seed, _ptr(out), _stream(stream)))
+        p = self._dev(out, (2, self.nq, self.n), "expanded ciphertext")
+        _check(lib().ctl_expand_seeded(self.handle, c0.ctypes.data_as(u64p), seed, p, _stream(stream)))
         return out
 
     def decrypt(self, keys: Keys, ct, k: int, stream=None) -> np.ndarray:
+        p = self._dev(ct, (2, k, self.n), "ciphertext")
         out = np.zeros((k, self.n), dtype=np.uint64)
-        _check(lib().ctl_decrypt(self.handle, keys.sk, _ptr(ct), k, out.ctypes.data_as(u64p), _stream(stream)))
+        _check(lib().ctl_decrypt(self.handle, keys.sk, p, k, out.ctypes.data_as(u64p), _stream(stream)))
         return out
 
     def decode(self, residues: np.ndarray, scale: float) -> np.ndarray:
         r = np.ascontiguousarray(residues, dtype=np.uint64)
+        if r.ndim != 2 or r.shape[1] != self.n or not 1 <= r.shape[0] <= self.nq:
+            raise ValueError("residues: shape %s, expected (k, %d) with 1 <= k <= %d" % (r.shape, self.n, self.nq))
         out = np.zeros(self.n // 2, dtype=np.float64)
         _check(lib().ctl_decode(self.handle, r.ctypes.data_as(u64p), r.shape[0], scale, out.ctypes.data_as(f64p)))
         return out
 
     def decode_items(self, model: Model, residues: np.ndarray) -> np.ndarray:
         r = np.ascontiguousarray(residues, dtype=np.uint64)
+        if r.shape != (model.info.k_out, self.n):
+            raise ValueError("residues: shape %s, expected %s" % (r.shape, (model.info.k_out, self.n)))
         out = np.zeros((model.info.items, model.info.n_out), dtype=np.float64)
         _check(lib().ctl_decode_items(self.handle, model.handle, r.ctypes.data_as(u64p), out.ctypes.data_as(f64p)))
         return out
@@ -567,77 +678,106 @@ class Context:
         _check(lib().ctl_workspace_freeze(self.handle, int(frozen)))
 
     def forward(self, model: Model, keys: Keys, ct, out=None, stream=None):
-        n_ct = ct.shape[0]
+        n_ct, _ = _batch_dims(ct, "forward input")
+        pi = self._dev(ct, (n_ct, 2, model.info.k_in, self.n), "forward input")
         if out is None:
             out = self.empty_ct(n_ct, model.info.k_out)
-        _check(lib().ctl_forward(self.handle, model.handle, keys.evk, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        po = self._dev(out, (n_ct, 2, model.info.k_out, self.n), "forward output")
+        check_disjoint(ct, out, "forward")
+        _check(lib().ctl_forward(self.handle, model.handle, keys.evk, pi, po, n_ct, _stream(stream)))
         return out
 
     def forward_multi(self, model: Model, keys: Sequence[Keys], ct, out=None, stream=None):
         """forward on a batch mixing clients: ciphertext b is evaluated with keys[b]. Key products
         run once per run of consecutive ciphertexts with the same Keys object."""
-        n_ct = ct.shape[0]
+        n_ct, _ = _batch_dims(ct, "forward input")
         if len(keys) != n_ct:
             raise ValueError("one Keys per ciphertext")
+        pi = self._dev(ct, (n_ct, 2, model.info.k_in, self.n), "forward input")
         if out is None:
             out = self.empty_ct(n_ct, model.info.k_out)
+        po = self._dev(out, (n_ct, 2, model.info.k_out, self.n), "forward output")
+        check_disjoint(ct, out, "forward_multi")
         arr = (ctypes.c_void_p * n_ct)(*[kk.evk for kk in keys])
-        _check(lib().ctl_forward_multi(self.handle, model.handle, arr, _ptr(ct), _ptr(out), n_ct,
-                                       _stream(stream)))
+        _check(lib().ctl_forward_multi(self.handle, model.handle, arr, pi, po, n_ct, _stream(stream)))
         return out
 
     def dense(self, model: Model, layer: int, keys: Keys, ct, out=None, stream=None):
-        n_ct, k = ct.shape[0], ct.shape[2]
+        n_ct, _ = _batch_dims(ct, "dense input")
+        if not 0 <= layer < model.info.n_layers:
+            raise ValueError("layer %d out of range" % layer)
+        k = model.info.layer_k[layer]
+        pi = self._dev(ct, (n_ct, 2, k, self.n), "dense input")
         if out is None:
             out = self.empty_ct(n_ct, k - 1)
-        _check(lib().ctl_dense(self.handle, model.handle, layer, keys.evk, _ptr(ct), _ptr(out), n_ct,
-                               _stream(stream)))
+        po = self._dev(out, (n_ct, 2, k - 1, self.n), "dense output")
+        check_disjoint(ct, out, "dense")
+        _check(lib().ctl_dense(self.handle, model.handle, layer, keys.evk, pi, po, n_ct, _stream(stream)))
         return out
 
     def mul(self, keys: Keys, a, b, out=None, stream=None):
-        n_ct, k = a.shape[0], a.shape[2]
+        n_ct, k = self._level(a, 2, "mul operand a")
+        pa = self._dev(a, (n_ct, 2, k, self.n), "mul operand a")
+        pb = self._dev(b, (n_ct, 2, k, self.n), "mul operand b")
         if out is None:
             out = self.empty_ct(n_ct, k - 1)
-        _check(lib().ctl_mul(self.handle, keys.evk, k, _ptr(a), _ptr(b), _ptr(out), n_ct, _stream(stream)))
+        po = self._dev(out, (n_ct, 2, k - 1, self.n), "mul output")
+        check_disjoint(a, out, "mul")
+        check_disjoint(b, out, "mul")
+        _check(lib().ctl_mul(self.handle, keys.evk, k, pa, pb, po, n_ct, _stream(stream)))
         return out
 
     def poly3(self, keys: Keys, ct, scale: float, coef: Sequence[float], out=None, stream=None):
         """Degree-3 activation; returns (output [n][2][k-2][N], output scale)."""
-        n_ct, k = ct.shape[0], ct.shape[2]
+        n_ct, k = self._level(ct, 3, "poly3 input")
+        pi = self._dev(ct, (n_ct, 2, k, self.n), "poly3 input")
         if out is None:
             out = self.empty_ct(n_ct, k - 2)
+        po = self._dev(out, (n_ct, 2, k - 2, self.n), "poly3 output")
+        check_disjoint(ct, out, "poly3")
         cf = (ctypes.c_double * 4)(*[float(c) for c in coef])
         so = ctypes.c_double()
-        _check(lib().ctl_poly3(self.handle, keys.evk, k, scale, cf, _ptr(ct), _ptr(out), n_ct, _stream(stream),
-                               ctypes.byref(so)))
+        _check(lib().ctl_poly3(self.handle, keys.evk, k, scale, cf, pi, po, n_ct, _stream(stream), ctypes.byref(so)))
         return out, so.value
 
     def square(self, keys: Keys, ct, out=None, stream=None):
-        n_ct, k = ct.shape[0], ct.shape[2]
+        n_ct, k = self._level(ct, 2, "square input")
+        pi = self._dev(ct, (n_ct, 2, k, self.n), "square input")
         if out is None:
             out = self.empty_ct(n_ct, k - 1)
-        _check(lib().ctl_square(self.handle, keys.evk, k, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        po = self._dev(out, (n_ct, 2, k - 1, self.n), "square output")
+        check_disjoint(ct, out, "square")
+        _check(lib().ctl_square(self.handle, keys.evk, k, pi, po, n_ct, _stream(stream)))
         return out
 
     def replicate(self, keys: Keys, ct, width: int, out=None, stream=None):
-        n_ct, k = ct.shape[0], ct.shape[2]
+        n_ct, k = self._level(ct, 1, "replicate input")
+        pi = self._dev(ct, (n_ct, 2, k, self.n), "replicate input")
         if out is None:
             out = self.empty_ct(n_ct, k)
-        _check(lib().ctl_replicate(self.handle, keys.evk, k, width, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        po = self._dev(out, (n_ct, 2, k, self.n), "replicate output")
+        check_disjoint(ct, out, "replicate")
+        _check(lib().ctl_replicate(self.handle, keys.evk, k, width, pi, po, n_ct, _stream(stream)))
         return out
 
     def rotate(self, keys: Keys, ct, rotation: int, out=None, stream=None):
-        n_ct, k = ct.shape[0], ct.shape[2]
+        n_ct, k = self._level(ct, 1, "rotate input")
+        pi = self._dev(ct, (n_ct, 2, k, self.n), "rotate input")
         if out is None:
             out = self.empty_ct(n_ct, k)
-        _check(lib().ctl_rotate(self.handle, keys.evk, k, rotation, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        po = self._dev(out, (n_ct, 2, k, self.n), "rotate output")
+        check_disjoint(ct, out, "rotate")
+        _check(lib().ctl_rotate(self.handle, keys.evk, k, rotation, pi, po, n_ct, _stream(stream)))
         return out
 
     def rescale(self, ct, out=None, stream=None):
-        n_ct, k = ct.shape[0], ct.shape[2]
+        n_ct, k = self._level(ct, 2, "rescale input")
+        pi = self._dev(ct, (n_ct, 2, k, self.n), "rescale input")
         if out is None:
             out = self.empty_ct(n_ct, k - 1)
-        _check(lib().ctl_rescale(self.handle, k, _ptr(ct), _ptr(out), n_ct, _stream(stream)))
+        po = self._dev(out, (n_ct, 2, k - 1, self.n), "rescale output")
+        check_disjoint(ct, out, "rescale")
+        _check(lib().ctl_rescale(self.handle, k, pi, po, n_ct, _stream(stream)))
         return out
 
 

@@ -54,5 +54,42 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+# AddressSanitizer + UndefinedBehaviorSanitizer on the host code only (the GPU code object is the
+# ordinary one): each sanitizer flag goes to the host compilation through -Xarch_host.
+SAN_FLAGS = ["-g", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def sanitizer_runtime() -> str:
+    """The compiler's shared AddressSanitizer runtime (it carries the UndefinedBehaviorSanitizer
+    handlers too); a process that loads a sanitized library must preload it."""
+    import glob
+    found = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not found:
+        raise RuntimeError("no AddressSanitizer runtime found under /opt/rocm/llvm")
+    return found[-1]
+
+
+def build_sanitized(out_dir: str) -> str:
+    """The library with its host sources built under the sanitizers, as out_dir/libcryptotl.so
+    (the kernels' object is reused from the ordinary build). Returns its path."""
+    kobj = os.path.join(OUT_DIR, "kernels.o")
+    if not os.path.exists(kobj):
+        build(force=True)
+    os.makedirs(out_dir, exist_ok=True)
+    objs = []
+    for s in SOURCES:
+        if s.endswith(".hip"):
+            objs.append(kobj)
+            continue
+        obj = os.path.join(out_dir, os.path.splitext(s)[0] + ".o")
+        _run([HIPCC] + COMMON + SAN_FLAGS + ["-c", os.path.join(CSRC, s), "-o", obj])
+        objs.append(obj)
+    lib = os.path.join(out_dir, "libcryptotl.so")
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", lib] + objs)
+    return lib
+
+
 if __name__ == "__main__":
     print(build(force="--lazy" not in sys.argv))

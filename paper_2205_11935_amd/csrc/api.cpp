@@ -1349,6 +1349,65 @@ int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, in
     return CTL_OK;
 }
 
+// ---------------------------------------------------------------- parity hooks
+int ctl_ct_export(ctl_ctx *ctx, const uint64_t *ct, int k, int n_poly, int form, uint64_t *host_out, void *stream) {
+    if (!ctx || !ct || !host_out || n_poly < 1) return fail(CTL_EINVAL, "bad argument");
+    if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    if (form != CTL_FORM_NTT && form != CTL_FORM_COEFF) return fail(CTL_EINVAL, "unknown form");
+    CTL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    const size_t words = (size_t)n_poly * k * ctx->hp.n;
+    const u64 *src = reinterpret_cast<const u64 *>(ct);
+    if (form == CTL_FORM_COEFF) {
+        u64 *tmp;
+        CTL_TRY(slot(ctx, S_COEF2, words, st, &tmp));
+        launch_ntt(ctx->hp.logn, true, src, dense_map(k), tmp, dense_map(k), n_poly * k, ctx->tab, st);
+        CTL_TRY(check_launch());
+        src = tmp;
+    }
+    CTL_HIP(hipMemcpyAsync(host_out, src, words * 8, hipMemcpyDeviceToHost, st));
+    CTL_HIP(hipStreamSynchronize(st));
+    return CTL_OK;
+}
+
+int ctl_ct_import(ctl_ctx *ctx, const uint64_t *host, int k, int n_poly, int form, uint64_t *ct_out, void *stream) {
+    if (!ctx || !host || !ct_out || n_poly < 1) return fail(CTL_EINVAL, "bad argument");
+    if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    if (form != CTL_FORM_NTT && form != CTL_FORM_COEFF) return fail(CTL_EINVAL, "unknown form");
+    const long n = ctx->hp.n;
+    for (int p = 0; p < n_poly; ++p)
+        for (int i = 0; i < k; ++i)
+            for (long x = 0; x < n; ++x)
+                if (host[((size_t)p * k + i) * n + x] >= ctx->hp.mods[i])
+                    return fail(CTL_EINVAL, "residue word not reduced modulo its prime");
+    CTL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    const size_t words = (size_t)n_poly * k * n;
+    u64 *dst = reinterpret_cast<u64 *>(ct_out);
+    if (form == CTL_FORM_COEFF) {
+        u64 *tmp;
+        CTL_TRY(slot(ctx, S_COEF2, words, st, &tmp));
+        CTL_HIP(hipMemcpyAsync(tmp, host, words * 8, hipMemcpyHostToDevice, st));
+        launch_ntt(ctx->hp.logn, false, tmp, dense_map(k), dst, dense_map(k), n_poly * k, ctx->tab, st);
+        CTL_TRY(check_launch());
+    } else {
+        CTL_HIP(hipMemcpyAsync(dst, host, words * 8, hipMemcpyHostToDevice, st));
+    }
+    CTL_HIP(hipStreamSynchronize(st));
+    return CTL_OK;
+}
+
+int ctl_pt_import(ctl_ctx *ctx, const int64_t *coeffs, int n_pt, int k, int ext, uint64_t *pt_out, void *stream) {
+    if (!ctx || !coeffs || !pt_out || n_pt < 1) return fail(CTL_EINVAL, "bad argument");
+    if (k < 1 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    const size_t cnt = (size_t)n_pt * ctx->hp.n;
+    for (size_t x = 0; x < cnt; ++x)
+        if (coeffs[x] >= (int64_t)(1ull << 62) || coeffs[x] <= -(int64_t)(1ull << 62))
+            return fail(CTL_ESCALE, "plaintext coefficient out of range");
+    CTL_HIP(hipSetDevice(ctx->device));
+    return upload_ints(ctx, as_stream(stream), coeffs, n_pt, k, reinterpret_cast<u64 *>(pt_out), ext != 0);
+}
+
 // ---------------------------------------------------------------- keys
 int ctl_keygen(ctl_ctx *ctx, uint64_t seed, const int32_t *rotations, int n_rot, int relin,
                ctl_sk **sk_out, ctl_pk **pk_out, ctl_evk **evk_out) {

@@ -255,6 +255,8 @@ class PsetSpec:
     lanes: int = 2
     lazy: bool = True
     qp: bool = True              # baby steps over Q*P (dense-layer variant)
+    raw_banks: Optional[List[np.ndarray]] = None    # already-encoded int64 [t][N] plaintexts per layer
+                                                    # (used instead of `weights` when given)
 
 
 class _Lane:
@@ -289,7 +291,8 @@ class GpuServer:
             w = s.workload
             ctxs = [Context.for_workload(w, device=device) for _ in range(s.lanes)]
             layers = [(l.n_in, l.n_out, l.t1) for l in w.layers]
-            m = ctxs[0].load_model(layers, s.weights, lazy=s.lazy, qp=s.qp)
+            m = (ctxs[0].load_model_raw(layers, s.raw_banks, lazy=s.lazy, qp=s.qp) if s.raw_banks is not None
+                 else ctxs[0].load_model(layers, s.weights, lazy=s.lazy, qp=s.qp))
             self.models[s.name] = m
             k_in, k_out = m.info.k_in, m.info.k_out
             per_slot = 2 * (k_in + k_out) * ctxs[0].n * 8

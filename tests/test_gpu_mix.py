@@ -44,12 +44,13 @@ def _setup(widths, nq_queries):
     return c, o, queries, keys, (s, pk, okeys, rlk)
 
 
-def _oracle_query(o, q, ct, bank, okeys, rlk):
+def _oracle_query(o, q, ct, bank, okeys, rlk, banks_ntt=None):
     for l in range(q.depth):
         w_in, w_out = q.widths[l], q.widths[l + 1]
         t = max(w_in, w_out)
         k = o.nq - 2 * l
-        pts = o.bank_ntt(bank(l, w_in, w_out, t), k, ext=True)
+        pts = (banks_ntt[(l, w_in, w_out)] if banks_ntt is not None
+               else o.bank_ntt(bank(l, w_in, w_out, t), k, ext=True))
         ct = o.dense(ct, pts, W.MIX_T1[t], okeys, lazy=True, qp=True)
         if l + 1 < q.depth:
             ct = o.square(ct, rlk)
@@ -74,6 +75,34 @@ def test_mix_bit_exact_against_oracle():
         got = ctl.to_numpy_u64(outs[i])
         assert got.shape == want.shape == (2, o.nq - 2 * q.depth + 1, o.n)
         assert np.array_equal(got, want), (i, q)
+
+
+def test_mix_bit_exact_wide_layers():
+    """Widths 512 and 768 only (t1 = 64, the largest banks), at every position: 10 queries of depth
+    1-3 on the shared 1536-slot block, each against the oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2205_11935_amd.batch_mix import MixEngine
+    import paper_2205_11935_amd as ctl
+    c, o, queries, keys, (s, pk, okeys, rlk) = _setup((512, 768), 10)
+    bank = _raw_bank(o.n)
+    eng = MixEngine(c, keys, bank, W.MIX_T1, W.MIX_BLOCK, raw=True, lazy=True)
+    msgs = W.raw_plaintexts(79, len(queries), o.n, bound_bits=40)
+    dev = c.empty_ct(len(queries), o.nq)
+    for i in range(len(queries)):
+        c.encrypt(keys, msgs[i], 800 + i, out=dev[i])
+    outs = [ctl.to_numpy_u64(x) for x in eng.run(dev, queries)]
+    shapes = {(l, q.widths[l], q.widths[l + 1]) for q in queries for l in range(q.depth)}
+    assert {sh[0] for sh in shapes} == {0, 1, 2} and {sh[1] for sh in shapes} == {512, 768}
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        # the C oracle releases the interpreter lock and keeps no shared mutable state
+        banks_ntt = dict(zip(sorted(shapes), ex.map(
+            lambda sh: o.bank_ntt(bank(sh[0], sh[1], sh[2], max(sh[1], sh[2])), o.nq - 2 * sh[0], ext=True),
+            sorted(shapes))))
+        wants = list(ex.map(lambda i: _oracle_query(o, queries[i], o.encrypt(pk, msgs[i], 800 + i), bank, okeys,
+                                                    rlk, banks_ntt), range(len(queries))))
+    for i, q in enumerate(queries):
+        assert outs[i].shape == wants[i].shape == (2, o.nq - 2 * q.depth + 1, o.n)
+        assert np.array_equal(outs[i], wants[i]), (i, q)
 
 
 def test_mix_graph_replays_match_eager():

@@ -3,7 +3,8 @@ clients arrive as a Poisson stream and are served with continuous batching (batc
 each evaluated with its own keys), with a key budget
 that holds only one N=2^14 client's keys at a time (so keys are evicted and uploaded again). Every
 result must equal, bit for bit, the same query evaluated alone with the client's own keys, and the
-decrypted results must match the FP64 forward pass."""
+decrypted results must match the FP64 forward pass. A second run serves a model of seeded integer
+plaintexts and checks served results against the CPU oracle."""
 import numpy as np
 import pytest
 
@@ -83,3 +84,60 @@ def test_serving_results_equal_alone_and_in_the_mix():
                 ref = ref * ref
         assert normwise_error(y, ref) < 2.0 ** -20, r.rid
     srv.close()
+
+
+def test_served_results_match_oracle():
+    """Both parameter sets served from integer plaintext banks (the bit-exact contract leaves FP64
+    encoding out): a burst of 8 queries from one client per set, then 4 more arriving while those
+    run; two served results per set equal the oracle's forward pass with that client's keys."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_2205_11935_amd as ctl
+    from oracle import CKKSOracle
+    from paper_2205_11935_amd.serving import GpuServer, PsetSpec, Request, latency_stats, poisson_arrivals
+
+    wl = {"mid": W.MID, "large": W.LARGE}
+    orc = {p: CKKSOracle.for_workload(wl[p]) for p in wl}
+    plans = {p: orc[p].plan([(l.n_in, l.n_out, l.t1) for l in wl[p].layers], lazy=True, qp=True) for p in wl}
+    raw = {p: [W.raw_plaintexts(91 + li, L.t, orc[p].n, bound_bits=45, stream=li) for li, L in enumerate(plans[p].layers)]
+           for p in wl}
+    specs = [PsetSpec("mid", W.MID, None, slot_bytes_budget=8 << 20, max_batch=4, lanes=2, raw_banks=raw["mid"]),
+             PsetSpec("large", W.LARGE, None, slot_bytes_budget=16 << 20, max_batch=4, lanes=2, raw_banks=raw["large"])]
+    clients = {0: "mid", 1: "large"}
+    cctx = {p: ctl.Context.for_workload(wl[p]) for p in wl}
+    ckeys = {c: cctx[p].keygen(wl[p].seed_keys + 100 * c, plans[p].rotations, relin=True) for c, p in clients.items()}
+    srv = GpuServer(specs, key_budget=1 << 34, keep_outputs=True)
+    for c, p in clients.items():
+        srv.register_client(c, p, ckeys[c].evaluation_keys())
+    srv.warmup()
+    reqs, msgs = [], []
+    for i in range(12):
+        c = i % 2
+        p = clients[c]
+        m = W.raw_plaintexts(95 + i, 1, orc[p].n, bound_bits=40)[0]
+        reqs.append(Request(i, c, p, ct=cctx[p].encrypt(ckeys[c], m, seed=9500 + i)))
+        msgs.append(m)
+    offsets = np.concatenate([np.zeros(8), poisson_arrivals(200.0, 4, seed=13)])
+    srv.run_trace(reqs, offsets, timeout=120)
+    assert latency_stats(reqs)["completed"] == 12
+    srv.close()
+
+    picks = [0, 2, 1, 11]                                 # two of each parameter set
+    oref = {}
+    for c, p in clients.items():
+        o, seed = orc[p], wl[p].seed_keys + 100 * c
+        s = o.keygen_secret(seed)
+        oref[c] = (o.keygen_public(seed, s), o.keygen_rotations(seed, s, plans[p].rotations), o.keygen_relin(seed, s),
+                   [o.bank_ntt(raw[p][li], L.k, ext=True) for li, L in enumerate(plans[p].layers)])
+
+    def oracle(i):
+        r = reqs[i]
+        o = orc[r.pset]
+        pk, okeys, rlk, banks = oref[r.client]
+        return o.forward(plans[r.pset], o.encrypt(pk, msgs[i], 9500 + i), banks, okeys, rlk)
+
+    with ThreadPoolExecutor(max_workers=4) as ex:      # the C oracle releases the interpreter lock
+        wants = list(ex.map(oracle, picks))
+    for i, want in zip(picks, wants):
+        assert np.array_equal(ctl.to_numpy_u64(reqs[i].out), want), (i, reqs[i].pset)
