@@ -29,23 +29,35 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 
 # MI355X figures used for the roofline: HBM3E 8 TB/s (published). The integer work runs on the
-# vector ALU: 256 CUs at 2.4 GHz, each issuing one 64-lane VALU instruction per clock at full rate.
+# vector ALU: 256 CUs at 2.4 GHz, each issuing one 64-lane VALU instruction per clock at full rate
+# (the unit-count figure); the rates each instruction class really issues at are measured by the
+# library's issue-rate probe (ctl_probe_valu) in every run and the ALU roof uses those.
 HBM_PEAK_GBS = 8000.0
 CUS, CLOCK_HZ, LANES_PER_CU_CLK = 256, 2.4e9, 64
 VALU_PEAK = CUS * CLOCK_HZ * LANES_PER_CU_CLK          # 39.3e12 lane-instructions / s
-# VALU lane-instructions per unit of algorithmic work. Residues modulo primes below 2^41 are
-# processed in exact FP64 arithmetic (full rate on gfx950), the others as 64-bit integers on the
-# 32-bit integer VALU (64-bit add/sub/compare = 2 instructions):
+# VALU lane-operations per unit of algorithmic work, by instruction class (add32: full-rate 32-bit
+# integer and logic ops, mul32: v_mul_lo/hi_u32, mad64: v_mad_u64_u32, fma64: FP64 ops). Residues
+# modulo primes below 2^41 are processed in exact FP64 arithmetic, the others as 64-bit integers on
+# the 32-bit integer VALU (64-bit add/sub/compare = 2 instructions):
 #   NTT butterfly, FP64: product y w (mul, fma for the exact low part, mul by 1/q, rint, fma) 5
-#     + x + t + x - t 2 ... + 1 for the sum of the product's two parts                  = 8
-#   NTT butterfly, integer (Harvey, Shoup product by the twiddle): Shoup product 16 (high half
-#     of x w': 1 mul_hi + 3 mad_u64_u32 + 1 add; low halves of x w and h q: 2 x (1 mad + 2 mul_lo
-#     + 1 add); subtract 2) + lazy correction 5 + add 2 + subtract with offset 4              = 27
-#   multiply-accumulate, FP64: exact product 6 + accumulate 1                              = 7
-#   multiply-accumulate, integer, into a 128-bit sum: 64x64->128 product 7 + 128-bit add 4 = 11
-SLOTS_BFLY = {"fp": 8, "int": 27}
-SLOTS_MAC = {"fp": 7, "int": 11}
+#     + x + t, x - t 2 + 1 for the sum of the product's two parts                      = 8 fma64
+#   NTT butterfly, integer (Harvey, Shoup product by the twiddle): high half of x w' 1 mul_hi
+#     + 3 mad + 1 add; low halves of x w and h q 2 x (1 mad + 2 mul_lo + 1 add); subtract 2;
+#     lazy correction 5, add 2, subtract with offset 4               = 5 mad64 + 5 mul32 + 17 add32
+#   product in the FP64 MAC and key product: exact product 5 + accumulate 1, plus the final
+#     conversion of each sum spread over its terms                                     = 7 fma64
+#   product in the integer MAC (30-bit limbs): 4 v_mad_u64_u32 into column sums, + the operand
+#     split and column normalization spread over the terms                    = 4 mad64 + 1 add32
+#   product in the integer key product (30-bit limbs): 4 mad64, + the reduction of each sum
+#     (carries, a Shoup product by 2^60 mod q, two conditional subtracts) spread over its K = 4..6
+#     terms                                                                  = 4.7 mad64 + 3.5 add32
+UNIT_OPS = {
+    "bfly": {"fp": {"fma64": 8}, "int": {"mad64": 5, "mul32": 5, "add32": 17}},
+    "mac": {"fp": {"fma64": 7}, "int": {"mad64": 4, "add32": 1}},
+    "keyip": {"fp": {"fma64": 7}, "int": {"mad64": 4.7, "add32": 3.5}},
+}
 NTT_FAMILIES = ("k_ntt_fwd", "k_ntt_inv", "k_modup", "k_drop", "k_int_ntt")
+MAC_FAMILIES = ("k_mac", "k_mac_fp", "k_mac_direct", "k_tensor")
 
 
 def _percentile(xs, p):
@@ -60,8 +72,9 @@ def _src_digest():
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str, digest: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if taken on this source."""
+def _traffic(kernel: str, site: str, digest: str):
+    """HBM bytes per launch of a kernel instance from the committed rocprofv3 counter summary, if
+    it was taken on this source."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         rec = json.load(open(path))
@@ -69,7 +82,7 @@ def _traffic(kernel: str, digest: str):
         return None
     if rec.get("source_digest") != digest:
         return None
-    k = rec.get("kernels", {}).get(kernel)
+    k = rec.get("instances", {}).get("%s @ %s" % (kernel, site))
     if not k:
         return None
     return k.get("bytes_per_launch")
@@ -135,6 +148,88 @@ def cpu_baseline(pool, workers: int):
                       "bank encoding and encryption excluded)" % (workers, _ORACLE_VARIANT, t1 - t0)}
 
 
+def valu_rates(c):
+    """Measured lane-operations per second of each instruction class (the library's probe)."""
+    return {k: c.probe_valu(k) for k in ("add32", "mul32", "mad64", "fma64")}
+
+
+def _alu_ops(family: str, work: float, fp_work: float, n: int):
+    """Model lane-operations of a launch by instruction class ({class: ops})."""
+    if family in NTT_FAMILIES:
+        units, model = (n // 2) * int(math.log2(n)), UNIT_OPS["bfly"]
+    elif family in MAC_FAMILIES:
+        units, model = 1, UNIT_OPS["mac"]
+    elif family == "k_keyip":
+        units, model = 1, UNIT_OPS["keyip"]
+    else:
+        return {}
+    ops = {}
+    for part, w in (("fp", fp_work), ("int", work - fp_work)):
+        for cls, per in model[part].items():
+            ops[cls] = ops.get(cls, 0.0) + per * w * units
+    return ops
+
+
+def _alg_bytes(family: str, work: float, model_bytes: float, n: int) -> float:
+    """Algorithmic HBM bytes of a launch: the library's model (key product, MAC), one read and one
+    write of a residue per transform (NTT-bearing kernels), else 0 (not modelled)."""
+    if model_bytes:
+        return model_bytes
+    if family in NTT_FAMILIES:
+        return 16.0 * n * work
+    return 0.0
+
+
+def instances(launches, steps: int, n: int, rates):
+    """Per kernel instance (family, layer, phase, work per launch) per step: time, algorithmic bytes,
+    model ALU operations, and the HBM and ALU fractions of its roofs (ALU roof: every class at its
+    measured rate)."""
+    groups = {}
+    for r in launches:
+        key = (r["family"], r["layer"], r["phase"], r["work"])
+        g = groups.setdefault(key, {"launches": 0, "ms": 0.0, "fp_work": 0.0, "bytes": 0.0})
+        g["launches"] += 1
+        g["ms"] += r["ms"]
+        g["fp_work"] += r["fp_work"]
+        g["bytes"] += r["bytes"]
+    out = []
+    for (fam, layer, phase, work), g in groups.items():
+        cnt = g["launches"]
+        avg_s = g["ms"] / cnt * 1e-3
+        fpw = g["fp_work"] / cnt
+        alg = _alg_bytes(fam, work, g["bytes"] / cnt, n)
+        ops = _alu_ops(fam, work, fpw, n)
+        alu_s = sum(v / rates[k] for k, v in ops.items()) if ops else 0.0
+        tot_ops = sum(ops.values())
+        site = ("layer %d " % layer if layer >= 0 else "") + (phase or "")
+        out.append({"kernel": fam, "site": site.strip(), "launches_per_step": cnt / steps,
+                    "ms_per_step": round(g["ms"] / steps, 4), "avg_launch_ms": round(g["ms"] / cnt, 4),
+                    "work_per_launch": work, "fp64_share": round(fpw / work, 3) if work else 0.0,
+                    "alg_bytes_per_launch": alg, "hbm_gbs": round(alg / avg_s / 1e9, 1) if avg_s else 0.0,
+                    "hbm_frac": round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4) if avg_s else 0.0,
+                    "alu_ops_per_launch": tot_ops, "alu_tops": round(tot_ops / avg_s / 1e12, 3) if avg_s else 0.0,
+                    "alu_frac": round(alu_s / avg_s, 4) if avg_s else 0.0})
+    out.sort(key=lambda x: -x["ms_per_step"])
+    return out
+
+
+def roofline_of(inst, traffic):
+    """The roofline object of one kernel instance: the binding roof is the one whose model time is
+    the larger (HBM at 8 TB/s on its algorithmic bytes; ALU at the measured class rates)."""
+    if inst["hbm_frac"] >= inst["alu_frac"]:
+        bound, achieved, peak, unit = "hbm", inst["hbm_gbs"], HBM_PEAK_GBS, "GB/s"
+    else:
+        # achieved model lane-ops per second against the rate they would run at on the measured
+        # class peaks (peak = achieved / alu_frac)
+        bound, achieved, unit = "alu", inst["alu_tops"], "T VALU lane-ops/s"
+        peak = round(inst["alu_tops"] / inst["alu_frac"], 3) if inst["alu_frac"] else None
+    return {"bound": bound, "kernel": inst["kernel"], "site": inst["site"], "achieved": achieved, "peak": peak,
+            "unit": unit, "frac": round(max(inst["hbm_frac"], inst["alu_frac"]), 4), "traffic": traffic,
+            "avg_launch_ms": inst["avg_launch_ms"], "alg_bytes_per_launch": inst["alg_bytes_per_launch"],
+            "hbm_gbs": inst["hbm_gbs"], "hbm_frac": inst["hbm_frac"], "alu_tops": inst["alu_tops"],
+            "alu_frac": inst["alu_frac"]}
+
+
 VARIANTS = ("qp", "lazy", "per-step")
 
 
@@ -152,7 +247,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16,
                     help="oracle worker processes for the CPU leg, one ciphertext each, capped at the host's "
                          "cores (0: skip)")
-    ap.add_argument("--no-profile", action="store_true", help="do not bracket launches with events")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the instrumented pass (launches bracketed with events) after the timed region")
     ap.add_argument("--variant", choices=VARIANTS, default="qp",
                     help="dense-layer variant: baby steps kept over Q*P with one ModDown per giant step "
                          "(qp), single-ModDown giant steps (lazy) or one ModDown per rotation (per-step); "
@@ -167,10 +263,16 @@ def main():
     ap.add_argument("--paper-stack", type=int, default=1,
                     help="also time the paper's frozen CNN stack (Conv1D, Dense+ReLU approx., AvgPool, "
                          "Dense) at CryptoTL_p1 and _p2 and report it beside the headline (0: skip)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
-                    help="serving sweep: seconds of Poisson arrivals per rate (0: skip the sweep)")
-    ap.add_argument("--serve-rates", default="10,100,500,1000,2000", help="serving sweep: arrival rates, q/s")
-    ap.add_argument("--mix-queries", type=int, default=512)
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="serving sweep: seconds of Poisson arrivals per rate, unless --serve-queries come "
+                         "sooner (0: skip the sweep)")
+    ap.add_argument("--serve-queries", type=int, default=5000,
+                    help="serving sweep: queries per rate, unless --serve-seconds of arrivals come sooner")
+    ap.add_argument("--serve-rates", default="10,20,50,100,200,500,1000,2000",
+                    help="serving sweep: arrival rates, q/s")
+    ap.add_argument("--mix-queries", type=int, default=512,
+                    help="batched mix: queries per pass (0: leave the mix out of the default line)")
+    ap.add_argument("--mix-steps", type=int, default=3, help="batched mix: timed passes in the default line")
     ap.add_argument("--graphs", action="store_true", help="mix: replay captured HIP graphs of the dense calls")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB once (a kernel of known "
@@ -226,8 +328,7 @@ def main():
                   "tuned_ms": round(tuning["best_ms"], 3), "trials": tuning["trials"]}
 
     # ---------------------------------------------------------------- timed region (batched)
-    if not args.no_profile:
-        c.profile_enable(True)
+    # no instrumentation here: the kernel breakdown comes from a separate pass below
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -238,10 +339,18 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     step_ms = [ev[s].elapsed_time(ev[s + 1]) for s in range(args.steps)]
-    prof = c.profile_read() if not args.no_profile else {}
-    prof_bytes = c.profile_bytes() if not args.no_profile else {}
-    c.profile_enable(False)
     value = B * args.steps / elapsed
+
+    # ---------------------------------------------------------------- instrumented pass: per-launch events
+    prof, prof_bytes, launches = {}, {}, []
+    if not args.no_profile:
+        c.profile_enable(True)
+        for _ in range(args.steps):
+            c.forward(model, keys, ct, out=out)
+        torch.cuda.synchronize()
+        prof, prof_bytes, launches = c.profile_read(), c.profile_bytes(), c.profile_launches()
+        c.profile_enable(False)
+    rates = valu_rates(c)
 
     if args.copy_calibration_mib > 0:
         words = args.copy_calibration_mib * (1 << 20) // 8
@@ -297,6 +406,21 @@ def main():
         plain_ms = [pev[s].elapsed_time(pev[s + 1]) for s in range(args.plain_steps)]
         plain = {"value": round(args.plain_steps / plain_elapsed, 3), "unit": "encrypted forward passes/s",
                  "p50_ms": _percentile(plain_ms, 50), "p99_ms": _percentile(plain_ms, 99)}
+        if not args.no_profile:               # where one ciphertext's time goes (instrumented pass)
+            c.profile_enable(True)
+            for _ in range(3):
+                c.forward(model, keys, one, out=one_out)
+            torch.cuda.synchronize()
+            pl = c.profile_launches()
+            c.profile_enable(False)
+            by_fam = {}
+            for r in pl:
+                f = by_fam.setdefault(r["family"], [0, 0.0])
+                f[0] += 1
+                f[1] += r["ms"]
+            plain["kernels"] = {f: {"launches": v[0] / 3, "ms": round(v[1] / 3, 4)}
+                                for f, v in sorted(by_fam.items(), key=lambda x: -x[1][1])}
+            plain["launches"] = len(pl) / 3
         # the same single-ciphertext pass replayed from a captured graph (the library's launch
         # sequence with the host's per-launch work removed); the workspace is frozen meanwhile so
         # that nothing is allocated under capture, and every replay must equal the eager result
@@ -347,50 +471,22 @@ def main():
     total_ms = sum(v[1] for v in prof.values()) or 1.0
     for name, (cnt, ms, work, fpw) in prof.items():
         if cnt:
-            kernels[name] = {"launches": cnt, "ms": round(ms, 3), "share": round(ms / total_ms, 4),
+            kernels[name] = {"launches": cnt, "ms_per_step": round(ms / args.steps, 3), "share": round(ms / total_ms, 4),
                              "avg_ms": round(ms / cnt, 4), "work": work, "fp64_share": round(fpw / work, 3)}
-    logn = int(math.log2(n))
-    butterflies_per_ntt = (n // 2) * logn
     ntt_res = sum(prof[f][2] for f in NTT_FAMILIES if f in prof)
     ntt_time = sum(prof[f][1] for f in NTT_FAMILIES if f in prof)
     ntt_gbs_fwd = 16.0 * n * ntt_res / (ntt_time * 1e-3) / 1e9 if ntt_time else None
+    digest = _src_digest()
+    inst = instances(launches, args.steps, n, rates) if launches else []
     roofline = None
-    if kernels:
-        dom = max(kernels, key=lambda k: kernels[k]["ms"])
-        cnt, ms, work, fpw = prof[dom]
-        avg_s = ms / cnt * 1e-3
-        if dom in NTT_FAMILIES:
-            slots = (fpw * SLOTS_BFLY["fp"] + (work - fpw) * SLOTS_BFLY["int"]) / cnt * butterflies_per_ntt
-            alg_bytes = work / cnt * 16.0 * n
-            ops = "NTT butterflies x (%d FP64 | %d integer) VALU lane-instructions" % (SLOTS_BFLY["fp"], SLOTS_BFLY["int"])
-        elif dom in ("k_mac", "k_mac_fp", "k_mac_direct", "k_keyip", "k_tensor"):
-            slots = (fpw * SLOTS_MAC["fp"] + (work - fpw) * SLOTS_MAC["int"]) / cnt
-            # the library's per-launch model: digits, keys, outputs (key product); ciphertexts,
-            # rotations, bank, outputs (MAC); see ctl_profile_read_bytes
-            alg_bytes = prof_bytes.get(dom, 0.0) / cnt or None
-            ops = "modular multiply-accumulates x (%d FP64 | %d integer) VALU lane-instructions" % (
-                SLOTS_MAC["fp"], SLOTS_MAC["int"])
-        else:
-            slots, alg_bytes, ops = 0.0, work / cnt * 16.0, "residue words"
-        digest = _src_digest()
-        alu = slots / avg_s / 1e12
-        alu_peak = VALU_PEAK / 1e12
-        hbm = alg_bytes / avg_s / 1e9 if alg_bytes else 0.0
-        # the binding roofline is the one the kernel is closer to: its time at that peak is the
-        # larger of the two model times
-        if hbm / HBM_PEAK_GBS > alu / alu_peak:
-            bound, achieved, peak, unit = "hbm", hbm, HBM_PEAK_GBS, "GB/s"
-        else:
-            bound, achieved, peak, unit = "alu", alu, alu_peak, "T VALU-lane-instr/s"
-        roofline = {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": round(peak, 2),
-                    "unit": unit, "frac": round(achieved / peak, 4),
-                    "traffic": _traffic(dom, digest), "avg_launch_ms": round(ms / cnt, 4),
-                    "work_per_launch": work / cnt, "ops": ops, "source_digest": digest,
-                    "alu_achieved": round(alu, 3), "alu_frac": round(alu / alu_peak, 4)}
-        if alg_bytes:
-            roofline["alg_bytes_per_launch"] = alg_bytes
-            roofline["hbm_gbs"] = round(hbm, 1)
-            roofline["hbm_frac"] = round(hbm / HBM_PEAK_GBS, 4)
+    if inst:
+        top = inst[0]
+        roofline = roofline_of(top, _traffic(top["kernel"], top["site"], digest))
+        roofline["source_digest"] = digest
+        roofline["valu_rates_tops"] = {k: round(v / 1e12, 2) for k, v in rates.items()}
+        roofline["valu_peak_unit_count_tops"] = round(VALU_PEAK / 1e12, 2)
+        roofline["top_instances"] = [{k: i[k] for k in ("kernel", "site", "ms_per_step", "avg_launch_ms", "hbm_frac",
+                                                        "alu_frac", "hbm_gbs", "alu_tops")} for i in inst[:4]]
 
     line = {
         "metric": "encrypted fwd passes/sec at N=2^14 (batched vs plain) + NTT GB/s; p50/p99",
@@ -418,13 +514,19 @@ def main():
                     "bytes_per_ntt": 16 * n},
         "decrypt_check_rel_err": rel_err,
         "kernels": kernels,
+        "instances": inst,
         "roofline": roofline,
         "setup_s": round(setup_s, 2),
         "workspace_gib": round(c.workspace_bytes() / 2 ** 30, 2),
     }
-    if args.serve_seconds > 0 or args.paper_stack:
+    if args.serve_seconds > 0 or args.paper_stack or args.mix_queries > 0:
         del c, model, others, keys, ct, out, one, one_out, buf
         import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+    if args.mix_queries > 0:
+        line["mix"] = mix_measure(args.mix_steps, args.mix_queries)
+        print("mix: %s" % json.dumps(line["mix"]), file=sys.stderr, flush=True)
         gc.collect()
         torch.cuda.empty_cache()
     if args.serve_seconds > 0:
@@ -481,7 +583,8 @@ def serving_sweep(args):
     sweep = []
     rid = 0
     for rate in [float(r) for r in args.serve_rates.split(",")]:
-        n = int(min(max(rate * args.serve_seconds, 50), 4 * rate * args.serve_seconds))
+        # at least serve_seconds of arrivals or serve_queries queries, whichever comes first
+        n = max(1, int(min(args.serve_queries, round(rate * args.serve_seconds))))
         offs = poisson_arrivals(rate, n, seed=int(rate))
         reqs = []
         for i in range(n):
@@ -492,17 +595,24 @@ def serving_sweep(args):
         wall = srv.run_trace(reqs, offs, timeout=300)
         st = latency_stats(reqs)
         per = {p: latency_stats([r for r in reqs if r.pset == p]) for p in wl}
-        sweep.append({"rate_qps": rate, "queries": n, "wall_s": round(wall, 3),
-                      "throughput_qps": round(st["throughput_qps"], 1),
+        sweep.append({"rate_qps": rate, "queries": n, "arrival_span_s": round(float(offs[-1]), 2),
+                      "wall_s": round(wall, 3), "throughput_qps": round(st["throughput_qps"], 1),
                       "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                      "p99_samples": st["completed"],
                       "mean_batch": round(st["mean_batch"], 2), "rejected": st["rejected"],
-                      "p99_ms_by_set": {p: round(per[p]["p99_ms"], 3) for p in per if per[p]["completed"]}})
+                      "by_set": {p: {"p50_ms": round(per[p]["p50_ms"], 3), "p99_ms": round(per[p]["p99_ms"], 3),
+                                     "samples": per[p]["completed"]} for p in per if per[p]["completed"]}})
         print("serving rate %.0f q/s: %s" % (rate, json.dumps(sweep[-1])), file=sys.stderr, flush=True)
     srv.close()
+    # the first offered rate the loop does not keep up with (throughput below 95% of it)
+    knee = next((p["rate_qps"] for p in sweep if p["throughput_qps"] < 0.95 * p["rate_qps"]), None)
     return {"workload": "Poisson arrivals, 80% mid (N=2^13, 512->128->128) / 20% large (N=2^14, "
                         "768->256->64), 4 clients per set, keys resident, 2 lanes per set, batches of up to 64 "
                         "of the oldest queries across clients",
-            "sweep": sweep, "key_bytes": key_budget, "setup_s": round(setup_s, 2)}
+            "per_rate": "min(%d queries, %g s of arrivals)" % (args.serve_queries, args.serve_seconds),
+            "sweep": sweep, "saturation_qps": knee if knee is not None else "above %g q/s (the highest rate swept)"
+            % max(p["rate_qps"] for p in sweep),
+            "key_bytes": key_budget, "setup_s": round(setup_s, 2)}
 
 
 PAPER_KB = {"cnn_p1": [235.3, 82.4], "cnn_p2": [838.1, 262.3]}
@@ -586,9 +696,6 @@ def bench_cnn(args):
 
 
 def bench_serve(args):
-    if args.serve_rates == "10,100,500,1000,2000":       # the full sweep of the serving workload
-        args.serve_rates = "10,20,50,100,200,500,1000,2000"
-        args.serve_seconds = max(args.serve_seconds, 5.0)
     sv = serving_sweep(args)
     top = sv["sweep"][-1]
     line = {"metric": "p50/p99 latency and throughput of the serving loop under Poisson load",
@@ -599,19 +706,21 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
-def bench_mix(args):
-    """Throughput of the batched mix: queries of 1-3 dense layers with widths drawn from
-    {128,256,512,768}, evaluated position by position with banks shared per shape."""
+def mix_measure(steps: int, n_queries: int, graphs: bool = False):
+    """The batched mix: queries of 1-3 dense layers with widths drawn from {128,256,512,768},
+    evaluated position by position with banks shared per shape. Throughput over `steps` passes of
+    the whole batch, and per-query latency within a pass (from the pass's start to the event
+    recorded after the dense group that finishes the query)."""
     import torch
     import paper_2205_11935_amd as ctl
     from paper_2205_11935_amd.batch_mix import MixEngine
     w = W.LARGE
     c = ctl.Context.for_workload(w)
-    queries = W.mix_queries(args.mix_queries)
+    queries = W.mix_queries(n_queries)
     t0 = time.perf_counter()
     keys = c.keygen(w.seed_keys, MixEngine.rotations(queries, W.MIX_T1), relin=True)
     eng = MixEngine(c, keys, lambda p, a, b, t: W.mix_weights(p, a, b), W.MIX_T1, W.MIX_BLOCK, lazy=True,
-                    graphs=args.graphs)
+                    graphs=graphs)
     items = (c.n // 2) // W.MIX_BLOCK
     xs = W.mix_inputs(queries, items)
     dev = c.empty_ct(len(queries), c.nq)
@@ -623,25 +732,41 @@ def bench_mix(args):
     setup_s = time.perf_counter() - t0
     eng.run(dev, queries)
     torch.cuda.synchronize()
-    if args.graphs:
+    if graphs:
         eng.freeze()
         eng.run(dev, queries)               # capture
         torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         eng.run(dev, queries)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # one more pass with a completion event per query
+    start, done = torch.cuda.Event(enable_timing=True), [None] * len(queries)
+    start.record()
+    eng.run(dev, queries, done_events=done)
+    torch.cuda.synchronize()
+    lat = [start.elapsed_time(e) for e in done]
+    if graphs:
+        c.workspace_freeze(False)
     depth_hist = {d: sum(1 for q in queries if q.depth == d) for d in (1, 2, 3)}
+    return {"workload": "mix: %d queries, 1-3 dense layers, widths from {128,256,512,768}, N=2^14, "
+                        "block 1536 (5 items per ciphertext)" % len(queries),
+            "queries": len(queries), "steps": steps, "value": round(len(queries) * steps / dt, 3),
+            "unit": "encrypted forward passes/s", "ms_per_pass": round(dt / steps * 1e3, 3),
+            "query_latency_ms": {"p50": _percentile(lat, 50), "p99": _percentile(lat, 99), "max": max(lat)},
+            "depths": depth_hist, "banks": len(eng.models), "graphs": bool(graphs), "setup_s": round(setup_s, 2)}
+
+
+def bench_mix(args):
+    mx = mix_measure(args.steps, args.mix_queries, graphs=args.graphs)
     line = {
         "metric": "encrypted fwd passes/sec at N=2^14, batched mix of layer widths and depths",
-        "value": round(len(queries) * args.steps / dt, 3), "unit": "encrypted forward passes/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "value": mx["value"], "unit": mx["unit"],
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": mx["ms_per_pass"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "mix: %d queries, 1-3 dense layers, widths from {128,256,512,768}, N=2^14, "
-                               "block 1536 (5 items per ciphertext)" % len(queries),
-                   "depths": depth_hist, "banks": len(eng.models), "graphs": bool(args.graphs)},
-        "setup_s": round(setup_s, 2),
+        "config": {"workload": mx["workload"], "depths": mx["depths"], "banks": mx["banks"], "graphs": mx["graphs"]},
+        "mix": mx,
     }
     print(json.dumps(line), flush=True)
 

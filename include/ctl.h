@@ -28,8 +28,12 @@
  *     share its workspace and race.
  *   - Key and model handles may be used with any context of identical parameters on the same
  *     device (several contexts, one per stream, can serve one parameter set with shared keys and
- *     banks); a handle from a context of other parameters is rejected with CTL_EINVAL. The
- *     context a handle was made on must outlive it.
+ *     banks); a handle from a context of other parameters is rejected with CTL_EINVAL.
+ *   - ctl_ctx_free may come before the frees of handles made on that context, in any order: it
+ *     releases the context's workspace at once, and the context's tables go with the last of its
+ *     handles. Its allocator hook (ctl_set_allocator) must stay callable until then, since
+ *     freeing those handles returns their device memory through it. A context may not be used
+ *     after ctl_ctx_free; its handles may, with other contexts of identical parameters.
  *
  * Readings of what the paper leaves open (prime choice, NTT order, slot order, sampling, key
  * switching variant, rounding) are listed in the design notes; the integer results of every
@@ -196,6 +200,27 @@ int ctl_profile_read(ctl_ctx *ctx, int family, int *launches_out, double *total_
  * the MAC families: ciphertext and rotated-ciphertext words once, plaintext-bank words once,
  * output words); 0 for the others. No synchronization. */
 int ctl_profile_read_bytes(ctl_ctx *ctx, int family, double *bytes_out);
+
+/* Launch records since profiling was enabled, in launch order: *n_out of them. Record i gives the
+ * kernel family, its duration in milliseconds (synchronizes its stop event), algorithmic work and
+ * the part on FP64 primes (as ctl_profile_read), algorithmic HBM bytes (as ctl_profile_read_bytes,
+ * 0 where not modelled) and the call site: the layer of the model (-1 outside a model's forward
+ * pass) and the phase within it ("baby steps", "mac", "giant steps", "moddown", "rescale",
+ * "square", "cubic", "replicate"; "" elsewhere; a static string). */
+int ctl_profile_launches(ctl_ctx *ctx, int *n_out);
+int ctl_profile_launch(ctl_ctx *ctx, int i, int *family_out, double *ms_out, double *work_out, double *fp_work_out,
+                       double *bytes_out, int *layer_out, const char **phase_out);
+
+/* Issue-rate probe of the vector ALU, for rooflines: a kernel of `iters` iterations of independent
+ * chains of one instruction class runs on every CU (enough waves to fill them) and
+ * *lane_ops_out receives lane-operations per second measured with HIP events on `stream`
+ * (synchronizes it). kind: 0 = 32-bit integer add, 1 = 32-bit multiply (low half), 2 = 32 x 32 + 64
+ * -> 64-bit multiply-add (v_mad_u64_u32), 3 = FP64 fused multiply-add. */
+#define CTL_PROBE_ADD32 0
+#define CTL_PROBE_MUL32 1
+#define CTL_PROBE_MAD64 2
+#define CTL_PROBE_FMA64 3
+int ctl_probe_valu(ctl_ctx *ctx, int kind, int iters, double *lane_ops_out, void *stream);
 
 /* ------------------------------------------------------------------ keys (client side) */
 typedef struct ctl_sk ctl_sk;
@@ -417,6 +442,20 @@ int ctl_forward_multi(ctl_ctx *ctx, const ctl_model *model, const ctl_evk *const
  * ctl_forward inserts is not part of this call). in: k = ctl_model_info.layer_k; out: k - 1. */
 int ctl_dense(ctl_ctx *ctx, const ctl_model *model, int layer, const ctl_evk *evk,
               const uint64_t *in, uint64_t *out, int n_ct, void *stream);
+
+/* Dense layers of several models over one batch grouped by model (queries whose layers have
+ * different widths, evaluated together): group g is counts[g] consecutive ciphertexts of `in`
+ * (n_ct = the sum of counts), evaluated by layer `layer` of models[g] exactly as ctl_dense of that
+ * model and layer alone would, bit for bit. Every such layer must keep its baby steps over Q*P
+ * (CTL_LAYER_BABY_QP; else CTL_EINVAL) and start at the same level k (else CTL_ELEVEL); the
+ * models may differ in width, t1 and t2 but must share one slot layout to be useful together.
+ * The hoisted ModUp of every ciphertext (Eq. (1)'s baby steps), the ModUp of every giant step's
+ * operand, the final ModDown and the rescale each run once over the whole batch; the key
+ * products, the plaintext products and the giant-step sums run per group. models, counts: host
+ * arrays of n_groups entries (1..4096). in: [n_ct][2][k][N]; out: [n_ct][2][k-1][N]. A missing
+ * Galois key of any group gives CTL_EKEY before anything is enqueued. */
+int ctl_dense_groups(ctl_ctx *ctx, const ctl_model *const *models, const int *counts, int n_groups, int layer,
+                     const ctl_evk *evk, const uint64_t *in, uint64_t *out, void *stream);
 
 /* Product of two ciphertexts at k primes: tensor, relinearization, rescale. k -> k - 1. */
 int ctl_mul(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *a, const uint64_t *b, uint64_t *out,

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import os
+import weakref
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
@@ -130,6 +131,13 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
     "ctl_profile_read_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "ctl_profile_launches": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
+    "ctl_profile_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_char_p)]),
+    "ctl_probe_valu": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.c_void_p]),
     "ctl_keygen": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, i32p, ctypes.c_int, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_void_p)]),
@@ -179,6 +187,9 @@ _SIGS = {
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "ctl_dense": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_dense_groups": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int),
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
     "ctl_square": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "ctl_mul": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
@@ -312,6 +323,7 @@ class ModelInfo:
 class Keys:
     def __init__(self, ctx: "Context", sk, pk, evk):
         self.ctx, self.sk, self.pk, self.evk = ctx, sk, pk, evk
+        ctx._handles.add(self)
 
     def secret(self) -> np.ndarray:
         s = np.zeros(self.ctx.n, dtype=np.int64)
@@ -344,17 +356,23 @@ class Keys:
         _check(lib().ctl_evk_bytes(self.evk, ctypes.byref(b)))
         return int(b.value)
 
-    def __del__(self):
+    def free(self):
+        """Release the key handles (also done by the context's close(): a handle must not outlive
+        the context it was made on)."""
         if _LIB is not None:
             for f, h in (("ctl_sk_free", self.sk), ("ctl_pk_free", self.pk), ("ctl_evk_free", self.evk)):
                 if h:
                     getattr(_LIB, f)(h)
-            self.sk = self.pk = self.evk = None
+        self.sk = self.pk = self.evk = None
+
+    def __del__(self):
+        self.free()
 
 
 class Model:
     def __init__(self, ctx: "Context", handle):
         self.ctx, self.handle = ctx, handle
+        ctx._handles.add(self)
         info = _ModelInfo()
         _check(lib().ctl_model_get_info(handle, ctypes.byref(info)))
         rots = (ctypes.c_int32 * max(info.n_rotations, 1))()
@@ -369,10 +387,14 @@ class Model:
         _check(lib().ctl_model_bytes(self.handle, ctypes.byref(b)))
         return int(b.value)
 
-    def __del__(self):
+    def free(self):
+        """Release the plaintext banks (also done by the context's close())."""
         if _LIB is not None and self.handle:
             _LIB.ctl_model_free(self.handle)
-            self.handle = None
+        self.handle = None
+
+    def __del__(self):
+        self.free()
 
 
 class Context:
@@ -382,6 +404,7 @@ class Context:
                  device: int = 0, torch_allocator: bool = True):
         import torch
         self._torch = torch
+        self._handles = weakref.WeakSet()          # keys and models made on this context
         self.log2n, self.n, self.nq = log2n, 1 << log2n, len(q_bits)
         self.device = device
         self.scale = float(2.0 ** log2_scale)
@@ -410,13 +433,26 @@ class Context:
         _check(lib().ctl_ctx_primes(self.handle, pr, ctypes.byref(n)))
         self.primes = [int(pr[i]) for i in range(n.value)]
 
+    def set_allocator(self, alloc, free):
+        """Install a device allocator for the context's workspace, keys and banks (before anything
+        is allocated): alloc(nbytes, stream, user) -> device pointer or None (the library then
+        fails with CTL_ENOMEM), free(ptr, stream, user). The ctypes thunks are kept on the context,
+        so they live as long as it and the handles made on it do."""
+        hooks = (_ALLOC_FN(alloc), _FREE_FN(free))
+        _check(lib().ctl_set_allocator(self.handle, hooks[0], hooks[1], None))
+        self._hooks = hooks
+
     @classmethod
     def for_workload(cls, w, **kw) -> "Context":
         return cls(w.log2n, w.q_bits, w.p_bits, w.log2_scale, w.sigma, **kw)
 
     def close(self):
+        """Free the context, after the keys and models made on it (which may still be referenced,
+        e.g. from a traceback; they become empty)."""
         if getattr(self, "handle", None):
             self._torch.cuda.synchronize()
+            for h in list(self._handles):
+                h.free()
             lib().ctl_ctx_free(self.handle)
             self.handle = None
 
@@ -472,6 +508,31 @@ class Context:
             _check(lib().ctl_profile_read_bytes(self.handle, f, ctypes.byref(b)))
             out[lib().ctl_profile_family_name(f).decode()] = b.value
         return out
+
+    def profile_launches(self):
+        """Every launch record since profiling was enabled, in launch order: dicts with the
+        kernel family, milliseconds, work, FP64 work, algorithmic bytes, layer and phase."""
+        n = ctypes.c_int()
+        _check(lib().ctl_profile_launches(self.handle, ctypes.byref(n)))
+        names = [lib().ctl_profile_family_name(f).decode() for f in range(lib().ctl_profile_families())]
+        out = []
+        for i in range(n.value):
+            fam, layer = ctypes.c_int(), ctypes.c_int()
+            ms, wk, fw, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            ph = ctypes.c_char_p()
+            _check(lib().ctl_profile_launch(self.handle, i, ctypes.byref(fam), ctypes.byref(ms), ctypes.byref(wk),
+                                            ctypes.byref(fw), ctypes.byref(by), ctypes.byref(layer), ctypes.byref(ph)))
+            out.append({"family": names[fam.value], "ms": ms.value, "work": wk.value, "fp_work": fw.value,
+                        "bytes": by.value, "layer": layer.value, "phase": (ph.value or b"").decode()})
+        return out
+
+    PROBES = {"add32": 0, "mul32": 1, "mad64": 2, "fma64": 3}
+
+    def probe_valu(self, kind: str, iters: int = 4096, stream=None) -> float:
+        """Measured vector-ALU lane operations per second of one instruction class (ctl_probe_valu)."""
+        v = ctypes.c_double()
+        _check(lib().ctl_probe_valu(self.handle, self.PROBES[kind], iters, ctypes.byref(v), _stream(stream)))
+        return v.value
 
     # ------------------------------------------------------------ parity hook
     def ntt(self, buf, prime_idx: Sequence[int], inverse: bool = False, stream=None):
@@ -713,6 +774,26 @@ class Context:
         po = self._dev(out, (n_ct, 2, k - 1, self.n), "dense output")
         check_disjoint(ct, out, "dense")
         _check(lib().ctl_dense(self.handle, model.handle, layer, keys.evk, pi, po, n_ct, _stream(stream)))
+        return out
+
+    def dense_groups(self, models: Sequence[Model], counts: Sequence[int], keys: Keys, ct, layer: int = 0,
+                     out=None, stream=None):
+        """Layer `layer` of models[g] on counts[g] consecutive ciphertexts of ct, for every g, in
+        one call (ctl_dense_groups: the ModUps, the final ModDown and the rescale shared)."""
+        n_ct, _ = _batch_dims(ct, "dense_groups input")
+        if len(models) != len(counts) or not models:
+            raise ValueError("one count per model")
+        if sum(counts) != n_ct or min(counts) < 1:
+            raise ValueError("counts must be positive and add up to the batch (%d)" % n_ct)
+        k = models[0].info.layer_k[layer]
+        pi = self._dev(ct, (n_ct, 2, k, self.n), "dense_groups input")
+        if out is None:
+            out = self.empty_ct(n_ct, k - 1)
+        po = self._dev(out, (n_ct, 2, k - 1, self.n), "dense_groups output")
+        check_disjoint(ct, out, "dense_groups")
+        ms = (ctypes.c_void_p * len(models))(*[m.handle for m in models])
+        cs = (ctypes.c_int * len(counts))(*[int(x) for x in counts])
+        _check(lib().ctl_dense_groups(self.handle, ms, cs, len(models), layer, keys.evk, pi, po, _stream(stream)))
         return out
 
     def mul(self, keys: Keys, a, b, out=None, stream=None):

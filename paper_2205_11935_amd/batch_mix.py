@@ -4,11 +4,13 @@ Every query is one ciphertext of the same CKKS context. Layer l of a query with 
 (w_0..w_d) uses the dense layer (l, w_l, w_{l+1}) whose diagonal plaintext bank is shared by all
 queries with that shape: all queries use one slot layout (a fixed block stride) and layer l always
 runs at the same level, so a bank per (position, w_in, w_out) serves every query. The batch is
-evaluated position by position: the ciphertexts at a position are grouped by bank and each group
-is one batched dense call; the x^2 of every continuing query is one batched call; replicate is
-grouped by the next layer's padded width. With graphs=True each group's dense launch sequence is
-captured once into a HIP graph (on static buffers, after the workspace has reached its size and
-been frozen) and replayed.
+evaluated position by position: the ciphertexts at a position are ordered by bank and every bank's
+dense layer runs in one ctl_dense_groups call (one ModUp of every ciphertext, the giant steps'
+ModUp, ModDown and rescale shared by all widths; key products and plaintext products per bank);
+the x^2 of every continuing query is one batched call; replicate is grouped by the next layer's
+padded width. With graphs=True the whole chain of a position (dense groups, x^2, replicates) is
+captured once per shape signature into a HIP graph (on static buffers, after the workspace has
+reached its size and been frozen) and replayed.
 
 Orchestration only: every arithmetic step runs in the library's kernels.
 """
@@ -70,33 +72,70 @@ class MixEngine:
         self.c.workspace_freeze(True)
         self._frozen = True
 
-    def _dense(self, model: Model, x):
-        if not self.graphs or not self._frozen:
-            return self.c.dense(model, 0, self.keys, x)
+    def _chain(self, pos: int, models, counts, sq_rows, rep_widths):
+        """The work of one position on its input x ([n][2][k][N], rows in group order): every
+        group's dense layer in one ctl_dense_groups call, then x^2 of the rows that continue (in
+        the order of their next layer's width) and one replicate per width. Returns a function
+        x -> (dense output [n][2][k-1][N], next input [m][2][k-2][N] or None)."""
         torch = self.torch
-        key = (id(model), x.shape[0])
+        k = self.level(pos)
+        sel = torch.tensor(sq_rows, dtype=torch.int64, device="cuda:%d" % self.c.device) if sq_rows else None
+
+        def dense(x):
+            if self.qp:
+                return self.c.dense_groups(models, counts, self.keys, x)
+            y = self.c.empty_ct(x.shape[0], k - 1)          # other variants: one call per bank
+            r0 = 0
+            for m, cnt in zip(models, counts):
+                self.c.dense(m, 0, self.keys, x[r0:r0 + cnt], out=y[r0:r0 + cnt])
+                r0 += cnt
+            return y
+
+        def chain(x):
+            y = dense(x)
+            if sel is None:
+                return y, None
+            sq = self.c.square(self.keys, y.index_select(0, sel))
+            nxt = self.c.empty_ct(len(sq_rows), k - 2)
+            r0 = 0
+            for width, cnt in rep_widths:
+                self.c.replicate(self.keys, sq[r0:r0 + cnt], width, out=nxt[r0:r0 + cnt])
+                r0 += cnt
+            return y, nxt
+        # a captured graph's index_select reads `sel` at every replay: whoever keeps the graph must
+        # keep this tensor alive with it
+        chain.index = sel
+        return chain
+
+    def _run_position(self, pos: int, models, counts, sq_rows, rep_widths, x):
+        if not self.graphs or not self._frozen:
+            return self._chain(pos, models, counts, sq_rows, rep_widths)(x)
+        torch = self.torch
+        key = (pos, tuple(id(m) for m in models), tuple(counts), tuple(sq_rows), tuple(rep_widths))
         if key not in self._graphs:
+            chain = self._chain(pos, models, counts, sq_rows, rep_widths)
             sin = torch.empty_like(x)
-            sout = self.c.empty_ct(x.shape[0], x.shape[2] - 1)
             sin.copy_(x)
             torch.cuda.synchronize()
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
-                self.c.dense(model, 0, self.keys, sin, out=sout)
-            self._graphs[key] = (g, sin, sout)
-        g, sin, sout = self._graphs[key]
+                y, nxt = chain(sin)
+            # the chain (and its index tensor, read by the graph's gather at every replay) lives
+            # as long as the graph
+            self._graphs[key] = (g, sin, y, nxt, chain)
+        g, sin, y, nxt, _ = self._graphs[key]
         sin.copy_(x)
         g.replay()
-        return sout.clone()
+        return y.clone(), (nxt.clone() if nxt is not None else None)
 
     # ------------------------------------------------------------------ evaluation
-    def run(self, cts, queries: Sequence) -> List:
+    def run(self, cts, queries: Sequence, done_events: Optional[List] = None) -> List:
         """cts: [Q][2][n_q][N] top-level ciphertexts (query i in row i). Returns one [2][k][N]
-        tensor per query (k = n_q - 2 depth + 1)."""
+        tensor per query (k = n_q - 2 depth + 1). With done_events (a list of Q entries), entry i
+        receives a CUDA event recorded on the current stream once query i's last layer is done."""
         torch = self.torch
         Q = len(queries)
         out: List[Optional[object]] = [None] * Q
-        cur = {i: None for i in range(Q)}
         rows = cts
         idx_of = {i: i for i in range(Q)}       # row of query i in `rows`
         active = list(range(Q))
@@ -105,37 +144,33 @@ class MixEngine:
             if not act:
                 break
             k = self.level(pos)
-            dense_out = {}
             groups = collections.defaultdict(list)
             for i in act:
                 groups[(queries[i].widths[pos], queries[i].widths[pos + 1])].append(i)
-            for (w_in, w_out), members in sorted(groups.items()):
-                sel = torch.tensor([idx_of[i] for i in members], device=rows.device)
-                x = rows.index_select(0, sel)[:, :, :k].contiguous()
-                y = self._dense(self.model(pos, w_in, w_out), x)
-                for r, i in enumerate(members):
-                    dense_out[i] = y[r]
-            cont = [i for i in act if queries[i].depth > pos + 1]
-            for i in act:
-                if queries[i].depth == pos + 1:
-                    out[i] = dense_out[i]
-            if not cont:
-                break
-            sq_in = torch.stack([dense_out[i] for i in cont])
-            sq = self.c.square(self.keys, sq_in)
-            sq_row = {i: r for r, i in enumerate(cont)}
+            shapes = sorted(groups)
+            order = [i for sh in shapes for i in groups[sh]]                  # rows in group order
+            models = [self.model(pos, w_in, w_out) for (w_in, w_out) in shapes]
+            counts = [len(groups[sh]) for sh in shapes]
             rgroups = collections.defaultdict(list)
-            for i in cont:
-                rgroups[max(queries[i].widths[pos + 1], queries[i].widths[pos + 2])].append(i)
-            nxt = self.c.empty_ct(len(cont), k - 2)
-            new_idx = {}
-            r0 = 0
-            for width, members in sorted(rgroups.items()):
-                sel = torch.tensor([sq_row[i] for i in members], device=sq.device)
-                rep = self.c.replicate(self.keys, sq.index_select(0, sel).contiguous(), width)
-                nxt[r0:r0 + len(members)] = rep
-                for r, i in enumerate(members):
-                    new_idx[i] = r0 + r
-                r0 += len(members)
-            rows, idx_of, active = nxt, new_idx, cont
+            for i in order:
+                if queries[i].depth > pos + 1:
+                    rgroups[max(queries[i].widths[pos + 1], queries[i].widths[pos + 2])].append(i)
+            widths = sorted(rgroups)
+            rorder = [i for wd in widths for i in rgroups[wd]]               # continuing, by next width
+            at = {i: r for r, i in enumerate(order)}
+            sel = torch.tensor([idx_of[i] for i in order], device=rows.device)
+            x = rows.index_select(0, sel)[:, :, :k].contiguous()
+            y, nxt = self._run_position(pos, models, counts, [at[i] for i in rorder],
+                                        [(wd, len(rgroups[wd])) for wd in widths], x)
+            finished = [i for i in order if queries[i].depth == pos + 1]
+            if done_events is not None and finished:
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record()
+                for i in finished:
+                    done_events[i] = ev
+            for i in finished:
+                out[i] = y[at[i]]
+            if not rorder:
+                break
+            rows, idx_of, active = nxt, {i: r for r, i in enumerate(rorder)}, rorder
         return out

@@ -3,6 +3,7 @@
 // activation, replicate and rescale. Every arithmetic step runs in the HIP kernels; the host only
 // samples client randomness, encodes FP64 slot vectors and orders launches on the caller's stream.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -67,6 +68,10 @@ struct ctl_ctx {
     std::vector<PrimeConst> pc;
     bool ws_frozen = false;
     Knobs knobs;
+    // lifetime: one reference for the context itself and one per live key or model handle made
+    // on it; ctl_ctx_free drops the context's own (and releases the workspace at once), and the
+    // tables and this struct go when the last reference does, whatever the order of the frees
+    std::atomic<int> refs{1};
     // launch instrumentation
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;      // pairs (start, stop)
@@ -74,7 +79,11 @@ struct ctl_ctx {
     std::vector<double> prof_work;        // algorithmic work of each recorded launch
     std::vector<double> prof_fp;          // the part of it on FP64 primes
     std::vector<double> prof_bytes;       // algorithmic HBM bytes of each recorded launch (0: not modelled)
+    std::vector<int> prof_layer_v;        // call site of each record: layer of the model (-1: none)
+    std::vector<const char *> prof_phase_v;   // and phase of the layer (static strings)
     size_t prof_used = 0;
+    int prof_layer = -1;                  // the current call site
+    const char *prof_phase = "";
 };
 
 struct ctl_sk {
@@ -134,6 +143,15 @@ void dev_free(ctl_ctx *c, void *p, hipStream_t st) {
     else (void)hipFree(p);
 }
 
+// Handles made on a context keep it alive (see ctl_ctx::refs).
+void ctx_retain(ctl_ctx *c) { c->refs.fetch_add(1); }
+void ctx_release(ctl_ctx *c) {
+    if (c->refs.fetch_sub(1) != 1) return;
+    (void)hipSetDevice(c->device);
+    (void)hipFree(c->tables_mem);
+    delete c;
+}
+
 int slot(ctl_ctx *c, Slot s, size_t words, hipStream_t st, u64 **out) {
     const size_t bytes = std::max<size_t>(words * 8, 256);
     if (c->slot_bytes[s] < bytes) {
@@ -171,12 +189,16 @@ class Prof {
             c->prof_work.push_back(0.0);
             c->prof_fp.push_back(0.0);
             c->prof_bytes.push_back(0.0);
+            c->prof_layer_v.push_back(-1);
+            c->prof_phase_v.push_back("");
         }
         idx_ = c->prof_used++;
         c->prof_fam[idx_] = f;
         c->prof_work[idx_] = work;
         c->prof_fp[idx_] = work * fp_share;
         c->prof_bytes[idx_] = bytes;
+        c->prof_layer_v[idx_] = c->prof_layer;
+        c->prof_phase_v[idx_] = c->prof_phase;
         (void)hipEventRecord(c->prof_ev[2 * idx_], st_);
     }
     ~Prof() {
@@ -187,6 +209,25 @@ class Prof {
     hipStream_t st_;
     size_t idx_;
 };
+// Call site recorded with the launches inside its scope: the layer of the model (layer < -1
+// keeps the current one) and the phase of the layer.
+class Site {
+  public:
+    Site(ctl_ctx *c, int layer, const char *phase) : c_(c), layer_(c->prof_layer), phase_(c->prof_phase) {
+        if (layer >= -1) c->prof_layer = layer;
+        if (phase) c->prof_phase = phase;
+    }
+    ~Site() {
+        c_->prof_layer = layer_;
+        c_->prof_phase = phase_;
+    }
+  private:
+    ctl_ctx *c_;
+    int layer_;
+    const char *phase_;
+};
+constexpr int kKeepLayer = -2;
+
 #define CTL_PROF(fam, work, share) Prof prof_##__LINE__(c, fam, st, (double)(work), (share))
 #define CTL_PROFB(fam, work, share, bytes) Prof prof_##__LINE__(c, fam, st, (double)(work), (share), (double)(bytes))
 
@@ -291,7 +332,18 @@ struct KeySet {
         int b0, nb;
     };
     std::vector<Run> runs;
+    KeySet slice(int b0, int nb) const;
 };
+
+// The key sets of ciphertexts b0 .. b0 + nb - 1, renumbered from 0.
+KeySet KeySet::slice(int b0, int nb) const {
+    KeySet out;
+    for (const Run &r : runs) {
+        const int lo = std::max(r.b0, b0), hi = std::min(r.b0 + r.nb, b0 + nb);
+        if (lo < hi) out.runs.push_back({r.evk, lo - b0, hi - lo});
+    }
+    return out;
+}
 
 KeySet one_key_set(const ctl_evk *evk, int B) {
     KeySet ks;
@@ -307,33 +359,33 @@ int need_key(const KeySet &ks, u64 id, const std::string &what) {
 }
 
 // ---------------------------------------------------------------- building blocks
-// Raise and multiply: for G = B R polynomials d (k residues each, located by dmap over B*R*k
-// residues, group order (b, r)), U[b][r] = sum_j ModUp(d)_j * key_r[j] gathered through
-// sigma_{gal[r]} (plus the fold term, see KeyFold), as [2][k+1][N] over q_0..q_{k-1}, P.
-// `hoisted` = the same d for every r (dmap covers B*k residues only). U goes to U_dst with batch
-// stride U_sb and [R][2][k+1][N] per ciphertext, or, with U_dst null, to workspace slot S_U as
-// [B][R][2][k+1][N]; *U_out receives its address.
-int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *d, const ResMap &dmap,
-                    bool hoisted, const KeySet &ks, const u64 *key_ids, const u64 *gal, u64 **U_out,
-                    const KeyFold *fold = nullptr, u64 *U_dst = nullptr, long U_sb = 0) {
+// ModUp of G polynomials d (k residues each, located by dmap, NTT form): iNTT, then the centered
+// lift of each digit to the other primes and P and its NTT, into workspace slot S_DIG as
+// [G][k][k+1][N] (*dig_out).
+int modup_digits(ctl_ctx *c, hipStream_t st, int k, int G, const u64 *d, const ResMap &dmap, u64 **dig_out) {
+    const int logn = c->hp.logn, nq = c->hp.nq;
+    const long N = c->hp.n;
+    u64 *coef, *dig;
+    CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
+    CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
+    { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
+    { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st); }
+    *dig_out = dig;
+    return check_launch();
+}
+
+// Key products of B ciphertexts and R rotations from ModUp digits (ciphertext b at dig + b db;
+// hoisted: the same digits for every rotation, else rotation r's at + r k(k+1)N): U[b][r] =
+// sum_j digit_j * key_r[j] gathered through sigma_{gal[r]} (+ the fold term), [2][k+1][N] at
+// U + b U_sb + r 2(k+1)N. One launch per key set.
+int key_product(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *dig, long db, bool hoisted,
+                const KeySet &ks, const u64 *key_ids, const u64 *gal, const KeyFold *fold, u64 *U, long U_sb) {
     const int logn = c->hp.logn, nq = c->hp.nq;
     const long N = c->hp.n;
     if (R > kMaxKeysPerLaunch) return fail(CTL_EINVAL, "too many rotations in one layer");
-    const int G = hoisted ? B : B * R;
-    u64 *coef, *dig, *U;
-    CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
-    CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
-    if (U_dst) {
-        U = U_dst;
-    } else {
-        CTL_TRY(slot(c, S_U, (size_t)B * R * 2 * (k + 1) * N, st, &U));
-        U_sb = (long)R * 2 * (k + 1) * N;
-    }
+    const long dsz = (long)k * (k + 1) * N;
     KeyFold fd{};
     if (fold) fd = *fold;
-    { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
-    { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st); }
-    const long dsz = (long)k * (k + 1) * N, db = hoisted ? dsz : (long)R * dsz;
     // algorithmic bytes: digits (once per ciphertext when hoisted), each key set's keys, the
     // outputs, and the fold term's words
     const double kip_bytes = 8.0 * N * ((double)B * (hoisted ? 1 : R) * k * (k + 1) +
@@ -353,8 +405,33 @@ int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
         launch_keyip(logn, k, dig + run.b0 * db, db, hoisted ? 0 : dsz, kl, R, U + run.b0 * U_sb, U_sb, fr,
                      run.nb, nq, c->tab, c->knobs, st);
     }
-    *U_out = U;
     return check_launch();
+}
+
+// Raise and multiply: for G = B R polynomials d (k residues each, located by dmap over B*R*k
+// residues, group order (b, r)), U[b][r] = sum_j ModUp(d)_j * key_r[j] gathered through
+// sigma_{gal[r]} (plus the fold term, see KeyFold), as [2][k+1][N] over q_0..q_{k-1}, P.
+// `hoisted` = the same d for every r (dmap covers B*k residues only). U goes to U_dst with batch
+// stride U_sb and [R][2][k+1][N] per ciphertext, or, with U_dst null, to workspace slot S_U as
+// [B][R][2][k+1][N]; *U_out receives its address.
+int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *d, const ResMap &dmap,
+                    bool hoisted, const KeySet &ks, const u64 *key_ids, const u64 *gal, u64 **U_out,
+                    const KeyFold *fold = nullptr, u64 *U_dst = nullptr, long U_sb = 0) {
+    const long N = c->hp.n;
+    if (R > kMaxKeysPerLaunch) return fail(CTL_EINVAL, "too many rotations in one layer");
+    const int G = hoisted ? B : B * R;
+    u64 *dig, *U;
+    if (U_dst) {
+        U = U_dst;
+    } else {
+        CTL_TRY(slot(c, S_U, (size_t)B * R * 2 * (k + 1) * N, st, &U));
+        U_sb = (long)R * 2 * (k + 1) * N;
+    }
+    CTL_TRY(modup_digits(c, st, k, G, d, dmap, &dig));
+    const long dsz = (long)k * (k + 1) * N, db = hoisted ? dsz : (long)R * dsz;
+    CTL_TRY(key_product(c, st, k, B, R, dig, db, hoisted, ks, key_ids, gal, fold, U, U_sb));
+    *U_out = U;
+    return CTL_OK;
 }
 
 // Lower G2 = 2 B R extended polynomials U ([G2][k+1][N]) by ModDown into out ([G2][k][N]),
@@ -545,70 +622,142 @@ int poly3_batch(ctl_ctx *c, hipStream_t st, const KeySet &ks, int k, int B, doub
     return check_launch();
 }
 
-// Dense layer with the baby steps kept over Q*P (double hoisting, see CTL_LAYER_BABY_QP):
+// Dense layer with the baby steps kept over Q*P (double hoisting, see CTL_LAYER_BABY_QP), for a
+// batch grouped by model: group g is counts[g] consecutive ciphertexts evaluated by layer li of
+// models[g] (every one a layer with baby steps over Q*P at the same input level k). Per group,
+// with rot~ etc. over its own ciphertexts:
 //   rot~[b][0] = P ct,  rot~[b][j] = U_j + (P sigma_j(c0), 0)        [B][t1][2][k+1][N]
 //   inner~[b][k2] = sum_j pt~_{k2 t1 + j} rot~[b][j]                   [B][t2][2][k+1][N]
 //   I1[b][k2-1] = ModDown(c1 of inner~[b][k2]), k2 >= 1                [B][t2-1][k][N]
 //   usum[b] = inner~[b][0] + sum_{k2 >= 1} (KS_k2(sigma I1) + (sigma(c0 of inner~[b][k2]), 0))
 //   out = rescale(ModDown(usum)).
-// The bank of such a layer carries a last row mod P ([t][k+1][N]).
-int dense_qp_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const KeySet &ks, int B,
-                   const u64 *in, u64 *out, const std::vector<u64> &gal1, const std::vector<u64> &gal2) {
-    const LayerPlan &L = m->layers[li];
-    const int logn = c->hp.logn, nq = c->hp.nq, k = L.k, t1 = L.t1, t2 = L.t2;
-    const int R1 = t1 - 1, R2 = t2 - 1;
-    const long N = c->hp.n, ctw = 2L * k * N, ext = 2L * (k + 1) * N;
-    u64 *rot, *inner, *acc;
-    CTL_TRY(slot(c, S_ROT, (size_t)B * t1 * ext, st, &rot));
-    CTL_TRY(slot(c, S_INNER, (size_t)B * t2 * ext, st, &inner));
-    CTL_TRY(slot(c, S_SUM, (size_t)B * ctw, st, &acc));
-    { CTL_PROF(F_ADD, (double)B * ext, 0.0); launch_times_p(logn, in, rot, (long)t1 * ext, B, k, nq, c->tab, st); }
-    if (R1 > 0) {
-        KeyFold fd{};
-        fd.src = in;                        // c0, gathered through sigma_j and scaled by P
-        fd.sb = ctw;
-        fd.sr = 0;
-        fd.rows = k;
-        for (int t = 0; t < k; ++t) fd.mul[t] = c->hp.mods[nq] % c->hp.mods[t];
-        u64 *U;
-        CTL_TRY(keyswitch_raise(c, st, k, B, R1, in, c1_map(k), true, ks, gal1.data(), gal1.data(), &U, &fd,
-                                rot + ext, (long)t1 * ext));
+// The hoisted ModUp of every c1, the ModUp of every I1, the final ModDown and the rescale each run
+// once over the whole batch; key products, MACs and giant-step sums run per group. The bank of
+// such a layer carries a last row mod P ([t][k+1][N]).
+struct QpGroup {
+    const ctl_model *m;
+    int B, b0;                        // ciphertexts and the first one
+    int t1, t2, R1, R2;
+    std::vector<u64> gal1, gal2;
+    long rot_off, inner_off, i1_off;  // words into the shared buffers
+};
+
+int dense_qp_groups(ctl_ctx *c, hipStream_t st, const ctl_model *const *models, const int *counts, int G, int li,
+                    const KeySet &ks, const u64 *in, u64 *out) {
+    const int logn = c->hp.logn, nq = c->hp.nq, k = models[0]->layers[li].k;
+    const long N = c->hp.n, ctw = 2L * k * N, ext = 2L * (k + 1) * N, dsz = (long)k * (k + 1) * N;
+    std::vector<QpGroup> gs(G);
+    int B = 0;
+    long rot_w = 0, inner_w = 0, i1_w = 0;
+    for (int g = 0; g < G; ++g) {
+        const LayerPlan &L = models[g]->layers[li];
+        QpGroup &q = gs[g];
+        q.m = models[g];
+        q.B = counts[g];
+        q.b0 = B;
+        q.t1 = L.t1;
+        q.t2 = L.t2;
+        q.R1 = L.t1 - 1;
+        q.R2 = L.t2 - 1;
+        for (int j = 1; j < L.t1; ++j) q.gal1.push_back(galois_elt(logn, L.rots1[j - 1]));
+        for (int k2 = 1; k2 < L.t2; ++k2) q.gal2.push_back(galois_elt(logn, (long)k2 * L.t1));
+        q.rot_off = rot_w;
+        q.inner_off = inner_w;
+        q.i1_off = i1_w;
+        rot_w += (long)q.B * q.t1 * ext;
+        inner_w += q.t2 > 1 ? (long)q.B * q.t2 * ext : 0;      // t2 = 1: the MAC writes the sum
+        i1_w += (long)q.B * q.R2;
+        B += q.B;
     }
-    run_mac(c, st, rot, (long)t1 * ext, rot + ext, (long)t1 * ext, m->banks[li], inner, B, k + 1, true, t1, t2);
-    CTL_TRY(check_launch());
+    u64 *rot, *inner = nullptr, *usum, *acc;
+    CTL_TRY(slot(c, S_ROT, (size_t)rot_w, st, &rot));
+    if (inner_w) CTL_TRY(slot(c, S_INNER, (size_t)inner_w, st, &inner));
+    CTL_TRY(slot(c, S_ROT2, (size_t)B * ext, st, &usum));
+    CTL_TRY(slot(c, S_SUM, (size_t)B * ctw, st, &acc));
+    {
+        Site site(c, kKeepLayer, "baby steps");
+        for (const QpGroup &q : gs) {
+            CTL_PROF(F_ADD, (double)q.B * ext, 0.0);
+            launch_times_p(logn, in + q.b0 * ctw, rot + q.rot_off, (long)q.t1 * ext, q.B, k, nq, c->tab, st);
+        }
+        bool any_baby = false;
+        for (const QpGroup &q : gs) any_baby = any_baby || q.R1 > 0;
+        if (any_baby) {
+            u64 *dig;
+            CTL_TRY(modup_digits(c, st, k, B, in, c1_map(k), &dig));       // one ModUp for every group
+            for (const QpGroup &q : gs) {
+                if (q.R1 <= 0) continue;
+                KeyFold fd{};
+                fd.src = in + q.b0 * ctw;           // c0, gathered through sigma_j and scaled by P
+                fd.sb = ctw;
+                fd.sr = 0;
+                fd.rows = k;
+                for (int t = 0; t < k; ++t) fd.mul[t] = c->hp.mods[nq] % c->hp.mods[t];
+                CTL_TRY(key_product(c, st, k, q.B, q.R1, dig + q.b0 * dsz, dsz, true, ks.slice(q.b0, q.B),
+                                    q.gal1.data(), q.gal1.data(), &fd, rot + q.rot_off + ext, (long)q.t1 * ext));
+            }
+        }
+    }
+    {
+        Site site(c, kKeepLayer, "mac");
+        for (const QpGroup &q : gs) {
+            u64 *dst = q.t2 > 1 ? inner + q.inner_off : usum + q.b0 * ext;
+            const u64 *r0 = rot + q.rot_off;
+            run_mac(c, st, r0, (long)q.t1 * ext, r0 + ext, (long)q.t1 * ext, q.m->banks[li], dst, q.B, k + 1, true,
+                    q.t1, q.t2);
+        }
+        CTL_TRY(check_launch());
+    }
+    if (i1_w > 0) {
+        Site site(c, kKeepLayer, "giant steps");
+        DropAdd none{};
+        none.R = 1;
+        none.mask = 0;
+        none.gal[0] = 1;
+        u64 *i1, *plast;
+        CTL_TRY(slot(c, S_COEF2, (size_t)i1_w * k * N, st, &i1));
+        CTL_TRY(slot(c, S_PLAST, (size_t)i1_w * N, st, &plast));
+        for (const QpGroup &q : gs) {              // I1 = ModDown of c1 of inner~[b][k2], k2 >= 1
+            if (q.R2 <= 0) continue;
+            const u64 *ig = inner + q.inner_off;
+            ResMap pm{};                            // the P rows of those c1
+            pm.per = 1;
+            pm.ngrp = q.R2;
+            pm.off = 3L * (k + 1) + k;
+            pm.gstride = 2L * (k + 1);
+            pm.ostride = (long)q.t2 * 2 * (k + 1);
+            pm.prime[0] = nq;
+            { CTL_PROF(F_NTT_INV, q.B * q.R2, fp_share_range(c, 0, true)); launch_ntt(logn, true, ig, pm, plast + q.i1_off * N, dense_map(1, nq), q.B * q.R2, c->tab, st); }
+            GrpMap xm{3L * (k + 1) * N, (long)q.t2 * ext, ext, q.R2};
+            { CTL_PROF(F_DROP, (double)q.B * q.R2 * k, fp_share_range(c, k, false)); launch_drop(logn, ig, plast + q.i1_off * N, i1 + q.i1_off * k * N, q.B * q.R2, k, nq, none, c->tab, c->knobs, st, &xm); }
+        }
+        u64 *dig, *U;
+        CTL_TRY(modup_digits(c, st, k, (int)i1_w, i1, dense_map(k), &dig));   // one ModUp for every group
+        CTL_TRY(slot(c, S_U, (size_t)i1_w * ext, st, &U));
+        GalList one{};
+        for (int r = 0; r < kMaxKeysPerLaunch; ++r) one.g[r] = 1;
+        for (const QpGroup &q : gs) {
+            if (q.R2 <= 0) continue;
+            const u64 *ig = inner + q.inner_off;
+            KeyFold fg{};
+            fg.src = ig + ext;                      // c0 of inner~[b][1], all k + 1 rows
+            fg.sb = (long)q.t2 * ext;
+            fg.sr = ext;
+            fg.rows = k + 1;
+            for (int t = 0; t <= k; ++t) fg.mul[t] = 1;
+            u64 *Ug = U + q.i1_off * ext;
+            CTL_TRY(key_product(c, st, k, q.B, q.R2, dig + q.i1_off * dsz, (long)q.R2 * dsz, false,
+                                ks.slice(q.b0, q.B), q.gal2.data(), q.gal2.data(), &fg, Ug, (long)q.R2 * ext));
+            { CTL_PROF(F_ADD, (double)q.B * ext, 0.0); launch_sum_gather(logn, usum + q.b0 * ext, ext, ig, (long)q.t2 * ext, Ug, (long)q.R2 * ext, ext, q.R2, k + 1, true, 3, one, q.B, nq, c->tab, st); }
+        }
+        CTL_TRY(check_launch());
+    }
     DropAdd none{};
     none.R = 1;
     none.mask = 0;
     none.gal[0] = 1;
-    const u64 *usum = inner;                // t2 = 1: inner~[b][0] is the whole sum
-    if (R2 > 0) {
-        u64 *i1, *plast, *U, *sum;
-        CTL_TRY(slot(c, S_COEF2, (size_t)B * R2 * k * N, st, &i1));
-        CTL_TRY(slot(c, S_PLAST, (size_t)B * R2 * N, st, &plast));
-        ResMap pm{};                        // the P rows of the c1 of inner~[b][k2], k2 >= 1
-        pm.per = 1;
-        pm.ngrp = R2;
-        pm.off = 3L * (k + 1) + k;
-        pm.gstride = 2L * (k + 1);
-        pm.ostride = (long)t2 * 2 * (k + 1);
-        pm.prime[0] = nq;
-        { CTL_PROF(F_NTT_INV, B * R2, fp_share_range(c, 0, true)); launch_ntt(logn, true, inner, pm, plast, dense_map(1, nq), B * R2, c->tab, st); }
-        GrpMap xm{3L * (k + 1) * N, (long)t2 * ext, ext, R2};
-        { CTL_PROF(F_DROP, (double)B * R2 * k, fp_share_range(c, k, false)); launch_drop(logn, inner, plast, i1, B * R2, k, nq, none, c->tab, c->knobs, st, &xm); }
-        KeyFold fg{};
-        fg.src = inner + ext;               // c0 of inner~[b][1], all k + 1 rows
-        fg.sb = (long)t2 * ext;
-        fg.sr = ext;
-        fg.rows = k + 1;
-        for (int t = 0; t <= k; ++t) fg.mul[t] = 1;
-        CTL_TRY(keyswitch_raise(c, st, k, B, R2, i1, dense_map(k), false, ks, gal2.data(), gal2.data(), &U, &fg));
-        CTL_TRY(slot(c, S_ROT2, (size_t)B * ext, st, &sum));
-        GalList one{};
-        for (int r = 0; r < kMaxKeysPerLaunch; ++r) one.g[r] = 1;
-        { CTL_PROF(F_ADD, (double)B * ext, 0.0); launch_sum_gather(logn, sum, ext, inner, (long)t2 * ext, U, (long)R2 * ext, ext, R2, k + 1, true, 3, one, B, nq, c->tab, st); }
-        usum = sum;
-    }
-    CTL_TRY(keyswitch_lower(c, st, k, B * 2, usum, none, acc));
+    { Site s(c, kKeepLayer, "moddown"); CTL_TRY(keyswitch_lower(c, st, k, B * 2, usum, none, acc)); }
+    Site s(c, kKeepLayer, "rescale");
     return rescale_batch(c, st, k, B, acc, out);
 }
 
@@ -629,11 +778,15 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const Ke
         gal2[k2 - 1] = galois_elt(logn, (long)k2 * t1);
         CTL_TRY(need_key(ks, gal2[k2 - 1], "Galois key for rotation " + std::to_string(k2 * t1)));
     }
-    if (L.qp) return dense_qp_batch(c, st, m, li, ks, B, in, out, gal1, gal2);
+    if (L.qp) {
+        const int cnt = B;
+        return dense_qp_groups(c, st, &m, &cnt, 1, li, ks, in, out);
+    }
     u64 *rot, *inner;
     CTL_TRY(slot(c, S_ROT, (size_t)B * std::max(R1, 1) * ctw, st, &rot));
     CTL_TRY(slot(c, S_INNER, (size_t)B * t2 * ctw, st, &inner));
     // baby steps rot_j(ct), j = 1..t1-1, sharing one ModUp of c1
+    Site baby(c, kKeepLayer, "baby steps");
     if (R1 > 0) {
         DropAdd add{};
         add.base = in;
@@ -645,8 +798,9 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const Ke
         CTL_TRY(keyswitch_batch(c, st, k, B, R1, in, c1_map(k), true, ks, gal1.data(), gal1.data(), add, rot));
     }
     // inner_k2 = sum_j diag'_{k2 t1 + j} * rot_j(ct)
-    run_mac(c, st, in, ctw, rot, (long)R1 * ctw, m->banks[li], inner, B, k, false, t1, t2);
+    { Site s(c, kKeepLayer, "mac"); run_mac(c, st, in, ctw, rot, (long)R1 * ctw, m->banks[li], inner, B, k, false, t1, t2); }
     CTL_TRY(check_launch());
+    Site giant(c, kKeepLayer, "giant steps");
     const u64 *sum = inner;
     if (R2 > 0 && L.lazy) {
         // giant steps: key products of all k2 summed over Q*P, one ModDown; sigma(c0) terms summed
@@ -701,6 +855,7 @@ int dense_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, int li, const Ke
         CTL_TRY(check_launch());
         sum = acc;
     }
+    Site s(c, kKeepLayer, "rescale");
     return rescale_batch(c, st, k, B, sum, out);
 }
 
@@ -720,7 +875,9 @@ int forward_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, const KeySet &
     const int L = (int)m->layers.size();
     for (int l = 0; l < L; ++l) {
         const LayerPlan &P = m->layers[l];
+        Site layer(c, l, "");
         if (P.rep_before) {
+            Site s(c, kKeepLayer, "replicate");
             u64 *dst = next();
             CTL_TRY(replicate_batch(c, st, ks, P.k, B, P.rep_before, cur, dst));
             cur = dst;
@@ -731,10 +888,12 @@ int forward_batch(ctl_ctx *c, hipStream_t st, const ctl_model *m, const KeySet &
         cur = dst;
         if (last) break;
         if (P.act == CTL_ACT_SQUARE) {
+            Site s(c, kKeepLayer, "square");
             u64 *d2 = next();
             CTL_TRY(square_batch(c, st, ks, P.k - 1, B, cur, d2));
             cur = d2;
         } else if (P.act == CTL_ACT_POLY3) {
+            Site s(c, kKeepLayer, "cubic");
             u64 *d2 = next();
             CTL_TRY(poly3_batch(c, st, ks, P.k - 1, B, P.act_scale_in, P.act_coef, cur, d2));
             cur = d2;
@@ -997,6 +1156,7 @@ int make_model(ctl_ctx *c, const ctl_layer_desc *layers, int n_layers, const int
         for (u64 *b : m->banks) dev_free(c, b, nullptr);
         return rc;
     }
+    ctx_retain(c);
     *out = m.release();
     return CTL_OK;
 }
@@ -1176,9 +1336,20 @@ int ctl_ctx_free(ctl_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (int s = 0; s < S_COUNT; ++s) dev_free(ctx, ctx->slot_ptr[s], nullptr);
+    for (int s = 0; s < S_COUNT; ++s) {
+        ctx->slot_ptr[s] = nullptr;
+        ctx->slot_bytes[s] = 0;
+    }
     for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
-    (void)hipFree(ctx->tables_mem);
-    delete ctx;
+    ctx->prof_ev.clear();
+    ctx->prof_fam.clear();
+    ctx->prof_work.clear();
+    ctx->prof_fp.clear();
+    ctx->prof_bytes.clear();
+    ctx->prof_layer_v.clear();
+    ctx->prof_phase_v.clear();
+    ctx->prof_used = 0;
+    ctx_release(ctx);              // the tables stay until the last handle made here is freed
     return CTL_OK;
 }
 
@@ -1307,6 +1478,61 @@ int ctl_profile_read_bytes(ctl_ctx *ctx, int family, double *bytes_out) {
     for (size_t i = 0; i < ctx->prof_used; ++i)
         if (ctx->prof_fam[i] == family) b += ctx->prof_bytes[i];
     *bytes_out = b;
+    return CTL_OK;
+}
+
+int ctl_profile_launches(ctl_ctx *ctx, int *n_out) {
+    if (!ctx || !n_out) return fail(CTL_EINVAL, "null argument");
+    *n_out = (int)ctx->prof_used;
+    return CTL_OK;
+}
+
+int ctl_profile_launch(ctl_ctx *ctx, int i, int *family_out, double *ms_out, double *work_out, double *fp_work_out,
+                       double *bytes_out, int *layer_out, const char **phase_out) {
+    if (!ctx || !family_out || !ms_out || !work_out || !fp_work_out || !bytes_out || !layer_out || !phase_out)
+        return fail(CTL_EINVAL, "null argument");
+    if (i < 0 || (size_t)i >= ctx->prof_used) return fail(CTL_EINVAL, "launch record out of range");
+    CTL_HIP(hipEventSynchronize(ctx->prof_ev[2 * i + 1]));
+    float ms = 0.f;
+    CTL_HIP(hipEventElapsedTime(&ms, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
+    *family_out = ctx->prof_fam[i];
+    *ms_out = ms;
+    *work_out = ctx->prof_work[i];
+    *fp_work_out = ctx->prof_fp[i];
+    *bytes_out = ctx->prof_bytes[i];
+    *layer_out = ctx->prof_layer_v[i];
+    *phase_out = ctx->prof_phase_v[i];
+    return CTL_OK;
+}
+
+int ctl_probe_valu(ctl_ctx *ctx, int kind, int iters, double *lane_ops_out, void *stream) {
+    if (!ctx || !lane_ops_out || kind < 0 || kind > 3 || iters < 1 || iters > (1 << 24))
+        return fail(CTL_EINVAL, "bad argument");
+    CTL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    hipDeviceProp_t prop;
+    CTL_HIP(hipGetDeviceProperties(&prop, ctx->device));
+    const int blocks = prop.multiProcessorCount * 8;       // 8 workgroups (32 waves) per CU
+    u64 *out;
+    CTL_TRY(slot(ctx, S_MISC, (size_t)blocks * 256, st, &out));
+    hipEvent_t e0, e1;
+    CTL_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(CTL_EHIP, "event creation failed");
+    }
+    launch_probe(kind, std::max(1, iters / 16), 1, out, blocks, st);      // warm-up
+    (void)hipEventRecord(e0, st);
+    launch_probe(kind, iters, 2, out, blocks, st);
+    (void)hipEventRecord(e1, st);
+    const hipError_t e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    const hipError_t e2 = e == hipSuccess ? hipEventElapsedTime(&ms, e0, e1) : e;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e2 != hipSuccess) return fail(CTL_EHIP, std::string("probe: ") + hipGetErrorString(e2));
+    CTL_TRY(check_launch());
+    *lane_ops_out = (double)blocks * 256 * iters * kProbeOpsPerThreadIter / (ms * 1e-3);
     return CTL_OK;
 }
 
@@ -1495,31 +1721,47 @@ int ctl_keygen(ctl_ctx *ctx, uint64_t seed, const int32_t *rotations, int n_rot,
             CTL_HIP(hipStreamSynchronize(st));
         }
     }
-    if (sk_out) *sk_out = sk.release();
-    else { dev_free(ctx, sk->d_s, st); }
-    if (pk_out) *pk_out = pk.release();
-    if (evk_out) *evk_out = evk.release();
+    if (sk_out) {
+        ctx_retain(ctx);
+        *sk_out = sk.release();
+    } else {
+        dev_free(ctx, sk->d_s, st);
+    }
+    if (pk_out) {
+        ctx_retain(ctx);
+        *pk_out = pk.release();
+    }
+    if (evk_out) {
+        ctx_retain(ctx);
+        *evk_out = evk.release();
+    }
     return CTL_OK;
 }
 
 int ctl_sk_free(ctl_sk *sk) {
     if (!sk) return CTL_OK;
-    dev_free(sk->ctx, sk->d_s, nullptr);
+    ctl_ctx *c = sk->ctx;
+    dev_free(c, sk->d_s, nullptr);
     delete sk;
+    ctx_release(c);
     return CTL_OK;
 }
 
 int ctl_pk_free(ctl_pk *pk) {
     if (!pk) return CTL_OK;
-    dev_free(pk->ctx, pk->d_pk, nullptr);
+    ctl_ctx *c = pk->ctx;
+    dev_free(c, pk->d_pk, nullptr);
     delete pk;
+    ctx_release(c);
     return CTL_OK;
 }
 
 int ctl_evk_free(ctl_evk *evk) {
     if (!evk) return CTL_OK;
-    for (auto &kv : evk->keys) dev_free(evk->ctx, kv.second, nullptr);
+    ctl_ctx *c = evk->ctx;
+    for (auto &kv : evk->keys) dev_free(c, kv.second, nullptr);
     delete evk;
+    ctx_release(c);
     return CTL_OK;
 }
 
@@ -1669,6 +1911,7 @@ int ctl_evk_import(ctl_ctx *ctx, const uint64_t *galois_elts, int n_keys, const 
         }
         evk->keys[galois_elts[i]] = key;
     }
+    ctx_retain(ctx);
     *evk_out = evk.release();
     return CTL_OK;
 }
@@ -1709,8 +1952,10 @@ int ctl_model_load_raw(ctl_ctx *ctx, const ctl_layer_desc *layers, int n_layers,
 
 int ctl_model_free(ctl_model *model) {
     if (!model) return CTL_OK;
-    for (u64 *b : model->banks) dev_free(model->ctx, b, nullptr);
+    ctl_ctx *c = model->ctx;
+    for (u64 *b : model->banks) dev_free(c, b, nullptr);
     delete model;
+    ctx_release(c);
     return CTL_OK;
 }
 
@@ -1884,6 +2129,36 @@ int ctl_dense(ctl_ctx *ctx, const ctl_model *model, int layer, const ctl_evk *ev
     CTL_HIP(hipSetDevice(ctx->device));
     return dense_batch(ctx, as_stream(stream), model, layer, one_key_set(evk, n_ct), n_ct, reinterpret_cast<const u64 *>(in),
                        reinterpret_cast<u64 *>(out));
+}
+
+int ctl_dense_groups(ctl_ctx *ctx, const ctl_model *const *models, const int *counts, int n_groups, int layer,
+                     const ctl_evk *evk, const uint64_t *in, uint64_t *out, void *stream) {
+    if (!ctx || !models || !counts || !evk || !in || !out || n_groups < 1 || n_groups > 4096)
+        return fail(CTL_EINVAL, "bad argument");
+    CTL_SAME(ctx, evk, "the evaluation key set");
+    int n_ct = 0, k = -1;
+    for (int g = 0; g < n_groups; ++g) {
+        const ctl_model *m = models[g];
+        if (!m) return fail(CTL_EINVAL, "null model");
+        CTL_SAME(ctx, m, "every model");
+        if (counts[g] < 1) return fail(CTL_EINVAL, "every group needs at least one ciphertext");
+        if (layer < 0 || layer >= (int)m->layers.size()) return fail(CTL_EINVAL, "layer out of range");
+        const LayerPlan &L = m->layers[layer];
+        if (!L.qp) return fail(CTL_EINVAL, "every layer must keep its baby steps over Q*P (CTL_LAYER_BABY_QP)");
+        if (k >= 0 && L.k != k) return fail(CTL_ELEVEL, "every group's layer must start at the same level");
+        k = L.k;
+        if (L.t1 - 1 > kMaxKeysPerLaunch || L.t2 - 1 > kMaxKeysPerLaunch)
+            return fail(CTL_EINVAL, "t1 and t2 must be at most 65");
+        for (long r : L.rots1)
+            CTL_TRY(need_key(one_key_set(evk, 1), galois_elt(ctx->hp.logn, r), "Galois key for rotation " + std::to_string(r)));
+        for (int k2 = 1; k2 < L.t2; ++k2)
+            CTL_TRY(need_key(one_key_set(evk, 1), galois_elt(ctx->hp.logn, (long)k2 * L.t1),
+                             "Galois key for rotation " + std::to_string(k2 * L.t1)));
+        n_ct += counts[g];
+    }
+    CTL_HIP(hipSetDevice(ctx->device));
+    return dense_qp_groups(ctx, as_stream(stream), models, counts, n_groups, layer, one_key_set(evk, n_ct),
+                           reinterpret_cast<const u64 *>(in), reinterpret_cast<u64 *>(out));
 }
 
 int ctl_square(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint64_t *out, int n_ct, void *stream) {

@@ -68,6 +68,10 @@ struct GalList {
 };
 
 hipError_t kernels_prepare(int logn);
+// Vector ALU issue-rate probe (kind 0..3, see ctl_probe_valu): `blocks` workgroups of 256 threads,
+// each thread 8 chains x 8 steps x iters operations; out: blocks * 256 words.
+constexpr int kProbeOpsPerThreadIter = 64;
+void launch_probe(int kind, int iters, u64 seed, u64 *out, int blocks, hipStream_t st);
 void launch_sum_gather(int logn, u64 *out, long o_sb, const u64 *base, long ba_sb, const u64 *src, long s_sb,
                        long s_sr, int R, int kk, bool ext, int mask, const GalList &gal, int B, int nq,
                        const Tables &tab, hipStream_t st);

@@ -1435,6 +1435,61 @@ static hipError_t prepare_all() {
     return set_lds(k_int_ntt<LOGN>, b);
 }
 
+// ---------------------------------------------------------------- vector ALU issue-rate probe
+// KIND 0: 32-bit add, 1: 32-bit multiply (low half), 2: v_mad_u64_u32 (32 x 32 + 64), 3: FP64 fma.
+// Each thread runs kProbeChains chains, each step of which takes its neighbour's previous value
+// (so no step can be folded or hoisted), for `iters` iterations of 8 steps; the result is stored.
+constexpr int kProbeChains = 8;
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_probe(int iters, u64 seed, u64 *__restrict__ out) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    u64 x[kProbeChains];
+    double d[kProbeChains];
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) {
+        x[c] = (seed + (u64)gid * 0x9E3779B97F4A7C15ull + (u64)c * 0xBF58476D1CE4E5B9ull) | 1ull;
+        d[c] = 1.0 + (double)((x[c] >> 11) & 1023) * 0x1p-12;
+    }
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if constexpr (KIND == 3) {
+                double nd[kProbeChains];
+#pragma unroll
+                for (int c = 0; c < kProbeChains; ++c) nd[c] = __fma_rn(d[c], -0.5, d[(c + 1) % kProbeChains]);
+#pragma unroll
+                for (int c = 0; c < kProbeChains; ++c) d[c] = nd[c];
+            } else {
+                u64 nx[kProbeChains];
+#pragma unroll
+                for (int c = 0; c < kProbeChains; ++c) {
+                    const u64 y = x[(c + 1) % kProbeChains];
+                    if constexpr (KIND == 0) nx[c] = (u32)x[c] + (u32)y;
+                    else if constexpr (KIND == 1) nx[c] = (u32)x[c] * (u32)y;
+                    else nx[c] = (u64)(u32)x[c] * (u32)(y >> 32) + x[c];
+                }
+#pragma unroll
+                for (int c = 0; c < kProbeChains; ++c) x[c] = nx[c];
+            }
+        }
+    }
+    u64 acc = 0;
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) acc ^= KIND == 3 ? (u64)__double_as_longlong(d[c]) : x[c];
+    out[gid] = acc;
+}
+
+void launch_probe(int kind, int iters, u64 seed, u64 *out, int blocks, hipStream_t st) {
+    const dim3 grid((unsigned)blocks), blk(256);
+    switch (kind) {
+        case 0: hipLaunchKernelGGL(k_probe<0>, grid, blk, 0, st, iters, seed, out); break;
+        case 1: hipLaunchKernelGGL(k_probe<1>, grid, blk, 0, st, iters, seed, out); break;
+        case 2: hipLaunchKernelGGL(k_probe<2>, grid, blk, 0, st, iters, seed, out); break;
+        default: hipLaunchKernelGGL(k_probe<3>, grid, blk, 0, st, iters, seed, out); break;
+    }
+}
+
 hipError_t kernels_prepare(int logn) {
     switch (logn) {
         case 12: return prepare_all<12>();

@@ -160,3 +160,43 @@ def test_mix_fp64_tolerance():
             if l + 1 < q.depth:
                 ref = ref * ref
         assert normwise_error(y, ref) < 2.0 ** -20, (i, q)
+
+
+def test_dense_groups_equals_dense_per_model():
+    """ctl_dense_groups over banks of all four widths at positions 0 and 1 (groups of 3, 1, 2 and
+    2 ciphertexts) equals ctl_dense of each model on its own ciphertexts, bit for bit; a model
+    without baby steps over Q*P, or one at another level, is rejected before anything runs."""
+    _need_gpu()
+    import paper_2205_11935_amd as ctl
+    from paper_2205_11935_amd.batch_mix import MixEngine
+    c, o, queries, keys, _ = _setup((128, 256, 512, 768), 24)
+    eng = MixEngine(c, keys, _raw_bank(o.n), W.MIX_T1, W.MIX_BLOCK, raw=True, lazy=True)
+    for pos, shapes in ((0, [(128, 768), (768, 256), (512, 512), (256, 128)]),
+                        (1, [(256, 512), (768, 768), (128, 128), (512, 256)])):
+        models = [eng.model(pos, a, b) for a, b in shapes]
+        counts = [3, 1, 2, 2]
+        k = eng.level(pos)
+        msgs = W.raw_plaintexts(80 + pos, sum(counts), o.n, bound_bits=40)
+        top = c.empty_ct(sum(counts), o.nq)
+        for i in range(sum(counts)):
+            c.encrypt(keys, msgs[i], 900 + 10 * pos + i, out=top[i])
+        x = top[:, :, :k].contiguous()
+        got = ctl.to_numpy_u64(c.dense_groups(models, counts, keys, x))
+        r0 = 0
+        for m, cnt in zip(models, counts):
+            want = ctl.to_numpy_u64(c.dense(m, 0, keys, x[r0:r0 + cnt].contiguous()))
+            assert np.array_equal(got[r0:r0 + cnt], want), (pos, r0)
+            r0 += cnt
+    lazy_only = c.load_model_ex([(128, 128, 32, 0)], pts=[_raw_bank(o.n)(0, 128, 128, 128)], lazy=True,
+                                block=W.MIX_BLOCK)
+    out = c.empty_ct(2, o.nq - 1)
+    out.fill_(3)
+    x2 = top[:2].contiguous()
+    with pytest.raises(ctl.CtlError) as ei:
+        c.dense_groups([eng.model(0, 128, 128), lazy_only], [1, 1], keys, x2, out=out)
+    assert ei.value.code == -1
+    with pytest.raises(ctl.CtlError) as ei:
+        c.dense_groups([eng.model(0, 128, 128), eng.model(1, 128, 128)], [1, 1], keys, x2, out=out)
+    assert ei.value.code == -3
+    torch.cuda.synchronize()
+    assert torch.all(out == 3)
