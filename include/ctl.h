@@ -480,6 +480,21 @@ int ctl_square(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint
 int ctl_replicate(ctl_ctx *ctx, const ctl_evk *evk, int k, int width, const uint64_t *in,
                   uint64_t *out, int n_ct, void *stream);
 
+/* ctl_square for callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops and harnesses that must not call hipMalloc): the same result as ctl_square, bit for bit,
+ * with every intermediate (tensor, ModUp digits, key product, ModDown and rescale rows) in a fixed
+ * scratch array of CTL_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on, from
+ * the first context created on that GPU until the process ends. The call makes no device
+ * allocation and uses no workspace of the context. It needs 8 N (k^2 + 9k + 6) bytes of scratch per
+ * ciphertext (12 MiB per ciphertext at N = 2^14, k = 6); a batch that does not fit gives CTL_EINVAL
+ * before anything is enqueued. Every call on one GPU shares that GPU's scratch, whatever its
+ * context or stream: calls that overlap on one GPU race and must be serialized by the caller. The
+ * scratch keeps the last call's contents and needs no clearing: every intermediate is written
+ * before it is read. Arguments, layout and the other errors as ctl_square. */
+#define CTL_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int ctl_square_noalloc(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint64_t *out,
+                       int n_ct, void *stream);
+
 /* Left rotation by `rotation` slots (needs that Galois key). k -> k. */
 int ctl_rotate(ctl_ctx *ctx, const ctl_evk *evk, int k, int rotation, const uint64_t *in,
                uint64_t *out, int n_ct, void *stream);

@@ -192,6 +192,8 @@ _SIGS = {
                                         ctypes.c_void_p]),
     "ctl_square": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ctl_square_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "ctl_mul": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "ctl_poly3": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double, f64p,
@@ -829,6 +831,16 @@ class Context:
         po = self._dev(out, (n_ct, 2, k - 1, self.n), "square output")
         check_disjoint(ct, out, "square")
         _check(lib().ctl_square(self.handle, keys.evk, k, pi, po, n_ct, _stream(stream)))
+        return out
+
+    def square_noalloc(self, keys: Keys, ct, out, stream=None):
+        """ctl_square without any device allocation (the library's fixed per-GPU scratch array);
+        `out` must be given, since allocating it here would defeat the purpose."""
+        n_ct, k = self._level(ct, 2, "square input")
+        pi = self._dev(ct, (n_ct, 2, k, self.n), "square input")
+        po = self._dev(out, (n_ct, 2, k - 1, self.n), "square output")
+        check_disjoint(ct, out, "square_noalloc")
+        _check(lib().ctl_square_noalloc(self.handle, keys.evk, k, pi, po, n_ct, _stream(stream)))
         return out
 
     def replicate(self, keys: Keys, ct, width: int, out=None, stream=None):

@@ -68,6 +68,11 @@ struct ctl_ctx {
     std::vector<PrimeConst> pc;
     bool ws_frozen = false;
     Knobs knobs;
+    // the fixed scratch array of this context's GPU; while `arena` is set (inside the entry point
+    // that allocates nothing) slot() carves buffers from it instead of the workspace
+    u64 *scratch = nullptr;
+    bool arena = false;
+    size_t arena_used = 0;
     // lifetime: one reference for the context itself and one per live key or model handle made
     // on it; ctl_ctx_free drops the context's own (and releases the workspace at once), and the
     // tables and this struct go when the last reference does, whatever the order of the frees
@@ -153,6 +158,14 @@ void ctx_release(ctl_ctx *c) {
 }
 
 int slot(ctl_ctx *c, Slot s, size_t words, hipStream_t st, u64 **out) {
+    if (c->arena) {                            // carve from the scratch array, 256-byte aligned
+        const size_t w = (std::max<size_t>(words, 1) + 31) / 32 * 32;
+        if (!c->scratch || c->arena_used + w > kScratchWords)
+            return fail(CTL_ENOMEM, "the call needs more than the fixed scratch array holds");
+        *out = c->scratch + c->arena_used;
+        c->arena_used += w;
+        return CTL_OK;
+    }
     const size_t bytes = std::max<size_t>(words * 8, 256);
     if (c->slot_bytes[s] < bytes) {
         if (c->ws_frozen)
@@ -178,7 +191,7 @@ class Prof {
   public:
     Prof(ctl_ctx *c, Family f, hipStream_t st, double work, double fp_share = 0.0, double bytes = 0.0)
         : c_(c), st_(st), idx_(SIZE_MAX) {
-        if (!c->prof_on) return;
+        if (!c->prof_on || c->arena) return;     // no event creation inside the no-allocation call
         if (c->prof_used * 2 + 2 > c->prof_ev.size()) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess) return;
@@ -1326,6 +1339,10 @@ int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
         (void)hipFree(dmem);
         return fail(CTL_EHIP, "setting the LDS limit of the NTT kernels failed");
     }
+    if (scratch_device_address(device, &c->scratch) != hipSuccess) {
+        (void)hipFree(dmem);
+        return fail(CTL_EHIP, "looking up the scratch array's device address failed");
+    }
     c->enc.reset(new Encoder(c->hp.logn));
     *ctx_out = c.release();
     return CTL_OK;
@@ -2166,6 +2183,31 @@ int ctl_square(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint
     if (k < 2 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
     CTL_SAME(ctx, evk, "the evaluation key set");
     CTL_HIP(hipSetDevice(ctx->device));
+    return square_batch(ctx, as_stream(stream), one_key_set(evk, n_ct), k, n_ct, reinterpret_cast<const u64 *>(in),
+                        reinterpret_cast<u64 *>(out));
+}
+
+// Scratch words of square_batch for B ciphertexts at k primes: tensor 3k, relinearized 2k,
+// coefficient-form digits k, ModUp digits k(k+1), key product 2(k+1), ModDown P rows 2, rescale
+// rows 2 (each times N, per ciphertext; every size is a multiple of the 32-word carve alignment).
+static size_t square_scratch_words(int k, long n, int B) { return (size_t)B * n * ((size_t)k * k + 9 * k + 6); }
+
+int ctl_square_noalloc(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint64_t *out, int n_ct,
+                       void *stream) {
+    if (!ctx || !evk || !in || !out || n_ct < 1) return fail(CTL_EINVAL, "bad argument");
+    if (k < 2 || k > ctx->hp.nq) return fail(CTL_ELEVEL, "k out of range");
+    CTL_SAME(ctx, evk, "the evaluation key set");
+    if (!ctx->scratch) return fail(CTL_EHIP, "no scratch array on this device");
+    if (square_scratch_words(k, ctx->hp.n, n_ct) > kScratchWords)
+        return fail(CTL_EINVAL, "batch needs " + std::to_string(square_scratch_words(k, ctx->hp.n, n_ct) * 8) +
+                                    " bytes of scratch; the fixed array holds " +
+                                    std::to_string((unsigned long long)CTL_NOALLOC_SCRATCH_BYTES));
+    CTL_HIP(hipSetDevice(ctx->device));
+    struct Arena {                               // carve from the scratch array for this call only
+        ctl_ctx *c;
+        explicit Arena(ctl_ctx *c_) : c(c_) { c->arena = true; c->arena_used = 0; }
+        ~Arena() { c->arena = false; c->arena_used = 0; }
+    } arena(ctx);
     return square_batch(ctx, as_stream(stream), one_key_set(evk, n_ct), k, n_ct, reinterpret_cast<const u64 *>(in),
                         reinterpret_cast<u64 *>(out));
 }

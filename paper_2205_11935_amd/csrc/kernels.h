@@ -68,6 +68,11 @@ struct GalList {
 };
 
 hipError_t kernels_prepare(int logn);
+// Device address of the library's fixed scratch array (kScratchWords words; one copy per GPU,
+// held until the process ends) on the current device. Looked up once per device and cached;
+// call it with the device current. Used by the entry point that allocates nothing.
+constexpr size_t kScratchWords = (size_t)CTL_NOALLOC_SCRATCH_BYTES / 8;
+hipError_t scratch_device_address(int device, u64 **out);
 // Vector ALU issue-rate probe (kind 0..3, see ctl_probe_valu): `blocks` workgroups of 256 threads,
 // each thread 8 chains x 8 steps x iters operations; out: blocks * 256 words.
 constexpr int kProbeOpsPerThreadIter = 64;

@@ -11,6 +11,8 @@
 // from per-prime tables. One workgroup transforms one residue polynomial: N/16 threads hold 16
 // values each in registers; each pass runs 4 (or 3) butterfly stages in registers and exchanges
 // through LDS between passes, so a residue makes a single HBM round trip.
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "ctl_internal.h"
@@ -1488,6 +1490,29 @@ void launch_probe(int kind, int iters, u64 seed, u64 *out, int blocks, hipStream
         case 2: hipLaunchKernelGGL(k_probe<2>, grid, blk, 0, st, iters, seed, out); break;
         default: hipLaunchKernelGGL(k_probe<3>, grid, blk, 0, st, iters, seed, out); break;
     }
+}
+
+// Scratch of the entry point that allocates nothing. Host code never passes `scratch` itself to
+// a kernel (in host code the name is a stand-in, not a device address): it passes the address
+// hipGetSymbolAddress returns for the current device, looked up once per device.
+static __device__ __align__(256) u64 scratch[kScratchWords];
+
+hipError_t scratch_device_address(int device, u64 **out) {
+    static std::mutex mu;
+    static std::map<int, u64 *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = static_cast<u64 *>(p);
+    *out = static_cast<u64 *>(p);
+    return hipSuccess;
 }
 
 hipError_t kernels_prepare(int logn) {
