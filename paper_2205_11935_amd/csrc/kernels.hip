@@ -169,41 +169,70 @@ __device__ __forceinline__ int lds_idx(int j) { return j + (j >> 5); }
 template <int LOGN>
 constexpr int lds_words() { return (1 << LOGN) + ((1 << LOGN) >> 5); }
 
-// element index of slot (g, e) of a pass over bits [LO, LO + RB)
-template <int LOGN, int LO, int RB>
+// Element index of slot (g, e) of a pass over bits [LO, LO + RB): e supplies those bits, the
+// group g and the thread the others. Workgroup mapping (WV = false): rest = g T + tid spans the
+// whole residue. Wave-local mapping (WV = true), for passes below bit 10 after the first one: wave
+// w = tid / 64 keeps the 1024 elements [1024 w, 1024 w + 1024), the bits of its lane and of g
+// filling the rest, so the pass and its LDS exchange involve that wave alone (after the first pass
+// the transform splits into independent sub-transforms over the lower bits).
+template <int LOGN, int LO, int RB, bool WV = false>
+__device__ __forceinline__ int pass_rest(int g, int tid) {
+    return WV ? (g << 6) | (tid & 63) : g * Geo<LOGN>::T + tid;
+}
+template <int LOGN, int LO, int RB, bool WV = false>
 __device__ __forceinline__ int pass_index(int g, int e, int tid) {
-    const int rest = g * Geo<LOGN>::T + tid;
-    return ((rest >> LO) << (LO + RB)) | (e << LO) | (rest & ((1 << LO) - 1));
+    const int rest = pass_rest<LOGN, LO, RB, WV>(g, tid);
+    const int idx = ((rest >> LO) << (LO + RB)) | (e << LO) | (rest & ((1 << LO) - 1));
+    return WV ? ((tid >> 6) << 10) | idx : idx;
+}
+// index >> (LO + RB) of the elements of group g (the twiddles of every stage of the pass follow
+// from it): uniform across a wave when LO >= 6
+template <int LOGN, int LO, int RB, bool WV = false>
+__device__ __forceinline__ int pass_hi(int g, int tid) {
+    const int hi = pass_rest<LOGN, LO, RB, WV>(g, tid) >> LO;
+    return WV ? ((tid >> 6) << (10 - LO - RB)) | hi : hi;
 }
 
-template <int LOGN, int LO, int RB, typename T>
+// Order the LDS accesses of one wave: its lanes' writes before its later reads (a wave's LDS
+// operations execute in order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Element j of the wave-local output / input layout: wave w's 1024 elements, 64 consecutive per
+// value slot e (coalesced loads and stores).
+__device__ __forceinline__ int wave_elem(int tid, int e) { return ((tid >> 6) << 10) | (e << 6) | (tid & 63); }
+
+template <int LOGN, int LO, int RB, bool WV = false, typename T>
 __device__ __forceinline__ void to_lds(const T (&v)[16], T *lds, int tid) {
     constexpr int R = 1 << RB, G = 16 / R;
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int e = 0; e < R; ++e) lds[lds_idx(pass_index<LOGN, LO, RB>(g, e, tid))] = v[g * R + e];
+        for (int e = 0; e < R; ++e) lds[lds_idx(pass_index<LOGN, LO, RB, WV>(g, e, tid))] = v[g * R + e];
 }
 
-template <int LOGN, int LO, int RB, typename T>
+template <int LOGN, int LO, int RB, bool WV = false, typename T>
 __device__ __forceinline__ void from_lds(T (&v)[16], const T *lds, int tid) {
     constexpr int R = 1 << RB, G = 16 / R;
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int e = 0; e < R; ++e) v[g * R + e] = lds[lds_idx(pass_index<LOGN, LO, RB>(g, e, tid))];
+        for (int e = 0; e < R; ++e) v[g * R + e] = lds[lds_idx(pass_index<LOGN, LO, RB, WV>(g, e, tid))];
 }
 
 // Cooley-Tukey stages over bits LO+RB-1 .. LO. Values enter and leave in [0, 4q).
-template <int LOGN, int LO, int RB>
+template <int LOGN, int LO, int RB, bool WV = false>
 __device__ __forceinline__ void fwd_pass(u64 (&v)[16], int tid, const u64 *__restrict__ tw,
                                          const u64 *__restrict__ tws, u64 q, u64 q2, u64 qn, u64 nq2) {
     constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         // for LO >= 6 the 64 lanes of a wave share hi: make that visible so twiddles use scalar loads
-        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane((g * Geo<LOGN>::T + tid) >> LO)
-                               : (g * Geo<LOGN>::T + tid) >> LO;
+        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane(pass_hi<LOGN, LO, RB, WV>(g, tid))
+                               : pass_hi<LOGN, LO, RB, WV>(g, tid);
 #pragma unroll
         for (int sb = RB - 1; sb >= 0; --sb) {
             const int b = LO + sb, half = 1 << sb;
@@ -222,15 +251,15 @@ __device__ __forceinline__ void fwd_pass(u64 (&v)[16], int tid, const u64 *__res
 }
 
 // Gentleman-Sande stages over bits LO .. LO+RB-1. Values enter and leave in [0, 2q).
-template <int LOGN, int LO, int RB>
+template <int LOGN, int LO, int RB, bool WV = false>
 __device__ __forceinline__ void inv_pass(u64 (&v)[16], int tid, const u64 *__restrict__ tw,
                                          const u64 *__restrict__ tws, u64 q, u64 q2, u64 qn, u64 nq2) {
     constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         // for LO >= 6 the 64 lanes of a wave share hi: make that visible so twiddles use scalar loads
-        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane((g * Geo<LOGN>::T + tid) >> LO)
-                               : (g * Geo<LOGN>::T + tid) >> LO;
+        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane(pass_hi<LOGN, LO, RB, WV>(g, tid))
+                               : pass_hi<LOGN, LO, RB, WV>(g, tid);
 #pragma unroll
         for (int sb = 0; sb < RB; ++sb) {
             const int b = LO + sb, half = 1 << sb;
@@ -250,15 +279,15 @@ __device__ __forceinline__ void inv_pass(u64 (&v)[16], int tid, const u64 *__res
 // FP64 Cooley-Tukey stages (prime < 2^41): t = w y with |t| <= 0.52 q, outputs x + t and x - t.
 // From canonical inputs the magnitude stays below (1 + 0.52 s) q after s stages (< 2^45 after 14),
 // so no intermediate reduction is needed.
-template <int LOGN, int LO, int RB>
+template <int LOGN, int LO, int RB, bool WV = false>
 __device__ __forceinline__ void fwd_pass_fp(double (&v)[16], int tid, const double *__restrict__ tw, double q,
                                             double qinv) {
     constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         // for LO >= 6 the 64 lanes of a wave share hi: make that visible so twiddles use scalar loads
-        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane((g * Geo<LOGN>::T + tid) >> LO)
-                               : (g * Geo<LOGN>::T + tid) >> LO;
+        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane(pass_hi<LOGN, LO, RB, WV>(g, tid))
+                               : pass_hi<LOGN, LO, RB, WV>(g, tid);
 #pragma unroll
         for (int sb = RB - 1; sb >= 0; --sb) {
             const int b = LO + sb, half = 1 << sb;
@@ -278,15 +307,15 @@ __device__ __forceinline__ void fwd_pass_fp(double (&v)[16], int tid, const doub
 // FP64 Gentleman-Sande stages: x + y and (x - y) w. Sums double per stage, so every value is
 // centered (|v| <= 0.51 q) at the end of each pass: within a pass of at most 4 stages magnitudes
 // stay below 16 q < 2^45.
-template <int LOGN, int LO, int RB>
+template <int LOGN, int LO, int RB, bool WV = false>
 __device__ __forceinline__ void inv_pass_fp(double (&v)[16], int tid, const double *__restrict__ tw, double q,
                                             double qinv) {
     constexpr int R = 1 << RB, G = 16 / R, N = Geo<LOGN>::N;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         // for LO >= 6 the 64 lanes of a wave share hi: make that visible so twiddles use scalar loads
-        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane((g * Geo<LOGN>::T + tid) >> LO)
-                               : (g * Geo<LOGN>::T + tid) >> LO;
+        const int hi = LO >= 6 ? __builtin_amdgcn_readfirstlane(pass_hi<LOGN, LO, RB, WV>(g, tid))
+                               : pass_hi<LOGN, LO, RB, WV>(g, tid);
 #pragma unroll
         for (int sb = 0; sb < RB; ++sb) {
             const int b = LO + sb, half = 1 << sb;
@@ -304,136 +333,130 @@ __device__ __forceinline__ void inv_pass_fp(double (&v)[16], int tid, const doub
     for (int e = 0; e < 16; ++e) v[e] = fp_center(v[e], q, qinv);
 }
 
-// FP64 cores: same pass plans and LDS exchanges as the integer cores below, on doubles.
+// Pass plans (bit ranges, lowest bit first for each pass):
+//   N = 2^12: [8,12) [4,8) [0,4)      N = 2^13: [9,13) [6,9) [3,6) [0,3)
+//   N = 2^14: [10,14) [6,10) [3,6) [0,3)
+// The top pass spans the whole residue (workgroup mapping: thread tid holds elements tid + T e)
+// and is the only one that needs a workgroup barrier; the passes below it are wave-local (see
+// pass_index), so each wave runs them on its own 1024 elements with no barrier, overlapping the
+// other waves' exchanges. The arithmetic of every butterfly is the same whatever the mapping.
+//
+// Forward: v holds elements j = tid + T e on entry; on exit the transformed residue is in LDS
+// (lds_idx(j)), values in [0, 4q) (integer) or |v| < 2^45 (FP64), and wave w's elements
+// [1024 w, 1024 w + 1024) are visible to wave w (read them through wave_elem).
+// Inverse: wave w's elements are in LDS (written by the wave itself, then wave_sync) on entry; on
+// exit v holds elements j = tid + T e, values in [0, 2q) (integer) or centered (FP64), not yet
+// multiplied by N^{-1}.
+template <int LOGN, typename T, typename Pass>
+__device__ __forceinline__ void fwd_plan(T (&v)[16], T *lds, int tid, Pass &&pass) {
+    if constexpr (LOGN == 12) {
+        pass(std::integral_constant<int, 8>{}, std::integral_constant<int, 4>{}, std::false_type{});
+        to_lds<12, 8, 4>(v, lds, tid); __syncthreads();
+        from_lds<12, 4, 4, true>(v, lds, tid);
+        pass(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{}, std::true_type{});
+        to_lds<12, 4, 4, true>(v, lds, tid); wave_sync();
+        from_lds<12, 0, 4, true>(v, lds, tid);
+        pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{}, std::true_type{});
+        to_lds<12, 0, 4, true>(v, lds, tid); wave_sync();
+    } else if constexpr (LOGN == 13) {
+        pass(std::integral_constant<int, 9>{}, std::integral_constant<int, 4>{}, std::false_type{});
+        to_lds<13, 9, 4>(v, lds, tid); __syncthreads();
+        from_lds<13, 6, 3, true>(v, lds, tid);
+        pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 3>{}, std::true_type{});
+        to_lds<13, 6, 3, true>(v, lds, tid); wave_sync();
+        from_lds<13, 3, 3, true>(v, lds, tid);
+        pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{}, std::true_type{});
+        to_lds<13, 3, 3, true>(v, lds, tid); wave_sync();
+        from_lds<13, 0, 3, true>(v, lds, tid);
+        pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, std::true_type{});
+        to_lds<13, 0, 3, true>(v, lds, tid); wave_sync();
+    } else {
+        static_assert(LOGN == 14, "unsupported ring degree");
+        pass(std::integral_constant<int, 10>{}, std::integral_constant<int, 4>{}, std::false_type{});
+        to_lds<14, 10, 4>(v, lds, tid); __syncthreads();
+        from_lds<14, 6, 4, true>(v, lds, tid);
+        pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 4>{}, std::true_type{});
+        to_lds<14, 6, 4, true>(v, lds, tid); wave_sync();
+        from_lds<14, 3, 3, true>(v, lds, tid);
+        pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{}, std::true_type{});
+        to_lds<14, 3, 3, true>(v, lds, tid); wave_sync();
+        from_lds<14, 0, 3, true>(v, lds, tid);
+        pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, std::true_type{});
+        to_lds<14, 0, 3, true>(v, lds, tid); wave_sync();
+    }
+}
+
+template <int LOGN, typename T, typename Pass>
+__device__ __forceinline__ void inv_plan(T (&v)[16], T *lds, int tid, Pass &&pass) {
+    if constexpr (LOGN == 12) {
+        from_lds<12, 0, 4, true>(v, lds, tid);
+        pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{}, std::true_type{});
+        to_lds<12, 0, 4, true>(v, lds, tid); wave_sync();
+        from_lds<12, 4, 4, true>(v, lds, tid);
+        pass(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{}, std::true_type{});
+        to_lds<12, 4, 4, true>(v, lds, tid); __syncthreads();
+        from_lds<12, 8, 4>(v, lds, tid);
+        pass(std::integral_constant<int, 8>{}, std::integral_constant<int, 4>{}, std::false_type{});
+    } else if constexpr (LOGN == 13) {
+        from_lds<13, 0, 3, true>(v, lds, tid);
+        pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, std::true_type{});
+        to_lds<13, 0, 3, true>(v, lds, tid); wave_sync();
+        from_lds<13, 3, 3, true>(v, lds, tid);
+        pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{}, std::true_type{});
+        to_lds<13, 3, 3, true>(v, lds, tid); wave_sync();
+        from_lds<13, 6, 3, true>(v, lds, tid);
+        pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 3>{}, std::true_type{});
+        to_lds<13, 6, 3, true>(v, lds, tid); __syncthreads();
+        from_lds<13, 9, 4>(v, lds, tid);
+        pass(std::integral_constant<int, 9>{}, std::integral_constant<int, 4>{}, std::false_type{});
+    } else {
+        static_assert(LOGN == 14, "unsupported ring degree");
+        from_lds<14, 0, 3, true>(v, lds, tid);
+        pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, std::true_type{});
+        to_lds<14, 0, 3, true>(v, lds, tid); wave_sync();
+        from_lds<14, 3, 3, true>(v, lds, tid);
+        pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{}, std::true_type{});
+        to_lds<14, 3, 3, true>(v, lds, tid); wave_sync();
+        from_lds<14, 6, 4, true>(v, lds, tid);
+        pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 4>{}, std::true_type{});
+        to_lds<14, 6, 4, true>(v, lds, tid); __syncthreads();
+        from_lds<14, 10, 4>(v, lds, tid);
+        pass(std::integral_constant<int, 10>{}, std::integral_constant<int, 4>{}, std::false_type{});
+    }
+}
+
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd_core_fp(double (&v)[16], double *lds, int tid, const double *tw,
                                                 double q, double qinv) {
-    if constexpr (LOGN == 12) {
-        fwd_pass_fp<12, 8, 4>(v, tid, tw, q, qinv);
-        to_lds<12, 8, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 4, 4>(v, lds, tid); fwd_pass_fp<12, 4, 4>(v, tid, tw, q, qinv);
-        to_lds<12, 4, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 0, 4>(v, lds, tid); fwd_pass_fp<12, 0, 4>(v, tid, tw, q, qinv);
-        to_lds<12, 0, 4>(v, lds, tid); __syncthreads();
-    } else if constexpr (LOGN == 13) {
-        fwd_pass_fp<13, 9, 4>(v, tid, tw, q, qinv);
-        to_lds<13, 9, 4>(v, lds, tid); __syncthreads();
-        from_lds<13, 6, 3>(v, lds, tid); fwd_pass_fp<13, 6, 3>(v, tid, tw, q, qinv);
-        to_lds<13, 6, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 3, 3>(v, lds, tid); fwd_pass_fp<13, 3, 3>(v, tid, tw, q, qinv);
-        to_lds<13, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 0, 3>(v, lds, tid); fwd_pass_fp<13, 0, 3>(v, tid, tw, q, qinv);
-        to_lds<13, 0, 3>(v, lds, tid); __syncthreads();
-    } else {
-        static_assert(LOGN == 14, "unsupported ring degree");
-        fwd_pass_fp<14, 10, 4>(v, tid, tw, q, qinv);
-        to_lds<14, 10, 4>(v, lds, tid); __syncthreads();
-        from_lds<14, 6, 4>(v, lds, tid); fwd_pass_fp<14, 6, 4>(v, tid, tw, q, qinv);
-        to_lds<14, 6, 4>(v, lds, tid); __syncthreads();
-        from_lds<14, 3, 3>(v, lds, tid); fwd_pass_fp<14, 3, 3>(v, tid, tw, q, qinv);
-        to_lds<14, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<14, 0, 3>(v, lds, tid); fwd_pass_fp<14, 0, 3>(v, tid, tw, q, qinv);
-        to_lds<14, 0, 3>(v, lds, tid); __syncthreads();
-    }
+    fwd_plan<LOGN>(v, lds, tid, [&](auto lo, auto rb, auto wv) {
+        fwd_pass_fp<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(v, tid, tw, q, qinv);
+    });
 }
 
 template <int LOGN>
 __device__ __forceinline__ void ntt_inv_core_fp(double (&v)[16], double *lds, int tid, const double *tw,
                                                 double q, double qinv) {
-    if constexpr (LOGN == 12) {
-        from_lds<12, 0, 4>(v, lds, tid); inv_pass_fp<12, 0, 4>(v, tid, tw, q, qinv);
-        to_lds<12, 0, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 4, 4>(v, lds, tid); inv_pass_fp<12, 4, 4>(v, tid, tw, q, qinv);
-        to_lds<12, 4, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 8, 4>(v, lds, tid); inv_pass_fp<12, 8, 4>(v, tid, tw, q, qinv);
-    } else if constexpr (LOGN == 13) {
-        from_lds<13, 0, 3>(v, lds, tid); inv_pass_fp<13, 0, 3>(v, tid, tw, q, qinv);
-        to_lds<13, 0, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 3, 3>(v, lds, tid); inv_pass_fp<13, 3, 3>(v, tid, tw, q, qinv);
-        to_lds<13, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 6, 3>(v, lds, tid); inv_pass_fp<13, 6, 3>(v, tid, tw, q, qinv);
-        to_lds<13, 6, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 9, 4>(v, lds, tid); inv_pass_fp<13, 9, 4>(v, tid, tw, q, qinv);
-    } else {
-        static_assert(LOGN == 14, "unsupported ring degree");
-        from_lds<14, 0, 3>(v, lds, tid); inv_pass_fp<14, 0, 3>(v, tid, tw, q, qinv);
-        to_lds<14, 0, 3>(v, lds, tid); __syncthreads();
-        from_lds<14, 3, 3>(v, lds, tid); inv_pass_fp<14, 3, 3>(v, tid, tw, q, qinv);
-        to_lds<14, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<14, 6, 4>(v, lds, tid); inv_pass_fp<14, 6, 4>(v, tid, tw, q, qinv);
-        to_lds<14, 6, 4>(v, lds, tid); __syncthreads();
-        from_lds<14, 10, 4>(v, lds, tid); inv_pass_fp<14, 10, 4>(v, tid, tw, q, qinv);
-    }
+    inv_plan<LOGN>(v, lds, tid, [&](auto lo, auto rb, auto wv) {
+        inv_pass_fp<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(v, tid, tw, q, qinv);
+    });
 }
 
-// Pass plans (bit ranges, lowest bit first for each pass):
-//   N = 2^12: [8,12) [4,8) [0,4)      N = 2^13: [9,13) [6,9) [3,6) [0,3)
-//   N = 2^14: [10,14) [6,10) [3,6) [0,3)
-// Forward: v holds elements j = tid + T e on entry; on exit the transformed residue is in LDS
-// (lds_idx(j)), values in [0, 4q), after a barrier.
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd_core(u64 (&v)[16], u64 *lds, int tid, const u64 *tw,
                                              const u64 *tws, const PrimeConst &pc) {
     const u64 q = pc.q, q2 = pc.q2, qn = pc.qn, nq2 = pc.nq2;
-    if constexpr (LOGN == 12) {
-        fwd_pass<12, 8, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<12, 8, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 4, 4>(v, lds, tid); fwd_pass<12, 4, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<12, 4, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 0, 4>(v, lds, tid); fwd_pass<12, 0, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<12, 0, 4>(v, lds, tid); __syncthreads();
-    } else if constexpr (LOGN == 13) {
-        fwd_pass<13, 9, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<13, 9, 4>(v, lds, tid); __syncthreads();
-        from_lds<13, 6, 3>(v, lds, tid); fwd_pass<13, 6, 3>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<13, 6, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 3, 3>(v, lds, tid); fwd_pass<13, 3, 3>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<13, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 0, 3>(v, lds, tid); fwd_pass<13, 0, 3>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<13, 0, 3>(v, lds, tid); __syncthreads();
-    } else {
-        static_assert(LOGN == 14, "unsupported ring degree");
-        fwd_pass<14, 10, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<14, 10, 4>(v, lds, tid); __syncthreads();
-        from_lds<14, 6, 4>(v, lds, tid); fwd_pass<14, 6, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<14, 6, 4>(v, lds, tid); __syncthreads();
-        from_lds<14, 3, 3>(v, lds, tid); fwd_pass<14, 3, 3>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<14, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<14, 0, 3>(v, lds, tid); fwd_pass<14, 0, 3>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<14, 0, 3>(v, lds, tid); __syncthreads();
-    }
+    fwd_plan<LOGN>(v, lds, tid, [&](auto lo, auto rb, auto wv) {
+        fwd_pass<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(v, tid, tw, tws, q, q2, qn, nq2);
+    });
 }
 
-// Inverse: the residue (values in [0, 2q)) is in LDS at lds_idx(j) after a barrier on entry; on
-// exit v holds elements j = tid + T e, values in [0, 2q), not yet multiplied by N^{-1}.
 template <int LOGN>
 __device__ __forceinline__ void ntt_inv_core(u64 (&v)[16], u64 *lds, int tid, const u64 *tw,
                                              const u64 *tws, const PrimeConst &pc) {
     const u64 q = pc.q, q2 = pc.q2, qn = pc.qn, nq2 = pc.nq2;
-    if constexpr (LOGN == 12) {
-        from_lds<12, 0, 4>(v, lds, tid); inv_pass<12, 0, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<12, 0, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 4, 4>(v, lds, tid); inv_pass<12, 4, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<12, 4, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 8, 4>(v, lds, tid); inv_pass<12, 8, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-    } else if constexpr (LOGN == 13) {
-        from_lds<13, 0, 3>(v, lds, tid); inv_pass<13, 0, 3>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<13, 0, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 3, 3>(v, lds, tid); inv_pass<13, 3, 3>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<13, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 6, 3>(v, lds, tid); inv_pass<13, 6, 3>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<13, 6, 3>(v, lds, tid); __syncthreads();
-        from_lds<13, 9, 4>(v, lds, tid); inv_pass<13, 9, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-    } else {
-        static_assert(LOGN == 14, "unsupported ring degree");
-        from_lds<14, 0, 3>(v, lds, tid); inv_pass<14, 0, 3>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<14, 0, 3>(v, lds, tid); __syncthreads();
-        from_lds<14, 3, 3>(v, lds, tid); inv_pass<14, 3, 3>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<14, 3, 3>(v, lds, tid); __syncthreads();
-        from_lds<14, 6, 4>(v, lds, tid); inv_pass<14, 6, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-        to_lds<14, 6, 4>(v, lds, tid); __syncthreads();
-        from_lds<14, 10, 4>(v, lds, tid); inv_pass<14, 10, 4>(v, tid, tw, tws, q, q2, qn, nq2);
-    }
+    inv_plan<LOGN>(v, lds, tid, [&](auto lo, auto rb, auto wv) {
+        inv_pass<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(v, tid, tw, tws, q, q2, qn, nq2);
+    });
 }
 
 __device__ __forceinline__ long res_offset(const ResMap &m, int r) {
@@ -447,7 +470,8 @@ __device__ __forceinline__ long res_offset(const ResMap &m, int r) {
 // in [0, q) either way, so the results are the same integers.
 
 // Forward transform of canonical values v[e] (element tid + T e) held in registers; the result is
-// left in LDS (as doubles for an FP64 prime, as lazy [0, 4q) integers otherwise). Returns fp.
+// left in LDS (as doubles for an FP64 prime, as lazy [0, 4q) integers otherwise), wave w's part
+// (elements wave_elem(tid, e)) visible to wave w. Returns fp.
 template <int LOGN>
 __device__ __forceinline__ bool fwd_transform(u64 (&v)[16], u64 *lds, int tid, const Tables &tab, int pi,
                                               const PrimeConst &p) {
@@ -485,7 +509,7 @@ k_ntt_fwd(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
     for (int e = 0; e < 16; ++e) v[e] = src[tid + T * e];
     const bool fp = fwd_transform<LOGN>(v, lds, tid, tab, pi, p);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) dst[tid + T * e] = fwd_result(lds, tid + T * e, fp, p);
+    for (int e = 0; e < 16; ++e) dst[wave_elem(tid, e)] = fwd_result(lds, wave_elem(tid, e), fp, p);
 }
 
 template <int LOGN>
@@ -501,8 +525,8 @@ k_ntt_inv(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
     if (p.fp) {
         double *dl = reinterpret_cast<double *>(lds);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) dl[lds_idx(tid + T * e)] = u64_to_fp(src[tid + T * e]);
-        __syncthreads();
+        for (int e = 0; e < 16; ++e) dl[lds_idx(wave_elem(tid, e))] = u64_to_fp(src[wave_elem(tid, e)]);
+        wave_sync();
         double d[16];
         ntt_inv_core_fp<LOGN>(d, dl, tid, reinterpret_cast<const double *>(tab.itws + (long)pi * N), p.qd, p.qinv);
 #pragma unroll
@@ -510,8 +534,8 @@ k_ntt_inv(const u64 *__restrict__ in, ResMap imap, u64 *__restrict__ out, ResMap
         return;
     }
 #pragma unroll
-    for (int e = 0; e < 16; ++e) lds[lds_idx(tid + T * e)] = src[tid + T * e];
-    __syncthreads();
+    for (int e = 0; e < 16; ++e) lds[lds_idx(wave_elem(tid, e))] = src[wave_elem(tid, e)];
+    wave_sync();
     u64 v[16];
     ntt_inv_core<LOGN>(v, lds, tid, tab.itw + (long)pi * N, tab.itws + (long)pi * N, p);
 #pragma unroll
@@ -571,10 +595,12 @@ k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u6
     for (int e = 0; e < 16; ++e) v[e] = lift_centered(src[tid + T * e], qj, qj_mod, p);
     if (fwd_transform<LOGN>(v, lds, tid, tab, pt, p)) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) __builtin_nontemporal_store(lds[lds_idx(tid + T * e)], &dst[tid + T * e]);
+        for (int e = 0; e < 16; ++e)
+            __builtin_nontemporal_store(lds[lds_idx(wave_elem(tid, e))], &dst[wave_elem(tid, e)]);
     } else {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) __builtin_nontemporal_store(fwd_result(lds, tid + T * e, false, p), &dst[tid + T * e]);
+        for (int e = 0; e < 16; ++e)
+            __builtin_nontemporal_store(fwd_result(lds, wave_elem(tid, e), false, p), &dst[wave_elem(tid, e)]);
     }
 }
 
@@ -619,7 +645,7 @@ k_drop(const u64 *__restrict__ x, GrpMap xm, const u64 *__restrict__ last, u64 *
         const double *dl = reinterpret_cast<const double *>(lds);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const int jj = tid + T * e;
+            const int jj = wave_elem(tid, e);
             double val = fp_mul(u64_to_fp(xi[jj]) - dl[lds_idx(jj)], cc.invd, p.qd, p.qinv);
             if (has_add) val += u64_to_fp(ap[g == 1 ? jj : galois_src(jj, g, LOGN)]);
             dst[jj] = fp_to_u64(val, p.qd, p.qinv);
@@ -628,7 +654,7 @@ k_drop(const u64 *__restrict__ x, GrpMap xm, const u64 *__restrict__ last, u64 *
     }
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const int jj = tid + T * e;
+        const int jj = wave_elem(tid, e);
         const u64 ext = red4(lds[lds_idx(jj)], p.q, p.q2);
         u64 val = red2(shoup_lazy(sub_mod(xi[jj], ext, p.q), cc.inv, cc.invs, p.q, p.qn), p.q);
         if (has_add) val = add_mod(val, ap[g == 1 ? jj : galois_src(jj, g, LOGN)], p.q);
@@ -658,7 +684,7 @@ k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, 
     const bool fp = fwd_transform<LOGN>(v, lds, tid, tab, pi, p);
     u64 *dst = out + ((long)grp * pl.n + slot) * N;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) dst[tid + T * e] = fwd_result(lds, tid + T * e, fp, p);
+    for (int e = 0; e < 16; ++e) dst[wave_elem(tid, e)] = fwd_result(lds, wave_elem(tid, e), fp, p);
 }
 
 // ---------------------------------------------------------------- 30-bit limb products
@@ -1595,6 +1621,8 @@ void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const Ke
     const int xo = kn.keyip_xcd ? 1 : 0;
     unsigned lt60 = 0;
     for (int i = 0; i <= nq && kn.mac_limb; ++i) lt60 |= (tab.host_lt60[i] ? 1u : 0u) << i;
+    // kn.keyip_rr rotations per workgroup share each digit word when the digits are hoisted
+    // (dr = 0) and the fold term, if any, is the same for every rotation (sr = 0)
     // kn.keyip_rr rotations per workgroup share each digit word when the digits are hoisted
     // (dr = 0) and the fold term, if any, is the same for every rotation (sr = 0)
     int rr = kn.keyip_rr < 1 ? 1 : kn.keyip_rr > 4 ? 4 : kn.keyip_rr;
