@@ -123,7 +123,11 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
  *   CTL_KNOB_KEYIP_RR    hoisted rotations per key-product workgroup, which read each digit word
  *                        once for all of them (1..4, default 4; at most 3 with 7 or more primes,
  *                        for the register budget; launches whose rotations have their own digits
- *                        use 1).
+ *                        use 1);
+ *   CTL_KNOB_NTT_SPLIT   launches of fewer residue transforms than this (0..4096, default 128; 0:
+ *                        never) split every transform over N/1024 single-wave workgroups in two
+ *                        launches through a workspace buffer, instead of one workgroup per
+ *                        transform (small batches fill the GPU; same residues).
  * Out-of-range values give CTL_EINVAL and leave the knob unchanged. */
 #define CTL_KNOB_MAC_CHUNK 0
 #define CTL_KNOB_MAC_CTS 1
@@ -132,6 +136,7 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
 #define CTL_KNOB_NTT_XCD 4
 #define CTL_KNOB_MAC_LIMB 5
 #define CTL_KNOB_KEYIP_RR 6
+#define CTL_KNOB_NTT_SPLIT 7
 int ctl_knob_set(ctl_ctx *ctx, int knob, int value);
 int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value);
 

@@ -24,6 +24,7 @@ CANDIDATES: Dict[str, List[int]] = {
     "ntt_xcd": [1, 0],
     "mac_limb": [1, 0],
     "keyip_rr": [4, 3, 2, 1],
+    "ntt_split": [128, 64, 256, 0],
 }
 
 

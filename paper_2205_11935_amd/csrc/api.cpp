@@ -49,7 +49,7 @@ const char *const kFamilyNames[F_COUNT] = {"k_ntt_fwd", "k_ntt_inv", "k_modup", 
 // Workspace slots: each grows on demand and is reused by later calls on the same context.
 enum Slot {
     S_COEF, S_DIG, S_U, S_PLAST, S_ROT, S_INNER, S_SUM, S_LAST, S_TENSOR, S_SQ, S_REP,
-    S_FWD_A, S_FWD_B, S_FWD_C, S_COEF2, S_ROT2, S_MISC, S_P_Z2, S_P_T, S_P_U, S_P_W, S_P_V, S_COUNT
+    S_FWD_A, S_FWD_B, S_FWD_C, S_COEF2, S_ROT2, S_MISC, S_P_Z2, S_P_T, S_P_U, S_P_W, S_P_V, S_NTT_TMP, S_COUNT
 };
 
 }  // namespace
@@ -185,6 +185,22 @@ int slot(ctl_ctx *c, Slot s, size_t words, hipStream_t st, u64 **out) {
 }
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+// Buffer for a launch of `count` residue transforms split over N/1024 workgroups each (the NTT
+// launches take it when the launch has fewer transforms than the ntt_split knob), or null for the
+// one-workgroup form: at or above the knob, inside the entry point that allocates nothing, or when
+// a frozen workspace cannot hold it (the one-workgroup form gives the same residues).
+u64 *split_buf(ctl_ctx *c, hipStream_t st, int count) {
+    if (count >= c->knobs.ntt_split || c->arena) return nullptr;
+    const std::string err = g_err;
+    u64 *t = nullptr;
+    // sized for the largest launch that splits, so that one small warm-up run reserves it
+    if (slot(c, S_NTT_TMP, (size_t)std::max(count, c->knobs.ntt_split - 1) * c->hp.n, st, &t) != CTL_OK) {
+        g_err = err;                             // not an error of the call: fall back
+        return nullptr;
+    }
+    return t;
+}
 
 // Brackets one launch with events when the context's instrumentation is on.
 class Prof {
@@ -381,8 +397,8 @@ int modup_digits(ctl_ctx *c, hipStream_t st, int k, int G, const u64 *d, const R
     u64 *coef, *dig;
     CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
     CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
-    { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st); }
-    { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st); }
+    { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st, split_buf(c, st, G * k)); }
+    { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st, split_buf(c, st, G * k * (k + 1))); }
     *dig_out = dig;
     return check_launch();
 }
@@ -461,8 +477,8 @@ int keyswitch_lower(ctl_ctx *c, hipStream_t st, int k, int groups, const u64 *U,
     pm.gstride = k + 1;
     pm.ostride = k + 1;
     pm.prime[0] = nq;
-    { CTL_PROF(F_NTT_INV, groups, fp_share_range(c, 0, true)); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), groups, c->tab, st); }
-    { CTL_PROF(F_DROP, (double)groups * k, fp_share_range(c, k, false)); launch_drop(logn, U, plast, out, groups, k, nq, add, c->tab, c->knobs, st); }
+    { CTL_PROF(F_NTT_INV, groups, fp_share_range(c, 0, true)); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), groups, c->tab, st, split_buf(c, st, groups)); }
+    { CTL_PROF(F_DROP, (double)groups * k, fp_share_range(c, k, false)); launch_drop(logn, U, plast, out, groups, k, nq, add, c->tab, c->knobs, st, nullptr, split_buf(c, st, groups * k)); }
     return check_launch();
 }
 
@@ -489,12 +505,12 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
     m.gstride = k;
     m.ostride = k;
     m.prime[0] = k - 1;
-    { CTL_PROF(F_NTT_INV, B * 2, fp_share(c, &m.prime[0], 1)); launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, st); }
+    { CTL_PROF(F_NTT_INV, B * 2, fp_share(c, &m.prime[0], 1)); launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, st, split_buf(c, st, B * 2)); }
     DropAdd add{};
     add.R = 1;
     add.mask = 0;
     add.gal[0] = 1;
-    { CTL_PROF(F_DROP, B * 2 * (k - 1), fp_share_range(c, k - 1, false)); launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, c->knobs, st); }
+    { CTL_PROF(F_DROP, B * 2 * (k - 1), fp_share_range(c, k - 1, false)); launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, c->knobs, st, nullptr, split_buf(c, st, B * 2 * (k - 1))); }
     return check_launch();
 }
 
@@ -740,9 +756,9 @@ int dense_qp_groups(ctl_ctx *c, hipStream_t st, const ctl_model *const *models, 
             pm.gstride = 2L * (k + 1);
             pm.ostride = (long)q.t2 * 2 * (k + 1);
             pm.prime[0] = nq;
-            { CTL_PROF(F_NTT_INV, q.B * q.R2, fp_share_range(c, 0, true)); launch_ntt(logn, true, ig, pm, plast + q.i1_off * N, dense_map(1, nq), q.B * q.R2, c->tab, st); }
+            { CTL_PROF(F_NTT_INV, q.B * q.R2, fp_share_range(c, 0, true)); launch_ntt(logn, true, ig, pm, plast + q.i1_off * N, dense_map(1, nq), q.B * q.R2, c->tab, st, split_buf(c, st, q.B * q.R2)); }
             GrpMap xm{3L * (k + 1) * N, (long)q.t2 * ext, ext, q.R2};
-            { CTL_PROF(F_DROP, (double)q.B * q.R2 * k, fp_share_range(c, k, false)); launch_drop(logn, ig, plast + q.i1_off * N, i1 + q.i1_off * k * N, q.B * q.R2, k, nq, none, c->tab, c->knobs, st, &xm); }
+            { CTL_PROF(F_DROP, (double)q.B * q.R2 * k, fp_share_range(c, k, false)); launch_drop(logn, ig, plast + q.i1_off * N, i1 + q.i1_off * k * N, q.B * q.R2, k, nq, none, c->tab, c->knobs, st, &xm, split_buf(c, st, q.B * q.R2 * k)); }
         }
         u64 *dig, *U;
         CTL_TRY(modup_digits(c, st, k, (int)i1_w, i1, dense_map(k), &dig));   // one ModUp for every group
@@ -1425,6 +1441,10 @@ int ctl_knob_set(ctl_ctx *ctx, int knob, int value) {
             if (value < 1 || value > 4) return fail(CTL_EINVAL, "rotations per key-product workgroup must lie in 1..4");
             ctx->knobs.keyip_rr = value;
             return CTL_OK;
+        case CTL_KNOB_NTT_SPLIT:
+            if (value < 0 || value > 4096) return fail(CTL_EINVAL, "the split threshold must lie in 0..4096");
+            ctx->knobs.ntt_split = value;
+            return CTL_OK;
         default:
             return fail(CTL_EINVAL, "unknown knob");
     }
@@ -1440,6 +1460,7 @@ int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value) {
         case CTL_KNOB_NTT_XCD: *value = ctx->knobs.ntt_xcd; return CTL_OK;
         case CTL_KNOB_MAC_LIMB: *value = ctx->knobs.mac_limb; return CTL_OK;
         case CTL_KNOB_KEYIP_RR: *value = ctx->knobs.keyip_rr; return CTL_OK;
+        case CTL_KNOB_NTT_SPLIT: *value = ctx->knobs.ntt_split; return CTL_OK;
         default: return fail(CTL_EINVAL, "unknown knob");
     }
 }

@@ -92,15 +92,19 @@ struct Knobs {
     int ntt_xcd = 1;             // XCD-grouped numbering of ModUp and ModDown workgroups
     int mac_limb = 1;            // integer-prime MAC by 30-bit limbs where every prime is below 2^60
     int keyip_rr = 4;            // key product: hoisted rotations per workgroup sharing digit words (1..4)
+    int ntt_split = 128;         // launches of fewer transforms split each over N/1024 workgroups (0: never)
 };
 
+// The NTT-bearing launches: with split_tmp (a buffer of one residue per transform of the launch,
+// [count][N] words) every transform is split over N / 1024 single-wave workgroups in two launches,
+// for launches of few transforms (the same residues either way).
 void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
-                int count, const Tables &tab, hipStream_t st);
+                int count, const Tables &tab, hipStream_t st, u64 *split_tmp = nullptr);
 void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
-                  int nq, const Tables &tab, const Knobs &kn, hipStream_t st);
+                  int nq, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp = nullptr);
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
                  const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st,
-                 const GrpMap *xmap = nullptr);
+                 const GrpMap *xmap = nullptr, u64 *split_tmp = nullptr);
 void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,
                     const Tables &tab, hipStream_t st);
 void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,

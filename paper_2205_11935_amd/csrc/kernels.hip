@@ -347,82 +347,93 @@ __device__ __forceinline__ void inv_pass_fp(double (&v)[16], int tid, const doub
 // Inverse: wave w's elements are in LDS (written by the wave itself, then wave_sync) on entry; on
 // exit v holds elements j = tid + T e, values in [0, 2q) (integer) or centered (FP64), not yet
 // multiplied by N^{-1}.
+// The passes below the top one, wave-local: `lt` is the thread index used for the LDS mapping
+// (the workgroup's tid with a residue-sized LDS, or the lane with one wave's 1024-element region),
+// the pass functor carries the tid used for the twiddles.
 template <int LOGN, typename T, typename Pass>
-__device__ __forceinline__ void fwd_plan(T (&v)[16], T *lds, int tid, Pass &&pass) {
+__device__ __forceinline__ void fwd_sub_plan(T (&v)[16], T *lds, int lt, Pass &&pass) {
     if constexpr (LOGN == 12) {
-        pass(std::integral_constant<int, 8>{}, std::integral_constant<int, 4>{}, std::false_type{});
-        to_lds<12, 8, 4>(v, lds, tid); __syncthreads();
-        from_lds<12, 4, 4, true>(v, lds, tid);
+        from_lds<12, 4, 4, true>(v, lds, lt);
         pass(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{}, std::true_type{});
-        to_lds<12, 4, 4, true>(v, lds, tid); wave_sync();
-        from_lds<12, 0, 4, true>(v, lds, tid);
+        to_lds<12, 4, 4, true>(v, lds, lt); wave_sync();
+        from_lds<12, 0, 4, true>(v, lds, lt);
         pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{}, std::true_type{});
-        to_lds<12, 0, 4, true>(v, lds, tid); wave_sync();
+        to_lds<12, 0, 4, true>(v, lds, lt); wave_sync();
     } else if constexpr (LOGN == 13) {
-        pass(std::integral_constant<int, 9>{}, std::integral_constant<int, 4>{}, std::false_type{});
-        to_lds<13, 9, 4>(v, lds, tid); __syncthreads();
-        from_lds<13, 6, 3, true>(v, lds, tid);
+        from_lds<13, 6, 3, true>(v, lds, lt);
         pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 3>{}, std::true_type{});
-        to_lds<13, 6, 3, true>(v, lds, tid); wave_sync();
-        from_lds<13, 3, 3, true>(v, lds, tid);
+        to_lds<13, 6, 3, true>(v, lds, lt); wave_sync();
+        from_lds<13, 3, 3, true>(v, lds, lt);
         pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{}, std::true_type{});
-        to_lds<13, 3, 3, true>(v, lds, tid); wave_sync();
-        from_lds<13, 0, 3, true>(v, lds, tid);
+        to_lds<13, 3, 3, true>(v, lds, lt); wave_sync();
+        from_lds<13, 0, 3, true>(v, lds, lt);
         pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, std::true_type{});
-        to_lds<13, 0, 3, true>(v, lds, tid); wave_sync();
+        to_lds<13, 0, 3, true>(v, lds, lt); wave_sync();
     } else {
         static_assert(LOGN == 14, "unsupported ring degree");
-        pass(std::integral_constant<int, 10>{}, std::integral_constant<int, 4>{}, std::false_type{});
-        to_lds<14, 10, 4>(v, lds, tid); __syncthreads();
-        from_lds<14, 6, 4, true>(v, lds, tid);
+        from_lds<14, 6, 4, true>(v, lds, lt);
         pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 4>{}, std::true_type{});
-        to_lds<14, 6, 4, true>(v, lds, tid); wave_sync();
-        from_lds<14, 3, 3, true>(v, lds, tid);
+        to_lds<14, 6, 4, true>(v, lds, lt); wave_sync();
+        from_lds<14, 3, 3, true>(v, lds, lt);
         pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{}, std::true_type{});
-        to_lds<14, 3, 3, true>(v, lds, tid); wave_sync();
-        from_lds<14, 0, 3, true>(v, lds, tid);
+        to_lds<14, 3, 3, true>(v, lds, lt); wave_sync();
+        from_lds<14, 0, 3, true>(v, lds, lt);
         pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, std::true_type{});
-        to_lds<14, 0, 3, true>(v, lds, tid); wave_sync();
+        to_lds<14, 0, 3, true>(v, lds, lt); wave_sync();
     }
 }
 
 template <int LOGN, typename T, typename Pass>
-__device__ __forceinline__ void inv_plan(T (&v)[16], T *lds, int tid, Pass &&pass) {
+__device__ __forceinline__ void inv_sub_plan(T (&v)[16], T *lds, int lt, Pass &&pass) {
     if constexpr (LOGN == 12) {
-        from_lds<12, 0, 4, true>(v, lds, tid);
+        from_lds<12, 0, 4, true>(v, lds, lt);
         pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{}, std::true_type{});
-        to_lds<12, 0, 4, true>(v, lds, tid); wave_sync();
-        from_lds<12, 4, 4, true>(v, lds, tid);
+        to_lds<12, 0, 4, true>(v, lds, lt); wave_sync();
+        from_lds<12, 4, 4, true>(v, lds, lt);
         pass(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{}, std::true_type{});
-        to_lds<12, 4, 4, true>(v, lds, tid); __syncthreads();
-        from_lds<12, 8, 4>(v, lds, tid);
-        pass(std::integral_constant<int, 8>{}, std::integral_constant<int, 4>{}, std::false_type{});
+        to_lds<12, 4, 4, true>(v, lds, lt); wave_sync();
     } else if constexpr (LOGN == 13) {
-        from_lds<13, 0, 3, true>(v, lds, tid);
+        from_lds<13, 0, 3, true>(v, lds, lt);
         pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, std::true_type{});
-        to_lds<13, 0, 3, true>(v, lds, tid); wave_sync();
-        from_lds<13, 3, 3, true>(v, lds, tid);
+        to_lds<13, 0, 3, true>(v, lds, lt); wave_sync();
+        from_lds<13, 3, 3, true>(v, lds, lt);
         pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{}, std::true_type{});
-        to_lds<13, 3, 3, true>(v, lds, tid); wave_sync();
-        from_lds<13, 6, 3, true>(v, lds, tid);
+        to_lds<13, 3, 3, true>(v, lds, lt); wave_sync();
+        from_lds<13, 6, 3, true>(v, lds, lt);
         pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 3>{}, std::true_type{});
-        to_lds<13, 6, 3, true>(v, lds, tid); __syncthreads();
-        from_lds<13, 9, 4>(v, lds, tid);
-        pass(std::integral_constant<int, 9>{}, std::integral_constant<int, 4>{}, std::false_type{});
+        to_lds<13, 6, 3, true>(v, lds, lt); wave_sync();
     } else {
         static_assert(LOGN == 14, "unsupported ring degree");
-        from_lds<14, 0, 3, true>(v, lds, tid);
+        from_lds<14, 0, 3, true>(v, lds, lt);
         pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, std::true_type{});
-        to_lds<14, 0, 3, true>(v, lds, tid); wave_sync();
-        from_lds<14, 3, 3, true>(v, lds, tid);
+        to_lds<14, 0, 3, true>(v, lds, lt); wave_sync();
+        from_lds<14, 3, 3, true>(v, lds, lt);
         pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{}, std::true_type{});
-        to_lds<14, 3, 3, true>(v, lds, tid); wave_sync();
-        from_lds<14, 6, 4, true>(v, lds, tid);
+        to_lds<14, 3, 3, true>(v, lds, lt); wave_sync();
+        from_lds<14, 6, 4, true>(v, lds, lt);
         pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 4>{}, std::true_type{});
-        to_lds<14, 6, 4, true>(v, lds, tid); __syncthreads();
-        from_lds<14, 10, 4>(v, lds, tid);
-        pass(std::integral_constant<int, 10>{}, std::integral_constant<int, 4>{}, std::false_type{});
+        to_lds<14, 6, 4, true>(v, lds, lt); wave_sync();
     }
+}
+
+// The whole transform in one workgroup: the top pass over bits [LOGN - 4, LOGN), one workgroup
+// exchange, then the wave-local passes.
+template <int LOGN, typename T, typename Pass>
+__device__ __forceinline__ void fwd_plan(T (&v)[16], T *lds, int tid, Pass &&pass) {
+    constexpr int TOP = LOGN - 4;
+    pass(std::integral_constant<int, TOP>{}, std::integral_constant<int, 4>{}, std::false_type{});
+    to_lds<LOGN, TOP, 4>(v, lds, tid);
+    __syncthreads();
+    fwd_sub_plan<LOGN>(v, lds, tid, pass);
+}
+
+template <int LOGN, typename T, typename Pass>
+__device__ __forceinline__ void inv_plan(T (&v)[16], T *lds, int tid, Pass &&pass) {
+    constexpr int TOP = LOGN - 4;
+    inv_sub_plan<LOGN>(v, lds, tid, pass);
+    __syncthreads();
+    from_lds<LOGN, TOP, 4>(v, lds, tid);
+    pass(std::integral_constant<int, TOP>{}, std::integral_constant<int, 4>{}, std::false_type{});
 }
 
 template <int LOGN>
@@ -659,6 +670,274 @@ k_drop(const u64 *__restrict__ x, GrpMap xm, const u64 *__restrict__ last, u64 *
         u64 val = red2(shoup_lazy(sub_mod(xi[jj], ext, p.q), cc.inv, cc.invs, p.q, p.qn), p.q);
         if (has_add) val = add_mod(val, ap[g == 1 ? jj : galois_src(jj, g, LOGN)], p.q);
         dst[jj] = val;
+    }
+}
+
+// ---------------------------------------------------------------- split transforms (few residues)
+// A launch of fewer residue transforms than CUs leaves most of the GPU idle, and one transform
+// takes a single CU tens of microseconds. Split, a transform runs as two launches of N / 1024
+// single-wave workgroups each: for the forward transform the top pass (each thread's 16 values
+// at stride T, as in the one-workgroup form), its result through a buffer (kept in L2), then each
+// wave's 1024 elements through the wave-local passes; the inverse the other way round. Every
+// butterfly is the one of the one-workgroup form, so the residues are the same. The operations
+// around the transform (lift on the load, combine on the store) come from an Op:
+//   prime(r)      prime-table index of residue r of the launch
+//   copy_only(r)  residue r is a plain copy (copy(r, j, tab) for element j), no transform
+//   load(r, j, p, tab)                          input of element j, canonical mod p
+//   store_fwd(r, j, x, fp, p, tab)              forward output: x as the LDS of the one-workgroup
+//                                               form holds it (double bits for an FP64 prime)
+//   store_inv(r, j, x, p) / store_inv_fp(r, j, d, p)   inverse output before the N^{-1} factor
+struct OpNtt {
+    const u64 *in;
+    ResMap imap;
+    u64 *out;
+    ResMap omap;
+    int logn;
+    __device__ int prime(int r) const { return imap.prime[r % imap.per]; }
+    __device__ bool copy_only(int) const { return false; }
+    __device__ void copy(int, int, const Tables &) const {}
+    __device__ u64 load(int r, int j, const PrimeConst &, const Tables &) const {
+        return in[(res_offset(imap, r) << logn) + j];
+    }
+    __device__ void store_fwd(int r, int j, u64 x, bool fp, const PrimeConst &p, const Tables &) const {
+        out[(res_offset(omap, r) << logn) + j] =
+            fp ? fp_to_u64(__longlong_as_double((long long)x), p.qd, p.qinv) : red4(x, p.q, p.q2);
+    }
+    __device__ void store_inv(int r, int j, u64 x, const PrimeConst &p) const {
+        out[(res_offset(omap, r) << logn) + j] = red2(shoup_lazy(x, p.ninv, p.ninvs, p.q, p.qn), p.q);
+    }
+    __device__ void store_inv_fp(int r, int j, double d, const PrimeConst &p) const {
+        out[(res_offset(omap, r) << logn) + j] = fp_to_u64(fp_mul(d, p.ninvd, p.qd, p.qinv), p.qd, p.qinv);
+    }
+};
+
+// ModUp (see k_modup), residues numbered r = gj (k + 1) + t.
+struct OpModup {
+    const u64 *coef, *d;
+    ResMap dmap;
+    u64 *digits;
+    int k, nq, logn;
+    __device__ int prime(int r) const { const int t = r % (k + 1); return t < k ? t : nq; }
+    __device__ bool copy_only(int r) const { return r % (k + 1) == (r / (k + 1)) % k; }
+    __device__ void copy(int r, int j, const Tables &tab) const {
+        const int t = r % (k + 1), gj = r / (k + 1);
+        const u64 x = d[(res_offset(dmap, gj) << logn) + j];
+        digits[((long)gj * (k + 1) + t << logn) + j] = tab.pc[t].fp ? (u64)__double_as_longlong(u64_to_fp(x)) : x;
+    }
+    __device__ u64 load(int r, int j, const PrimeConst &p, const Tables &tab) const {
+        const int t = r % (k + 1), gj = r / (k + 1), j0 = gj % k, pt = t < k ? t : nq;
+        return lift_centered(coef[((long)gj << logn) + j], tab.pc[j0].q, tab.cross[pt * kMaxMods + j0].qj_mod_qi, p);
+    }
+    __device__ void store_fwd(int r, int j, u64 x, bool fp, const PrimeConst &p, const Tables &) const {
+        const int t = r % (k + 1), gj = r / (k + 1);
+        __builtin_nontemporal_store(fp ? x : red4(x, p.q, p.q2), &digits[((long)gj * (k + 1) + t << logn) + j]);
+    }
+    __device__ void store_inv(int, int, u64, const PrimeConst &) const {}
+    __device__ void store_inv_fp(int, int, double, const PrimeConst &) const {}
+};
+
+// Drop the last modulus (see k_drop), residues numbered r = grp k + i.
+struct OpDrop {
+    const u64 *x;
+    GrpMap xm;
+    const u64 *last;
+    u64 *out;
+    int k, drop, logn;
+    DropAdd add;
+    __device__ int prime(int r) const { return r % k; }
+    __device__ bool copy_only(int) const { return false; }
+    __device__ void copy(int, int, const Tables &) const {}
+    __device__ u64 load(int r, int j, const PrimeConst &p, const Tables &tab) const {
+        const int i = r % k, grp = r / k;
+        return lift_centered(last[((long)grp << logn) + j], tab.pc[drop].q, tab.cross[i * kMaxMods + drop].qj_mod_qi, p);
+    }
+    __device__ void store_fwd(int r, int j, u64 v, bool fp, const PrimeConst &p, const Tables &tab) const {
+        const int i = r % k, grp = r / k;
+        const long N = 1L << logn;
+        const CrossConst cc = tab.cross[i * kMaxMods + drop];
+        const u64 xv = x[xm.off + (long)(grp / xm.R) * xm.sb + (long)(grp % xm.R) * xm.sr + (long)i * N + j];
+        const int c = grp & 1, rr = (grp >> 1) % add.R, b = (grp >> 1) / add.R;
+        const bool has_add = (add.mask >> c) & 1;
+        const u64 g = add.gal[rr];
+        const u64 av = has_add ? add.base[b * add.sb + rr * add.sr + c * add.sc + (long)i * N +
+                                          (g == 1 ? j : galois_src(j, g, logn))] : 0;
+        u64 *dst = out + ((long)grp * k + i) * N + j;
+        if (fp) {
+            double val = fp_mul(u64_to_fp(xv) - __longlong_as_double((long long)v), cc.invd, p.qd, p.qinv);
+            if (has_add) val += u64_to_fp(av);
+            *dst = fp_to_u64(val, p.qd, p.qinv);
+            return;
+        }
+        const u64 ext = red4(v, p.q, p.q2);
+        u64 val = red2(shoup_lazy(sub_mod(xv, ext, p.q), cc.inv, cc.invs, p.q, p.qn), p.q);
+        if (has_add) val = add_mod(val, av, p.q);
+        *dst = val;
+    }
+    __device__ void store_inv(int, int, u64, const PrimeConst &) const {}
+    __device__ void store_inv_fp(int, int, double, const PrimeConst &) const {}
+};
+
+template <int LOGN, class Op>
+__global__ void __launch_bounds__(64)
+k_fwd_top(Op op, u64 *__restrict__ tmp, int count, Tables tab) {
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T, S = T / 64;
+    const int r = blockIdx.x / S, tid = (blockIdx.x % S) * 64 + threadIdx.x;
+    if (r >= count) return;
+    if (op.copy_only(r)) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) op.copy(r, tid + T * e, tab);
+        return;
+    }
+    const int pi = op.prime(r);
+    const PrimeConst p = tab.pc[pi];
+    u64 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = op.load(r, tid + T * e, p, tab);
+    u64 *t = tmp + (long)r * N;
+    if (p.fp) {
+        double d[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) d[e] = u64_to_fp(v[e]);
+        fwd_pass_fp<LOGN, LOGN - 4, 4>(d, tid, reinterpret_cast<const double *>(tab.tws + (long)pi * N), p.qd, p.qinv);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) t[tid + T * e] = (u64)__double_as_longlong(d[e]);
+        return;
+    }
+    fwd_pass<LOGN, LOGN - 4, 4>(v, tid, tab.tw + (long)pi * N, tab.tws + (long)pi * N, p.q, p.q2, p.qn, p.nq2);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[tid + T * e] = v[e];
+}
+
+template <int LOGN, class Op>
+__global__ void __launch_bounds__(64)
+k_fwd_sub(Op op, const u64 *__restrict__ tmp, int count, Tables tab) {
+    __shared__ u64 lds[1024 + 32];
+    constexpr int N = Geo<LOGN>::N, S = N / 1024;
+    const int r = blockIdx.x / S, w = blockIdx.x % S, lane = threadIdx.x, tid = w * 64 + lane;
+    if (r >= count || op.copy_only(r)) return;
+    const int pi = op.prime(r);
+    const PrimeConst p = tab.pc[pi];
+    const u64 *t = tmp + (long)r * N + (w << 10);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) lds[lds_idx((e << 6) | lane)] = t[(e << 6) | lane];
+    wave_sync();
+    if (p.fp) {
+        double d[16];
+        const double *tw = reinterpret_cast<const double *>(tab.tws + (long)pi * N);
+        fwd_sub_plan<LOGN>(d, reinterpret_cast<double *>(lds), lane, [&](auto lo, auto rb, auto wv) {
+            fwd_pass_fp<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(d, tid, tw, p.qd, p.qinv);
+        });
+    } else {
+        u64 v[16];
+        const u64 *tw = tab.tw + (long)pi * N, *tws = tab.tws + (long)pi * N;
+        fwd_sub_plan<LOGN>(v, lds, lane, [&](auto lo, auto rb, auto wv) {
+            fwd_pass<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(v, tid, tw, tws, p.q, p.q2,
+                                                                                        p.qn, p.nq2);
+        });
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int jl = (e << 6) | lane;
+        op.store_fwd(r, (w << 10) | jl, lds[lds_idx(jl)], p.fp != 0, p, tab);
+    }
+}
+
+template <int LOGN, class Op>
+__global__ void __launch_bounds__(64)
+k_inv_sub(Op op, u64 *__restrict__ tmp, int count, Tables tab) {
+    __shared__ u64 lds[1024 + 32];
+    constexpr int N = Geo<LOGN>::N, S = N / 1024;
+    const int r = blockIdx.x / S, w = blockIdx.x % S, lane = threadIdx.x, tid = w * 64 + lane;
+    if (r >= count) return;
+    const int pi = op.prime(r);
+    const PrimeConst p = tab.pc[pi];
+    u64 *t = tmp + (long)r * N + (w << 10);
+    if (p.fp) {
+        double *dl = reinterpret_cast<double *>(lds);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) dl[lds_idx((e << 6) | lane)] = u64_to_fp(op.load(r, (w << 10) | (e << 6) | lane, p, tab));
+        wave_sync();
+        double d[16];
+        const double *tw = reinterpret_cast<const double *>(tab.itws + (long)pi * N);
+        inv_sub_plan<LOGN>(d, dl, lane, [&](auto lo, auto rb, auto wv) {
+            inv_pass_fp<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(d, tid, tw, p.qd, p.qinv);
+        });
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) lds[lds_idx((e << 6) | lane)] = op.load(r, (w << 10) | (e << 6) | lane, p, tab);
+        wave_sync();
+        u64 v[16];
+        const u64 *tw = tab.itw + (long)pi * N, *tws = tab.itws + (long)pi * N;
+        inv_sub_plan<LOGN>(v, lds, lane, [&](auto lo, auto rb, auto wv) {
+            inv_pass<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(v, tid, tw, tws, p.q, p.q2,
+                                                                                        p.qn, p.nq2);
+        });
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[(e << 6) | lane] = lds[lds_idx((e << 6) | lane)];
+}
+
+template <int LOGN, class Op>
+__global__ void __launch_bounds__(64)
+k_inv_top(Op op, const u64 *__restrict__ tmp, int count, Tables tab) {
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T, S = T / 64;
+    const int r = blockIdx.x / S, tid = (blockIdx.x % S) * 64 + threadIdx.x;
+    if (r >= count) return;
+    const int pi = op.prime(r);
+    const PrimeConst p = tab.pc[pi];
+    const u64 *t = tmp + (long)r * N;
+    if (p.fp) {
+        double d[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) d[e] = __longlong_as_double((long long)t[tid + T * e]);
+        inv_pass_fp<LOGN, LOGN - 4, 4>(d, tid, reinterpret_cast<const double *>(tab.itws + (long)pi * N), p.qd, p.qinv);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) op.store_inv_fp(r, tid + T * e, d[e], p);
+        return;
+    }
+    u64 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = t[tid + T * e];
+    inv_pass<LOGN, LOGN - 4, 4>(v, tid, tab.itw + (long)pi * N, tab.itws + (long)pi * N, p.q, p.q2, p.qn, p.nq2);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) op.store_inv(r, tid + T * e, v[e], p);
+}
+
+template <class Op>
+static void launch_split_fwd(int logn, const Op &op, u64 *tmp, int count, const Tables &tab, hipStream_t st) {
+    const dim3 grid((unsigned)count << (logn - 10)), blk(64);
+    switch (logn) {
+        case 12:
+            hipLaunchKernelGGL((k_fwd_top<12, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            hipLaunchKernelGGL((k_fwd_sub<12, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            break;
+        case 13:
+            hipLaunchKernelGGL((k_fwd_top<13, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            hipLaunchKernelGGL((k_fwd_sub<13, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            break;
+        default:
+            hipLaunchKernelGGL((k_fwd_top<14, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            hipLaunchKernelGGL((k_fwd_sub<14, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            break;
+    }
+}
+
+template <class Op>
+static void launch_split_inv(int logn, const Op &op, u64 *tmp, int count, const Tables &tab, hipStream_t st) {
+    const dim3 grid((unsigned)count << (logn - 10)), blk(64);
+    switch (logn) {
+        case 12:
+            hipLaunchKernelGGL((k_inv_sub<12, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            hipLaunchKernelGGL((k_inv_top<12, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            break;
+        case 13:
+            hipLaunchKernelGGL((k_inv_sub<13, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            hipLaunchKernelGGL((k_inv_top<13, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            break;
+        default:
+            hipLaunchKernelGGL((k_inv_sub<14, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            hipLaunchKernelGGL((k_inv_top<14, Op>), grid, blk, 0, st, op, tmp, count, tab);
+            break;
     }
 }
 
@@ -1554,8 +1833,14 @@ static dim3 ntt_block(int logn) { return dim3(1u << (logn - 4)); }
 static size_t ntt_lds(int logn) { return (size_t)((1 << logn) + ((1 << logn) >> 5)) * 8; }
 
 void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
-                int count, const Tables &tab, hipStream_t st) {
+                int count, const Tables &tab, hipStream_t st, u64 *split_tmp) {
     if (count <= 0) return;
+    if (split_tmp) {
+        const OpNtt op{in, imap, out, omap, logn};
+        if (inverse) launch_split_inv(logn, op, split_tmp, count, tab, st);
+        else launch_split_fwd(logn, op, split_tmp, count, tab, st);
+        return;
+    }
     const dim3 grid(count), blk = ntt_block(logn);
     const size_t sh = ntt_lds(logn);
     if (inverse) {
@@ -1574,8 +1859,12 @@ void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *
 }
 
 void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
-                  int nq, const Tables &tab, const Knobs &kn, hipStream_t st) {
+                  int nq, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp) {
     if (groups <= 0) return;
+    if (split_tmp) {
+        launch_split_fwd(logn, OpModup{coef, d, dmap, digits, k, nq, logn}, split_tmp, groups * k * (k + 1), tab, st);
+        return;
+    }
     const int units = groups * k, xo = kn.ntt_xcd ? 1 : 0;
     const dim3 grid(xo ? ((units + 7) / 8) * 8 * (k + 1) : units * (k + 1)), blk = ntt_block(logn);
     const size_t sh = ntt_lds(logn);
@@ -1587,10 +1876,15 @@ void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u
 }
 
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
-                 const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st, const GrpMap *xmap) {
+                 const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st, const GrpMap *xmap,
+                 u64 *split_tmp) {
     if (groups <= 0) return;
     const long N = 1L << logn;
     const GrpMap xm = xmap ? *xmap : GrpMap{0, (k + 1) * N, 0, 1};
+    if (split_tmp) {
+        launch_split_fwd(logn, OpDrop{x, xm, last, out, k, drop, logn, add}, split_tmp, groups * k, tab, st);
+        return;
+    }
     const int xo = kn.ntt_xcd ? 1 : 0;
     const dim3 grid(xo ? ((groups + 7) / 8) * 8 * k : groups * k), blk = ntt_block(logn);
     const size_t sh = ntt_lds(logn);

@@ -335,7 +335,10 @@ class GpuServer:
             for ln in lanes:
                 ln.inp.zero_()
                 with torch.cuda.stream(ln.stream):
+                    # the largest batch, and one query (small batches split their transforms
+                    # through a buffer of their own)
                     ln.ctx.forward(self.models[name], keys, ln.inp, out=ln.out, stream=ln.stream)
+                    ln.ctx.forward(self.models[name], keys, ln.inp[:1], out=ln.out[:1], stream=ln.stream)
                 ln.stream.synchronize()
                 ln.ctx.workspace_freeze(True)
             self.keys.release(client)

@@ -324,6 +324,38 @@ def test_forward_ragged_batch(lazy):
         assert np.array_equal(_u64(c.forward(model, lk, dev[b:b + 1].contiguous()))[0], got[b]), b
 
 
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_split_transforms_equal_one_workgroup_form(name):
+    """Launches of few transforms split each one over N/1024 workgroups (the ntt_split knob): a
+    forward pass of 1 and 3 ciphertexts and a batch of residue transforms give the same residues
+    with splitting on (default) and off."""
+    o, c = _orc(name), _ctx(name)
+    lk, _, _, okeys, rlk = _keys(name)
+    model, _ = _raw_model(name, seed=31, lazy="qp")
+    dev, _ = _fresh_ct(name, 25, count=3)
+    rng = np.random.default_rng(9)
+    idx = [i % o.np for i in range(2 * o.np + 1)]
+    host = np.stack([rng.integers(0, o.primes[p], size=o.n, dtype=np.uint64) for p in idx])
+    before = c.knob("ntt_split")
+    try:
+        outs = {}
+        for split in (before, 0):
+            c.knob("ntt_split", split)
+            res = [_u64(c.forward(model, lk, dev[:1].contiguous())), _u64(c.forward(model, lk, dev))]
+            buf = _dev(host)
+            c.ntt(buf, idx)
+            res.append(_u64(buf))
+            c.ntt(buf, idx, inverse=True)
+            res.append(_u64(buf))
+            outs[split] = res
+    finally:
+        c.knob("ntt_split", before)
+    assert before > 2 * o.np + 1
+    for a, b in zip(outs[before], outs[0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(outs[0][3], host)
+
+
 def test_profile_bytes_model():
     """The algorithmic bytes the library records for a key product: one rotation of 3 ciphertexts
     reads 3 k(k+1) digit rows and one key set's 2 k(k+1) key rows and writes 3 2(k+1) rows, N
