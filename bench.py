@@ -159,7 +159,7 @@ def _alu_ops(family: str, work: float, fp_work: float, n: int):
         units, model = (n // 2) * int(math.log2(n)), UNIT_OPS["bfly"]
     elif family in MAC_FAMILIES:
         units, model = 1, UNIT_OPS["mac"]
-    elif family == "k_keyip":
+    elif family in ("k_keyip", "k_keyip_fp"):
         units, model = 1, UNIT_OPS["keyip"]
     else:
         return {}

@@ -190,7 +190,8 @@ int ctl_pt_import(ctl_ctx *ctx, const int64_t *coeffs, int n_pt, int k, int ext,
  * the number of launches, their summed durations in milliseconds, and the algorithmic work they
  * processed since profiling was enabled: for the NTT-bearing kernels (k_ntt_fwd, k_ntt_inv,
  * k_modup, k_drop, k_int_ntt) the number of length-N residue transforms; for the product kernels
- * (k_keyip, k_mac, k_tensor) the number of 64-bit modular products; for k_add_terms the number of
+ * (k_keyip, k_keyip_fp, k_mac, k_mac_fp, k_mac_direct, k_tensor) the number of 64-bit modular
+ * products; for k_add_terms the number of
  * residue words written. fp_work_out receives the part of that work done on primes below 2^41,
  * which run in exact FP64 arithmetic (the rest runs in 64-bit integer arithmetic). Enabling clears
  * earlier records. Adds a few microseconds per launch. */
@@ -200,8 +201,9 @@ const char *ctl_profile_family_name(int family);
 int ctl_profile_read(ctl_ctx *ctx, int family, int *launches_out, double *total_ms_out,
                      double *work_out, double *fp_work_out);
 /* Algorithmic HBM bytes of the launches of family `family` recorded since profiling was enabled,
- * for the families that model them (k_keyip: digit words once per ciphertext when the rotations
- * are hoisted, else once per rotation, each key set's key words once, output words, fold words;
+ * for the families that model them (k_keyip and k_keyip_fp, each over the residue rows of its
+ * arithmetic class: digit words once per ciphertext when the rotations are hoisted, else once per
+ * rotation, each key set's key words once, output words, fold words;
  * the MAC families: ciphertext and rotated-ciphertext words once, plaintext-bank words once,
  * output words); 0 for the others. No synchronization. */
 int ctl_profile_read_bytes(ctl_ctx *ctx, int family, double *bytes_out);

@@ -39,12 +39,13 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 enum Family { F_NTT_FWD, F_NTT_INV, F_MODUP, F_KEYIP, F_DROP, F_MAC, F_ADD, F_TENSOR, F_INT_NTT, F_OTHER,
-              F_MAC_FP, F_MAC_DIRECT, F_COUNT };
-// Names of the kernels each family brackets (k_mac: the MAC over integer primes; k_mac_fp: over
-// FP64 primes; k_mac_direct: the unstaged MAC of small batches, all primes in one launch).
+              F_MAC_FP, F_MAC_DIRECT, F_KEYIP_FP, F_COUNT };
+// Names of the kernels each family brackets (k_mac and k_keyip: the MAC and the key product over
+// integer primes, limb or 128-bit form; k_mac_fp and k_keyip_fp: over FP64 primes; k_mac_direct:
+// the unstaged MAC of small batches, all primes in one launch).
 const char *const kFamilyNames[F_COUNT] = {"k_ntt_fwd", "k_ntt_inv", "k_modup", "k_keyip", "k_drop",
                                             "k_mac", "k_add_terms", "k_tensor", "k_int_ntt", "other",
-                                            "k_mac_fp", "k_mac_direct"};
+                                            "k_mac_fp", "k_mac_direct", "k_keyip_fp"};
 
 // Workspace slots: each grows on demand and is reused by later calls on the same context.
 enum Slot {
@@ -415,24 +416,40 @@ int key_product(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *dig,
     const long dsz = (long)k * (k + 1) * N;
     KeyFold fd{};
     if (fold) fd = *fold;
-    // algorithmic bytes: digits (once per ciphertext when hoisted), each key set's keys, the
-    // outputs, and the fold term's words
-    const double kip_bytes = 8.0 * N * ((double)B * (hoisted ? 1 : R) * k * (k + 1) +
-                                        (double)ks.runs.size() * R * 2 * k * (k + 1) + (double)B * R * 2 * (k + 1) +
-                                        (fold && fold->src ? (double)B * (fold->sr ? R : 1) * fold->rows : 0.0));
-    CTL_PROFB(F_KEYIP, 2.0 * B * R * (k + 1) * k * N, fp_share_range(c, k, true), kip_bytes);
-    for (const KeySet::Run &run : ks.runs) {       // one launch per key set
-        KeyList kl{};
+    auto key_list = [&](const KeySet::Run &run, KeyList &kl) {
+        kl = KeyList{};
         for (int r = 0; r < R; ++r) {
             kl.key[r] = find_key(run.evk, key_ids[r]);
-            if (!kl.key[r]) return fail(CTL_EKEY, "missing evaluation key");
+            if (!kl.key[r]) return false;
             kl.gal[r] = gal[r];
             kl.ginv[r] = galois_inv(logn, gal[r]);
         }
-        KeyFold fr = fd;
-        if (fr.src) fr.src += run.b0 * fr.sb;
-        launch_keyip(logn, k, dig + run.b0 * db, db, hoisted ? 0 : dsz, kl, R, U + run.b0 * U_sb, U_sb, fr,
-                     run.nb, nq, c->tab, c->knobs, st);
+        return true;
+    };
+    KeyList kl;
+    for (const KeySet::Run &run : ks.runs)          // every key present before anything is launched
+        if (!key_list(run, kl)) return fail(CTL_EKEY, "missing evaluation key");
+    RowSet rows[KIP_CLASSES];
+    keyip_rows(k, nq, c->tab, c->knobs, rows);
+    for (int cls = 0; cls < KIP_CLASSES; ++cls) {  // one launch per arithmetic class and key set
+        const RowSet &rs = rows[cls];
+        if (rs.n == 0) continue;
+        int fold_rows = 0;
+        for (int i = 0; i < rs.n; ++i) fold_rows += fold && fold->src && rs.t[i] < fold->rows ? 1 : 0;
+        // algorithmic bytes of these rows: digits (once per ciphertext when hoisted), each key
+        // set's keys, the outputs, and the fold term's words
+        const double kip_bytes = 8.0 * N * ((double)B * (hoisted ? 1 : R) * k * rs.n +
+                                            (double)ks.runs.size() * R * 2 * k * rs.n + (double)B * R * 2 * rs.n +
+                                            (fold && fold->src ? (double)B * (fold->sr ? R : 1) * fold_rows : 0.0));
+        CTL_PROFB(cls == KIP_FP ? F_KEYIP_FP : F_KEYIP, 2.0 * B * R * rs.n * k * N, cls == KIP_FP ? 1.0 : 0.0,
+                  kip_bytes);
+        for (const KeySet::Run &run : ks.runs) {
+            key_list(run, kl);
+            KeyFold fr = fd;
+            if (fr.src) fr.src += run.b0 * fr.sb;
+            launch_keyip(logn, k, cls, rs, dig + run.b0 * db, db, hoisted ? 0 : dsz, kl, R, U + run.b0 * U_sb,
+                         U_sb, fr, run.nb, nq, c->tab, c->knobs, st);
+        }
     }
     return check_launch();
 }

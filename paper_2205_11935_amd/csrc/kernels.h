@@ -107,9 +107,20 @@ void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, 
                  const GrpMap *xmap = nullptr, u64 *split_tmp = nullptr);
 void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,
                     const Tables &tab, hipStream_t st);
-void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
-                  u64 *out, long ob, const KeyFold &fold, int B, int nq, const Tables &tab, const Knobs &kn,
-                  hipStream_t st);
+// Key products run one launch per arithmetic class of their rows: FP64 products (primes below
+// 2^41), 30-bit limbs (below 2^60, with kn.mac_limb) or 128-bit sums.
+enum KeyipClass { KIP_FP = 0, KIP_LIMB = 1, KIP_WIDE = 2, KIP_CLASSES = 3 };
+// Rows t (0..k; row k is the one mod P) of one key-product launch.
+struct RowSet {
+    int n;
+    int t[kMaxMods];
+};
+// The rows of a key product over k residues and the special prime, split by class.
+void keyip_rows(int k, int nq, const Tables &tab, const Knobs &kn, RowSet (&rows)[KIP_CLASSES]);
+// The key product of the rows of one class (see k_keyip); nothing is launched for an empty set.
+void launch_keyip(int logn, int k, int cls, const RowSet &rows, const u64 *digits, long db, long dr,
+                  const KeyList &keys, int R, u64 *out, long ob, const KeyFold &fold, int B, int nq,
+                  const Tables &tab, const Knobs &kn, hipStream_t st);
 // rows = k residues per polynomial, or k + 1 with the last one mod P (ext_nq = its prime index;
 // -1 without). ct / rot: j = 0 / j >= 1 operands with batch strides ct_sb / rot_sb. part: 0 =
 // every row, 1 = the FP64-prime rows only, 2 = the integer-prime rows only (batches above

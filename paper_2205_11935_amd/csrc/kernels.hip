@@ -722,7 +722,7 @@ struct OpModup {
     __device__ void copy(int r, int j, const Tables &tab) const {
         const int t = r % (k + 1), gj = r / (k + 1);
         const u64 x = d[(res_offset(dmap, gj) << logn) + j];
-        digits[((long)gj * (k + 1) + t << logn) + j] = tab.pc[t].fp ? (u64)__double_as_longlong(u64_to_fp(x)) : x;
+        digits[(((long)gj * (k + 1) + t) << logn) + j] = tab.pc[t].fp ? (u64)__double_as_longlong(u64_to_fp(x)) : x;
     }
     __device__ u64 load(int r, int j, const PrimeConst &p, const Tables &tab) const {
         const int t = r % (k + 1), gj = r / (k + 1), j0 = gj % k, pt = t < k ? t : nq;
@@ -730,7 +730,7 @@ struct OpModup {
     }
     __device__ void store_fwd(int r, int j, u64 x, bool fp, const PrimeConst &p, const Tables &) const {
         const int t = r % (k + 1), gj = r / (k + 1);
-        __builtin_nontemporal_store(fp ? x : red4(x, p.q, p.q2), &digits[((long)gj * (k + 1) + t << logn) + j]);
+        __builtin_nontemporal_store(fp ? x : red4(x, p.q, p.q2), &digits[(((long)gj * (k + 1) + t) << logn) + j]);
     }
     __device__ void store_inv(int, int, u64, const PrimeConst &) const {}
     __device__ void store_inv_fp(int, int, double, const PrimeConst &) const {}
@@ -1028,25 +1028,31 @@ __device__ __forceinline__ u64 limb_reduce4(const u64 (&c)[4], const PrimeConst 
 // such that all rotation groups of one (source tile, t) run back to back on the same XCD (with
 // hoisted digits, dr = 0, they read the same digit words, which its L2 serves); otherwise tiles
 // vary fastest, then t, then the rotation group.
-template <int K, int RR>
-__global__ void __launch_bounds__(256, RR == 2 ? 3 : RR > 2 ? 2 : 1)
-k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__restrict__ out, long ob,
-        KeyFold fold, int B, int R, int nq, int logn, int xcd_order, unsigned lt60, const PrimeConst *__restrict__ pcs) {
-    const int pairs = (K + 1) << (logn - 8);
+//
+// The rows of one launch (RowSet) all take one arithmetic class (KeyipClass), and each class is
+// its own kernel, so that each gets the register budget of its own products: k_keyip_fp (FP64
+// primes), k_keyip_limb (30-bit limbs, primes below 2^60) and k_keyip (128-bit sums).
+template <int K, int RR, int CLS>
+__device__ __forceinline__ void
+keyip_body(const u64 *__restrict__ digits, long db, long dr, const KeyList &keys, u64 *__restrict__ out, long ob,
+           const KeyFold &fold, const RowSet &rows, int B, int R, int nq, int logn, int xcd_order,
+           const PrimeConst *__restrict__ pcs) {
+    const int nt = rows.n;
+    const int pairs = nt << (logn - 8);
     const int RG = (R + RR - 1) / RR;                       // groups of RR rotations
     int rg, pair;
     if (xcd_order) {
         const int id = blockIdx.x, xcd = id & 7, j = id >> 3;
         rg = j % RG;
-        pair = (j / RG) * 8 + xcd;                           // pair = tile * (K + 1) + t
+        pair = (j / RG) * 8 + xcd;                           // pair = tile * nt + row
     } else {
         const int tiles = 1 << (logn - 8), id = blockIdx.x;
         rg = id / pairs;
-        pair = (id % tiles) * (K + 1) + (id / tiles) % (K + 1);
+        pair = (id % tiles) * nt + (id / tiles) % nt;
     }
     if (pair >= pairs || rg >= RG) return;
-    const int m = (pair / (K + 1)) * 256 + threadIdx.x;     // source coefficient
-    const int t = pair % (K + 1);
+    const int m = (pair / nt) * 256 + threadIdx.x;          // source coefficient
+    const int t = rows.t[pair % nt];
     const int N = 1 << logn, np = nq + 1;
     const int pt = t < K ? t : nq;
     const PrimeConst p = pcs[pt];
@@ -1103,7 +1109,7 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
             }
         }
     };
-    if (p.fp) {
+    if constexpr (CLS == KIP_FP) {
         // FP64 products (prime < 2^41): each term |.| <= 0.52 q, sums stay far below 2^53
         double kb[RR][K], ka[RR][K];
 #pragma unroll
@@ -1136,9 +1142,7 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
         };
         if (fd) run(std::true_type{});
         else run(std::false_type{});
-        return;
-    }
-    if ((lt60 >> pt) & 1) {
+    } else if constexpr (CLS == KIP_LIMB) {
         // prime below 2^60: 30-bit limb products into carry-free column sums (see k_mac_limb);
         // with the two cross products in separate columns every column takes 16 terms, and a
         // sum has at most K + 1 <= 9
@@ -1192,38 +1196,56 @@ k_keyip(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__r
         };
         if (fd) run(std::true_type{});
         else run(std::false_type{});
-        return;
-    }
-    u64 kb[RR][K], ka[RR][K];
+    } else {
+        // other primes: 128-bit sums of full products, one reduction per output
+        u64 kb[RR][K], ka[RR][K];
 #pragma unroll
-    for (int rr = 0; rr < RR; ++rr)
+        for (int rr = 0; rr < RR; ++rr)
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int n = (voff_o[rr] >> 3) % N;
-            kb[rr][j] = key[rr][((long)(j * 2 + 0) * np + pt) * N + n];
-            ka[rr][j] = key[rr][((long)(j * 2 + 1) * np + pt) * N + n];
-        }
-    auto run = [&](auto fold_tag) {
-        constexpr bool FOLD = decltype(fold_tag)::value;
-        batch(fold_tag, [&](int b, const u64 (&x)[K], u64 fx) {
-#pragma unroll
-            for (int rr = 0; rr < RR; ++rr) {
-                Acc a0, a1;
-                acc_zero(a0);
-                acc_zero(a1);
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    acc_mac(a0, x[j], kb[rr][j]);
-                    acc_mac(a1, x[j], ka[rr][j]);
-                }
-                if constexpr (FOLD) acc_mac(a0, fx, fm);
-                store(b, rr, acc_reduce(a0, p), acc_reduce(a1, p));
+            for (int j = 0; j < K; ++j) {
+                const int n = (voff_o[rr] >> 3) % N;
+                kb[rr][j] = key[rr][((long)(j * 2 + 0) * np + pt) * N + n];
+                ka[rr][j] = key[rr][((long)(j * 2 + 1) * np + pt) * N + n];
             }
-        });
-    };
-    if (fd) run(std::true_type{});
-    else run(std::false_type{});
+        auto run = [&](auto fold_tag) {
+            constexpr bool FOLD = decltype(fold_tag)::value;
+            batch(fold_tag, [&](int b, const u64 (&x)[K], u64 fx) {
+#pragma unroll
+                for (int rr = 0; rr < RR; ++rr) {
+                    Acc a0, a1;
+                    acc_zero(a0);
+                    acc_zero(a1);
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        acc_mac(a0, x[j], kb[rr][j]);
+                        acc_mac(a1, x[j], ka[rr][j]);
+                    }
+                    if constexpr (FOLD) acc_mac(a0, fx, fm);
+                    store(b, rr, acc_reduce(a0, p), acc_reduce(a1, p));
+                }
+            });
+        };
+        if (fd) run(std::true_type{});
+        else run(std::false_type{});
+    }
 }
+
+// Waves per SIMD each key-product kernel is compiled for (its register budget: 512 / waves).
+template <int CLS, int RR>
+constexpr int kKeyipWaves = CLS == KIP_FP ? 3 : (RR <= 2 ? 3 : 2);
+
+#define CTL_KEYIP_KERNEL(NAME, CLS)                                                                        \
+    template <int K, int RR>                                                                               \
+    __global__ void __launch_bounds__(256, (kKeyipWaves<CLS, RR>))                                         \
+    NAME(const u64 *__restrict__ digits, long db, long dr, KeyList keys, u64 *__restrict__ out, long ob,    \
+         KeyFold fold, RowSet rows, int B, int R, int nq, int logn, int xcd_order,                         \
+         const PrimeConst *__restrict__ pcs) {                                                             \
+        keyip_body<K, RR, CLS>(digits, db, dr, keys, out, ob, fold, rows, B, R, nq, logn, xcd_order, pcs); \
+    }
+CTL_KEYIP_KERNEL(k_keyip_fp, KIP_FP)
+CTL_KEYIP_KERNEL(k_keyip_limb, KIP_LIMB)
+CTL_KEYIP_KERNEL(k_keyip, KIP_WIDE)
+#undef CTL_KEYIP_KERNEL
 
 // Baby-step MAC of Eq. (1): inner[b][k2][c][i] = sum_{j < t1} pt[k2 t1 + j][i] * rot_j(ct_b)[c][i]
 // with rot_0 = ct itself (ct_b at ct + b ct_sb, [2][K][N]) and rot_j, j >= 1, at rot + b rot_sb +
@@ -1907,33 +1929,55 @@ void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const Pr
     }
 }
 
-void launch_keyip(int logn, int k, const u64 *digits, long db, long dr, const KeyList &keys, int R,
-                  u64 *out, long ob, const KeyFold &fold, int B, int nq, const Tables &tab, const Knobs &kn,
-                  hipStream_t st) {
-    if (R <= 0 || B <= 0) return;
-    const int pairs = (k + 1) << (logn - 8);
+void keyip_rows(int k, int nq, const Tables &tab, const Knobs &kn, RowSet (&rows)[KIP_CLASSES]) {
+    for (RowSet &r : rows) r.n = 0;
+    for (int t = 0; t <= k; ++t) {
+        const int pt = t < k ? t : nq;
+        const int cls = tab.host_fp[pt] ? KIP_FP : (kn.mac_limb && tab.host_lt60[pt]) ? KIP_LIMB : KIP_WIDE;
+        rows[cls].t[rows[cls].n++] = t;
+    }
+}
+
+void launch_keyip(int logn, int k, int cls, const RowSet &rows, const u64 *digits, long db, long dr,
+                  const KeyList &keys, int R, u64 *out, long ob, const KeyFold &fold, int B, int nq,
+                  const Tables &tab, const Knobs &kn, hipStream_t st) {
+    if (R <= 0 || B <= 0 || rows.n <= 0 || cls < 0 || cls >= KIP_CLASSES) return;
+    const int pairs = rows.n << (logn - 8);
     const int xo = kn.keyip_xcd ? 1 : 0;
-    unsigned lt60 = 0;
-    for (int i = 0; i <= nq && kn.mac_limb; ++i) lt60 |= (tab.host_lt60[i] ? 1u : 0u) << i;
-    // kn.keyip_rr rotations per workgroup share each digit word when the digits are hoisted
-    // (dr = 0) and the fold term, if any, is the same for every rotation (sr = 0)
     // kn.keyip_rr rotations per workgroup share each digit word when the digits are hoisted
     // (dr = 0) and the fold term, if any, is the same for every rotation (sr = 0)
     int rr = kn.keyip_rr < 1 ? 1 : kn.keyip_rr > 4 ? 4 : kn.keyip_rr;
-    if (k >= 7 && rr > 3) rr = 3;                 // register budget: 4 would spill heavily
+    // register budget: a thread holds RR k key words per polynomial (2 VGPRs each, FP64 or 30-bit
+    // limb pairs); these caps keep every class at 3 or more waves per SIMD with nothing spilled
+    const int words = cls == KIP_FP ? 28 : cls == KIP_LIMB ? 12 : 10;
+    const int cap = words / k < 1 ? 1 : words / k;
+    if (rr > cap) rr = cap;
     if (dr != 0 || (fold.src && fold.sr != 0)) rr = 1;
     if (rr > R) rr = R;
     const int RG = (R + rr - 1) / rr;
     const dim3 grid((unsigned)(xo ? ((pairs + 7) / 8) * 8 * RG : pairs * RG)), blk(256);
-    switch (k * 4 + rr - 1) {
-#define CTL_KIP(K) case 4 * K: hipLaunchKernelGGL((k_keyip<K, 1>), grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, lt60, tab.pc); break; \
-                   case 4 * K + 1: hipLaunchKernelGGL((k_keyip<K, 2>), grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, lt60, tab.pc); break; \
-                   case 4 * K + 2: hipLaunchKernelGGL((k_keyip<K, 3>), grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, lt60, tab.pc); break; \
-                   case 4 * K + 3: hipLaunchKernelGGL((k_keyip<K, 4>), grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, B, R, nq, logn, xo, lt60, tab.pc); break;
+#define CTL_KIP_ONE(KERNEL, K, RR) \
+    hipLaunchKernelGGL((KERNEL<K, RR>), grid, blk, 0, st, digits, db, dr, keys, out, ob, fold, rows, B, R, nq, logn, xo, tab.pc)
+#define CTL_KIP_RR(KERNEL, K)                        \
+    switch (rr) {                                    \
+        case 1: CTL_KIP_ONE(KERNEL, K, 1); break;    \
+        case 2: CTL_KIP_ONE(KERNEL, K, 2); break;    \
+        case 3: CTL_KIP_ONE(KERNEL, K, 3); break;    \
+        default: CTL_KIP_ONE(KERNEL, K, 4); break;   \
+    }
+#define CTL_KIP(K)                                                  \
+    case K:                                                         \
+        if (cls == KIP_FP) { CTL_KIP_RR(k_keyip_fp, K) }            \
+        else if (cls == KIP_LIMB) { CTL_KIP_RR(k_keyip_limb, K) }   \
+        else { CTL_KIP_RR(k_keyip, K) }                             \
+        break;
+    switch (k) {
         CTL_KIP(1) CTL_KIP(2) CTL_KIP(3) CTL_KIP(4) CTL_KIP(5) CTL_KIP(6) CTL_KIP(7) CTL_KIP(8)
-#undef CTL_KIP
         default: break;
     }
+#undef CTL_KIP
+#undef CTL_KIP_RR
+#undef CTL_KIP_ONE
 }
 
 // Largest supported giant-step chunk that divides t2 and does not exceed cap.

@@ -86,6 +86,18 @@ def counter_values(path: str) -> Dict[Tuple[str, int], Dict[str, List[float]]]:
     return out
 
 
+def copy_dispatch(values, counter: str):
+    """The calibration copy among the dispatches of a counter run: the largest reading of a copy
+    kernel (the runtime's blit kernel for a device-to-device copy, or an elementwise copy); the
+    library's own kernels (k_*) are never taken, whatever they read."""
+    cands = [(k, v[counter]) for k, v in values.items()
+             if counter in v and not k[0].startswith("k_") and "copy" in k[0].lower()]
+    if not cands:
+        raise SystemExit("no copy kernel among the %s dispatches: run the profiled command with "
+                         "--copy-calibration-mib" % counter)
+    return max(cands, key=lambda x: max(x[1]))
+
+
 def cmd_stats(a):
     stats = sorted(_rows(a.stats), key=lambda r: -float(_col(r, "TotalDurationNs")))
     inst = trace_instances(a.trace)
@@ -112,9 +124,8 @@ def cmd_stats(a):
 def cmd_counters(a):
     fetch, write = counter_values(a.fetch), counter_values(a.write)
     copy_bytes = a.copy_mib * (1 << 20)
-    # the copy kernel: the instance whose counters are largest (reads and writes copy_bytes once)
-    cf = max(((k, v["FETCH_SIZE"]) for k, v in fetch.items() if "FETCH_SIZE" in v), key=lambda x: max(x[1]))
-    cw = max(((k, v["WRITE_SIZE"]) for k, v in write.items() if "WRITE_SIZE" in v), key=lambda x: max(x[1]))
+    cf = copy_dispatch(fetch, "FETCH_SIZE")
+    cw = copy_dispatch(write, "WRITE_SIZE")
     fs = copy_bytes / (max(cf[1]) * 1024.0)
     ws = copy_bytes / (max(cw[1]) * 1024.0)
     inst = trace_instances(a.trace) if a.trace else {}
@@ -134,10 +145,11 @@ def cmd_counters(a):
             e["trace_avg_ms"] = statistics.mean(inst[key])
             e["gbs"] = (fb + wb) / (e["trace_avg_ms"] * 1e-3) / 1e9
         rec["instances"]["%s grid %d" % (k, g)] = e
-    for name, site in (a.site or []):
-        # bench.py's name for an instance: "<family> @ <site>" -> the rocprof instance given
-        if name in rec["instances"]:
-            rec["instances"]["%s @ %s" % (name.split("<")[0].split(" grid")[0], site)] = rec["instances"][name]
+    for name, key in (a.site or []):
+        # bench.py's name for an instance ("<family> @ <site>") -> the rocprof instance given
+        if name not in rec["instances"]:
+            raise SystemExit("no instance %r in the counter runs" % name)
+        rec["instances"][key] = rec["instances"][name]
     lines = ["# HBM traffic and VALU issue per kernel instance", "",
              "Counter passes (each its own run; from the repository root, one MI355X):", "",
              "```", a.cmd_fetch, a.cmd_write] + ([a.cmd_valu] if a.cmd_valu else []) + ["```", ""]
@@ -207,8 +219,9 @@ def main(argv=None):
     c.add_argument("--cmd-write", required=True)
     c.add_argument("--cmd-valu", default="")
     c.add_argument("--note", default="")
-    c.add_argument("--site", nargs=2, action="append", metavar=("INSTANCE", "SITE"),
-                   help="also key an instance ('k_x<..> grid G') by bench.py's site name")
+    c.add_argument("--site", nargs=2, action="append", metavar=("INSTANCE", "KEY"),
+                   help="also key an instance ('k_x<..> grid G') by bench.py's name for it "
+                        "('family @ site')")
     c.add_argument("--json", required=True)
     c.add_argument("--md", required=True)
     a = ap.parse_args(argv)

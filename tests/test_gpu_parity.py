@@ -373,8 +373,11 @@ def test_profile_bytes_model():
         pb = c.profile_bytes()
     finally:
         c.profile_enable(False)
-    assert launches["k_keyip"][0] == 1 and launches["k_ntt_inv"][0] >= 1
-    assert pb["k_keyip"] == 8.0 * n * (3 * k * (k + 1) + 2 * k * (k + 1) + 3 * 2 * (k + 1))
+    # one launch per arithmetic class present among the k + 1 rows (FP64 primes / integer primes),
+    # each with the bytes of its own rows
+    fams = [f for f in ("k_keyip_fp", "k_keyip") if launches.get(f, (0,))[0]]
+    assert fams and all(launches[f][0] == 1 for f in fams) and launches["k_ntt_inv"][0] >= 1
+    assert sum(pb[f] for f in fams) == 8.0 * n * (3 * k * (k + 1) + 2 * k * (k + 1) + 3 * 2 * (k + 1))
     assert pb["k_ntt_inv"] == 0.0
 
 
