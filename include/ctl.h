@@ -121,13 +121,18 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
  *                        keeps at most 8 giant-step accumulators per thread); 0: 128-bit
  *                        accumulation. Primes of 61 bits always take the latter;
  *   CTL_KNOB_KEYIP_RR    hoisted rotations per key-product workgroup, which read each digit word
- *                        once for all of them (1..4, default 4; at most 3 with 7 or more primes,
- *                        for the register budget; launches whose rotations have their own digits
- *                        use 1);
+ *                        once for all of them (1..4, default 4; each arithmetic class caps it
+ *                        by its register budget, e.g. 2 for 30-bit-limb rows with 6 primes;
+ *                        launches whose rotations have their own digits use 1);
  *   CTL_KNOB_NTT_SPLIT   launches of fewer residue transforms than this (0..4096, default 128; 0:
  *                        never) split every transform over N/1024 single-wave workgroups in two
  *                        launches through a workspace buffer, instead of one workgroup per
- *                        transform (small batches fill the GPU; same residues).
+ *                        transform (small batches fill the GPU; same residues);
+ *   CTL_KNOB_NTT_LOOP    launches with at least this many residue transforms per compute unit
+ *                        in each arithmetic class present, FP64 primes and integer primes
+ *                        (0..64, default 8; 0: never), run as resident workgroups that loop
+ *                        over the transforms of one class per launch, bringing the next one's
+ *                        input into L2 while they compute the current one (same residues).
  * Out-of-range values give CTL_EINVAL and leave the knob unchanged. */
 #define CTL_KNOB_MAC_CHUNK 0
 #define CTL_KNOB_MAC_CTS 1
@@ -137,6 +142,7 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
 #define CTL_KNOB_MAC_LIMB 5
 #define CTL_KNOB_KEYIP_RR 6
 #define CTL_KNOB_NTT_SPLIT 7
+#define CTL_KNOB_NTT_LOOP 8
 int ctl_knob_set(ctl_ctx *ctx, int knob, int value);
 int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value);
 

@@ -32,9 +32,11 @@ CTL_KNOB_NTT_XCD = 4
 CTL_KNOB_MAC_LIMB = 5
 CTL_KNOB_KEYIP_RR = 6
 CTL_KNOB_NTT_SPLIT = 7
+CTL_KNOB_NTT_LOOP = 8
 KNOBS = {"mac_chunk": CTL_KNOB_MAC_CHUNK, "mac_cts": CTL_KNOB_MAC_CTS, "keyip_xcd": CTL_KNOB_KEYIP_XCD,
          "mac_direct": CTL_KNOB_MAC_DIRECT, "ntt_xcd": CTL_KNOB_NTT_XCD, "mac_limb": CTL_KNOB_MAC_LIMB,
-         "keyip_rr": CTL_KNOB_KEYIP_RR, "ntt_split": CTL_KNOB_NTT_SPLIT}
+         "keyip_rr": CTL_KNOB_KEYIP_RR, "ntt_split": CTL_KNOB_NTT_SPLIT,
+         "ntt_loop": CTL_KNOB_NTT_LOOP}
 CTL_FORM_NTT = 0
 CTL_FORM_COEFF = 1
 CTL_LAYER_DENSE = 0

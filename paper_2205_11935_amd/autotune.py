@@ -2,7 +2,8 @@
 and prime chain.
 
 The knobs choose how work is divided among kernels (the MAC's giant-step chunk and ciphertexts per
-workgroup, the key product's workgroup numbering); every choice computes the same residues. The
+workgroup, the key product's workgroup numbering, when transforms split or loop); every choice
+computes the same residues. The
 tuner times the caller's own workload — typically one batched forward pass — for each candidate
 value, one knob at a time starting from the current settings (coordinate descent), keeps the
 fastest, and checks that every candidate's output equals the first one bit for bit. Results can be
@@ -25,6 +26,7 @@ CANDIDATES: Dict[str, List[int]] = {
     "mac_limb": [1, 0],
     "keyip_rr": [4, 3, 2, 1],
     "ntt_split": [128, 64, 256, 0],
+    "ntt_loop": [8, 4, 16, 0],
 }
 
 

@@ -398,7 +398,7 @@ int modup_digits(ctl_ctx *c, hipStream_t st, int k, int G, const u64 *d, const R
     u64 *coef, *dig;
     CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
     CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
-    { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, st, split_buf(c, st, G * k)); }
+    { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, c->knobs, st, split_buf(c, st, G * k)); }
     { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st, split_buf(c, st, G * k * (k + 1))); }
     *dig_out = dig;
     return check_launch();
@@ -494,7 +494,7 @@ int keyswitch_lower(ctl_ctx *c, hipStream_t st, int k, int groups, const u64 *U,
     pm.gstride = k + 1;
     pm.ostride = k + 1;
     pm.prime[0] = nq;
-    { CTL_PROF(F_NTT_INV, groups, fp_share_range(c, 0, true)); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), groups, c->tab, st, split_buf(c, st, groups)); }
+    { CTL_PROF(F_NTT_INV, groups, fp_share_range(c, 0, true)); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), groups, c->tab, c->knobs, st, split_buf(c, st, groups)); }
     { CTL_PROF(F_DROP, (double)groups * k, fp_share_range(c, k, false)); launch_drop(logn, U, plast, out, groups, k, nq, add, c->tab, c->knobs, st, nullptr, split_buf(c, st, groups * k)); }
     return check_launch();
 }
@@ -522,7 +522,7 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
     m.gstride = k;
     m.ostride = k;
     m.prime[0] = k - 1;
-    { CTL_PROF(F_NTT_INV, B * 2, fp_share(c, &m.prime[0], 1)); launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, st, split_buf(c, st, B * 2)); }
+    { CTL_PROF(F_NTT_INV, B * 2, fp_share(c, &m.prime[0], 1)); launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, c->knobs, st, split_buf(c, st, B * 2)); }
     DropAdd add{};
     add.R = 1;
     add.mask = 0;
@@ -773,7 +773,7 @@ int dense_qp_groups(ctl_ctx *c, hipStream_t st, const ctl_model *const *models, 
             pm.gstride = 2L * (k + 1);
             pm.ostride = (long)q.t2 * 2 * (k + 1);
             pm.prime[0] = nq;
-            { CTL_PROF(F_NTT_INV, q.B * q.R2, fp_share_range(c, 0, true)); launch_ntt(logn, true, ig, pm, plast + q.i1_off * N, dense_map(1, nq), q.B * q.R2, c->tab, st, split_buf(c, st, q.B * q.R2)); }
+            { CTL_PROF(F_NTT_INV, q.B * q.R2, fp_share_range(c, 0, true)); launch_ntt(logn, true, ig, pm, plast + q.i1_off * N, dense_map(1, nq), q.B * q.R2, c->tab, c->knobs, st, split_buf(c, st, q.B * q.R2)); }
             GrpMap xm{3L * (k + 1) * N, (long)q.t2 * ext, ext, q.R2};
             { CTL_PROF(F_DROP, (double)q.B * q.R2 * k, fp_share_range(c, k, false)); launch_drop(logn, ig, plast + q.i1_off * N, i1 + q.i1_off * k * N, q.B * q.R2, k, nq, none, c->tab, c->knobs, st, &xm, split_buf(c, st, q.B * q.R2 * k)); }
         }
@@ -1288,6 +1288,8 @@ int ctl_ctx_create(const ctl_params *params, int device, ctl_ctx **ctx_out) {
     CTL_HIP(hipSetDevice(device));
     hipDeviceProp_t prop;
     CTL_HIP(hipGetDeviceProperties(&prop, device));
+    c->tab.cus = prop.multiProcessorCount;
+    c->tab.lds_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
     const size_t lds_need = (size_t)(c->hp.n + c->hp.n / 32) * 8;
     if (prop.sharedMemPerBlock < lds_need && prop.maxSharedMemoryPerMultiProcessor < lds_need)
         return fail(CTL_EPARAM, "device LDS too small for N = " + std::to_string(c->hp.n));
@@ -1462,6 +1464,10 @@ int ctl_knob_set(ctl_ctx *ctx, int knob, int value) {
             if (value < 0 || value > 4096) return fail(CTL_EINVAL, "the split threshold must lie in 0..4096");
             ctx->knobs.ntt_split = value;
             return CTL_OK;
+        case CTL_KNOB_NTT_LOOP:
+            if (value < 0 || value > 64) return fail(CTL_EINVAL, "the loop threshold must lie in 0..64");
+            ctx->knobs.ntt_loop = value;
+            return CTL_OK;
         default:
             return fail(CTL_EINVAL, "unknown knob");
     }
@@ -1478,6 +1484,7 @@ int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value) {
         case CTL_KNOB_MAC_LIMB: *value = ctx->knobs.mac_limb; return CTL_OK;
         case CTL_KNOB_KEYIP_RR: *value = ctx->knobs.keyip_rr; return CTL_OK;
         case CTL_KNOB_NTT_SPLIT: *value = ctx->knobs.ntt_split; return CTL_OK;
+        case CTL_KNOB_NTT_LOOP: *value = ctx->knobs.ntt_loop; return CTL_OK;
         default: return fail(CTL_EINVAL, "unknown knob");
     }
 }
@@ -1610,7 +1617,7 @@ int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, in
         for (int i = 0; i < period; ++i) m.prime[i] = prime_idx[i];
         u64 *p = reinterpret_cast<u64 *>(dev);
         Prof prof(ctx, inverse ? F_NTT_INV : F_NTT_FWD, st, n_res, fp_share(ctx, prime_idx, period));
-        launch_ntt(ctx->hp.logn, inverse != 0, p, m, p, m, n_res, ctx->tab, st);
+        launch_ntt(ctx->hp.logn, inverse != 0, p, m, p, m, n_res, ctx->tab, ctx->knobs, st);
         return check_launch();
     }
     for (int r0 = 0; r0 < n_res; r0 += kMaxMods) {
@@ -1624,7 +1631,7 @@ int ctl_ntt(ctl_ctx *ctx, uint64_t *dev, int n_res, const int32_t *prime_idx, in
         for (int i = 0; i < cnt; ++i) m.prime[i] = prime_idx[r0 + i];
         u64 *p = reinterpret_cast<u64 *>(dev) + (size_t)r0 * N;
         Prof prof(ctx, inverse ? F_NTT_INV : F_NTT_FWD, st, cnt, fp_share(ctx, prime_idx + r0, cnt));
-        launch_ntt(ctx->hp.logn, inverse != 0, p, m, p, m, cnt, ctx->tab, st);
+        launch_ntt(ctx->hp.logn, inverse != 0, p, m, p, m, cnt, ctx->tab, ctx->knobs, st);
         CTL_TRY(check_launch());
     }
     return CTL_OK;
@@ -1642,7 +1649,7 @@ int ctl_ct_export(ctl_ctx *ctx, const uint64_t *ct, int k, int n_poly, int form,
     if (form == CTL_FORM_COEFF) {
         u64 *tmp;
         CTL_TRY(slot(ctx, S_COEF2, words, st, &tmp));
-        launch_ntt(ctx->hp.logn, true, src, dense_map(k), tmp, dense_map(k), n_poly * k, ctx->tab, st);
+        launch_ntt(ctx->hp.logn, true, src, dense_map(k), tmp, dense_map(k), n_poly * k, ctx->tab, ctx->knobs, st);
         CTL_TRY(check_launch());
         src = tmp;
     }
@@ -1669,7 +1676,7 @@ int ctl_ct_import(ctl_ctx *ctx, const uint64_t *host, int k, int n_poly, int for
         u64 *tmp;
         CTL_TRY(slot(ctx, S_COEF2, words, st, &tmp));
         CTL_HIP(hipMemcpyAsync(tmp, host, words * 8, hipMemcpyHostToDevice, st));
-        launch_ntt(ctx->hp.logn, false, tmp, dense_map(k), dst, dense_map(k), n_poly * k, ctx->tab, st);
+        launch_ntt(ctx->hp.logn, false, tmp, dense_map(k), dst, dense_map(k), n_poly * k, ctx->tab, ctx->knobs, st);
         CTL_TRY(check_launch());
     } else {
         CTL_HIP(hipMemcpyAsync(dst, host, words * 8, hipMemcpyHostToDevice, st));
@@ -2140,7 +2147,7 @@ int ctl_decrypt(ctl_ctx *ctx, const ctl_sk *sk, const uint64_t *ct, int k, uint6
     u64 *m;
     CTL_TRY(slot(ctx, S_COEF2, (size_t)k * n, st, &m));
     launch_dec_mul(ctx->hp.logn, reinterpret_cast<const u64 *>(ct), sk->d_s, m, k, ctx->tab, st);
-    launch_ntt(ctx->hp.logn, true, m, dense_map(k), m, dense_map(k), k, ctx->tab, st);
+    launch_ntt(ctx->hp.logn, true, m, dense_map(k), m, dense_map(k), k, ctx->tab, ctx->knobs, st);
     CTL_TRY(check_launch());
     CTL_HIP(hipMemcpyAsync(residues_out, m, (size_t)k * n * 8, hipMemcpyDeviceToHost, st));
     CTL_HIP(hipStreamSynchronize(st));

@@ -22,6 +22,8 @@ struct Tables {
     const CrossConst *cross;            // [kMaxMods][kMaxMods], entry [i * kMaxMods + j]
     unsigned char host_fp[kMaxMods];    // host copy of pc[i].fp, for launch decisions
     unsigned char host_lt60[kMaxMods];  // prime i below 2^60 (30-bit limb products apply)
+    int cus;                            // compute units of the device
+    int lds_cu;                         // LDS bytes per compute unit
 };
 
 constexpr int kMaxKeysPerLaunch = 64;
@@ -93,13 +95,14 @@ struct Knobs {
     int mac_limb = 1;            // integer-prime MAC by 30-bit limbs where every prime is below 2^60
     int keyip_rr = 4;            // key product: hoisted rotations per workgroup sharing digit words (1..4)
     int ntt_split = 128;         // launches of fewer transforms split each over N/1024 workgroups (0: never)
+    int ntt_loop = 8;            // launches with at least this many transforms of each class per CU loop (0: never)
 };
 
 // The NTT-bearing launches: with split_tmp (a buffer of one residue per transform of the launch,
 // [count][N] words) every transform is split over N / 1024 single-wave workgroups in two launches,
 // for launches of few transforms (the same residues either way).
 void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
-                int count, const Tables &tab, hipStream_t st, u64 *split_tmp = nullptr);
+                int count, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp = nullptr);
 void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
                   int nq, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp = nullptr);
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,

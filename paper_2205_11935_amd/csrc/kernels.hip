@@ -683,7 +683,8 @@ k_drop(const u64 *__restrict__ x, GrpMap xm, const u64 *__restrict__ last, u64 *
 // around the transform (lift on the load, combine on the store) come from an Op:
 //   prime(r)      prime-table index of residue r of the launch
 //   copy_only(r)  residue r is a plain copy (copy(r, j, tab) for element j), no transform
-//   load(r, j, p, tab)                          input of element j, canonical mod p
+//   load(r, j, p, tab)                          input of element j, canonical mod p: the word
+//                                               fetch(r, j) brought to p by prep(r, x, p, tab)
 //   store_fwd(r, j, x, fp, p, tab)              forward output: x as the LDS of the one-workgroup
 //                                               form holds it (double bits for an FP64 prime)
 //   store_inv(r, j, x, p) / store_inv_fp(r, j, d, p)   inverse output before the N^{-1} factor
@@ -696,9 +697,9 @@ struct OpNtt {
     __device__ int prime(int r) const { return imap.prime[r % imap.per]; }
     __device__ bool copy_only(int) const { return false; }
     __device__ void copy(int, int, const Tables &) const {}
-    __device__ u64 load(int r, int j, const PrimeConst &, const Tables &) const {
-        return in[(res_offset(imap, r) << logn) + j];
-    }
+    __device__ u64 fetch(int r, int j) const { return in[(res_offset(imap, r) << logn) + j]; }
+    __device__ u64 prep(int, u64 x, const PrimeConst &, const Tables &) const { return x; }
+    __device__ u64 load(int r, int j, const PrimeConst &p, const Tables &tab) const { return prep(r, fetch(r, j), p, tab); }
     __device__ void store_fwd(int r, int j, u64 x, bool fp, const PrimeConst &p, const Tables &) const {
         out[(res_offset(omap, r) << logn) + j] =
             fp ? fp_to_u64(__longlong_as_double((long long)x), p.qd, p.qinv) : red4(x, p.q, p.q2);
@@ -724,10 +725,12 @@ struct OpModup {
         const u64 x = d[(res_offset(dmap, gj) << logn) + j];
         digits[(((long)gj * (k + 1) + t) << logn) + j] = tab.pc[t].fp ? (u64)__double_as_longlong(u64_to_fp(x)) : x;
     }
-    __device__ u64 load(int r, int j, const PrimeConst &p, const Tables &tab) const {
-        const int t = r % (k + 1), gj = r / (k + 1), j0 = gj % k, pt = t < k ? t : nq;
-        return lift_centered(coef[((long)gj << logn) + j], tab.pc[j0].q, tab.cross[pt * kMaxMods + j0].qj_mod_qi, p);
+    __device__ u64 fetch(int r, int j) const { return coef[((long)(r / (k + 1)) << logn) + j]; }
+    __device__ u64 prep(int r, u64 x, const PrimeConst &p, const Tables &tab) const {
+        const int t = r % (k + 1), j0 = (r / (k + 1)) % k, pt = t < k ? t : nq;
+        return lift_centered(x, tab.pc[j0].q, tab.cross[pt * kMaxMods + j0].qj_mod_qi, p);
     }
+    __device__ u64 load(int r, int j, const PrimeConst &p, const Tables &tab) const { return prep(r, fetch(r, j), p, tab); }
     __device__ void store_fwd(int r, int j, u64 x, bool fp, const PrimeConst &p, const Tables &) const {
         const int t = r % (k + 1), gj = r / (k + 1);
         __builtin_nontemporal_store(fp ? x : red4(x, p.q, p.q2), &digits[(((long)gj * (k + 1) + t) << logn) + j]);
@@ -747,10 +750,11 @@ struct OpDrop {
     __device__ int prime(int r) const { return r % k; }
     __device__ bool copy_only(int) const { return false; }
     __device__ void copy(int, int, const Tables &) const {}
-    __device__ u64 load(int r, int j, const PrimeConst &p, const Tables &tab) const {
-        const int i = r % k, grp = r / k;
-        return lift_centered(last[((long)grp << logn) + j], tab.pc[drop].q, tab.cross[i * kMaxMods + drop].qj_mod_qi, p);
+    __device__ u64 fetch(int r, int j) const { return last[((long)(r / k) << logn) + j]; }
+    __device__ u64 prep(int r, u64 x, const PrimeConst &p, const Tables &tab) const {
+        return lift_centered(x, tab.pc[drop].q, tab.cross[(r % k) * kMaxMods + drop].qj_mod_qi, p);
     }
+    __device__ u64 load(int r, int j, const PrimeConst &p, const Tables &tab) const { return prep(r, fetch(r, j), p, tab); }
     __device__ void store_fwd(int r, int j, u64 v, bool fp, const PrimeConst &p, const Tables &tab) const {
         const int i = r % k, grp = r / k;
         const long N = 1L << logn;
@@ -939,6 +943,247 @@ static void launch_split_inv(int logn, const Op &op, u64 *tmp, int count, const 
             hipLaunchKernelGGL((k_inv_top<14, Op>), grid, blk, 0, st, op, tmp, count, tab);
             break;
     }
+}
+
+// Workgroup and dynamic LDS of the one-workgroup transforms.
+static dim3 ntt_block(int logn) { return dim3(1u << (logn - 4)); }
+static size_t ntt_lds(int logn) { return (size_t)((1 << logn) + ((1 << logn) >> 5)) * 8; }
+
+// ---------------------------------------------------------------- looped transforms (many residues)
+// With one residue per workgroup, the residue-sized LDS admits one workgroup per CU (at N = 2^14),
+// which runs load -> passes -> store with the CU's memory traffic and its arithmetic in turn, and waits for
+// the next workgroup's dispatch after its last wave ends. For launches of many residues, a grid of
+// as many workgroups as fit on the CUs at once loops over the residues instead: while the waves transform one residue,
+// the input lines of the next are brought into L2 (one word per line and thread, loop_touch), so
+// that its loads at the next iteration are L2 hits; a second barrier per residue keeps the next
+// exchange from overwriting LDS words that a slower wave still reads. Each arithmetic class (FP64 or integer
+// primes) is a kernel of its own, launched over the residues of its primes, so that each is held
+// to its own register budget. Every butterfly is the one of the one-workgroup form, so the
+// residues are the same. The lift and the combine come from the Op (fetch / prep / store_*).
+//
+// The residues of a launch are numbered in periods (the k + 1 targets of a ModUp digit, the k
+// primes of a ModDown group); those of the kernel's class are the r with r mod period in pos.
+// Period d goes to XCD d mod 8 (workgroup b runs on XCD b mod 8), and the S workgroups of an XCD
+// take its residues in turn, so the residues of one period, which read the same input words, run
+// at the same time on one L2.
+// x, opaque to the compiler: index arithmetic derived from it inside a loop iteration is redone
+// there rather than hoisted out of the loop and kept in registers across iterations.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+struct SlotSet {
+    int period, n;
+    int pos[kMaxMods];
+};
+
+struct LoopUnits {
+    int x, S, U, count;
+};
+__device__ __forceinline__ LoopUnits loop_units(const SlotSet &ss, int count) {
+    LoopUnits lu;
+    lu.x = blockIdx.x & 7;
+    lu.S = gridDim.x >> 3;
+    lu.count = count;
+    const int D = (count + ss.period - 1) / ss.period;
+    lu.U = (D > lu.x ? (D - 1 - lu.x) / 8 + 1 : 0) * ss.n;
+    return lu;
+}
+__device__ __forceinline__ int loop_residue(const LoopUnits &lu, const SlotSet &ss, int u) {
+    return ((u / ss.n) * 8 + lu.x) * ss.period + ss.pos[u % ss.n];
+}
+__device__ __forceinline__ int loop_next(const LoopUnits &lu, const SlotSet &ss, int u) {
+    for (u += lu.S; u < lu.U && loop_residue(lu, ss, u) >= lu.count; u += lu.S) {}
+    return u;
+}
+__device__ __forceinline__ int loop_first(const LoopUnits &lu, const SlotSet &ss) {
+    const int u = blockIdx.x >> 3;
+    return u < lu.U && loop_residue(lu, ss, u) >= lu.count ? loop_next(lu, ss, u) : u;
+}
+
+// Bring the input lines of residue u into L2: each thread loads one word of its own 128-byte line
+// (16 T words = one residue). The loaded word is kept until the end of the iteration (keep), so
+// the load is neither dropped nor waited for before then.
+template <int LOGN, class Op>
+__device__ __forceinline__ u64 loop_touch(const Op &op, const LoopUnits &lu, const SlotSet &ss, int u) {
+    if (u >= lu.U) return 0;
+    const int r = loop_residue(lu, ss, u);
+    if (op.copy_only(r)) return 0;
+    return op.fetch(r, opaque(threadIdx.x) * 16);
+}
+__device__ __forceinline__ void keep(u64 x) { asm volatile("" ::"v"(x)); }
+
+template <int LOGN, class Op, bool FP>
+__global__ void __launch_bounds__(Geo<LOGN>::T)
+k_fwd_loop(Op op, SlotSet ss, int count, Tables tab) {
+    extern __shared__ u64 lds[];
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T, TOP = LOGN - 4;
+    const LoopUnits lu = loop_units(ss, count);
+    for (int u = loop_first(lu, ss); u < lu.U;) {
+        const int r = loop_residue(lu, ss, u), un = loop_next(lu, ss, u);
+        const int pi = op.prime(r);
+        const PrimeConst p = tab.pc[pi];
+        const int tid = opaque(threadIdx.x);
+        if (op.copy_only(r)) {
+            const u64 t = loop_touch<LOGN>(op, lu, ss, un);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) op.copy(r, tid + T * e, tab);
+            keep(t);
+            u = un;
+            continue;
+        }
+        if constexpr (FP) {
+            double d[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) d[e] = u64_to_fp(op.load(r, tid + T * e, p, tab));
+            const u64 t = loop_touch<LOGN>(op, lu, ss, un);
+            const double *tw = reinterpret_cast<const double *>(tab.tws + (long)pi * N);
+            double *dl = reinterpret_cast<double *>(lds);
+            fwd_pass_fp<LOGN, TOP, 4>(d, tid, tw, p.qd, p.qinv);
+            __syncthreads();                      // every wave is done with the previous residue's LDS
+            to_lds<LOGN, TOP, 4>(d, dl, tid);
+            __syncthreads();
+            fwd_sub_plan<LOGN>(d, dl, tid, [&](auto lo, auto rb, auto wv) {
+                fwd_pass_fp<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(d, tid, tw, p.qd,
+                                                                                               p.qinv);
+            });
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int j = wave_elem(tid, e);
+                op.store_fwd(r, j, lds[lds_idx(j)], true, p, tab);
+            }
+            keep(t);
+        } else {
+            u64 v[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = op.load(r, tid + T * e, p, tab);
+            const u64 t = loop_touch<LOGN>(op, lu, ss, un);
+            const u64 *tw = tab.tw + (long)pi * N, *tws = tab.tws + (long)pi * N;
+            fwd_pass<LOGN, TOP, 4>(v, tid, tw, tws, p.q, p.q2, p.qn, p.nq2);
+            __syncthreads();
+            to_lds<LOGN, TOP, 4>(v, lds, tid);
+            __syncthreads();
+            fwd_sub_plan<LOGN>(v, lds, tid, [&](auto lo, auto rb, auto wv) {
+                fwd_pass<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(v, tid, tw, tws, p.q,
+                                                                                            p.q2, p.qn, p.nq2);
+            });
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int j = wave_elem(tid, e);
+                op.store_fwd(r, j, lds[lds_idx(j)], false, p, tab);
+            }
+            keep(t);
+        }
+        u = un;
+    }
+}
+
+template <int LOGN, class Op, bool FP>
+__global__ void __launch_bounds__(Geo<LOGN>::T)
+k_inv_loop(Op op, SlotSet ss, int count, Tables tab) {
+    extern __shared__ u64 lds[];
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T, TOP = LOGN - 4;
+    const LoopUnits lu = loop_units(ss, count);
+    for (int u = loop_first(lu, ss); u < lu.U;) {
+        const int r = loop_residue(lu, ss, u), un = loop_next(lu, ss, u);
+        const int pi = op.prime(r);
+        const PrimeConst p = tab.pc[pi];
+        const int tid = opaque(threadIdx.x);
+        u64 x[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) x[e] = op.load(r, wave_elem(tid, e), p, tab);
+        const u64 t = loop_touch<LOGN>(op, lu, ss, un);
+        __syncthreads();                          // every wave is done with the previous residue's LDS
+        if constexpr (FP) {
+            double *dl = reinterpret_cast<double *>(lds);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) dl[lds_idx(wave_elem(tid, e))] = u64_to_fp(x[e]);
+            wave_sync();
+            double d[16];
+            const double *tw = reinterpret_cast<const double *>(tab.itws + (long)pi * N);
+            inv_sub_plan<LOGN>(d, dl, tid, [&](auto lo, auto rb, auto wv) {
+                inv_pass_fp<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(d, tid, tw, p.qd,
+                                                                                               p.qinv);
+            });
+            __syncthreads();
+            from_lds<LOGN, TOP, 4>(d, dl, tid);
+            inv_pass_fp<LOGN, TOP, 4>(d, tid, tw, p.qd, p.qinv);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) op.store_inv_fp(r, tid + T * e, d[e], p);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) lds[lds_idx(wave_elem(tid, e))] = x[e];
+            wave_sync();
+            u64 v[16];
+            const u64 *tw = tab.itw + (long)pi * N, *tws = tab.itws + (long)pi * N;
+            inv_sub_plan<LOGN>(v, lds, tid, [&](auto lo, auto rb, auto wv) {
+                inv_pass<LOGN, decltype(lo)::value, decltype(rb)::value, decltype(wv)::value>(v, tid, tw, tws, p.q,
+                                                                                            p.q2, p.qn, p.nq2);
+            });
+            __syncthreads();
+            from_lds<LOGN, TOP, 4>(v, lds, tid);
+            inv_pass<LOGN, TOP, 4>(v, tid, tw, tws, p.q, p.q2, p.qn, p.nq2);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) op.store_inv(r, tid + T * e, v[e], p);
+        }
+        keep(t);
+        u = un;
+    }
+}
+
+// The slots of a period of residue primes `prime[0..period)` by class (0: FP64, 1: integer).
+static void class_slots(const int *prime, int period, const Tables &tab, SlotSet (&ss)[2]) {
+    ss[0] = SlotSet{period, 0, {}};
+    ss[1] = SlotSet{period, 0, {}};
+    for (int i = 0; i < period; ++i) {
+        SlotSet &s = ss[tab.host_fp[prime[i]] ? 0 : 1];
+        s.pos[s.n++] = i;
+    }
+}
+
+template <int LOGN, bool INV, class Op>
+static void launch_loop_one(const Op &op, const SlotSet (&ss)[2], int count, const Tables &tab, hipStream_t st) {
+    const size_t sh = ntt_lds(LOGN);
+    const int per_cu = (size_t)tab.lds_cu >= 2 * sh ? (int)((size_t)tab.lds_cu / sh) : 1;   // resident per CU
+    const dim3 grid((unsigned)((tab.cus & ~7) * per_cu)), blk = ntt_block(LOGN);
+    for (int c = 0; c < 2; ++c) {
+        if (ss[c].n == 0) continue;
+        if constexpr (INV) {
+            if (c == 0) hipLaunchKernelGGL((k_inv_loop<LOGN, Op, true>), grid, blk, sh, st, op, ss[c], count, tab);
+            else hipLaunchKernelGGL((k_inv_loop<LOGN, Op, false>), grid, blk, sh, st, op, ss[c], count, tab);
+        } else {
+            if (c == 0) hipLaunchKernelGGL((k_fwd_loop<LOGN, Op, true>), grid, blk, sh, st, op, ss[c], count, tab);
+            else hipLaunchKernelGGL((k_fwd_loop<LOGN, Op, false>), grid, blk, sh, st, op, ss[c], count, tab);
+        }
+    }
+}
+
+template <bool INV, class Op>
+static void launch_loop(int logn, const Op &op, const int *prime, int period, int count, const Tables &tab,
+                        hipStream_t st) {
+    SlotSet ss[2];
+    class_slots(prime, period, tab, ss);
+    switch (logn) {
+        case 12: launch_loop_one<12, INV>(op, ss, count, tab, st); break;
+        case 13: launch_loop_one<13, INV>(op, ss, count, tab, st); break;
+        default: launch_loop_one<14, INV>(op, ss, count, tab, st); break;
+    }
+}
+
+// A launch loops when each arithmetic class among its residues has at least kn.ntt_loop residues
+// per CU (0: never): each class is a launch of its own with a fixed share of residues per
+// workgroup, and few residues per CU would leave a tail of idle CUs behind each.
+static bool use_loop(int count, const int *prime, int period, const Tables &tab, const Knobs &kn) {
+    if (kn.ntt_loop <= 0 || tab.cus < 8 || period <= 0) return false;
+    long per_class[2] = {0, 0};
+    for (int i = 0; i < period; ++i) {
+        const long n = count / period + (i < count % period ? 1 : 0);
+        per_class[tab.host_fp[prime[i]] ? 0 : 1] += n;
+    }
+    for (long n : per_class)
+        if (n > 0 && n < (long)kn.ntt_loop * tab.cus) return false;
+    return true;
 }
 
 // Signed 64-bit coefficients -> residues mod q_p -> NTT. src: dense [G][N] int64; out: [G][P][N]
@@ -1761,6 +2006,14 @@ static hipError_t prepare_all() {
     if ((e = set_lds(k_ntt_inv<LOGN>, b)) != hipSuccess) return e;
     if ((e = set_lds(k_modup<LOGN>, b)) != hipSuccess) return e;
     if ((e = set_lds(k_drop<LOGN>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_fwd_loop<LOGN, OpNtt, true>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_fwd_loop<LOGN, OpNtt, false>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_inv_loop<LOGN, OpNtt, true>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_inv_loop<LOGN, OpNtt, false>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_fwd_loop<LOGN, OpModup, true>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_fwd_loop<LOGN, OpModup, false>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_fwd_loop<LOGN, OpDrop, true>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_fwd_loop<LOGN, OpDrop, false>, b)) != hipSuccess) return e;
     return set_lds(k_int_ntt<LOGN>, b);
 }
 
@@ -1851,16 +2104,20 @@ hipError_t kernels_prepare(int logn) {
     }
 }
 
-static dim3 ntt_block(int logn) { return dim3(1u << (logn - 4)); }
-static size_t ntt_lds(int logn) { return (size_t)((1 << logn) + ((1 << logn) >> 5)) * 8; }
 
 void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
-                int count, const Tables &tab, hipStream_t st, u64 *split_tmp) {
+                int count, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp) {
     if (count <= 0) return;
     if (split_tmp) {
         const OpNtt op{in, imap, out, omap, logn};
         if (inverse) launch_split_inv(logn, op, split_tmp, count, tab, st);
         else launch_split_fwd(logn, op, split_tmp, count, tab, st);
+        return;
+    }
+    if (use_loop(count, imap.prime, imap.per, tab, kn)) {
+        const OpNtt op{in, imap, out, omap, logn};
+        if (inverse) launch_loop<true>(logn, op, imap.prime, imap.per, count, tab, st);
+        else launch_loop<false>(logn, op, imap.prime, imap.per, count, tab, st);
         return;
     }
     const dim3 grid(count), blk = ntt_block(logn);
@@ -1888,6 +2145,12 @@ void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u
         return;
     }
     const int units = groups * k, xo = kn.ntt_xcd ? 1 : 0;
+    int prime[kMaxMods];
+    for (int t = 0; t <= k; ++t) prime[t] = t < k ? t : nq;
+    if (use_loop(units * (k + 1), prime, k + 1, tab, kn)) {
+        launch_loop<false>(logn, OpModup{coef, d, dmap, digits, k, nq, logn}, prime, k + 1, units * (k + 1), tab, st);
+        return;
+    }
     const dim3 grid(xo ? ((units + 7) / 8) * 8 * (k + 1) : units * (k + 1)), blk = ntt_block(logn);
     const size_t sh = ntt_lds(logn);
     switch (logn) {
@@ -1905,6 +2168,12 @@ void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, 
     const GrpMap xm = xmap ? *xmap : GrpMap{0, (k + 1) * N, 0, 1};
     if (split_tmp) {
         launch_split_fwd(logn, OpDrop{x, xm, last, out, k, drop, logn, add}, split_tmp, groups * k, tab, st);
+        return;
+    }
+    int prime[kMaxMods];
+    for (int i = 0; i < k; ++i) prime[i] = i;
+    if (use_loop(groups * k, prime, k, tab, kn)) {
+        launch_loop<false>(logn, OpDrop{x, xm, last, out, k, drop, logn, add}, prime, k, groups * k, tab, st);
         return;
     }
     const int xo = kn.ntt_xcd ? 1 : 0;

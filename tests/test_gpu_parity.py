@@ -356,6 +356,38 @@ def test_split_transforms_equal_one_workgroup_form(name):
     assert np.array_equal(outs[0][3], host)
 
 
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_looped_transforms_equal_one_workgroup_form(name):
+    """Launches of many transforms run a grid of resident workgroups that loop over them (the
+    ntt_loop knob): a forward pass of 16 ciphertexts and 2050 residue transforms (the prime pattern
+    ends in a partial period) give the same residues looped (every launch with at least one
+    transform per CU in each class) and in the one-workgroup-per-transform form."""
+    o, c = _orc(name), _ctx(name)
+    lk, _, _, okeys, rlk = _keys(name)
+    model, _ = _raw_model(name, seed=33, lazy="qp")
+    dev, _ = _fresh_ct(name, 27, count=16)
+    rng = np.random.default_rng(11)
+    idx = [i % o.np for i in range(2050)]
+    host = np.stack([rng.integers(0, o.primes[p], size=o.n, dtype=np.uint64) for p in idx])
+    before = c.knob("ntt_loop")
+    try:
+        outs = {}
+        for loop in (1, 0):
+            c.knob("ntt_loop", loop)
+            res = [_u64(c.forward(model, lk, dev))]
+            buf = _dev(host)
+            c.ntt(buf, idx)
+            res.append(_u64(buf))
+            c.ntt(buf, idx, inverse=True)
+            res.append(_u64(buf))
+            outs[loop] = res
+    finally:
+        c.knob("ntt_loop", before)
+    for a, b in zip(outs[1], outs[0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(outs[1][2], host)
+
+
 def test_profile_bytes_model():
     """The algorithmic bytes the library records for a key product: one rotation of 3 ciphertexts
     reads 3 k(k+1) digit rows and one key set's 2 k(k+1) key rows and writes 3 2(k+1) rows, N
