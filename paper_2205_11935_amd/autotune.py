@@ -72,11 +72,21 @@ def _median(xs):
     return xs[len(xs) // 2]
 
 
+def pick(times: Dict[int, float], entry: int, margin: float) -> int:
+    """The fastest value of `times` ({value: ms}), unless it is within `margin` of `entry`'s."""
+    fastest = min(times, key=times.get)
+    if entry in times and times[fastest] >= (1.0 - margin) * times[entry]:
+        return entry
+    return fastest
+
+
 def tune(ctx, run: Callable[[], object], reps: int = 3,
-         candidates: Optional[Dict[str, List[int]]] = None) -> Dict:
+         candidates: Optional[Dict[str, List[int]]] = None, margin: float = 0.01) -> Dict:
     """run() enqueues the workload on the current stream and returns its output tensor. Returns
     {"knobs": best settings (applied to ctx), "baseline_ms": time with the settings on entry,
-    "best_ms": time with the best ones, "trials": {knob: {value: ms}}}."""
+    "best_ms": time with the best ones, "trials": {knob: {value: ms}}}. A knob leaves the value it
+    had on entry only for one that is faster by more than `margin` (a fraction): differences
+    within run-to-run noise, e.g. of a knob the workload does not exercise, change nothing."""
     import torch
     candidates = candidates or CANDIDATES
     stream = torch.cuda.current_stream()
@@ -99,6 +109,7 @@ def tune(ctx, run: Callable[[], object], reps: int = 3,
     trials: Dict[str, Dict[int, float]] = {}
     for name, values in candidates.items():
         trials[name] = {}
+        entry = ctx.knob(name)
         for v in values:
             ctx.knob(name, v)
             out = run()
@@ -107,7 +118,7 @@ def tune(ctx, run: Callable[[], object], reps: int = 3,
                 ctx.knob(name, best[name])
                 raise RuntimeError("knob %s=%d changed the result" % (name, v))
             trials[name][v] = timed()
-        best[name] = min(trials[name], key=trials[name].get)
+        best[name] = pick(trials[name], entry, margin)
         ctx.knob(name, best[name])
     return {"knobs": best, "baseline_ms": baseline, "best_ms": timed(),
             "trials": {k: {str(v): round(t, 3) for v, t in d.items()} for k, d in trials.items()}}

@@ -1679,7 +1679,9 @@ k_mac(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long 
 // and 2^60 (c[1] takes both cross products). Every 8 terms the columns are normalized (c0, c1 <
 // 2^30, c2 < 2^62), which keeps each below 2^64 for the next 8: c0 < 2^30 + 8 2^60,
 // c1 < 2^30 + 16 (2^30 - 1)^2, c2 < 2^62 + 8 2^60 + 2^34. Once per output the 128-bit value
-// c0 + c1 2^30 + c2 2^60 is reduced mod q. Same staging, grid and outputs as k_mac.
+// c0 + c1 2^30 + c2 2^60 is reduced mod q. Same staging, grid and outputs as k_mac; plaintext
+// words are staged split into their limbs, wl | wh 2^32, so that the waves reading the LDS copy
+// find the limbs as register halves.
 template <int KC>
 __global__ void __launch_bounds__(512)
 k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long rot_sb,
@@ -1700,6 +1702,7 @@ k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, 
     const u64 *rot_b = rot + (long)(live ? b : 0) * rot_sb + i * N + n0 + nl;
     const u64 *bk = bank + (long)kc0 * t1 * kn + i * N + n0 + nl;
     auto bank_row = [&](int j0, int r) -> u64 { return bk[((long)(r % KC) * t1 + j0 + r / KC) * kn]; };
+    auto split = [](u64 w) -> u64 { return (w & kM30) | ((w >> 30) << 32); };
     u64 c[KC][2][3];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
@@ -1716,7 +1719,7 @@ k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, 
                 xr[jj][1] = __builtin_nontemporal_load(&src[kn]);
             }
         }
-        for (int r = bl; r < jn * KC; r += by) wt[0][r * 64 + nl] = bank_row(0, r);
+        for (int r = bl; r < jn * KC; r += by) wt[0][r * 64 + nl] = split(bank_row(0, r));
     }
     __syncthreads();
     int since = 0;                               // terms added since the last normalization
@@ -1755,7 +1758,7 @@ k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, 
 #pragma unroll
                 for (int kk = 0; kk < KC; ++kk) {
                     const u64 w = w_l[(jj * KC + kk) * 64 + nl];
-                    const u32 wl = (u32)w & (u32)kM30, wh = (u32)(w >> 30);
+                    const u32 wl = (u32)w, wh = (u32)(w >> 32);
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
                         c[kk][q][0] += (u64)xl[q] * wl;
@@ -1771,9 +1774,9 @@ k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, 
 #pragma unroll
         for (int s = 0; s < kSt; ++s) {
             const int r = bl + s * by;
-            if (r < rows1) w_n[r * 64 + nl] = bs[s];
+            if (r < rows1) w_n[r * 64 + nl] = split(bs[s]);
         }
-        for (int r = bl + kSt * by; r < rows1; r += by) w_n[r * 64 + nl] = bank_row(j1, r);
+        for (int r = bl + kSt * by; r < rows1; r += by) w_n[r * 64 + nl] = split(bank_row(j1, r));
         __syncthreads();
     }
     if (live) {
@@ -2296,7 +2299,8 @@ void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb
         bool limb = kn.mac_limb != 0;
         for (int y = 0; y < in.n; ++y) limb = limb && tab.host_lt60[in.prime[y]];
         if (limb) {
-            const int kl = mac_chunk(t2, kn.mac_chunk_cap < 8 ? kn.mac_chunk_cap : 8);   // 12 VGPRs per chunk entry
+            // 12 VGPRs per chunk entry; at most 8 (KC = 12 fits at 2 waves per SIMD but runs slower)
+            const int kl = mac_chunk(t2, kn.mac_chunk_cap < 8 ? kn.mac_chunk_cap : 8);
             const dim3 grid((1u << logn) / 64, in.n, ((B + by_int - 1) / by_int) * (t2 / kl)), blk(64, by_int);
             switch (kl) {
 #define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac_limb<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, in, tab.pc); break;

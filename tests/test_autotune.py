@@ -18,6 +18,14 @@ class FakeCtx:
         return self.k[name]
 
 
+def test_pick_keeps_entry_within_margin():
+    # a candidate replaces the value on entry only when faster by more than the margin
+    assert autotune.pick({128: 18.10, 0: 18.00, 64: 18.05}, 128, 0.01) == 128
+    assert autotune.pick({128: 18.50, 0: 18.00}, 128, 0.01) == 0
+    assert autotune.pick({4: 10.0, 8: 9.0}, 8, 0.01) == 8
+    assert autotune.pick({4: 10.0, 8: 9.0}, 16, 0.01) == 8     # entry value not among the trials
+
+
 def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "tune.json")
     k1 = autotune.cache_key("gfx950", 14, [3, 5, 7])
