@@ -56,7 +56,8 @@ UNIT_OPS = {
     "mac": {"fp": {"fma64": 7}, "int": {"mad64": 4, "add32": 1}},
     "keyip": {"fp": {"fma64": 7}, "int": {"mad64": 4.7, "add32": 3.5}},
 }
-NTT_FAMILIES = ("k_ntt_fwd", "k_ntt_inv", "k_modup", "k_drop", "k_int_ntt")
+NTT_FAMILIES = ("k_ntt_fwd", "k_ntt_inv", "k_modup", "k_drop", "k_int_ntt",
+                "k_ntt_fwd_fp", "k_ntt_inv_fp", "k_modup_fp", "k_drop_fp")
 MAC_FAMILIES = ("k_mac", "k_mac_fp", "k_mac_direct", "k_tensor")
 
 

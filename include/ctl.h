@@ -195,7 +195,8 @@ int ctl_pt_import(ctl_ctx *ctx, const int64_t *coeffs, int n_pt, int k, int ext,
  * the recorded events and returns, for kernel family `family` (0 .. ctl_profile_families()-1),
  * the number of launches, their summed durations in milliseconds, and the algorithmic work they
  * processed since profiling was enabled: for the NTT-bearing kernels (k_ntt_fwd, k_ntt_inv,
- * k_modup, k_drop, k_int_ntt) the number of length-N residue transforms; for the product kernels
+ * k_modup, k_drop, k_int_ntt; a looped launch records its FP64-prime kernel under the same name
+ * with an _fp suffix) the number of length-N residue transforms; for the product kernels
  * (k_keyip, k_keyip_fp, k_mac, k_mac_fp, k_mac_direct, k_tensor) the number of 64-bit modular
  * products; for k_add_terms the number of
  * residue words written. fp_work_out receives the part of that work done on primes below 2^41,

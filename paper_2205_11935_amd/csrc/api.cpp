@@ -39,13 +39,16 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 enum Family { F_NTT_FWD, F_NTT_INV, F_MODUP, F_KEYIP, F_DROP, F_MAC, F_ADD, F_TENSOR, F_INT_NTT, F_OTHER,
-              F_MAC_FP, F_MAC_DIRECT, F_KEYIP_FP, F_COUNT };
+              F_MAC_FP, F_MAC_DIRECT, F_KEYIP_FP, F_NTT_FWD_FP, F_NTT_INV_FP, F_MODUP_FP, F_DROP_FP, F_COUNT };
 // Names of the kernels each family brackets (k_mac and k_keyip: the MAC and the key product over
 // integer primes, limb or 128-bit form; k_mac_fp and k_keyip_fp: over FP64 primes; k_mac_direct:
-// the unstaged MAC of small batches, all primes in one launch).
+// the unstaged MAC of small batches, all primes in one launch; the transform families cover every
+// prime of a launch, except that a looped launch runs one kernel per class and records its
+// FP64-prime kernel under the _fp family).
 const char *const kFamilyNames[F_COUNT] = {"k_ntt_fwd", "k_ntt_inv", "k_modup", "k_keyip", "k_drop",
                                             "k_mac", "k_add_terms", "k_tensor", "k_int_ntt", "other",
-                                            "k_mac_fp", "k_mac_direct", "k_keyip_fp"};
+                                            "k_mac_fp", "k_mac_direct", "k_keyip_fp", "k_ntt_fwd_fp",
+                                            "k_ntt_inv_fp", "k_modup_fp", "k_drop_fp"};
 
 // Workspace slots: each grows on demand and is reused by later calls on the same context.
 enum Slot {
@@ -289,6 +292,26 @@ double fp_share_range(const ctl_ctx *c, int k, bool with_p) {
     return fp_share(c, pr, n);
 }
 
+// One NTT-bearing launch, bracketed per kernel: a looped launch (classes != 0) runs one kernel per
+// arithmetic class, the FP64-prime one recorded under fam_fp with its share of the work.
+template <typename Launch>
+void transforms(ctl_ctx *c, hipStream_t st, Family fam, Family fam_fp, double work, double share, int classes,
+                Launch &&launch) {
+    if (!classes) {
+        CTL_PROF(fam, work, share);
+        launch(-1);
+        return;
+    }
+    if (classes & 1) {
+        CTL_PROF(fam_fp, work * share, 1.0);
+        launch(0);
+    }
+    if (classes & 2) {
+        CTL_PROF(fam, work * (1.0 - share), 0.0);
+        launch(1);
+    }
+}
+
 // The plaintext-product MAC over `rows` residue rows (the last one mod P when ext), bracketed per
 // kernel: the FP64-prime and integer-prime launches, or the one unstaged launch of a small batch.
 void run_mac(ctl_ctx *c, hipStream_t st, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb, const u64 *bank,
@@ -398,8 +421,20 @@ int modup_digits(ctl_ctx *c, hipStream_t st, int k, int G, const u64 *d, const R
     u64 *coef, *dig;
     CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
     CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
-    { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, c->knobs, st, split_buf(c, st, G * k)); }
-    { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st, split_buf(c, st, G * k * (k + 1))); }
+    {
+        u64 *sp = split_buf(c, st, G * k);
+        transforms(c, st, F_NTT_INV, F_NTT_INV_FP, G * k, fp_share_range(c, k, false),
+                   ntt_loop_classes(G * k, dmap, c->tab, c->knobs, sp), [&](int cls) {
+                       launch_ntt(logn, true, d, dmap, coef, dense_map(k), G * k, c->tab, c->knobs, st, sp, cls);
+                   });
+    }
+    {
+        u64 *sp = split_buf(c, st, G * k * (k + 1));
+        transforms(c, st, F_MODUP, F_MODUP_FP, G * k * k, modup_share(c, k),
+                   modup_loop_classes(G, k, nq, c->tab, c->knobs, sp), [&](int cls) {
+                       launch_modup(logn, coef, d, dmap, dig, G, k, nq, c->tab, c->knobs, st, sp, cls);
+                   });
+    }
     *dig_out = dig;
     return check_launch();
 }
@@ -494,8 +529,20 @@ int keyswitch_lower(ctl_ctx *c, hipStream_t st, int k, int groups, const u64 *U,
     pm.gstride = k + 1;
     pm.ostride = k + 1;
     pm.prime[0] = nq;
-    { CTL_PROF(F_NTT_INV, groups, fp_share_range(c, 0, true)); launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), groups, c->tab, c->knobs, st, split_buf(c, st, groups)); }
-    { CTL_PROF(F_DROP, (double)groups * k, fp_share_range(c, k, false)); launch_drop(logn, U, plast, out, groups, k, nq, add, c->tab, c->knobs, st, nullptr, split_buf(c, st, groups * k)); }
+    {
+        u64 *sp = split_buf(c, st, groups);
+        transforms(c, st, F_NTT_INV, F_NTT_INV_FP, groups, fp_share_range(c, 0, true),
+                   ntt_loop_classes(groups, pm, c->tab, c->knobs, sp), [&](int cls) {
+                       launch_ntt(logn, true, U, pm, plast, dense_map(1, nq), groups, c->tab, c->knobs, st, sp, cls);
+                   });
+    }
+    {
+        u64 *sp = split_buf(c, st, groups * k);
+        transforms(c, st, F_DROP, F_DROP_FP, (double)groups * k, fp_share_range(c, k, false),
+                   drop_loop_classes(groups, k, c->tab, c->knobs, sp), [&](int cls) {
+                       launch_drop(logn, U, plast, out, groups, k, nq, add, c->tab, c->knobs, st, nullptr, sp, cls);
+                   });
+    }
     return check_launch();
 }
 
@@ -522,12 +569,24 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
     m.gstride = k;
     m.ostride = k;
     m.prime[0] = k - 1;
-    { CTL_PROF(F_NTT_INV, B * 2, fp_share(c, &m.prime[0], 1)); launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, c->knobs, st, split_buf(c, st, B * 2)); }
+    {
+        u64 *sp = split_buf(c, st, B * 2);
+        transforms(c, st, F_NTT_INV, F_NTT_INV_FP, B * 2, fp_share(c, &m.prime[0], 1),
+                   ntt_loop_classes(B * 2, m, c->tab, c->knobs, sp), [&](int cls) {
+                       launch_ntt(logn, true, in, m, last, dense_map(1, k - 1), B * 2, c->tab, c->knobs, st, sp, cls);
+                   });
+    }
     DropAdd add{};
     add.R = 1;
     add.mask = 0;
     add.gal[0] = 1;
-    { CTL_PROF(F_DROP, B * 2 * (k - 1), fp_share_range(c, k - 1, false)); launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, c->knobs, st, nullptr, split_buf(c, st, B * 2 * (k - 1))); }
+    {
+        u64 *sp = split_buf(c, st, B * 2 * (k - 1));
+        transforms(c, st, F_DROP, F_DROP_FP, B * 2 * (k - 1), fp_share_range(c, k - 1, false),
+                   drop_loop_classes(B * 2, k - 1, c->tab, c->knobs, sp), [&](int cls) {
+                       launch_drop(logn, in, last, out, B * 2, k - 1, k - 1, add, c->tab, c->knobs, st, nullptr, sp, cls);
+                   });
+    }
     return check_launch();
 }
 
@@ -773,9 +832,23 @@ int dense_qp_groups(ctl_ctx *c, hipStream_t st, const ctl_model *const *models, 
             pm.gstride = 2L * (k + 1);
             pm.ostride = (long)q.t2 * 2 * (k + 1);
             pm.prime[0] = nq;
-            { CTL_PROF(F_NTT_INV, q.B * q.R2, fp_share_range(c, 0, true)); launch_ntt(logn, true, ig, pm, plast + q.i1_off * N, dense_map(1, nq), q.B * q.R2, c->tab, c->knobs, st, split_buf(c, st, q.B * q.R2)); }
+            {
+                u64 *sp = split_buf(c, st, q.B * q.R2);
+                transforms(c, st, F_NTT_INV, F_NTT_INV_FP, q.B * q.R2, fp_share_range(c, 0, true),
+                           ntt_loop_classes(q.B * q.R2, pm, c->tab, c->knobs, sp), [&](int cls) {
+                               launch_ntt(logn, true, ig, pm, plast + q.i1_off * N, dense_map(1, nq), q.B * q.R2, c->tab,
+                                          c->knobs, st, sp, cls);
+                           });
+            }
             GrpMap xm{3L * (k + 1) * N, (long)q.t2 * ext, ext, q.R2};
-            { CTL_PROF(F_DROP, (double)q.B * q.R2 * k, fp_share_range(c, k, false)); launch_drop(logn, ig, plast + q.i1_off * N, i1 + q.i1_off * k * N, q.B * q.R2, k, nq, none, c->tab, c->knobs, st, &xm, split_buf(c, st, q.B * q.R2 * k)); }
+            {
+                u64 *sp = split_buf(c, st, q.B * q.R2 * k);
+                transforms(c, st, F_DROP, F_DROP_FP, (double)q.B * q.R2 * k, fp_share_range(c, k, false),
+                           drop_loop_classes(q.B * q.R2, k, c->tab, c->knobs, sp), [&](int cls) {
+                               launch_drop(logn, ig, plast + q.i1_off * N, i1 + q.i1_off * k * N, q.B * q.R2, k, nq, none,
+                                           c->tab, c->knobs, st, &xm, sp, cls);
+                           });
+            }
         }
         u64 *dig, *U;
         CTL_TRY(modup_digits(c, st, k, (int)i1_w, i1, dense_map(k), &dig));   // one ModUp for every group

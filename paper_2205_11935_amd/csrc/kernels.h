@@ -100,14 +100,24 @@ struct Knobs {
 
 // The NTT-bearing launches: with split_tmp (a buffer of one residue per transform of the launch,
 // [count][N] words) every transform is split over N / 1024 single-wave workgroups in two launches,
-// for launches of few transforms (the same residues either way).
+// for launches of few transforms; launches of many (kn.ntt_loop) run as looped workgroups, one
+// kernel per arithmetic class present; otherwise one workgroup per transform. The same residues
+// come out of every form. cls (looped launches only): 0 launches the FP64-prime kernel alone, 1
+// the integer-prime one, -1 both.
 void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
-                int count, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp = nullptr);
+                int count, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp = nullptr,
+                int cls = -1);
 void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
-                  int nq, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp = nullptr);
+                  int nq, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp = nullptr,
+                  int cls = -1);
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
                  const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st,
-                 const GrpMap *xmap = nullptr, u64 *split_tmp = nullptr);
+                 const GrpMap *xmap = nullptr, u64 *split_tmp = nullptr, int cls = -1);
+// The classes (bit 0: FP64 primes, bit 1: integer primes) that the launch above with the same
+// arguments runs as separate looped kernels; 0 when it runs in another form.
+int ntt_loop_classes(int count, const ResMap &imap, const Tables &tab, const Knobs &kn, const u64 *split_tmp);
+int modup_loop_classes(int groups, int k, int nq, const Tables &tab, const Knobs &kn, const u64 *split_tmp);
+int drop_loop_classes(int groups, int k, const Tables &tab, const Knobs &kn, const u64 *split_tmp);
 void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,
                     const Tables &tab, hipStream_t st);
 // Key products run one launch per arithmetic class of their rows: FP64 products (primes below

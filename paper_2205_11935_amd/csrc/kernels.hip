@@ -1143,12 +1143,13 @@ static void class_slots(const int *prime, int period, const Tables &tab, SlotSet
 }
 
 template <int LOGN, bool INV, class Op>
-static void launch_loop_one(const Op &op, const SlotSet (&ss)[2], int count, const Tables &tab, hipStream_t st) {
+static void launch_loop_one(const Op &op, const SlotSet (&ss)[2], int count, const Tables &tab, hipStream_t st,
+                            int cls) {
     const size_t sh = ntt_lds(LOGN);
     const int per_cu = (size_t)tab.lds_cu >= 2 * sh ? (int)((size_t)tab.lds_cu / sh) : 1;   // resident per CU
     const dim3 grid((unsigned)((tab.cus & ~7) * per_cu)), blk = ntt_block(LOGN);
     for (int c = 0; c < 2; ++c) {
-        if (ss[c].n == 0) continue;
+        if (ss[c].n == 0 || (cls >= 0 && c != cls)) continue;
         if constexpr (INV) {
             if (c == 0) hipLaunchKernelGGL((k_inv_loop<LOGN, Op, true>), grid, blk, sh, st, op, ss[c], count, tab);
             else hipLaunchKernelGGL((k_inv_loop<LOGN, Op, false>), grid, blk, sh, st, op, ss[c], count, tab);
@@ -1161,29 +1162,58 @@ static void launch_loop_one(const Op &op, const SlotSet (&ss)[2], int count, con
 
 template <bool INV, class Op>
 static void launch_loop(int logn, const Op &op, const int *prime, int period, int count, const Tables &tab,
-                        hipStream_t st) {
+                        hipStream_t st, int cls) {
     SlotSet ss[2];
     class_slots(prime, period, tab, ss);
     switch (logn) {
-        case 12: launch_loop_one<12, INV>(op, ss, count, tab, st); break;
-        case 13: launch_loop_one<13, INV>(op, ss, count, tab, st); break;
-        default: launch_loop_one<14, INV>(op, ss, count, tab, st); break;
+        case 12: launch_loop_one<12, INV>(op, ss, count, tab, st, cls); break;
+        case 13: launch_loop_one<13, INV>(op, ss, count, tab, st, cls); break;
+        default: launch_loop_one<14, INV>(op, ss, count, tab, st, cls); break;
     }
 }
 
 // A launch loops when each arithmetic class among its residues has at least kn.ntt_loop residues
 // per CU (0: never): each class is a launch of its own with a fixed share of residues per
 // workgroup, and few residues per CU would leave a tail of idle CUs behind each.
-static bool use_loop(int count, const int *prime, int period, const Tables &tab, const Knobs &kn) {
-    if (kn.ntt_loop <= 0 || tab.cus < 8 || period <= 0) return false;
+static int loop_mask(int count, const int *prime, int period, const Tables &tab, const Knobs &kn) {
+    if (kn.ntt_loop <= 0 || tab.cus < 8 || period <= 0) return 0;
     long per_class[2] = {0, 0};
     for (int i = 0; i < period; ++i) {
         const long n = count / period + (i < count % period ? 1 : 0);
         per_class[tab.host_fp[prime[i]] ? 0 : 1] += n;
     }
-    for (long n : per_class)
-        if (n > 0 && n < (long)kn.ntt_loop * tab.cus) return false;
-    return true;
+    int mask = 0;
+    for (int c = 0; c < 2; ++c) {
+        if (per_class[c] > 0 && per_class[c] < (long)kn.ntt_loop * tab.cus) return 0;
+        if (per_class[c] > 0) mask |= 1 << c;
+    }
+    return mask;
+}
+static bool use_loop(int count, const int *prime, int period, const Tables &tab, const Knobs &kn) {
+    return loop_mask(count, prime, period, tab, kn) != 0;
+}
+
+static void modup_primes(int k, int nq, int (&prime)[kMaxMods]) {
+    for (int t = 0; t <= k; ++t) prime[t] = t < k ? t : nq;
+}
+static void drop_primes(int k, int (&prime)[kMaxMods]) {
+    for (int i = 0; i < k; ++i) prime[i] = i;
+}
+
+int ntt_loop_classes(int count, const ResMap &imap, const Tables &tab, const Knobs &kn, const u64 *split_tmp) {
+    return split_tmp || count <= 0 ? 0 : loop_mask(count, imap.prime, imap.per, tab, kn);
+}
+int modup_loop_classes(int groups, int k, int nq, const Tables &tab, const Knobs &kn, const u64 *split_tmp) {
+    if (split_tmp || groups <= 0) return 0;
+    int prime[kMaxMods];
+    modup_primes(k, nq, prime);
+    return loop_mask(groups * k * (k + 1), prime, k + 1, tab, kn);
+}
+int drop_loop_classes(int groups, int k, const Tables &tab, const Knobs &kn, const u64 *split_tmp) {
+    if (split_tmp || groups <= 0) return 0;
+    int prime[kMaxMods];
+    drop_primes(k, prime);
+    return loop_mask(groups * k, prime, k, tab, kn);
 }
 
 // Signed 64-bit coefficients -> residues mod q_p -> NTT. src: dense [G][N] int64; out: [G][P][N]
@@ -2109,7 +2139,7 @@ hipError_t kernels_prepare(int logn) {
 
 
 void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *out, const ResMap &omap,
-                int count, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp) {
+                int count, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp, int cls) {
     if (count <= 0) return;
     if (split_tmp) {
         const OpNtt op{in, imap, out, omap, logn};
@@ -2119,8 +2149,8 @@ void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *
     }
     if (use_loop(count, imap.prime, imap.per, tab, kn)) {
         const OpNtt op{in, imap, out, omap, logn};
-        if (inverse) launch_loop<true>(logn, op, imap.prime, imap.per, count, tab, st);
-        else launch_loop<false>(logn, op, imap.prime, imap.per, count, tab, st);
+        if (inverse) launch_loop<true>(logn, op, imap.prime, imap.per, count, tab, st, cls);
+        else launch_loop<false>(logn, op, imap.prime, imap.per, count, tab, st, cls);
         return;
     }
     const dim3 grid(count), blk = ntt_block(logn);
@@ -2141,7 +2171,7 @@ void launch_ntt(int logn, bool inverse, const u64 *in, const ResMap &imap, u64 *
 }
 
 void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
-                  int nq, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp) {
+                  int nq, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp, int cls) {
     if (groups <= 0) return;
     if (split_tmp) {
         launch_split_fwd(logn, OpModup{coef, d, dmap, digits, k, nq, logn}, split_tmp, groups * k * (k + 1), tab, st);
@@ -2149,9 +2179,10 @@ void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u
     }
     const int units = groups * k, xo = kn.ntt_xcd ? 1 : 0;
     int prime[kMaxMods];
-    for (int t = 0; t <= k; ++t) prime[t] = t < k ? t : nq;
+    modup_primes(k, nq, prime);
     if (use_loop(units * (k + 1), prime, k + 1, tab, kn)) {
-        launch_loop<false>(logn, OpModup{coef, d, dmap, digits, k, nq, logn}, prime, k + 1, units * (k + 1), tab, st);
+        launch_loop<false>(logn, OpModup{coef, d, dmap, digits, k, nq, logn}, prime, k + 1, units * (k + 1), tab, st,
+                           cls);
         return;
     }
     const dim3 grid(xo ? ((units + 7) / 8) * 8 * (k + 1) : units * (k + 1)), blk = ntt_block(logn);
@@ -2165,7 +2196,7 @@ void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u
 
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
                  const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st, const GrpMap *xmap,
-                 u64 *split_tmp) {
+                 u64 *split_tmp, int cls) {
     if (groups <= 0) return;
     const long N = 1L << logn;
     const GrpMap xm = xmap ? *xmap : GrpMap{0, (k + 1) * N, 0, 1};
@@ -2174,9 +2205,9 @@ void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, 
         return;
     }
     int prime[kMaxMods];
-    for (int i = 0; i < k; ++i) prime[i] = i;
+    drop_primes(k, prime);
     if (use_loop(groups * k, prime, k, tab, kn)) {
-        launch_loop<false>(logn, OpDrop{x, xm, last, out, k, drop, logn, add}, prime, k, groups * k, tab, st);
+        launch_loop<false>(logn, OpDrop{x, xm, last, out, k, drop, logn, add}, prime, k, groups * k, tab, st, cls);
         return;
     }
     const int xo = kn.ntt_xcd ? 1 : 0;
