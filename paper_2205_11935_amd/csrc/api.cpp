@@ -53,7 +53,8 @@ const char *const kFamilyNames[F_COUNT] = {"k_ntt_fwd", "k_ntt_inv", "k_modup", 
 // Workspace slots: each grows on demand and is reused by later calls on the same context.
 enum Slot {
     S_COEF, S_DIG, S_U, S_PLAST, S_ROT, S_INNER, S_SUM, S_LAST, S_TENSOR, S_SQ, S_REP,
-    S_FWD_A, S_FWD_B, S_FWD_C, S_COEF2, S_ROT2, S_MISC, S_P_Z2, S_P_T, S_P_U, S_P_W, S_P_V, S_NTT_TMP, S_COUNT
+    S_FWD_A, S_FWD_B, S_FWD_C, S_COEF2, S_ROT2, S_MISC, S_P_Z2, S_P_T, S_P_U, S_P_W, S_P_V, S_NTT_TMP, S_NTT_TMP2,
+    S_COUNT
 };
 
 }  // namespace
@@ -194,16 +195,25 @@ hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 // launches take it when the launch has fewer transforms than the ntt_split knob), or null for the
 // one-workgroup form: at or above the knob, inside the entry point that allocates nothing, or when
 // a frozen workspace cannot hold it (the one-workgroup form gives the same residues).
-u64 *split_buf(ctl_ctx *c, hipStream_t st, int count) {
+u64 *split_buf(ctl_ctx *c, hipStream_t st, int count, Slot which = S_NTT_TMP) {
     if (count >= c->knobs.ntt_split || c->arena) return nullptr;
     const std::string err = g_err;
     u64 *t = nullptr;
     // sized for the largest launch that splits, so that one small warm-up run reserves it
-    if (slot(c, S_NTT_TMP, (size_t)std::max(count, c->knobs.ntt_split - 1) * c->hp.n, st, &t) != CTL_OK) {
+    if (slot(c, which, (size_t)std::max(count, c->knobs.ntt_split - 1) * c->hp.n, st, &t) != CTL_OK) {
         g_err = err;                             // not an error of the call: fall back
         return nullptr;
     }
     return t;
+}
+
+// Buffers of a split chain: an inverse transform of count_i residues fused into the forward
+// transforms of their count_i * per targets (see launch_modup_chain); false when the forward
+// launch does not split.
+bool split_chain(ctl_ctx *c, hipStream_t st, int count_i, int per, u64 **tmp_i, u64 **tmp_f) {
+    *tmp_f = split_buf(c, st, count_i * per);
+    *tmp_i = *tmp_f ? split_buf(c, st, count_i, S_NTT_TMP2) : nullptr;
+    return *tmp_i != nullptr;
 }
 
 // Brackets one launch with events when the context's instrumentation is on.
@@ -419,8 +429,15 @@ int modup_digits(ctl_ctx *c, hipStream_t st, int k, int G, const u64 *d, const R
     const int logn = c->hp.logn, nq = c->hp.nq;
     const long N = c->hp.n;
     u64 *coef, *dig;
-    CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
     CTL_TRY(slot(c, S_DIG, (size_t)G * k * (k + 1) * N, st, &dig));
+    u64 *ti, *tf;
+    if (split_chain(c, st, G * k, k + 1, &ti, &tf)) {
+        { CTL_PROF(F_NTT_INV, G * k, fp_share_range(c, k, false)); launch_modup_chain(logn, true, d, dmap, dig, G, k, nq, c->tab, st, ti, tf); }
+        { CTL_PROF(F_MODUP, G * k * k, modup_share(c, k)); launch_modup_chain(logn, false, d, dmap, dig, G, k, nq, c->tab, st, ti, tf); }
+        *dig_out = dig;
+        return check_launch();
+    }
+    CTL_TRY(slot(c, S_COEF, (size_t)G * k * N, st, &coef));
     {
         u64 *sp = split_buf(c, st, G * k);
         transforms(c, st, F_NTT_INV, F_NTT_INV_FP, G * k, fp_share_range(c, k, false),
@@ -529,6 +546,13 @@ int keyswitch_lower(ctl_ctx *c, hipStream_t st, int k, int groups, const u64 *U,
     pm.gstride = k + 1;
     pm.ostride = k + 1;
     pm.prime[0] = nq;
+    u64 *ti, *tf;
+    if (split_chain(c, st, groups, k, &ti, &tf)) {
+        const GrpMap xm{0, (k + 1) * N, 0, 1};
+        { CTL_PROF(F_NTT_INV, groups, fp_share_range(c, 0, true)); launch_drop_chain(logn, true, U, pm, U, xm, out, groups, k, nq, add, c->tab, st, ti, tf); }
+        { CTL_PROF(F_DROP, (double)groups * k, fp_share_range(c, k, false)); launch_drop_chain(logn, false, U, pm, U, xm, out, groups, k, nq, add, c->tab, st, ti, tf); }
+        return check_launch();
+    }
     {
         u64 *sp = split_buf(c, st, groups);
         transforms(c, st, F_NTT_INV, F_NTT_INV_FP, groups, fp_share_range(c, 0, true),
@@ -569,6 +593,17 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
     m.gstride = k;
     m.ostride = k;
     m.prime[0] = k - 1;
+    u64 *ti, *tf;
+    if (split_chain(c, st, B * 2, k - 1, &ti, &tf)) {
+        DropAdd add{};
+        add.R = 1;
+        add.mask = 0;
+        add.gal[0] = 1;
+        const GrpMap xm{0, k * N, 0, 1};
+        { CTL_PROF(F_NTT_INV, B * 2, fp_share(c, &m.prime[0], 1)); launch_drop_chain(logn, true, in, m, in, xm, out, B * 2, k - 1, k - 1, add, c->tab, st, ti, tf); }
+        { CTL_PROF(F_DROP, B * 2 * (k - 1), fp_share_range(c, k - 1, false)); launch_drop_chain(logn, false, in, m, in, xm, out, B * 2, k - 1, k - 1, add, c->tab, st, ti, tf); }
+        return check_launch();
+    }
     {
         u64 *sp = split_buf(c, st, B * 2);
         transforms(c, st, F_NTT_INV, F_NTT_INV_FP, B * 2, fp_share(c, &m.prime[0], 1),
@@ -832,6 +867,14 @@ int dense_qp_groups(ctl_ctx *c, hipStream_t st, const ctl_model *const *models, 
             pm.gstride = 2L * (k + 1);
             pm.ostride = (long)q.t2 * 2 * (k + 1);
             pm.prime[0] = nq;
+            GrpMap xm{3L * (k + 1) * N, (long)q.t2 * ext, ext, q.R2};
+            u64 *ti, *tf;
+            if (split_chain(c, st, q.B * q.R2, k, &ti, &tf)) {
+                u64 *o = i1 + q.i1_off * k * N;
+                { CTL_PROF(F_NTT_INV, q.B * q.R2, fp_share_range(c, 0, true)); launch_drop_chain(logn, true, ig, pm, ig, xm, o, q.B * q.R2, k, nq, none, c->tab, st, ti, tf); }
+                { CTL_PROF(F_DROP, (double)q.B * q.R2 * k, fp_share_range(c, k, false)); launch_drop_chain(logn, false, ig, pm, ig, xm, o, q.B * q.R2, k, nq, none, c->tab, st, ti, tf); }
+                continue;
+            }
             {
                 u64 *sp = split_buf(c, st, q.B * q.R2);
                 transforms(c, st, F_NTT_INV, F_NTT_INV_FP, q.B * q.R2, fp_share_range(c, 0, true),
@@ -840,7 +883,6 @@ int dense_qp_groups(ctl_ctx *c, hipStream_t st, const ctl_model *const *models, 
                                           c->knobs, st, sp, cls);
                            });
             }
-            GrpMap xm{3L * (k + 1) * N, (long)q.t2 * ext, ext, q.R2};
             {
                 u64 *sp = split_buf(c, st, q.B * q.R2 * k);
                 transforms(c, st, F_DROP, F_DROP_FP, (double)q.B * q.R2 * k, fp_share_range(c, k, false),

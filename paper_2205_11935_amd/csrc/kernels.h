@@ -113,6 +113,16 @@ void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
                  const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st,
                  const GrpMap *xmap = nullptr, u64 *split_tmp = nullptr, int cls = -1);
+// ModUp (iNTT of the digits of d, lifts, NTTs) and ModDown / rescale (iNTT of the dropped prime's
+// residue of each group, located by imap; lifts, NTTs and the combine of launch_drop with x, xm,
+// add) as split chains, the inverse's top pass fused into the forward top passes:
+// inverse_part = true launches the inverse's wave-local passes, false the rest. tmp_i holds one
+// residue per inverse transform, tmp_f one per forward transform.
+void launch_modup_chain(int logn, bool inverse_part, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
+                        int nq, const Tables &tab, hipStream_t st, u64 *tmp_i, u64 *tmp_f);
+void launch_drop_chain(int logn, bool inverse_part, const u64 *in, const ResMap &imap, const u64 *x, const GrpMap &xm,
+                       u64 *out, int groups, int k, int drop, const DropAdd &add, const Tables &tab, hipStream_t st,
+                       u64 *tmp_i, u64 *tmp_f);
 // The classes (bit 0: FP64 primes, bit 1: integer primes) that the launch above with the same
 // arguments runs as separate looped kernels; 0 when it runs in another form.
 int ntt_loop_classes(int count, const ResMap &imap, const Tables &tab, const Knobs &kn, const u64 *split_tmp);

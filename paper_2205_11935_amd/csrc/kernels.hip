@@ -1216,6 +1216,111 @@ int drop_loop_classes(int groups, int k, const Tables &tab, const Knobs &kn, con
     return loop_mask(groups * k, prime, k, tab, kn);
 }
 
+// ---------------------------------------------------------------- split chains (few residues)
+// ModUp, ModDown and rescale each run an inverse transform whose coefficients only feed the lifts
+// of the forward transforms after it (a ModUp digit to its k + 1 targets, the dropped prime to the
+// other k). In split form the chain is k_inv_sub over the inverse's residues, one kernel in which
+// workgroup (r, t, s) runs the inverse's top pass of residue r (the one-workgroup form's inverse
+// result, scaled by N^{-1}) and then, on the same 16 coefficients per thread, the lift and the
+// forward top pass of target t of r, and k_fwd_sub over the targets: three launches instead of four,
+// and the coefficients never leave registers. The inverse's top pass is recomputed per target, on
+// CUs that a launch of a few residues leaves idle anyway. Target u = r per + t of the forward Op.
+template <int LOGN, class OpF>
+__global__ void __launch_bounds__(64)
+k_inv_fwd_top(OpNtt opi, OpF opf, const u64 *__restrict__ tmp_i, u64 *__restrict__ tmp_f, int count_i, int per,
+              Tables tab) {
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T, S = T / 64, TOP = LOGN - 4;
+    const int ri = blockIdx.x / (S * per), t = (blockIdx.x / S) % per, tid = (blockIdx.x % S) * 64 + threadIdx.x;
+    if (ri >= count_i) return;
+    const int rf = ri * per + t;
+    if (opf.copy_only(rf)) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) opf.copy(rf, tid + T * e, tab);
+        return;
+    }
+    u64 cf[16];                                   // canonical coefficients of residue ri
+    {
+        const int pi = opi.prime(ri);
+        const PrimeConst p = tab.pc[pi];
+        const u64 *ti = tmp_i + (long)ri * N;
+        if (p.fp) {
+            double d[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) d[e] = __longlong_as_double((long long)ti[tid + T * e]);
+            inv_pass_fp<LOGN, TOP, 4>(d, tid, reinterpret_cast<const double *>(tab.itws + (long)pi * N), p.qd, p.qinv);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) cf[e] = fp_to_u64(fp_mul(d[e], p.ninvd, p.qd, p.qinv), p.qd, p.qinv);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) cf[e] = ti[tid + T * e];
+            inv_pass<LOGN, TOP, 4>(cf, tid, tab.itw + (long)pi * N, tab.itws + (long)pi * N, p.q, p.q2, p.qn, p.nq2);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) cf[e] = red2(shoup_lazy(cf[e], p.ninv, p.ninvs, p.q, p.qn), p.q);
+        }
+    }
+    const int pf = opf.prime(rf);
+    const PrimeConst q = tab.pc[pf];
+    u64 *tf = tmp_f + (long)rf * N;
+    if (q.fp) {
+        double d[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) d[e] = u64_to_fp(opf.prep(rf, cf[e], q, tab));
+        fwd_pass_fp<LOGN, TOP, 4>(d, tid, reinterpret_cast<const double *>(tab.tws + (long)pf * N), q.qd, q.qinv);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) tf[tid + T * e] = (u64)__double_as_longlong(d[e]);
+        return;
+    }
+    u64 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = opf.prep(rf, cf[e], q, tab);
+    fwd_pass<LOGN, TOP, 4>(v, tid, tab.tw + (long)pf * N, tab.tws + (long)pf * N, q.q, q.q2, q.qn, q.nq2);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) tf[tid + T * e] = v[e];
+}
+
+template <int LOGN, class OpF>
+static void launch_chain_one(bool inverse_part, const OpNtt &opi, int count_i, const OpF &opf, int per, u64 *tmp_i,
+                             u64 *tmp_f, const Tables &tab, hipStream_t st) {
+    const dim3 blk(64);
+    if (inverse_part) {
+        hipLaunchKernelGGL((k_inv_sub<LOGN, OpNtt>), dim3((unsigned)count_i << (LOGN - 10)), blk, 0, st, opi, tmp_i,
+                           count_i, tab);
+        return;
+    }
+    const int count_f = count_i * per;
+    hipLaunchKernelGGL((k_inv_fwd_top<LOGN, OpF>), dim3((unsigned)count_f << (LOGN - 10)), blk, 0, st, opi, opf, tmp_i,
+                       tmp_f, count_i, per, tab);
+    hipLaunchKernelGGL((k_fwd_sub<LOGN, OpF>), dim3((unsigned)count_f << (LOGN - 10)), blk, 0, st, opf, tmp_f, count_f,
+                       tab);
+}
+
+template <class OpF>
+static void launch_chain(int logn, bool inverse_part, const OpNtt &opi, int count_i, const OpF &opf, int per,
+                         u64 *tmp_i, u64 *tmp_f, const Tables &tab, hipStream_t st) {
+    switch (logn) {
+        case 12: launch_chain_one<12>(inverse_part, opi, count_i, opf, per, tmp_i, tmp_f, tab, st); break;
+        case 13: launch_chain_one<13>(inverse_part, opi, count_i, opf, per, tmp_i, tmp_f, tab, st); break;
+        default: launch_chain_one<14>(inverse_part, opi, count_i, opf, per, tmp_i, tmp_f, tab, st); break;
+    }
+}
+
+void launch_modup_chain(int logn, bool inverse_part, const u64 *d, const ResMap &dmap, u64 *digits, int groups, int k,
+                        int nq, const Tables &tab, hipStream_t st, u64 *tmp_i, u64 *tmp_f) {
+    if (groups <= 0) return;
+    const OpNtt opi{d, dmap, nullptr, ResMap{}, logn};
+    launch_chain(logn, inverse_part, opi, groups * k, OpModup{nullptr, d, dmap, digits, k, nq, logn}, k + 1, tmp_i,
+                 tmp_f, tab, st);
+}
+
+void launch_drop_chain(int logn, bool inverse_part, const u64 *in, const ResMap &imap, const u64 *x, const GrpMap &xm,
+                       u64 *out, int groups, int k, int drop, const DropAdd &add, const Tables &tab, hipStream_t st,
+                       u64 *tmp_i, u64 *tmp_f) {
+    if (groups <= 0) return;
+    const OpNtt opi{in, imap, nullptr, ResMap{}, logn};
+    launch_chain(logn, inverse_part, opi, groups, OpDrop{x, xm, nullptr, out, k, drop, logn, add}, k, tmp_i, tmp_f,
+                 tab, st);
+}
+
 // Signed 64-bit coefficients -> residues mod q_p -> NTT. src: dense [G][N] int64; out: [G][P][N]
 // for the P prime indices plist[0..P).
 template <int LOGN>
