@@ -371,10 +371,13 @@ def test_looped_transforms_equal_one_workgroup_form(name):
     host = np.stack([rng.integers(0, o.primes[p], size=o.n, dtype=np.uint64) for p in idx])
     before = c.knob("ntt_loop")
     try:
-        outs = {}
+        outs, recs = {}, {}
         for loop in (1, 0):
             c.knob("ntt_loop", loop)
+            c.profile_enable(True)
             res = [_u64(c.forward(model, lk, dev))]
+            recs[loop] = c.profile_read()                # synchronizes the recorded events
+            c.profile_enable(False)
             buf = _dev(host)
             c.ntt(buf, idx)
             res.append(_u64(buf))
@@ -382,10 +385,18 @@ def test_looped_transforms_equal_one_workgroup_form(name):
             res.append(_u64(buf))
             outs[loop] = res
     finally:
+        c.profile_enable(False)
         c.knob("ntt_loop", before)
     for a, b in zip(outs[1], outs[0]):
         assert np.array_equal(a, b)
     assert np.array_equal(outs[1][2], host)
+    # a looped launch is one kernel per prime class, each with a record of its own: the FP64-prime
+    # kernels under the _fp families, none of them unlooped (the large chain has both classes, and
+    # its 16-ciphertext ModUp has more than one transform per CU of each)
+    assert recs[0]["k_modup_fp"][0] == 0 and recs[0]["k_modup"][0] > 0
+    if name == "large":
+        assert any(q < (1 << 41) for q in c.primes) and any(q >= (1 << 41) for q in c.primes)
+        assert recs[1]["k_modup_fp"][0] > 0 and recs[1]["k_modup"][0] > 0
 
 
 def test_profile_bytes_model():
