@@ -732,8 +732,8 @@ class Context:
         return Model(self, h)
 
     def knob(self, name: str, value: Optional[int] = None) -> int:
-        """Read (value None) or set a launch knob ("mac_chunk", "mac_cts", "keyip_xcd", "mac_direct", "ntt_xcd",
-        "mac_limb", "keyip_rr")."""
+        """Read (value None) or set a launch knob (the names of KNOBS: "mac_chunk", "mac_cts", "keyip_xcd",
+        "mac_direct", "ntt_xcd", "mac_limb", "keyip_rr", "ntt_split", "ntt_loop"; ranges in ctl.h)."""
         if value is not None:
             _check(lib().ctl_knob_set(self.handle, KNOBS[name], int(value)))
         v = ctypes.c_int()
