@@ -2356,8 +2356,11 @@ void launch_keyip(int logn, int k, int cls, const RowSet &rows, const u64 *digit
     // (dr = 0) and the fold term, if any, is the same for every rotation (sr = 0)
     int rr = kn.keyip_rr < 1 ? 1 : kn.keyip_rr > 4 ? 4 : kn.keyip_rr;
     // register budget: a thread holds RR k key words per polynomial (2 VGPRs each, FP64 or 30-bit
-    // limb pairs); these caps keep every class at 3 or more waves per SIMD with nothing spilled
-    const int words = cls == KIP_FP ? 28 : cls == KIP_LIMB ? 12 : 10;
+    // limb pairs). FP64 and 128-bit rows: caps that keep 3 or more waves per SIMD with nothing
+    // spilled. Limb rows: sharing each digit word among more rotations wins over occupancy (k = 6:
+    // RR = 4 at 2 waves per SIMD, 2 VGPRs spilled, runs 9% faster than RR = 2 at 3 waves), up to
+    // k = 7 (RR = 3); at k = 8 only RR = 1 fits without heavy spills.
+    const int words = cls == KIP_FP ? 28 : cls == KIP_LIMB ? (k <= 7 ? 24 : 12) : 10;
     const int cap = words / k < 1 ? 1 : words / k;
     if (rr > cap) rr = cap;
     if (dr != 0 || (fold.src && fold.sr != 0)) rr = 1;
