@@ -24,7 +24,7 @@ CANDIDATES: Dict[str, List[int]] = {
     "keyip_xcd": [1, 0],
     "ntt_xcd": [1, 0],
     "mac_limb": [1, 0],
-    "keyip_rr": [4, 3, 2, 1],
+    "keyip_rr": [8, 6, 4, 2, 1],
     "ntt_split": [128, 64, 256, 0],
     "ntt_loop": [8, 4, 16, 0],
 }

@@ -1572,7 +1572,7 @@ int ctl_knob_set(ctl_ctx *ctx, int knob, int value) {
             ctx->knobs.mac_limb = value;
             return CTL_OK;
         case CTL_KNOB_KEYIP_RR:
-            if (value < 1 || value > 4) return fail(CTL_EINVAL, "rotations per key-product workgroup must lie in 1..4");
+            if (value < 1 || value > 8) return fail(CTL_EINVAL, "rotations per key-product workgroup must lie in 1..8");
             ctx->knobs.keyip_rr = value;
             return CTL_OK;
         case CTL_KNOB_NTT_SPLIT:

@@ -93,7 +93,7 @@ struct Knobs {
     int mac_direct_max = 3;      // batches up to this size use the unstaged MAC
     int ntt_xcd = 1;             // XCD-grouped numbering of ModUp and ModDown workgroups
     int mac_limb = 1;            // integer-prime MAC by 30-bit limbs where every prime is below 2^60
-    int keyip_rr = 4;            // key product: hoisted rotations per workgroup sharing digit words (1..4)
+    int keyip_rr = 8;            // key product: hoisted rotations per workgroup sharing digit words (1..8)
     int ntt_split = 128;         // launches of fewer transforms split each over N/1024 workgroups (0: never)
     int ntt_loop = 8;            // launches with at least this many transforms of each class per CU loop (0: never)
 };

@@ -1612,7 +1612,7 @@ keyip_body(const u64 *__restrict__ digits, long db, long dr, const KeyList &keys
 
 // Waves per SIMD each key-product kernel is compiled for (its register budget: 512 / waves).
 template <int CLS, int RR>
-constexpr int kKeyipWaves = CLS == KIP_FP ? 3 : (RR <= 2 ? 3 : 2);
+constexpr int kKeyipWaves = CLS == KIP_FP ? (RR <= 4 ? 3 : 2) : (RR <= 2 ? 3 : 2);
 
 #define CTL_KEYIP_KERNEL(NAME, CLS)                                                                        \
     template <int K, int RR>                                                                               \
@@ -2354,15 +2354,17 @@ void launch_keyip(int logn, int k, int cls, const RowSet &rows, const u64 *digit
     const int xo = kn.keyip_xcd ? 1 : 0;
     // kn.keyip_rr rotations per workgroup share each digit word when the digits are hoisted
     // (dr = 0) and the fold term, if any, is the same for every rotation (sr = 0)
-    int rr = kn.keyip_rr < 1 ? 1 : kn.keyip_rr > 4 ? 4 : kn.keyip_rr;
+    int rr = kn.keyip_rr < 1 ? 1 : kn.keyip_rr > 8 ? 8 : kn.keyip_rr;
     // register budget: a thread holds RR k key words per polynomial (2 VGPRs each, FP64 or 30-bit
-    // limb pairs). FP64 and 128-bit rows: caps that keep 3 or more waves per SIMD with nothing
-    // spilled. Limb rows: sharing each digit word among more rotations wins over occupancy (k = 6:
-    // RR = 4 at 2 waves per SIMD, 2 VGPRs spilled, runs 9% faster than RR = 2 at 3 waves), up to
-    // k = 7 (RR = 3); at k = 8 only RR = 1 fits without heavy spills.
-    const int words = cls == KIP_FP ? 28 : cls == KIP_LIMB ? (k <= 7 ? 24 : 12) : 10;
+    // limb pairs). Sharing each digit word among more rotations wins over occupancy: FP64 rows take
+    // RR = 8 at 2 waves per SIMD up to k = 6 (no spill; 8% faster than 4 at 3 waves), else the
+    // spill-free 3-wave cap; limb rows RR = 4 up to k = 6 (2 waves, 2 VGPRs spilled; 9% faster than
+    // 2 at 3 waves) and 3 at k = 7, 1 at k = 8; 128-bit rows the spill-free 3-wave cap.
+    const int words = cls == KIP_FP ? (k <= 6 ? 48 : 28) : cls == KIP_LIMB ? (k <= 7 ? 24 : 12) : 10;
     const int cap = words / k < 1 ? 1 : words / k;
     if (rr > cap) rr = cap;
+    if (cls != KIP_FP && rr > 4) rr = 4;          // 6 and 8 rotations only for FP64 rows
+    if (rr == 5 || rr == 7) rr -= 1;              // instantiated: 1, 2, 3, 4, 6, 8
     if (dr != 0 || (fold.src && fold.sr != 0)) rr = 1;
     if (rr > R) rr = R;
     const int RG = (R + rr - 1) / rr;
@@ -2376,9 +2378,15 @@ void launch_keyip(int logn, int k, int cls, const RowSet &rows, const u64 *digit
         case 3: CTL_KIP_ONE(KERNEL, K, 3); break;    \
         default: CTL_KIP_ONE(KERNEL, K, 4); break;   \
     }
+#define CTL_KIP_RR8(KERNEL, K)                       \
+    switch (rr) {                                    \
+        case 6: CTL_KIP_ONE(KERNEL, K, 6); break;    \
+        case 8: CTL_KIP_ONE(KERNEL, K, 8); break;    \
+        default: CTL_KIP_RR(KERNEL, K)               \
+    }
 #define CTL_KIP(K)                                                  \
     case K:                                                         \
-        if (cls == KIP_FP) { CTL_KIP_RR(k_keyip_fp, K) }            \
+        if (cls == KIP_FP) { CTL_KIP_RR8(k_keyip_fp, K) }           \
         else if (cls == KIP_LIMB) { CTL_KIP_RR(k_keyip_limb, K) }   \
         else { CTL_KIP_RR(k_keyip, K) }                             \
         break;
@@ -2387,6 +2395,7 @@ void launch_keyip(int logn, int k, int cls, const RowSet &rows, const u64 *digit
         default: break;
     }
 #undef CTL_KIP
+#undef CTL_KIP_RR8
 #undef CTL_KIP_RR
 #undef CTL_KIP_ONE
 }

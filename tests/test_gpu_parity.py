@@ -425,10 +425,10 @@ def test_profile_bytes_model():
 
 
 def test_forward_key_product_rotation_groups():
-    """Hoisted rotations per key-product workgroup (the keyip_rr knob, 1..4): every setting gives
-    the same residues, the oracle's, on the large workload with a batch of 5 (odd for the key
-    product's ciphertext pairs); 63 and 31 baby rotations leave a short last group for 2, 3 and 4
-    (groups of 2 and 4 at layer 1, of 2, 3 and 4 at layer 2)."""
+    """Hoisted rotations per key-product workgroup (the keyip_rr knob, 1..8; 6 and 8 reach the
+    FP64 rows only, the limb rows stop at 4): every setting gives the same residues, the oracle's,
+    on the large workload with a batch of 5 (odd for the key product's ciphertext pairs); 63 and 31
+    baby rotations leave a short last group for every group size but 1."""
     name, lazy = "large", "qp"
     o, c = _orc(name), _ctx(name)
     lk, _, _, okeys, rlk = _keys(name)
@@ -438,12 +438,12 @@ def test_forward_key_product_rotation_groups():
     before = c.knob("keyip_rr")
     try:
         outs = {}
-        for rr in (1, 2, 3, 4):
+        for rr in (1, 2, 3, 4, 6, 8):
             c.knob("keyip_rr", rr)
             outs[rr] = _u64(c.forward(model, lk, dev))
     finally:
         c.knob("keyip_rr", before)
-    for rr in (1, 2, 3):
+    for rr in (1, 2, 3, 6, 8):
         assert np.array_equal(outs[rr], outs[4]), rr
     for b in (0, 4):
         assert np.array_equal(outs[4][b], o.forward(plan, ref[b], banks_ntt, okeys, rlk)), b
