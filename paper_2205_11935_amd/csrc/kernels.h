@@ -44,7 +44,7 @@ struct PrimeList {
     int prime[kMaxMods];
 };
 
-// Term folded into the key product of polynomial 0 (see k_keyip): rows t < rows add
+// Term folded into the key product of polynomial 0 (see keyip_body): rows t < rows add
 // mul[t] * src[b sb + r sr + t N + sigma_r(n)].
 struct KeyFold {
     const u64 *src;      // null: no fold
@@ -140,7 +140,7 @@ struct RowSet {
 };
 // The rows of a key product over k residues and the special prime, split by class.
 void keyip_rows(int k, int nq, const Tables &tab, const Knobs &kn, RowSet (&rows)[KIP_CLASSES]);
-// The key product of the rows of one class (see k_keyip); nothing is launched for an empty set.
+// The key product of the rows of one class (see keyip_body); nothing is launched for an empty set.
 void launch_keyip(int logn, int k, int cls, const RowSet &rows, const u64 *digits, long db, long dr,
                   const KeyList &keys, int R, u64 *out, long ob, const KeyFold &fold, int B, int nq,
                   const Tables &tab, const Knobs &kn, hipStream_t st);

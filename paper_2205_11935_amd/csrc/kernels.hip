@@ -1392,7 +1392,7 @@ __device__ __forceinline__ u64 limb_reduce4(const u64 (&c)[4], const PrimeConst 
 // Key inner product with the automorphism fused into the digit gather:
 //   out[b][r][0][t] = sum_j D[b][r][j][t][sigma_r] * key_r[j][0][t] (+ fold),  out[..][1][t]
 //   likewise with key_r[j][1][t]; t = 0..k (k = the special prime). D: digits + b db + r dr +
-//   (j (k+1) + t) N, as k_modup stores them (FP64 bit patterns for FP64 primes);
+//   (j (k+1) + t) N, as ModUp stores them (FP64 bit patterns for FP64 primes);
 //   out[b][r] at out + b ob + r 2 (k+1) N. For rows t < fold.rows, polynomial 0
 //   also gets fold.mul[t] * fold.src[b sb + r sr + t N] gathered through sigma_r (the P sigma(c0)
 //   term of a baby step kept over Q*P, or the sigma(c0) of a giant step's extended operand).
