@@ -133,7 +133,11 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
  *                        in each arithmetic class present, FP64 primes and integer primes
  *                        (0..64, default 8; 0: never), run as resident workgroups that loop
  *                        over the transforms of one class per launch, bringing the next one's
- *                        input into L2 while they compute the current one (same residues).
+ *                        input into L2 while they compute the current one (same residues);
+ *   CTL_KNOB_FUSE_RESCALE 1 (default): the ModDown by P that ends a key switch and the rescale
+ *                        after it (dense layers, products) run as one pass: the inverse transforms
+ *                        of the last prime's row and the P row, then one forward transform per
+ *                        remaining prime (same residues); 0: the two steps apart.
  * Out-of-range values give CTL_EINVAL and leave the knob unchanged. */
 #define CTL_KNOB_MAC_CHUNK 0
 #define CTL_KNOB_MAC_CTS 1
@@ -144,6 +148,7 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
 #define CTL_KNOB_KEYIP_RR 6
 #define CTL_KNOB_NTT_SPLIT 7
 #define CTL_KNOB_NTT_LOOP 8
+#define CTL_KNOB_FUSE_RESCALE 9
 int ctl_knob_set(ctl_ctx *ctx, int knob, int value);
 int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value);
 

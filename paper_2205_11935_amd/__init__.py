@@ -33,10 +33,11 @@ CTL_KNOB_MAC_LIMB = 5
 CTL_KNOB_KEYIP_RR = 6
 CTL_KNOB_NTT_SPLIT = 7
 CTL_KNOB_NTT_LOOP = 8
+CTL_KNOB_FUSE_RESCALE = 9
 KNOBS = {"mac_chunk": CTL_KNOB_MAC_CHUNK, "mac_cts": CTL_KNOB_MAC_CTS, "keyip_xcd": CTL_KNOB_KEYIP_XCD,
          "mac_direct": CTL_KNOB_MAC_DIRECT, "ntt_xcd": CTL_KNOB_NTT_XCD, "mac_limb": CTL_KNOB_MAC_LIMB,
          "keyip_rr": CTL_KNOB_KEYIP_RR, "ntt_split": CTL_KNOB_NTT_SPLIT,
-         "ntt_loop": CTL_KNOB_NTT_LOOP}
+         "ntt_loop": CTL_KNOB_NTT_LOOP, "fuse_rescale": CTL_KNOB_FUSE_RESCALE}
 CTL_FORM_NTT = 0
 CTL_FORM_COEFF = 1
 CTL_LAYER_DENSE = 0
@@ -733,7 +734,8 @@ class Context:
 
     def knob(self, name: str, value: Optional[int] = None) -> int:
         """Read (value None) or set a launch knob (the names of KNOBS: "mac_chunk", "mac_cts", "keyip_xcd",
-        "mac_direct", "ntt_xcd", "mac_limb", "keyip_rr", "ntt_split", "ntt_loop"; ranges in ctl.h)."""
+        "mac_direct", "ntt_xcd", "mac_limb", "keyip_rr", "ntt_split", "ntt_loop", "fuse_rescale"; ranges
+        in ctl.h)."""
         if value is not None:
             _check(lib().ctl_knob_set(self.handle, KNOBS[name], int(value)))
         v = ctypes.c_int()

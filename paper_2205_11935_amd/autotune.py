@@ -27,6 +27,7 @@ CANDIDATES: Dict[str, List[int]] = {
     "keyip_rr": [8, 6, 4, 2, 1],
     "ntt_split": [128, 64, 256, 0],
     "ntt_loop": [8, 4, 16, 0],
+    "fuse_rescale": [1, 0],
 }
 
 

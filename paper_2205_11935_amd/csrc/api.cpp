@@ -625,6 +625,48 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
     return check_launch();
 }
 
+// ModDown of G = 2 B extended polynomials U ([G][k+1][N]) by P, adding `add` (R = 1, no rotation),
+// then the rescale by q_{k-1}, into out ([B][2][k-1][N]). With the fuse_rescale knob set both run as
+// one pass (launch_drop_rescale: the inverse transforms of rows k - 1 and P, then k - 1 forward
+// transforms per polynomial, the residues of the two steps; U's row k - 1 takes the addend's
+// first); otherwise ModDown into mid ([B][2][k][N]) and the rescale after it.
+int lower_rescale(ctl_ctx *c, hipStream_t st, int k, int B, u64 *U, const DropAdd &add, u64 *mid, u64 *out) {
+    if (k < 2) return fail(CTL_ELEVEL, "cannot rescale at one prime");
+    if (!c->knobs.fuse_rescale || (add.mask && (add.R != 1 || add.gal[0] != 1))) {
+        if (!mid) return fail(CTL_EINVAL, "ModDown apart from the rescale needs an intermediate buffer");
+        CTL_TRY(keyswitch_lower(c, st, k, B * 2, U, add, mid));
+        return rescale_batch(c, st, k, B, mid, out);
+    }
+    const int logn = c->hp.logn, nq = c->hp.nq, kl = k - 1, G = B * 2;
+    const long N = c->hp.n, xs = (long)(k + 1) * N;
+    if (add.mask) { CTL_PROF(F_ADD, (double)G * N, 0.0); launch_fold_last(logn, U, xs, G, kl, nq, add, c->tab, st); }
+    u64 *coef;
+    CTL_TRY(slot(c, S_PLAST, (size_t)G * 2 * N, st, &coef));
+    ResMap im{};                              // rows k - 1 and P of each polynomial
+    im.per = 2;
+    im.ngrp = 1;
+    im.off = kl;
+    im.gstride = k + 1;
+    im.ostride = k + 1;
+    im.prime[0] = kl;
+    im.prime[1] = nq;
+    {
+        u64 *sp = split_buf(c, st, G * 2);
+        transforms(c, st, F_NTT_INV, F_NTT_INV_FP, G * 2, fp_share(c, im.prime, 2),
+                   ntt_loop_classes(G * 2, im, c->tab, c->knobs, sp), [&](int cls) {
+                       launch_ntt(logn, true, U, im, coef, dense_map(2), G * 2, c->tab, c->knobs, st, sp, cls);
+                   });
+    }
+    {
+        u64 *sp = split_buf(c, st, G * kl);
+        transforms(c, st, F_DROP, F_DROP_FP, (double)G * kl, fp_share_range(c, kl, false),
+                   drop_loop_classes(G, kl, c->tab, c->knobs, sp), [&](int cls) {
+                       launch_drop_rescale(logn, U, xs, coef, out, G, kl, nq, add, c->tab, c->knobs, st, sp, cls);
+                   });
+    }
+    return check_launch();
+}
+
 ResMap c1_map(int k) {        // the c1 residues of a [B][2][k][N] batch
     ResMap m{};
     m.per = k;
@@ -667,9 +709,9 @@ int mul_batch(ctl_ctx *c, hipStream_t st, const KeySet &ks, int k, int B, const 
     const long N = c->hp.n;
     CTL_TRY(need_key(ks, 0, "relinearization key"));
     if (k < 2) return fail(CTL_ELEVEL, "a ciphertext product needs at least two primes");
-    u64 *t3, *sq;
+    u64 *t3, *sq = nullptr;
     CTL_TRY(slot(c, S_TENSOR, (size_t)B * 3 * k * N, st, &t3));
-    CTL_TRY(slot(c, S_SQ, (size_t)B * 2 * k * N, st, &sq));
+    if (!c->knobs.fuse_rescale) CTL_TRY(slot(c, S_SQ, (size_t)B * 2 * k * N, st, &sq));
     { CTL_PROF(F_TENSOR, 4.0 * B * k * N, 0.0); launch_tensor(c->hp.logn, a, b, t3, B, k, c->tab, st); }
     ResMap dm{};
     dm.per = k;
@@ -686,8 +728,9 @@ int mul_batch(ctl_ctx *c, hipStream_t st, const KeySet &ks, int k, int B, const 
     add.mask = 3;
     add.gal[0] = 1;
     const u64 rlk_id = 0, one = 1;
-    CTL_TRY(keyswitch_batch(c, st, k, B, 1, t3, dm, false, ks, &rlk_id, &one, add, sq));
-    return rescale_batch(c, st, k, B, sq, out);
+    u64 *U;
+    CTL_TRY(keyswitch_raise(c, st, k, B, 1, t3, dm, false, ks, &rlk_id, &one, &U));
+    return lower_rescale(c, st, k, B, U, add, sq, out);
 }
 
 int square_batch(ctl_ctx *c, hipStream_t st, const KeySet &ks, int k, int B, const u64 *in, u64 *out) {
@@ -917,6 +960,10 @@ int dense_qp_groups(ctl_ctx *c, hipStream_t st, const ctl_model *const *models, 
     none.R = 1;
     none.mask = 0;
     none.gal[0] = 1;
+    if (c->knobs.fuse_rescale) {
+        Site s(c, kKeepLayer, "moddown + rescale");
+        return lower_rescale(c, st, k, B, usum, none, acc, out);
+    }
     { Site s(c, kKeepLayer, "moddown"); CTL_TRY(keyswitch_lower(c, st, k, B * 2, usum, none, acc)); }
     Site s(c, kKeepLayer, "rescale");
     return rescale_batch(c, st, k, B, acc, out);
@@ -1583,6 +1630,10 @@ int ctl_knob_set(ctl_ctx *ctx, int knob, int value) {
             if (value < 0 || value > 64) return fail(CTL_EINVAL, "the loop threshold must lie in 0..64");
             ctx->knobs.ntt_loop = value;
             return CTL_OK;
+        case CTL_KNOB_FUSE_RESCALE:
+            if (value != 0 && value != 1) return fail(CTL_EINVAL, "the ModDown + rescale switch is 0 or 1");
+            ctx->knobs.fuse_rescale = value;
+            return CTL_OK;
         default:
             return fail(CTL_EINVAL, "unknown knob");
     }
@@ -1600,6 +1651,7 @@ int ctl_knob_get(const ctl_ctx *ctx, int knob, int *value) {
         case CTL_KNOB_KEYIP_RR: *value = ctx->knobs.keyip_rr; return CTL_OK;
         case CTL_KNOB_NTT_SPLIT: *value = ctx->knobs.ntt_split; return CTL_OK;
         case CTL_KNOB_NTT_LOOP: *value = ctx->knobs.ntt_loop; return CTL_OK;
+        case CTL_KNOB_FUSE_RESCALE: *value = ctx->knobs.fuse_rescale; return CTL_OK;
         default: return fail(CTL_EINVAL, "unknown knob");
     }
 }
@@ -2347,9 +2399,11 @@ int ctl_square(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint
                         reinterpret_cast<u64 *>(out));
 }
 
-// Scratch words of square_batch for B ciphertexts at k primes: tensor 3k, relinearized 2k,
-// coefficient-form digits k, ModUp digits k(k+1), key product 2(k+1), ModDown P rows 2, rescale
-// rows 2 (each times N, per ciphertext; every size is a multiple of the 32-word carve alignment).
+// Scratch words of square_batch for B ciphertexts at k primes: tensor 3k, relinearized 2k (ModDown
+// and rescale apart), coefficient-form digits k, ModUp digits k(k+1), key product 2(k+1), ModDown
+// P rows 2, rescale rows 2 (each times N, per ciphertext; every size is a multiple of the 32-word
+// carve alignment; ModDown and rescale as one pass take 4 coefficient rows and no relinearized
+// rows, within this bound).
 static size_t square_scratch_words(int k, long n, int B) { return (size_t)B * n * ((size_t)k * k + 9 * k + 6); }
 
 int ctl_square_noalloc(ctl_ctx *ctx, const ctl_evk *evk, int k, const uint64_t *in, uint64_t *out, int n_ct,

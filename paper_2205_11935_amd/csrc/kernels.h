@@ -96,6 +96,7 @@ struct Knobs {
     int keyip_rr = 8;            // key product: hoisted rotations per workgroup sharing digit words (1..8)
     int ntt_split = 128;         // launches of fewer transforms split each over N/1024 workgroups (0: never)
     int ntt_loop = 8;            // launches with at least this many transforms of each class per CU loop (0: never)
+    int fuse_rescale = 1;        // ModDown by P and the rescale after it as one pass
 };
 
 // The NTT-bearing launches: with split_tmp (a buffer of one residue per transform of the launch,
@@ -113,6 +114,16 @@ void launch_modup(int logn, const u64 *coef, const u64 *d, const ResMap &dmap, u
 void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, int k, int drop,
                  const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st,
                  const GrpMap *xmap = nullptr, u64 *split_tmp = nullptr, int cls = -1);
+// ModDown by P of groups extended polynomials x (group g, row t at x + g xs + t N; rows 0..kl
+// over Q, kl + 1 mod P) followed by the rescale by q_kl, into out ([groups][kl][N]): coef holds
+// the inverse transforms of row kl and of the P row ([groups][2][N]); add (R = 1, no rotation)
+// must already be folded into row kl by launch_fold_last and is added to rows 0..kl-1 here.
+void launch_drop_rescale(int logn, const u64 *x, long xs, const u64 *coef, u64 *out, int groups, int kl, int np,
+                         const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st,
+                         u64 *split_tmp = nullptr, int cls = -1);
+// x[g][kl] += P a[g][kl] mod q_kl for each group whose polynomial has an addend in add.
+void launch_fold_last(int logn, u64 *x, long xs, int groups, int kl, int np, const DropAdd &add, const Tables &tab,
+                      hipStream_t st);
 // ModUp (iNTT of the digits of d, lifts, NTTs) and ModDown / rescale (iNTT of the dropped prime's
 // residue of each group, located by imap; lifts, NTTs and the combine of launch_drop with x, xm,
 // add) as split chains, the inverse's top pass fused into the forward top passes:

@@ -475,6 +475,13 @@ __device__ __forceinline__ long res_offset(const ResMap &m, int r) {
     return m.off + (long)(t / m.ngrp) * m.ostride + (long)(t % m.ngrp) * m.gstride + e;
 }
 
+// x, opaque to the compiler: index arithmetic derived from it (inside a loop iteration, or per
+// loaded element) is redone where it is used rather than hoisted and kept in registers.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // ---------------------------------------------------------------- NTT kernels
 // Every NTT-bearing kernel picks the arithmetic per workgroup from its prime (uniform branch):
 // FP64 for primes below 2^41, 64-bit integer otherwise. Inputs and outputs are canonical residues
@@ -569,7 +576,7 @@ k_modup(const u64 *__restrict__ coef, const u64 *__restrict__ d, ResMap dmap, u6
         int nq, int units, int xcd_order, Tables tab) {
     extern __shared__ u64 lds[];
     constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
-    const int tid = threadIdx.x;
+    const int tid = opaque(threadIdx.x);
     int t, gj;                                // gj = g * k + j, the digit; t, its target
     if (xcd_order) {
         // the k + 1 targets of a digit run back to back on one XCD (workgroups are dealt to the 8
@@ -626,7 +633,7 @@ k_drop(const u64 *__restrict__ x, GrpMap xm, const u64 *__restrict__ last, u64 *
        int drop, int groups, int xcd_order, DropAdd add, Tables tab) {
     extern __shared__ u64 lds[];
     constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
-    const int tid = threadIdx.x;
+    const int tid = opaque(threadIdx.x);
     int i, grp;
     if (xcd_order) {
         // the k primes of a group run back to back on one XCD, which then reads `last` once
@@ -780,6 +787,107 @@ struct OpDrop {
     __device__ void store_inv(int, int, u64, const PrimeConst &) const {}
     __device__ void store_inv_fp(int, int, double, const PrimeConst &) const {}
 };
+
+// ModDown by P followed by the rescale by q_l, l = kl (the last prime of Q), in one forward pass
+// (hybrid key switch, then the rescale, Section 2). With c_P the coefficients of the P row and
+// y_l those of the ModDown result's row l, the two steps give, for i < l,
+//   out_i = ((x_i - NTT([c_P]_i)) P^-1 + a_i - NTT([y_l]_i)) q_l^-1
+//         = ((x_i - NTT([c_P]_i + P [y_l]_i)) P^-1 + a_i) q_l^-1          (NTT is linear mod q_i)
+// ([c]_i the centred lift of c into q_i), and y_l = (c_l - [c_P]_l) P^-1 mod q_l with c_l the
+// coefficients of row l of x: when the addend a is present its row l has been added to x's as
+// P a_l beforehand (see k_fold_last), which puts a_l into y_l. So the forward transforms take
+// [c_P]_i + P [y_l]_i (computed from the two coefficient rows by load) and the combine multiplies
+// by P^-1 and q_l^-1 in turn: the residues of the two steps, with one inverse transform more and
+// the k forward transforms of the ModDown's own pass fewer. Residues r = g kl + i.
+struct OpDropRescale {
+    const u64 *x;        // group g, row t at x + g xs + t N (rows 0..kl over Q, kl + 1 the P row)
+    long xs;
+    const u64 *coef;     // [groups][2][N]: inverse transforms of row kl (mod q_kl) and of the P row
+    u64 *out;            // [groups][kl][N]
+    int kl, np, logn;
+    DropAdd add;         // R = 1, no rotation: polynomial c of group g = 2 b + c adds base + b sb + c sc
+    __device__ int prime(int r) const { return r % kl; }
+    __device__ bool copy_only(int) const { return false; }
+    __device__ void copy(int, int, const Tables &) const {}
+    __device__ u64 fetch(int r, int j) const { return coef[((long)(r / kl) * 2 << logn) + j]; }
+    __device__ u64 prep(int, u64 x, const PrimeConst &, const Tables &) const { return x; }
+    __device__ u64 load(int r, int j, const PrimeConst &p, const Tables &tab) const {
+        const int i = r % kl;
+        const long g = r / kl;
+        const u64 cl = coef[(g * 2 << logn) + j], cp = coef[((g * 2 + 1) << logn) + j];
+        const PrimeConst pl = tab.pc[kl];
+        const u64 P = tab.pc[np].q;
+        const CrossConst lp = tab.cross[kl * kMaxMods + np];
+        const u64 yl = red2(shoup_lazy(sub_mod(cl, lift_centered(cp, P, lp.qj_mod_qi, pl), pl.q), lp.inv, lp.invs,
+                                       pl.q, pl.qn), pl.q);
+        const CrossConst ip = tab.cross[i * kMaxMods + np];
+        const u64 a = lift_centered(cp, P, ip.qj_mod_qi, p);
+        const u64 b = lift_centered(yl, pl.q, tab.cross[i * kMaxMods + kl].qj_mod_qi, p);
+        return add_mod(a, mul_mod(b, ip.qj_mod_qi, p), p.q);
+    }
+    __device__ void store_fwd(int r, int j, u64 v, bool fp, const PrimeConst &p, const Tables &tab) const {
+        const int i = r % kl, grp = r / kl;
+        const long N = 1L << logn;
+        const CrossConst ip = tab.cross[i * kMaxMods + np], il = tab.cross[i * kMaxMods + kl];
+        const u64 xv = x[grp * xs + (long)i * N + j];
+        const int c = grp & 1;
+        const bool has_add = (add.mask >> c) & 1;
+        const u64 av = has_add ? add.base[(grp >> 1) * add.sb + c * add.sc + (long)i * N + j] : 0;
+        u64 *dst = out + ((long)grp * kl + i) * N + j;
+        if (fp) {
+            double val = fp_mul(u64_to_fp(xv) - __longlong_as_double((long long)v), ip.invd, p.qd, p.qinv);
+            if (has_add) val += u64_to_fp(av);
+            *dst = fp_to_u64(fp_mul(val, il.invd, p.qd, p.qinv), p.qd, p.qinv);
+            return;
+        }
+        const u64 ext = red4(v, p.q, p.q2);
+        u64 val = red2(shoup_lazy(sub_mod(xv, ext, p.q), ip.inv, ip.invs, p.q, p.qn), p.q);
+        if (has_add) val = add_mod(val, av, p.q);
+        *dst = red2(shoup_lazy(val, il.inv, il.invs, p.q, p.qn), p.q);
+    }
+    __device__ void store_inv(int, int, u64, const PrimeConst &) const {}
+    __device__ void store_inv_fp(int, int, double, const PrimeConst &) const {}
+};
+
+// One workgroup per forward transform of an Op (load, transform, store_fwd). With xcd_order the
+// `period` residues of a group (which read the same input words) run back to back on one XCD.
+template <int LOGN, class Op>
+__global__ void __launch_bounds__(Geo<LOGN>::T)
+k_fwd_one(Op op, int count, int period, int xcd_order, Tables tab) {
+    extern __shared__ u64 lds[];
+    constexpr int T = Geo<LOGN>::T;
+    const int tid = opaque(threadIdx.x);
+    int r = blockIdx.x;
+    if (xcd_order) {
+        const int loc = blockIdx.x >> 3;
+        r = ((loc / period) * 8 + (blockIdx.x & 7)) * period + loc % period;
+    }
+    if (r >= count) return;
+    const int pi = op.prime(r);
+    const PrimeConst p = tab.pc[pi];
+    u64 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = op.load(r, tid + T * e, p, tab);
+    const bool fp = fwd_transform<LOGN>(v, lds, tid, tab, pi, p);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int j = wave_elem(tid, e);
+        op.store_fwd(r, j, lds[lds_idx(j)], fp, p, tab);
+    }
+}
+
+// x[g][kl] += P a[g][kl] mod q_kl for the polynomials g = 2 b + c with an addend (see
+// OpDropRescale). grid: x = N / 256, y = groups.
+__global__ void __launch_bounds__(256)
+k_fold_last(u64 *__restrict__ x, long xs, int kl, int np, DropAdd add, int logn, Tables tab) {
+    const long N = 1L << logn;
+    const int n = blockIdx.x * 256 + threadIdx.x, grp = blockIdx.y, c = grp & 1;
+    if (!((add.mask >> c) & 1)) return;
+    const PrimeConst p = tab.pc[kl];
+    const u64 a = add.base[(grp >> 1) * add.sb + c * add.sc + (long)kl * N + n];
+    u64 *xp = x + grp * xs + (long)kl * N + n;
+    *xp = add_mod(*xp, mul_mod(a, tab.cross[kl * kMaxMods + np].qj_mod_qi, p), p.q);
+}
 
 template <int LOGN, class Op>
 __global__ void __launch_bounds__(64)
@@ -966,12 +1074,6 @@ static size_t ntt_lds(int logn) { return (size_t)((1 << logn) + ((1 << logn) >> 
 // Period d goes to XCD d mod 8 (workgroup b runs on XCD b mod 8), and the S workgroups of an XCD
 // take its residues in turn, so the residues of one period, which read the same input words, run
 // at the same time on one L2.
-// x, opaque to the compiler: index arithmetic derived from it inside a loop iteration is redone
-// there rather than hoisted out of the loop and kept in registers across iterations.
-__device__ __forceinline__ int opaque(int x) {
-    asm volatile("" : "+v"(x));
-    return x;
-}
 
 struct SlotSet {
     int period, n;
@@ -1328,7 +1430,7 @@ __global__ void __launch_bounds__(Geo<LOGN>::T)
 k_int_ntt(const int64_t *__restrict__ src, u64 *__restrict__ out, PrimeList pl, Tables tab) {
     extern __shared__ u64 lds[];
     constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T;
-    const int tid = threadIdx.x;
+    const int tid = opaque(threadIdx.x);
     const int slot = blockIdx.x % pl.n, grp = blockIdx.x / pl.n;
     const int pi = pl.idx[slot];
     const PrimeConst p = tab.pc[pi];
@@ -2152,6 +2254,9 @@ static hipError_t prepare_all() {
     if ((e = set_lds(k_fwd_loop<LOGN, OpModup, false>, b)) != hipSuccess) return e;
     if ((e = set_lds(k_fwd_loop<LOGN, OpDrop, true>, b)) != hipSuccess) return e;
     if ((e = set_lds(k_fwd_loop<LOGN, OpDrop, false>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_fwd_loop<LOGN, OpDropRescale, true>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_fwd_loop<LOGN, OpDropRescale, false>, b)) != hipSuccess) return e;
+    if ((e = set_lds(k_fwd_one<LOGN, OpDropRescale>, b)) != hipSuccess) return e;
     return set_lds(k_int_ntt<LOGN>, b);
 }
 
@@ -2323,6 +2428,38 @@ void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, 
         case 13: hipLaunchKernelGGL(k_drop<13>, grid, blk, sh, st, x, xm, last, out, k, drop, groups, xo, add, tab); break;
         default: hipLaunchKernelGGL(k_drop<14>, grid, blk, sh, st, x, xm, last, out, k, drop, groups, xo, add, tab); break;
     }
+}
+
+void launch_drop_rescale(int logn, const u64 *x, long xs, const u64 *coef, u64 *out, int groups, int kl, int np,
+                         const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st, u64 *split_tmp,
+                         int cls) {
+    if (groups <= 0 || kl <= 0) return;
+    const OpDropRescale op{x, xs, coef, out, kl, np, logn, add};
+    if (split_tmp) {
+        launch_split_fwd(logn, op, split_tmp, groups * kl, tab, st);
+        return;
+    }
+    int prime[kMaxMods];
+    drop_primes(kl, prime);
+    if (use_loop(groups * kl, prime, kl, tab, kn)) {
+        launch_loop<false>(logn, op, prime, kl, groups * kl, tab, st, cls);
+        return;
+    }
+    const int xo = kn.ntt_xcd ? 1 : 0;
+    const dim3 grid(xo ? ((groups + 7) / 8) * 8 * kl : groups * kl), blk = ntt_block(logn);
+    const size_t sh = ntt_lds(logn);
+    switch (logn) {
+        case 12: hipLaunchKernelGGL((k_fwd_one<12, OpDropRescale>), grid, blk, sh, st, op, groups * kl, kl, xo, tab); break;
+        case 13: hipLaunchKernelGGL((k_fwd_one<13, OpDropRescale>), grid, blk, sh, st, op, groups * kl, kl, xo, tab); break;
+        default: hipLaunchKernelGGL((k_fwd_one<14, OpDropRescale>), grid, blk, sh, st, op, groups * kl, kl, xo, tab); break;
+    }
+}
+
+void launch_fold_last(int logn, u64 *x, long xs, int groups, int kl, int np, const DropAdd &add, const Tables &tab,
+                      hipStream_t st) {
+    if (groups <= 0 || !add.mask) return;
+    const dim3 grid((1u << logn) / 256, groups), blk(256);
+    hipLaunchKernelGGL(k_fold_last, grid, blk, 0, st, x, xs, kl, np, add, logn, tab);
 }
 
 void launch_int_ntt(int logn, const int64_t *src, u64 *out, int groups, const PrimeList &pl,

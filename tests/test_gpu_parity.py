@@ -399,6 +399,41 @@ def test_looped_transforms_equal_one_workgroup_form(name):
         assert recs[1]["k_modup_fp"][0] > 0 and recs[1]["k_modup"][0] > 0
 
 
+@pytest.mark.parametrize("count,loop", [(1, 0), (16, 0), (128, 1)])
+def test_moddown_rescale_one_pass_equals_two(count, loop):
+    """The ModDown by P that ends a key switch and the rescale after it, as one pass (the
+    fuse_rescale knob) and as two: the same residues for squares of uniform residues at k = n_q and
+    k = 2 (the relinearization adds d0, d1: the addend path) and for the forward pass (no addend),
+    with the transforms split (1 ciphertext), one workgroup each (16) and looped (128 ciphertexts,
+    ntt_loop 1: at least one transform per CU in each class of every launch of the pass)."""
+    name = "large"
+    o, c = _orc(name), _ctx(name)
+    lk = _keys(name)[0]
+    rng = np.random.default_rng(1000 + count)
+    host = np.stack([np.stack([np.stack([rng.integers(0, o.primes[i], size=o.n, dtype=np.uint64)
+                                         for i in range(o.nq)]) for _ in range(2)]) for _ in range(count)])
+    dev = _dev(host)
+    model = None
+    if count <= 16:
+        model, _ = _raw_model(name, seed=35, lazy="qp")
+    before = (c.knob("fuse_rescale"), c.knob("ntt_loop"))
+    try:
+        outs = {}
+        c.knob("ntt_loop", 1 if loop else before[1])
+        for fuse in (1, 0):
+            c.knob("fuse_rescale", fuse)
+            res = [_u64(c.square(lk, dev[:, :, :k].contiguous())) for k in (o.nq, 2)]
+            if model is not None:
+                res.append(_u64(c.forward(model, lk, dev)))
+            outs[fuse] = res
+    finally:
+        c.knob("fuse_rescale", before[0])
+        c.knob("ntt_loop", before[1])
+    assert len(outs[1]) == len(outs[0])
+    for a, b in zip(outs[1], outs[0]):
+        assert a.shape == b.shape and np.array_equal(a, b)
+
+
 def test_profile_bytes_model():
     """The algorithmic bytes the library records for a key product: one rotation of 3 ciphertexts
     reads 3 k(k+1) digit rows and one key set's 2 k(k+1) key rows and writes 3 2(k+1) rows, N
