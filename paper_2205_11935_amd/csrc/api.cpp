@@ -629,7 +629,8 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
 // then the rescale by q_{k-1}, into out ([B][2][k-1][N]). With the fuse_rescale knob set both run as
 // one pass (launch_drop_rescale: the inverse transforms of rows k - 1 and P, then k - 1 forward
 // transforms per polynomial, the residues of the two steps; U's row k - 1 takes the addend's
-// first); otherwise ModDown into mid ([B][2][k][N]) and the rescale after it.
+// first; a split chain for few polynomials); otherwise ModDown into mid ([B][2][k][N]) and the
+// rescale after it.
 int lower_rescale(ctl_ctx *c, hipStream_t st, int k, int B, u64 *U, const DropAdd &add, u64 *mid, u64 *out) {
     if (k < 2) return fail(CTL_ELEVEL, "cannot rescale at one prime");
     if (!c->knobs.fuse_rescale || (add.mask && (add.R != 1 || add.gal[0] != 1))) {
@@ -640,6 +641,15 @@ int lower_rescale(ctl_ctx *c, hipStream_t st, int k, int B, u64 *U, const DropAd
     const int logn = c->hp.logn, nq = c->hp.nq, kl = k - 1, G = B * 2;
     const long N = c->hp.n, xs = (long)(k + 1) * N;
     if (add.mask) { CTL_PROF(F_ADD, (double)G * N, 0.0); launch_fold_last(logn, U, xs, G, kl, nq, add, c->tab, st); }
+    {
+        u64 *tf = split_buf(c, st, G * kl), *ti = tf ? split_buf(c, st, G * 2, S_NTT_TMP2) : nullptr;
+        if (ti) {
+            const int pr[2] = {kl, nq};
+            { CTL_PROF(F_NTT_INV, G * 2, fp_share(c, pr, 2)); launch_drop_rescale_chain(logn, true, U, xs, out, G, kl, nq, add, c->tab, st, ti, tf); }
+            { CTL_PROF(F_DROP, (double)G * kl, fp_share_range(c, kl, false)); launch_drop_rescale_chain(logn, false, U, xs, out, G, kl, nq, add, c->tab, st, ti, tf); }
+            return check_launch();
+        }
+    }
     u64 *coef;
     CTL_TRY(slot(c, S_PLAST, (size_t)G * 2 * N, st, &coef));
     ResMap im{};                              // rows k - 1 and P of each polynomial

@@ -121,6 +121,11 @@ void launch_drop(int logn, const u64 *x, const u64 *last, u64 *out, int groups, 
 void launch_drop_rescale(int logn, const u64 *x, long xs, const u64 *coef, u64 *out, int groups, int kl, int np,
                          const DropAdd &add, const Tables &tab, const Knobs &kn, hipStream_t st,
                          u64 *split_tmp = nullptr, int cls = -1);
+// launch_drop_rescale as a split chain (few polynomials): inverse_part = true launches the
+// inverse's wave-local passes over rows kl and P into tmp_i ([2 groups][N]), false the rest
+// (tmp_f: [groups kl][N]).
+void launch_drop_rescale_chain(int logn, bool inverse_part, const u64 *x, long xs, u64 *out, int groups, int kl, int np,
+                               const DropAdd &add, const Tables &tab, hipStream_t st, u64 *tmp_i, u64 *tmp_f);
 // x[g][kl] += P a[g][kl] mod q_kl for each group whose polynomial has an addend in add.
 void launch_fold_last(int logn, u64 *x, long xs, int groups, int kl, int np, const DropAdd &add, const Tables &tab,
                       hipStream_t st);

@@ -812,9 +812,12 @@ struct OpDropRescale {
     __device__ u64 fetch(int r, int j) const { return coef[((long)(r / kl) * 2 << logn) + j]; }
     __device__ u64 prep(int, u64 x, const PrimeConst &, const Tables &) const { return x; }
     __device__ u64 load(int r, int j, const PrimeConst &p, const Tables &tab) const {
-        const int i = r % kl;
         const long g = r / kl;
-        const u64 cl = coef[(g * 2 << logn) + j], cp = coef[((g * 2 + 1) << logn) + j];
+        return combine(r, coef[(g * 2 << logn) + j], coef[((g * 2 + 1) << logn) + j], p, tab);
+    }
+    // [c_P]_i + P [y_l]_i mod q_i from the coefficients cl (mod q_kl) and cp (mod P)
+    __device__ u64 combine(int r, u64 cl, u64 cp, const PrimeConst &p, const Tables &tab) const {
+        const int i = r % kl;
         const PrimeConst pl = tab.pc[kl];
         const u64 P = tab.pc[np].q;
         const CrossConst lp = tab.cross[kl * kMaxMods + np];
@@ -1327,6 +1330,29 @@ int drop_loop_classes(int groups, int k, const Tables &tab, const Knobs &kn, con
 // forward top pass of target t of r, and k_fwd_sub over the targets: three launches instead of four,
 // and the coefficients never leave registers. The inverse's top pass is recomputed per target, on
 // CUs that a launch of a few residues leaves idle anyway. Target u = r per + t of the forward Op.
+// The inverse's top pass of one residue of prime pi whose wave-local passes k_inv_sub left in ti,
+// scaled by N^-1: canonical coefficients tid + T e.
+template <int LOGN>
+__device__ __forceinline__ void inv_top_coeffs(const u64 *__restrict__ ti, int pi, int tid, const Tables &tab,
+                                               u64 (&cf)[16]) {
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T, TOP = LOGN - 4;
+    const PrimeConst p = tab.pc[pi];
+    if (p.fp) {
+        double d[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) d[e] = __longlong_as_double((long long)ti[tid + T * e]);
+        inv_pass_fp<LOGN, TOP, 4>(d, tid, reinterpret_cast<const double *>(tab.itws + (long)pi * N), p.qd, p.qinv);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) cf[e] = fp_to_u64(fp_mul(d[e], p.ninvd, p.qd, p.qinv), p.qd, p.qinv);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) cf[e] = ti[tid + T * e];
+        inv_pass<LOGN, TOP, 4>(cf, tid, tab.itw + (long)pi * N, tab.itws + (long)pi * N, p.q, p.q2, p.qn, p.nq2);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) cf[e] = red2(shoup_lazy(cf[e], p.ninv, p.ninvs, p.q, p.qn), p.q);
+    }
+}
+
 template <int LOGN, class OpF>
 __global__ void __launch_bounds__(64)
 k_inv_fwd_top(OpNtt opi, OpF opf, const u64 *__restrict__ tmp_i, u64 *__restrict__ tmp_f, int count_i, int per,
@@ -1341,25 +1367,7 @@ k_inv_fwd_top(OpNtt opi, OpF opf, const u64 *__restrict__ tmp_i, u64 *__restrict
         return;
     }
     u64 cf[16];                                   // canonical coefficients of residue ri
-    {
-        const int pi = opi.prime(ri);
-        const PrimeConst p = tab.pc[pi];
-        const u64 *ti = tmp_i + (long)ri * N;
-        if (p.fp) {
-            double d[16];
-#pragma unroll
-            for (int e = 0; e < 16; ++e) d[e] = __longlong_as_double((long long)ti[tid + T * e]);
-            inv_pass_fp<LOGN, TOP, 4>(d, tid, reinterpret_cast<const double *>(tab.itws + (long)pi * N), p.qd, p.qinv);
-#pragma unroll
-            for (int e = 0; e < 16; ++e) cf[e] = fp_to_u64(fp_mul(d[e], p.ninvd, p.qd, p.qinv), p.qd, p.qinv);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) cf[e] = ti[tid + T * e];
-            inv_pass<LOGN, TOP, 4>(cf, tid, tab.itw + (long)pi * N, tab.itws + (long)pi * N, p.q, p.q2, p.qn, p.nq2);
-#pragma unroll
-            for (int e = 0; e < 16; ++e) cf[e] = red2(shoup_lazy(cf[e], p.ninv, p.ninvs, p.q, p.qn), p.q);
-        }
-    }
+    inv_top_coeffs<LOGN>(tmp_i + (long)ri * N, opi.prime(ri), tid, tab, cf);
     const int pf = opf.prime(rf);
     const PrimeConst q = tab.pc[pf];
     u64 *tf = tmp_f + (long)rf * N;
@@ -1394,6 +1402,57 @@ static void launch_chain_one(bool inverse_part, const OpNtt &opi, int count_i, c
                        tmp_f, count_i, per, tab);
     hipLaunchKernelGGL((k_fwd_sub<LOGN, OpF>), dim3((unsigned)count_f << (LOGN - 10)), blk, 0, st, opf, tmp_f, count_f,
                        tab);
+}
+
+// Split chain of the one-pass ModDown and rescale (OpDropRescale): k_inv_sub over the two
+// coefficient rows of each polynomial g (residues 2 g: row kl, 2 g + 1: the P row), then workgroup
+// (g, t, s) runs the inverse's top pass of both rows on its 16 coefficients per thread, forms the
+// lift of target t from them (OpDropRescale::combine) and runs its forward top pass; k_fwd_sub
+// over the g kl + t targets finishes.
+template <int LOGN>
+__global__ void __launch_bounds__(64)
+k_inv2_fwd_top(OpDropRescale opf, const u64 *__restrict__ tmp_i, u64 *__restrict__ tmp_f, int groups, Tables tab) {
+    constexpr int N = Geo<LOGN>::N, T = Geo<LOGN>::T, S = T / 64, TOP = LOGN - 4;
+    const int kl = opf.kl;
+    const int g = blockIdx.x / (S * kl), t = (blockIdx.x / S) % kl, tid = (blockIdx.x % S) * 64 + threadIdx.x;
+    if (g >= groups) return;
+    const int rf = g * kl + t;
+    u64 cl[16], cp[16];
+    inv_top_coeffs<LOGN>(tmp_i + (long)(2 * g) * N, kl, tid, tab, cl);
+    inv_top_coeffs<LOGN>(tmp_i + (long)(2 * g + 1) * N, opf.np, tid, tab, cp);
+    const PrimeConst q = tab.pc[t];
+    u64 *tf = tmp_f + (long)rf * N;
+    if (q.fp) {
+        double d[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) d[e] = u64_to_fp(opf.combine(rf, cl[e], cp[e], q, tab));
+        fwd_pass_fp<LOGN, TOP, 4>(d, tid, reinterpret_cast<const double *>(tab.tws + (long)t * N), q.qd, q.qinv);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) tf[tid + T * e] = (u64)__double_as_longlong(d[e]);
+        return;
+    }
+    u64 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = opf.combine(rf, cl[e], cp[e], q, tab);
+    fwd_pass<LOGN, TOP, 4>(v, tid, tab.tw + (long)t * N, tab.tws + (long)t * N, q.q, q.q2, q.qn, q.nq2);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) tf[tid + T * e] = v[e];
+}
+
+template <int LOGN>
+static void launch_drop_rescale_chain_one(bool inverse_part, const OpNtt &opi, const OpDropRescale &opf, int groups,
+                                          u64 *tmp_i, u64 *tmp_f, const Tables &tab, hipStream_t st) {
+    const dim3 blk(64);
+    if (inverse_part) {
+        hipLaunchKernelGGL((k_inv_sub<LOGN, OpNtt>), dim3((unsigned)(2 * groups) << (LOGN - 10)), blk, 0, st, opi, tmp_i,
+                           2 * groups, tab);
+        return;
+    }
+    const int count_f = groups * opf.kl;
+    hipLaunchKernelGGL(k_inv2_fwd_top<LOGN>, dim3((unsigned)count_f << (LOGN - 10)), blk, 0, st, opf, tmp_i, tmp_f,
+                       groups, tab);
+    hipLaunchKernelGGL((k_fwd_sub<LOGN, OpDropRescale>), dim3((unsigned)count_f << (LOGN - 10)), blk, 0, st, opf,
+                       tmp_f, count_f, tab);
 }
 
 template <class OpF>
@@ -2452,6 +2511,26 @@ void launch_drop_rescale(int logn, const u64 *x, long xs, const u64 *coef, u64 *
         case 12: hipLaunchKernelGGL((k_fwd_one<12, OpDropRescale>), grid, blk, sh, st, op, groups * kl, kl, xo, tab); break;
         case 13: hipLaunchKernelGGL((k_fwd_one<13, OpDropRescale>), grid, blk, sh, st, op, groups * kl, kl, xo, tab); break;
         default: hipLaunchKernelGGL((k_fwd_one<14, OpDropRescale>), grid, blk, sh, st, op, groups * kl, kl, xo, tab); break;
+    }
+}
+
+void launch_drop_rescale_chain(int logn, bool inverse_part, const u64 *x, long xs, u64 *out, int groups, int kl, int np,
+                               const DropAdd &add, const Tables &tab, hipStream_t st, u64 *tmp_i, u64 *tmp_f) {
+    if (groups <= 0 || kl <= 0) return;
+    ResMap im{};                                  // rows kl and P of each polynomial
+    im.per = 2;
+    im.ngrp = 1;
+    im.off = kl;
+    im.gstride = xs >> logn;
+    im.ostride = xs >> logn;
+    im.prime[0] = kl;
+    im.prime[1] = np;
+    const OpNtt opi{x, im, nullptr, im, logn};
+    const OpDropRescale opf{x, xs, nullptr, out, kl, np, logn, add};
+    switch (logn) {
+        case 12: launch_drop_rescale_chain_one<12>(inverse_part, opi, opf, groups, tmp_i, tmp_f, tab, st); break;
+        case 13: launch_drop_rescale_chain_one<13>(inverse_part, opi, opf, groups, tmp_i, tmp_f, tab, st); break;
+        default: launch_drop_rescale_chain_one<14>(inverse_part, opi, opf, groups, tmp_i, tmp_f, tab, st); break;
     }
 }
 

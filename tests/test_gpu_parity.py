@@ -404,8 +404,9 @@ def test_moddown_rescale_one_pass_equals_two(count, loop):
     """The ModDown by P that ends a key switch and the rescale after it, as one pass (the
     fuse_rescale knob) and as two: the same residues for squares of uniform residues at k = n_q and
     k = 2 (the relinearization adds d0, d1: the addend path) and for the forward pass (no addend),
-    with the transforms split (1 ciphertext), one workgroup each (16) and looped (128 ciphertexts,
-    ntt_loop 1: at least one transform per CU in each class of every launch of the pass)."""
+    with the transforms split (1 ciphertext: the split chain, both coefficient rows' inverse top
+    passes in the forward top pass's workgroups), one workgroup each (16) and looped (128
+    ciphertexts, ntt_loop 1: at least one transform per CU in each class of every launch)."""
     name = "large"
     o, c = _orc(name), _ctx(name)
     lk = _keys(name)[0]
