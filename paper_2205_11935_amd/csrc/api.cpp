@@ -537,8 +537,6 @@ int keyswitch_raise(ctl_ctx *c, hipStream_t st, int k, int B, int R, const u64 *
 int keyswitch_lower(ctl_ctx *c, hipStream_t st, int k, int groups, const u64 *U, const DropAdd &add, u64 *out) {
     const int logn = c->hp.logn, nq = c->hp.nq;
     const long N = c->hp.n;
-    u64 *plast;
-    CTL_TRY(slot(c, S_PLAST, (size_t)groups * N, st, &plast));
     ResMap pm{};
     pm.per = 1;
     pm.ngrp = 1;
@@ -553,6 +551,8 @@ int keyswitch_lower(ctl_ctx *c, hipStream_t st, int k, int groups, const u64 *U,
         { CTL_PROF(F_DROP, (double)groups * k, fp_share_range(c, k, false)); launch_drop_chain(logn, false, U, pm, U, xm, out, groups, k, nq, add, c->tab, st, ti, tf); }
         return check_launch();
     }
+    u64 *plast;                                  // coefficients of the P rows (not in the chain)
+    CTL_TRY(slot(c, S_PLAST, (size_t)groups * N, st, &plast));
     {
         u64 *sp = split_buf(c, st, groups);
         transforms(c, st, F_NTT_INV, F_NTT_INV_FP, groups, fp_share_range(c, 0, true),
@@ -584,8 +584,6 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
     const int logn = c->hp.logn;
     const long N = c->hp.n;
     if (k < 2) return fail(CTL_ELEVEL, "cannot rescale at one prime");
-    u64 *last;
-    CTL_TRY(slot(c, S_LAST, (size_t)B * 2 * N, st, &last));
     ResMap m{};
     m.per = 1;
     m.ngrp = 1;
@@ -604,6 +602,8 @@ int rescale_batch(ctl_ctx *c, hipStream_t st, int k, int B, const u64 *in, u64 *
         { CTL_PROF(F_DROP, B * 2 * (k - 1), fp_share_range(c, k - 1, false)); launch_drop_chain(logn, false, in, m, in, xm, out, B * 2, k - 1, k - 1, add, c->tab, st, ti, tf); }
         return check_launch();
     }
+    u64 *last;                                   // coefficients of the dropped prime (not in the chain)
+    CTL_TRY(slot(c, S_LAST, (size_t)B * 2 * N, st, &last));
     {
         u64 *sp = split_buf(c, st, B * 2);
         transforms(c, st, F_NTT_INV, F_NTT_INV_FP, B * 2, fp_share(c, &m.prime[0], 1),
