@@ -124,7 +124,8 @@ int ctl_ctx_primes(const ctl_ctx *ctx, uint64_t *primes_out, int *n_out);
  *                        once for all of them (1..8, default 8; 5 and 7 act as 4 and 6; each
  *                        arithmetic class caps it by its register budget, e.g. 8 for FP64 rows
  *                        and 4 for 30-bit-limb rows with 6 primes, 1 for limb rows with 8;
- *                        launches whose rotations have their own digits use 1);
+ *                        launches over at most 4 ciphertexts use at most 2; launches whose
+ *                        rotations have their own digits use 1);
  *   CTL_KNOB_NTT_SPLIT   launches of fewer residue transforms than this (0..4096, default 128; 0:
  *                        never) split every transform over N/1024 single-wave workgroups in two
  *                        launches through a workspace buffer, instead of one workgroup per
