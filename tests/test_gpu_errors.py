@@ -64,10 +64,6 @@ def _small_setup(ctl, hook=False):
     return w, c, h, m, keys, ct
 
 
-@pytest.mark.skip(reason="held back: an earlier form of this test (its allocator thunks owned by a helper "
-                         "object, not by the context) crashed the process in a garbage collection that freed the "
-                         "thunks before the context that still called them; the thunks now live on the context "
-                         "(Context.set_allocator) and the frozen-workspace case runs in its own test")
 def test_enomem_leaves_outputs_unchanged():
     _need_gpu()
     import paper_2205_11935_amd as ctl
