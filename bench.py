@@ -244,7 +244,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=W.LARGE.batch)
-    ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--cpu-sample", type=int, default=16,
                     help="oracle worker processes for the CPU leg, one ciphertext each, capped at the host's "
                          "cores (0: skip)")
@@ -269,7 +269,7 @@ def main():
                          "sooner (0: skip the sweep)")
     ap.add_argument("--serve-queries", type=int, default=5000,
                     help="serving sweep: queries per rate, unless --serve-seconds of arrivals come sooner")
-    ap.add_argument("--serve-rates", default="10,20,50,100,200,500,1000,2000",
+    ap.add_argument("--serve-rates", default="10,20,50,100,200,500,1000,2000,5000,10000,20000",
                     help="serving sweep: arrival rates, q/s")
     ap.add_argument("--mix-queries", type=int, default=512,
                     help="batched mix: queries per pass (0: leave the mix out of the default line)")
@@ -393,7 +393,7 @@ def main():
     one = one_out = None
     if args.plain_steps > 0:
         one, one_out = ct[:1].contiguous(), c.empty_ct(1, model.info.k_out)
-        for _ in range(2):
+        for _ in range(20):                 # some 25 ms of single-ciphertext passes before timing
             c.forward(model, keys, one, out=one_out)
         torch.cuda.synchronize()
         pev = [torch.cuda.Event(enable_timing=True) for _ in range(args.plain_steps + 1)]
