@@ -1975,9 +1975,10 @@ k_mac(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long 
 // and 2^60 (c[1] takes both cross products). Every 8 terms the columns are normalized (c0, c1 <
 // 2^30, c2 < 2^62), which keeps each below 2^64 for the next 8: c0 < 2^30 + 8 2^60,
 // c1 < 2^30 + 16 (2^30 - 1)^2, c2 < 2^62 + 8 2^60 + 2^34. Once per output the 128-bit value
-// c0 + c1 2^30 + c2 2^60 is reduced mod q. Same staging, grid and outputs as k_mac; plaintext
+// c0 + c1 2^30 + c2 2^60 is reduced mod q. Same staging and outputs as k_mac; plaintext
 // words are staged split into their limbs, wl | wh 2^32, so that the waves reading the LDS copy
-// find the limbs as register halves.
+// find the limbs as register halves. grid: x = N / 64 tiles times t2 / KC chunks (tile-major in
+// blocks of 8 tiles, see below), y = prime, z = ceil(B / blockDim.y) ciphertext groups.
 template <int KC>
 __global__ void __launch_bounds__(512)
 k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, long rot_sb,
@@ -1988,10 +1989,12 @@ k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, 
     const int nl = threadIdx.x, bl = __builtin_amdgcn_readfirstlane(threadIdx.y), by = blockDim.y;
     const int i = pl.idx[blockIdx.y];
     const long N = 1L << logn, kn = (long)k * N;
-    const long n0 = (long)blockIdx.x * 64;
-    const int nbz = (B + by - 1) / by;              // grid z = ciphertext groups x KC-chunks
-    const int b = (blockIdx.z % nbz) * by + bl;
-    const int kc0 = (blockIdx.z / nbz) * KC;
+    // grid x = tiles x KC-chunks, the chunks of one tile 8 workgroups apart: they run on one XCD
+    // at about the same time, so all but the first read the tile's ciphertext words from its L2
+    const int nch = t2 / KC, hx = (int)blockIdx.x >> 3, lx = (int)blockIdx.x & 7;
+    const long n0 = (long)(nch == 1 ? (int)blockIdx.x : (hx / nch) * 8 + lx) * 64;
+    const int kc0 = nch == 1 ? 0 : (hx % nch) * KC;
+    const int b = (int)blockIdx.z * by + bl;        // grid z = ciphertext groups
     const bool live = b < B;
     const PrimeConst p = pcs[pl.prime[blockIdx.y]];
     const u64 *ct_b = ct + (long)(live ? b : 0) * ct_sb + i * N + n0 + nl;
@@ -2669,7 +2672,8 @@ void launch_mac(int logn, const u64 *ct, long ct_sb, const u64 *rot, long rot_sb
         if (limb) {
             // 12 VGPRs per chunk entry; at most 8 (KC = 12 fits at 2 waves per SIMD but runs slower)
             const int kl = mac_chunk(t2, kn.mac_chunk_cap < 8 ? kn.mac_chunk_cap : 8);
-            const dim3 grid((1u << logn) / 64, in.n, ((B + by_int - 1) / by_int) * (t2 / kl)), blk(64, by_int);
+            // the kernel interleaves chunks with tiles in blocks of 8 tiles (N / 64 is a multiple of 8)
+            const dim3 grid(((1u << logn) / 64) * (t2 / kl), in.n, (B + by_int - 1) / by_int), blk(64, by_int);
             switch (kl) {
 #define CTL_MAC(KC) case KC: hipLaunchKernelGGL(k_mac_limb<KC>, grid, blk, 0, st, ct, ct_sb, rot, rot_sb, bank, inner, B, rows, t1, t2, logn, in, tab.pc); break;
                 CTL_MAC(8) CTL_MAC(6) CTL_MAC(4) CTL_MAC(3) CTL_MAC(2)
