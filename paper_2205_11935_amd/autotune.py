@@ -20,7 +20,7 @@ from typing import Callable, Dict, List, Optional, Sequence
 
 CANDIDATES: Dict[str, List[int]] = {
     "mac_chunk": [16, 12, 8, 6, 4],
-    "mac_cts": [16, 8, 4, 2],
+    "mac_cts": [8, 16, 4, 2],
     "keyip_xcd": [1, 0],
     "ntt_xcd": [1, 0],
     "mac_limb": [1, 0],

@@ -83,12 +83,12 @@ void launch_sum_gather(int logn, u64 *out, long o_sb, const u64 *base, long ba_s
                        long s_sr, int R, int kk, bool ext, int mask, const GalList &gal, int B, int nq,
                        const Tables &tab, hipStream_t st);
 // Launch choices an autotuner may set (defaults in brackets): the largest giant-step chunk of the
-// MAC [16], ciphertexts per MAC workgroup [16], XCD-grouped key-product numbering [1], largest
+// MAC [16], ciphertexts per MAC workgroup [8], XCD-grouped key-product numbering [1], largest
 // batch that uses the unstaged MAC [3], XCD-grouped ModUp / ModDown numbering [1], 30-bit limb
-// products in the integer-prime MAC [1], hoisted rotations per key-product workgroup [4].
+// products in the integer-prime MAC [1], hoisted rotations per key-product workgroup [8].
 struct Knobs {
     int mac_chunk_cap = 16;
-    int mac_cts = 16;
+    int mac_cts = 8;
     int keyip_xcd = 1;
     int mac_direct_max = 3;      // batches up to this size use the unstaged MAC
     int ntt_xcd = 1;             // XCD-grouped numbering of ModUp and ModDown workgroups
