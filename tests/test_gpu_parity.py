@@ -307,9 +307,10 @@ def test_forward_full_batch(lazy):
 
 @pytest.mark.parametrize("lazy", [True, "qp"])
 def test_forward_ragged_batch(lazy):
-    """13 ciphertexts of the mid workload: fewer than the FP64 MAC's ciphertexts per workgroup
-    (16), not a multiple of the integer MAC's (8), and odd for the key product's pairs; ciphertexts 0, 7 and 12 against the oracle, every one
-    against its own evaluation alone."""
+    """13 ciphertexts of the mid workload: not a multiple of the MACs' ciphertexts per workgroup
+    (8 by default; fewer than 16, the FP64 MAC's largest workgroup), and odd for the key
+    product's pairs; ciphertexts 0, 7 and 12 against the oracle, every one against its own
+    evaluation alone."""
     name = "mid"
     o, c = _orc(name), _ctx(name)
     lk, _, _, okeys, rlk = _keys(name)
