@@ -2091,7 +2091,9 @@ k_mac_limb(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot, 
 // The same MAC for batches of one or two ciphertexts: there is nothing to share a staged plaintext
 // word with, so each thread reads its plaintext words straight from memory (coalesced across the
 // coefficients of a wave), with no LDS and no barriers, and FP64 and integer primes go in one
-// launch (the branch is uniform per workgroup). grid: x = N / 64 tiles, y = residue row
+// launch (the branch is uniform per workgroup). Plaintext words are read once per launch, so their
+// loads are non-temporal: they stay out of L2, which keeps the rotated ciphertext words the
+// giant-step chunks share. grid: x = N / 64 tiles, y = residue row
 // (PrimeList), z = B t2 / KC.
 template <int KC>
 __global__ void __launch_bounds__(64)
@@ -2115,7 +2117,7 @@ k_mac_direct(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot
             const double x0 = u64_to_fp(src[0]), x1 = u64_to_fp(src[kn]);
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
-                const double w = u64_to_fp(bk[((long)(kc0 + kk) * t1 + j) * kn]);
+                const double w = u64_to_fp(__builtin_nontemporal_load(&bk[((long)(kc0 + kk) * t1 + j) * kn]));
                 acc[kk][0] += fp_mul(x0, w, p.qd, p.qinv);
                 acc[kk][1] += fp_mul(x1, w, p.qd, p.qinv);
             }
@@ -2136,7 +2138,7 @@ k_mac_direct(const u64 *__restrict__ ct, long ct_sb, const u64 *__restrict__ rot
         const u64 x0 = src[0], x1 = src[kn];
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
-            const u64 w = bk[((long)(kc0 + kk) * t1 + j) * kn];
+            const u64 w = __builtin_nontemporal_load(&bk[((long)(kc0 + kk) * t1 + j) * kn]);
             acc_mac(acc[kk][0], w, x0);
             acc_mac(acc[kk][1], w, x1);
         }
