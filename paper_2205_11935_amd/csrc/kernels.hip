@@ -1650,6 +1650,8 @@ keyip_body(const u64 *__restrict__ digits, long db, long dr, const KeyList &keys
             }
         }
     };
+    // each key word is read once per launch (held in registers over the batch loop), so its loads
+    // are non-temporal and leave L2 to the digit words that the rotations of a tile share
     if constexpr (CLS == KIP_FP) {
         // FP64 products (prime < 2^41): each term |.| <= 0.52 q, sums stay far below 2^53
         double kb[RR][K], ka[RR][K];
@@ -1658,8 +1660,8 @@ keyip_body(const u64 *__restrict__ digits, long db, long dr, const KeyList &keys
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int n = (voff_o[rr] >> 3) % N;
-                kb[rr][j] = u64_to_fp(key[rr][((long)(j * 2 + 0) * np + pt) * N + n]);
-                ka[rr][j] = u64_to_fp(key[rr][((long)(j * 2 + 1) * np + pt) * N + n]);
+                kb[rr][j] = u64_to_fp(__builtin_nontemporal_load(&key[rr][((long)(j * 2 + 0) * np + pt) * N + n]));
+                ka[rr][j] = u64_to_fp(__builtin_nontemporal_load(&key[rr][((long)(j * 2 + 1) * np + pt) * N + n]));
             }
         const double fmd = u64_to_fp(fm);
         auto run = [&](auto fold_tag) {
@@ -1745,8 +1747,8 @@ keyip_body(const u64 *__restrict__ digits, long db, long dr, const KeyList &keys
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int n = (voff_o[rr] >> 3) % N;
-                kb[rr][j] = key[rr][((long)(j * 2 + 0) * np + pt) * N + n];
-                ka[rr][j] = key[rr][((long)(j * 2 + 1) * np + pt) * N + n];
+                kb[rr][j] = __builtin_nontemporal_load(&key[rr][((long)(j * 2 + 0) * np + pt) * N + n]);
+                ka[rr][j] = __builtin_nontemporal_load(&key[rr][((long)(j * 2 + 1) * np + pt) * N + n]);
             }
         auto run = [&](auto fold_tag) {
             constexpr bool FOLD = decltype(fold_tag)::value;
